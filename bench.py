@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Throughput of HaTT recompression on one MI355X.
+
+Workload ("spectral"): pairs of order-20 TTs with mode size 32 and ranks 20,
+every core a Haar left-orthonormal factor times diag(2^(-j/2)); each pair's
+Hadamard product is recompressed with a seeded Gaussian sketch of width 40
+and truncated to rank 30 by TT-Rounding.  One step recompresses a batch of
+independent pairs (inputs resident in HBM before timing starts).
+
+Prints one JSON line (see the design doc for the field definitions).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def _parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=64, help="pairs recompressed per step")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-explicit", action="store_true")
+    return ap.parse_args()
+
+
+def _time_steps(fn, steps, torch):
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(steps):
+        fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1000.0, wall
+
+
+def main() -> int:
+    args = _parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}): this build has no "
+              "multi-GPU path; independent pairs would shard across GPUs without communication "
+              "(see DESIGN.md).", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+
+    import workloads as wk
+    import paper_2410_04385_amd as H
+    from paper_2410_04385_amd import perfmodel
+    from paper_2410_04385_amd._lib import HattError
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    cfg = wk.WORKLOADS["spectral"]
+    d, n, r, ell, cap = cfg["d"], cfg["n"], cfg["r"], cfg["ell"], cfg["max_rank"]
+    B = args.batch
+    seed = 2024
+    print(f"[bench] generating {B} pairs d={d} n={n} r={r}", file=sys.stderr, flush=True)
+    pairs = [wk.spectral_pair(1000 + b, d, n, r, r) for b in range(B)]
+    x = H.TT.from_cores([p[0] for p in pairs])
+    y = H.TT.from_cores([p[1] for p in pairs])
+    p = H.plan(x, y, ell, max_rank=cap, seed=seed)
+    out = H.TT.empty(x.n, p["ell"], B)
+    ranks = torch.empty((B, d + 1), dtype=torch.int64, device="cuda")
+    ws = torch.empty(p["ws_bytes"], dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+
+    def step():
+        H.recompress(x, y, ell, max_rank=cap, seed=seed, workspace=ws, out=out, ranks=ranks)
+
+    print(f"[bench] warmup {args.warmup} steps, batch {B}, workspace {p['ws_bytes'] / 2**20:.1f} MiB",
+          file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    gpu_s, wall_s = _time_steps(step, args.steps, torch)
+    ms_per_step = 1000.0 * wall_s / args.steps
+    value = B * args.steps / wall_s
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step (events {1000 * gpu_s / args.steps:.3f})",
+          file=sys.stderr, flush=True)
+
+    # per-kernel-class event timing over a second, identical region
+    H.profile_start()
+    for _ in range(args.steps):
+        step()
+    prof = H.profile_stop()
+    torch.cuda.synchronize()
+    flops = perfmodel.hatt_round_flops(x.n, x.ranks, y.ranks, p["ell"], cap)
+    classes = {}
+    for name, (ms, calls) in prof.items():
+        if calls:
+            classes[name] = {"ms_per_step": ms / args.steps, "calls_per_step": calls / args.steps}
+    dom = max(classes, key=lambda k: classes[k]["ms_per_step"])
+    dom_flops = flops.get(dom, 0.0) * B
+    dom_s = classes[dom]["ms_per_step"] / 1000.0
+    achieved = dom_flops / dom_s / 1e12 if dom_flops > 0 else None
+    roof = {
+        "kernel": dom,
+        "bound": "mfma" if dom in ("gemm_f64",) else "alu",
+        "achieved": achieved,
+        "peak": perfmodel.PEAK_FP64_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": (achieved / perfmodel.PEAK_FP64_TFLOPS) if achieved else None,
+        "traffic": None,
+    }
+    for name in classes:
+        f = flops.get(name, 0.0) * B
+        if f > 0:
+            classes[name]["tflops"] = f / (classes[name]["ms_per_step"] / 1000.0) / 1e12
+    step_tflops = flops["total"] * B / (ms_per_step / 1000.0) / 1e12
+
+    # explicit PKP + TT-Rounding on the GPU (the comparator of the metric)
+    explicit = None
+    if not args.no_explicit:
+        try:
+            xe = H.TT.from_cores([pairs[0][0]])
+            ye = H.TT.from_cores([pairs[0][1]])
+            a = H.hadamard_explicit(xe, ye)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            a = H.hadamard_explicit(xe, ye)
+            torch.cuda.synchronize()
+            t_pkp = time.perf_counter() - t0
+            pkp_bytes = a.total * 8
+            explicit = {"pkp_ms": 1000 * t_pkp, "pkp_GBs": pkp_bytes / t_pkp / 1e9}
+            t0 = time.perf_counter()
+            H.round(a, max_rank=cap)
+            torch.cuda.synchronize()
+            explicit["round_ms"] = 1000 * (time.perf_counter() - t0)
+            explicit["recompressions_per_s"] = 1.0 / (t_pkp + explicit["round_ms"] / 1000)
+        except HattError as e:
+            explicit = (explicit or {})
+            explicit["status"] = f"unsupported: {e}"
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_info
+
+        from oracle import hatt as ohatt
+        from oracle import philox, rounding, tt
+
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        l = p["ell"]
+        R = philox.sketch(seed, x.n, l)
+        t0 = time.perf_counter()
+        done = 0
+        refs = []
+        while done < B and (time.perf_counter() - t0) < args.cpu_seconds:
+            yb, zb = pairs[done]
+            refs.append(rounding.tt_round(ohatt.hatt(yb, zb, R), max_rank=cap))
+            done += 1
+        t_hatt = time.perf_counter() - t0
+        cpu = {"value": done / t_hatt, "unit": "recompressions/s", "cores": threads, "kind": "oracle",
+               "sample": f"{done} of the {B} pairs, FP64 numpy HaTT-1 + TT-Rounding, seeded sketch"}
+        errs = []
+        rk = ranks.cpu()
+        for b in range(len(refs)):
+            got = out.to_numpy(b, rk[b].tolist())
+            errs.append(tt.rel_err(got, refs[b]))
+        parity = {"pairs_checked": len(refs), "max_rel_err_vs_oracle": max(errs)}
+        if (time.perf_counter() - t0) < 2 * args.cpu_seconds:
+            t1 = time.perf_counter()
+            rounding.tt_round(tt.pkp(*pairs[0]), max_rank=cap)
+            cpu["explicit_pkp_round_value"] = 1.0 / (time.perf_counter() - t1)
+
+    line = {
+        "metric": "HaTT recompressions/s + GB/s/MFMA% vs explicit-PKP rounding, 1 GPU @ rel err 1e-8",
+        "value": value,
+        "unit": "recompressions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"spectral d={d} n={n} r_x=r_y={r} sketch={ell} max_rank={cap}",
+                   "pairs_per_step": B, "variant": "HaTT-1", "seed": seed},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "step_tflops_algorithmic": step_tflops,
+        "kernel_classes": classes,
+        "explicit_pkp_rounding_gpu": explicit,
+        "parity": parity,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,180 @@
+/*
+ * hatt.h -- C ABI of the MI355X (gfx950) library for recompressing the
+ * Hadamard product of two tensor trains without forming its partial
+ * Kronecker product (PKP) cores ("HaTT", Sun, Huang, Xiao and Yang).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All floating point data is IEEE double, on the device, owned by the
+ *   caller.  The library never allocates device memory: scratch space is a
+ *   caller-provided workspace whose size the *_plan calls report.
+ * - A TT view (hatt_tt) describes `batch` tensor trains of identical shape
+ *   stored back to back.  Core k of train b starts at element
+ *       data + b * batch_stride + sum_{j<k} rank[j] * n[j] * rank[j+1]
+ *   and is row-major [rank[k]][n[k]][rank[k+1]] (last index fastest, the
+ *   multi-index convention of Sec. 2.1; H(T) and V(T) are then plain
+ *   row-major reshapes).  rank[0] = rank[d] = 1.
+ * - Outputs of recompression/rounding are written at "capacity" shape: core
+ *   k occupies cap[k] * n[k] * cap[k+1] elements (cap from the plan call),
+ *   and when a bond's kept rank rho[k] is smaller than cap[k] the extra
+ *   rows/columns are zero.  The kept ranks are written, per train, to a
+ *   device int64 array out_rank[batch][d+1].  Zero padding does not change
+ *   the represented tensor, so a caller may use the padded cores directly or
+ *   slice core k to [rho[k]][n[k]][rho[k+1]].
+ * - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *   enqueues work on it (no host synchronisation) unless stated otherwise.
+ * - Arguments are validated before anything is enqueued; on an error nothing
+ *   is launched and hatt_last_error() returns a message (thread-local).
+ *   Device/launch failures return HATT_EDEVICE.  No C++ exception crosses
+ *   the ABI.  Calls are re-entrant when they use distinct workspaces.
+ */
+#ifndef HATT_H_
+#define HATT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define HATT_API __attribute__((visibility("default")))
+#else
+#define HATT_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HATT_OK = 0,
+  HATT_EINVAL = -1,      /* a NULL pointer, a non-positive size or an option out of range */
+  HATT_ESHAPE = -2,      /* inconsistent mode sizes or ranks (rank[0] or rank[d] != 1, ...) */
+  HATT_EWORKSPACE = -3,  /* workspace smaller than the plan call reported */
+  HATT_EDEVICE = -4,     /* a HIP call or kernel launch failed */
+  HATT_ENOTCONV = -5,    /* reserved: adaptive sketch growth did not converge */
+  HATT_ENONFINITE = -6,  /* reserved: non-finite input detected */
+  HATT_EUNSUPPORTED = -7 /* a shape this build does not handle (see message) */
+} hatt_status;
+
+typedef struct {
+  int32_t d;              /* order, >= 1 */
+  int32_t batch;          /* number of trains of identical shape, >= 1 */
+  const int64_t *n;       /* host [d]: mode sizes, >= 1 */
+  const int64_t *rank;    /* host [d+1]: bond ranks, rank[0] = rank[d] = 1 */
+  double *data;           /* device: cores (layout above) */
+  int64_t batch_stride;   /* elements between trains; 0 means packed */
+} hatt_tt;
+
+typedef struct {
+  int32_t variant;        /* 1: HaTT-1, sketch split W = W I (eq. HPCRL--1);
+                             2: HaTT-2, truncated SVD split (eq. HPCRL--2) */
+  double ep;              /* HaTT-2: keep rank-1 terms with sigma > ep * ||W||_2 */
+  int64_t ell;            /* requested sketch width l_k for every interior bond */
+  const int64_t *ell_bond;/* optional host [d+1] per-bond request (overrides ell) */
+  int64_t max_rank;       /* truncation cap on every bond after the sweep; <= 0: none */
+  double tol;             /* relative Frobenius tolerance of that truncation; <= 0: none */
+  uint64_t seed;          /* key of the Philox4x32-10 sketch (used when no sketch is passed) */
+} hatt_opts;
+
+/*
+ * hatt_plan -- sketch widths and workspace size of hatt_recompress.
+ * The requested widths are clamped (Sec. 2.2 rank bound and the economy-QR
+ * shape condition of Sec. 4): l_0 = l_d = 1; l_k <= r_k s_k;
+ * l_k <= l_{k-1} n_k (left to right); l_{k-1} <= n_k l_k (right to left).
+ * ell_out: host [d+1] clamped widths, which are also the output capacities.
+ * ws_bytes: device workspace bytes for a call with x->batch trains.
+ * out_elems: elements of one output train at capacity shape.
+ */
+HATT_API hatt_status hatt_plan(const hatt_tt *x, const hatt_tt *y, const hatt_opts *opts,
+                      int64_t *ell_out, size_t *ws_bytes, int64_t *out_elems);
+
+/*
+ * hatt_recompress -- Alg. 4 (HaTT): recompress x (.) y (elementwise product,
+ * Sec. 2.2) for every train of the batch, then optionally truncate the
+ * result with TT-Rounding (Alg. 1) to max_rank and/or tol.
+ *   - Sketch: `sketch` may hold an explicit Gaussian TT with ranks
+ *     ell_out of hatt_plan (batch 1: shared by all trains, or batch equal to
+ *     x->batch: one per train); if NULL the library draws the random
+ *     Gaussian TT of Def. 2.1 from Philox4x32-10 keyed by opts->seed
+ *     (the same sketch for every train of the batch).
+ *   - HPCRL (Alg. 3) builds the sketches W^{(k)} right to left from the cores
+ *     of x and y (eqs. 3.3, WLWR, LISRmatrix); the left-to-right sweep
+ *     (eqs. updatcores1/2, M*core0) never forms a PKP core.
+ *   - out: device, x->batch trains at capacity shape (ell_out), batch stride
+ *     out_stride elements (0 = packed, i.e. out_elems).  Without truncation
+ *     the output cores 1..d-1 are left-orthogonal (V(X_k)^T V(X_k) = I).
+ *   - out_rank: device int64 [batch][d+1], the kept ranks.
+ * x and y must have the same d, batch and mode sizes.
+ */
+HATT_API hatt_status hatt_recompress(const hatt_tt *x, const hatt_tt *y, const hatt_tt *sketch,
+                            const hatt_opts *opts, double *out, int64_t out_stride,
+                            int64_t *out_rank, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * tt_hadamard_explicit -- the PKP cores of x (.) y (Sec. 2.2):
+ * A_k(a s + b, i, a' s' + b') = X_k(a, i, a') Y_k(b, i, b'), ranks r_k s_k.
+ * out: device, batch trains with ranks r_k s_k, stride out_stride
+ * (0 = packed).  HBM-write bound; no workspace.
+ */
+HATT_API hatt_status tt_hadamard_explicit(const hatt_tt *x, const hatt_tt *y, double *out,
+                                 int64_t out_stride, void *stream);
+
+/*
+ * tt_round_plan / tt_round -- TT-Rounding (Alg. 1): right-to-left QR
+ * orthogonalisation, then left-to-right economy QR + SVD truncation.
+ * Bond rule: delta = tol ||a||_F / sqrt(d-1); keep the smallest rho >= 1
+ * whose discarded tail sum_{j>rho} sigma_j^2 <= delta^2 (all of them when
+ * tol <= 0), then rho = min(rho, max_rank) when max_rank > 0.
+ * Output at capacity shape cap (written by tt_round_plan to cap_out
+ * [d+1]: the input ranks, clamped to the economy-QR shapes), zero padded,
+ * kept ranks in out_rank (device int64 [batch][d+1]).
+ */
+HATT_API hatt_status tt_round_plan(const hatt_tt *a, int64_t *cap_out, size_t *ws_bytes, int64_t *out_elems);
+HATT_API hatt_status tt_round(const hatt_tt *a, int64_t max_rank, double tol, double *out,
+                     int64_t out_stride, int64_t *out_rank, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/*
+ * tt_norm -- Frobenius norm (Sec. 2.1) of every train, computed as
+ * ||B_1||_F after right-to-left QR orthogonalisation (the identity used by
+ * Alg. 1).  out: device double [batch].  Workspace from tt_norm_plan.
+ */
+HATT_API hatt_status tt_norm_plan(const hatt_tt *a, size_t *ws_bytes);
+HATT_API hatt_status tt_norm(const hatt_tt *a, double *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * hatt_sketch_fill -- materialise the seeded random Gaussian TT (Def. 2.1)
+ * with ranks ell[0..d] (ell[0] = ell[d] = 1) and mode sizes n[0..d-1]:
+ * entries N(0, 1/(ell_{k-1} n_k ell_k)) from Philox4x32-10 (key = seed,
+ * counter = (pair index low, pair index high, k, 0x5A7C), two 53-bit
+ * uniforms per pair of entries, Box-Muller).  out: device, packed cores.
+ */
+HATT_API hatt_status hatt_sketch_fill(uint64_t seed, int32_t d, const int64_t *n, const int64_t *ell,
+                             double *out, void *stream);
+
+/*
+ * Instrumentation (not thread-safe; for benchmarks).  Between
+ * hatt_profile_start() and hatt_profile_stop() every kernel launch the
+ * library enqueues is bracketed by two HIP events on the launching stream
+ * and attributed to one of HATT_PROFILE_CLASSES kernel classes (names from
+ * hatt_profile_class_name).  hatt_profile_stop() waits for those events and
+ * writes, per class, the summed event-to-event milliseconds to ms_out and
+ * the number of launcher calls to calls_out (both host arrays of length
+ * HATT_PROFILE_CLASSES).  A launcher call may enqueue more than one kernel
+ * (a split-K GEMM adds its reduction, a QR one kernel per tree level).
+ */
+#define HATT_PROFILE_CLASSES 8
+HATT_API hatt_status hatt_profile_start(void);
+HATT_API hatt_status hatt_profile_stop(double *ms_out, int64_t *calls_out);
+HATT_API const char *hatt_profile_class_name(int32_t cls);
+
+/* Message describing the last error of the calling thread ("" if none). */
+HATT_API const char *hatt_last_error(void);
+
+/* Library version string. */
+HATT_API const char *hatt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HATT_H_ */

@@ -1,0 +1,23 @@
+"""MI355X-native HaTT: recompression of the Hadamard product of two tensor
+trains without forming its partial Kronecker product cores.
+
+The arithmetic lives in the HIP library ``libhatt.so`` (C ABI in
+``include/hatt.h``); this package only marshals arguments and uses PyTorch
+for device memory and streams.  Importing the package does not load the
+library; the first call does, and fails loudly if it has not been built.
+"""
+
+from .api import (  # noqa: F401
+    TT,
+    Result,
+    hadamard_explicit,
+    norm,
+    plan,
+    profile_start,
+    profile_stop,
+    recompress,
+    round,
+    round_plan,
+    sketch_fill,
+    version,
+)

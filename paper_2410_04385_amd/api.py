@@ -1,0 +1,235 @@
+"""Python binding of libhatt: device memory and streams come from PyTorch;
+every arithmetic step runs in the HIP library behind the C ABI."""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import HattOpts, HattTT, check, i64_array, lib
+
+
+def _offsets(n: Sequence[int], r: Sequence[int]):
+    off, acc = [], 0
+    for k in range(len(n)):
+        off.append(acc)
+        acc += int(r[k]) * int(n[k]) * int(r[k + 1])
+    return off, acc
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class TT:
+    """``batch`` tensor trains of identical shape in one flat float64 device
+    tensor; core k of train b is the row-major block
+    data[b*stride + off[k] : ...] of shape (rank[k], n[k], rank[k+1])."""
+
+    def __init__(self, data: torch.Tensor, n: Sequence[int], ranks: Sequence[int], batch: int = 1,
+                 stride: Optional[int] = None):
+        self.n = [int(v) for v in n]
+        self.ranks = [int(v) for v in ranks]
+        self.d = len(self.n)
+        self.batch = int(batch)
+        self.off, self.total = _offsets(self.n, self.ranks)
+        self.stride = int(stride) if stride else self.total
+        if data.dtype != torch.float64 or data.dim() != 1:
+            raise ValueError("TT data must be a flat float64 tensor")
+        if data.numel() < (self.batch - 1) * self.stride + self.total:
+            raise ValueError("TT data too small for its shape")
+        self.data = data
+
+    @staticmethod
+    def empty(n, ranks, batch=1, device="cuda") -> "TT":
+        _, tot = _offsets(n, ranks)
+        return TT(torch.zeros(batch * tot, dtype=torch.float64, device=device), n, ranks, batch)
+
+    @staticmethod
+    def from_cores(trains, device="cuda") -> "TT":
+        """``trains``: one TT (list of arrays) or a list of TTs of one shape."""
+        if isinstance(trains[0], np.ndarray) or torch.is_tensor(trains[0]):
+            trains = [trains]
+        n = [int(c.shape[1]) for c in trains[0]]
+        ranks = [int(trains[0][0].shape[0])] + [int(c.shape[2]) for c in trains[0]]
+        flat = []
+        for t in trains:
+            if [int(c.shape[1]) for c in t] != n:
+                raise ValueError("trains differ in shape")
+            for c in t:
+                flat.append(np.ascontiguousarray(np.asarray(c, dtype=np.float64)).ravel())
+        host = torch.from_numpy(np.concatenate(flat))
+        return TT(host.to(device), n, ranks, len(trains))
+
+    def view(self):
+        n_arr, r_arr = i64_array(self.n), i64_array(self.ranks)
+        v = HattTT(self.d, self.batch, n_arr, r_arr, ctypes.c_void_p(self.data.data_ptr()), self.stride)
+        return v, (n_arr, r_arr)
+
+    def core(self, k: int, b: int = 0) -> torch.Tensor:
+        s = b * self.stride + self.off[k]
+        e = s + self.ranks[k] * self.n[k] * self.ranks[k + 1]
+        return self.data[s:e].view(self.ranks[k], self.n[k], self.ranks[k + 1])
+
+    def to_numpy(self, b: int = 0, kept: Optional[Sequence[int]] = None) -> List[np.ndarray]:
+        out = []
+        for k in range(self.d):
+            c = self.core(k, b).detach().cpu().numpy()
+            if kept is not None:
+                c = c[: int(kept[k]), :, : int(kept[k + 1])]
+            out.append(np.array(c))
+        return out
+
+
+@dataclass
+class Result:
+    out: TT                  # capacity-shape cores
+    ranks: torch.Tensor      # device int64 [batch, d+1]
+
+    def train(self, b: int = 0) -> List[np.ndarray]:
+        kept = self.ranks[b].cpu().tolist()
+        return self.out.to_numpy(b, kept)
+
+
+def _opts(ell, max_rank, tol, seed, variant, ep, d):
+    ell_arr = None
+    if not np.isscalar(ell):
+        if len(ell) != d + 1:
+            raise ValueError("per-bond ell needs d+1 entries")
+        ell_arr = i64_array(ell)
+        ell_u = 0
+    else:
+        ell_u = int(ell)
+    o = HattOpts(int(variant), float(ep), ell_u, ell_arr if ell_arr is not None else None,
+                 int(max_rank), float(tol), int(seed) & 0xFFFFFFFFFFFFFFFF)
+    return o, ell_arr
+
+
+def plan(x: TT, y: TT, ell, max_rank: int = 0, tol: float = 0.0, seed: int = 0, variant: int = 1,
+         ep: float = 0.0):
+    xv, kx = x.view()
+    yv, ky = y.view()
+    o, ka = _opts(ell, max_rank, tol, seed, variant, ep, x.d)
+    ell_out = (ctypes.c_int64 * (x.d + 1))()
+    ws = ctypes.c_size_t(0)
+    oe = ctypes.c_int64(0)
+    check("hatt_plan", lib().hatt_plan(ctypes.byref(xv), ctypes.byref(yv), ctypes.byref(o), ell_out,
+                                       ctypes.byref(ws), ctypes.byref(oe)))
+    return {"ell": list(ell_out), "ws_bytes": int(ws.value), "out_elems": int(oe.value)}
+
+
+def recompress(x: TT, y: TT, ell, *, max_rank: int = 0, tol: float = 0.0, seed: int = 0,
+               sketch: Optional[TT] = None, variant: int = 1, ep: float = 0.0,
+               workspace: Optional[torch.Tensor] = None, out: Optional[TT] = None,
+               ranks: Optional[torch.Tensor] = None, stream=None) -> Result:
+    """HaTT (Alg. 4) of x (.) y for every train of the batch, optionally
+    truncated by TT-Rounding to ``max_rank`` / ``tol``."""
+    p = plan(x, y, ell, max_rank, tol, seed, variant, ep)
+    dev = x.data.device
+    if out is None:
+        out = TT.empty(x.n, p["ell"], x.batch, device=dev)
+    if ranks is None:
+        ranks = torch.empty((x.batch, x.d + 1), dtype=torch.int64, device=dev)
+    if workspace is None or workspace.numel() < p["ws_bytes"]:
+        workspace = torch.empty(max(p["ws_bytes"], 1), dtype=torch.uint8, device=dev)
+    xv, kx = x.view()
+    yv, ky = y.view()
+    o, ka = _opts(ell, max_rank, tol, seed, variant, ep, x.d)
+    sk_ptr = None
+    keep = None
+    if sketch is not None:
+        sv, keep = sketch.view()
+        sk_ptr = ctypes.byref(sv)
+    st = lib().hatt_recompress(ctypes.byref(xv), ctypes.byref(yv), sk_ptr, ctypes.byref(o),
+                               ctypes.c_void_p(out.data.data_ptr()), out.stride,
+                               ctypes.c_void_p(ranks.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+                               workspace.numel(), _stream_ptr(stream))
+    check("hatt_recompress", st)
+    return Result(out, ranks)
+
+
+def hadamard_explicit(x: TT, y: TT, out: Optional[TT] = None, stream=None) -> TT:
+    """Explicit PKP cores of x (.) y (ranks r_k s_k)."""
+    rr = [a * b for a, b in zip(x.ranks, y.ranks)]
+    if out is None:
+        out = TT.empty(x.n, rr, x.batch, device=x.data.device)
+    xv, kx = x.view()
+    yv, ky = y.view()
+    check("tt_hadamard_explicit", lib().tt_hadamard_explicit(
+        ctypes.byref(xv), ctypes.byref(yv), ctypes.c_void_p(out.data.data_ptr()), out.stride,
+        _stream_ptr(stream)))
+    return out
+
+
+def round_plan(a: TT):
+    av, ka = a.view()
+    cap = (ctypes.c_int64 * (a.d + 1))()
+    ws = ctypes.c_size_t(0)
+    oe = ctypes.c_int64(0)
+    check("tt_round_plan", lib().tt_round_plan(ctypes.byref(av), cap, ctypes.byref(ws), ctypes.byref(oe)))
+    return {"cap": list(cap), "ws_bytes": int(ws.value), "out_elems": int(oe.value)}
+
+
+def round(a: TT, max_rank: int = 0, tol: float = 0.0, *, workspace: Optional[torch.Tensor] = None,
+          stream=None) -> Result:  # noqa: A001 - mirrors the C name tt_round
+    """TT-Rounding (Alg. 1) of every train."""
+    p = round_plan(a)
+    dev = a.data.device
+    out = TT.empty(a.n, p["cap"], a.batch, device=dev)
+    ranks = torch.empty((a.batch, a.d + 1), dtype=torch.int64, device=dev)
+    if workspace is None or workspace.numel() < p["ws_bytes"]:
+        workspace = torch.empty(max(p["ws_bytes"], 1), dtype=torch.uint8, device=dev)
+    av, ka = a.view()
+    check("tt_round", lib().tt_round(ctypes.byref(av), int(max_rank), float(tol),
+                                     ctypes.c_void_p(out.data.data_ptr()), out.stride,
+                                     ctypes.c_void_p(ranks.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+                                     workspace.numel(), _stream_ptr(stream)))
+    return Result(out, ranks)
+
+
+def norm(a: TT, *, workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Frobenius norms (device tensor of length batch)."""
+    av, ka = a.view()
+    ws = ctypes.c_size_t(0)
+    check("tt_norm_plan", lib().tt_norm_plan(ctypes.byref(av), ctypes.byref(ws)))
+    dev = a.data.device
+    if workspace is None or workspace.numel() < ws.value:
+        workspace = torch.empty(max(ws.value, 1), dtype=torch.uint8, device=dev)
+    out = torch.empty(a.batch, dtype=torch.float64, device=dev)
+    check("tt_norm", lib().tt_norm(ctypes.byref(av), ctypes.c_void_p(out.data_ptr()),
+                                   ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                   _stream_ptr(stream)))
+    return out
+
+
+def sketch_fill(seed: int, n: Sequence[int], ell: Sequence[int], device="cuda", stream=None) -> TT:
+    """The seeded random Gaussian TT of Def. 2.1 (Philox4x32-10)."""
+    t = TT.empty(n, ell, 1, device=device)
+    check("hatt_sketch_fill", lib().hatt_sketch_fill(int(seed) & 0xFFFFFFFFFFFFFFFF, len(n), i64_array(n),
+                                                     i64_array(ell), ctypes.c_void_p(t.data.data_ptr()),
+                                                     _stream_ptr(stream)))
+    return t
+
+
+def profile_start() -> None:
+    check("hatt_profile_start", lib().hatt_profile_start())
+
+
+def profile_stop() -> dict:
+    """Per kernel class: (milliseconds summed over launches, launcher calls)."""
+    n = _lib.PROFILE_CLASSES
+    ms = (ctypes.c_double * n)()
+    calls = (ctypes.c_int64 * n)()
+    check("hatt_profile_stop", lib().hatt_profile_stop(ms, calls))
+    return {lib().hatt_profile_class_name(i).decode(): (float(ms[i]), int(calls[i])) for i in range(n)}
+
+
+def version() -> str:
+    return lib().hatt_version().decode()

@@ -1,0 +1,148 @@
+// Internal declarations shared by the host orchestration and the kernel
+// translation units of libhatt.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace hatt {
+
+// Largest column count of one TSQR panel and of the in-LDS Jacobi SVD.
+constexpr int kQrMaxCols = 128;
+constexpr int kSvdMaxN = 96;
+// Doubles of dynamic LDS a TSQR block may use (of the 160 KiB per CU).
+constexpr int kQrLdsDoubles = 19456;
+
+// ---------------------------------------------------------------------------
+// Strided matrix view used by the generic kernels: element (r, c) of pair p
+// lives at ptr[p * bs + r * rs + c * cs].
+struct Mat {
+  double *ptr;
+  int64_t rs, cs, bs;
+};
+struct CMat {
+  const double *ptr;
+  int64_t rs, cs, bs;
+};
+
+// ---- sketch / elementwise kernels (k_basic.hip) ---------------------------
+hipError_t launch_sketch_fill(uint64_t seed, int core, int64_t count, double scale, double *out,
+                              hipStream_t s);
+
+// A(a s0 + b, i, a' s1 + b') = X(a, i, a') Y(b, i, b') for `batch` pairs.
+struct PkpArgs {
+  const double *x;
+  const double *y;
+  double *out;
+  int64_t r0, r1, s0, s1, n;
+  int64_t xs, ys, os;  // batch strides (elements)
+  int batch;
+};
+hipError_t launch_pkp(const PkpArgs &a, hipStream_t s);
+
+// W(a s + b, g) = sum_i X(a, i) Y(b, i) R(g, i) (last cores, right rank 1).
+struct LastArgs {
+  const double *x;
+  const double *y;
+  const double *r;
+  double *w;
+  int64_t rx, sy, l, n;
+  int64_t xs, ys, rsb, ws;  // batch strides
+  int batch;
+};
+hipError_t launch_hpcrl_last(const LastArgs &a, hipStream_t s);
+
+// Sandwich: out_{i,g}(a', b') = sum_{a,b} YL_i(a', a) C_g(a, b) ZR_i(b, b')
+// for i < n, g < G.  All operands strided; see hatt.cpp for the two uses
+// (W_L columns of HPCRL and the PKP-free core update).
+struct SandwichArgs {
+  const double *yl;  // YL_i(a', a) = yl[p*ylb + i*yli + a'*ylr + a*ylc]
+  int64_t ylb, yli, ylr, ylc;
+  const double *zr;  // ZR_i(b, b') = zr[p*zrb + i*zri + b*zrr + b'*zrc]
+  int64_t zrb, zri, zrr, zrc;
+  const double *c;   // C_g(a, b) = c[p*cb + g*cg + a*ca + b*cbb]
+  int64_t cb, cg, ca, cbb;
+  double *o;         // out = o[p*ob + i*oi + g*og + a'*oa + b'*obb]
+  int64_t ob, oi, og, oa, obb;
+  int RA, RI, SI, SO;  // YL is RA x RI, C is RI x SI, ZR is SI x SO
+  int64_t n, G;
+  int batch;
+};
+hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s);
+
+// Batched strided copy: dst(r, c) = src(r, c) for an M x N block.
+hipError_t launch_copy(CMat src, Mat dst, int64_t M, int64_t N, int batch, hipStream_t s);
+hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t s);
+hipError_t launch_fill_i64(int64_t *p, int64_t count, int64_t v, hipStream_t s);
+// dst[p * len + k] = pattern[k] for p < batch, k < len (len <= kMaxRankPattern).
+constexpr int kMaxRankPattern = 256;
+hipError_t launch_rank_pattern(int64_t *dst, int batch, int len, const int64_t *host_pattern, hipStream_t s);
+
+// ---- GEMM (k_gemm.hip) -----------------------------------------------------
+// C = alpha A B + beta C, A is M x K, B is K x N, batched.  With ksplit > 1
+// the K range is cut in ksplit chunks whose partial products go to `part`
+// (batch * ksplit * M * N doubles) and are summed in a fixed order.
+struct GemmArgs {
+  CMat A, B;
+  Mat C;
+  int64_t M, N, K;
+  double alpha, beta;
+  int batch;
+  int ksplit;
+  double *part;
+};
+hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
+int gemm_pick_ksplit(int64_t M, int64_t N, int64_t K, int batch);
+
+// ---- TSQR (k_qr.hip) -------------------------------------------------------
+// Economy Householder QR of an m x n matrix per pair, by a tree of block
+// QRs (n <= kQrMaxCols).  k = min(m, n) columns: Q (m x k) is written to `q`
+// and R (k x n, upper trapezoidal, diag >= 0) to `r` when r.ptr != nullptr.
+constexpr int kQrMaxLevels = 64;
+struct QrPlan {
+  int64_t m, n, k;
+  int levels;
+  int64_t rows[kQrMaxLevels];    // rows of the matrix factored at each level
+  int64_t blocks[kQrMaxLevels];  // row blocks per level
+  int64_t off_v[kQrMaxLevels], off_tau[kQrMaxLevels], off_stack[kQrMaxLevels];
+  int64_t off_rtop;
+  int64_t ws_doubles;            // per pair
+};
+bool qr_make_plan(int64_t m, int64_t n, QrPlan *p);
+hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_t ws_pair_stride,
+                       int batch, hipStream_t s);
+
+// ---- Jacobi SVD + rank choice (k_svd.hip) ----------------------------------
+// For each pair: R (kr x nc, row-major, kr <= nc <= kSvdMaxN) = U S V^T by
+// one-sided Jacobi.  Chooses rho (tail rule, cap, and rho <= kmax with
+// kmax = min(prev_rank * n_mode, nc) when prev_rank != nullptr, else
+// min(kr, nc)), then writes U (kr x ucap, row-major, columns >= rho zero) and
+// SVt = S V^T (ucap x nc, rows >= rho zero).  delta2[p] holds
+// tol^2 ||A||^2 / (d-1); the first bond computes it from ||R||_F.
+struct SvdArgs {
+  const double *r;
+  int64_t rbs;
+  int kr, nc, ucap;
+  double *u;
+  int64_t ubs;
+  double *svt;
+  int64_t sbs;
+  int batch;
+  double *delta2;        // [batch]
+  int first_bond;
+  double tol2_over_dm1;  // tol^2 / (d-1), 0 for no tolerance
+  int64_t cap;           // max_rank, <= 0 for none
+  const int64_t *prev_rank;  // device, element p * rank_bs (may be null)
+  int64_t n_mode;
+  int64_t *rank_out;     // device, element p * rank_bs
+  int64_t rank_bs;
+};
+hipError_t launch_svd_trunc(const SvdArgs &a, hipStream_t s);
+
+// Frobenius norm of a batch of contiguous blocks: out[p] = ||x_p||.
+hipError_t launch_block_norm(const double *x, int64_t count, int64_t bs, double *out, int batch,
+                             hipStream_t s);
+
+}  // namespace hatt

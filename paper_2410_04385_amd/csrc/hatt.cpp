@@ -1,0 +1,847 @@
+// Host side of libhatt: validation, planning, workspace carving and the
+// kernel sequences of HaTT (Alg. 3 + Alg. 4), TT-Rounding (Alg. 1), the
+// explicit PKP Hadamard product and the TT norm.  Everything here runs on the
+// host and only enqueues kernels; no device memory is allocated.
+#include <math.h>
+#include <string.h>
+
+#include <cmath>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "hatt.h"
+
+using namespace hatt;
+
+namespace {
+
+thread_local std::string g_err;
+
+hatt_status fail(hatt_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+struct Shape {
+  int d = 0;
+  int batch = 0;
+  std::vector<int64_t> n, r, off;
+  int64_t total = 0;
+  int64_t stride = 0;
+  double *data = nullptr;
+};
+
+void make_offsets(const std::vector<int64_t> &n, const std::vector<int64_t> &r,
+                  std::vector<int64_t> *off, int64_t *total) {
+  const int d = (int)n.size();
+  off->assign(d, 0);
+  int64_t acc = 0;
+  for (int k = 0; k < d; ++k) {
+    (*off)[k] = acc;
+    acc += r[k] * n[k] * r[k + 1];
+  }
+  *total = acc;
+}
+
+hatt_status read_tt(const hatt_tt *t, const char *name, Shape *s, bool need_data) {
+  if (t == nullptr) return fail(HATT_EINVAL, std::string(name) + ": NULL tensor view");
+  if (t->d < 1) return fail(HATT_EINVAL, std::string(name) + ": d must be >= 1");
+  if (t->batch < 1) return fail(HATT_EINVAL, std::string(name) + ": batch must be >= 1");
+  if (t->n == nullptr || t->rank == nullptr)
+    return fail(HATT_EINVAL, std::string(name) + ": NULL n or rank array");
+  s->d = t->d;
+  s->batch = t->batch;
+  s->n.assign(t->n, t->n + t->d);
+  s->r.assign(t->rank, t->rank + t->d + 1);
+  for (int k = 0; k < t->d; ++k)
+    if (s->n[k] < 1) return fail(HATT_ESHAPE, std::string(name) + ": mode size < 1");
+  for (int k = 0; k <= t->d; ++k)
+    if (s->r[k] < 1) return fail(HATT_ESHAPE, std::string(name) + ": rank < 1");
+  if (s->r[0] != 1 || s->r[t->d] != 1)
+    return fail(HATT_ESHAPE, std::string(name) + ": rank[0] and rank[d] must be 1");
+  make_offsets(s->n, s->r, &s->off, &s->total);
+  if (t->batch_stride != 0 && t->batch_stride < s->total)
+    return fail(HATT_EINVAL, std::string(name) + ": batch_stride smaller than one train");
+  s->stride = t->batch_stride ? t->batch_stride : s->total;
+  s->data = t->data;
+  if (need_data && s->data == nullptr) return fail(HATT_EINVAL, std::string(name) + ": NULL data");
+  return HATT_OK;
+}
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures.
+struct Ws {
+  char *base;
+  size_t off = 0;
+  explicit Ws(void *b) : base((char *)b) {}
+  double *d(int64_t count) {
+    size_t bytes = ((size_t)std::max<int64_t>(count, 1) * 8 + 255) & ~(size_t)255;
+    double *p = base ? (double *)(base + off) : nullptr;
+    off += bytes;
+    return p;
+  }
+  int64_t *i64(int64_t count) { return (int64_t *)d(count); }
+};
+
+// Optional per-launch timing: when enabled, every launcher call below is
+// bracketed by two HIP events on its stream and attributed to a kernel class.
+enum { P_SKETCH, P_PKP, P_LAST, P_SANDWICH, P_GEMM, P_TSQR, P_SVD, P_OTHER, P_NCLASS };
+const char *kClassNames[P_NCLASS] = {"sketch_fill", "pkp_expand", "hpcrl_last", "sandwich",
+                                     "gemm_f64",    "tsqr",       "svd_trunc",  "copy_fill_norm"};
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+};
+struct Profiler {
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+Profiler g_prof;
+
+int class_of(const char *expr) {
+  if (strstr(expr, "launch_gemm")) return P_GEMM;
+  if (strstr(expr, "launch_tsqr")) return P_TSQR;
+  if (strstr(expr, "launch_sandwich")) return P_SANDWICH;
+  if (strstr(expr, "launch_svd")) return P_SVD;
+  if (strstr(expr, "launch_pkp")) return P_PKP;
+  if (strstr(expr, "launch_hpcrl_last")) return P_LAST;
+  if (strstr(expr, "launch_sketch")) return P_SKETCH;
+  return P_OTHER;
+}
+
+#define LAUNCH(expr)                                                            \
+  do {                                                                          \
+    if (run) {                                                                  \
+      hipEvent_t pa_ = nullptr, pb_ = nullptr;                                  \
+      if (g_prof.on) {                                                          \
+        pa_ = g_prof.get();                                                     \
+        pb_ = g_prof.get();                                                     \
+        if (pa_) (void)hipEventRecord(pa_, st);                                       \
+      }                                                                         \
+      hipError_t e_ = (expr);                                                   \
+      if (g_prof.on && pa_ && pb_) {                                            \
+        (void)hipEventRecord(pb_, st);                                          \
+        g_prof.recs.push_back(ProfRec{class_of(#expr), pa_, pb_});              \
+      }                                                                         \
+      if (e_ != hipSuccess)                                                     \
+        return fail(HATT_EDEVICE, std::string("HIP error in ") + #expr + ": " + \
+                                      hipGetErrorString(e_));                   \
+    }                                                                           \
+  } while (0)
+
+std::vector<int64_t> clamp_ell(const std::vector<int64_t> &n, const std::vector<int64_t> &rx,
+                               const std::vector<int64_t> &ry, const std::vector<int64_t> &req) {
+  const int d = (int)n.size();
+  std::vector<int64_t> l(d + 1, 1);
+  for (int k = 1; k < d; ++k) l[k] = std::max<int64_t>(1, std::min(req[k], rx[k] * ry[k]));
+  for (int k = 1; k < d; ++k) l[k] = std::min(l[k], l[k - 1] * n[k - 1]);
+  for (int k = d - 1; k >= 1; --k) l[k] = std::min(l[k], n[k] * l[k + 1]);
+  return l;
+}
+
+// GEMM helper: picks the split and checks the partial buffer.
+struct GemmCtx {
+  double *part;
+  int64_t part_cap;   // doubles available
+  int64_t part_need;  // max requested (measuring)
+};
+
+hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_t N, int64_t K,
+                 double alpha, double beta, int batch, hipStream_t st, bool allow_split) {
+  GemmArgs g{};
+  g.A = A;
+  g.B = B;
+  g.C = C;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.alpha = alpha;
+  g.beta = beta;
+  g.batch = batch;
+  g.ksplit = allow_split ? gemm_pick_ksplit(M, N, K, batch) : 1;
+  const int64_t need = g.ksplit > 1 ? (int64_t)batch * g.ksplit * M * N : 0;
+  gc.part_need = std::max(gc.part_need, need);
+  if (g.ksplit > 1 && need > gc.part_cap) g.ksplit = 1;
+  g.part = gc.part;
+  LAUNCH(launch_gemm(g, st));
+  return HATT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// TT-Rounding (Alg. 1) of `batch` trains.
+//   src: cores with ranks rin (layout from rin), pair stride sstride.
+//   If in_place, the work is done directly on src (then rin must already
+//   satisfy the economy-QR shape clamps and the output capacities equal rin);
+//   else src is copied to a work buffer first.
+//   out: capacity layout `cap`, pair stride ostride; orank: [batch][d+1].
+struct RoundSpec {
+  std::vector<int64_t> n, rin, cap;
+  double *src;
+  int64_t sstride;
+  bool in_place;
+  double *out;
+  int64_t ostride;
+  int64_t *orank;
+  int64_t max_rank;
+  double tol;
+  int batch;
+  bool norm_only;     // stop after the right-to-left sweep and write ||B_1||
+  double *norm_out;   // [batch] (norm_only)
+};
+
+std::vector<int64_t> round_caps(const std::vector<int64_t> &n, const std::vector<int64_t> &r) {
+  const int d = (int)n.size();
+  std::vector<int64_t> b(r);
+  b[d] = 1;
+  for (int k = d - 1; k >= 1; --k) b[k] = std::min(r[k], n[k] * b[k + 1]);
+  std::vector<int64_t> c(b);
+  c[0] = 1;
+  for (int k = 1; k < d; ++k) c[k] = std::min(c[k], c[k - 1] * n[k - 1]);
+  return c;
+}
+
+hatt_status round_run(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipStream_t st) {
+  const int d = (int)sp.n.size();
+  const int P = sp.batch;
+  const auto &n = sp.n;
+  std::vector<int64_t> soff;
+  int64_t stot;
+  make_offsets(n, sp.rin, &soff, &stot);
+  // right-to-left ranks
+  std::vector<int64_t> rb(sp.rin);
+  for (int c = d - 1; c >= 1; --c) rb[c] = std::min(sp.rin[c], n[c] * rb[c + 1]);
+  const auto &cap = sp.cap;
+  // --- sizes
+  int64_t qr_ws = 0, qbuf = 1, rbuf = 1, ubuf = 1, sbuf = 1, tbuf = 1, tmp = 1;
+  std::vector<QrPlan> plan_rl(d), plan_lr(d);
+  for (int c = d - 1; c >= 1; --c) {
+    const int64_t m = n[c] * rb[c + 1], nc = sp.rin[c];
+    if (!qr_make_plan(m, nc, &plan_rl[c]))
+      return fail(HATT_EUNSUPPORTED, "TT-Rounding: a right-to-left QR of " + std::to_string(m) + " x " +
+                                         std::to_string(nc) + " exceeds this build's QR limits (<= " +
+                                         std::to_string(kQrMaxCols) + " columns)");
+    qr_ws = std::max(qr_ws, plan_rl[c].ws_doubles);
+    rbuf = std::max(rbuf, plan_rl[c].k * nc);
+    tmp = std::max(tmp, sp.rin[c - 1] * n[c - 1] * plan_rl[c].k);
+  }
+  if (!sp.norm_only) {
+    for (int c = 0; c < d - 1; ++c) {
+      const int64_t m = cap[c] * n[c], nc = rb[c + 1];
+      if (!qr_make_plan(m, nc, &plan_lr[c]))
+        return fail(HATT_EUNSUPPORTED, "TT-Rounding: a left-to-right QR of " + std::to_string(m) + " x " +
+                                           std::to_string(nc) + " exceeds this build's QR limits");
+      if (nc > kSvdMaxN)
+        return fail(HATT_EUNSUPPORTED, "TT-Rounding: bond rank " + std::to_string(nc) +
+                                           " exceeds this build's SVD limit (" + std::to_string(kSvdMaxN) + ")");
+      const int64_t k = plan_lr[c].k;
+      qr_ws = std::max(qr_ws, plan_lr[c].ws_doubles);
+      qbuf = std::max(qbuf, m * k);
+      rbuf = std::max(rbuf, k * nc);
+      ubuf = std::max(ubuf, k * cap[c + 1]);
+      sbuf = std::max(sbuf, cap[c + 1] * nc);
+      tbuf = std::max(tbuf, cap[c + 1] * n[c + 1] * rb[c + 2]);
+    }
+  }
+  double *work = sp.in_place ? sp.src : ws.d((int64_t)P * stot);
+  const int64_t wstride = sp.in_place ? sp.sstride : stot;
+  double *wqr = ws.d((int64_t)P * qr_ws);
+  double *Qb = ws.d((int64_t)P * qbuf);
+  double *Rb = ws.d((int64_t)P * rbuf);
+  double *Ub = ws.d((int64_t)P * ubuf);
+  double *Sb = ws.d((int64_t)P * sbuf);
+  double *T0 = ws.d((int64_t)P * tbuf);
+  double *T1 = ws.d((int64_t)P * tbuf);
+  double *Tm = ws.d((int64_t)P * tmp);
+  double *dl2 = ws.d(P);
+
+  if (!sp.in_place)
+    LAUNCH(launch_copy(CMat{sp.src, stot, 1, sp.sstride}, Mat{work, stot, 1, stot}, 1, stot, P, st));
+  if (d == 1) {
+    if (sp.norm_only) {
+      LAUNCH(launch_block_norm(work, stot, wstride, sp.norm_out, P, st));
+    } else {
+      LAUNCH(launch_copy(CMat{work, stot, 1, wstride}, Mat{sp.out, stot, 1, sp.ostride}, 1, stot, P, st));
+      LAUNCH(launch_fill_i64(sp.orank, (int64_t)P * 2, 1, st));
+    }
+    return HATT_OK;
+  }
+  // --- right-to-left orthogonalisation; core c layout: [*][n_c][rb_{c+1}] compact
+  for (int c = d - 1; c >= 1; --c) {
+    const QrPlan &pl = plan_rl[c];
+    const int64_t m = n[c] * rb[c + 1], nc = sp.rin[c], k = pl.k;
+    double *core = work + soff[c];
+    // H(B_c)^T is m x nc: element (j, a) = core[a * m + j]
+    LAUNCH(launch_tsqr(pl, CMat{core, 1, m, wstride}, Mat{core, 1, m, wstride}, Mat{Rb, nc, 1, rbuf},
+                       wqr, qr_ws, P, st));
+    // V(B_{c-1}) R^T, V(B_{c-1}) is (rin_{c-1} n_{c-1}) x nc with row stride nc
+    double *prev = work + soff[c - 1];
+    const int64_t mp = sp.rin[c - 1] * n[c - 1];
+    hatt_status s = gemm(run, gc, CMat{prev, nc, 1, wstride}, CMat{Rb, 1, nc, rbuf}, Mat{Tm, k, 1, tmp}, mp,
+                         k, nc, 1.0, 0.0, P, st, false);
+    if (s != HATT_OK) return s;
+    LAUNCH(launch_copy(CMat{Tm, k, 1, tmp}, Mat{prev, k, 1, wstride}, mp, k, P, st));
+  }
+  if (sp.norm_only) {
+    LAUNCH(launch_block_norm(work + soff[0], n[0] * rb[1], wstride, sp.norm_out, P, st));
+    return HATT_OK;
+  }
+  // --- left-to-right truncation
+  LAUNCH(launch_fill_i64(sp.orank, (int64_t)P * (d + 1), 1, st));
+  std::vector<int64_t> ooff;
+  int64_t otot;
+  make_offsets(n, cap, &ooff, &otot);
+  const double tol2 = (sp.tol > 0.0) ? sp.tol * sp.tol / (double)(d - 1) : 0.0;
+  double *Tcur = nullptr, *Tnext = T0;
+  for (int c = 0; c < d - 1; ++c) {
+    const QrPlan &pl = plan_lr[c];
+    const int64_t m = cap[c] * n[c], nc = rb[c + 1], k = pl.k;
+    CMat V = (c == 0) ? CMat{work + soff[0], nc, 1, wstride} : CMat{Tcur, nc, 1, tbuf};
+    LAUNCH(launch_tsqr(pl, V, Mat{Qb, k, 1, qbuf}, Mat{Rb, nc, 1, rbuf}, wqr, qr_ws, P, st));
+    SvdArgs sa{};
+    sa.r = Rb;
+    sa.rbs = rbuf;
+    sa.kr = (int)k;
+    sa.nc = (int)nc;
+    sa.ucap = (int)cap[c + 1];
+    sa.u = Ub;
+    sa.ubs = ubuf;
+    sa.svt = Sb;
+    sa.sbs = sbuf;
+    sa.batch = P;
+    sa.delta2 = dl2;
+    sa.first_bond = (c == 0);
+    sa.tol2_over_dm1 = tol2;
+    sa.cap = sp.max_rank;
+    sa.prev_rank = (c == 0) ? nullptr : sp.orank + c;
+    sa.n_mode = n[c];
+    sa.rank_out = sp.orank + c + 1;
+    sa.rank_bs = d + 1;
+    if (k > nc) return fail(HATT_EUNSUPPORTED, "internal: QR rank exceeds columns");
+    LAUNCH(launch_svd_trunc(sa, st));
+    // out core c = Q U  (m x cap_{c+1})
+    hatt_status s = gemm(run, gc, CMat{Qb, k, 1, qbuf}, CMat{Ub, cap[c + 1], 1, ubuf},
+                         Mat{sp.out + ooff[c], cap[c + 1], 1, sp.ostride}, m, cap[c + 1], k, 1.0, 0.0, P, st, false);
+    if (s != HATT_OK) return s;
+    // next core = SVt H(B_{c+1}):  (cap_{c+1} x nc) (nc x n_{c+1} rb_{c+2})
+    const int64_t ncol = n[c + 1] * rb[c + 2];
+    s = gemm(run, gc, CMat{Sb, nc, 1, sbuf}, CMat{work + soff[c + 1], ncol, 1, wstride},
+             Mat{Tnext, ncol, 1, tbuf}, cap[c + 1], ncol, nc, 1.0, 0.0, P, st, false);
+    if (s != HATT_OK) return s;
+    Tcur = Tnext;
+    Tnext = (Tnext == T0) ? T1 : T0;
+  }
+  // last core
+  LAUNCH(launch_copy(CMat{Tcur, 1, 1, tbuf}, Mat{sp.out + ooff[d - 1], 1, 1, sp.ostride}, 1,
+                     cap[d - 1] * n[d - 1], P, st));
+  return HATT_OK;
+}
+
+// ---------------------------------------------------------------------------
+struct HattSpec {
+  Shape X, Y;
+  std::vector<int64_t> ell;
+  const double *sketch;  // explicit sketch data or nullptr
+  int64_t sketch_stride;
+  hatt_opts o;
+  double *out;
+  int64_t ostride;
+  int64_t *orank;
+};
+
+hatt_status hatt_run(bool run, const HattSpec &sp, Ws &ws, hipStream_t st) {
+  const int d = sp.X.d, P = sp.X.batch;
+  const auto &n = sp.X.n, &r = sp.X.r, &s = sp.Y.r, &l = sp.ell;
+  std::vector<int64_t> ooff, skoff;
+  int64_t otot, sktot;
+  make_offsets(n, l, &ooff, &otot);
+  make_offsets(n, l, &skoff, &sktot);
+  const double *xd = sp.X.data, *yd = sp.Y.data;
+  const int64_t xs = sp.X.stride, ys = sp.Y.stride;
+
+  GemmCtx gc{nullptr, 0, 0};
+  // ---- sizes
+  std::vector<int64_t> woff(d + 1, 0);
+  int64_t wtot = 0;
+  for (int b = 1; b < d; ++b) {
+    woff[b] = wtot;
+    wtot += r[b] * s[b] * l[b];
+  }
+  int64_t wlsz = 1, xsz = 1, ysz = 1, msz = 1, qrws = 0;
+  std::vector<QrPlan> qp(d);
+  for (int c = 1; c <= d - 2; ++c) wlsz = std::max(wlsz, r[c] * s[c] * n[c] * l[c + 1]);
+  for (int c = 0; c < d; ++c) xsz = std::max(xsz, l[c] * n[c] * r[c + 1] * s[c + 1]);
+  for (int c = 0; c < d - 1; ++c) {
+    ysz = std::max(ysz, l[c] * n[c] * l[c + 1]);
+    msz = std::max(msz, l[c + 1] * r[c + 1] * s[c + 1]);
+    if (!qr_make_plan(l[c] * n[c], l[c + 1], &qp[c]))
+      return fail(HATT_EUNSUPPORTED, "HaTT: sketch width " + std::to_string(l[c + 1]) +
+                                         " exceeds this build's QR limit (" + std::to_string(kQrMaxCols) + ")");
+    qrws = std::max(qrws, qp[c].ws_doubles);
+  }
+  double *sk = nullptr;
+  int64_t sks = 0;
+  if (sp.sketch) {
+    sk = (double *)sp.sketch;
+    sks = sp.sketch_stride;
+  } else {
+    sk = ws.d(sktot);
+    sks = 0;
+  }
+  double *W = ws.d((int64_t)P * std::max<int64_t>(wtot, 1));
+  double *WL = ws.d((int64_t)P * wlsz);
+  double *Xc = ws.d((int64_t)P * xsz);
+  double *Yb = ws.d((int64_t)P * ysz);
+  double *Mb = ws.d((int64_t)P * msz);
+  double *wqr = ws.d((int64_t)P * std::max<int64_t>(qrws, 1));
+  // split-K partials: measured below by a dry pass over the GEMM shapes
+  int64_t part_need = 0;
+  {
+    auto acc = [&](int64_t M, int64_t N, int64_t K) {
+      int ks = gemm_pick_ksplit(M, N, K, P);
+      if (ks > 1) part_need = std::max(part_need, (int64_t)P * ks * M * N);
+    };
+    for (int c = d - 2; c >= 1; --c) acc(r[c] * s[c], l[c], n[c] * l[c + 1]);
+    for (int c = 0; c < d - 1; ++c) {
+      acc(l[c] * n[c], l[c + 1], r[c + 1] * s[c + 1]);
+      acc(l[c + 1], r[c + 1] * s[c + 1], l[c] * n[c]);
+    }
+  }
+  gc.part = ws.d(std::max<int64_t>(part_need, 1));
+  gc.part_cap = part_need;
+
+  if (d == 1) {
+    LAUNCH(launch_fill_i64(sp.orank, (int64_t)P * 2, 1, st));
+    PkpArgs pa{xd, yd, sp.out, 1, 1, 1, 1, n[0], xs, ys, sp.ostride, P};
+    LAUNCH(launch_pkp(pa, st));
+    return HATT_OK;
+  }
+  if (!sp.sketch) {
+    for (int k = 0; k < d; ++k) {
+      const int64_t cnt = l[k] * n[k] * l[k + 1];
+      LAUNCH(launch_sketch_fill(sp.o.seed, k, cnt, 1.0 / sqrt((double)cnt), sk + skoff[k], st));
+    }
+  }
+  // ---- HPCRL (Alg. 3), HaTT-1 split
+  {
+    LastArgs la{};
+    la.x = xd + sp.X.off[d - 1];
+    la.y = yd + sp.Y.off[d - 1];
+    la.r = sk + skoff[d - 1];
+    la.w = W + woff[d - 1];
+    la.rx = r[d - 1];
+    la.sy = s[d - 1];
+    la.l = l[d - 1];
+    la.n = n[d - 1];
+    la.xs = xs;
+    la.ys = ys;
+    la.rsb = sks;
+    la.ws = wtot;
+    la.batch = P;
+    LAUNCH(launch_hpcrl_last(la, st));
+  }
+  for (int c = d - 2; c >= 1; --c) {
+    SandwichArgs a{};
+    a.yl = xd + sp.X.off[c];
+    a.ylb = xs;
+    a.yli = r[c + 1];
+    a.ylr = n[c] * r[c + 1];
+    a.ylc = 1;
+    a.zr = yd + sp.Y.off[c];
+    a.zrb = ys;
+    a.zri = s[c + 1];
+    a.zrr = 1;
+    a.zrc = n[c] * s[c + 1];
+    a.c = W + woff[c + 1];
+    a.cb = wtot;
+    a.cg = 1;
+    a.ca = s[c + 1] * l[c + 1];
+    a.cbb = l[c + 1];
+    a.o = WL;
+    a.ob = wlsz;
+    a.oi = l[c + 1];
+    a.og = 1;
+    a.oa = s[c] * n[c] * l[c + 1];
+    a.obb = n[c] * l[c + 1];
+    a.RA = (int)r[c];
+    a.RI = (int)r[c + 1];
+    a.SI = (int)s[c + 1];
+    a.SO = (int)s[c];
+    a.n = n[c];
+    a.G = l[c + 1];
+    a.batch = P;
+    LAUNCH(launch_sandwich(a, st));
+    const int64_t K = n[c] * l[c + 1];
+    hatt_status stt = gemm(run, gc, CMat{WL, K, 1, wlsz}, CMat{sk + skoff[c], 1, K, sks},
+                           Mat{W + woff[c], l[c], 1, wtot}, r[c] * s[c], l[c], K, 1.0, 0.0, P, st, true);
+    if (stt != HATT_OK) return stt;
+  }
+  // ---- sweep (Alg. 4)
+  {
+    PkpArgs pa{xd, yd, Xc, 1, r[1], 1, s[1], n[0], xs, ys, xsz, P};
+    LAUNCH(launch_pkp(pa, st));
+  }
+  for (int c = 0; c < d - 1; ++c) {
+    const int64_t m = l[c] * n[c], rs1 = r[c + 1] * s[c + 1];
+    hatt_status stt = gemm(run, gc, CMat{Xc, rs1, 1, xsz}, CMat{W + woff[c + 1], l[c + 1], 1, wtot},
+                           Mat{Yb, l[c + 1], 1, ysz}, m, l[c + 1], rs1, 1.0, 0.0, P, st, true);
+    if (stt != HATT_OK) return stt;
+    double *qcore = sp.out + ooff[c];
+    LAUNCH(launch_tsqr(qp[c], CMat{Yb, l[c + 1], 1, ysz}, Mat{qcore, l[c + 1], 1, sp.ostride},
+                       Mat{nullptr, 0, 0, 0}, wqr, qrws, P, st));
+    stt = gemm(run, gc, CMat{qcore, 1, l[c + 1], sp.ostride}, CMat{Xc, rs1, 1, xsz}, Mat{Mb, rs1, 1, msz},
+               l[c + 1], rs1, m, 1.0, 0.0, P, st, true);
+    if (stt != HATT_OK) return stt;
+    const int cn = c + 1;
+    SandwichArgs a{};
+    a.yl = xd + sp.X.off[cn];
+    a.ylb = xs;
+    a.yli = r[cn + 1];
+    a.ylr = 1;
+    a.ylc = n[cn] * r[cn + 1];
+    a.zr = yd + sp.Y.off[cn];
+    a.zrb = ys;
+    a.zri = s[cn + 1];
+    a.zrr = n[cn] * s[cn + 1];
+    a.zrc = 1;
+    a.c = Mb;
+    a.cb = msz;
+    a.cg = rs1;
+    a.ca = s[cn];
+    a.cbb = 1;
+    if (cn < d - 1) {
+      a.o = Xc;
+      a.ob = xsz;
+      a.oi = r[cn + 1] * s[cn + 1];
+      a.og = n[cn] * r[cn + 1] * s[cn + 1];
+      a.oa = s[cn + 1];
+      a.obb = 1;
+    } else {
+      a.o = sp.out + ooff[cn];
+      a.ob = sp.ostride;
+      a.oi = 1;
+      a.og = n[cn];
+      a.oa = 1;
+      a.obb = 1;
+    }
+    a.RA = (int)r[cn + 1];
+    a.RI = (int)r[cn];
+    a.SI = (int)s[cn];
+    a.SO = (int)s[cn + 1];
+    a.n = n[cn];
+    a.G = l[cn];
+    a.batch = P;
+    LAUNCH(launch_sandwich(a, st));
+  }
+  // ranks before truncation: the sketch widths
+  if ((int)l.size() > kMaxRankPattern) return fail(HATT_EUNSUPPORTED, "order too large for this build");
+  LAUNCH(launch_rank_pattern(sp.orank, P, d + 1, l.data(), st));
+  // ---- truncation (Alg. 1 on the rank-l result)
+  const bool trunc = (sp.o.max_rank > 0) || (sp.o.tol > 0.0);
+  if (trunc) {
+    RoundSpec rs{};
+    rs.n = n;
+    rs.rin = l;
+    rs.cap = l;
+    rs.src = sp.out;
+    rs.sstride = sp.ostride;
+    rs.in_place = true;
+    rs.out = sp.out;
+    rs.ostride = sp.ostride;
+    rs.orank = sp.orank;
+    rs.max_rank = sp.o.max_rank;
+    rs.tol = sp.o.tol;
+    rs.batch = P;
+    GemmCtx gr{nullptr, 0, 0};
+    hatt_status s1 = round_run(run, rs, ws, gr, st);
+    if (s1 != HATT_OK) return s1;
+  }
+  return HATT_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char *hatt_last_error(void) { return g_err.c_str(); }
+
+hatt_status hatt_profile_start(void) {
+  g_prof.recs.clear();
+  g_prof.used = 0;
+  g_prof.on = true;
+  return HATT_OK;
+}
+
+hatt_status hatt_profile_stop(double *ms_out, int64_t *calls_out) {
+  g_prof.on = false;
+  if (ms_out == nullptr || calls_out == nullptr) return fail(HATT_EINVAL, "profile_stop: NULL output");
+  for (int c = 0; c < P_NCLASS; ++c) {
+    ms_out[c] = 0.0;
+    calls_out[c] = 0;
+  }
+  for (const ProfRec &r : g_prof.recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return fail(HATT_EDEVICE, "profile_stop: event sync failed");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+      return fail(HATT_EDEVICE, "profile_stop: elapsed time failed");
+    ms_out[r.cls] += ms;
+    calls_out[r.cls] += 1;
+  }
+  g_prof.recs.clear();
+  g_prof.used = 0;
+  return HATT_OK;
+}
+
+const char *hatt_profile_class_name(int32_t cls) {
+  if (cls < 0 || cls >= P_NCLASS) return "";
+  return kClassNames[cls];
+}
+const char *hatt_version(void) { return "hatt-mi355x 0.1 (gfx950, fp64)"; }
+
+static hatt_status hatt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_opts *o, HattSpec *sp,
+                                bool need_data) {
+  if (o == nullptr) return fail(HATT_EINVAL, "opts is NULL");
+  hatt_status st = read_tt(x, "x", &sp->X, need_data);
+  if (st != HATT_OK) return st;
+  st = read_tt(y, "y", &sp->Y, need_data);
+  if (st != HATT_OK) return st;
+  if (sp->X.d != sp->Y.d) return fail(HATT_ESHAPE, "x and y have different orders");
+  if (sp->X.batch != sp->Y.batch) return fail(HATT_ESHAPE, "x and y have different batch counts");
+  if (sp->X.n != sp->Y.n) return fail(HATT_ESHAPE, "x and y have different mode sizes");
+  if (o->variant != 1) return fail(HATT_EUNSUPPORTED, "only variant 1 (HaTT-1) is built");
+  if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(HATT_EINVAL, "tol must be finite and >= 0");
+  const int d = sp->X.d;
+  std::vector<int64_t> req(d + 1, 1);
+  for (int k = 1; k < d; ++k) {
+    req[k] = o->ell_bond ? o->ell_bond[k] : o->ell;
+    if (req[k] < 1) return fail(HATT_EINVAL, "sketch width must be >= 1");
+  }
+  sp->ell = clamp_ell(sp->X.n, sp->X.r, sp->Y.r, req);
+  sp->o = *o;
+  return HATT_OK;
+}
+
+hatt_status hatt_plan(const hatt_tt *x, const hatt_tt *y, const hatt_opts *opts, int64_t *ell_out,
+                      size_t *ws_bytes, int64_t *out_elems) {
+  HattSpec sp{};
+  hatt_status st = hatt_prepare(x, y, opts, &sp, false);
+  if (st != HATT_OK) return st;
+  sp.sketch = nullptr;
+  sp.out = nullptr;
+  sp.orank = nullptr;
+  Ws ws(nullptr);
+  st = hatt_run(false, sp, ws, nullptr);
+  if (st != HATT_OK) return st;
+  if (ell_out)
+    for (int k = 0; k <= sp.X.d; ++k) ell_out[k] = sp.ell[k];
+  if (ws_bytes) *ws_bytes = ws.off;
+  if (out_elems) {
+    std::vector<int64_t> off;
+    int64_t tot;
+    make_offsets(sp.X.n, sp.ell, &off, &tot);
+    *out_elems = tot;
+  }
+  g_err.clear();
+  return HATT_OK;
+}
+
+hatt_status hatt_recompress(const hatt_tt *x, const hatt_tt *y, const hatt_tt *sketch, const hatt_opts *opts,
+                            double *out, int64_t out_stride, int64_t *out_rank, void *ws, size_t ws_bytes,
+                            void *stream) {
+  HattSpec sp{};
+  hatt_status st = hatt_prepare(x, y, opts, &sp, true);
+  if (st != HATT_OK) return st;
+  if (out == nullptr || out_rank == nullptr) return fail(HATT_EINVAL, "out or out_rank is NULL");
+  std::vector<int64_t> off;
+  int64_t otot;
+  make_offsets(sp.X.n, sp.ell, &off, &otot);
+  if (out_stride != 0 && out_stride < otot) return fail(HATT_EINVAL, "out_stride smaller than one output train");
+  sp.out = out;
+  sp.ostride = out_stride ? out_stride : otot;
+  sp.orank = out_rank;
+  sp.sketch = nullptr;
+  sp.sketch_stride = 0;
+  if (sketch != nullptr) {
+    Shape sk;
+    st = read_tt(sketch, "sketch", &sk, true);
+    if (st != HATT_OK) return st;
+    if (sk.d != sp.X.d || sk.n != sp.X.n || sk.r != sp.ell)
+      return fail(HATT_ESHAPE, "sketch shape differs from the planned sketch widths");
+    if (sk.batch != 1 && sk.batch != sp.X.batch)
+      return fail(HATT_ESHAPE, "sketch batch must be 1 or equal to the input batch");
+    sp.sketch = sk.data;
+    sp.sketch_stride = (sk.batch == 1) ? 0 : sk.stride;
+  }
+  Ws meas(nullptr);
+  st = hatt_run(false, sp, meas, nullptr);
+  if (st != HATT_OK) return st;
+  if (ws == nullptr || ws_bytes < meas.off)
+    return fail(HATT_EWORKSPACE, "workspace too small: need " + std::to_string(meas.off) + " bytes");
+  Ws w(ws);
+  st = hatt_run(true, sp, w, (hipStream_t)stream);
+  if (st == HATT_OK) g_err.clear();
+  return st;
+}
+
+hatt_status tt_hadamard_explicit(const hatt_tt *x, const hatt_tt *y, double *out, int64_t out_stride,
+                                 void *stream) {
+  Shape X, Y;
+  hatt_status rc = read_tt(x, "x", &X, true);
+  if (rc != HATT_OK) return rc;
+  rc = read_tt(y, "y", &Y, true);
+  if (rc != HATT_OK) return rc;
+  if (X.d != Y.d || X.batch != Y.batch || X.n != Y.n) return fail(HATT_ESHAPE, "x and y shapes differ");
+  if (out == nullptr) return fail(HATT_EINVAL, "out is NULL");
+  std::vector<int64_t> rr(X.d + 1), off;
+  for (int k = 0; k <= X.d; ++k) rr[k] = X.r[k] * Y.r[k];
+  int64_t tot;
+  make_offsets(X.n, rr, &off, &tot);
+  if (out_stride != 0 && out_stride < tot) return fail(HATT_EINVAL, "out_stride smaller than one output train");
+  const int64_t os = out_stride ? out_stride : tot;
+  const bool run = true;
+  hipStream_t st = (hipStream_t)stream;
+  for (int k = 0; k < X.d; ++k) {
+    PkpArgs pa{X.data + X.off[k], Y.data + Y.off[k], out + off[k], X.r[k], X.r[k + 1], Y.r[k], Y.r[k + 1],
+               X.n[k], X.stride, Y.stride, os, X.batch};
+    LAUNCH(launch_pkp(pa, st));
+  }
+  g_err.clear();
+  return HATT_OK;
+}
+
+static hatt_status round_prepare(const hatt_tt *a, RoundSpec *rs, Shape *A, bool need_data) {
+  hatt_status st = read_tt(a, "a", A, need_data);
+  if (st != HATT_OK) return st;
+  rs->n = A->n;
+  rs->rin = A->r;
+  rs->cap = round_caps(A->n, A->r);
+  rs->src = A->data;
+  rs->sstride = A->stride;
+  rs->in_place = false;
+  rs->batch = A->batch;
+  return HATT_OK;
+}
+
+hatt_status tt_round_plan(const hatt_tt *a, int64_t *cap_out, size_t *ws_bytes, int64_t *out_elems) {
+  RoundSpec rs{};
+  Shape A;
+  hatt_status st = round_prepare(a, &rs, &A, false);
+  if (st != HATT_OK) return st;
+  rs.norm_only = false;
+  Ws ws(nullptr);
+  GemmCtx gm{nullptr, 0, 0};
+  st = round_run(false, rs, ws, gm, nullptr);
+  if (st != HATT_OK) return st;
+  if (cap_out)
+    for (int k = 0; k <= A.d; ++k) cap_out[k] = rs.cap[k];
+  if (ws_bytes) *ws_bytes = ws.off;
+  if (out_elems) {
+    std::vector<int64_t> off;
+    int64_t tot;
+    make_offsets(A.n, rs.cap, &off, &tot);
+    *out_elems = tot;
+  }
+  g_err.clear();
+  return HATT_OK;
+}
+
+hatt_status tt_round(const hatt_tt *a, int64_t max_rank, double tol, double *out, int64_t out_stride,
+                     int64_t *out_rank, void *ws, size_t ws_bytes, void *stream) {
+  RoundSpec rs{};
+  Shape A;
+  hatt_status st = round_prepare(a, &rs, &A, true);
+  if (st != HATT_OK) return st;
+  if (out == nullptr || out_rank == nullptr) return fail(HATT_EINVAL, "out or out_rank is NULL");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(HATT_EINVAL, "tol must be finite and >= 0");
+  std::vector<int64_t> off;
+  int64_t otot;
+  make_offsets(A.n, rs.cap, &off, &otot);
+  if (out_stride != 0 && out_stride < otot) return fail(HATT_EINVAL, "out_stride smaller than one output train");
+  rs.out = out;
+  rs.ostride = out_stride ? out_stride : otot;
+  rs.orank = out_rank;
+  rs.max_rank = max_rank;
+  rs.tol = tol;
+  Ws meas(nullptr);
+  GemmCtx gm{nullptr, 0, 0};
+  st = round_run(false, rs, meas, gm, nullptr);
+  if (st != HATT_OK) return st;
+  if (ws == nullptr || ws_bytes < meas.off)
+    return fail(HATT_EWORKSPACE, "workspace too small: need " + std::to_string(meas.off) + " bytes");
+  Ws w(ws);
+  GemmCtx g2{nullptr, 0, 0};
+  st = round_run(true, rs, w, g2, (hipStream_t)stream);
+  if (st == HATT_OK) g_err.clear();
+  return st;
+}
+
+hatt_status tt_norm_plan(const hatt_tt *a, size_t *ws_bytes) {
+  RoundSpec rs{};
+  Shape A;
+  hatt_status st = round_prepare(a, &rs, &A, false);
+  if (st != HATT_OK) return st;
+  rs.norm_only = true;
+  Ws ws(nullptr);
+  GemmCtx gm{nullptr, 0, 0};
+  st = round_run(false, rs, ws, gm, nullptr);
+  if (st != HATT_OK) return st;
+  if (ws_bytes) *ws_bytes = ws.off;
+  g_err.clear();
+  return HATT_OK;
+}
+
+hatt_status tt_norm(const hatt_tt *a, double *out, void *ws, size_t ws_bytes, void *stream) {
+  RoundSpec rs{};
+  Shape A;
+  hatt_status st = round_prepare(a, &rs, &A, true);
+  if (st != HATT_OK) return st;
+  if (out == nullptr) return fail(HATT_EINVAL, "out is NULL");
+  rs.norm_only = true;
+  rs.norm_out = out;
+  Ws meas(nullptr);
+  GemmCtx gm{nullptr, 0, 0};
+  st = round_run(false, rs, meas, gm, nullptr);
+  if (st != HATT_OK) return st;
+  if (ws == nullptr || ws_bytes < meas.off)
+    return fail(HATT_EWORKSPACE, "workspace too small: need " + std::to_string(meas.off) + " bytes");
+  Ws w(ws);
+  GemmCtx g2{nullptr, 0, 0};
+  st = round_run(true, rs, w, g2, (hipStream_t)stream);
+  if (st == HATT_OK) g_err.clear();
+  return st;
+}
+
+hatt_status hatt_sketch_fill(uint64_t seed, int32_t d, const int64_t *n, const int64_t *ell, double *out,
+                             void *stream) {
+  if (d < 1 || n == nullptr || ell == nullptr || out == nullptr)
+    return fail(HATT_EINVAL, "sketch_fill: bad arguments");
+  if (ell[0] != 1 || ell[d] != 1) return fail(HATT_ESHAPE, "sketch_fill: ell[0] and ell[d] must be 1");
+  int64_t off = 0;
+  for (int k = 0; k < d; ++k) {
+    if (n[k] < 1 || ell[k] < 1) return fail(HATT_ESHAPE, "sketch_fill: sizes must be >= 1");
+  }
+  const bool run = true;
+  hipStream_t st = (hipStream_t)stream;
+  for (int k = 0; k < d; ++k) {
+    const int64_t cnt = ell[k] * n[k] * ell[k + 1];
+    LAUNCH(launch_sketch_fill(seed, k, cnt, 1.0 / sqrt((double)cnt), out + off, st));
+    off += cnt;
+  }
+  g_err.clear();
+  return HATT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,341 @@
+// Elementwise and small-contraction kernels: Philox sketch, PKP expansion,
+// the last-core sketch of HPCRL and the "sandwich" contraction that carries
+// both the W_L columns of HPCRL (eq. WLWR) and the PKP-free core update of
+// the HaTT sweep (eq. M*core0).
+#include "common.h"
+
+namespace hatt {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64 products
+// with the published multipliers, Weyl key schedule between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int rnd = 0; rnd < 10; ++rnd) {
+    const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+    uint32_t lo0 = m0 * c[0], hi0 = __umulhi(m0, c[0]);
+    uint32_t lo1 = m1 * c[2], hi1 = __umulhi(m1, c[2]);
+    uint32_t n0 = hi1 ^ c[1] ^ k0;
+    uint32_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
+  // ((a >> 5) 2^26 + (b >> 6) + 1/2) 2^-53, strictly inside (0, 1)
+  return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+__global__ void sketch_fill_kernel(uint64_t seed, uint32_t core, int64_t count, double scale,
+                                   double *__restrict__ out) {
+  const int64_t npairs = (count + 1) / 2;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npairs;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t c[4] = {(uint32_t)(p & 0xFFFFFFFFu), (uint32_t)((uint64_t)p >> 32), core, 0x5A7Cu};
+    philox4x32_10(c, (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32));
+    const double ua = u53(c[0], c[1]);
+    const double ub = u53(c[2], c[3]);
+    const double rad = sqrt(-2.0 * log(ua)) * scale;
+    const double ang = 6.283185307179586476925286766559 * ub;
+    const double g0 = rad * cos(ang), g1 = rad * sin(ang);
+    out[2 * p] = g0;
+    if (2 * p + 1 < count) out[2 * p + 1] = g1;
+  }
+}
+
+hipError_t launch_sketch_fill(uint64_t seed, int core, int64_t count, double scale, double *out,
+                              hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int64_t npairs = (count + 1) / 2;
+  int grid = (int)std::min<int64_t>((npairs + 255) / 256, 8192);
+  sketch_fill_kernel<<<grid, 256, 0, s>>>(seed, (uint32_t)core, count, scale, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// PKP expansion (Sec. 2.2).  Memory bound: one thread per output element,
+// consecutive threads write consecutive (a', b') so stores coalesce; inputs
+// are small and stay in cache.
+__global__ void pkp_kernel(PkpArgs a) {
+  const int64_t cols = a.r1 * a.s1;
+  const int64_t per = a.r0 * a.s0 * a.n * cols;
+  const int64_t total = per * a.batch;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / per;
+    int64_t rem = e - p * per;
+    const int64_t col = rem % cols;
+    rem /= cols;
+    const int64_t i = rem % a.n;
+    const int64_t row = rem / a.n;
+    const int64_t ra = row / a.s0, sb = row - ra * a.s0;
+    const int64_t ca = col / a.s1, cb = col - ca * a.s1;
+    const double xv = a.x[p * a.xs + (ra * a.n + i) * a.r1 + ca];
+    const double yv = a.y[p * a.ys + (sb * a.n + i) * a.s1 + cb];
+    a.out[p * a.os + (row * a.n + i) * cols + col] = xv * yv;
+  }
+}
+
+hipError_t launch_pkp(const PkpArgs &a, hipStream_t s) {
+  const int64_t total = a.r0 * a.s0 * a.n * a.r1 * a.s1 * a.batch;
+  if (total <= 0) return hipSuccess;
+  int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  pkp_kernel<<<grid, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// W^{(d-1)}(a s + b, g) = sum_i X_d(a, i) Y_d(b, i) R_d(g, i)  (Alg. 3, first
+// line).  One thread per output entry; the sum over i is short.
+__global__ void hpcrl_last_kernel(LastArgs a) {
+  const int64_t rows = a.rx * a.sy;
+  const int64_t per = rows * a.l;
+  const int64_t total = per * a.batch;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / per;
+    const int64_t rem = e - p * per;
+    const int64_t row = rem / a.l, g = rem - row * a.l;
+    const int64_t ia = row / a.sy, ib = row - ia * a.sy;
+    const double *xp = a.x + p * a.xs + ia * a.n;
+    const double *yp = a.y + p * a.ys + ib * a.n;
+    const double *rp = a.r + p * a.rsb + g * a.n;
+    double acc = 0.0;
+    for (int64_t i = 0; i < a.n; ++i) acc += xp[i] * yp[i] * rp[i];
+    a.w[p * a.ws + rem] = acc;
+  }
+}
+
+hipError_t launch_hpcrl_last(const LastArgs &a, hipStream_t s) {
+  const int64_t total = a.rx * a.sy * a.l * a.batch;
+  if (total <= 0) return hipSuccess;
+  int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  hpcrl_last_kernel<<<grid, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Sandwich contraction out_{i,g} = YL_i C_g ZR_i for a chunk of GC values of
+// g per workgroup, slice i = blockIdx.x.  YL_i and ZR_i are staged once in
+// LDS, the GC matrices C_g next to them; the product is formed as
+// T = C_g ZR_i (RI x SO) and then YL_i T.  Two LDS layouts: with g innermost
+// when the output is contiguous in g (the W_L columns of HPCRL), else with
+// the column index innermost (the core update, contiguous in (a', b')).
+// Every LDS access pattern is either a broadcast or unit stride.
+template <bool GFAST>
+__global__ __launch_bounds__(256) void sandwich_kernel(SandwichArgs a, int GC) {
+  extern __shared__ double sm[];
+  const int RA = a.RA, RI = a.RI, SI = a.SI, SO = a.SO;
+  double *YL = sm;                  // RA x RI      YL[a'*RI + a]
+  double *ZR = YL + RA * RI;        // SI x SO      ZR[b*SO + b']
+  double *Cs = ZR + SI * SO;        // GC x RI x SI
+  double *Ts = Cs + GC * RI * SI;   // GC x RI x SO
+  const int tid = threadIdx.x;
+  const int64_t i = blockIdx.x;
+  const int64_t g0 = (int64_t)blockIdx.y * GC;
+  const int p = blockIdx.z;
+  const int gc = (int)std::min<int64_t>(GC, a.G - g0);
+  if (gc <= 0) return;
+
+  const double *yl = a.yl + p * a.ylb + i * a.yli;
+  if (a.ylc == 1) {
+    for (int e = tid; e < RA * RI; e += 256) {
+      int ap = e / RI, aa = e - ap * RI;
+      YL[e] = yl[ap * a.ylr + aa];
+    }
+  } else {
+    for (int e = tid; e < RA * RI; e += 256) {
+      int aa = e / RA, ap = e - aa * RA;
+      YL[ap * RI + aa] = yl[ap * a.ylr + aa * a.ylc];
+    }
+  }
+  const double *zr = a.zr + p * a.zrb + i * a.zri;
+  if (a.zrc == 1) {
+    for (int e = tid; e < SI * SO; e += 256) {
+      int b = e / SO, bp = e - b * SO;
+      ZR[e] = zr[b * a.zrr + bp];
+    }
+  } else {
+    for (int e = tid; e < SI * SO; e += 256) {
+      int bp = e / SI, b = e - bp * SI;
+      ZR[b * SO + bp] = zr[b * a.zrr + bp * a.zrc];
+    }
+  }
+  const double *cbase = a.c + p * a.cb + g0 * a.cg;
+  const int nC = gc * RI * SI;
+  if (GFAST) {
+    // Cs[(a*SI + b)*GC + gg]
+    for (int e = tid; e < nC; e += 256) {
+      int gg = e % gc, rest = e / gc;
+      int b = rest % SI, aa = rest / SI;
+      Cs[(aa * SI + b) * GC + gg] = cbase[gg * a.cg + aa * a.ca + b * a.cbb];
+    }
+  } else {
+    // Cs[(gg*RI + a)*SI + b]
+    for (int e = tid; e < nC; e += 256) {
+      int b = e % SI, rest = e / SI;
+      int aa = rest % RI, gg = rest / RI;
+      Cs[e] = cbase[gg * a.cg + aa * a.ca + b * a.cbb];
+    }
+  }
+  __syncthreads();
+
+  // T = C_g ZR  (RI x SO per g)
+  const int nT = gc * RI * SO;
+  for (int e = tid; e < nT; e += 256) {
+    double acc = 0.0;
+    if (GFAST) {
+      int gg = e % gc, rest = e / gc;
+      int bp = rest % SO, aa = rest / SO;
+      const double *cr = Cs + aa * SI * GC + gg;
+      for (int b = 0; b < SI; ++b) acc += cr[b * GC] * ZR[b * SO + bp];
+      Ts[(aa * SO + bp) * GC + gg] = acc;
+    } else {
+      int bp = e % SO, rest = e / SO;
+      int aa = rest % RI, gg = rest / RI;
+      const double *cr = Cs + (gg * RI + aa) * SI;
+      for (int b = 0; b < SI; ++b) acc += cr[b] * ZR[b * SO + bp];
+      Ts[(gg * RI + aa) * SO + bp] = acc;
+    }
+  }
+  __syncthreads();
+
+  // out = YL T  (RA x SO per g)
+  double *obase = a.o + p * a.ob + i * a.oi + g0 * a.og;
+  const int nO = gc * RA * SO;
+  for (int e = tid; e < nO; e += 256) {
+    double acc = 0.0;
+    if (GFAST) {
+      int gg = e % gc, rest = e / gc;
+      int bp = rest % SO, ap = rest / SO;
+      const double *yr = YL + ap * RI;
+      const double *tc = Ts + bp * GC + gg;
+      for (int aa = 0; aa < RI; ++aa) acc += yr[aa] * tc[aa * SO * GC];
+      obase[gg * a.og + ap * a.oa + bp * a.obb] = acc;
+    } else {
+      int bp = e % SO, rest = e / SO;
+      int ap = rest % RA, gg = rest / RA;
+      const double *yr = YL + ap * RI;
+      const double *tc = Ts + gg * RI * SO + bp;
+      for (int aa = 0; aa < RI; ++aa) acc += yr[aa] * tc[aa * SO];
+      obase[gg * a.og + ap * a.oa + bp * a.obb] = acc;
+    }
+  }
+}
+
+hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s) {
+  if (a.n <= 0 || a.G <= 0 || a.batch <= 0) return hipSuccess;
+  const int64_t fixed = (int64_t)a.RA * a.RI + (int64_t)a.SI * a.SO;
+  const int64_t perg = (int64_t)a.RI * a.SI + (int64_t)a.RI * a.SO;
+  const int64_t budget = 19456;  // doubles of dynamic LDS
+  int64_t gc = std::min<int64_t>(8, (budget - fixed) / perg);
+  if (gc < 1) return hipErrorInvalidValue;
+  gc = std::min<int64_t>(gc, a.G);
+  const size_t lds = (size_t)(fixed + gc * perg) * sizeof(double);
+  dim3 grid((unsigned)a.n, (unsigned)((a.G + gc - 1) / gc), (unsigned)a.batch);
+  if (a.og == 1) {
+    hipFuncSetAttribute((const void *)sandwich_kernel<true>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    sandwich_kernel<true><<<grid, 256, lds, s>>>(a, (int)gc);
+  } else {
+    hipFuncSetAttribute((const void *)sandwich_kernel<false>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    sandwich_kernel<false><<<grid, 256, lds, s>>>(a, (int)gc);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__global__ void copy_kernel(CMat src, Mat dst, int64_t M, int64_t N, int batch) {
+  const int64_t per = M * N, total = per * batch;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / per, rem = e - p * per;
+    const int64_t r = rem / N, c = rem - r * N;
+    dst.ptr[p * dst.bs + r * dst.rs + c * dst.cs] = src.ptr[p * src.bs + r * src.rs + c * src.cs];
+  }
+}
+
+hipError_t launch_copy(CMat src, Mat dst, int64_t M, int64_t N, int batch, hipStream_t s) {
+  const int64_t total = M * N * batch;
+  if (total <= 0) return hipSuccess;
+  int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  copy_kernel<<<grid, 256, 0, s>>>(src, dst, M, N, batch);
+  return hipGetLastError();
+}
+
+__global__ void fill_kernel(double *p, int64_t count, double v) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+__global__ void fill_i64_kernel(int64_t *p, int64_t count, int64_t v) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int grid = (int)std::min<int64_t>((count + 255) / 256, 65536);
+  fill_kernel<<<grid, 256, 0, s>>>(p, count, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_i64(int64_t *p, int64_t count, int64_t v, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int grid = (int)std::min<int64_t>((count + 255) / 256, 65536);
+  fill_i64_kernel<<<grid, 256, 0, s>>>(p, count, v);
+  return hipGetLastError();
+}
+
+struct RankPattern {
+  int64_t v[kMaxRankPattern];
+};
+__global__ void rank_pattern_kernel(int64_t *dst, int batch, int len, RankPattern pat) {
+  const int64_t total = (int64_t)batch * len;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = pat.v[e % len];
+}
+
+hipError_t launch_rank_pattern(int64_t *dst, int batch, int len, const int64_t *host_pattern, hipStream_t s) {
+  if (len > kMaxRankPattern) return hipErrorInvalidValue;
+  RankPattern pat;
+  for (int k = 0; k < len; ++k) pat.v[k] = host_pattern[k];
+  const int64_t total = (int64_t)batch * len;
+  if (total <= 0) return hipSuccess;
+  int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
+  rank_pattern_kernel<<<grid, 256, 0, s>>>(dst, batch, len, pat);
+  return hipGetLastError();
+}
+
+// Frobenius norm of each pair's contiguous block, fixed reduction order.
+__global__ __launch_bounds__(256) void block_norm_kernel(const double *x, int64_t count, int64_t bs,
+                                                         double *out) {
+  __shared__ double red[256];
+  const int p = blockIdx.x;
+  const double *xp = x + p * bs;
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < count; e += 256) acc += xp[e] * xp[e];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[p] = sqrt(red[0]);
+}
+
+hipError_t launch_block_norm(const double *x, int64_t count, int64_t bs, double *out, int batch,
+                             hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  block_norm_kernel<<<batch, 256, 0, s>>>(x, count, bs, out);
+  return hipGetLastError();
+}
+
+}  // namespace hatt

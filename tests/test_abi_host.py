@@ -1,0 +1,144 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and
+exports every declared entry point, planning reproduces the clamp rules, and
+bad arguments are rejected before anything is launched."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as wk
+from oracle import plan as oplan
+from paper_2410_04385_amd import _lib, api
+from paper_2410_04385_amd._lib import HattError
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"HATT_API\s+[\w\s\*]+?\b(\w+)\s*\(", src))
+    return names
+
+
+def _cpu_tt(n, ranks, batch=1):
+    _, tot = api._offsets(n, ranks)
+    return api.TT(torch.zeros(batch * tot, dtype=torch.float64), n, ranks, batch)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    declared = _declared_symbols()
+    assert declared == set(_lib.EXPORTED)
+    for name in declared:
+        assert hasattr(L, name)
+    assert "gfx950" in api.version()
+
+
+def test_plan_matches_oracle_clamps():
+    rng = np.random.default_rng(0)
+    for _ in range(40):
+        d = int(rng.integers(1, 9))
+        n = [int(v) for v in rng.integers(1, 7, size=d)]
+        rx = wk.feasible_ranks(n, int(rng.integers(1, 7)))
+        ry = wk.feasible_ranks(n, int(rng.integers(1, 7)))
+        ell = int(rng.integers(1, 40))
+        p = api.plan(_cpu_tt(n, rx), _cpu_tt(n, ry), ell)
+        assert p["ell"] == oplan.clamp_ell(n, rx, ry, ell)
+        _, tot = api._offsets(n, p["ell"])
+        assert p["out_elems"] == tot
+        assert p["ws_bytes"] > 0
+
+
+def test_plan_tiny_workload_exact_rank():
+    y, z = wk.tiny_pair(0)
+    p = api.plan(_cpu_tt([4] * 6, wk.ranks_of(y)), _cpu_tt([4] * 6, wk.ranks_of(z)), 9)
+    assert p["ell"] == [1, 4, 9, 9, 9, 4, 1]
+
+
+def test_per_bond_widths_and_workspace_growth():
+    n = [5] * 5
+    x = _cpu_tt(n, [1, 4, 4, 4, 4, 1])
+    p1 = api.plan(x, x, [1, 3, 5, 7, 2, 1])
+    assert p1["ell"] == [1, 3, 5, 7, 2, 1]
+    xb = _cpu_tt(n, [1, 4, 4, 4, 4, 1], batch=8)
+    p8 = api.plan(xb, xb, [1, 3, 5, 7, 2, 1])
+    assert p8["ws_bytes"] > p1["ws_bytes"]
+
+
+def test_round_plan_capacities_follow_qr_shapes():
+    # the PKP of the tiny workload has ranks 9 but boundary modes of size 4
+    p = api.round_plan(_cpu_tt([4] * 6, [1, 9, 9, 9, 9, 9, 1]))
+    assert p["cap"] == [1, 4, 9, 9, 9, 4, 1]
+
+
+@pytest.mark.parametrize("bad", ["rank0", "rankd", "modes", "order", "batch"])
+def test_shape_errors(bad):
+    n = [3, 4, 3]
+    x = _cpu_tt(n, [1, 2, 2, 1])
+    y = _cpu_tt(n, [1, 2, 2, 1])
+    if bad == "rank0":
+        y = api.TT(torch.zeros(64, dtype=torch.float64), n, [2, 2, 2, 1])
+    elif bad == "rankd":
+        y = api.TT(torch.zeros(64, dtype=torch.float64), n, [1, 2, 2, 2])
+    elif bad == "modes":
+        y = _cpu_tt([3, 5, 3], [1, 2, 2, 1])
+    elif bad == "order":
+        y = _cpu_tt([3, 4], [1, 2, 1])
+    elif bad == "batch":
+        y = _cpu_tt(n, [1, 2, 2, 1], batch=2)
+    with pytest.raises(HattError) as e:
+        api.plan(x, y, 3)
+    assert e.value.status == -2
+
+
+def test_option_errors():
+    n = [3, 4, 3]
+    x = _cpu_tt(n, [1, 2, 2, 1])
+    with pytest.raises(HattError) as e:
+        api.plan(x, x, 0)
+    assert e.value.status == -1
+    with pytest.raises(HattError) as e:
+        api.plan(x, x, 3, tol=-1.0)
+    assert e.value.status == -1
+    with pytest.raises(HattError) as e:
+        api.plan(x, x, 3, variant=3)
+    assert e.value.status in (-1, -7)
+
+
+def test_workspace_too_small_is_rejected_before_launch():
+    n = [3, 4, 3]
+    x = _cpu_tt(n, [1, 2, 2, 1])
+    L = _lib.lib()
+    xv, k1 = x.view()
+    o, k2 = api._opts(3, 0, 0.0, 1, 1, 0.0, 3)
+    out = torch.zeros(1000, dtype=torch.float64)
+    rk = torch.zeros(8, dtype=torch.int64)
+    ws = torch.zeros(16, dtype=torch.uint8)
+    st = L.hatt_recompress(ctypes.byref(xv), ctypes.byref(xv), None, ctypes.byref(o),
+                           ctypes.c_void_p(out.data_ptr()), 0, ctypes.c_void_p(rk.data_ptr()),
+                           ctypes.c_void_p(ws.data_ptr()), 16, None)
+    assert st == -3
+    assert b"workspace too small" in L.hatt_last_error()
+
+
+def test_null_arguments_are_rejected():
+    L = _lib.lib()
+    assert L.hatt_plan(None, None, None, None, None, None) == -1
+    assert L.tt_norm_plan(None, None) == -1
+    assert L.hatt_sketch_fill(0, 0, None, None, None, None) == -1
+
+
+def test_unsupported_widths_are_reported():
+    # a sketch wider than the TSQR panel limit is refused with a message
+    n = [256, 256, 256]
+    x = _cpu_tt(n, [1, 40, 40, 1])
+    with pytest.raises(HattError) as e:
+        api.plan(x, x, 300)
+    assert e.value.status == -7
