@@ -11,7 +11,7 @@ namespace hatt {
 
 // Largest column count of one TSQR panel and of the in-LDS Jacobi SVD.
 constexpr int kQrMaxCols = 128;
-constexpr int kSvdMaxN = 96;
+constexpr int kSvdMaxN = 139;
 // Doubles of dynamic LDS a TSQR block may use (of the 160 KiB per CU).
 constexpr int kQrLdsDoubles = 19456;
 

@@ -1,30 +1,43 @@
 // Tall-skinny Householder QR (TSQR) in FP64.
 //
 // The m x n matrix is cut into row blocks that each fit in LDS; every block
-// is factored by unblocked Householder reflections (one workgroup, the block
-// held column-major in LDS so that column sweeps are unit stride).  The n x n
-// R factors of the blocks are stacked and factored again, level by level,
-// until one block remains.  The explicit Q is then formed top-down: each
-// block applies its reflectors to its n x k slice of the Q of the level
-// above, padded with zeros.  Reflectors follow the usual convention
-// H = I - tau v v^T, v(0) = 1, beta = -sign(x0) ||x||; a zero column gives
-// tau = 0 (H = I), so rank-deficient inputs still produce orthonormal Q.
-// Finally the signs of diag(R) are made non-negative (columns of Q and rows
-// of R flipped together), which fixes the factorization uniquely for
-// full-rank input.
+// is factored by unblocked Householder reflections in one workgroup, the
+// block held column-major in LDS (odd leading dimension, so that lanes that
+// walk down one column touch distinct banks).  The k x n R factors of the
+// blocks are stacked and factored again, level by level, until one block
+// remains.  The explicit Q is then formed top-down: each block applies its
+// reflectors, last to first, to its slice of the Q of the level above padded
+// with zeros.
+//
+// Inner products never go through cross-lane shuffles: for a reflector step
+// the (column, row-group) products are spread over all 256 threads, written
+// as partial sums to LDS and summed by one thread per column after a
+// barrier.  With v = A(j:, j) / (x0 - beta), the products needed by a step,
+// D_c = sum_{r>j} A(r, j) A(r, c), are all available before the reflector is
+// known, so one pass gives both ||A(j+1:, j)||^2 (c = j) and the trailing
+// projections.  Reflector convention: H = I - tau v v^T, v(j) = 1,
+// beta = -sign(x0) ||x||; a zero column gives tau = 0 (H = I), so
+// rank-deficient input still yields an orthonormal Q.  Finally the signs of
+// diag(R) are made non-negative (columns of Q and rows of R flipped
+// together).
 #include "common.h"
 
 namespace hatt {
 
-constexpr int kQrChunk = 8;  // Q columns formed per LDS pass
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+// Column chunk width the Q-forming kernel keeps in LDS next to the
+// reflectors, for a panel of n columns (largest that still lets a block hold
+// at least n rows).
+static int qr_chunk(int64_t n, int64_t k) {
+  const int cand[5] = {(int)std::min<int64_t>(k, 64), 32, 16, 8, 4};
+  for (int i = 0; i < 5; ++i) {
+    const int ch = std::max(1, std::min<int>(cand[i], (int)k));
+    const int64_t mb = kQrLdsDoubles / (n + ch) - 1;
+    if (mb >= n) return ch;
+  }
+  return 1;
 }
 
-static int64_t qr_block_rows_max(int64_t n) { return kQrLdsDoubles / (n + kQrChunk); }
+static int64_t qr_block_rows_max(int64_t n, int64_t k) { return kQrLdsDoubles / (n + qr_chunk(n, k)) - 1; }
 
 bool qr_make_plan(int64_t m, int64_t n, QrPlan *p) {
   if (m < 1 || n < 1 || n > kQrMaxCols) return false;
@@ -32,7 +45,8 @@ bool qr_make_plan(int64_t m, int64_t n, QrPlan *p) {
   q.m = m;
   q.n = n;
   q.k = std::min(m, n);
-  const int64_t mb = qr_block_rows_max(n);
+  const int64_t mb = qr_block_rows_max(n, q.k);
+  if (mb < std::min(m, n)) return false;
   int64_t rows = m;
   int64_t off = 0;
   int L = 0;
@@ -77,81 +91,112 @@ struct QrLevelArgs {
 };
 
 __global__ __launch_bounds__(256) void tsqr_factor_kernel(QrLevelArgs a) {
-  extern __shared__ double A[];  // column-major block: A[c * nr + r]
-  __shared__ double red[4];
-  __shared__ double s_tau, s_scal;
+  extern __shared__ double A[];  // column-major block: A[c * ld + r]
+  __shared__ double part[256];
+  __shared__ double Ds[kQrMaxCols];
+  __shared__ double Ws[kQrMaxCols];
   __shared__ double bet[kQrMaxCols];
   __shared__ double taus[kQrMaxCols];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double scals[kQrMaxCols];
+  const int tid = threadIdx.x;
   const int64_t blk = blockIdx.x;
   const int p = blockIdx.y;
   const int64_t r0 = blk * a.rows / a.blocks, r1 = (blk + 1) * a.rows / a.blocks;
   const int nr = (int)(r1 - r0);
+  const int ld = nr | 1;
   const int n = (int)a.n;
   const double *src = a.src.ptr + p * a.src.bs;
   if (a.src.cs == 1) {
     for (int e = tid; e < nr * n; e += 256) {
       int r = e / n, c = e - r * n;
-      A[c * nr + r] = src[(r0 + r) * a.src.rs + c];
+      A[c * ld + r] = src[(r0 + r) * a.src.rs + c];
     }
   } else {
     for (int e = tid; e < nr * n; e += 256) {
       int c = e / nr, r = e - c * nr;
-      A[c * nr + r] = src[(r0 + r) * a.src.rs + c * a.src.cs];
+      A[c * ld + r] = src[(r0 + r) * a.src.rs + c * a.src.cs];
     }
   }
   __syncthreads();
   const int kref = min(nr, n);
   for (int j = 0; j < kref; ++j) {
-    double part = 0.0;
-    for (int r = j + 1 + tid; r < nr; r += 256) {
-      double v = A[j * nr + r];
-      part += v * v;
+    const int nc = n - j;           // columns j..n-1
+    const int nrow = nr - j - 1;    // rows j+1..nr-1
+    const int NG = max(1, 256 / nc);
+    // pass 1: partial products D_c over row groups; deferred scaling of column j-1
+    if (tid < nc * NG) {
+      const int rg = tid % NG, c = j + tid / NG;
+      const double *aj = A + j * ld, *ac = A + c * ld;
+      double s = 0.0;
+      for (int r = j + 1 + rg; r < nr; r += NG) s += aj[r] * ac[r];
+      part[tid] = s;
     }
-    part = wave_sum(part);
-    if (lane == 0) red[wave] = part;
+    if (j > 0) {
+      const double sc = scals[j - 1];
+      double *ap = A + (j - 1) * ld;
+      for (int r = j + tid; r < nr; r += 256) ap[r] *= sc;
+    }
     __syncthreads();
-    if (tid == 0) {
-      const double sigma2 = red[0] + red[1] + red[2] + red[3];
-      const double x0 = A[j * nr + j];
-      double tau = 0.0, scal = 0.0, beta = x0;
-      if (sigma2 > 0.0) {
-        const double nrm = sqrt(x0 * x0 + sigma2);
-        beta = (x0 >= 0.0) ? -nrm : nrm;
-        tau = (beta - x0) / beta;
-        scal = 1.0 / (x0 - beta);
+    if (tid < nc) {
+      double s = 0.0;
+      for (int g = 0; g < NG; ++g) s += part[tid * NG + g];
+      Ds[j + tid] = s;
+      if (tid == 0) {
+        const double sigma2 = s;
+        const double x0 = A[j * ld + j];
+        double tau = 0.0, scal = 0.0, beta = x0;
+        if (sigma2 > 0.0) {
+          const double nrm = sqrt(x0 * x0 + sigma2);
+          beta = (x0 >= 0.0) ? -nrm : nrm;
+          tau = (beta - x0) / beta;
+          scal = 1.0 / (x0 - beta);
+        }
+        bet[j] = beta;
+        taus[j] = tau;
+        scals[j] = scal;
       }
-      s_tau = tau;
-      s_scal = scal;
-      bet[j] = beta;
-      taus[j] = tau;
     }
     __syncthreads();
-    const double scal = s_scal, tau = s_tau;
-    for (int r = j + 1 + tid; r < nr; r += 256) A[j * nr + r] *= scal;
-    __syncthreads();
+    const double tau = taus[j], scal = scals[j];
     if (tau != 0.0) {
-      for (int c = j + 1 + wave; c < n; c += 4) {
-        double pw = 0.0;
-        for (int r = j + 1 + lane; r < nr; r += 64) pw += A[j * nr + r] * A[c * nr + r];
-        double w = (wave_sum(pw) + A[c * nr + j]) * tau;
-        for (int r = j + 1 + lane; r < nr; r += 64) A[c * nr + r] -= A[j * nr + r] * w;
-        if (lane == 0) A[c * nr + j] -= w;
+      if (tid < nc - 1) {
+        const int c = j + 1 + tid;
+        Ws[c] = tau * (A[c * ld + j] + scal * Ds[c]);
+      }
+      __syncthreads();
+      // pass 2: trailing update of rows j..nr-1 in columns j+1..n-1
+      const int span = nrow + 1;
+      const int total = (nc - 1) * span;
+      const double *aj = A + j * ld;
+      for (int e = tid; e < total; e += 256) {
+        const int c = j + 1 + e / span, r = j + e % span;
+        const double w = Ws[c];
+        if (r == j) A[c * ld + j] -= w;
+        else A[c * ld + r] -= aj[r] * scal * w;
       }
     }
     __syncthreads();
   }
-  // reflectors (column-major block, contiguous per block) and taus
+  if (kref > 0) {
+    const double sc = scals[kref - 1];
+    double *ap = A + (kref - 1) * ld;
+    for (int r = kref + tid; r < nr; r += 256) ap[r] *= sc;
+  }
+  __syncthreads();
+  // reflectors (column-major, leading dimension nr, contiguous per block) and taus
   double *ws = a.ws + p * a.wsp;
   double *vout = ws + a.off_v + r0 * n;
-  for (int e = tid; e < nr * n; e += 256) vout[e] = A[e];
+  for (int e = tid; e < nr * n; e += 256) {
+    int c = e / nr, r = e - c * nr;
+    vout[e] = A[c * ld + r];
+  }
   for (int j = tid; j < n; j += 256) ws[a.off_tau + blk * n + j] = (j < kref) ? taus[j] : 0.0;
   // R rows of this block (kref x n, upper trapezoidal)
   double *rout = ws + a.off_rout + blk * (int64_t)kref * a.ld_rout;
   for (int e = tid; e < kref * n; e += 256) {
     int jj = e / n, c = e - jj * n;
     double v = 0.0;
-    if (c > jj) v = A[c * nr + jj];
+    if (c > jj) v = A[c * ld + jj];
     else if (c == jj) v = bet[jj];
     rout[jj * a.ld_rout + c] = v;
   }
@@ -159,6 +204,7 @@ __global__ __launch_bounds__(256) void tsqr_factor_kernel(QrLevelArgs a) {
 
 struct QrFormArgs {
   int64_t rows, blocks, n, k;
+  int chunk;
   double *ws;
   int64_t wsp;
   int64_t off_v, off_tau;
@@ -171,20 +217,26 @@ struct QrFormArgs {
 
 __global__ __launch_bounds__(256) void tsqr_formq_kernel(QrFormArgs a) {
   extern __shared__ double sm[];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double part[256];
+  __shared__ double Ws[kQrMaxCols];
+  __shared__ double taus[kQrMaxCols];
+  __shared__ double sgn[kQrMaxCols];
+  const int tid = threadIdx.x;
   const int64_t blk = blockIdx.x;
   const int p = blockIdx.y;
   const int64_t r0 = blk * a.rows / a.blocks, r1 = (blk + 1) * a.rows / a.blocks;
   const int nr = (int)(r1 - r0);
-  const int n = (int)a.n, k = (int)a.k;
+  const int ld = nr | 1;
+  const int n = (int)a.n, k = (int)a.k, CH = a.chunk;
   const int kref = min(nr, n);
-  double *Vs = sm;                  // nr x n column-major
-  double *X = Vs + nr * n;          // nr x kQrChunk column-major
-  __shared__ double taus[kQrMaxCols];
-  __shared__ double sgn[kQrMaxCols];
+  double *Vs = sm;              // ld x n column-major
+  double *X = Vs + ld * n;      // ld x CH column-major
   double *ws = a.ws + p * a.wsp;
   const double *vin = ws + a.off_v + r0 * n;
-  for (int e = tid; e < nr * n; e += 256) Vs[e] = vin[e];
+  for (int e = tid; e < nr * n; e += 256) {
+    int c = e / nr, r = e - c * nr;
+    Vs[c * ld + r] = vin[e];
+  }
   for (int j = tid; j < n; j += 256) taus[j] = ws[a.off_tau + blk * n + j];
   if (a.top) {
     const double *rt = ws + a.off_rtop;
@@ -193,8 +245,8 @@ __global__ __launch_bounds__(256) void tsqr_formq_kernel(QrFormArgs a) {
   __syncthreads();
   const double *cin = a.top ? nullptr : ws + a.off_cin + blk * (int64_t)n * k;
   double *dst = a.dst.ptr + p * a.dst.bs;
-  for (int c0 = 0; c0 < k; c0 += kQrChunk) {
-    const int cw = min(kQrChunk, k - c0);
+  for (int c0 = 0; c0 < k; c0 += CH) {
+    const int cw = min(CH, k - c0);
     for (int e = tid; e < nr * cw; e += 256) {
       int cc = e / nr, r = e - cc * nr;
       double v = 0.0;
@@ -202,26 +254,41 @@ __global__ __launch_bounds__(256) void tsqr_formq_kernel(QrFormArgs a) {
         if (a.top) v = (r == c0 + cc) ? sgn[r] : 0.0;
         else v = cin[r * k + c0 + cc];
       }
-      X[cc * nr + r] = v;
+      X[cc * ld + r] = v;
     }
     __syncthreads();
-    for (int cc = wave; cc < cw; cc += 4) {
-      double *x = X + cc * nr;
-      for (int j = kref - 1; j >= 0; --j) {
-        const double tau = taus[j];
-        if (tau == 0.0) continue;
-        const double *v = Vs + j * nr;
-        double pw = 0.0;
-        for (int r = j + 1 + lane; r < nr; r += 64) pw += v[r] * x[r];
-        const double w = (wave_sum(pw) + x[j]) * tau;
-        for (int r = j + 1 + lane; r < nr; r += 64) x[r] -= v[r] * w;
-        if (lane == 0) x[j] -= w;
+    const int NG = max(1, 256 / cw);
+    for (int j = kref - 1; j >= 0; --j) {
+      const double tau = taus[j];
+      if (tau == 0.0) continue;
+      const double *vj = Vs + j * ld;
+      if (tid < cw * NG) {
+        const int rg = tid % NG, cc = tid / NG;
+        const double *xc = X + cc * ld;
+        double s = 0.0;
+        for (int r = j + 1 + rg; r < nr; r += NG) s += vj[r] * xc[r];
+        part[tid] = s;
       }
+      __syncthreads();
+      if (tid < cw) {
+        double s = X[tid * ld + j];
+        for (int g = 0; g < NG; ++g) s += part[tid * NG + g];
+        Ws[tid] = tau * s;
+      }
+      __syncthreads();
+      const int span = nr - j;
+      const int total = cw * span;
+      for (int e = tid; e < total; e += 256) {
+        const int cc = e / span, r = j + e % span;
+        const double w = Ws[cc];
+        if (r == j) X[cc * ld + j] -= w;
+        else X[cc * ld + r] -= vj[r] * w;
+      }
+      __syncthreads();
     }
-    __syncthreads();
     for (int e = tid; e < nr * cw; e += 256) {
       int r = e / cw, cc = e - r * cw;
-      dst[(r0 + r) * a.dst.rs + (c0 + cc) * a.dst.cs] = X[cc * nr + r];
+      dst[(r0 + r) * a.dst.rs + (c0 + cc) * a.dst.cs] = X[cc * ld + r];
     }
     __syncthreads();
   }
@@ -239,7 +306,8 @@ hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_
                        hipStream_t s) {
   if (batch <= 0) return hipSuccess;
   const int64_t n = p.n;
-  const int64_t mb = qr_block_rows_max(n);
+  const int ch = qr_chunk(n, p.k);
+  const size_t lds_max = (size_t)kQrLdsDoubles * sizeof(double);
   // upward pass
   for (int L = 0; L < p.levels; ++L) {
     QrLevelArgs la{};
@@ -255,9 +323,9 @@ hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_
     la.off_rout = (L + 1 < p.levels) ? p.off_stack[L + 1] : p.off_rtop;
     la.ld_rout = n;
     const int64_t nrmax = (la.rows + la.blocks - 1) / la.blocks;
-    const size_t lds = (size_t)nrmax * n * sizeof(double);
+    const size_t lds = (size_t)(nrmax | 1) * n * sizeof(double);
     hipFuncSetAttribute((const void *)tsqr_factor_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)(mb * (n + kQrChunk) * sizeof(double)));
+                        (int)lds_max);
     tsqr_factor_kernel<<<dim3((unsigned)la.blocks, (unsigned)batch), 256, lds, s>>>(la);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -269,6 +337,7 @@ hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_
     fa.blocks = p.blocks[L];
     fa.n = n;
     fa.k = p.k;
+    fa.chunk = ch;
     fa.ws = ws;
     fa.wsp = wsp;
     fa.off_v = p.off_v[L];
@@ -280,9 +349,9 @@ hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_
     else fa.dst = Mat{ws + p.off_stack[L], p.k, 1, wsp};
     fa.rdst = fa.top ? r : Mat{nullptr, 0, 0, 0};
     const int64_t nrmax = (fa.rows + fa.blocks - 1) / fa.blocks;
-    const size_t lds = (size_t)nrmax * (n + kQrChunk) * sizeof(double);
+    const size_t lds = (size_t)(nrmax | 1) * (n + ch) * sizeof(double);
     hipFuncSetAttribute((const void *)tsqr_formq_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)(mb * (n + kQrChunk) * sizeof(double)));
+                        (int)lds_max);
     tsqr_formq_kernel<<<dim3((unsigned)fa.blocks, (unsigned)batch), 256, lds, s>>>(fa);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -1,39 +1,179 @@
-// Small dense SVD by one-sided (Hestenes) Jacobi, one workgroup per matrix,
-// followed by the truncation-rank choice of TT-Rounding.
+// Small dense SVD by one-sided (Hestenes) Jacobi, followed by the
+// truncation-rank choice of TT-Rounding.
 //
-// The kr x nc matrix is held column-major in LDS together with V (nc x nc).
-// A sweep visits every column pair once using the round-robin (circle)
-// ordering: nc' - 1 rounds (nc' = nc rounded up to even) of nc'/2 disjoint
-// pairs, each pair handled by a group of lanes inside one wavefront, so the
-// three inner products of a pair reduce with cross-lane shuffles.  A pair is
-// rotated when |a_p . a_q| > 1e-15 ||a_p|| ||a_q||; sweeps stop when no pair
-// needs rotating.  On exit A V^T-rotation gives A_final = R V with orthogonal
-// columns, sigma_j = ||A_final(:, j)||, U(:, j) = A_final(:, j) / sigma_j, so
-// U diag(sigma) V^T reproduces R exactly up to rounding even for zero or tiny
-// sigma_j.
+// One-sided Jacobi rotates column pairs of A = R (kr x nc) until all columns
+// are mutually orthogonal: A_final = R J with J orthogonal, so
+// sigma_j = ||A_final(:, j)|| and U(:, j) = A_final(:, j) / sigma_j.  The
+// columns of A_final stay orthogonal to working precision *relative to their
+// own norms*, so U is orthonormal even where sigma_j is tiny; the right factor
+// is therefore never accumulated: S V^T restricted to the kept rows is formed
+// as U_rho^T R, which equals S_rho V_rho^T up to rounding.
+//
+// A sweep visits every column pair once in the round-robin (circle) order:
+// nc' - 1 rounds (nc' = nc rounded up to even) of nc'/2 disjoint pairs.  A
+// pair is rotated when |a_p . a_q| > 1e-15 ||a_p|| ||a_q||; sweeps stop when
+// none is.
+//   * nc <= 64: one wavefront per matrix, lane c keeps column c in registers
+//     and fetches its round partner through LDS; no block barriers.
+//   * larger nc: one 256-thread workgroup per matrix, A in LDS, each pair
+//     handled by a group of lanes that reduce with shuffles.
 #include "common.h"
 
 namespace hatt {
 
-__global__ __launch_bounds__(256) void svd_trunc_kernel(SvdArgs a, int tpg) {
-  extern __shared__ double sm[];
+__device__ __forceinline__ int rr_partner(int c, int t, int np) {
+  // round t: position 0 holds index 0, position j >= 1 holds 1 + (j - 1 + t) mod (np - 1);
+  // positions k and np - 1 - k are paired
+  const int m = np - 1;
+  const int pos = (c == 0) ? 0 : 1 + ((c - 1 - t) % m + m) % m;
+  const int ppos = np - 1 - pos;
+  return (ppos == 0) ? 0 : 1 + (ppos - 1 + t) % m;
+}
+
+// Rank rule shared by both kernels (thread-serial, n <= 139).
+__device__ int choose_rank(const double *sig_sorted, int kr, int nc, const SvdArgs &a, int p) {
+  double tot2 = 0.0;
+  for (int j = 0; j < nc; ++j) tot2 += sig_sorted[j] * sig_sorted[j];
+  if (a.first_bond) a.delta2[p] = a.tol2_over_dm1 * tot2;
+  const double d2 = a.delta2[p];
+  int kmax = min(kr, nc);
+  if (a.prev_rank != nullptr) {
+    const int64_t lim = a.prev_rank[p * a.rank_bs] * a.n_mode;
+    if (lim < kmax) kmax = (int)lim;
+  }
+  int rho = kmax;
+  if (d2 > 0.0) {
+    double tail = 0.0;
+    for (int j = kmax - 1; j >= 1; --j) {
+      const double sj = sig_sorted[j];
+      tail += sj * sj;
+      if (tail <= d2) rho = j;
+      else break;
+    }
+  }
+  if (a.cap > 0 && rho > a.cap) rho = (int)a.cap;
+  if (rho > a.ucap) rho = a.ucap;
+  if (rho < 1) rho = 1;
+  a.rank_out[p * a.rank_bs] = rho;
+  return rho;
+}
+
+template <int KR>
+__global__ __launch_bounds__(64) void svd_wave_kernel(SvdArgs a) {
+  constexpr int LD = KR + 1;
+  __shared__ double xch[64 * LD];
+  __shared__ double sig[64];
+  __shared__ double sigs[64];
+  __shared__ int perm[64];
+  __shared__ int s_rho;
+  const int lane = threadIdx.x;
+  const int p = blockIdx.x;
   const int kr = a.kr, nc = a.nc;
-  double *A = sm;            // A[c * kr + r]
-  double *V = A + nc * kr;   // V[c * nc + r]  (column c of V)
+  const double *R = a.r + p * a.rbs;
+  double col[KR];
+#pragma unroll
+  for (int r = 0; r < KR; ++r) col[r] = (lane < nc && r < kr) ? R[r * nc + lane] : 0.0;
+  const int np = nc + (nc & 1);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    int rot = 0;
+    for (int t = 0; t < np - 1; ++t) {
+#pragma unroll
+      for (int r = 0; r < KR; ++r) xch[lane * LD + r] = col[r];
+      __syncthreads();
+      const int q = rr_partner(lane, t, np);
+      if (lane < nc && q < nc) {
+        const double *pc = xch + q * LD;
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int r = 0; r < KR; ++r) {
+          const double x = col[r], y = pc[r];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+        // roles: the lower index is "p"
+        const bool isp = lane < q;
+        const double ap = isp ? al : be, aq = isp ? be : al;
+        if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(ap * aq)) {
+          const double zeta = (aq - ap) / (2.0 * ga);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          if (isp) {
+#pragma unroll
+            for (int r = 0; r < KR; ++r) col[r] = cs * col[r] - sn * pc[r];
+          } else {
+#pragma unroll
+            for (int r = 0; r < KR; ++r) col[r] = sn * pc[r] + cs * col[r];
+          }
+          rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (!__any(rot)) break;
+  }
+  double s2 = 0.0;
+#pragma unroll
+  for (int r = 0; r < KR; ++r) s2 += col[r] * col[r];
+  sig[lane] = (lane < nc) ? sqrt(s2) : -1.0;
+#pragma unroll
+  for (int r = 0; r < KR; ++r) xch[lane * LD + r] = col[r];
+  __syncthreads();
+  if (lane < nc) {
+    int rk = 0;
+    const double sc = sig[lane];
+    for (int j = 0; j < nc; ++j) rk += (sig[j] > sc) || (sig[j] == sc && j < lane);
+    perm[rk] = lane;
+    sigs[rk] = sc;
+  }
+  __syncthreads();
+  if (lane == 0) s_rho = choose_rank(sigs, kr, nc, a, p);
+  __syncthreads();
+  const int rho = s_rho;
+  double *U = a.u + p * a.ubs;
+  for (int e = lane; e < kr * a.ucap; e += 64) {
+    const int r = e / a.ucap, j = e - r * a.ucap;
+    double v = 0.0;
+    if (j < rho) {
+      const int c = perm[j];
+      const double sc = sigs[j];
+      v = (sc > 0.0) ? xch[c * LD + r] / sc : 0.0;
+    }
+    U[e] = v;
+  }
+  // S V^T rows = U_rho^T R: lane owns column c of R
+  double *S = a.svt + p * a.sbs;
+  for (int c = lane; c < nc; c += 64) {
+    for (int j = 0; j < a.ucap; ++j) {
+      double v = 0.0;
+      if (j < rho) {
+        const int cj = perm[j];
+        const double sc = sigs[j];
+        if (sc > 0.0) {
+          const double inv = 1.0 / sc;
+          for (int r = 0; r < kr; ++r) v += xch[cj * LD + r] * R[r * nc + c];
+          v *= inv;
+        }
+      }
+      S[j * nc + c] = v;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void svd_block_kernel(SvdArgs a, int tpg) {
+  extern __shared__ double A[];  // A[c * kr + r]
   __shared__ double sig[kSvdMaxN];
+  __shared__ double sigs[kSvdMaxN];
   __shared__ int perm[kSvdMaxN];
   __shared__ int s_rot;
   __shared__ int s_rho;
+  const int kr = a.kr, nc = a.nc;
   const int tid = threadIdx.x;
   const int p = blockIdx.x;
   const double *R = a.r + p * a.rbs;
   for (int e = tid; e < kr * nc; e += 256) {
     int r = e / nc, c = e - r * nc;
     A[c * kr + r] = R[e];
-  }
-  for (int e = tid; e < nc * nc; e += 256) {
-    int c = e / nc, r = e - c * nc;
-    V[e] = (r == c) ? 1.0 : 0.0;
   }
   const int np = nc + (nc & 1);
   const int npairs = np / 2;
@@ -72,12 +212,6 @@ __global__ __launch_bounds__(256) void svd_trunc_kernel(SvdArgs a, int tpg) {
               ap[r] = cs * x - sn * y;
               aq[r] = sn * x + cs * y;
             }
-            double *vp = V + ip * nc, *vq = V + iq * nc;
-            for (int r = gl; r < nc; r += tpg) {
-              const double x = vp[r], y = vq[r];
-              vp[r] = cs * x - sn * y;
-              vq[r] = sn * x + cs * y;
-            }
             myrot = 1;
           }
         }
@@ -89,7 +223,6 @@ __global__ __launch_bounds__(256) void svd_trunc_kernel(SvdArgs a, int tpg) {
     if (s_rot == 0) break;
     __syncthreads();
   }
-  // singular values and descending order (ties keep index order)
   for (int c = tid; c < nc; c += 256) {
     double s2 = 0.0;
     for (int r = 0; r < kr; ++r) s2 += A[c * kr + r] * A[c * kr + r];
@@ -101,34 +234,10 @@ __global__ __launch_bounds__(256) void svd_trunc_kernel(SvdArgs a, int tpg) {
     const double sc = sig[c];
     for (int j = 0; j < nc; ++j) rk += (sig[j] > sc) || (sig[j] == sc && j < c);
     perm[rk] = c;
+    sigs[rk] = sc;
   }
   __syncthreads();
-  if (tid == 0) {
-    double tot2 = 0.0;
-    for (int j = 0; j < nc; ++j) tot2 += sig[j] * sig[j];
-    if (a.first_bond) a.delta2[p] = a.tol2_over_dm1 * tot2;
-    const double d2 = a.delta2[p];
-    int kmax = min(kr, nc);
-    if (a.prev_rank != nullptr) {
-      const int64_t lim = a.prev_rank[p * a.rank_bs] * a.n_mode;
-      if (lim < kmax) kmax = (int)lim;
-    }
-    int rho = kmax;
-    if (d2 > 0.0) {
-      double tail = 0.0;
-      for (int j = kmax - 1; j >= 1; --j) {
-        const double sj = sig[perm[j]];
-        tail += sj * sj;
-        if (tail <= d2) rho = j;
-        else break;
-      }
-    }
-    if (a.cap > 0 && rho > a.cap) rho = (int)a.cap;
-    if (rho > a.ucap) rho = a.ucap;
-    if (rho < 1) rho = 1;
-    s_rho = rho;
-    a.rank_out[p * a.rank_bs] = rho;
-  }
+  if (tid == 0) s_rho = choose_rank(sigs, kr, nc, a, p);
   __syncthreads();
   const int rho = s_rho;
   double *U = a.u + p * a.ubs;
@@ -137,18 +246,22 @@ __global__ __launch_bounds__(256) void svd_trunc_kernel(SvdArgs a, int tpg) {
     double v = 0.0;
     if (j < rho) {
       const int c = perm[j];
-      const double sc = sig[c];
+      const double sc = sigs[j];
       v = (sc > 0.0) ? A[c * kr + r] / sc : 0.0;
     }
     U[e] = v;
   }
   double *S = a.svt + p * a.sbs;
   for (int e = tid; e < a.ucap * nc; e += 256) {
-    int j = e / nc, col = e - j * nc;
+    int j = e / nc, c = e - j * nc;
     double v = 0.0;
     if (j < rho) {
-      const int c = perm[j];
-      v = sig[c] * V[c * nc + col];
+      const int cj = perm[j];
+      const double sc = sigs[j];
+      if (sc > 0.0) {
+        for (int r = 0; r < kr; ++r) v += A[cj * kr + r] * R[r * nc + c];
+        v /= sc;
+      }
     }
     S[e] = v;
   }
@@ -156,15 +269,21 @@ __global__ __launch_bounds__(256) void svd_trunc_kernel(SvdArgs a, int tpg) {
 
 hipError_t launch_svd_trunc(const SvdArgs &a, hipStream_t s) {
   if (a.batch <= 0) return hipSuccess;
-  if (a.nc > kSvdMaxN || a.kr > a.nc || a.kr < 1) return hipErrorInvalidValue;
+  if (a.kr > a.nc || a.kr < 1) return hipErrorInvalidValue;
+  if (a.nc <= 64) {
+    if (a.kr <= 16) svd_wave_kernel<16><<<a.batch, 64, 0, s>>>(a);
+    else if (a.kr <= 32) svd_wave_kernel<32><<<a.batch, 64, 0, s>>>(a);
+    else svd_wave_kernel<64><<<a.batch, 64, 0, s>>>(a);
+    return hipGetLastError();
+  }
+  if (a.nc > kSvdMaxN || (int64_t)a.nc * a.kr > kQrLdsDoubles) return hipErrorInvalidValue;
   const int np = a.nc + (a.nc & 1);
   const int npairs = np / 2;
   int tpg = 64;
   while (tpg > 1 && tpg * npairs > 256) tpg >>= 1;
-  const size_t lds = (size_t)(a.nc * a.kr + a.nc * a.nc) * sizeof(double);
-  hipFuncSetAttribute((const void *)svd_trunc_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds);
-  svd_trunc_kernel<<<a.batch, 256, lds, s>>>(a, tpg);
+  const size_t lds = (size_t)a.nc * a.kr * sizeof(double);
+  hipFuncSetAttribute((const void *)svd_block_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  svd_block_kernel<<<a.batch, 256, lds, s>>>(a, tpg);
   return hipGetLastError();
 }
 

@@ -142,3 +142,17 @@ def test_unsupported_widths_are_reported():
     with pytest.raises(HattError) as e:
         api.plan(x, x, 300)
     assert e.value.status == -7
+
+
+def test_perfmodel_matches_oracle_counts():
+    from oracle import flops as oflops
+    from paper_2410_04385_amd import perfmodel
+
+    n = [6, 7, 5, 8, 6]
+    rx, ry, ell = [1, 3, 4, 5, 2, 1], [1, 2, 3, 4, 3, 1], [1, 5, 9, 7, 4, 1]
+    a = perfmodel.hatt_round_flops(n, rx, ry, ell, cap=None)
+    b = oflops.hatt1_bonds(n, rx, ry, ell)
+    assert abs(a["sandwich"] - (b["wl"] + b["update"])) < 1e-6 * a["sandwich"]
+    assert abs(a["gemm_f64"] - (b["wr"] + b["xw"] + b["proj"])) < 1e-6 * a["gemm_f64"]
+    assert abs(a["tsqr"] - b["qr"]) < 1e-6 * a["tsqr"]
+    assert perfmodel.chatt_paper(20, 32, 20, 20, 40) == oflops.table41(20, 32, 20, 20, 40)["hatt1"]
