@@ -12,6 +12,7 @@ namespace hatt {
 // Largest column count of one TSQR panel and of the in-LDS Jacobi SVD.
 constexpr int kQrMaxCols = 128;
 constexpr int kSvdMaxN = 139;
+constexpr int kSvdBigMaxN = 1024;
 // Doubles of dynamic LDS a TSQR block may use (of the 160 KiB per CU).
 constexpr int kQrLdsDoubles = 19456;
 
@@ -75,6 +76,8 @@ hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s);
 // Batched strided copy: dst(r, c) = src(r, c) for an M x N block.
 hipError_t launch_copy(CMat src, Mat dst, int64_t M, int64_t N, int batch, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t s);
+// Batched strided accumulate: dst(r, c) += src(r, c).
+hipError_t launch_add(CMat src, Mat dst, int64_t M, int64_t N, int batch, hipStream_t s);
 hipError_t launch_fill_i64(int64_t *p, int64_t count, int64_t v, hipStream_t s);
 // dst[p * len + k] = pattern[k] for p < batch, k < len (len <= kMaxRankPattern).
 constexpr int kMaxRankPattern = 256;
@@ -140,6 +143,19 @@ struct SvdArgs {
   int64_t rank_bs;
 };
 hipError_t launch_svd_trunc(const SvdArgs &a, hipStream_t s);
+
+// Block one-sided Jacobi for matrices too large for one workgroup's LDS:
+// A (kr x nc per pair, column-major in `acol`, pair stride acs) is rotated in
+// place, one launch per round of disjoint block pairs; flags[2p] collects
+// "rotated this sweep", flags[2p+1] is set once a full sweep rotated nothing.
+int svd_big_block_width(int kr);
+hipError_t launch_svd_big_prepare(const double *r, int64_t rbs, int kr, int nc, double *acol, int64_t acs,
+                                  int *flags, int batch, hipStream_t s);
+hipError_t launch_svd_big_round(double *acol, int64_t acs, int kr, int nc, int bw, int nb, int t, int *flags,
+                                int batch, hipStream_t s);
+hipError_t launch_svd_big_sweep_end(int *flags, int batch, hipStream_t s);
+// sigma, order, rank choice, U and S V^T (= U^T R) from the rotated columns.
+hipError_t launch_svd_big_finish(const SvdArgs &a, const double *acol, int64_t acs, hipStream_t s);
 
 // Frobenius norm of a batch of contiguous blocks: out[p] = ||x_p||.
 hipError_t launch_block_norm(const double *x, int64_t count, int64_t bs, double *out, int batch,

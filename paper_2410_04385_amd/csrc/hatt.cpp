@@ -8,6 +8,7 @@
 #include <cmath>
 
 #include <algorithm>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -181,6 +182,138 @@ hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_
 }
 
 // ---------------------------------------------------------------------------
+// QR dispatch.  Up to kQrMaxCols columns: one TSQR.  Wider (m >= n): block
+// Gram-Schmidt applied twice per panel of kPanel columns (the panel is
+// projected against the finished columns twice, each time with two GEMMs),
+// then the panel itself is factored by TSQR; R collects the projection
+// coefficients above the diagonal blocks.
+constexpr int64_t kPanel = 64;
+
+struct QrOp {
+  int64_t m = 0, n = 0, k = 0;
+  bool big = false;
+  bool wide = false;                 // m < n, n > kQrMaxCols: QR of the first m columns, then R2 = Q^T A2
+  std::shared_ptr<QrOp> sub;
+  QrPlan direct{};
+  std::vector<QrPlan> panels;
+  int64_t ws_doubles = 0;  // per pair
+};
+
+bool qr_prepare(int64_t m, int64_t n, QrOp *op) {
+  op->m = m;
+  op->n = n;
+  op->k = std::min(m, n);
+  op->big = op->wide = false;
+  if (n <= kQrMaxCols) {
+    if (!qr_make_plan(m, n, &op->direct)) return false;
+    op->ws_doubles = op->direct.ws_doubles;
+    return true;
+  }
+  if (m < n) {
+    // Householder reflectors of a wide matrix depend only on its first m columns
+    op->wide = true;
+    op->sub = std::make_shared<QrOp>();
+    if (!qr_prepare(m, m, op->sub.get())) return false;
+    op->ws_doubles = op->sub->ws_doubles;
+    return true;
+  }
+  op->big = true;
+  op->panels.clear();
+  int64_t w = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += kPanel) {
+    const int64_t cw = std::min(kPanel, n - c0);
+    QrPlan pl;
+    if (!qr_make_plan(m, cw, &pl)) return false;
+    op->panels.push_back(pl);
+    w = std::max(w, pl.ws_doubles);
+  }
+  op->ws_doubles = w + 2 * n * kPanel;  // TSQR tree + two coefficient blocks
+  return true;
+}
+
+// A (m x n), Q (m x k), R (k x n row-major with row stride r.rs, or null).
+// R, when given, must be a contiguous per-pair block of rbuf doubles.
+hatt_status qr_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, int64_t rbuf, double *ws, int64_t wsp,
+                    int P, GemmCtx &gc, hipStream_t st) {
+  if (op.wide) {
+    hatt_status s0 = qr_exec(run, *op.sub, A, Q, R, rbuf, ws, wsp, P, gc, st);
+    if (s0 != HATT_OK) return s0;
+    if (R.ptr) {
+      const int64_t m = op.m;
+      return gemm(run, gc, CMat{Q.ptr, Q.cs, Q.rs, Q.bs}, CMat{A.ptr + m * A.cs, A.rs, A.cs, A.bs},
+                  Mat{R.ptr + m * R.cs, R.rs, R.cs, R.bs}, m, op.n - m, m, 1.0, 0.0, P, st, true);
+    }
+    return HATT_OK;
+  }
+  if (!op.big) {
+    LAUNCH(launch_tsqr(op.direct, A, Q, R, ws, wsp, P, st));
+    return HATT_OK;
+  }
+  const int64_t m = op.m, n = op.n;
+  double *coef0 = ws + (op.ws_doubles - 2 * n * kPanel);
+  double *coef1 = coef0 + n * kPanel;
+  LAUNCH(launch_copy(A, Q, m, n, P, st));
+  if (R.ptr) LAUNCH(launch_fill(R.ptr, (int64_t)P * rbuf, 0.0, st));
+  int pi = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += kPanel, ++pi) {
+    const int64_t cw = std::min(kPanel, n - c0);
+    CMat Qprev{Q.ptr, Q.rs, Q.cs, Q.bs};
+    Mat Qpan{Q.ptr + c0 * Q.cs, Q.rs, Q.cs, Q.bs};
+    CMat Qpanc{Qpan.ptr, Qpan.rs, Qpan.cs, Qpan.bs};
+    if (c0 > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        double *cf = pass ? coef1 : coef0;
+        // cf (c0 x cw) = Qprev^T Qpan
+        hatt_status s1 = gemm(run, gc, CMat{Qprev.ptr, Qprev.cs, Qprev.rs, Qprev.bs}, Qpanc,
+                              Mat{cf, cw, 1, wsp}, c0, cw, m, 1.0, 0.0, P, st, true);
+        if (s1 != HATT_OK) return s1;
+        // Qpan -= Qprev cf
+        s1 = gemm(run, gc, Qprev, CMat{cf, cw, 1, wsp}, Qpan, m, cw, c0, -1.0, 1.0, P, st, false);
+        if (s1 != HATT_OK) return s1;
+        if (R.ptr) {
+          Mat rblk{R.ptr + c0 * R.cs, R.rs, R.cs, R.bs};
+          if (pass == 0) LAUNCH(launch_copy(CMat{cf, cw, 1, wsp}, rblk, c0, cw, P, st));
+          else LAUNCH(launch_add(CMat{cf, cw, 1, wsp}, rblk, c0, cw, P, st));
+        }
+      }
+    }
+    Mat rpp = R.ptr ? Mat{R.ptr + c0 * R.rs + c0 * R.cs, R.rs, R.cs, R.bs} : Mat{nullptr, 0, 0, 0};
+    LAUNCH(launch_tsqr(op.panels[pi], Qpanc, Qpan, rpp, ws, wsp, P, st));
+  }
+  return HATT_OK;
+}
+
+// SVD + rank choice dispatch: one-workgroup Jacobi when the matrix fits in
+// LDS, else block Jacobi over global memory (scratch `big` of kr*nc doubles
+// per pair plus 2 ints).
+constexpr int kBigSweeps = 14;
+
+int64_t svd_ws_doubles(int kr, int nc) {
+  if (nc <= kSvdMaxN && (int64_t)kr * nc <= kQrLdsDoubles) return 0;
+  return (int64_t)kr * nc + 1;
+}
+
+hatt_status svd_exec(bool run, const SvdArgs &sa, double *big, int64_t bigp, int *flags, hipStream_t st) {
+  if (sa.nc <= kSvdMaxN && (int64_t)sa.kr * sa.nc <= kQrLdsDoubles) {
+    LAUNCH(launch_svd_trunc(sa, st));
+    return HATT_OK;
+  }
+  if (sa.nc > kSvdBigMaxN) return fail(HATT_EUNSUPPORTED, "SVD of more than 1024 columns is not built");
+  const int bw = svd_big_block_width(sa.kr);
+  if (bw < 1) return fail(HATT_EUNSUPPORTED, "SVD column too long for the block Jacobi");
+  int nb = (sa.nc + bw - 1) / bw;
+  nb += nb & 1;
+  LAUNCH(launch_svd_big_prepare(sa.r, sa.rbs, sa.kr, sa.nc, big, bigp, flags, sa.batch, st));
+  for (int sw = 0; sw < kBigSweeps; ++sw) {
+    for (int t = 0; t < nb - 1; ++t)
+      LAUNCH(launch_svd_big_round(big, bigp, sa.kr, sa.nc, bw, nb, t, flags, sa.batch, st));
+    LAUNCH(launch_svd_big_sweep_end(flags, sa.batch, st));
+  }
+  LAUNCH(launch_svd_big_finish(sa, big, bigp, st));
+  return HATT_OK;
+}
+
+// ---------------------------------------------------------------------------
 // TT-Rounding (Alg. 1) of `batch` trains.
 //   src: cores with ranks rin (layout from rin), pair stride sstride.
 //   If in_place, the work is done directly on src (then rin must already
@@ -213,7 +346,7 @@ std::vector<int64_t> round_caps(const std::vector<int64_t> &n, const std::vector
   return c;
 }
 
-hatt_status round_run(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipStream_t st) {
+hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipStream_t st) {
   const int d = (int)sp.n.size();
   const int P = sp.batch;
   const auto &n = sp.n;
@@ -225,34 +358,34 @@ hatt_status round_run(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipStr
   for (int c = d - 1; c >= 1; --c) rb[c] = std::min(sp.rin[c], n[c] * rb[c + 1]);
   const auto &cap = sp.cap;
   // --- sizes
-  int64_t qr_ws = 0, qbuf = 1, rbuf = 1, ubuf = 1, sbuf = 1, tbuf = 1, tmp = 1;
-  std::vector<QrPlan> plan_rl(d), plan_lr(d);
+  int64_t qr_ws = 1, qbuf = 1, rbuf = 1, ubuf = 1, sbuf = 1, tbuf = 1, tmp = 1, svd_ws = 1;
+  std::vector<QrOp> op_rl(d), op_lr(d);
   for (int c = d - 1; c >= 1; --c) {
     const int64_t m = n[c] * rb[c + 1], nc = sp.rin[c];
-    if (!qr_make_plan(m, nc, &plan_rl[c]))
+    if (!qr_prepare(m, nc, &op_rl[c]))
       return fail(HATT_EUNSUPPORTED, "TT-Rounding: a right-to-left QR of " + std::to_string(m) + " x " +
-                                         std::to_string(nc) + " exceeds this build's QR limits (<= " +
-                                         std::to_string(kQrMaxCols) + " columns)");
-    qr_ws = std::max(qr_ws, plan_rl[c].ws_doubles);
-    rbuf = std::max(rbuf, plan_rl[c].k * nc);
-    tmp = std::max(tmp, sp.rin[c - 1] * n[c - 1] * plan_rl[c].k);
+                                         std::to_string(nc) + " exceeds this build's QR limits");
+    qr_ws = std::max(qr_ws, op_rl[c].ws_doubles);
+    rbuf = std::max(rbuf, op_rl[c].k * nc);
+    tmp = std::max(tmp, sp.rin[c - 1] * n[c - 1] * op_rl[c].k);
   }
   if (!sp.norm_only) {
     for (int c = 0; c < d - 1; ++c) {
       const int64_t m = cap[c] * n[c], nc = rb[c + 1];
-      if (!qr_make_plan(m, nc, &plan_lr[c]))
+      if (!qr_prepare(m, nc, &op_lr[c]))
         return fail(HATT_EUNSUPPORTED, "TT-Rounding: a left-to-right QR of " + std::to_string(m) + " x " +
                                            std::to_string(nc) + " exceeds this build's QR limits");
-      if (nc > kSvdMaxN)
+      if (nc > kSvdBigMaxN)
         return fail(HATT_EUNSUPPORTED, "TT-Rounding: bond rank " + std::to_string(nc) +
-                                           " exceeds this build's SVD limit (" + std::to_string(kSvdMaxN) + ")");
-      const int64_t k = plan_lr[c].k;
-      qr_ws = std::max(qr_ws, plan_lr[c].ws_doubles);
+                                           " exceeds this build's SVD limit (" + std::to_string(kSvdBigMaxN) + ")");
+      const int64_t k = op_lr[c].k;
+      qr_ws = std::max(qr_ws, op_lr[c].ws_doubles);
       qbuf = std::max(qbuf, m * k);
       rbuf = std::max(rbuf, k * nc);
       ubuf = std::max(ubuf, k * cap[c + 1]);
       sbuf = std::max(sbuf, cap[c + 1] * nc);
       tbuf = std::max(tbuf, cap[c + 1] * n[c + 1] * rb[c + 2]);
+      svd_ws = std::max(svd_ws, svd_ws_doubles((int)k, (int)nc));
     }
   }
   double *work = sp.in_place ? sp.src : ws.d((int64_t)P * stot);
@@ -266,6 +399,8 @@ hatt_status round_run(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipStr
   double *T1 = ws.d((int64_t)P * tbuf);
   double *Tm = ws.d((int64_t)P * tmp);
   double *dl2 = ws.d(P);
+  double *svdbig = ws.d((int64_t)P * svd_ws);
+  int *flags = (int *)ws.d(P);
 
   if (!sp.in_place)
     LAUNCH(launch_copy(CMat{sp.src, stot, 1, sp.sstride}, Mat{work, stot, 1, stot}, 1, stot, P, st));
@@ -280,17 +415,18 @@ hatt_status round_run(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipStr
   }
   // --- right-to-left orthogonalisation; core c layout: [*][n_c][rb_{c+1}] compact
   for (int c = d - 1; c >= 1; --c) {
-    const QrPlan &pl = plan_rl[c];
-    const int64_t m = n[c] * rb[c + 1], nc = sp.rin[c], k = pl.k;
+    const QrOp &op = op_rl[c];
+    const int64_t m = n[c] * rb[c + 1], nc = sp.rin[c], k = op.k;
     double *core = work + soff[c];
     // H(B_c)^T is m x nc: element (j, a) = core[a * m + j]
-    LAUNCH(launch_tsqr(pl, CMat{core, 1, m, wstride}, Mat{core, 1, m, wstride}, Mat{Rb, nc, 1, rbuf},
-                       wqr, qr_ws, P, st));
+    hatt_status s = qr_exec(run, op, CMat{core, 1, m, wstride}, Mat{core, 1, m, wstride}, Mat{Rb, nc, 1, rbuf},
+                            rbuf, wqr, qr_ws, P, gc, st);
+    if (s != HATT_OK) return s;
     // V(B_{c-1}) R^T, V(B_{c-1}) is (rin_{c-1} n_{c-1}) x nc with row stride nc
     double *prev = work + soff[c - 1];
     const int64_t mp = sp.rin[c - 1] * n[c - 1];
-    hatt_status s = gemm(run, gc, CMat{prev, nc, 1, wstride}, CMat{Rb, 1, nc, rbuf}, Mat{Tm, k, 1, tmp}, mp,
-                         k, nc, 1.0, 0.0, P, st, false);
+    s = gemm(run, gc, CMat{prev, nc, 1, wstride}, CMat{Rb, 1, nc, rbuf}, Mat{Tm, k, 1, tmp}, mp, k, nc, 1.0,
+             0.0, P, st, true);
     if (s != HATT_OK) return s;
     LAUNCH(launch_copy(CMat{Tm, k, 1, tmp}, Mat{prev, k, 1, wstride}, mp, k, P, st));
   }
@@ -306,10 +442,11 @@ hatt_status round_run(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipStr
   const double tol2 = (sp.tol > 0.0) ? sp.tol * sp.tol / (double)(d - 1) : 0.0;
   double *Tcur = nullptr, *Tnext = T0;
   for (int c = 0; c < d - 1; ++c) {
-    const QrPlan &pl = plan_lr[c];
-    const int64_t m = cap[c] * n[c], nc = rb[c + 1], k = pl.k;
+    const QrOp &op = op_lr[c];
+    const int64_t m = cap[c] * n[c], nc = rb[c + 1], k = op.k;
     CMat V = (c == 0) ? CMat{work + soff[0], nc, 1, wstride} : CMat{Tcur, nc, 1, tbuf};
-    LAUNCH(launch_tsqr(pl, V, Mat{Qb, k, 1, qbuf}, Mat{Rb, nc, 1, rbuf}, wqr, qr_ws, P, st));
+    hatt_status s = qr_exec(run, op, V, Mat{Qb, k, 1, qbuf}, Mat{Rb, nc, 1, rbuf}, rbuf, wqr, qr_ws, P, gc, st);
+    if (s != HATT_OK) return s;
     SvdArgs sa{};
     sa.r = Rb;
     sa.rbs = rbuf;
@@ -330,15 +467,16 @@ hatt_status round_run(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipStr
     sa.rank_out = sp.orank + c + 1;
     sa.rank_bs = d + 1;
     if (k > nc) return fail(HATT_EUNSUPPORTED, "internal: QR rank exceeds columns");
-    LAUNCH(launch_svd_trunc(sa, st));
+    s = svd_exec(run, sa, svdbig, svd_ws, flags, st);
+    if (s != HATT_OK) return s;
     // out core c = Q U  (m x cap_{c+1})
-    hatt_status s = gemm(run, gc, CMat{Qb, k, 1, qbuf}, CMat{Ub, cap[c + 1], 1, ubuf},
-                         Mat{sp.out + ooff[c], cap[c + 1], 1, sp.ostride}, m, cap[c + 1], k, 1.0, 0.0, P, st, false);
+    s = gemm(run, gc, CMat{Qb, k, 1, qbuf}, CMat{Ub, cap[c + 1], 1, ubuf},
+             Mat{sp.out + ooff[c], cap[c + 1], 1, sp.ostride}, m, cap[c + 1], k, 1.0, 0.0, P, st, true);
     if (s != HATT_OK) return s;
     // next core = SVt H(B_{c+1}):  (cap_{c+1} x nc) (nc x n_{c+1} rb_{c+2})
     const int64_t ncol = n[c + 1] * rb[c + 2];
     s = gemm(run, gc, CMat{Sb, nc, 1, sbuf}, CMat{work + soff[c + 1], ncol, 1, wstride},
-             Mat{Tnext, ncol, 1, tbuf}, cap[c + 1], ncol, nc, 1.0, 0.0, P, st, false);
+             Mat{Tnext, ncol, 1, tbuf}, cap[c + 1], ncol, nc, 1.0, 0.0, P, st, true);
     if (s != HATT_OK) return s;
     Tcur = Tnext;
     Tnext = (Tnext == T0) ? T1 : T0;
@@ -347,6 +485,19 @@ hatt_status round_run(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipStr
   LAUNCH(launch_copy(CMat{Tcur, 1, 1, tbuf}, Mat{sp.out + ooff[d - 1], 1, 1, sp.ostride}, 1,
                      cap[d - 1] * n[d - 1], P, st));
   return HATT_OK;
+}
+
+// Measures the split-K partial buffer with a dry pass, reserves it at the
+// front of this call's workspace share, then runs (or measures) the body.
+hatt_status round_run(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &, hipStream_t st) {
+  Ws probe(nullptr);
+  GemmCtx g0{nullptr, 0, 0};
+  hatt_status s = round_body(false, sp, probe, g0, st);
+  if (s != HATT_OK) return s;
+  GemmCtx g1{nullptr, 0, 0};
+  g1.part = ws.d(std::max<int64_t>(g0.part_need, 1));
+  g1.part_cap = g0.part_need;
+  return round_body(run, sp, ws, g1, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -361,7 +512,7 @@ struct HattSpec {
   int64_t *orank;
 };
 
-hatt_status hatt_run(bool run, const HattSpec &sp, Ws &ws, hipStream_t st) {
+hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStream_t st) {
   const int d = sp.X.d, P = sp.X.batch;
   const auto &n = sp.X.n, &r = sp.X.r, &s = sp.Y.r, &l = sp.ell;
   std::vector<int64_t> ooff, skoff;
@@ -371,7 +522,6 @@ hatt_status hatt_run(bool run, const HattSpec &sp, Ws &ws, hipStream_t st) {
   const double *xd = sp.X.data, *yd = sp.Y.data;
   const int64_t xs = sp.X.stride, ys = sp.Y.stride;
 
-  GemmCtx gc{nullptr, 0, 0};
   // ---- sizes
   std::vector<int64_t> woff(d + 1, 0);
   int64_t wtot = 0;
@@ -379,16 +529,16 @@ hatt_status hatt_run(bool run, const HattSpec &sp, Ws &ws, hipStream_t st) {
     woff[b] = wtot;
     wtot += r[b] * s[b] * l[b];
   }
-  int64_t wlsz = 1, xsz = 1, ysz = 1, msz = 1, qrws = 0;
-  std::vector<QrPlan> qp(d);
+  int64_t wlsz = 1, xsz = 1, ysz = 1, msz = 1, qrws = 1;
+  std::vector<QrOp> qp(d);
   for (int c = 1; c <= d - 2; ++c) wlsz = std::max(wlsz, r[c] * s[c] * n[c] * l[c + 1]);
   for (int c = 0; c < d; ++c) xsz = std::max(xsz, l[c] * n[c] * r[c + 1] * s[c + 1]);
   for (int c = 0; c < d - 1; ++c) {
     ysz = std::max(ysz, l[c] * n[c] * l[c + 1]);
     msz = std::max(msz, l[c + 1] * r[c + 1] * s[c + 1]);
-    if (!qr_make_plan(l[c] * n[c], l[c + 1], &qp[c]))
-      return fail(HATT_EUNSUPPORTED, "HaTT: sketch width " + std::to_string(l[c + 1]) +
-                                         " exceeds this build's QR limit (" + std::to_string(kQrMaxCols) + ")");
+    if (!qr_prepare(l[c] * n[c], l[c + 1], &qp[c]))
+      return fail(HATT_EUNSUPPORTED, "HaTT: the QR of a " + std::to_string(l[c] * n[c]) + " x " +
+                                         std::to_string(l[c + 1]) + " sketched frame is not supported");
     qrws = std::max(qrws, qp[c].ws_doubles);
   }
   double *sk = nullptr;
@@ -405,22 +555,7 @@ hatt_status hatt_run(bool run, const HattSpec &sp, Ws &ws, hipStream_t st) {
   double *Xc = ws.d((int64_t)P * xsz);
   double *Yb = ws.d((int64_t)P * ysz);
   double *Mb = ws.d((int64_t)P * msz);
-  double *wqr = ws.d((int64_t)P * std::max<int64_t>(qrws, 1));
-  // split-K partials: measured below by a dry pass over the GEMM shapes
-  int64_t part_need = 0;
-  {
-    auto acc = [&](int64_t M, int64_t N, int64_t K) {
-      int ks = gemm_pick_ksplit(M, N, K, P);
-      if (ks > 1) part_need = std::max(part_need, (int64_t)P * ks * M * N);
-    };
-    for (int c = d - 2; c >= 1; --c) acc(r[c] * s[c], l[c], n[c] * l[c + 1]);
-    for (int c = 0; c < d - 1; ++c) {
-      acc(l[c] * n[c], l[c + 1], r[c + 1] * s[c + 1]);
-      acc(l[c + 1], r[c + 1] * s[c + 1], l[c] * n[c]);
-    }
-  }
-  gc.part = ws.d(std::max<int64_t>(part_need, 1));
-  gc.part_cap = part_need;
+  double *wqr = ws.d((int64_t)P * qrws);
 
   if (d == 1) {
     LAUNCH(launch_fill_i64(sp.orank, (int64_t)P * 2, 1, st));
@@ -499,8 +634,9 @@ hatt_status hatt_run(bool run, const HattSpec &sp, Ws &ws, hipStream_t st) {
                            Mat{Yb, l[c + 1], 1, ysz}, m, l[c + 1], rs1, 1.0, 0.0, P, st, true);
     if (stt != HATT_OK) return stt;
     double *qcore = sp.out + ooff[c];
-    LAUNCH(launch_tsqr(qp[c], CMat{Yb, l[c + 1], 1, ysz}, Mat{qcore, l[c + 1], 1, sp.ostride},
-                       Mat{nullptr, 0, 0, 0}, wqr, qrws, P, st));
+    stt = qr_exec(run, qp[c], CMat{Yb, l[c + 1], 1, ysz}, Mat{qcore, l[c + 1], 1, sp.ostride},
+                  Mat{nullptr, 0, 0, 0}, 0, wqr, qrws, P, gc, st);
+    if (stt != HATT_OK) return stt;
     stt = gemm(run, gc, CMat{qcore, 1, l[c + 1], sp.ostride}, CMat{Xc, rs1, 1, xsz}, Mat{Mb, rs1, 1, msz},
                l[c + 1], rs1, m, 1.0, 0.0, P, st, true);
     if (stt != HATT_OK) return stt;
@@ -569,6 +705,17 @@ hatt_status hatt_run(bool run, const HattSpec &sp, Ws &ws, hipStream_t st) {
     if (s1 != HATT_OK) return s1;
   }
   return HATT_OK;
+}
+
+hatt_status hatt_run(bool run, const HattSpec &sp, Ws &ws, hipStream_t st) {
+  Ws probe(nullptr);
+  GemmCtx g0{nullptr, 0, 0};
+  hatt_status s = hatt_body(false, sp, probe, g0, st);
+  if (s != HATT_OK) return s;
+  GemmCtx g1{nullptr, 0, 0};
+  g1.part = ws.d(std::max<int64_t>(g0.part_need, 1));
+  g1.part_cap = g0.part_need;
+  return hatt_body(run, sp, ws, g1, st);
 }
 
 }  // namespace

@@ -269,6 +269,24 @@ hipError_t launch_copy(CMat src, Mat dst, int64_t M, int64_t N, int batch, hipSt
   return hipGetLastError();
 }
 
+__global__ void add_kernel(CMat src, Mat dst, int64_t M, int64_t N, int batch) {
+  const int64_t per = M * N, total = per * batch;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / per, rem = e - p * per;
+    const int64_t r = rem / N, c = rem - r * N;
+    dst.ptr[p * dst.bs + r * dst.rs + c * dst.cs] += src.ptr[p * src.bs + r * src.rs + c * src.cs];
+  }
+}
+
+hipError_t launch_add(CMat src, Mat dst, int64_t M, int64_t N, int batch, hipStream_t s) {
+  const int64_t total = M * N * batch;
+  if (total <= 0) return hipSuccess;
+  int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  add_kernel<<<grid, 256, 0, s>>>(src, dst, M, N, batch);
+  return hipGetLastError();
+}
+
 __global__ void fill_kernel(double *p, int64_t count, double v) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
        e += (int64_t)gridDim.x * blockDim.x)

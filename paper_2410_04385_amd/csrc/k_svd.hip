@@ -287,4 +287,200 @@ hipError_t launch_svd_trunc(const SvdArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Block one-sided Jacobi for nc > kSvdMaxN.  Columns are grouped in blocks of
+// bw; a round pairs blocks with the circle order and every workgroup fully
+// orthogonalises the columns of its two blocks against each other (an inner
+// one-sided Jacobi on <= 2 bw columns held in LDS).  A sweep over all block
+// pairs that rotates nothing ends the iteration (flags).
+int svd_big_block_width(int kr) {
+  int bw = kQrLdsDoubles / (2 * std::max(kr, 1));
+  if (bw > 32) bw = 32;
+  return bw;
+}
+
+__global__ void svd_big_prepare_kernel(const double *r, int64_t rbs, int kr, int nc, double *acol, int64_t acs,
+                                       int *flags, int batch) {
+  const int64_t per = (int64_t)kr * nc, total = per * batch;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / per, rem = e - p * per;
+    const int64_t rr = rem / nc, c = rem - rr * nc;
+    acol[p * acs + c * kr + rr] = r[p * rbs + rem];
+  }
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < 2 * batch) flags[t] = 0;
+}
+
+hipError_t launch_svd_big_prepare(const double *r, int64_t rbs, int kr, int nc, double *acol, int64_t acs,
+                                  int *flags, int batch, hipStream_t s) {
+  const int64_t total = std::max<int64_t>((int64_t)kr * nc * batch, 2 * batch);
+  int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  svd_big_prepare_kernel<<<grid, 256, 0, s>>>(r, rbs, kr, nc, acol, acs, flags, batch);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void svd_big_round_kernel(double *acol, int64_t acs, int kr, int nc, int bw,
+                                                            int nb, int t, int *flags) {
+  extern __shared__ double A[];  // w columns of length kr
+  __shared__ int s_any, s_rot;
+  const int p = blockIdx.y;
+  if (flags[2 * p + 1]) return;
+  const int tid = threadIdx.x;
+  const int m = nb - 1;
+  const int pa = blockIdx.x, pb = nb - 1 - blockIdx.x;
+  const int ba = (pa == 0) ? 0 : 1 + (pa - 1 + t) % m;
+  const int bb = 1 + (pb - 1 + t) % m;
+  const int a0 = ba * bw, a1 = min(nc, a0 + bw);
+  const int b0 = bb * bw, b1 = min(nc, b0 + bw);
+  const int wa = max(0, a1 - a0), wb = max(0, b1 - b0);
+  const int w = wa + wb;
+  if (w < 2) return;
+  double *base = acol + p * acs;
+  for (int e = tid; e < w * kr; e += 256) {
+    const int c = e / kr, r = e - c * kr;
+    const int gc = (c < wa) ? a0 + c : b0 + (c - wa);
+    A[e] = base[(int64_t)gc * kr + r];
+  }
+  if (tid == 0) s_any = 0;
+  const int np = w + (w & 1);
+  const int npairs = np / 2;
+  int tpg = 64;
+  while (tpg > 1 && tpg * npairs > 256) tpg >>= 1;
+  const int grp = tid / tpg, gl = tid % tpg;
+  __syncthreads();
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    int myrot = 0;
+    for (int tt = 0; tt < np - 1; ++tt) {
+      if (grp < npairs) {
+        const int qa = grp, qb = np - 1 - grp;
+        int ip = (qa == 0) ? 0 : 1 + (qa - 1 + tt) % (np - 1);
+        int iq = 1 + (qb - 1 + tt) % (np - 1);
+        if (ip > iq) { int tmp = ip; ip = iq; iq = tmp; }
+        if (iq < w) {
+          double *ap = A + ip * kr, *aq = A + iq * kr;
+          double al = 0.0, be = 0.0, ga = 0.0;
+          for (int r = gl; r < kr; r += tpg) {
+            const double x = ap[r], y = aq[r];
+            al += x * x;
+            be += y * y;
+            ga += x * y;
+          }
+          for (int off = tpg / 2; off > 0; off >>= 1) {
+            al += __shfl_xor(al, off, tpg);
+            be += __shfl_xor(be, off, tpg);
+            ga += __shfl_xor(ga, off, tpg);
+          }
+          if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+            const double zeta = (be - al) / (2.0 * ga);
+            const double t2 = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double cs = 1.0 / sqrt(1.0 + t2 * t2), sn = cs * t2;
+            for (int r = gl; r < kr; r += tpg) {
+              const double x = ap[r], y = aq[r];
+              ap[r] = cs * x - sn * y;
+              aq[r] = sn * x + cs * y;
+            }
+            myrot = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (myrot) s_rot = 1;
+    __syncthreads();
+    if (s_rot == 0) break;
+    if (tid == 0) s_any = 1;
+    __syncthreads();
+  }
+  for (int e = tid; e < w * kr; e += 256) {
+    const int c = e / kr, r = e - c * kr;
+    const int gc = (c < wa) ? a0 + c : b0 + (c - wa);
+    base[(int64_t)gc * kr + r] = A[e];
+  }
+  if (tid == 0 && s_any) atomicOr(flags + 2 * p, 1);
+}
+
+hipError_t launch_svd_big_round(double *acol, int64_t acs, int kr, int nc, int bw, int nb, int t, int *flags,
+                                int batch, hipStream_t s) {
+  const size_t lds = (size_t)2 * bw * kr * sizeof(double);
+  hipFuncSetAttribute((const void *)svd_big_round_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  svd_big_round_kernel<<<dim3((unsigned)(nb / 2), (unsigned)batch), 256, lds, s>>>(acol, acs, kr, nc, bw, nb, t,
+                                                                                 flags);
+  return hipGetLastError();
+}
+
+__global__ void svd_big_sweep_end_kernel(int *flags, int batch) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < batch) {
+    if (flags[2 * p] == 0) flags[2 * p + 1] = 1;
+    flags[2 * p] = 0;
+  }
+}
+
+hipError_t launch_svd_big_sweep_end(int *flags, int batch, hipStream_t s) {
+  svd_big_sweep_end_kernel<<<(batch + 255) / 256, 256, 0, s>>>(flags, batch);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void svd_big_finish_kernel(SvdArgs a, const double *acol, int64_t acs) {
+  __shared__ double sig[kSvdBigMaxN];
+  __shared__ double sigs[kSvdBigMaxN];
+  __shared__ int perm[kSvdBigMaxN];
+  __shared__ int s_rho;
+  const int kr = a.kr, nc = a.nc;
+  const int tid = threadIdx.x;
+  const int p = blockIdx.x;
+  const double *A = acol + p * acs;
+  const double *R = a.r + p * a.rbs;
+  for (int c = tid; c < nc; c += 256) {
+    double s2 = 0.0;
+    for (int r = 0; r < kr; ++r) s2 += A[(int64_t)c * kr + r] * A[(int64_t)c * kr + r];
+    sig[c] = sqrt(s2);
+  }
+  __syncthreads();
+  for (int c = tid; c < nc; c += 256) {
+    int rk = 0;
+    const double sc = sig[c];
+    for (int j = 0; j < nc; ++j) rk += (sig[j] > sc) || (sig[j] == sc && j < c);
+    perm[rk] = c;
+    sigs[rk] = sc;
+  }
+  __syncthreads();
+  if (tid == 0) s_rho = choose_rank(sigs, kr, nc, a, p);
+  __syncthreads();
+  const int rho = s_rho;
+  double *U = a.u + p * a.ubs;
+  for (int e = tid; e < kr * a.ucap; e += 256) {
+    const int r = e / a.ucap, j = e - r * a.ucap;
+    double v = 0.0;
+    if (j < rho) {
+      const double sc = sigs[j];
+      v = (sc > 0.0) ? A[(int64_t)perm[j] * kr + r] / sc : 0.0;
+    }
+    U[e] = v;
+  }
+  double *S = a.svt + p * a.sbs;
+  for (int e = tid; e < a.ucap * nc; e += 256) {
+    const int j = e / nc, c = e - j * nc;
+    double v = 0.0;
+    if (j < rho) {
+      const double sc = sigs[j];
+      if (sc > 0.0) {
+        const double *u = A + (int64_t)perm[j] * kr;
+        for (int r = 0; r < kr; ++r) v += u[r] * R[(int64_t)r * nc + c];
+        v /= sc;
+      }
+    }
+    S[e] = v;
+  }
+}
+
+hipError_t launch_svd_big_finish(const SvdArgs &a, const double *acol, int64_t acs, hipStream_t s) {
+  if (a.nc > kSvdBigMaxN) return hipErrorInvalidValue;
+  svd_big_finish_kernel<<<a.batch, 256, 0, s>>>(a, acol, acs);
+  return hipGetLastError();
+}
+
 }  // namespace hatt

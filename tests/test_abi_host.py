@@ -136,12 +136,15 @@ def test_null_arguments_are_rejected():
 
 
 def test_unsupported_widths_are_reported():
-    # a sketch wider than the TSQR panel limit is refused with a message
-    n = [256, 256, 256]
+    # truncating a sketch wider than the largest SVD this build has is refused
+    n = [2048, 2048, 2048]
     x = _cpu_tt(n, [1, 40, 40, 1])
+    p = api.plan(x, x, 1100)            # no truncation: any width is fine
+    assert p["ell"] == [1, 1100, 1100, 1][:1] + [1100, 1100] + [1]
     with pytest.raises(HattError) as e:
-        api.plan(x, x, 300)
+        api.plan(x, x, 1100, tol=1e-6)
     assert e.value.status == -7
+    assert b"SVD" in _lib.lib().hatt_last_error()
 
 
 def test_perfmodel_matches_oracle_counts():

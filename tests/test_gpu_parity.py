@@ -205,3 +205,34 @@ def test_spectral_workload_full_size():
     got = res.train(0)
     assert tt.ranks(got) == tt.ranks(ref)
     assert tt.rel_err(got, ref) <= TOL
+
+
+def test_round_large_ranks_panel_qr_and_block_jacobi():
+    """PKP ranks up to 144: exercises the wide-matrix QR, the panelled
+    (block Gram-Schmidt twice + TSQR) QR for more than 128 columns and the
+    block Jacobi SVD for more than 139 columns."""
+    y, z = _pair(31, [8, 9, 9, 8], 12, 12)
+    a = tt.pkp(y, z)
+    assert max(tt.ranks(a)) == 144
+    for kw in ({"max_rank": 20}, {"tol": 1e-2}):
+        _say(f"tt_round pkp ranks {tt.ranks(a)} {kw}")
+        res = H.round(H.TT.from_cores(a), **kw)
+        torch.cuda.synchronize()
+        ref = rounding.tt_round(a, max_rank=kw.get("max_rank"), tol=kw.get("tol", 0.0))
+        got = res.train(0)
+        assert tt.ranks(got) == tt.ranks(ref)
+        assert tt.rel_err(got, ref) <= TOL
+
+
+def test_hatt_sketch_wider_than_one_panel():
+    """Sketch width 150 (> 128 QR columns, > 139 SVD columns), truncated by tol."""
+    y, z = _pair(32, [12, 13, 13, 12], 14, 14)
+    l = _ell(y, z, 150)
+    assert max(l) == 150
+    R = wk.gaussian_sketch(np.random.default_rng(3), tt.modes(y), l)
+    _say(f"hatt_recompress ell={l} tol=1e-6")
+    res = _gpu_hatt(y, z, 150, sketch=H.TT.from_cores(R), tol=1e-6)
+    ref = rounding.tt_round(ohatt.hatt(y, z, R), tol=1e-6)
+    got = res.train(0)
+    assert tt.ranks(got) == tt.ranks(ref)
+    assert tt.rel_err(got, ref) <= TOL
