@@ -141,6 +141,7 @@ struct SvdArgs {
   int64_t n_mode;
   int64_t *rank_out;     // device, element p * rank_bs
   int64_t rank_bs;
+  double rel_keep;       // > 0: keep sigma_j > rel_keep * sigma_1 instead (HaTT-2 split)
 };
 hipError_t launch_svd_trunc(const SvdArgs &a, hipStream_t s);
 

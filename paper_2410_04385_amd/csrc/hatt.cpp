@@ -541,6 +541,22 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
                                          std::to_string(l[c + 1]) + " sketched frame is not supported");
     qrws = std::max(qrws, qp[c].ws_doubles);
   }
+  // HaTT-2: per HPCRL bond, QR + SVD of W^{(k)} (r s x l), U (r s x l), W_R (l' n x l)
+  const bool v2 = (sp.o.variant == 2);
+  std::vector<QrOp> qw(d);
+  int64_t h2_q = 1, h2_r = 1, h2_wr = 1, h2_svd = 1;
+  if (v2) {
+    for (int c = d - 2; c >= 1; --c) {
+      const int64_t rs1 = r[c + 1] * s[c + 1], l1 = l[c + 1];
+      if (!qr_prepare(rs1, l1, &qw[c]))
+        return fail(HATT_EUNSUPPORTED, "HaTT-2: QR of a sketch matrix is not supported at this size");
+      qrws = std::max(qrws, qw[c].ws_doubles);
+      h2_q = std::max(h2_q, rs1 * l1);
+      h2_r = std::max(h2_r, l1 * l1);
+      h2_wr = std::max(h2_wr, l[c] * n[c] * l1);
+      h2_svd = std::max(h2_svd, svd_ws_doubles((int)l1, (int)l1));
+    }
+  }
   double *sk = nullptr;
   int64_t sks = 0;
   if (sp.sketch) {
@@ -556,7 +572,14 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
   double *Yb = ws.d((int64_t)P * ysz);
   double *Mb = ws.d((int64_t)P * msz);
   double *wqr = ws.d((int64_t)P * qrws);
-
+  double *h2Q = v2 ? ws.d((int64_t)P * h2_q) : nullptr;   // Q of W, then U = Q U_R
+  double *h2U = v2 ? ws.d((int64_t)P * h2_q) : nullptr;
+  double *h2R = v2 ? ws.d((int64_t)P * h2_r) : nullptr;   // R of W
+  double *h2Ur = v2 ? ws.d((int64_t)P * h2_r) : nullptr;  // U of R (zero beyond the kept terms)
+  double *h2S = v2 ? ws.d((int64_t)P * h2_r) : nullptr;   // S V^T rows
+  double *h2WR = v2 ? ws.d((int64_t)P * h2_wr) : nullptr;
+  double *h2big = v2 ? ws.d((int64_t)P * h2_svd) : nullptr;
+  double *h2misc = v2 ? ws.d((int64_t)P * 3) : nullptr;    // [delta2 | SVD flags | kept terms] x P
   if (d == 1) {
     LAUNCH(launch_fill_i64(sp.orank, (int64_t)P * 2, 1, st));
     PkpArgs pa{xd, yd, sp.out, 1, 1, 1, 1, n[0], xs, ys, sp.ostride, P};
@@ -588,6 +611,46 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     LAUNCH(launch_hpcrl_last(la, st));
   }
   for (int c = d - 2; c >= 1; --c) {
+    const int64_t rs1 = r[c + 1] * s[c + 1], l1 = l[c + 1];
+    const double *ucol = W + woff[c + 1];  // U operand: W itself (HaTT-1) or U_R (HaTT-2)
+    int64_t ucb = wtot;
+    if (v2) {
+      // eq. HPCRL--2: W = Q R, R = U_R S V^T, keep sigma > ep sigma_1
+      hatt_status s2 = qr_exec(run, qw[c], CMat{W + woff[c + 1], l1, 1, wtot}, Mat{h2Q, l1, 1, h2_q},
+                               Mat{h2R, l1, 1, h2_r}, h2_r, wqr, qrws, P, gc, st);
+      if (s2 != HATT_OK) return s2;
+      SvdArgs sa{};
+      sa.r = h2R;
+      sa.rbs = h2_r;
+      sa.kr = (int)l1;
+      sa.nc = (int)l1;
+      sa.ucap = (int)l1;
+      sa.u = h2Ur;
+      sa.ubs = h2_r;
+      sa.svt = h2S;
+      sa.sbs = h2_r;
+      sa.batch = P;
+      sa.delta2 = h2misc;
+      sa.first_bond = 0;
+      sa.tol2_over_dm1 = 0.0;
+      sa.cap = 0;
+      sa.prev_rank = nullptr;
+      sa.n_mode = 1;
+      sa.rank_out = (int64_t *)(h2misc + 2 * P);
+      sa.rank_bs = 1;
+      sa.rel_keep = std::max(sp.o.ep, 1e-300);
+      s2 = svd_exec(run, sa, h2big, h2_svd, (int *)(h2misc + P), st);
+      if (s2 != HATT_OK) return s2;
+      s2 = gemm(run, gc, CMat{h2Q, l1, 1, h2_q}, CMat{h2Ur, l1, 1, h2_r}, Mat{h2U, l1, 1, h2_q}, rs1, l1, l1,
+                1.0, 0.0, P, st, true);
+      if (s2 != HATT_OK) return s2;
+      // W_R(g', (i, gamma)) = R_k(i) (sigma V)(:, gamma): V(R_k) (S V^T)^T
+      s2 = gemm(run, gc, CMat{sk + skoff[c], l1, 1, sks}, CMat{h2S, 1, l1, h2_r}, Mat{h2WR, l1, 1, h2_wr},
+                l[c] * n[c], l1, l1, 1.0, 0.0, P, st, true);
+      if (s2 != HATT_OK) return s2;
+      ucol = h2U;
+      ucb = h2_q;
+    }
     SandwichArgs a{};
     a.yl = xd + sp.X.off[c];
     a.ylb = xs;
@@ -599,28 +662,29 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     a.zri = s[c + 1];
     a.zrr = 1;
     a.zrc = n[c] * s[c + 1];
-    a.c = W + woff[c + 1];
-    a.cb = wtot;
+    a.c = ucol;
+    a.cb = ucb;
     a.cg = 1;
-    a.ca = s[c + 1] * l[c + 1];
-    a.cbb = l[c + 1];
+    a.ca = s[c + 1] * l1;
+    a.cbb = l1;
     a.o = WL;
     a.ob = wlsz;
-    a.oi = l[c + 1];
+    a.oi = l1;
     a.og = 1;
-    a.oa = s[c] * n[c] * l[c + 1];
-    a.obb = n[c] * l[c + 1];
+    a.oa = s[c] * n[c] * l1;
+    a.obb = n[c] * l1;
     a.RA = (int)r[c];
     a.RI = (int)r[c + 1];
     a.SI = (int)s[c + 1];
     a.SO = (int)s[c];
     a.n = n[c];
-    a.G = l[c + 1];
+    a.G = l1;
     a.batch = P;
     LAUNCH(launch_sandwich(a, st));
-    const int64_t K = n[c] * l[c + 1];
-    hatt_status stt = gemm(run, gc, CMat{WL, K, 1, wlsz}, CMat{sk + skoff[c], 1, K, sks},
-                           Mat{W + woff[c], l[c], 1, wtot}, r[c] * s[c], l[c], K, 1.0, 0.0, P, st, true);
+    const int64_t K = n[c] * l1;
+    const CMat wr = v2 ? CMat{h2WR, 1, K, h2_wr} : CMat{sk + skoff[c], 1, K, sks};
+    hatt_status stt = gemm(run, gc, CMat{WL, K, 1, wlsz}, wr, Mat{W + woff[c], l[c], 1, wtot}, r[c] * s[c], l[c],
+                           K, 1.0, 0.0, P, st, true);
     if (stt != HATT_OK) return stt;
   }
   // ---- sweep (Alg. 4)
@@ -768,7 +832,8 @@ static hatt_status hatt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_o
   if (sp->X.d != sp->Y.d) return fail(HATT_ESHAPE, "x and y have different orders");
   if (sp->X.batch != sp->Y.batch) return fail(HATT_ESHAPE, "x and y have different batch counts");
   if (sp->X.n != sp->Y.n) return fail(HATT_ESHAPE, "x and y have different mode sizes");
-  if (o->variant != 1) return fail(HATT_EUNSUPPORTED, "only variant 1 (HaTT-1) is built");
+  if (o->variant != 1 && o->variant != 2) return fail(HATT_EINVAL, "variant must be 1 or 2");
+  if (o->variant == 2 && !(o->ep >= 0.0 && o->ep < 1.0)) return fail(HATT_EINVAL, "ep must be in [0, 1)");
   if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(HATT_EINVAL, "tol must be finite and >= 0");
   const int d = sp->X.d;
   std::vector<int64_t> req(d + 1, 1);

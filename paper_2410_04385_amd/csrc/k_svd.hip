@@ -32,6 +32,16 @@ __device__ __forceinline__ int rr_partner(int c, int t, int np) {
 
 // Rank rule shared by both kernels (thread-serial, n <= 139).
 __device__ int choose_rank(const double *sig_sorted, int kr, int nc, const SvdArgs &a, int p) {
+  if (a.rel_keep > 0.0) {
+    // eq. HPCRL--2 split: terms with sigma_j > ep ||W||_2, at least one
+    int rho = 0;
+    const int kmax = min(kr, nc);
+    for (int j = 0; j < kmax; ++j) rho += (sig_sorted[j] > a.rel_keep * sig_sorted[0]);
+    if (rho > a.ucap) rho = a.ucap;
+    if (rho < 1) rho = 1;
+    a.rank_out[p * a.rank_bs] = rho;
+    return rho;
+  }
   double tot2 = 0.0;
   for (int j = 0; j < nc; ++j) tot2 += sig_sorted[j] * sig_sorted[j];
   if (a.first_bond) a.delta2[p] = a.tol2_over_dm1 * tot2;

@@ -236,3 +236,19 @@ def test_hatt_sketch_wider_than_one_panel():
     got = res.train(0)
     assert tt.ranks(got) == tt.ranks(ref)
     assert tt.rel_err(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("ep", [1e-14, 1e-3, 0.3])
+def test_hatt2_matches_oracle(ep):
+    """HaTT-2 (truncated SVD split of W^{(k)}, eq. HPCRL--2) against the oracle."""
+    y, z = _pair(41, [5, 6, 7, 6, 5], 3, 3)
+    l = _ell(y, z, 8)
+    R = wk.gaussian_sketch(np.random.default_rng(4), tt.modes(y), l)
+    w, used = ohatt.hpcrl(y, z, R, variant=2, ep=ep, return_split_ranks=True)
+    for b in range(2, len(y)):   # keep ep away from a singular value of W^{(b)}
+        sv = np.linalg.svd(ohatt.hpcrl(y, z, R, variant=1)[b], compute_uv=False)
+        assert np.min(np.abs(sv / sv[0] - ep)) > 1e-6
+    _say(f"hatt_recompress variant 2 ep={ep} terms={used}")
+    res = _gpu_hatt(y, z, 8, sketch=H.TT.from_cores(R), variant=2, ep=ep)
+    ref = ohatt.hatt(y, z, R, variant=2, ep=ep)
+    assert tt.rel_err(res.train(0), ref) <= TOL
