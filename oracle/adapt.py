@@ -1,0 +1,73 @@
+"""Tolerance-driven HaTT: grow the sketch widths until the truncation leaves
+slack (oracle side).
+
+The paper fixes target ranks and leaves tolerance control to future work
+(Sec. 6); it notes that when the smallest singular value of a sketch is not
+small enough, l should be increased (Sec. 5.1.1).  The rule implemented here
+(the same on both sides):
+
+* start: l_k = max(r_k, s_k) + p (p = oversampling, default 8), clamped;
+* run HaTT with the sketch keyed by seed + attempt, then TT-Rounding at tol;
+* accept when every bond keeps rho_k <= l_k - p, or l_k already equals its
+  largest feasible value (then the sketch captured the bond exactly);
+* otherwise on each failing bond set l_k = min(cap_k, ceil(1.5 l_k) + p) and
+  retry; give up after ``max_attempts``.
+
+For a batch of pairs the widths are common to all pairs and a bond fails if
+it fails for any pair.
+"""
+
+from __future__ import annotations
+
+import math
+from typing import List, Sequence
+
+import numpy as np
+
+from . import philox, plan, rounding, tt
+from .hatt import hatt
+
+BIG = 1 << 40
+
+
+def initial_widths(n, rx, ry, p: int = 8) -> List[int]:
+    d = len(n)
+    req = [1] + [max(int(rx[k]), int(ry[k])) + p for k in range(1, d)] + [1]
+    return plan.clamp_ell(n, rx, ry, req)
+
+
+def grow(ell: Sequence[int], fail: Sequence[int], cap: Sequence[int], p: int = 8) -> List[int]:
+    out = list(ell)
+    for k in fail:
+        out[k] = min(int(cap[k]), int(math.ceil(1.5 * ell[k])) + p)
+    return out
+
+
+def failing_bonds(kept: Sequence[Sequence[int]], ell: Sequence[int], cap: Sequence[int], p: int = 8) -> List[int]:
+    d = len(ell) - 1
+    bad = set()
+    for rho in kept:
+        for k in range(1, d):
+            if rho[k] > ell[k] - p and ell[k] < cap[k]:
+                bad.add(k)
+    return sorted(bad)
+
+
+def hatt_adaptive(pairs, tol: float, seed: int, p: int = 8, max_attempts: int = 8, variant: int = 1,
+                  ep: float = 0.0):
+    """``pairs``: list of (y, z) of one shape.  Returns (outputs, widths used,
+    attempts, converged)."""
+    y0, z0 = pairs[0]
+    n, rx, ry = tt.modes(y0), tt.ranks(y0), tt.ranks(z0)
+    cap = plan.clamp_ell(n, rx, ry, BIG)
+    ell = initial_widths(n, rx, ry, p)
+    outs = None
+    for attempt in range(max_attempts):
+        l = plan.clamp_ell(n, rx, ry, ell)
+        R = philox.sketch(seed + attempt, n, l)
+        outs = [rounding.tt_round(hatt(y, z, R, variant, ep), tol=tol) for (y, z) in pairs]
+        bad = failing_bonds([tt.ranks(o) for o in outs], l, cap, p)
+        if not bad:
+            return outs, l, attempt + 1, True
+        ell = grow(l, bad, cap, p)
+    return outs, l, max_attempts, False
