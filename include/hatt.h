@@ -110,6 +110,42 @@ HATT_API hatt_status hatt_recompress(const hatt_tt *x, const hatt_tt *y, const h
                             int64_t *out_rank, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Tolerance-driven recompression.  The paper fixes target ranks and leaves
+ * tolerance control open (Sec. 6); it suggests enlarging l when a sketch's
+ * smallest singular value is not small enough (Sec. 5.1.1).  Rule:
+ *   start l_k = max(r_k, s_k) + p (clamped as in hatt_plan); run HaTT with
+ *   the Philox sketch keyed by seed + attempt, then TT-Rounding at tol;
+ *   accept when every bond keeps rho_k <= l_k - p or l_k is at its largest
+ *   feasible value; else on each failing bond (failing for any train of the
+ *   batch) l_k = min(cap_k, ceil(1.5 l_k) + p) and retry.
+ * hatt_adaptive_plan: cap_out (host [d+1]) = largest feasible widths,
+ * ws_bytes = workspace for any attempt, out_elems = elements of one output
+ * train at the cap widths (the per-train slot size).
+ * hatt_recompress_adaptive: synchronises `stream` once per attempt (the
+ * decision needs the kept ranks on the host).  The result of the last
+ * attempt is written per train at the widths returned in ell_out (host
+ * [d+1]; packed inside each train's slot of out_stride elements, 0 = the
+ * planned slot size), kept ranks in out_rank (device [batch][d+1]), the
+ * number of attempts in *attempts_out.  Returns HATT_ENOTCONV (with the last
+ * attempt's result in place) if max_attempts did not suffice.
+ */
+typedef struct {
+  double tol;             /* relative Frobenius tolerance, > 0 */
+  uint64_t seed;          /* attempt a uses the sketch keyed by seed + a */
+  int32_t oversample;     /* p; <= 0 means 8 */
+  int32_t max_attempts;   /* <= 0 means 8 */
+  int32_t variant;        /* 1 or 2 as in hatt_opts */
+  double ep;              /* HaTT-2 threshold */
+} hatt_adapt_opts;
+
+HATT_API hatt_status hatt_adaptive_plan(const hatt_tt *x, const hatt_tt *y, const hatt_adapt_opts *opts,
+                                        int64_t *cap_out, size_t *ws_bytes, int64_t *out_elems);
+HATT_API hatt_status hatt_recompress_adaptive(const hatt_tt *x, const hatt_tt *y, const hatt_adapt_opts *opts,
+                                              double *out, int64_t out_stride, int64_t *out_rank,
+                                              int64_t *ell_out, int32_t *attempts_out, void *ws,
+                                              size_t ws_bytes, void *stream);
+
+/*
  * tt_hadamard_explicit -- the PKP cores of x (.) y (Sec. 2.2):
  * A_k(a s + b, i, a' s' + b') = X_k(a, i, a') Y_k(b, i, b'), ranks r_k s_k.
  * out: device, batch trains with ranks r_k s_k, stride out_stride

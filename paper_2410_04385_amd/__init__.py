@@ -16,6 +16,7 @@ from .api import (  # noqa: F401
     profile_start,
     profile_stop,
     recompress,
+    recompress_adaptive,
     round,
     round_plan,
     sketch_fill,

@@ -17,7 +17,7 @@ STATUS_NAMES = {
 }
 
 EXPORTED = [
-    "hatt_plan", "hatt_recompress", "tt_hadamard_explicit", "tt_round_plan", "tt_round",
+    "hatt_plan", "hatt_recompress", "hatt_adaptive_plan", "hatt_recompress_adaptive", "tt_hadamard_explicit", "tt_round_plan", "tt_round",
     "tt_norm_plan", "tt_norm", "hatt_sketch_fill", "hatt_profile_start", "hatt_profile_stop",
     "hatt_profile_class_name", "hatt_last_error", "hatt_version",
 ]
@@ -49,6 +49,17 @@ class HattOpts(ctypes.Structure):
     ]
 
 
+class HattAdaptOpts(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("oversample", ctypes.c_int32),
+        ("max_attempts", ctypes.c_int32),
+        ("variant", ctypes.c_int32),
+        ("ep", ctypes.c_double),
+    ]
+
+
 class HattError(RuntimeError):
     def __init__(self, fn: str, status: int, msg: str):
         super().__init__(f"{fn} failed with {STATUS_NAMES.get(status, status)}: {msg}")
@@ -71,6 +82,10 @@ def lib() -> ctypes.CDLL:
     szp = ctypes.POINTER(ctypes.c_size_t)
     L.hatt_plan.argtypes = [ttp, ttp, optp, i64p, szp, i64p]
     L.hatt_recompress.argtypes = [ttp, ttp, ttp, optp, vp, ctypes.c_int64, vp, vp, ctypes.c_size_t, vp]
+    aop = ctypes.POINTER(HattAdaptOpts)
+    L.hatt_adaptive_plan.argtypes = [ttp, ttp, aop, i64p, szp, i64p]
+    L.hatt_recompress_adaptive.argtypes = [ttp, ttp, aop, vp, ctypes.c_int64, vp, i64p,
+                                           ctypes.POINTER(ctypes.c_int32), vp, ctypes.c_size_t, vp]
     L.tt_hadamard_explicit.argtypes = [ttp, ttp, vp, ctypes.c_int64, vp]
     L.tt_round_plan.argtypes = [ttp, i64p, szp, i64p]
     L.tt_round.argtypes = [ttp, ctypes.c_int64, ctypes.c_double, vp, ctypes.c_int64, vp, vp, ctypes.c_size_t, vp]

@@ -11,7 +11,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import HattOpts, HattTT, check, i64_array, lib
+from ._lib import HattAdaptOpts, HattOpts, HattTT, check, i64_array, lib
 
 
 def _offsets(n: Sequence[int], r: Sequence[int]):
@@ -153,6 +153,37 @@ def recompress(x: TT, y: TT, ell, *, max_rank: int = 0, tol: float = 0.0, seed: 
                                workspace.numel(), _stream_ptr(stream))
     check("hatt_recompress", st)
     return Result(out, ranks)
+
+
+def recompress_adaptive(x: TT, y: TT, tol: float, *, seed: int = 0, oversample: int = 8,
+                        max_attempts: int = 8, variant: int = 1, ep: float = 0.0,
+                        workspace: Optional[torch.Tensor] = None, stream=None):
+    """Tolerance-driven HaTT: grows the sketch widths until the truncation
+    at ``tol`` leaves slack on every bond.  Returns (Result, widths used,
+    attempts)."""
+    xv, kx = x.view()
+    yv, ky = y.view()
+    o = HattAdaptOpts(float(tol), int(seed) & 0xFFFFFFFFFFFFFFFF, int(oversample), int(max_attempts),
+                      int(variant), float(ep))
+    cap = (ctypes.c_int64 * (x.d + 1))()
+    ws = ctypes.c_size_t(0)
+    oe = ctypes.c_int64(0)
+    check("hatt_adaptive_plan", lib().hatt_adaptive_plan(ctypes.byref(xv), ctypes.byref(yv), ctypes.byref(o),
+                                                         cap, ctypes.byref(ws), ctypes.byref(oe)))
+    dev = x.data.device
+    slot = int(oe.value)
+    data = torch.zeros(x.batch * slot, dtype=torch.float64, device=dev)
+    ranks = torch.empty((x.batch, x.d + 1), dtype=torch.int64, device=dev)
+    if workspace is None or workspace.numel() < ws.value:
+        workspace = torch.empty(max(ws.value, 1), dtype=torch.uint8, device=dev)
+    ell = (ctypes.c_int64 * (x.d + 1))()
+    att = ctypes.c_int32(0)
+    check("hatt_recompress_adaptive", lib().hatt_recompress_adaptive(
+        ctypes.byref(xv), ctypes.byref(yv), ctypes.byref(o), ctypes.c_void_p(data.data_ptr()), slot,
+        ctypes.c_void_p(ranks.data_ptr()), ell, ctypes.byref(att), ctypes.c_void_p(workspace.data_ptr()),
+        workspace.numel(), _stream_ptr(stream)))
+    out = TT(data, x.n, list(ell), x.batch, stride=slot)
+    return Result(out, ranks), list(ell), int(att.value)
 
 
 def hadamard_explicit(x: TT, y: TT, out: Optional[TT] = None, stream=None) -> TT:

@@ -908,6 +908,112 @@ hatt_status hatt_recompress(const hatt_tt *x, const hatt_tt *y, const hatt_tt *s
   return st;
 }
 
+// ---------------------------------------------------------------------------
+static hatt_status adapt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_adapt_opts *ao, HattSpec *sp,
+                                 std::vector<int64_t> *cap, std::vector<int64_t> *ell0, int *p, int *maxa,
+                                 bool need_data) {
+  if (ao == nullptr) return fail(HATT_EINVAL, "adapt opts is NULL");
+  if (!(ao->tol > 0.0) || !std::isfinite(ao->tol)) return fail(HATT_EINVAL, "tol must be finite and > 0");
+  hatt_opts o{};
+  o.variant = ao->variant ? ao->variant : 1;
+  o.ep = ao->ep;
+  o.ell = 1;
+  o.tol = ao->tol;
+  o.seed = ao->seed;
+  hatt_status st = hatt_prepare(x, y, &o, sp, need_data);
+  if (st != HATT_OK) return st;
+  const int d = sp->X.d;
+  *p = ao->oversample > 0 ? ao->oversample : 8;
+  *maxa = ao->max_attempts > 0 ? ao->max_attempts : 8;
+  std::vector<int64_t> big(d + 1, (int64_t)1 << 40), req(d + 1, 1);
+  *cap = clamp_ell(sp->X.n, sp->X.r, sp->Y.r, big);
+  for (int k = 1; k < d; ++k) req[k] = std::max(sp->X.r[k], sp->Y.r[k]) + *p;
+  *ell0 = clamp_ell(sp->X.n, sp->X.r, sp->Y.r, req);
+  return HATT_OK;
+}
+
+hatt_status hatt_adaptive_plan(const hatt_tt *x, const hatt_tt *y, const hatt_adapt_opts *opts, int64_t *cap_out,
+                               size_t *ws_bytes, int64_t *out_elems) {
+  HattSpec sp{};
+  std::vector<int64_t> cap, ell0;
+  int p, maxa;
+  hatt_status st = adapt_prepare(x, y, opts, &sp, &cap, &ell0, &p, &maxa, false);
+  if (st != HATT_OK) return st;
+  sp.ell = cap;
+  sp.sketch = nullptr;
+  Ws ws(nullptr);
+  st = hatt_run(false, sp, ws, nullptr);
+  if (st != HATT_OK) return st;
+  if (cap_out)
+    for (int k = 0; k <= sp.X.d; ++k) cap_out[k] = cap[k];
+  // widths below the caps need no more than the caps' buffers up to the
+  // integer effects of the QR tree shapes; keep a margin and re-check per attempt
+  if (ws_bytes) *ws_bytes = ws.off + ws.off / 8 + ((size_t)4 << 20);
+  if (out_elems) {
+    std::vector<int64_t> off;
+    int64_t tot;
+    make_offsets(sp.X.n, cap, &off, &tot);
+    *out_elems = tot;
+  }
+  g_err.clear();
+  return HATT_OK;
+}
+
+hatt_status hatt_recompress_adaptive(const hatt_tt *x, const hatt_tt *y, const hatt_adapt_opts *opts, double *out,
+                                     int64_t out_stride, int64_t *out_rank, int64_t *ell_out, int32_t *attempts_out,
+                                     void *ws, size_t ws_bytes, void *stream) {
+  HattSpec sp{};
+  std::vector<int64_t> cap, ell;
+  int p, maxa;
+  hatt_status st = adapt_prepare(x, y, opts, &sp, &cap, &ell, &p, &maxa, true);
+  if (st != HATT_OK) return st;
+  if (out == nullptr || out_rank == nullptr || ell_out == nullptr || attempts_out == nullptr)
+    return fail(HATT_EINVAL, "NULL output argument");
+  const int d = sp.X.d, P = sp.X.batch;
+  std::vector<int64_t> coff;
+  int64_t ctot;
+  make_offsets(sp.X.n, cap, &coff, &ctot);
+  if (out_stride != 0 && out_stride < ctot) return fail(HATT_EINVAL, "out_stride smaller than the planned slot");
+  sp.out = out;
+  sp.ostride = out_stride ? out_stride : ctot;
+  sp.orank = out_rank;
+  sp.sketch = nullptr;
+  hipStream_t strm = (hipStream_t)stream;
+  std::vector<int64_t> host_rank((size_t)P * (d + 1));
+  for (int attempt = 0; attempt < maxa; ++attempt) {
+    sp.ell = clamp_ell(sp.X.n, sp.X.r, sp.Y.r, ell);
+    sp.o.seed = opts->seed + (uint64_t)attempt;
+    Ws meas(nullptr);
+    st = hatt_run(false, sp, meas, nullptr);
+    if (st != HATT_OK) return st;
+    if (ws == nullptr || ws_bytes < meas.off)
+      return fail(HATT_EWORKSPACE, "workspace too small: need " + std::to_string(meas.off) + " bytes");
+    Ws w(ws);
+    st = hatt_run(true, sp, w, strm);
+    if (st != HATT_OK) return st;
+    if (hipMemcpyAsync(host_rank.data(), out_rank, host_rank.size() * sizeof(int64_t), hipMemcpyDeviceToHost,
+                       strm) != hipSuccess ||
+        hipStreamSynchronize(strm) != hipSuccess)
+      return fail(HATT_EDEVICE, "reading the kept ranks failed");
+    std::vector<int> bad;
+    for (int k = 1; k < d; ++k) {
+      bool b = false;
+      for (int q = 0; q < P; ++q)
+        if (host_rank[(size_t)q * (d + 1) + k] > sp.ell[k] - p && sp.ell[k] < cap[k]) b = true;
+      if (b) bad.push_back(k);
+    }
+    for (int k = 0; k <= d; ++k) ell_out[k] = sp.ell[k];
+    *attempts_out = attempt + 1;
+    if (bad.empty()) {
+      g_err.clear();
+      return HATT_OK;
+    }
+    ell = sp.ell;
+    for (int k : bad) ell[k] = std::min<int64_t>(cap[k], (int64_t)std::ceil(1.5 * (double)sp.ell[k]) + p);
+  }
+  return fail(HATT_ENOTCONV, "sketch widths did not converge within max_attempts");
+}
+
 hatt_status tt_hadamard_explicit(const hatt_tt *x, const hatt_tt *y, double *out, int64_t out_stride,
                                  void *stream) {
   Shape X, Y;

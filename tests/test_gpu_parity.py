@@ -252,3 +252,41 @@ def test_hatt2_matches_oracle(ep):
     res = _gpu_hatt(y, z, 8, sketch=H.TT.from_cores(R), variant=2, ep=ep)
     ref = ohatt.hatt(y, z, R, variant=2, ep=ep)
     assert tt.rel_err(res.train(0), ref) <= TOL
+
+
+def test_adaptive_matches_oracle_small_trig():
+    """Tolerance-driven widths: same growth decisions and result as the oracle."""
+    from oracle import adapt
+    u = wk.trig_u(3, n=48, terms=12, nfreq=6)
+    seed, tol = 17, 1e-8
+    _say("hatt_recompress_adaptive small trig u*u tol=1e-8")
+    res, ell, att = H.recompress_adaptive(H.TT.from_cores(u), H.TT.from_cores(u), tol, seed=seed)
+    torch.cuda.synchronize()
+    outs, l_ref, att_ref, ok = adapt.hatt_adaptive([(u, u)], tol=tol, seed=seed)
+    assert ok and ell == l_ref and att == att_ref
+    got = res.train(0)
+    assert tt.ranks(got) == tt.ranks(outs[0]) == [1, 25, 25, 1]
+    assert tt.rel_err(got, outs[0]) <= TOL
+
+
+def test_trig_workload_products_at_tolerance():
+    """u on the 256^3 grid (40 separable sin/cos terms): u*u and (u*u)*u at
+    tol 1e-8 reach the closed-form ranks 81 and 121 and the pointwise values."""
+    cfg = wk.WORKLOADS["trig"]
+    u = wk.trig_u(11, n=cfg["n"], terms=2 * cfg["nfreq"], nfreq=cfg["nfreq"])
+    fu = tt.full(u)
+    U = H.TT.from_cores(u)
+    _say("hatt_recompress_adaptive trig 256^3 u*u tol=1e-8")
+    r2, ell2, att2 = H.recompress_adaptive(U, U, cfg["tol"], seed=1)
+    torch.cuda.synchronize()
+    u2 = r2.train(0)
+    assert tt.ranks(u2) == [1, 81, 81, 1]
+    e2 = np.linalg.norm(tt.full(u2) - fu ** 2) / np.linalg.norm(fu ** 2)
+    assert e2 <= cfg["tol"]
+    _say(f"hatt_recompress_adaptive trig (u*u)*u tol=1e-8 (u*u widths {ell2}, {att2} attempts)")
+    r3, ell3, att3 = H.recompress_adaptive(H.TT.from_cores(u2), U, cfg["tol"], seed=2)
+    torch.cuda.synchronize()
+    u3 = r3.train(0)
+    assert tt.ranks(u3) == [1, 121, 121, 1]
+    e3 = np.linalg.norm(tt.full(u3) - fu ** 3) / np.linalg.norm(fu ** 3)
+    assert e3 <= 3 * cfg["tol"]
