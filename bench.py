@@ -28,10 +28,11 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=64, help="pairs recompressed per step")
+    ap.add_argument("--batch", type=int, default=128, help="pairs recompressed per step")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-explicit", action="store_true")
+    ap.add_argument("--eager", action="store_true", help="launch kernels directly instead of replaying a HIP graph")
     return ap.parse_args()
 
 
@@ -90,7 +91,24 @@ def main() -> int:
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    gpu_s, wall_s = _time_steps(step, args.steps, torch)
+    timed = step
+    mode = "eager"
+    if not args.eager:
+        # the step allocates nothing and never synchronises: capture it once
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            step()
+        torch.cuda.current_stream().wait_stream(s)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        timed = graph.replay
+        mode = "hip_graph"
+    gpu_s, wall_s = _time_steps(timed, args.steps, torch)
     ms_per_step = 1000.0 * wall_s / args.steps
     value = B * args.steps / wall_s
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step (events {1000 * gpu_s / args.steps:.3f})",
@@ -195,7 +213,7 @@ def main() -> int:
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"spectral d={d} n={n} r_x=r_y={r} sketch={ell} max_rank={cap}",
-                   "pairs_per_step": B, "variant": "HaTT-1", "seed": seed},
+                   "pairs_per_step": B, "variant": "HaTT-1", "seed": seed, "launch": mode},
         "roofline": roof,
         "cpu_baseline": cpu,
         "step_tflops_algorithmic": step_tflops,

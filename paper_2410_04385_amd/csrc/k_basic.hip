@@ -238,15 +238,16 @@ hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s) {
   gc = std::min<int64_t>(gc, a.G);
   const size_t lds = (size_t)(fixed + gc * perg) * sizeof(double);
   dim3 grid((unsigned)a.n, (unsigned)((a.G + gc - 1) / gc), (unsigned)a.batch);
-  if (a.og == 1) {
-    hipFuncSetAttribute((const void *)sandwich_kernel<true>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    sandwich_kernel<true><<<grid, 256, lds, s>>>(a, (int)gc);
-  } else {
-    hipFuncSetAttribute((const void *)sandwich_kernel<false>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    sandwich_kernel<false><<<grid, 256, lds, s>>>(a, (int)gc);
+  static bool attr_done = false;  // set once: the maximum a launch may ask for
+  if (!attr_done) {
+    hipFuncSetAttribute((const void *)sandwich_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)(budget * sizeof(double)));
+    hipFuncSetAttribute((const void *)sandwich_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)(budget * sizeof(double)));
+    attr_done = true;
   }
+  if (a.og == 1) sandwich_kernel<true><<<grid, 256, lds, s>>>(a, (int)gc);
+  else sandwich_kernel<false><<<grid, 256, lds, s>>>(a, (int)gc);
   return hipGetLastError();
 }
 

@@ -1,9 +1,9 @@
 // Batched, strided FP64 GEMM on the CDNA matrix cores
 // (v_mfma_f64_16x16x4_f64), with an optional deterministic split-K.
 //
-// Tile: 64 x 64 outputs per 256-thread workgroup, K staged through LDS in
-// slabs of 16.  Each of the 4 waves owns a 32 x 32 quadrant = 2 x 2 MFMA
-// blocks of 16 x 16; one MFMA consumes a 16 x 4 slice of A and a 4 x 16 slice
+// Tile: 64 x 64 (or 64 x 32, 32 x 64, 32 x 32 for thin operands) outputs per
+// 256-thread workgroup, K staged through LDS in slabs of 16.  Each of the 4
+// waves owns a quadrant made of 16 x 16 MFMA blocks; one MFMA consumes a 16 x 4 slice of A and a 4 x 16 slice
 // of B, one double per lane each (lane l holds A(l%16, l/16) and
 // B(l/16, l%16)); its 16 x 16 result sits 4 doubles per lane, lane l holding
 // rows l/16 + 4v, v = 0..3, of column l%16 (rows interleaved by 4, checked
@@ -16,13 +16,19 @@ namespace hatt {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 16, LDA_S = BM + 1, LDB_S = BN + 1;
+constexpr int BK = 16;
 
+// BM x BN output tile, 4 waves in a 2 x 2 grid, each wave (BM/2) x (BN/2) as
+// (BM/32) x (BN/32) MFMA blocks of 16 x 16.
+template <int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
+  constexpr int LDA_S = BM + 1, LDB_S = BN + 1;
+  constexpr int MI = BM / 32, NJ = BN / 32;
+  constexpr int A_PER = BM * BK / 256, B_PER = BN * BK / 256;
   __shared__ double As[BK * LDA_S];  // As[k * LDA_S + m]
   __shared__ double Bs[BK * LDB_S];  // Bs[k * LDB_S + n]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
   const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
   const int ks = g.ksplit;
   const int p = blockIdx.z / ks, kc = blockIdx.z - (blockIdx.z / ks) * ks;
@@ -36,30 +42,30 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
   const bool a_kfast = (g.A.cs == 1);
   const bool b_nfast = (g.B.cs == 1) || (g.B.rs != 1);
 
-  d4_t acc[2][2];
+  d4_t acc[MI][NJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NJ; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
 
   for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < A_PER; ++t) {
       const int e = tid + 256 * t;
       int mm, kk;
-      if (a_kfast) { kk = e & 15; mm = e >> 4; }
-      else { mm = e & 63; kk = e >> 6; }
+      if (a_kfast) { kk = e % BK; mm = e / BK; }
+      else { mm = e % BM; kk = e / BM; }
       const int64_t gm = m0 + mm, gk = k0 + kk;
       double v = 0.0;
       if (gm < g.M && gk < kend) v = Ab[gm * g.A.rs + gk * g.A.cs];
       As[kk * LDA_S + mm] = v;
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < B_PER; ++t) {
       const int e = tid + 256 * t;
       int nn, kk;
-      if (b_nfast) { nn = e & 63; kk = e >> 6; }
-      else { kk = e & 15; nn = e >> 4; }
+      if (b_nfast) { nn = e % BN; kk = e / BN; }
+      else { kk = e % BK; nn = e / BK; }
       const int64_t gn = n0 + nn, gk = k0 + kk;
       double v = 0.0;
       if (gn < g.N && gk < kend) v = Bb[gk * g.B.rs + gn * g.B.cs];
@@ -69,15 +75,15 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4), c16 = lane & 15;
-      double av[2], bv[2];
+      double av[MI], bv[NJ];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) av[i] = As[kr * LDA_S + wm + i * 16 + c16];
+      for (int i = 0; i < MI; ++i) av[i] = As[kr * LDA_S + wm + i * 16 + c16];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bv[j] = Bs[kr * LDB_S + wn + j * 16 + c16];
+      for (int j = 0; j < NJ; ++j) bv[j] = Bs[kr * LDB_S + wn + j * 16 + c16];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
@@ -87,9 +93,9 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
   if (ks == 1) {
     double *Cb = g.C.ptr + p * g.C.bs;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < NJ; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t gm = m0 + wm + i * 16 + rq + 4 * v, gn = n0 + wn + j * 16 + cq;
@@ -103,9 +109,9 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
   } else {
     double *Pb = g.part + ((int64_t)p * ks + kc) * g.M * g.N;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < NJ; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t gm = m0 + wm + i * 16 + rq + 4 * v, gn = n0 + wn + j * 16 + cq;
@@ -130,8 +136,18 @@ __global__ void splitk_reduce_kernel(GemmArgs g) {
   }
 }
 
+// Tile shape: 32 rows or columns when that side of C is at most 32 wide
+// (less padding for the thin operands of the sweep), else 64.
+static void gemm_tile(int64_t M, int64_t N, int *bm, int *bn) {
+  *bm = (M <= 32) ? 32 : 64;
+  *bn = (N <= 32) ? 32 : 64;
+  if (*bm == 64 && *bn == 64 && N <= 48 && M >= 256) *bn = 32;  // e.g. N = 40: 2 tiles of 32
+}
+
 int gemm_pick_ksplit(int64_t M, int64_t N, int64_t K, int batch) {
-  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * (int64_t)batch;
+  int bm, bn;
+  gemm_tile(M, N, &bm, &bn);
+  const int64_t tiles = ((M + bm - 1) / bm) * ((N + bn - 1) / bn) * (int64_t)batch;
   int ks = 1;
   // aim for ~2 workgroups per CU while keeping >= 4 K slabs per chunk
   while (tiles * ks < 512 && K / ((int64_t)(ks * 2) * BK) >= 4 && ks < 64) ks *= 2;
@@ -141,15 +157,16 @@ int gemm_pick_ksplit(int64_t M, int64_t N, int64_t K, int batch) {
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   GemmArgs a = g;
-  if (a.K <= 0) {
-    // C = beta C
-    a.ksplit = 1;
-  }
+  if (a.K <= 0) a.ksplit = 1;  // C = beta C
   if (a.ksplit < 1) a.ksplit = 1;
   if (a.ksplit > 1 && a.part == nullptr) a.ksplit = 1;
-  dim3 grid((unsigned)((a.M + BM - 1) / BM), (unsigned)((a.N + BN - 1) / BN),
-            (unsigned)(a.batch * a.ksplit));
-  gemm_f64_kernel<<<grid, 256, 0, s>>>(a);
+  int bm, bn;
+  gemm_tile(a.M, a.N, &bm, &bn);
+  dim3 grid((unsigned)((a.M + bm - 1) / bm), (unsigned)((a.N + bn - 1) / bn), (unsigned)(a.batch * a.ksplit));
+  if (bm == 64 && bn == 64) gemm_f64_kernel<64, 64><<<grid, 256, 0, s>>>(a);
+  else if (bm == 64) gemm_f64_kernel<64, 32><<<grid, 256, 0, s>>>(a);
+  else if (bn == 64) gemm_f64_kernel<32, 64><<<grid, 256, 0, s>>>(a);
+  else gemm_f64_kernel<32, 32><<<grid, 256, 0, s>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || a.ksplit == 1) return e;
   const int64_t total = a.M * a.N * a.batch;

@@ -308,6 +308,12 @@ hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_
   const int64_t n = p.n;
   const int ch = qr_chunk(n, p.k);
   const size_t lds_max = (size_t)kQrLdsDoubles * sizeof(double);
+  static bool attr_done = false;  // set once: the maximum a launch may ask for
+  if (!attr_done) {
+    hipFuncSetAttribute((const void *)tsqr_factor_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
+    hipFuncSetAttribute((const void *)tsqr_formq_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
+    attr_done = true;
+  }
   // upward pass
   for (int L = 0; L < p.levels; ++L) {
     QrLevelArgs la{};
@@ -324,8 +330,6 @@ hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_
     la.ld_rout = n;
     const int64_t nrmax = (la.rows + la.blocks - 1) / la.blocks;
     const size_t lds = (size_t)(nrmax | 1) * n * sizeof(double);
-    hipFuncSetAttribute((const void *)tsqr_factor_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds_max);
     tsqr_factor_kernel<<<dim3((unsigned)la.blocks, (unsigned)batch), 256, lds, s>>>(la);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -350,8 +354,6 @@ hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_
     fa.rdst = fa.top ? r : Mat{nullptr, 0, 0, 0};
     const int64_t nrmax = (fa.rows + fa.blocks - 1) / fa.blocks;
     const size_t lds = (size_t)(nrmax | 1) * (n + ch) * sizeof(double);
-    hipFuncSetAttribute((const void *)tsqr_formq_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds_max);
     tsqr_formq_kernel<<<dim3((unsigned)fa.blocks, (unsigned)batch), 256, lds, s>>>(fa);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -292,7 +292,12 @@ hipError_t launch_svd_trunc(const SvdArgs &a, hipStream_t s) {
   int tpg = 64;
   while (tpg > 1 && tpg * npairs > 256) tpg >>= 1;
   const size_t lds = (size_t)a.nc * a.kr * sizeof(double);
-  hipFuncSetAttribute((const void *)svd_block_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  static bool attr_done = false;  // set once: the maximum a launch may ask for
+  if (!attr_done) {
+    hipFuncSetAttribute((const void *)svd_block_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)(kQrLdsDoubles * sizeof(double)));
+    attr_done = true;
+  }
   svd_block_kernel<<<a.batch, 256, lds, s>>>(a, tpg);
   return hipGetLastError();
 }
@@ -415,7 +420,12 @@ __global__ __launch_bounds__(256) void svd_big_round_kernel(double *acol, int64_
 hipError_t launch_svd_big_round(double *acol, int64_t acs, int kr, int nc, int bw, int nb, int t, int *flags,
                                 int batch, hipStream_t s) {
   const size_t lds = (size_t)2 * bw * kr * sizeof(double);
-  hipFuncSetAttribute((const void *)svd_big_round_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  static bool attr_done = false;  // set once: the maximum a launch may ask for
+  if (!attr_done) {
+    hipFuncSetAttribute((const void *)svd_big_round_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)(kQrLdsDoubles * sizeof(double)));
+    attr_done = true;
+  }
   svd_big_round_kernel<<<dim3((unsigned)(nb / 2), (unsigned)batch), 256, lds, s>>>(acol, acs, kr, nc, bw, nb, t,
                                                                                  flags);
   return hipGetLastError();
