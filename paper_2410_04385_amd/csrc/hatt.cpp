@@ -187,7 +187,7 @@ hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_
 // projected against the finished columns twice, each time with two GEMMs),
 // then the panel itself is factored by TSQR; R collects the projection
 // coefficients above the diagonal blocks.
-constexpr int64_t kPanel = 64;
+constexpr int64_t kPanel = 64;  // <= 64 columns: a TSQR tree with >= 2n-row blocks always exists
 
 struct QrOp {
   int64_t m = 0, n = 0, k = 0;
@@ -204,13 +204,13 @@ bool qr_prepare(int64_t m, int64_t n, QrOp *op) {
   op->n = n;
   op->k = std::min(m, n);
   op->big = op->wide = false;
-  if (n <= kQrMaxCols) {
-    if (!qr_make_plan(m, n, &op->direct)) return false;
+  if (n <= kQrMaxCols && qr_make_plan(m, n, &op->direct)) {
     op->ws_doubles = op->direct.ws_doubles;
     return true;
   }
   if (m < n) {
     // Householder reflectors of a wide matrix depend only on its first m columns
+    if (n <= kQrMaxCols) return false;
     op->wide = true;
     op->sub = std::make_shared<QrOp>();
     if (!qr_prepare(m, m, op->sub.get())) return false;

@@ -127,6 +127,27 @@ hipError_t launch_hpcrl_last(const LastArgs &a, hipStream_t s) {
 // when the output is contiguous in g (the W_L columns of HPCRL), else with
 // the column index innermost (the core update, contiguous in (a', b')).
 // Every LDS access pattern is either a broadcast or unit stride.
+// Three-digit counter (i0 fastest, radices n0, n1) stepped by a fixed stride
+// with carries instead of a division per element.
+struct Rad3 {
+  int i0, i1, i2, n0, n1, s0, s1, s2;
+  __device__ Rad3(int start, int stride, int n0_, int n1_) : n0(n0_), n1(n1_) {
+    i0 = start % n0;
+    i1 = (start / n0) % n1;
+    i2 = start / (n0 * n1);
+    s0 = stride % n0;
+    s1 = (stride / n0) % n1;
+    s2 = stride / (n0 * n1);
+  }
+  __device__ __forceinline__ void next() {
+    i0 += s0;
+    i1 += s1;
+    i2 += s2;
+    if (i0 >= n0) { i0 -= n0; ++i1; }
+    if (i1 >= n1) { i1 -= n1; ++i2; }
+  }
+};
+
 template <bool GFAST>
 __global__ __launch_bounds__(256) void sandwich_kernel(SandwichArgs a, int GC) {
   extern __shared__ double sm[];
@@ -169,38 +190,37 @@ __global__ __launch_bounds__(256) void sandwich_kernel(SandwichArgs a, int GC) {
   const double *cbase = a.c + p * a.cb + g0 * a.cg;
   const int nC = gc * RI * SI;
   if (GFAST) {
-    // Cs[(a*SI + b)*GC + gg]
-    for (int e = tid; e < nC; e += 256) {
-      int gg = e % gc, rest = e / gc;
-      int b = rest % SI, aa = rest / SI;
-      Cs[(aa * SI + b) * GC + gg] = cbase[gg * a.cg + aa * a.ca + b * a.cbb];
-    }
+    // Cs[(a*SI + b)*GC + gg], digits (gg, b, a)
+    Rad3 d(tid, 256, gc, SI);
+    for (int e = tid; e < nC; e += 256, d.next())
+      Cs[(d.i2 * SI + d.i1) * GC + d.i0] = cbase[d.i0 * a.cg + d.i2 * a.ca + d.i1 * a.cbb];
   } else {
-    // Cs[(gg*RI + a)*SI + b]
-    for (int e = tid; e < nC; e += 256) {
-      int b = e % SI, rest = e / SI;
-      int aa = rest % RI, gg = rest / RI;
-      Cs[e] = cbase[gg * a.cg + aa * a.ca + b * a.cbb];
-    }
+    // Cs[(gg*RI + a)*SI + b], digits (b, a, gg)
+    Rad3 d(tid, 256, SI, RI);
+    for (int e = tid; e < nC; e += 256, d.next())
+      Cs[e] = cbase[d.i2 * a.cg + d.i1 * a.ca + d.i0 * a.cbb];
   }
   __syncthreads();
 
   // T = C_g ZR  (RI x SO per g)
   const int nT = gc * RI * SO;
-  for (int e = tid; e < nT; e += 256) {
-    double acc = 0.0;
-    if (GFAST) {
-      int gg = e % gc, rest = e / gc;
-      int bp = rest % SO, aa = rest / SO;
-      const double *cr = Cs + aa * SI * GC + gg;
-      for (int b = 0; b < SI; ++b) acc += cr[b * GC] * ZR[b * SO + bp];
-      Ts[(aa * SO + bp) * GC + gg] = acc;
-    } else {
-      int bp = e % SO, rest = e / SO;
-      int aa = rest % RI, gg = rest / RI;
-      const double *cr = Cs + (gg * RI + aa) * SI;
-      for (int b = 0; b < SI; ++b) acc += cr[b] * ZR[b * SO + bp];
-      Ts[(gg * RI + aa) * SO + bp] = acc;
+  if (GFAST) {
+    Rad3 d(tid, 256, gc, SO);  // digits (gg, b', a)
+    for (int e = tid; e < nT; e += 256, d.next()) {
+      const double *cr = Cs + d.i2 * SI * GC + d.i0;
+      const double *zc = ZR + d.i1;
+      double acc = 0.0;
+      for (int b = 0; b < SI; ++b) acc += cr[b * GC] * zc[b * SO];
+      Ts[(d.i2 * SO + d.i1) * GC + d.i0] = acc;
+    }
+  } else {
+    Rad3 d(tid, 256, SO, RI);  // digits (b', a, gg)
+    for (int e = tid; e < nT; e += 256, d.next()) {
+      const double *cr = Cs + (d.i2 * RI + d.i1) * SI;
+      const double *zc = ZR + d.i0;
+      double acc = 0.0;
+      for (int b = 0; b < SI; ++b) acc += cr[b] * zc[b * SO];
+      Ts[e] = acc;
     }
   }
   __syncthreads();
@@ -208,22 +228,23 @@ __global__ __launch_bounds__(256) void sandwich_kernel(SandwichArgs a, int GC) {
   // out = YL T  (RA x SO per g)
   double *obase = a.o + p * a.ob + i * a.oi + g0 * a.og;
   const int nO = gc * RA * SO;
-  for (int e = tid; e < nO; e += 256) {
-    double acc = 0.0;
-    if (GFAST) {
-      int gg = e % gc, rest = e / gc;
-      int bp = rest % SO, ap = rest / SO;
-      const double *yr = YL + ap * RI;
-      const double *tc = Ts + bp * GC + gg;
+  if (GFAST) {
+    Rad3 d(tid, 256, gc, SO);  // digits (gg, b', a')
+    for (int e = tid; e < nO; e += 256, d.next()) {
+      const double *yr = YL + d.i2 * RI;
+      const double *tc = Ts + d.i1 * GC + d.i0;
+      double acc = 0.0;
       for (int aa = 0; aa < RI; ++aa) acc += yr[aa] * tc[aa * SO * GC];
-      obase[gg * a.og + ap * a.oa + bp * a.obb] = acc;
-    } else {
-      int bp = e % SO, rest = e / SO;
-      int ap = rest % RA, gg = rest / RA;
-      const double *yr = YL + ap * RI;
-      const double *tc = Ts + gg * RI * SO + bp;
+      obase[d.i0 * a.og + d.i2 * a.oa + d.i1 * a.obb] = acc;
+    }
+  } else {
+    Rad3 d(tid, 256, SO, RA);  // digits (b', a', gg)
+    for (int e = tid; e < nO; e += 256, d.next()) {
+      const double *yr = YL + d.i1 * RI;
+      const double *tc = Ts + d.i2 * RI * SO + d.i0;
+      double acc = 0.0;
       for (int aa = 0; aa < RI; ++aa) acc += yr[aa] * tc[aa * SO];
-      obase[gg * a.og + ap * a.oa + bp * a.obb] = acc;
+      obase[d.i2 * a.og + d.i1 * a.oa + d.i0 * a.obb] = acc;
     }
   }
 }

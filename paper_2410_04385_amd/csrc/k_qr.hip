@@ -28,11 +28,13 @@ namespace hatt {
 // reflectors, for a panel of n columns (largest that still lets a block hold
 // at least n rows).
 static int qr_chunk(int64_t n, int64_t k) {
-  const int cand[5] = {(int)std::min<int64_t>(k, 64), 32, 16, 8, 4};
-  for (int i = 0; i < 5; ++i) {
-    const int ch = std::max(1, std::min<int>(cand[i], (int)k));
-    const int64_t mb = kQrLdsDoubles / (n + ch) - 1;
-    if (mb >= n) return ch;
+  const int cand[6] = {(int)std::min<int64_t>(k, 64), 32, 16, 8, 4, 1};
+  for (int need = 2; need >= 1; --need) {   // prefer blocks of >= 2n rows: the tree then shrinks
+    for (int i = 0; i < 6; ++i) {
+      const int ch = std::max(1, std::min<int>(cand[i], (int)k));
+      const int64_t mb = kQrLdsDoubles / (n + ch) - 1;
+      if (mb >= need * n) return ch;
+    }
   }
   return 1;
 }
@@ -70,6 +72,7 @@ bool qr_make_plan(int64_t m, int64_t n, QrPlan *p) {
     off += blocks * n;
     ++L;
     if (blocks == 1) break;
+    if (blocks * n >= rows) return false;  // a level that does not shrink: use panels instead
     rows = blocks * n;
   }
   q.levels = L;
@@ -164,15 +167,16 @@ __global__ __launch_bounds__(256) void tsqr_factor_kernel(QrLevelArgs a) {
         Ws[c] = tau * (A[c * ld + j] + scal * Ds[c]);
       }
       __syncthreads();
-      // pass 2: trailing update of rows j..nr-1 in columns j+1..n-1
-      const int span = nrow + 1;
-      const int total = (nc - 1) * span;
+      // pass 2: trailing update of rows j..nr-1 in columns j+1..n-1; a wave
+      // walks 64 consecutive rows of one column, the 4 waves take every 4th column
       const double *aj = A + j * ld;
-      for (int e = tid; e < total; e += 256) {
-        const int c = j + 1 + e / span, r = j + e % span;
+      const int lane = tid & 63, wv = tid >> 6;
+      for (int c = j + 1 + wv; c < n; c += 4) {
         const double w = Ws[c];
-        if (r == j) A[c * ld + j] -= w;
-        else A[c * ld + r] -= aj[r] * scal * w;
+        const double sw = scal * w;
+        double *ac = A + c * ld;
+        for (int r = j + 1 + lane; r < nr; r += 64) ac[r] -= aj[r] * sw;
+        if (lane == 0) ac[j] -= w;
       }
     }
     __syncthreads();
@@ -276,13 +280,14 @@ __global__ __launch_bounds__(256) void tsqr_formq_kernel(QrFormArgs a) {
         Ws[tid] = tau * s;
       }
       __syncthreads();
-      const int span = nr - j;
-      const int total = cw * span;
-      for (int e = tid; e < total; e += 256) {
-        const int cc = e / span, r = j + e % span;
-        const double w = Ws[cc];
-        if (r == j) X[cc * ld + j] -= w;
-        else X[cc * ld + r] -= vj[r] * w;
+      {
+        const int lane = tid & 63, wv = tid >> 6;
+        for (int cc = wv; cc < cw; cc += 4) {
+          const double w = Ws[cc];
+          double *xc = X + cc * ld;
+          for (int r = j + 1 + lane; r < nr; r += 64) xc[r] -= vj[r] * w;
+          if (lane == 0) xc[j] -= w;
+        }
       }
       __syncthreads();
     }

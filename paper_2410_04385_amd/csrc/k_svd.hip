@@ -70,8 +70,7 @@ __device__ int choose_rank(const double *sig_sorted, int kr, int nc, const SvdAr
 
 template <int KR>
 __global__ __launch_bounds__(64) void svd_wave_kernel(SvdArgs a) {
-  constexpr int LD = KR + 1;
-  __shared__ double xch[64 * LD];
+  __shared__ double xch[KR * 64];  // xch[r * 64 + c]: lanes touch consecutive words
   __shared__ double sig[64];
   __shared__ double sigs[64];
   __shared__ int perm[64];
@@ -88,15 +87,15 @@ __global__ __launch_bounds__(64) void svd_wave_kernel(SvdArgs a) {
     int rot = 0;
     for (int t = 0; t < np - 1; ++t) {
 #pragma unroll
-      for (int r = 0; r < KR; ++r) xch[lane * LD + r] = col[r];
+      for (int r = 0; r < KR; ++r) xch[r * 64 + lane] = col[r];
       __syncthreads();
       const int q = rr_partner(lane, t, np);
       if (lane < nc && q < nc) {
-        const double *pc = xch + q * LD;
+        const double *pc = xch + q;
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
         for (int r = 0; r < KR; ++r) {
-          const double x = col[r], y = pc[r];
+          const double x = col[r], y = pc[r * 64];
           al += x * x;
           be += y * y;
           ga += x * y;
@@ -110,10 +109,10 @@ __global__ __launch_bounds__(64) void svd_wave_kernel(SvdArgs a) {
           const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
           if (isp) {
 #pragma unroll
-            for (int r = 0; r < KR; ++r) col[r] = cs * col[r] - sn * pc[r];
+            for (int r = 0; r < KR; ++r) col[r] = cs * col[r] - sn * pc[r * 64];
           } else {
 #pragma unroll
-            for (int r = 0; r < KR; ++r) col[r] = sn * pc[r] + cs * col[r];
+            for (int r = 0; r < KR; ++r) col[r] = sn * pc[r * 64] + cs * col[r];
           }
           rot = 1;
         }
@@ -127,7 +126,7 @@ __global__ __launch_bounds__(64) void svd_wave_kernel(SvdArgs a) {
   for (int r = 0; r < KR; ++r) s2 += col[r] * col[r];
   sig[lane] = (lane < nc) ? sqrt(s2) : -1.0;
 #pragma unroll
-  for (int r = 0; r < KR; ++r) xch[lane * LD + r] = col[r];
+  for (int r = 0; r < KR; ++r) xch[r * 64 + lane] = col[r];
   __syncthreads();
   if (lane < nc) {
     int rk = 0;
@@ -147,7 +146,7 @@ __global__ __launch_bounds__(64) void svd_wave_kernel(SvdArgs a) {
     if (j < rho) {
       const int c = perm[j];
       const double sc = sigs[j];
-      v = (sc > 0.0) ? xch[c * LD + r] / sc : 0.0;
+      v = (sc > 0.0) ? xch[r * 64 + c] / sc : 0.0;
     }
     U[e] = v;
   }
@@ -161,7 +160,7 @@ __global__ __launch_bounds__(64) void svd_wave_kernel(SvdArgs a) {
         const double sc = sigs[j];
         if (sc > 0.0) {
           const double inv = 1.0 / sc;
-          for (int r = 0; r < kr; ++r) v += xch[cj * LD + r] * R[r * nc + c];
+          for (int r = 0; r < kr; ++r) v += xch[r * 64 + cj] * R[r * nc + c];
           v *= inv;
         }
       }
@@ -283,6 +282,7 @@ hipError_t launch_svd_trunc(const SvdArgs &a, hipStream_t s) {
   if (a.nc <= 64) {
     if (a.kr <= 16) svd_wave_kernel<16><<<a.batch, 64, 0, s>>>(a);
     else if (a.kr <= 32) svd_wave_kernel<32><<<a.batch, 64, 0, s>>>(a);
+    else if (a.kr <= 48) svd_wave_kernel<48><<<a.batch, 64, 0, s>>>(a);
     else svd_wave_kernel<64><<<a.batch, 64, 0, s>>>(a);
     return hipGetLastError();
   }
