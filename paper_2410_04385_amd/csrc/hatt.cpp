@@ -183,10 +183,14 @@ hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_
 
 // ---------------------------------------------------------------------------
 // QR dispatch.  Up to kQrMaxCols columns: one TSQR.  Wider (m >= n): block
-// Gram-Schmidt applied twice per panel of kPanel columns (the panel is
-// projected against the finished columns twice, each time with two GEMMs),
-// then the panel itself is factored by TSQR; R collects the projection
-// coefficients above the diagonal blocks.
+// classical Gram-Schmidt with re-orthogonalisation of each panel's Q factor
+// (BCGS2 of Barlow and Smoktunowicz), panels of kPanel columns:
+//   S1 = Q_prev^T A_p;  W = A_p - Q_prev S1;  W = Q1 R1 (TSQR)
+//   S2 = Q_prev^T Q1;   W2 = Q1 - Q_prev S2;  W2 = Q2 R2 (TSQR)
+//   R(prev, p) = S1 + S2 R1,  R(p, p) = R2 R1.
+// The second pass is what keeps Q orthonormal when a panel is (numerically)
+// rank deficient: the first TSQR then completes the panel with normalised
+// rounding noise that still has O(1) components along Q_prev.
 constexpr int64_t kPanel = 64;  // <= 64 columns: a TSQR tree with >= 2n-row blocks always exists
 
 struct QrOp {
@@ -197,6 +201,7 @@ struct QrOp {
   QrPlan direct{};
   std::vector<QrPlan> panels;
   int64_t ws_doubles = 0;  // per pair
+  int64_t ws_tree = 0;     // big: TSQR tree part at the front
 };
 
 bool qr_prepare(int64_t m, int64_t n, QrOp *op) {
@@ -227,7 +232,9 @@ bool qr_prepare(int64_t m, int64_t n, QrOp *op) {
     op->panels.push_back(pl);
     w = std::max(w, pl.ws_doubles);
   }
-  op->ws_doubles = w + 2 * n * kPanel;  // TSQR tree + two coefficient blocks
+  op->ws_tree = w;
+  // TSQR tree + S1, S2 (n x kPanel each) + R1, R2 (kPanel x kPanel each)
+  op->ws_doubles = w + 2 * n * kPanel + 2 * kPanel * kPanel;
   return true;
 }
 
@@ -250,35 +257,49 @@ hatt_status qr_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, int64_t rbuf
     return HATT_OK;
   }
   const int64_t m = op.m, n = op.n;
-  double *coef0 = ws + (op.ws_doubles - 2 * n * kPanel);
-  double *coef1 = coef0 + n * kPanel;
+  double *s1buf = ws + op.ws_tree;
+  double *s2buf = s1buf + n * kPanel;
+  double *r1buf = s2buf + n * kPanel;
+  double *r2buf = r1buf + kPanel * kPanel;
   LAUNCH(launch_copy(A, Q, m, n, P, st));
   if (R.ptr) LAUNCH(launch_fill(R.ptr, (int64_t)P * rbuf, 0.0, st));
   int pi = 0;
   for (int64_t c0 = 0; c0 < n; c0 += kPanel, ++pi) {
     const int64_t cw = std::min(kPanel, n - c0);
     CMat Qprev{Q.ptr, Q.rs, Q.cs, Q.bs};
+    CMat QprevT{Q.ptr, Q.cs, Q.rs, Q.bs};
     Mat Qpan{Q.ptr + c0 * Q.cs, Q.rs, Q.cs, Q.bs};
     CMat Qpanc{Qpan.ptr, Qpan.rs, Qpan.cs, Qpan.bs};
-    if (c0 > 0) {
-      for (int pass = 0; pass < 2; ++pass) {
-        double *cf = pass ? coef1 : coef0;
-        // cf (c0 x cw) = Qprev^T Qpan
-        hatt_status s1 = gemm(run, gc, CMat{Qprev.ptr, Qprev.cs, Qprev.rs, Qprev.bs}, Qpanc,
-                              Mat{cf, cw, 1, wsp}, c0, cw, m, 1.0, 0.0, P, st, true);
-        if (s1 != HATT_OK) return s1;
-        // Qpan -= Qprev cf
-        s1 = gemm(run, gc, Qprev, CMat{cf, cw, 1, wsp}, Qpan, m, cw, c0, -1.0, 1.0, P, st, false);
-        if (s1 != HATT_OK) return s1;
-        if (R.ptr) {
-          Mat rblk{R.ptr + c0 * R.cs, R.rs, R.cs, R.bs};
-          if (pass == 0) LAUNCH(launch_copy(CMat{cf, cw, 1, wsp}, rblk, c0, cw, P, st));
-          else LAUNCH(launch_add(CMat{cf, cw, 1, wsp}, rblk, c0, cw, P, st));
-        }
-      }
+    Mat rdiag = R.ptr ? Mat{R.ptr + c0 * R.rs + c0 * R.cs, R.rs, R.cs, R.bs} : Mat{nullptr, 0, 0, 0};
+    if (c0 == 0) {
+      LAUNCH(launch_tsqr(op.panels[pi], Qpanc, Qpan, rdiag, ws, wsp, P, st));
+      continue;
     }
-    Mat rpp = R.ptr ? Mat{R.ptr + c0 * R.rs + c0 * R.cs, R.rs, R.cs, R.bs} : Mat{nullptr, 0, 0, 0};
-    LAUNCH(launch_tsqr(op.panels[pi], Qpanc, Qpan, rpp, ws, wsp, P, st));
+    // first pass: S1 goes straight into R's block above the diagonal
+    Mat s1 = R.ptr ? Mat{R.ptr + c0 * R.cs, R.rs, R.cs, R.bs} : Mat{s1buf, cw, 1, wsp};
+    CMat s1c{s1.ptr, s1.rs, s1.cs, s1.bs};
+    hatt_status sg = gemm(run, gc, QprevT, Qpanc, s1, c0, cw, m, 1.0, 0.0, P, st, true);
+    if (sg != HATT_OK) return sg;
+    sg = gemm(run, gc, Qprev, s1c, Qpan, m, cw, c0, -1.0, 1.0, P, st, false);
+    if (sg != HATT_OK) return sg;
+    Mat r1 = R.ptr ? Mat{r1buf, cw, 1, wsp} : Mat{nullptr, 0, 0, 0};
+    LAUNCH(launch_tsqr(op.panels[pi], Qpanc, Qpan, r1, ws, wsp, P, st));
+    // second pass on the orthonormalised panel
+    sg = gemm(run, gc, QprevT, Qpanc, Mat{s2buf, cw, 1, wsp}, c0, cw, m, 1.0, 0.0, P, st, true);
+    if (sg != HATT_OK) return sg;
+    sg = gemm(run, gc, Qprev, CMat{s2buf, cw, 1, wsp}, Qpan, m, cw, c0, -1.0, 1.0, P, st, false);
+    if (sg != HATT_OK) return sg;
+    Mat r2 = R.ptr ? Mat{r2buf, cw, 1, wsp} : Mat{nullptr, 0, 0, 0};
+    LAUNCH(launch_tsqr(op.panels[pi], Qpanc, Qpan, r2, ws, wsp, P, st));
+    if (R.ptr) {
+      // R(prev, p) += S2 R1;  R(p, p) = R2 R1
+      sg = gemm(run, gc, CMat{s2buf, cw, 1, wsp}, CMat{r1buf, cw, 1, wsp}, s1, c0, cw, cw, 1.0, 1.0, P, st,
+                false);
+      if (sg != HATT_OK) return sg;
+      sg = gemm(run, gc, CMat{r2buf, cw, 1, wsp}, CMat{r1buf, cw, 1, wsp}, rdiag, cw, cw, cw, 1.0, 0.0, P, st,
+                false);
+      if (sg != HATT_OK) return sg;
+    }
   }
   return HATT_OK;
 }

@@ -290,3 +290,59 @@ def test_trig_workload_products_at_tolerance():
     assert tt.ranks(u3) == [1, 121, 121, 1]
     e3 = np.linalg.norm(tt.full(u3) - fu ** 3) / np.linalg.norm(fu ** 3)
     assert e3 <= 3 * cfg["tol"]
+
+
+def _padded(train, r, seed):
+    """The same tensor as ``train`` (d = 3) carried on bonds of rank r: zero
+    padding, then a random orthogonal change of basis on each bond."""
+    rng = np.random.default_rng(seed)
+    c0, c1, c2 = train
+    a, b = c1.shape[0], c1.shape[2]
+    q1, _ = np.linalg.qr(rng.standard_normal((r, r)))
+    q2, _ = np.linalg.qr(rng.standard_normal((r, r)))
+    p0 = np.zeros((1, c0.shape[1], r))
+    p0[:, :, :a] = c0
+    p1 = np.zeros((r, c1.shape[1], r))
+    p1[:a, :, :b] = c1
+    p2 = np.zeros((r, c2.shape[1], 1))
+    p2[:b] = c2
+    return [np.einsum("inj,jk->ink", p0, q1), np.einsum("ij,jnk,kl->inl", q1.T, p1, q2),
+            np.einsum("ij,jnk->ink", q2.T, p2)]
+
+
+@pytest.mark.parametrize("r", [100, 145, 200])
+def test_round_rank_deficient_wide_bonds(r):
+    """TT-Rounding of a rank-30 tensor carried on bonds of rank r: the
+    orthogonalisation QRs are rank deficient (and panelled above 128
+    columns); the truncation must still find rank 30."""
+    base = wk.gaussian_tt(np.random.default_rng(7), [256, 64, 256], [1, 30, 30, 1])
+    pad = _padded(base, r, 3)
+    _say(f"tt_round rank-deficient padded r={r}")
+    res = H.round(H.TT.from_cores([pad]), tol=1e-10)
+    torch.cuda.synchronize()
+    got = res.train(0)
+    ref = rounding.tt_round(pad, tol=1e-10)
+    assert tt.ranks(got) == tt.ranks(ref) == [1, 30, 30, 1]
+    assert tt.rel_err(got, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("ell", [128, 150])
+def test_hatt_rank_deficient_sketch(ell):
+    """u*u for 20 trig terms has exact rank 41 per bond; sketches of width
+    128 and 150 make every sketched matrix rank deficient and send the
+    256 x ell QR down the panelled path."""
+    u = wk.trig_u(5, n=256, terms=20, nfreq=10)
+    ells = [1, ell, ell, 1]
+    _say(f"hatt_recompress rank-deficient sketch ell={ell}")
+    U = H.TT.from_cores([u])
+    res = H.recompress(U, U, ells, seed=9)
+    torch.cuda.synchronize()
+    got = res.train(0)
+    R = philox.sketch(9, tt.modes(u), ells)
+    ref = ohatt.hatt(u, u, R)
+    assert tt.rel_err(got, ref) <= 1e-10
+    res = H.recompress(U, U, ells, tol=1e-10, seed=9)
+    torch.cuda.synchronize()
+    got = res.train(0)
+    assert tt.ranks(got) == [1, 41, 41, 1]
+    assert tt.rel_err(got, rounding.tt_round(ref, tol=1e-10)) <= 1e-9
