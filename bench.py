@@ -120,6 +120,7 @@ def main() -> int:
         step()
     prof = H.profile_stop()
     torch.cuda.synchronize()
+    print("[bench] per launch site over the profiled steps:\n" + H.profile_report(), file=sys.stderr, flush=True)
     flops = perfmodel.hatt_round_flops(x.n, x.ranks, y.ranks, p["ell"], cap)
     classes = {}
     for name, (ms, calls) in prof.items():

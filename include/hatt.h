@@ -188,6 +188,22 @@ HATT_API hatt_status hatt_sketch_fill(uint64_t seed, int32_t d, const int64_t *n
                              double *out, void *stream);
 
 /*
+ * QR method used by every entry point for the QR factorisations of the
+ * HaTT sweep (Alg. 4) and of TT-Rounding (Alg. 1), process-wide:
+ *   0 (default): CholeskyQR2 on the matrix cores for matrices of at most 64
+ *      columns (and at least as many rows), Householder TSQR otherwise; a
+ *      pair whose Gram matrix is too ill-conditioned for CholeskyQR2
+ *      (condition number beyond about 1e6, rank deficiency included) is
+ *      recomputed by Householder TSQR inside the same call;
+ *   1: Householder TSQR (and panelled block Gram-Schmidt above 128 columns)
+ *      everywhere.
+ * Workspace sizes depend on the method: plan again after changing it.  Not
+ * thread-safe with concurrent plan or compute calls.  HATT_EINVAL for other
+ * values.
+ */
+HATT_API hatt_status hatt_set_qr_method(int32_t method);
+
+/*
  * Instrumentation (not thread-safe; for benchmarks).  Between
  * hatt_profile_start() and hatt_profile_stop() every kernel launch the
  * library enqueues is bracketed by two HIP events on the launching stream
@@ -202,6 +218,10 @@ HATT_API hatt_status hatt_sketch_fill(uint64_t seed, int32_t d, const int64_t *n
 HATT_API hatt_status hatt_profile_start(void);
 HATT_API hatt_status hatt_profile_stop(double *ms_out, int64_t *calls_out);
 HATT_API const char *hatt_profile_class_name(int32_t cls);
+/* Text table written by the last hatt_profile_stop(): one line per launch
+ * site ("class: label", GEMMs labelled with M x N x K and split), with its
+ * summed milliseconds and calls, largest first.  Valid until the next stop. */
+HATT_API const char *hatt_profile_report(void);
 
 /* Message describing the last error of the calling thread ("" if none). */
 HATT_API const char *hatt_last_error(void);

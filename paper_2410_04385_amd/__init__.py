@@ -13,12 +13,14 @@ from .api import (  # noqa: F401
     hadamard_explicit,
     norm,
     plan,
+    profile_report,
     profile_start,
     profile_stop,
     recompress,
     recompress_adaptive,
     round,
     round_plan,
+    set_qr_method,
     sketch_fill,
     version,
 )

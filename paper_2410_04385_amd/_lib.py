@@ -19,7 +19,8 @@ STATUS_NAMES = {
 EXPORTED = [
     "hatt_plan", "hatt_recompress", "hatt_adaptive_plan", "hatt_recompress_adaptive", "tt_hadamard_explicit", "tt_round_plan", "tt_round",
     "tt_norm_plan", "tt_norm", "hatt_sketch_fill", "hatt_profile_start", "hatt_profile_stop",
-    "hatt_profile_class_name", "hatt_last_error", "hatt_version",
+    "hatt_profile_class_name", "hatt_last_error", "hatt_version", "hatt_set_qr_method",
+    "hatt_profile_report",
 ]
 PROFILE_CLASSES = 8
 
@@ -97,10 +98,11 @@ def lib() -> ctypes.CDLL:
     L.hatt_profile_class_name.argtypes = [ctypes.c_int32]
     L.hatt_profile_class_name.restype = ctypes.c_char_p
     for fn in EXPORTED:
-        if fn not in ("hatt_profile_class_name", "hatt_last_error", "hatt_version"):
+        if fn not in ("hatt_profile_class_name", "hatt_last_error", "hatt_version", "hatt_profile_report"):
             getattr(L, fn).restype = ctypes.c_int
     L.hatt_last_error.restype = ctypes.c_char_p
     L.hatt_version.restype = ctypes.c_char_p
+    L.hatt_profile_report.restype = ctypes.c_char_p
     _lib = L
     return L
 

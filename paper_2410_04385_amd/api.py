@@ -262,5 +262,19 @@ def profile_stop() -> dict:
     return {lib().hatt_profile_class_name(i).decode(): (float(ms[i]), int(calls[i])) for i in range(n)}
 
 
+def profile_report() -> str:
+    """Per-launch-site table of the last profile_stop()."""
+    return lib().hatt_profile_report().decode()
+
+
+def set_qr_method(method: str) -> None:
+    """"cholqr2" (default: CholeskyQR2 with per-pair Householder fallback) or
+    "householder" (TSQR everywhere).  Plan again afterwards."""
+    codes = {"cholqr2": 0, "householder": 1}
+    if method not in codes:
+        raise ValueError(f"unknown QR method {method!r}")
+    check("hatt_set_qr_method", lib().hatt_set_qr_method(codes[method]))
+
+
 def version() -> str:
     return lib().hatt_version().decode()

@@ -95,7 +95,8 @@ struct GemmArgs {
   int batch;
   int ksplit;
   double *part;
-  const int *run_flag;  // optional: pair p is computed only when run_flag[p] == run_when
+  const int *run_flag;  // optional: pair p is computed only when run_flag[p * run_flag_stride] == run_when
+  int64_t run_flag_stride;
   int run_when;
 };
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
@@ -116,17 +117,17 @@ struct QrPlan {
   int64_t ws_doubles;            // per pair
 };
 bool qr_make_plan(int64_t m, int64_t n, QrPlan *p);
-// skip_flag (optional): pairs with skip_flag[p] == 1 are left untouched.
+// skip_flag (optional): pairs with skip_flag[p * skip_stride] == 1 are left untouched.
 hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_t ws_pair_stride,
-                       int batch, hipStream_t s, const int *skip_flag = nullptr);
+                       int batch, hipStream_t s, const int *skip_flag = nullptr, int64_t skip_stride = 0);
 
 // Cholesky factor of a Gram matrix G (n x n, n <= 64, row-major, pair stride
 // gbs): R (upper, diag > 0) and R^{-1}, both n x n row-major with pair stride
-// rbs.  flag[p] is set to (ok) when first != 0, else and-ed with ok; ok means
-// every pivot exceeded 1e-12 times the largest diagonal entry of G.
+// rbs.  flag[p * fstride] is set to ok when first != 0, else and-ed with ok;
+// ok means every pivot exceeded thr_rel times the largest diagonal entry of G.
 constexpr int kCholMaxN = 64;
 hipError_t launch_chol(const double *g, int64_t gbs, double *r, double *rinv, int64_t rbs, int n, int *flag,
-                       int first, int batch, hipStream_t s);
+                       int64_t fstride, int first, double thr_rel, int batch, hipStream_t s);
 
 // ---- Jacobi SVD + rank choice (k_svd.hip) ----------------------------------
 // For each pair: R (kr x nc, row-major, kr <= nc <= kSvdMaxN) = U S V^T by

@@ -3,6 +3,8 @@
 // explicit PKP Hadamard product and the TT norm.  Everything here runs on the
 // host and only enqueues kernels; no device memory is allocated.
 #include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <cmath>
@@ -10,6 +12,7 @@
 #include <algorithm>
 #include <memory>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "common.h"
@@ -89,13 +92,29 @@ struct Ws {
 
 // Optional per-launch timing: when enabled, every launcher call below is
 // bracketed by two HIP events on its stream and attributed to a kernel class.
-enum { P_SKETCH, P_PKP, P_LAST, P_SANDWICH, P_GEMM, P_TSQR, P_SVD, P_OTHER, P_NCLASS };
+// Every launch made inside a QR (CholeskyQR2 GEMMs and Cholesky factors,
+// Householder TSQR, panel projections) is attributed to the class "qr".
+enum { P_SKETCH, P_PKP, P_LAST, P_SANDWICH, P_GEMM, P_QR, P_SVD, P_OTHER, P_NCLASS };
 const char *kClassNames[P_NCLASS] = {"sketch_fill", "pkp_expand", "hpcrl_last", "sandwich",
-                                     "gemm_f64",    "tsqr",       "svd_trunc",  "copy_fill_norm"};
+                                     "gemm_f64",    "qr",         "svd_trunc",  "copy_fill_norm"};
+int g_class_override = -1;
+struct ClassScope {
+  int prev;
+  explicit ClassScope(int c) : prev(g_class_override) { g_class_override = c; }
+  ~ClassScope() { g_class_override = prev; }
+};
+// QR method: 0 = CholeskyQR2 where it applies (<= 64 columns) with per-pair
+// Householder fallback, 1 = Householder TSQR only.
+bool g_use_chol = true;
 struct ProfRec {
   int cls;
   hipEvent_t a, b;
+  std::string site;
 };
+// Label of the next launch for the per-site report (set by helpers that
+// know the shape, e.g. the GEMM dispatcher); empty: the launcher's name.
+std::string g_site;
+std::string g_prof_report;
 struct Profiler {
   bool on = false;
   std::vector<ProfRec> recs;
@@ -113,14 +132,35 @@ struct Profiler {
 Profiler g_prof;
 
 int class_of(const char *expr) {
+  if (g_class_override >= 0) return g_class_override;
   if (strstr(expr, "launch_gemm")) return P_GEMM;
-  if (strstr(expr, "launch_tsqr")) return P_TSQR;
+  if (strstr(expr, "launch_tsqr")) return P_QR;
   if (strstr(expr, "launch_sandwich")) return P_SANDWICH;
   if (strstr(expr, "launch_svd")) return P_SVD;
   if (strstr(expr, "launch_pkp")) return P_PKP;
   if (strstr(expr, "launch_hpcrl_last")) return P_LAST;
   if (strstr(expr, "launch_sketch")) return P_SKETCH;
   return P_OTHER;
+}
+
+void site(const char *fmt, ...) {
+  if (!g_prof.on) return;
+  char b[96];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(b, sizeof b, fmt, ap);
+  va_end(ap);
+  g_site = b;
+}
+
+std::string site_of(const char *expr) {
+  std::string lab = g_site;
+  if (lab.empty()) {
+    const char *e = strchr(expr, '(');
+    lab.assign(expr, e ? (size_t)(e - expr) : strlen(expr));
+  }
+  const char *cls = kClassNames[class_of(expr)];
+  return std::string(cls) + ": " + lab;
 }
 
 #define LAUNCH(expr)                                                            \
@@ -135,8 +175,9 @@ int class_of(const char *expr) {
       hipError_t e_ = (expr);                                                   \
       if (g_prof.on && pa_ && pb_) {                                            \
         (void)hipEventRecord(pb_, st);                                          \
-        g_prof.recs.push_back(ProfRec{class_of(#expr), pa_, pb_});              \
+        g_prof.recs.push_back(ProfRec{class_of(#expr), pa_, pb_, site_of(#expr)}); \
       }                                                                         \
+      if (g_prof.on) g_site.clear();                                            \
       if (e_ != hipSuccess)                                                     \
         return fail(HATT_EDEVICE, std::string("HIP error in ") + #expr + ": " + \
                                       hipGetErrorString(e_));                   \
@@ -161,8 +202,12 @@ struct GemmCtx {
 };
 
 hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_t N, int64_t K,
-                 double alpha, double beta, int batch, hipStream_t st, bool allow_split) {
+                 double alpha, double beta, int batch, hipStream_t st, bool allow_split,
+                 const int *run_flag = nullptr, int64_t run_flag_stride = 0) {
   GemmArgs g{};
+  g.run_flag = run_flag;
+  g.run_flag_stride = run_flag_stride;
+  g.run_when = 1;
   g.A = A;
   g.B = B;
   g.C = C;
@@ -177,7 +222,14 @@ hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_
   gc.part_need = std::max(gc.part_need, need);
   if (g.ksplit > 1 && need > gc.part_cap) g.ksplit = 1;
   g.part = gc.part;
+  if (g_prof.on) {
+    char b[96];
+    snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=%d%s", (long long)M, (long long)N, (long long)K, g.ksplit,
+             run_flag ? " flagged" : "");
+    g_site = b;
+  }
   LAUNCH(launch_gemm(g, st));
+  g_site.clear();
   return HATT_OK;
 }
 
@@ -195,22 +247,40 @@ constexpr int64_t kPanel = 64;  // <= 64 columns: a TSQR tree with >= 2n-row blo
 
 struct QrOp {
   int64_t m = 0, n = 0, k = 0;
+  bool chol = false;                 // CholeskyQR2 with per-pair TSQR fallback
   bool big = false;
   bool wide = false;                 // m < n, n > kQrMaxCols: QR of the first m columns, then R2 = Q^T A2
   std::shared_ptr<QrOp> sub;
   QrPlan direct{};
   std::vector<QrPlan> panels;
   int64_t ws_doubles = 0;  // per pair
-  int64_t ws_tree = 0;     // big: TSQR tree part at the front
+  int64_t ws_tree = 0;     // big: TSQR tree part at the front; chol: fallback TSQR tree
 };
+
+// CholeskyQR2 (n <= kCholMaxN, m >= n): G = A^T A, R1 = chol(G), Q1 = A R1^{-1},
+// then the same on Q1 giving R2; Q = Q1 R2^{-1}, R = R2 R1.  All products run
+// on the MFMA GEMM.  A pair whose first Gram matrix has a pivot below 1e-12 of
+// its largest diagonal entry (condition number beyond ~1e6, which includes
+// rank-deficient inputs), or whose second Gram matrix is not close to the
+// identity, is recomputed by Householder TSQR instead; the decision is taken
+// on the device, per pair, so no host synchronisation is needed.
+constexpr double kCholThr1 = 1e-12;
+constexpr double kCholThr2 = 0.5;
+
+int64_t chol_ws_doubles(int64_t m, int64_t n) { return m * n + 5 * n * n + 1; }
 
 bool qr_prepare(int64_t m, int64_t n, QrOp *op) {
   op->m = m;
   op->n = n;
   op->k = std::min(m, n);
-  op->big = op->wide = false;
+  op->big = op->wide = op->chol = false;
   if (n <= kQrMaxCols && qr_make_plan(m, n, &op->direct)) {
     op->ws_doubles = op->direct.ws_doubles;
+    if (g_use_chol && m >= n && n <= kCholMaxN) {
+      op->chol = true;
+      op->ws_tree = op->direct.ws_doubles;
+      op->ws_doubles = op->ws_tree + chol_ws_doubles(m, n);
+    }
     return true;
   }
   if (m < n) {
@@ -238,10 +308,42 @@ bool qr_prepare(int64_t m, int64_t n, QrOp *op) {
   return true;
 }
 
+hatt_status cholqr2_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double *ws, int64_t wsp, int P,
+                         GemmCtx &gc, hipStream_t st) {
+  const int64_t m = op.m, n = op.n;
+  double *q1 = ws + op.ws_tree;  // m x n row-major
+  double *g = q1 + m * n;
+  double *r1 = g + n * n, *r1i = r1 + n * n, *r2 = r1i + n * n, *r2i = r2 + n * n;
+  int *flag = reinterpret_cast<int *>(r2i + n * n);
+  const int64_t fst = 2 * wsp;  // flag stride in ints
+  CMat At{A.ptr, A.cs, A.rs, A.bs};
+  CMat q1c{q1, n, 1, wsp}, q1t{q1, 1, n, wsp};
+  hatt_status sg = gemm(run, gc, At, A, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true);
+  if (sg != HATT_OK) return sg;
+  site("chol %lld", (long long)n);
+  LAUNCH(launch_chol(g, wsp, r1, r1i, wsp, (int)n, flag, fst, 1, kCholThr1, P, st));
+  sg = gemm(run, gc, A, CMat{r1i, n, 1, wsp}, Mat{q1, n, 1, wsp}, m, n, n, 1.0, 0.0, P, st, false);
+  if (sg != HATT_OK) return sg;
+  sg = gemm(run, gc, q1t, q1c, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true);
+  if (sg != HATT_OK) return sg;
+  site("chol %lld", (long long)n);
+  LAUNCH(launch_chol(g, wsp, r2, r2i, wsp, (int)n, flag, fst, 0, kCholThr2, P, st));
+  sg = gemm(run, gc, q1c, CMat{r2i, n, 1, wsp}, Q, m, n, n, 1.0, 0.0, P, st, false, flag, fst);
+  if (sg != HATT_OK) return sg;
+  if (R.ptr) {
+    sg = gemm(run, gc, CMat{r2, n, 1, wsp}, CMat{r1, n, 1, wsp}, R, n, n, n, 1.0, 0.0, P, st, false, flag, fst);
+    if (sg != HATT_OK) return sg;
+  }
+  site("tsqr fallback %lldx%lld", (long long)m, (long long)n);
+  LAUNCH(launch_tsqr(op.direct, A, Q, R, ws, wsp, P, st, flag, fst));
+  return HATT_OK;
+}
+
 // A (m x n), Q (m x k), R (k x n row-major with row stride r.rs, or null).
 // R, when given, must be a contiguous per-pair block of rbuf doubles.
 hatt_status qr_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, int64_t rbuf, double *ws, int64_t wsp,
                     int P, GemmCtx &gc, hipStream_t st) {
+  ClassScope cls(P_QR);
   if (op.wide) {
     hatt_status s0 = qr_exec(run, *op.sub, A, Q, R, rbuf, ws, wsp, P, gc, st);
     if (s0 != HATT_OK) return s0;
@@ -252,7 +354,9 @@ hatt_status qr_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, int64_t rbuf
     }
     return HATT_OK;
   }
+  if (op.chol) return cholqr2_exec(run, op, A, Q, R, ws, wsp, P, gc, st);
   if (!op.big) {
+    site("tsqr %lldx%lld", (long long)op.m, (long long)op.n);
     LAUNCH(launch_tsqr(op.direct, A, Q, R, ws, wsp, P, st));
     return HATT_OK;
   }
@@ -316,6 +420,7 @@ int64_t svd_ws_doubles(int kr, int nc) {
 
 hatt_status svd_exec(bool run, const SvdArgs &sa, double *big, int64_t bigp, int *flags, hipStream_t st) {
   if (sa.nc <= kSvdMaxN && (int64_t)sa.kr * sa.nc <= kQrLdsDoubles) {
+    site("svd %dx%d", sa.kr, sa.nc);
     LAUNCH(launch_svd_trunc(sa, st));
     return HATT_OK;
   }
@@ -701,6 +806,7 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     a.n = n[c];
     a.G = l1;
     a.batch = P;
+    site("sandwich W_L n=%lld G=%lld", (long long)n[c], (long long)l1);
     LAUNCH(launch_sandwich(a, st));
     const int64_t K = n[c] * l1;
     const CMat wr = v2 ? CMat{h2WR, 1, K, h2_wr} : CMat{sk + skoff[c], 1, K, sks};
@@ -764,6 +870,7 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     a.n = n[cn];
     a.G = l[cn];
     a.batch = P;
+    site("sandwich update n=%lld G=%lld", (long long)n[cn], (long long)l[cn]);
     LAUNCH(launch_sandwich(a, st));
   }
   // ranks before truncation: the sketch widths
@@ -824,6 +931,7 @@ hatt_status hatt_profile_stop(double *ms_out, int64_t *calls_out) {
     ms_out[c] = 0.0;
     calls_out[c] = 0;
   }
+  std::map<std::string, std::pair<double, int64_t>> by_site;
   for (const ProfRec &r : g_prof.recs) {
     if (hipEventSynchronize(r.b) != hipSuccess) return fail(HATT_EDEVICE, "profile_stop: event sync failed");
     float ms = 0.f;
@@ -831,9 +939,29 @@ hatt_status hatt_profile_stop(double *ms_out, int64_t *calls_out) {
       return fail(HATT_EDEVICE, "profile_stop: elapsed time failed");
     ms_out[r.cls] += ms;
     calls_out[r.cls] += 1;
+    auto &acc = by_site[r.site];
+    acc.first += ms;
+    acc.second += 1;
   }
+  std::vector<std::pair<double, std::string>> rows;
+  for (auto &kv : by_site) {
+    char b[64];
+    snprintf(b, sizeof b, "%12.3f ms %8lld calls  ", kv.second.first, (long long)kv.second.second);
+    rows.emplace_back(kv.second.first, std::string(b) + kv.first);
+  }
+  std::sort(rows.begin(), rows.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+  g_prof_report.clear();
+  for (auto &rw : rows) g_prof_report += rw.second + "\n";
   g_prof.recs.clear();
   g_prof.used = 0;
+  return HATT_OK;
+}
+
+const char *hatt_profile_report(void) { return g_prof_report.c_str(); }
+
+hatt_status hatt_set_qr_method(int32_t method) {
+  if (method != 0 && method != 1) return fail(HATT_EINVAL, "QR method must be 0 (CholeskyQR2 + fallback) or 1");
+  g_use_chol = (method == 0);
   return HATT_OK;
 }
 

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
   const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
   const int ks = g.ksplit;
   const int p = blockIdx.z / ks, kc = blockIdx.z - (blockIdx.z / ks) * ks;
-  if (g.run_flag != nullptr && g.run_flag[p] != g.run_when) return;
+  if (g.run_flag != nullptr && g.run_flag[p * g.run_flag_stride] != g.run_when) return;
   int64_t kchunk = (g.K + ks - 1) / ks;
   kchunk = ((kchunk + BK - 1) / BK) * BK;
   const int64_t kbeg = kc * kchunk;
@@ -127,7 +127,7 @@ __global__ void splitk_reduce_kernel(GemmArgs g) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = e / per, rem = e - p * per;
-    if (g.run_flag != nullptr && g.run_flag[p] != g.run_when) continue;
+    if (g.run_flag != nullptr && g.run_flag[p * g.run_flag_stride] != g.run_when) continue;
     const int64_t r = rem / g.N, c = rem - r * g.N;
     const double *src = g.part + p * g.ksplit * per + rem;
     double acc = 0.0;

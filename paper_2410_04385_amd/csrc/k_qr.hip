@@ -91,11 +91,12 @@ struct QrLevelArgs {
   int64_t off_v, off_tau;
   int64_t off_rout;  // where the stacked R factors (or the final R) go
   int64_t ld_rout;   // row stride of that buffer
-  const int *skip;   // optional: pairs with skip[p] == 1 are left untouched
+  const int *skip;   // optional: pairs with skip[p * skip_stride] == 1 are left untouched
+  int64_t skip_stride;
 };
 
 __global__ __launch_bounds__(256) void tsqr_factor_kernel(QrLevelArgs a) {
-  if (a.skip != nullptr && a.skip[blockIdx.y] == 1) return;
+  if (a.skip != nullptr && a.skip[blockIdx.y * a.skip_stride] == 1) return;
   extern __shared__ double A[];  // column-major block: A[c * ld + r]
   __shared__ double part[256];
   __shared__ double Ds[kQrMaxCols];
@@ -220,10 +221,11 @@ struct QrFormArgs {
   Mat dst;            // this level's explicit Q (rows x k)
   Mat rdst;           // final R destination (top level only, may be null)
   const int *skip;
+  int64_t skip_stride;
 };
 
 __global__ __launch_bounds__(256) void tsqr_formq_kernel(QrFormArgs a) {
-  if (a.skip != nullptr && a.skip[blockIdx.y] == 1) return;
+  if (a.skip != nullptr && a.skip[blockIdx.y * a.skip_stride] == 1) return;
   extern __shared__ double sm[];
   __shared__ double part[256];
   __shared__ double Ws[kQrMaxCols];
@@ -312,7 +314,7 @@ __global__ __launch_bounds__(256) void tsqr_formq_kernel(QrFormArgs a) {
 }
 
 hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_t wsp, int batch,
-                       hipStream_t s, const int *skip_flag) {
+                       hipStream_t s, const int *skip_flag, int64_t skip_stride) {
   if (batch <= 0) return hipSuccess;
   const int64_t n = p.n;
   const int ch = qr_chunk(n, p.k);
@@ -338,6 +340,7 @@ hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_
     la.off_rout = (L + 1 < p.levels) ? p.off_stack[L + 1] : p.off_rtop;
     la.ld_rout = n;
     la.skip = skip_flag;
+    la.skip_stride = skip_stride;
     const int64_t nrmax = (la.rows + la.blocks - 1) / la.blocks;
     const size_t lds = (size_t)(nrmax | 1) * n * sizeof(double);
     tsqr_factor_kernel<<<dim3((unsigned)la.blocks, (unsigned)batch), 256, lds, s>>>(la);
@@ -363,6 +366,7 @@ hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_
     else fa.dst = Mat{ws + p.off_stack[L], p.k, 1, wsp};
     fa.rdst = fa.top ? r : Mat{nullptr, 0, 0, 0};
     fa.skip = skip_flag;
+    fa.skip_stride = skip_stride;
     const int64_t nrmax = (fa.rows + fa.blocks - 1) / fa.blocks;
     const size_t lds = (size_t)(nrmax | 1) * (n + ch) * sizeof(double);
     tsqr_formq_kernel<<<dim3((unsigned)fa.blocks, (unsigned)batch), 256, lds, s>>>(fa);
@@ -373,70 +377,81 @@ hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky factor of a small Gram matrix in one wavefront (row-oriented,
-// left-looking: row j of R needs rows 0..j-1), then R^{-1} by independent
-// back substitutions, one column per lane.  Used by CholeskyQR2.
+// Cholesky factor of a small Gram matrix in one wavefront (row-oriented:
+// row j of R needs rows 0..j-1), then R^{-1} by back substitution, one
+// column per lane, all in LDS.  Used by CholeskyQR2.
 __global__ __launch_bounds__(64) void chol_kernel(const double *g, int64_t gbs, double *r, double *rinv,
-                                                  int64_t rbs, int n, int *flag, int first) {
-  __shared__ double Rs[kCholMaxN * kCholMaxN];  // R row-major
+                                                  int64_t rbs, int n, int *flag, int64_t fstride, int first,
+                                                  double thr_rel) {
+  __shared__ double Rs[kCholMaxN * (kCholMaxN + 1)];  // R row-major, padded rows
+  __shared__ double Ri[kCholMaxN * (kCholMaxN + 1)];  // R^{-1}, column c owned by lane c
   __shared__ double dmax_s;
   __shared__ int bad_s;
+  constexpr int L = kCholMaxN + 1;
   const int lane = threadIdx.x;
   const int p = blockIdx.x;
   const double *G = g + p * gbs;
-  if (lane == 0) {
-    double m = 0.0;
-    for (int j = 0; j < n; ++j) m = fmax(m, G[j * n + j]);
-    dmax_s = m;
-    bad_s = !(m > 0.0);
+  for (int e = lane; e < n * n; e += 64) {
+    const int i = e / n, cc = e - i * n;
+    Rs[i * L + cc] = G[e];
   }
   __syncthreads();
-  const double thr = 1e-12 * dmax_s;
+  if (lane == 0) {
+    double m = 0.0;
+    for (int j = 0; j < n; ++j) m = fmax(m, Rs[j * L + j]);
+    dmax_s = m;
+    bad_s = !(m > 0.0) || !(m < 1e300);
+  }
+  __syncthreads();
+  const double thr = thr_rel * dmax_s;
+  const int c = lane;
+  // in-place factorisation of the upper triangle, row j finished at step j
   for (int j = 0; j < n; ++j) {
     double s = 0.0;
-    const int c = lane;
     if (c >= j && c < n) {
-      s = G[j * n + c];
-      for (int l = 0; l < j; ++l) s -= Rs[l * kCholMaxN + j] * Rs[l * kCholMaxN + c];
-      if (c == j) {
-        if (!(s > thr)) {
-          bad_s = 1;
-          s = fmax(s, thr) ;
-          if (!(s > 0.0)) s = 1.0;
-        }
-        Rs[j * kCholMaxN + j] = sqrt(s);
+      s = Rs[j * L + c];
+      for (int l = 0; l < j; ++l) s -= Rs[l * L + j] * Rs[l * L + c];
+    }
+    if (c == j) {
+      if (!(s > thr)) {  // also catches NaN
+        bad_s = 1;
+        s = (thr > 0.0 && thr < 1e300) ? thr : 1.0;
       }
+      Rs[j * L + j] = sqrt(s);
     }
     __syncthreads();
-    if (c > j && c < n) Rs[j * kCholMaxN + c] = s / Rs[j * kCholMaxN + j];
-    if (c < j) Rs[j * kCholMaxN + c] = 0.0;
+    if (c > j && c < n) Rs[j * L + c] = s / Rs[j * L + j];
+    if (c < j) Rs[j * L + c] = 0.0;
     __syncthreads();
   }
-  // R^{-1}: column c solves R x = e_c (upper triangular), rows c..0
-  double *ri = rinv + p * rbs;
-  double *ro = r + p * rbs;
-  if (lane < n) {
-    const int c = lane;
-    for (int i = n - 1; i > c; --i) ri[i * n + c] = 0.0;
-    double xc = 1.0 / Rs[c * kCholMaxN + c];
-    ri[c * n + c] = xc;
+  if (c < n) {
+    for (int i = n - 1; i > c; --i) Ri[i * L + c] = 0.0;
+    Ri[c * L + c] = 1.0 / Rs[c * L + c];
     for (int i = c - 1; i >= 0; --i) {
       double acc = 0.0;
-      for (int l = i + 1; l <= c; ++l) acc += Rs[i * kCholMaxN + l] * ri[l * n + c];
-      ri[i * n + c] = -acc / Rs[i * kCholMaxN + i];
+      for (int l = i + 1; l <= c; ++l) acc += Rs[i * L + l] * Ri[l * L + c];
+      Ri[i * L + c] = -acc / Rs[i * L + i];
     }
-    for (int i = 0; i < n; ++i) ro[i * n + c] = Rs[i * kCholMaxN + c];
+  }
+  __syncthreads();
+  double *ri = rinv + p * rbs;
+  double *ro = r + p * rbs;
+  for (int e = lane; e < n * n; e += 64) {
+    const int i = e / n, cc = e - (e / n) * n;
+    ri[e] = Ri[i * L + cc];
+    ro[e] = Rs[i * L + cc];
   }
   if (lane == 0) {
     const int ok = bad_s ? 0 : 1;
-    flag[p] = first ? ok : (flag[p] & ok);
+    int *f = flag + p * fstride;
+    *f = first ? ok : (*f & ok);
   }
 }
 
 hipError_t launch_chol(const double *g, int64_t gbs, double *r, double *rinv, int64_t rbs, int n, int *flag,
-                       int first, int batch, hipStream_t s) {
+                       int64_t fstride, int first, double thr_rel, int batch, hipStream_t s) {
   if (n > kCholMaxN || n < 1) return hipErrorInvalidValue;
-  chol_kernel<<<batch, 64, 0, s>>>(g, gbs, r, rinv, rbs, n, flag, first);
+  chol_kernel<<<batch, 64, 0, s>>>(g, gbs, r, rinv, rbs, n, flag, fstride, first, thr_rel);
   return hipGetLastError();
 }
 

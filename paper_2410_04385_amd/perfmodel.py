@@ -17,7 +17,9 @@ PEAK_HBM_GBS = 8000.0
 
 
 def _qr_flops(m: int, n: int) -> float:
-    """Economy Householder QR forming Q (Sec. 4): 4 m n^2 - 4 n^3 / 3."""
+    """Economy Householder QR forming Q (Sec. 4): 4 m n^2 - 4 n^3 / 3.  This
+    algorithmic count is kept whatever QR method runs (CholeskyQR2 performs
+    about 8 m n^2)."""
     k = min(m, n)
     return 4.0 * m * k * k - 4.0 * k ** 3 / 3.0
 
@@ -25,7 +27,7 @@ def _qr_flops(m: int, n: int) -> float:
 def hatt_round_flops(n: Sequence[int], r: Sequence[int], s: Sequence[int], ell: Sequence[int],
                      cap: int | None = None) -> Dict[str, float]:
     d = len(n)
-    out = {"sandwich": 0.0, "gemm_f64": 0.0, "tsqr": 0.0}
+    out = {"sandwich": 0.0, "gemm_f64": 0.0, "qr": 0.0}
     # HPCRL: W_L columns (Z U Y^T per (i, gamma)) and W_L W_R^T
     for c in range(1, d - 1):
         r0, r1, s0, s1, l0, l1 = r[c], r[c + 1], s[c], s[c + 1], ell[c], ell[c + 1]
@@ -36,19 +38,19 @@ def hatt_round_flops(n: Sequence[int], r: Sequence[int], s: Sequence[int], ell: 
         m = ell[c] * n[c]
         rs1 = r[c + 1] * s[c + 1]
         out["gemm_f64"] += 2.0 * m * ell[c + 1] * rs1 + 2.0 * ell[c + 1] * rs1 * m
-        out["tsqr"] += _qr_flops(m, ell[c + 1])
+        out["qr"] += _qr_flops(m, ell[c + 1])
         cn = c + 1
         out["sandwich"] += 2.0 * n[cn] * ell[cn] * (r[cn] * s[cn] * s[cn + 1] + r[cn + 1] * r[cn] * s[cn + 1])
     if cap is not None and d > 1:
         # TT-Rounding of the rank-l result: right-to-left QR + absorb,
         # left-to-right QR + (Q U) + (S V^T) H(B_{k+1})
         for c in range(d - 1, 0, -1):
-            out["tsqr"] += _qr_flops(n[c] * ell[c + 1], ell[c])
+            out["qr"] += _qr_flops(n[c] * ell[c + 1], ell[c])
             out["gemm_f64"] += 2.0 * ell[c - 1] * n[c - 1] * ell[c] * ell[c]
         caps = [1] + [min(cap, ell[k]) for k in range(1, d)] + [1]
         for c in range(d - 1):
             m = caps[c] * n[c]
-            out["tsqr"] += _qr_flops(m, ell[c + 1])
+            out["qr"] += _qr_flops(m, ell[c + 1])
             out["gemm_f64"] += 2.0 * m * ell[c + 1] * caps[c + 1]
             out["gemm_f64"] += 2.0 * caps[c + 1] * ell[c + 1] * n[c + 1] * ell[c + 2]
     out["total"] = sum(out.values())

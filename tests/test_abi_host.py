@@ -157,5 +157,22 @@ def test_perfmodel_matches_oracle_counts():
     b = oflops.hatt1_bonds(n, rx, ry, ell)
     assert abs(a["sandwich"] - (b["wl"] + b["update"])) < 1e-6 * a["sandwich"]
     assert abs(a["gemm_f64"] - (b["wr"] + b["xw"] + b["proj"])) < 1e-6 * a["gemm_f64"]
-    assert abs(a["tsqr"] - b["qr"]) < 1e-6 * a["tsqr"]
+    assert abs(a["qr"] - b["qr"]) < 1e-6 * a["qr"]
     assert perfmodel.chatt_paper(20, 32, 20, 20, 40) == oflops.table41(20, 32, 20, 20, 40)["hatt1"]
+
+
+def test_qr_method_switch_and_workspace():
+    """Method 0 (CholeskyQR2 + fallback) needs more workspace than method 1
+    (Householder only); other values are rejected."""
+    x = _cpu_tt([32] * 6, [1, 20, 20, 20, 20, 20, 1])
+    try:
+        api.set_qr_method("householder")
+        w1 = api.plan(x, x, 40, max_rank=30)["ws_bytes"]
+        api.set_qr_method("cholqr2")
+        w0 = api.plan(x, x, 40, max_rank=30)["ws_bytes"]
+    finally:
+        api.set_qr_method("cholqr2")
+    assert w0 > w1
+    assert _lib.lib().hatt_set_qr_method(2) == -1
+    with pytest.raises(ValueError):
+        api.set_qr_method("qr")

@@ -326,11 +326,12 @@ def test_round_rank_deficient_wide_bonds(r):
     assert tt.rel_err(got, ref) <= 1e-10
 
 
-@pytest.mark.parametrize("ell", [128, 150])
+@pytest.mark.parametrize("ell", [60, 128, 150])
 def test_hatt_rank_deficient_sketch(ell):
-    """u*u for 20 trig terms has exact rank 41 per bond; sketches of width
-    128 and 150 make every sketched matrix rank deficient and send the
-    256 x ell QR down the panelled path."""
+    """u*u for 20 trig terms has exact rank 41 per bond; sketches wider than
+    that make every sketched matrix rank deficient: width 60 exercises the
+    CholeskyQR2 rejection and Householder fallback, 128 and 150 the
+    panelled path."""
     u = wk.trig_u(5, n=256, terms=20, nfreq=10)
     ells = [1, ell, ell, 1]
     _say(f"hatt_recompress rank-deficient sketch ell={ell}")
@@ -346,3 +347,39 @@ def test_hatt_rank_deficient_sketch(ell):
     got = res.train(0)
     assert tt.ranks(got) == [1, 41, 41, 1]
     assert tt.rel_err(got, rounding.tt_round(ref, tol=1e-10)) <= 1e-9
+
+
+def test_qr_fallback_mixed_batch():
+    """One batch, two pairs of the same shape: a trig product whose sketched
+    matrices are rank deficient (width 60 > rank 41, so CholeskyQR2 rejects
+    them and Householder TSQR recomputes that pair) and a Gaussian pair of
+    full rank (CholeskyQR2 accepted).  Both must match the oracle."""
+    u = wk.trig_u(5, n=256, terms=20, nfreq=10)
+    g = wk.gaussian_tt(np.random.default_rng(3), [256, 256, 256], [1, 20, 20, 1])
+    ells = [1, 60, 60, 1]
+    _say("hatt_recompress mixed CholeskyQR2 / fallback batch ell=60")
+    X = H.TT.from_cores([u, g])
+    Y = H.TT.from_cores([u, g])
+    res = H.recompress(X, Y, ells, seed=4)
+    torch.cuda.synchronize()
+    R = philox.sketch(4, tt.modes(u), ells)
+    for b, (y, z) in enumerate([(u, u), (g, g)]):
+        assert tt.rel_err(res.train(b), ohatt.hatt(y, z, R)) <= 1e-10
+
+
+@pytest.mark.parametrize("method", ["householder", "cholqr2"])
+def test_qr_methods_agree_with_oracle(method):
+    """The spectral pair at reduced order under each QR method."""
+    y, z = wk.spectral_pair(21, 8, 32, 20, 20)
+    try:
+        H.set_qr_method(method)
+        _say(f"hatt_recompress spectral d=8 qr={method}")
+        res = H.recompress(H.TT.from_cores([y]), H.TT.from_cores([z]), 40, max_rank=30, seed=8)
+        torch.cuda.synchronize()
+    finally:
+        H.set_qr_method("cholqr2")
+    R = philox.sketch(8, tt.modes(y), plan.clamp_ell(tt.modes(y), tt.ranks(y), tt.ranks(z), 40))
+    ref = rounding.tt_round(ohatt.hatt(y, z, R), max_rank=30)
+    got = res.train(0)
+    assert tt.ranks(got) == tt.ranks(ref)
+    assert tt.rel_err(got, ref) <= 1e-10
