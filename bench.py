@@ -33,6 +33,9 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-explicit", action="store_true")
     ap.add_argument("--eager", action="store_true", help="launch kernels directly instead of replaying a HIP graph")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before timing, run one plain device copy of this many MiB (reference dispatch for "
+                         "hardware byte counters)")
     return ap.parse_args()
 
 
@@ -82,6 +85,15 @@ def main() -> int:
     ranks = torch.empty((B, d + 1), dtype=torch.int64, device="cuda")
     ws = torch.empty(p["ws_bytes"], dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
+    if args.calib_copy_mib > 0:
+        nbytes = args.calib_copy_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {nbytes} bytes done", file=sys.stderr, flush=True)
+        del src, dst
 
     def step():
         H.recompress(x, y, ell, max_rank=cap, seed=seed, workspace=ws, out=out, ranks=ranks)

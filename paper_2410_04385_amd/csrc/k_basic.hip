@@ -148,6 +148,28 @@ struct Rad3 {
   }
 };
 
+// Global -> LDS staging with U loads in flight per thread: element e of the
+// block (digits in d, advanced by the block stride) is read by src(d) and
+// stored at dst[idx(d)].
+template <int U, typename Src, typename Idx>
+__device__ __forceinline__ void stage_lds(int total, Rad3 d, double *dst, Src src, Idx idx) {
+  for (int e0 = threadIdx.x; e0 < total; e0 += 256 * U) {
+    double v[U];
+    int di[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (e0 + 256 * u < total) {
+        v[u] = src(d);
+        di[u] = idx(d);
+      }
+      d.next();
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e0 + 256 * u < total) dst[di[u]] = v[u];
+  }
+}
+
 template <bool GFAST>
 __global__ __launch_bounds__(256) void sandwich_kernel(SandwichArgs a, int GC) {
   extern __shared__ double sm[];
@@ -249,11 +271,166 @@ __global__ __launch_bounds__(256) void sandwich_kernel(SandwichArgs a, int GC) {
   }
 }
 
+// Register-blocked variant for ranks up to MAXR.  Thread (g, b') keeps the
+// b'-columns of ZR (SI x BPT) and of T_g = C_g ZR (RI x BPT) in registers;
+// rows of C_g and of YL are read from LDS as double2 words that every lane
+// working on the same g (stage 1) or every lane (stage 2) shares, so one LDS
+// instruction feeds 2 * BPT FMAs.  Rows are zero-padded to even length.
+// LANE_G: lanes run along g (outputs with g fastest), else along b'.
+template <int MAXR, int BPT, bool LANE_G>
+__global__ __launch_bounds__(256) void sandwich_reg_kernel(SandwichArgs a, int GC, int TPG) {
+  extern __shared__ double sm[];
+  const int RA = a.RA, RI = a.RI, SI = a.SI, SO = a.SO;
+  const int RIp = (RI + 1) & ~1, SIp = (SI + 1) & ~1;
+  const int cgs = RI * SIp + 2;          // per-g stride of the C chunk (padding breaks bank aliasing)
+  const int zsz = (SI * SO + 1) & ~1;
+  double *YL = sm;                       // RA x RIp
+  double *ZR = YL + RA * RIp;            // SI x SO
+  double *Cs = ZR + zsz;                 // GC x cgs
+  const int tid = threadIdx.x;
+  const int64_t i = blockIdx.x;
+  const int64_t g0 = (int64_t)blockIdx.y * GC;
+  const int p = blockIdx.z;
+  const int gc = (int)std::min<int64_t>(GC, a.G - g0);
+  if (gc <= 0) return;
+
+  const double *yl = a.yl + p * a.ylb + i * a.yli;
+  stage_lds<4>(RA * RIp, Rad3(tid, 256, RIp, RA), YL,  // digits (a, a')
+               [&](const Rad3 &d) { return (d.i0 < RI) ? yl[d.i1 * a.ylr + d.i0 * a.ylc] : 0.0; },
+               [&](const Rad3 &d) { return d.i1 * RIp + d.i0; });
+  const double *zr = a.zr + p * a.zrb + i * a.zri;
+  stage_lds<4>(SI * SO, Rad3(tid, 256, SO, SI), ZR,  // digits (b', b)
+               [&](const Rad3 &d) { return zr[d.i1 * a.zrr + d.i0 * a.zrc]; },
+               [&](const Rad3 &d) { return d.i1 * SO + d.i0; });
+  const double *cbase = a.c + p * a.cb + g0 * a.cg;
+  const int per = RI * SIp;
+  if (a.cg == 1) {
+    // g is the fastest index of C in memory: consecutive threads take consecutive g
+    stage_lds<8>(gc * per, Rad3(tid, 256, gc, SIp), Cs,  // digits (g, b, a)
+                 [&](const Rad3 &d) {
+                   return (d.i1 < SI) ? cbase[d.i0 * a.cg + d.i2 * a.ca + d.i1 * a.cbb] : 0.0;
+                 },
+                 [&](const Rad3 &d) { return d.i0 * cgs + d.i2 * SIp + d.i1; });
+  } else {
+    stage_lds<8>(gc * per, Rad3(tid, 256, SIp, RI), Cs,  // digits (b, a, g)
+                 [&](const Rad3 &d) {
+                   return (d.i0 < SI) ? cbase[d.i2 * a.cg + d.i1 * a.ca + d.i0 * a.cbb] : 0.0;
+                 },
+                 [&](const Rad3 &d) { return d.i2 * cgs + d.i1 * SIp + d.i0; });
+  }
+  __syncthreads();
+
+  int tg, tb;
+  if (LANE_G) {
+    tg = tid % GC;
+    tb = tid / GC;
+  } else {
+    tb = tid % TPG;
+    tg = tid / TPG;
+  }
+  if (tg >= gc || tb >= TPG) return;
+  const int bp0 = tb * BPT;
+
+  double zc[MAXR][BPT];
+#pragma unroll
+  for (int b = 0; b < MAXR; ++b)
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) zc[b][j] = (b < SI && bp0 + j < SO) ? ZR[b * SO + bp0 + j] : 0.0;
+
+  // stage 1: T_g(:, b') = C_g ZR(:, b')
+  double t[MAXR][BPT];
+  const double *cg = Cs + tg * cgs;
+#pragma unroll
+  for (int aa = 0; aa < MAXR; ++aa) {
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) t[aa][j] = 0.0;
+    if (aa < RI) {
+      const double *crow = cg + aa * SIp;
+#pragma unroll
+      for (int b = 0; b < MAXR; b += 2) {
+        if (b < SIp) {
+          const double2 c2 = *reinterpret_cast<const double2 *>(crow + b);
+#pragma unroll
+          for (int j = 0; j < BPT; ++j) t[aa][j] = fma(c2.x, zc[b][j], fma(c2.y, zc[b + 1][j], t[aa][j]));
+        }
+      }
+    }
+  }
+  // stage 2: out(a', b') = YL(a', :) T_g(:, b')
+  double *obase = a.o + p * a.ob + i * a.oi + (g0 + tg) * a.og;
+  for (int ap = 0; ap < RA; ++ap) {
+    const double *yrow = YL + ap * RIp;
+    double acc[BPT];
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) acc[j] = 0.0;
+#pragma unroll
+    for (int aa = 0; aa < MAXR; aa += 2) {
+      if (aa < RIp) {
+        const double2 y2 = *reinterpret_cast<const double2 *>(yrow + aa);
+#pragma unroll
+        for (int j = 0; j < BPT; ++j) acc[j] = fma(y2.x, t[aa][j], fma(y2.y, t[aa + 1][j], acc[j]));
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < BPT; ++j)
+      if (bp0 + j < SO) obase[ap * a.oa + (bp0 + j) * a.obb] = acc[j];
+  }
+}
+
+namespace {
+template <int MAXR, int BPT, bool LG>
+hipError_t sandwich_reg_launch(const SandwichArgs &a, hipStream_t s, int64_t budget) {
+  const int RIp = (a.RI + 1) & ~1, SIp = (a.SI + 1) & ~1;
+  const int64_t cgs = (int64_t)a.RI * SIp + 2;
+  const int64_t fixed = (int64_t)a.RA * RIp + (((int64_t)a.SI * a.SO + 1) & ~1);
+  const int TPG = (a.SO + BPT - 1) / BPT;
+  int64_t gmax = std::min<int64_t>(256 / TPG, (budget - fixed) / cgs);
+  if (gmax < 1) return hipErrorInvalidValue;
+  const int64_t chunks = (a.G + gmax - 1) / gmax;
+  const int64_t GC = (a.G + chunks - 1) / chunks;
+  const size_t lds = (size_t)(fixed + GC * cgs) * sizeof(double);
+  static bool attr_done = false;
+  if (!attr_done) {
+    hipFuncSetAttribute((const void *)sandwich_reg_kernel<MAXR, BPT, LG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)(budget * sizeof(double)));
+    attr_done = true;
+  }
+  dim3 grid((unsigned)a.n, (unsigned)chunks, (unsigned)a.batch);
+  sandwich_reg_kernel<MAXR, BPT, LG><<<grid, 256, lds, s>>>(a, (int)GC, TPG);
+  return hipGetLastError();
+}
+
+template <bool LG>
+hipError_t sandwich_reg_dispatch(const SandwichArgs &a, hipStream_t s, int64_t budget, bool *done) {
+  const int m = std::max(std::max(a.RI, a.SI), 1);
+  *done = (a.SO <= 256);  // one g's threads must fit a block
+  if (!*done) return hipSuccess;
+  if (m <= 16) return sandwich_reg_launch<16, 2, LG>(a, s, budget);
+  if (m <= 24) return sandwich_reg_launch<24, 2, LG>(a, s, budget);
+  if (m <= 32) return sandwich_reg_launch<32, 1, LG>(a, s, budget);
+  if (m <= 48) return sandwich_reg_launch<48, 1, LG>(a, s, budget);
+  *done = false;
+  return hipSuccess;
+}
+}  // namespace
+
+bool g_sandwich_reg = true;
+
 hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s) {
   if (a.n <= 0 || a.G <= 0 || a.batch <= 0) return hipSuccess;
+  const int64_t budget = 19456;  // doubles of dynamic LDS
+  if (g_sandwich_reg) {
+    const int RIp = (a.RI + 1) & ~1, SIp = (a.SI + 1) & ~1;
+    const int64_t fixed = (int64_t)a.RA * RIp + (((int64_t)a.SI * a.SO + 1) & ~1);
+    if (fixed + (int64_t)a.RI * SIp + 2 <= budget) {
+      bool done = false;
+      hipError_t e = (a.og == 1) ? sandwich_reg_dispatch<true>(a, s, budget, &done)
+                                 : sandwich_reg_dispatch<false>(a, s, budget, &done);
+      if (done) return e;
+    }
+  }
   const int64_t fixed = (int64_t)a.RA * a.RI + (int64_t)a.SI * a.SO;
   const int64_t perg = (int64_t)a.RI * a.SI + (int64_t)a.RI * a.SO;
-  const int64_t budget = 19456;  // doubles of dynamic LDS
   int64_t gc = std::min<int64_t>(8, (budget - fixed) / perg);
   if (gc < 1) return hipErrorInvalidValue;
   gc = std::min<int64_t>(gc, a.G);

@@ -2,7 +2,7 @@
 // (v_mfma_f64_16x16x4_f64), with an optional deterministic split-K.
 //
 // Tile: 64 x 64 (or 64 x 32, 32 x 64, 32 x 32 for thin operands) outputs per
-// 256-thread workgroup, K staged through LDS in slabs of 16.  Each of the 4
+// 256-thread workgroup, K staged through LDS in slabs of 32.  Each of the 4
 // waves owns a quadrant made of 16 x 16 MFMA blocks; one MFMA consumes a 16 x 4 slice of A and a 4 x 16 slice
 // of B, one double per lane each (lane l holds A(l%16, l/16) and
 // B(l/16, l%16)); its 16 x 16 result sits 4 doubles per lane, lane l holding
@@ -16,10 +16,11 @@ namespace hatt {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-constexpr int BK = 16;
+constexpr int BK = 32;
 
 // BM x BN output tile, 4 waves in a 2 x 2 grid, each wave (BM/2) x (BN/2) as
-// (BM/32) x (BN/32) MFMA blocks of 16 x 16.
+// (BM/32) x (BN/32) MFMA blocks of 16 x 16.  The next K slab is fetched into
+// registers while the MFMAs consume the current one from LDS.
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
   constexpr int LDA_S = BM + 1, LDB_S = BN + 1;
@@ -43,36 +44,100 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
   const bool a_kfast = (g.A.cs == 1);
   const bool b_nfast = (g.B.cs == 1) || (g.B.rs != 1);
 
+  // Per-thread load slots t = 0..PER-1 are element tid + 256 t of the slab
+  // tile; along the unit-stride dimension they share one index, so each
+  // operand needs one base pointer and one per-slot stride.
+  const int64_t rem0 = kend - kbeg;
+  const double *abase, *bbase;
+  int64_t astep, bstep;  // pointer distance between slots t and t + 1
+  int a_lds0, a_ldsd, b_lds0, b_ldsd;
+  int a_fix, a_var0, a_vard, a_lim, b_fix, b_var0, b_vard, b_lim;  // bound checks, see fetch
+  if (a_kfast) {
+    const int kk = tid % BK, mm = tid / BK;
+    abase = Ab + (m0 + mm) * g.A.rs + (kbeg + kk) * g.A.cs;
+    astep = (256 / BK) * g.A.rs;
+    a_lds0 = kk * LDA_S + mm;
+    a_ldsd = 256 / BK;
+    a_fix = kk;                      // k index: fixed, checked against the slab's remaining K
+    a_var0 = (int)std::min<int64_t>(m0 + mm, 1 << 30);
+    a_vard = 256 / BK;               // m index grows with t
+    a_lim = (int)std::min<int64_t>(g.M, 1 << 30);
+  } else {
+    const int mm = tid % BM, kk = tid / BM;
+    abase = Ab + (m0 + mm) * g.A.rs + (kbeg + kk) * g.A.cs;
+    astep = (256 / BM) * g.A.cs;
+    a_lds0 = kk * LDA_S + mm;
+    a_ldsd = (256 / BM) * LDA_S;
+    a_fix = (m0 + mm < g.M) ? -1 : (1 << 30);  // -1: the m index is inside
+    a_var0 = kk;
+    a_vard = 256 / BM;               // k index grows with t
+    a_lim = 0;
+  }
+  if (b_nfast) {
+    const int nn = tid % BN, kk = tid / BN;
+    bbase = Bb + (kbeg + kk) * g.B.rs + (n0 + nn) * g.B.cs;
+    bstep = (256 / BN) * g.B.rs;
+    b_lds0 = kk * LDB_S + nn;
+    b_ldsd = (256 / BN) * LDB_S;
+    b_fix = (n0 + nn < g.N) ? -1 : (1 << 30);
+    b_var0 = kk;
+    b_vard = 256 / BN;
+    b_lim = 0;
+  } else {
+    const int kk = tid % BK, nn = tid / BK;
+    bbase = Bb + (kbeg + kk) * g.B.rs + (n0 + nn) * g.B.cs;
+    bstep = (256 / BK) * g.B.cs;
+    b_lds0 = kk * LDB_S + nn;
+    b_ldsd = 256 / BK;
+    b_fix = kk;
+    b_var0 = (int)std::min<int64_t>(n0 + nn, 1 << 30);
+    b_vard = 256 / BK;
+    b_lim = (int)std::min<int64_t>(g.N, 1 << 30);
+  }
+  (void)rem0;
+  const int64_t a_kstep = BK * g.A.cs, b_kstep = BK * g.B.rs;
+  double ra[A_PER], rb[B_PER];
+  // slot t is in range when: k-fast layout: fixed k < rem and m (n) < limit;
+  // m-fast (n-fast) layout: the fixed m (n) is inside and k < rem.
+  auto fetch = [&](int64_t k0, int64_t slab) {
+    const int rem = (int)std::min<int64_t>(kend - k0, 1 << 30);
+    const double *pa = abase + slab * a_kstep;
+    const double *pb = bbase + slab * b_kstep;
+#pragma unroll
+    for (int t = 0; t < A_PER; ++t) {
+      const int v = a_var0 + t * a_vard;
+      const bool ok = a_kfast ? (a_fix < rem && v < a_lim) : (a_fix < 0 && v < rem);
+      ra[t] = ok ? pa[t * astep] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < B_PER; ++t) {
+      const int v = b_var0 + t * b_vard;
+      const bool ok = b_nfast ? (b_fix < 0 && v < rem) : (b_fix < rem && v < b_lim);
+      rb[t] = ok ? pb[t * bstep] : 0.0;
+    }
+  };
+  auto park = [&]() {
+#pragma unroll
+    for (int t = 0; t < A_PER; ++t) As[a_lds0 + t * a_ldsd] = ra[t];
+#pragma unroll
+    for (int t = 0; t < B_PER; ++t) Bs[b_lds0 + t * b_ldsd] = rb[t];
+  };
+
   d4_t acc[MI][NJ];
 #pragma unroll
   for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
 
-  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-#pragma unroll
-    for (int t = 0; t < A_PER; ++t) {
-      const int e = tid + 256 * t;
-      int mm, kk;
-      if (a_kfast) { kk = e % BK; mm = e / BK; }
-      else { mm = e % BM; kk = e / BM; }
-      const int64_t gm = m0 + mm, gk = k0 + kk;
-      double v = 0.0;
-      if (gm < g.M && gk < kend) v = Ab[gm * g.A.rs + gk * g.A.cs];
-      As[kk * LDA_S + mm] = v;
-    }
-#pragma unroll
-    for (int t = 0; t < B_PER; ++t) {
-      const int e = tid + 256 * t;
-      int nn, kk;
-      if (b_nfast) { nn = e % BN; kk = e / BN; }
-      else { kk = e % BK; nn = e / BK; }
-      const int64_t gn = n0 + nn, gk = k0 + kk;
-      double v = 0.0;
-      if (gn < g.N && gk < kend) v = Bb[gk * g.B.rs + gn * g.B.cs];
-      Bs[kk * LDB_S + nn] = v;
-    }
-    __syncthreads();
+  if (kbeg < kend) {
+    fetch(kbeg, 0);
+    park();
+  }
+  __syncthreads();
+  int64_t slab = 0;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK, ++slab) {
+    const bool more = k0 + BK < kend;
+    if (more) fetch(k0 + BK, slab + 1);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4), c16 = lane & 15;
@@ -88,6 +153,10 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
+    if (more) {
+      park();
+      __syncthreads();
+    }
   }
 
   const int rq = lane >> 4, cq = lane & 15;
@@ -151,8 +220,8 @@ int gemm_pick_ksplit(int64_t M, int64_t N, int64_t K, int batch) {
   gemm_tile(M, N, &bm, &bn);
   const int64_t tiles = ((M + bm - 1) / bm) * ((N + bn - 1) / bn) * (int64_t)batch;
   int ks = 1;
-  // aim for ~2 workgroups per CU while keeping >= 4 K slabs per chunk
-  while (tiles * ks < 512 && K / ((int64_t)(ks * 2) * BK) >= 4 && ks < 64) ks *= 2;
+  // aim for ~8 workgroups per CU (latency hiding) while keeping >= 4 K slabs per chunk
+  while (tiles * ks < 2048 && K / ((int64_t)(ks * 2) * BK) >= 4 && ks < 64) ks *= 2;
   return ks;
 }
 
