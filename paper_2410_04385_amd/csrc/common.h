@@ -95,12 +95,14 @@ struct GemmArgs {
   int batch;
   int ksplit;
   double *part;
+  int no_reduce;        // split-K: leave the partial products in `part` (the caller reduces them)
   const int *run_flag;  // optional: pair p is computed only when run_flag[p * run_flag_stride] == run_when
   int64_t run_flag_stride;
   int run_when;
 };
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
 int gemm_pick_ksplit(int64_t M, int64_t N, int64_t K, int batch);
+// Layout of the split-K partials: pair p, chunk t at part + (p * ksplit + t) * M * N.
 
 // ---- TSQR (k_qr.hip) -------------------------------------------------------
 // Economy Householder QR of an m x n matrix per pair, by a tree of block
@@ -121,13 +123,16 @@ bool qr_make_plan(int64_t m, int64_t n, QrPlan *p);
 hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_t ws_pair_stride,
                        int batch, hipStream_t s, const int *skip_flag = nullptr, int64_t skip_stride = 0);
 
-// Cholesky factor of a Gram matrix G (n x n, n <= 64, row-major, pair stride
-// gbs): R (upper, diag > 0) and R^{-1}, both n x n row-major with pair stride
-// rbs.  flag[p * fstride] is set to ok when first != 0, else and-ed with ok;
-// ok means every pivot exceeded thr_rel times the largest diagonal entry of G.
+// Cholesky factor of a Gram matrix G (n x n, n <= 64, row-major): R (upper,
+// diag > 0) and R^{-1}, both n x n row-major with pair stride rbs.  G of pair
+// p is the sum over t < ks of g[p * gbs + t * kstride + (i n + j)] (split-K
+// partials summed in order; ks = 1 for a plain G).  flag[p * fstride] is set to
+// ok when first != 0, else and-ed with ok; ok means every pivot exceeded
+// thr_rel times the largest diagonal entry of G.
 constexpr int kCholMaxN = 64;
-hipError_t launch_chol(const double *g, int64_t gbs, double *r, double *rinv, int64_t rbs, int n, int *flag,
-                       int64_t fstride, int first, double thr_rel, int batch, hipStream_t s);
+hipError_t launch_chol(const double *g, int64_t gbs, int ks, int64_t kstride, double *r, double *rinv,
+                       int64_t rbs, int n, int *flag, int64_t fstride, int first, double thr_rel, int batch,
+                       hipStream_t s);
 
 // ---- Jacobi SVD + rank choice (k_svd.hip) ----------------------------------
 // For each pair: R (kr x nc, row-major, kr <= nc <= kSvdMaxN) = U S V^T by

@@ -203,8 +203,9 @@ struct GemmCtx {
 
 hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_t N, int64_t K,
                  double alpha, double beta, int batch, hipStream_t st, bool allow_split,
-                 const int *run_flag = nullptr, int64_t run_flag_stride = 0) {
+                 const int *run_flag = nullptr, int64_t run_flag_stride = 0, int *ks_out = nullptr) {
   GemmArgs g{};
+  g.no_reduce = (ks_out != nullptr);
   g.run_flag = run_flag;
   g.run_flag_stride = run_flag_stride;
   g.run_when = 1;
@@ -222,6 +223,7 @@ hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_
   gc.part_need = std::max(gc.part_need, need);
   if (g.ksplit > 1 && need > gc.part_cap) g.ksplit = 1;
   g.part = gc.part;
+  if (ks_out != nullptr) *ks_out = g.ksplit;
   if (g_prof.on) {
     char b[96];
     snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=%d%s", (long long)M, (long long)N, (long long)K, g.ksplit,
@@ -318,16 +320,20 @@ hatt_status cholqr2_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double 
   const int64_t fst = 2 * wsp;  // flag stride in ints
   CMat At{A.ptr, A.cs, A.rs, A.bs};
   CMat q1c{q1, n, 1, wsp}, q1t{q1, 1, n, wsp};
-  hatt_status sg = gemm(run, gc, At, A, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true);
+  // G = A^T A: with a K split the Cholesky kernel sums the partials itself
+  int ks = 1;
+  hatt_status sg = gemm(run, gc, At, A, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true, nullptr, 0, &ks);
   if (sg != HATT_OK) return sg;
   site("chol %lld", (long long)n);
-  LAUNCH(launch_chol(g, wsp, r1, r1i, wsp, (int)n, flag, fst, 1, kCholThr1, P, st));
+  if (ks > 1) LAUNCH(launch_chol(gc.part, ks * n * n, ks, n * n, r1, r1i, wsp, (int)n, flag, fst, 1, kCholThr1, P, st));
+  else LAUNCH(launch_chol(g, wsp, 1, 0, r1, r1i, wsp, (int)n, flag, fst, 1, kCholThr1, P, st));
   sg = gemm(run, gc, A, CMat{r1i, n, 1, wsp}, Mat{q1, n, 1, wsp}, m, n, n, 1.0, 0.0, P, st, false);
   if (sg != HATT_OK) return sg;
-  sg = gemm(run, gc, q1t, q1c, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true);
+  sg = gemm(run, gc, q1t, q1c, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true, nullptr, 0, &ks);
   if (sg != HATT_OK) return sg;
   site("chol %lld", (long long)n);
-  LAUNCH(launch_chol(g, wsp, r2, r2i, wsp, (int)n, flag, fst, 0, kCholThr2, P, st));
+  if (ks > 1) LAUNCH(launch_chol(gc.part, ks * n * n, ks, n * n, r2, r2i, wsp, (int)n, flag, fst, 0, kCholThr2, P, st));
+  else LAUNCH(launch_chol(g, wsp, 1, 0, r2, r2i, wsp, (int)n, flag, fst, 0, kCholThr2, P, st));
   sg = gemm(run, gc, q1c, CMat{r2i, n, 1, wsp}, Q, m, n, n, 1.0, 0.0, P, st, false, flag, fst);
   if (sg != HATT_OK) return sg;
   if (R.ptr) {

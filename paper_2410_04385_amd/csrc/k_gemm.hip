@@ -239,7 +239,7 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
   else if (bn == 64) gemm_f64_kernel<32, 64><<<grid, 256, 0, s>>>(a);
   else gemm_f64_kernel<32, 32><<<grid, 256, 0, s>>>(a);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || a.ksplit == 1) return e;
+  if (e != hipSuccess || a.ksplit == 1 || a.no_reduce) return e;
   const int64_t total = a.M * a.N * a.batch;
   int rg = (int)std::min<int64_t>((total + 255) / 256, 65536);
   splitk_reduce_kernel<<<rg, 256, 0, s>>>(a);

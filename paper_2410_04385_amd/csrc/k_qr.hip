@@ -377,81 +377,122 @@ hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky factor of a small Gram matrix in one wavefront (row-oriented:
-// row j of R needs rows 0..j-1), then R^{-1} by back substitution, one
-// column per lane, all in LDS.  Used by CholeskyQR2.
-__global__ __launch_bounds__(64) void chol_kernel(const double *g, int64_t gbs, double *r, double *rinv,
-                                                  int64_t rbs, int n, int *flag, int64_t fstride, int first,
-                                                  double thr_rel) {
-  __shared__ double Rs[kCholMaxN * (kCholMaxN + 1)];  // R row-major, padded rows
-  __shared__ double Ri[kCholMaxN * (kCholMaxN + 1)];  // R^{-1}, column c owned by lane c
+// Cholesky factor R (G = R^T R) and R^{-1} of a small Gram matrix, from one
+// symmetric Gaussian elimination of the augmented block [G | I]: after step j
+// the upper triangle of the left half holds D L^T (G = L D L^T, L unit lower)
+// and the right half holds L^{-1}; then R = D^{1/2} L^T and
+// R^{-1} = L^{-T} D^{-1/2}.  Only the upper triangle of the left half is
+// updated (the trailing block stays symmetric, so the multiplier of row i at
+// step j is read from row j).  G is read as the in-order sum of ks split-K
+// partial products (ks = 1: G itself), the same order a split-K reduction
+// uses.  One 256-thread block per pair; W has n rows of 2n + 1 doubles.
+__global__ __launch_bounds__(256) void chol_kernel(const double *g, int64_t gbs, int ks, int64_t kstride,
+                                                   double *r, double *rinv, int64_t rbs, int n, int *flag,
+                                                   int64_t fstride, int first, double thr_rel) {
+  extern __shared__ double W[];
+  __shared__ double piv[kCholMaxN];
   __shared__ double dmax_s;
-  __shared__ int bad_s;
-  constexpr int L = kCholMaxN + 1;
-  const int lane = threadIdx.x;
+  const int ld = 2 * n + 1;
+  const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
   const int p = blockIdx.x;
   const double *G = g + p * gbs;
-  for (int e = lane; e < n * n; e += 64) {
-    const int i = e / n, cc = e - i * n;
-    Rs[i * L + cc] = G[e];
-  }
-  __syncthreads();
-  if (lane == 0) {
-    double m = 0.0;
-    for (int j = 0; j < n; ++j) m = fmax(m, Rs[j * L + j]);
-    dmax_s = m;
-    bad_s = !(m > 0.0) || !(m < 1e300);
-  }
-  __syncthreads();
-  const double thr = thr_rel * dmax_s;
-  const int c = lane;
-  // in-place factorisation of the upper triangle, row j finished at step j
-  for (int j = 0; j < n; ++j) {
-    double s = 0.0;
-    if (c >= j && c < n) {
-      s = Rs[j * L + c];
-      for (int l = 0; l < j; ++l) s -= Rs[l * L + j] * Rs[l * L + c];
-    }
-    if (c == j) {
-      if (!(s > thr)) {  // also catches NaN
-        bad_s = 1;
-        s = (thr > 0.0 && thr < 1e300) ? thr : 1.0;
+  for (int i = ty; i < n; i += 4) {
+    for (int c = tx; c < n; c += 64) {
+      // partials fetched 8 at a time, summed in chunk order
+      double v = 0.0;
+      for (int t0 = 0; t0 < ks; t0 += 8) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = (t0 + u < ks) ? G[(t0 + u) * kstride + i * n + c] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (t0 + u < ks) v += x[u];
       }
-      Rs[j * L + j] = sqrt(s);
-    }
-    __syncthreads();
-    if (c > j && c < n) Rs[j * L + c] = s / Rs[j * L + j];
-    if (c < j) Rs[j * L + c] = 0.0;
-    __syncthreads();
-  }
-  if (c < n) {
-    for (int i = n - 1; i > c; --i) Ri[i * L + c] = 0.0;
-    Ri[c * L + c] = 1.0 / Rs[c * L + c];
-    for (int i = c - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int l = i + 1; l <= c; ++l) acc += Rs[i * L + l] * Ri[l * L + c];
-      Ri[i * L + c] = -acc / Rs[i * L + i];
+      W[i * ld + c] = v;
+      W[i * ld + n + c] = (i == c) ? 1.0 : 0.0;
     }
   }
   __syncthreads();
-  double *ri = rinv + p * rbs;
-  double *ro = r + p * rbs;
-  for (int e = lane; e < n * n; e += 64) {
-    const int i = e / n, cc = e - (e / n) * n;
-    ri[e] = Ri[i * L + cc];
-    ro[e] = Rs[i * L + cc];
+  if (tid == 0) {
+    double m = 0.0;
+    for (int j = 0; j < n; ++j) m = fmax(m, W[j * ld + j]);
+    dmax_s = m;
   }
-  if (lane == 0) {
-    const int ok = bad_s ? 0 : 1;
+  __syncthreads();
+  const double dmax = dmax_s;
+  const bool dmax_ok = (dmax > 0.0) && (dmax < 1e300);
+  const double thr = thr_rel * dmax;
+  int bad = dmax_ok ? 0 : 1;
+  for (int j = 0; j < n; ++j) {
+    double d = W[j * ld + j];
+    if (!(d > thr)) {  // also catches NaN; every thread takes the same decision
+      bad = 1;
+      d = (thr > 0.0 && thr < 1e300) ? thr : 1.0;
+    }
+    if (tid == 0) piv[j] = d;
+    const double inv = 1.0 / d;
+    const double *wj = W + j * ld;
+    // this thread's rows i = j + 1 + ty + 4k: multipliers W(j, i) in registers
+    constexpr int KMAX = kCholMaxN / 4;
+    double mul[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const int i = j + 1 + ty + 4 * k;
+      mul[k] = (i < n) ? wj[i] : 0.0;
+    }
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+      const int c = tx + 64 * cc;
+      if (c >= 2 * n) continue;
+      const bool left = c < n;
+      if (left ? (c <= j) : (c > n + j)) continue;
+      const double wjc = wj[c] * inv;
+      // rows i in (j, n); left-half entries only on or above the diagonal
+      const int ilim = left ? min(c, n - 1) : n - 1;
+      double x[KMAX];
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        const int i = j + 1 + ty + 4 * k;
+        x[k] = (i <= ilim) ? W[i * ld + c] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        const int i = j + 1 + ty + 4 * k;
+        if (i <= ilim) W[i * ld + c] = x[k] - mul[k] * wjc;
+      }
+    }
+    __syncthreads();
+  }
+  double *ro = r + p * rbs;
+  double *ri = rinv + p * rbs;
+  for (int i = ty; i < n; i += 4) {
+    const double si = sqrt(piv[i]);
+    for (int c = tx; c < n; c += 64) {
+      // R(i, c) = U(i, c) / sqrt(d_i) above the diagonal, sqrt(d_i) on it
+      ro[i * n + c] = (c > i) ? W[i * ld + c] / si : ((c == i) ? si : 0.0);
+      // R^{-1}(i, c) = L^{-1}(c, i) / sqrt(d_c), zero below the diagonal
+      ri[i * n + c] = (c >= i) ? W[c * ld + n + i] / sqrt(piv[c]) : 0.0;
+    }
+  }
+  if (tid == 0) {
+    const int ok = bad ? 0 : 1;
     int *f = flag + p * fstride;
     *f = first ? ok : (*f & ok);
   }
 }
 
-hipError_t launch_chol(const double *g, int64_t gbs, double *r, double *rinv, int64_t rbs, int n, int *flag,
-                       int64_t fstride, int first, double thr_rel, int batch, hipStream_t s) {
-  if (n > kCholMaxN || n < 1) return hipErrorInvalidValue;
-  chol_kernel<<<batch, 64, 0, s>>>(g, gbs, r, rinv, rbs, n, flag, fstride, first, thr_rel);
+hipError_t launch_chol(const double *g, int64_t gbs, int ks, int64_t kstride, double *r, double *rinv,
+                       int64_t rbs, int n, int *flag, int64_t fstride, int first, double thr_rel, int batch,
+                       hipStream_t s) {
+  if (n > kCholMaxN || n < 1 || ks < 1) return hipErrorInvalidValue;
+  const size_t lds = (size_t)n * (2 * n + 1) * sizeof(double);
+  static bool attr_done = false;
+  if (!attr_done) {
+    hipFuncSetAttribute((const void *)chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)(kCholMaxN * (2 * kCholMaxN + 1) * sizeof(double)));
+    attr_done = true;
+  }
+  chol_kernel<<<batch, 256, lds, s>>>(g, gbs, ks, kstride, r, rinv, rbs, n, flag, fstride, first, thr_rel);
   return hipGetLastError();
 }
 

@@ -13,8 +13,9 @@
 // nc' - 1 rounds (nc' = nc rounded up to even) of nc'/2 disjoint pairs.  A
 // pair is rotated when |a_p . a_q| > 1e-15 ||a_p|| ||a_q||; sweeps stop when
 // none is.
-//   * nc <= 64: one wavefront per matrix, lane c keeps column c in registers
-//     and fetches its round partner through LDS; no block barriers.
+//   * nc <= 64: one 256-thread workgroup per matrix, lane c of each of the
+//     four waves keeps a quarter of column c in registers; partners are read
+//     through LDS and the dot products are reduced over the waves.
 //   * larger nc: one 256-thread workgroup per matrix, A in LDS, each pair
 //     handled by a group of lanes that reduce with shuffles.
 #include "common.h"
@@ -68,38 +69,63 @@ __device__ int choose_rank(const double *sig_sorted, int kr, int nc, const SvdAr
   return rho;
 }
 
-template <int KR>
-__global__ __launch_bounds__(64) void svd_wave_kernel(SvdArgs a) {
-  __shared__ double xch[KR * 64];  // xch[r * 64 + c]: lanes touch consecutive words
+// nc <= 64: four wavefronts per matrix.  Lane c of every wave holds column c;
+// wave w holds rows w*KR4 .. w*KR4 + KR4 - 1 of it in registers.  A round
+// publishes the rows through LDS (double-buffered by round parity), each wave
+// forms partial dot products with the partner column, and the partials are
+// summed over the waves in a fixed order, so both lanes of a pair, in every
+// wave, derive bit-identical rotations.
+template <int KR4>
+__global__ __launch_bounds__(256) void svd_quad_kernel(SvdArgs a) {
+  extern __shared__ double sm[];
+  constexpr int ROWS = 4 * KR4;
+  double *xb0 = sm;                   // ROWS x 64, xb[r * 64 + c]
+  double *xb1 = sm + ROWS * 64;
+  double *part = sm + 2 * ROWS * 64;  // part[(w * 3 + k) * 64 + c]
   __shared__ double sig[64];
   __shared__ double sigs[64];
   __shared__ int perm[64];
   __shared__ int s_rho;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int p = blockIdx.x;
   const int kr = a.kr, nc = a.nc;
   const double *R = a.r + p * a.rbs;
-  double col[KR];
+  const int r0 = w * KR4;
+  double col[KR4];
 #pragma unroll
-  for (int r = 0; r < KR; ++r) col[r] = (lane < nc && r < kr) ? R[r * nc + lane] : 0.0;
+  for (int i = 0; i < KR4; ++i) col[i] = (lane < nc && r0 + i < kr) ? R[(r0 + i) * nc + lane] : 0.0;
   const int np = nc + (nc & 1);
+  int buf = 0;
   for (int sweep = 0; sweep < 60; ++sweep) {
     int rot = 0;
     for (int t = 0; t < np - 1; ++t) {
+      double *xb = buf ? xb1 : xb0;
+      buf ^= 1;
 #pragma unroll
-      for (int r = 0; r < KR; ++r) xch[r * 64 + lane] = col[r];
+      for (int i = 0; i < KR4; ++i) xb[(r0 + i) * 64 + lane] = col[i];
       __syncthreads();
       const int q = rr_partner(lane, t, np);
-      if (lane < nc && q < nc) {
-        const double *pc = xch + q;
-        double al = 0.0, be = 0.0, ga = 0.0;
+      const bool act = lane < nc && q < nc;
+      double y[KR4];
+      double al = 0.0, be = 0.0, ga = 0.0;
+      if (act) {
+        const double *pc = xb + r0 * 64 + q;
 #pragma unroll
-        for (int r = 0; r < KR; ++r) {
-          const double x = col[r], y = pc[r * 64];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
+        for (int i = 0; i < KR4; ++i) {
+          y[i] = pc[i * 64];
+          al += col[i] * col[i];
+          be += y[i] * y[i];
+          ga += col[i] * y[i];
         }
+      }
+      part[(w * 3 + 0) * 64 + lane] = al;
+      part[(w * 3 + 1) * 64 + lane] = be;
+      part[(w * 3 + 2) * 64 + lane] = ga;
+      __syncthreads();
+      if (act) {
+        al = ((part[0 * 64 + lane] + part[3 * 64 + lane]) + part[6 * 64 + lane]) + part[9 * 64 + lane];
+        be = ((part[1 * 64 + lane] + part[4 * 64 + lane]) + part[7 * 64 + lane]) + part[10 * 64 + lane];
+        ga = ((part[2 * 64 + lane] + part[5 * 64 + lane]) + part[8 * 64 + lane]) + part[11 * 64 + lane];
         // roles: the lower index is "p"
         const bool isp = lane < q;
         const double ap = isp ? al : be, aq = isp ? be : al;
@@ -109,26 +135,32 @@ __global__ __launch_bounds__(64) void svd_wave_kernel(SvdArgs a) {
           const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
           if (isp) {
 #pragma unroll
-            for (int r = 0; r < KR; ++r) col[r] = cs * col[r] - sn * pc[r * 64];
+            for (int i = 0; i < KR4; ++i) col[i] = cs * col[i] - sn * y[i];
           } else {
 #pragma unroll
-            for (int r = 0; r < KR; ++r) col[r] = sn * pc[r * 64] + cs * col[r];
+            for (int i = 0; i < KR4; ++i) col[i] = sn * y[i] + cs * col[i];
           }
           rot = 1;
         }
       }
-      __syncthreads();
     }
-    if (!__any(rot)) break;
+    if (!__syncthreads_or(rot)) break;
   }
+  // column norms (partials summed in wave order), final columns to xb0, R to xb1
   double s2 = 0.0;
 #pragma unroll
-  for (int r = 0; r < KR; ++r) s2 += col[r] * col[r];
-  sig[lane] = (lane < nc) ? sqrt(s2) : -1.0;
+  for (int i = 0; i < KR4; ++i) s2 += col[i] * col[i];
+  part[w * 64 + lane] = s2;
 #pragma unroll
-  for (int r = 0; r < KR; ++r) xch[r * 64 + lane] = col[r];
+  for (int i = 0; i < KR4; ++i) xb0[(r0 + i) * 64 + lane] = col[i];
+  for (int e = tid; e < kr * nc; e += 256) xb1[e] = R[e];
   __syncthreads();
-  if (lane < nc) {
+  if (w == 0) {
+    const double t2 = ((part[lane] + part[64 + lane]) + part[128 + lane]) + part[192 + lane];
+    sig[lane] = (lane < nc) ? sqrt(t2) : -1.0;
+  }
+  __syncthreads();
+  if (w == 0 && lane < nc) {
     int rk = 0;
     const double sc = sig[lane];
     for (int j = 0; j < nc; ++j) rk += (sig[j] > sc) || (sig[j] == sc && j < lane);
@@ -136,38 +168,49 @@ __global__ __launch_bounds__(64) void svd_wave_kernel(SvdArgs a) {
     sigs[rk] = sc;
   }
   __syncthreads();
-  if (lane == 0) s_rho = choose_rank(sigs, kr, nc, a, p);
+  if (tid == 0) s_rho = choose_rank(sigs, kr, nc, a, p);
   __syncthreads();
   const int rho = s_rho;
   double *U = a.u + p * a.ubs;
-  for (int e = lane; e < kr * a.ucap; e += 64) {
+  for (int e = tid; e < kr * a.ucap; e += 256) {
     const int r = e / a.ucap, j = e - r * a.ucap;
     double v = 0.0;
     if (j < rho) {
-      const int c = perm[j];
       const double sc = sigs[j];
-      v = (sc > 0.0) ? xch[r * 64 + c] / sc : 0.0;
+      v = (sc > 0.0) ? xb0[r * 64 + perm[j]] / sc : 0.0;
     }
     U[e] = v;
   }
-  // S V^T rows = U_rho^T R: lane owns column c of R
+  // S V^T rows = U_rho^T R
   double *S = a.svt + p * a.sbs;
-  for (int c = lane; c < nc; c += 64) {
-    for (int j = 0; j < a.ucap; ++j) {
-      double v = 0.0;
-      if (j < rho) {
+  for (int e = tid; e < a.ucap * nc; e += 256) {
+    const int j = e / nc, c = e - j * nc;
+    double v = 0.0;
+    if (j < rho) {
+      const double sc = sigs[j];
+      if (sc > 0.0) {
         const int cj = perm[j];
-        const double sc = sigs[j];
-        if (sc > 0.0) {
-          const double inv = 1.0 / sc;
-          for (int r = 0; r < kr; ++r) v += xch[r * 64 + cj] * R[r * nc + c];
-          v *= inv;
-        }
+        for (int r = 0; r < kr; ++r) v += xb0[r * 64 + cj] * xb1[r * nc + c];
+        v *= 1.0 / sc;
       }
-      S[j * nc + c] = v;
     }
+    S[e] = v;
   }
 }
+
+namespace {
+template <int KR4>
+hipError_t svd_quad_launch(const SvdArgs &a, hipStream_t s) {
+  const size_t lds = (size_t)(2 * 4 * KR4 * 64 + 12 * 64) * sizeof(double);
+  static bool attr_done = false;
+  if (!attr_done) {
+    hipFuncSetAttribute((const void *)svd_quad_kernel<KR4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr_done = true;
+  }
+  svd_quad_kernel<KR4><<<a.batch, 256, lds, s>>>(a);
+  return hipGetLastError();
+}
+}  // namespace
 
 __global__ __launch_bounds__(256) void svd_block_kernel(SvdArgs a, int tpg) {
   extern __shared__ double A[];  // A[c * kr + r]
@@ -280,11 +323,11 @@ hipError_t launch_svd_trunc(const SvdArgs &a, hipStream_t s) {
   if (a.batch <= 0) return hipSuccess;
   if (a.kr > a.nc || a.kr < 1) return hipErrorInvalidValue;
   if (a.nc <= 64) {
-    if (a.kr <= 16) svd_wave_kernel<16><<<a.batch, 64, 0, s>>>(a);
-    else if (a.kr <= 32) svd_wave_kernel<32><<<a.batch, 64, 0, s>>>(a);
-    else if (a.kr <= 48) svd_wave_kernel<48><<<a.batch, 64, 0, s>>>(a);
-    else svd_wave_kernel<64><<<a.batch, 64, 0, s>>>(a);
-    return hipGetLastError();
+    if (a.kr <= 16) return svd_quad_launch<4>(a, s);
+    if (a.kr <= 32) return svd_quad_launch<8>(a, s);
+    if (a.kr <= 40) return svd_quad_launch<10>(a, s);
+    if (a.kr <= 48) return svd_quad_launch<12>(a, s);
+    return svd_quad_launch<16>(a, s);
   }
   if (a.nc > kSvdMaxN || (int64_t)a.nc * a.kr > kQrLdsDoubles) return hipErrorInvalidValue;
   const int np = a.nc + (a.nc & 1);
