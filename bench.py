@@ -13,8 +13,10 @@ Prints one JSON line (see the design doc for the field definitions).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -52,6 +54,73 @@ def _time_steps(fn, steps, torch):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return e0.elapsed_time(e1) / 1000.0, wall
+
+
+_SITE = re.compile(r"^\s*([0-9.]+) ms\s+([0-9]+) calls\s+([a-z_0-9]+): (.*)$")
+_SW = re.compile(r"sandwich (W_L|update) n=(\d+) G=(\d+) RA=(\d+) RI=(\d+) SI=(\d+) SO=(\d+) \[(.+)\]")
+_GEMM = re.compile(r"gemm (\d+)x(\d+)x(\d+) .*\[(.+)\]")
+
+
+def _site_group(label, batch):
+    """Compiled kernel a launch site runs (named as in a rocprofv3 trace),
+    its bound, and its algorithmic FP64 flops per launch (whole batch)."""
+    m = _SW.match(label)
+    if m:
+        n, G, RA, RI, SI, SO = (int(v) for v in m.groups()[1:7])
+        return m.group(8), "alu", 2.0 * n * G * (RI * SI * SO + RA * RI * SO) * batch
+    m = _GEMM.match(label)
+    if m:
+        M, N, K = (int(v) for v in m.groups()[:3])
+        return m.group(4), "mfma", 2.0 * M * N * K * batch
+    return None
+
+
+def _roofline(report, batch, steps, perfmodel):
+    groups = {}
+    for line in report.splitlines():
+        m = _SITE.match(line)
+        if not m:
+            continue
+        ms, calls, _cls, label = float(m.group(1)), int(m.group(2)), m.group(3), m.group(4)
+        g = _site_group(label, batch)
+        if g is None:
+            continue
+        kernel, bound, f = g
+        acc = groups.setdefault(kernel, {"ms": 0.0, "calls": 0, "flops": 0.0, "bound": bound})
+        acc["ms"] += ms
+        acc["calls"] += calls
+        acc["flops"] += f * calls
+    if not groups:
+        return None
+    dom = max(groups, key=lambda k: groups[k]["ms"])
+    gr = groups[dom]
+    avg_s = gr["ms"] / gr["calls"] / 1000.0
+    per_launch = gr["flops"] / gr["calls"]
+    achieved = per_launch / avg_s / 1e12
+    peak = perfmodel.PEAK_FP64_TFLOPS
+    return {"kernel": dom, "bound": gr["bound"], "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": _traffic(dom),
+            "avg_launch_us": 1e6 * avg_s, "launches_per_step": gr["calls"] / steps,
+            "algorithmic_flop_per_launch": per_launch}
+
+
+def _traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed hardware-counter
+    summary, or None when none was taken or the kernel source has changed
+    since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    ent = data.get(kernel)
+    if not ent:
+        return None
+    src = os.path.join(ROOT, ent["source"])
+    with open(src, "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != ent["source_sha256"]:
+            return None
+    return ent["hbm_bytes_per_launch"]
 
 
 def main() -> int:
@@ -126,37 +195,26 @@ def main() -> int:
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step (events {1000 * gpu_s / args.steps:.3f})",
           file=sys.stderr, flush=True)
 
-    # per-kernel-class event timing over a second, identical region
+    # per-kernel event timing over a second, identical region (eager launches:
+    # two HIP events on the library's stream around every launch)
     H.profile_start()
     for _ in range(args.steps):
         step()
     prof = H.profile_stop()
     torch.cuda.synchronize()
-    print("[bench] per launch site over the profiled steps:\n" + H.profile_report(), file=sys.stderr, flush=True)
+    report = H.profile_report()
+    print("[bench] per launch site over the profiled steps:\n" + report, file=sys.stderr, flush=True)
     flops = perfmodel.hatt_round_flops(x.n, x.ranks, y.ranks, p["ell"], cap)
     classes = {}
     for name, (ms, calls) in prof.items():
         if calls:
             classes[name] = {"ms_per_step": ms / args.steps, "calls_per_step": calls / args.steps}
-    dom = max(classes, key=lambda k: classes[k]["ms_per_step"])
-    dom_flops = flops.get(dom, 0.0) * B
-    dom_s = classes[dom]["ms_per_step"] / 1000.0
-    achieved = dom_flops / dom_s / 1e12 if dom_flops > 0 else None
-    roof = {
-        "kernel": dom,
-        "bound": "mfma" if dom in ("gemm_f64",) else "alu",
-        "achieved": achieved,
-        "peak": perfmodel.PEAK_FP64_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": (achieved / perfmodel.PEAK_FP64_TFLOPS) if achieved else None,
-        "traffic": None,
-    }
     for name in classes:
         f = flops.get(name, 0.0) * B
         if f > 0:
             classes[name]["tflops"] = f / (classes[name]["ms_per_step"] / 1000.0) / 1e12
     step_tflops = flops["total"] * B / (ms_per_step / 1000.0) / 1e12
-
+    roof = _roofline(report, B, args.steps, perfmodel)
     # explicit PKP + TT-Rounding on the GPU (the comparator of the metric)
     explicit = None
     if not args.no_explicit:

@@ -72,6 +72,8 @@ struct SandwichArgs {
   int batch;
 };
 hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s);
+// Name of the compiled kernel launch_sandwich picks for these arguments.
+const char *sandwich_kernel_name(const SandwichArgs &a);
 
 // Batched strided copy: dst(r, c) = src(r, c) for an M x N block.
 hipError_t launch_copy(CMat src, Mat dst, int64_t M, int64_t N, int batch, hipStream_t s);
@@ -102,6 +104,10 @@ struct GemmArgs {
 };
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
 int gemm_pick_ksplit(int64_t M, int64_t N, int64_t K, int batch);
+// Sum of the split-K partials of a launch made with no_reduce set, into C.
+hipError_t launch_splitk_reduce(const GemmArgs &g, hipStream_t s);
+// Output tile (BM x BN) the launcher uses for an M x N product.
+void gemm_tile(int64_t M, int64_t N, int *bm, int *bn);
 // Layout of the split-K partials: pair p, chunk t at part + (p * ksplit + t) * M * N.
 
 // ---- TSQR (k_qr.hip) -------------------------------------------------------

@@ -133,7 +133,7 @@ Profiler g_prof;
 
 int class_of(const char *expr) {
   if (g_class_override >= 0) return g_class_override;
-  if (strstr(expr, "launch_gemm")) return P_GEMM;
+  if (strstr(expr, "launch_gemm") || strstr(expr, "launch_splitk")) return P_GEMM;
   if (strstr(expr, "launch_tsqr")) return P_QR;
   if (strstr(expr, "launch_sandwich")) return P_SANDWICH;
   if (strstr(expr, "launch_svd")) return P_SVD;
@@ -145,7 +145,7 @@ int class_of(const char *expr) {
 
 void site(const char *fmt, ...) {
   if (!g_prof.on) return;
-  char b[96];
+  char b[160];
   va_list ap;
   va_start(ap, fmt);
   vsnprintf(b, sizeof b, fmt, ap);
@@ -205,7 +205,7 @@ hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_
                  double alpha, double beta, int batch, hipStream_t st, bool allow_split,
                  const int *run_flag = nullptr, int64_t run_flag_stride = 0, int *ks_out = nullptr) {
   GemmArgs g{};
-  g.no_reduce = (ks_out != nullptr);
+  g.no_reduce = 1;  // the reduction, when needed, is its own launch below
   g.run_flag = run_flag;
   g.run_flag_stride = run_flag_stride;
   g.run_when = 1;
@@ -225,13 +225,19 @@ hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_
   g.part = gc.part;
   if (ks_out != nullptr) *ks_out = g.ksplit;
   if (g_prof.on) {
-    char b[96];
-    snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=%d%s", (long long)M, (long long)N, (long long)K, g.ksplit,
-             run_flag ? " flagged" : "");
+    char b[160];
+    int bm = 0, bn = 0;
+    gemm_tile(M, N, &bm, &bn);
+    snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=%d%s [gemm_f64_kernel<%d, %d>]", (long long)M, (long long)N,
+             (long long)K, g.ksplit, run_flag ? " flagged" : "", bm, bn);
     g_site = b;
   }
   LAUNCH(launch_gemm(g, st));
   g_site.clear();
+  if (g.ksplit > 1 && ks_out == nullptr) {
+    site("splitk_reduce %lldx%lld ks=%d", (long long)M, (long long)N, g.ksplit);
+    LAUNCH(launch_splitk_reduce(g, st));
+  }
   return HATT_OK;
 }
 
@@ -812,7 +818,8 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     a.n = n[c];
     a.G = l1;
     a.batch = P;
-    site("sandwich W_L n=%lld G=%lld", (long long)n[c], (long long)l1);
+    site("sandwich W_L n=%lld G=%lld RA=%d RI=%d SI=%d SO=%d [%s]", (long long)n[c], (long long)l1, a.RA, a.RI,
+         a.SI, a.SO, sandwich_kernel_name(a));
     LAUNCH(launch_sandwich(a, st));
     const int64_t K = n[c] * l1;
     const CMat wr = v2 ? CMat{h2WR, 1, K, h2_wr} : CMat{sk + skoff[c], 1, K, sks};
@@ -876,7 +883,8 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     a.n = n[cn];
     a.G = l[cn];
     a.batch = P;
-    site("sandwich update n=%lld G=%lld", (long long)n[cn], (long long)l[cn]);
+    site("sandwich update n=%lld G=%lld RA=%d RI=%d SI=%d SO=%d [%s]", (long long)n[cn], (long long)l[cn], a.RA,
+         a.RI, a.SI, a.SO, sandwich_kernel_name(a));
     LAUNCH(launch_sandwich(a, st));
   }
   // ranks before truncation: the sketch widths

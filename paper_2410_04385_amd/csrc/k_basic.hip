@@ -416,6 +416,21 @@ hipError_t sandwich_reg_dispatch(const SandwichArgs &a, hipStream_t s, int64_t b
 
 bool g_sandwich_reg = true;
 
+const char *sandwich_kernel_name(const SandwichArgs &a) {
+  const int64_t budget = 19456;
+  const int RIp = (a.RI + 1) & ~1, SIp = (a.SI + 1) & ~1;
+  const int64_t fixed = (int64_t)a.RA * RIp + (((int64_t)a.SI * a.SO + 1) & ~1);
+  const int m = std::max(std::max(a.RI, a.SI), 1);
+  const bool lg = (a.og == 1);
+  if (g_sandwich_reg && fixed + (int64_t)a.RI * SIp + 2 <= budget && a.SO <= 256 && m <= 48) {
+    if (m <= 16) return lg ? "sandwich_reg_kernel<16, 2, true>" : "sandwich_reg_kernel<16, 2, false>";
+    if (m <= 24) return lg ? "sandwich_reg_kernel<24, 2, true>" : "sandwich_reg_kernel<24, 2, false>";
+    if (m <= 32) return lg ? "sandwich_reg_kernel<32, 1, true>" : "sandwich_reg_kernel<32, 1, false>";
+    return lg ? "sandwich_reg_kernel<48, 1, true>" : "sandwich_reg_kernel<48, 1, false>";
+  }
+  return lg ? "sandwich_kernel<true>" : "sandwich_kernel<false>";
+}
+
 hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s) {
   if (a.n <= 0 || a.G <= 0 || a.batch <= 0) return hipSuccess;
   const int64_t budget = 19456;  // doubles of dynamic LDS

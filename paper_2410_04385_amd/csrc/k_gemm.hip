@@ -209,7 +209,7 @@ __global__ void splitk_reduce_kernel(GemmArgs g) {
 
 // Tile shape: 32 rows or columns when that side of C is at most 32 wide
 // (less padding for the thin operands of the sweep), else 64.
-static void gemm_tile(int64_t M, int64_t N, int *bm, int *bn) {
+void gemm_tile(int64_t M, int64_t N, int *bm, int *bn) {
   *bm = (M <= 32) ? 32 : 64;
   *bn = (N <= 32) ? 32 : 64;
   if (*bm == 64 && *bn == 64 && N <= 48 && M >= 256) *bn = 32;  // e.g. N = 40: 2 tiles of 32
@@ -240,6 +240,11 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
   else gemm_f64_kernel<32, 32><<<grid, 256, 0, s>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || a.ksplit == 1 || a.no_reduce) return e;
+  return launch_splitk_reduce(a, s);
+}
+
+hipError_t launch_splitk_reduce(const GemmArgs &a, hipStream_t s) {
+  if (a.M <= 0 || a.N <= 0 || a.batch <= 0 || a.ksplit <= 1) return hipSuccess;
   const int64_t total = a.M * a.N * a.batch;
   int rg = (int)std::min<int64_t>((total + 255) / 256, 65536);
   splitk_reduce_kernel<<<rg, 256, 0, s>>>(a);

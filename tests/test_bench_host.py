@@ -1,0 +1,50 @@
+"""Host-side pieces of bench.py: the roofline grouping of launch sites by
+compiled kernel and its algorithmic flop counts (no GPU)."""
+
+import importlib.util
+import os
+
+import pytest
+
+from paper_2410_04385_amd import perfmodel
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+REPORT = """\
+     100.000 ms       20 calls  sandwich: sandwich update n=32 G=40 RA=20 RI=20 SI=20 SO=20 [sandwich_reg_kernel<24, 2, false>]
+      50.000 ms       10 calls  gemm_f64: gemm 400x40x1280 ks=2 [gemm_f64_kernel<64, 32>]
+      60.000 ms       10 calls  qr: gemm 1280x40x40 ks=1 flagged [gemm_f64_kernel<64, 32>]
+       5.000 ms       10 calls  gemm_f64: splitk_reduce 400x40 ks=2
+       9.000 ms       10 calls  qr: chol 40
+"""
+
+
+def test_roofline_groups_sites_by_compiled_kernel():
+    b = _bench()
+    roof = b._roofline(REPORT, 128, 10, perfmodel)
+    # gemm_f64_kernel<64, 32>: 110 ms over 20 launches beats the sandwich's 100 ms
+    assert roof["kernel"] == "gemm_f64_kernel<64, 32>"
+    assert roof["bound"] == "mfma"
+    assert roof["avg_launch_us"] == pytest.approx(110.0 / 20 * 1000)
+    flops = (2 * 400 * 40 * 1280 * 10 + 2 * 1280 * 40 * 40 * 10) * 128
+    assert roof["algorithmic_flop_per_launch"] == pytest.approx(flops / 20)
+    assert roof["achieved"] == pytest.approx(flops / 0.110 / 1e12)
+    assert roof["frac"] == pytest.approx(roof["achieved"] / 78.6)
+
+
+def test_sandwich_site_flops():
+    b = _bench()
+    kern, bound, f = b._site_group(
+        "sandwich W_L n=32 G=40 RA=20 RI=20 SI=20 SO=20 [sandwich_reg_kernel<24, 2, true>]", 2)
+    assert kern == "sandwich_reg_kernel<24, 2, true>" and bound == "alu"
+    # per (i, g): T = C ZR (RI x SI x SO) then YL T (RA x RI x SO), 2 flops per multiply-add
+    assert f == 2.0 * 32 * 40 * (20 * 20 * 20 + 20 * 20 * 20) * 2
+    assert b._site_group("qr: chol 40", 1) is None
