@@ -72,6 +72,33 @@ struct SandwichArgs {
   int batch;
 };
 hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s);
+// Matrix-core variant (k_sandwich.hip): block and LDS plan for a chunk of GC
+// sketch columns per workgroup; false when even one column does not fit.
+// Division by a launch constant d as a multiply-high: q = (x * m) >> 32 with
+// m = ceil(2^32 / d) equals floor(x / d) for 0 <= x < 2^16 and 1 < d <= 4096
+// (checked exhaustively); m = 0 marks d = 1.
+struct FastDiv {
+  uint32_t m;
+  int d;
+};
+inline FastDiv make_fastdiv(int d) {
+  FastDiv f;
+  f.d = d;
+  f.m = (d <= 1) ? 0u : (uint32_t)(((1ull << 32) + (uint64_t)d - 1) / (uint64_t)d);
+  return f;
+}
+constexpr int64_t kSandwichLdsDoubles = 19456;
+constexpr int kSwPrefetch = 8;  // register slots per thread for the next slice's YL / ZR
+struct SwPlan {
+  int GC, chunks;
+  int ipb, iblocks;           // mode indices per block, blocks along i
+  int RI4, SI4, SO16, RA16;   // padded sizes (K edges to 4, M/N edges to 16)
+  int ldc, ldz, ldy, ldt, M1; // LDS row strides; padded stage-1 row count
+  int64_t lds_doubles;
+  FastDiv fd_ri, fd_so, fd_gc; // index decodes of the stage-1 rows and stage-2 columns
+};
+bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl);
+hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStream_t s);
 // Name of the compiled kernel launch_sandwich picks for these arguments.
 const char *sandwich_kernel_name(const SandwichArgs &a);
 

@@ -3,6 +3,7 @@
 // both the W_L columns of HPCRL (eq. WLWR) and the PKP-free core update of
 // the HaTT sweep (eq. M*core0).
 #include "common.h"
+#include "stage.h"
 
 namespace hatt {
 
@@ -127,49 +128,6 @@ hipError_t launch_hpcrl_last(const LastArgs &a, hipStream_t s) {
 // when the output is contiguous in g (the W_L columns of HPCRL), else with
 // the column index innermost (the core update, contiguous in (a', b')).
 // Every LDS access pattern is either a broadcast or unit stride.
-// Three-digit counter (i0 fastest, radices n0, n1) stepped by a fixed stride
-// with carries instead of a division per element.
-struct Rad3 {
-  int i0, i1, i2, n0, n1, s0, s1, s2;
-  __device__ Rad3(int start, int stride, int n0_, int n1_) : n0(n0_), n1(n1_) {
-    i0 = start % n0;
-    i1 = (start / n0) % n1;
-    i2 = start / (n0 * n1);
-    s0 = stride % n0;
-    s1 = (stride / n0) % n1;
-    s2 = stride / (n0 * n1);
-  }
-  __device__ __forceinline__ void next() {
-    i0 += s0;
-    i1 += s1;
-    i2 += s2;
-    if (i0 >= n0) { i0 -= n0; ++i1; }
-    if (i1 >= n1) { i1 -= n1; ++i2; }
-  }
-};
-
-// Global -> LDS staging with U loads in flight per thread: element e of the
-// block (digits in d, advanced by the block stride) is read by src(d) and
-// stored at dst[idx(d)].
-template <int U, typename Src, typename Idx>
-__device__ __forceinline__ void stage_lds(int total, Rad3 d, double *dst, Src src, Idx idx) {
-  for (int e0 = threadIdx.x; e0 < total; e0 += 256 * U) {
-    double v[U];
-    int di[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (e0 + 256 * u < total) {
-        v[u] = src(d);
-        di[u] = idx(d);
-      }
-      d.next();
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (e0 + 256 * u < total) dst[di[u]] = v[u];
-  }
-}
-
 template <bool GFAST>
 __global__ __launch_bounds__(256) void sandwich_kernel(SandwichArgs a, int GC) {
   extern __shared__ double sm[];
@@ -415,9 +373,13 @@ hipError_t sandwich_reg_dispatch(const SandwichArgs &a, hipStream_t s, int64_t b
 }  // namespace
 
 bool g_sandwich_reg = true;
+bool g_sandwich_mfma = true;
 
 const char *sandwich_kernel_name(const SandwichArgs &a) {
   const int64_t budget = 19456;
+  SwPlan pl;
+  if (g_sandwich_mfma && sandwich_mfma_plan(a, kSandwichLdsDoubles, &pl))
+    return (a.og == 1) ? "sandwich_mfma_kernel<true>" : "sandwich_mfma_kernel<false>";
   const int RIp = (a.RI + 1) & ~1, SIp = (a.SI + 1) & ~1;
   const int64_t fixed = (int64_t)a.RA * RIp + (((int64_t)a.SI * a.SO + 1) & ~1);
   const int m = std::max(std::max(a.RI, a.SI), 1);
@@ -434,6 +396,10 @@ const char *sandwich_kernel_name(const SandwichArgs &a) {
 hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s) {
   if (a.n <= 0 || a.G <= 0 || a.batch <= 0) return hipSuccess;
   const int64_t budget = 19456;  // doubles of dynamic LDS
+  if (g_sandwich_mfma) {
+    SwPlan pl;
+    if (sandwich_mfma_plan(a, kSandwichLdsDoubles, &pl)) return launch_sandwich_mfma(a, pl, s);
+  }
   if (g_sandwich_reg) {
     const int RIp = (a.RI + 1) & ~1, SIp = (a.SI + 1) & ~1;
     const int64_t fixed = (int64_t)a.RA * RIp + (((int64_t)a.SI * a.SO + 1) & ~1);

@@ -1,0 +1,286 @@
+// The sandwich contraction on the FP64 matrix cores.
+//
+// For one pair p, one mode index i and a chunk of GC sketch columns g, the
+// kernel forms out_g = YL_i C_g ZR_i (RA x RI, RI x SI, SI x SO) as two
+// products (the same operation as sandwich_kernel, see common.h):
+//   stage 1  T = [C_g0; C_g1; ...] ZR      rows (g, a) stacked, K = SI
+//   stage 2  out = YL [T_g0 | T_g1 | ...]  columns (g, b') side by side, K = RI
+// Both run on v_mfma_f64_16x16x4f64 (16 x 16 output blocks, K steps of 4);
+// every operand sits in LDS, zero-padded to whole blocks.  Stage 1 stacks the
+// g blocks along M and stage 2 along N, so only the short dimension of each
+// product is padded to 16.  The column order of stage 2 is chosen so that the
+// 16 lanes of an output row segment store to consecutive addresses:
+// (b', g) with g fastest when the output is contiguous in g (the W_L columns
+// of HPCRL), (g, b') otherwise (the core update).
+#include "common.h"
+#include "stage.h"
+
+namespace hatt {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+namespace {
+__host__ __device__ inline int rup(int x, int m) { return (x + m - 1) / m * m; }
+}  // namespace
+
+bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
+  const int RI4 = rup(a.RI, 4), SI4 = rup(a.SI, 4);
+  const int SO16 = rup(a.SO, 16), RA16 = rup(a.RA, 16);
+  const int ldc = SI4 + 1, ldz = SO16 + 1, ldy = RI4 + 1;
+  const int64_t yz = (int64_t)SI4 * ldz + (int64_t)RA16 * ldy;  // one YL + ZR buffer
+  // the register prefetch of the next slice covers every YL / ZR slot
+  if ((int64_t)RA16 * RI4 + (int64_t)SI4 * SO16 > kSwPrefetch * 256) return false;
+  auto lds_for = [&](int gc, int *ldt, int *m1) {
+    *m1 = rup(gc * a.RI, 16);
+    *ldt = rup(gc * a.SO, 16) + 1;
+    return (int64_t)(*m1) * ldc + 2 * yz + (int64_t)RI4 * (*ldt);
+  };
+  // largest chunk (<= 16 columns) that keeps two blocks per CU, else one
+  int best = 0;
+  for (int pass = 0; pass < 2 && best == 0; ++pass) {
+    const int64_t lim = pass == 0 ? std::min<int64_t>(budget, 9728) : budget;
+    for (int gc = (int)std::min<int64_t>(16, a.G); gc >= 1; --gc) {
+      int ldt, m1;
+      if (lds_for(gc, &ldt, &m1) <= lim) {
+        best = gc;
+        break;
+      }
+    }
+  }
+  if (best == 0) return false;
+  const int64_t chunks = (a.G + best - 1) / best;
+  const int GC = (int)((a.G + chunks - 1) / chunks);  // balanced chunks
+  int ldt, m1;
+  pl->lds_doubles = lds_for(GC, &ldt, &m1);
+  pl->GC = GC;
+  pl->chunks = (int)chunks;
+  pl->RI4 = RI4;
+  pl->SI4 = SI4;
+  pl->SO16 = SO16;
+  pl->RA16 = RA16;
+  pl->ldc = ldc;
+  pl->ldz = ldz;
+  pl->ldy = ldy;
+  pl->ldt = ldt;
+  pl->M1 = m1;
+  pl->fd_ri = make_fastdiv(a.RI);
+  pl->fd_so = make_fastdiv(a.SO);
+  pl->fd_gc = make_fastdiv(GC);
+  // the multiply-high decodes need row / column indices below 2^16 and divisors <= 4096
+  if (m1 >= (1 << 16) || ldt >= (1 << 16) || a.RI > 4096 || a.SO > 4096) return false;
+  if (RI4 > 64 || SI4 > 64) return false;  // K steps of the unrolled MFMA loop
+  // slices per block: about 2048 blocks in the grid; C is staged once per block
+  const int64_t others = chunks * (int64_t)a.batch;
+  int64_t ipb = std::max<int64_t>(1, (a.n * others) / 2048);
+  ipb = std::min<int64_t>(ipb, a.n);
+  pl->iblocks = (int)((a.n + ipb - 1) / ipb);
+  pl->ipb = (int)((a.n + pl->iblocks - 1) / pl->iblocks);  // balanced
+  // prefetch offsets are 32-bit
+  const int64_t ymax = (int64_t)(a.RA - 1) * std::llabs(a.ylr) + (int64_t)(a.RI - 1) * std::llabs(a.ylc);
+  const int64_t zmax = (int64_t)(a.SI - 1) * std::llabs(a.zrr) + (int64_t)(a.SO - 1) * std::llabs(a.zrc);
+  return ymax < (1LL << 31) && zmax < (1LL << 31);
+}
+
+// Two 16 x 16 output blocks per pass (two accumulation chains in flight):
+// c0 += A0 B0, c1 += A1 B1 over K steps of 4 (A rows advance by lda_k per
+// step, B rows by ldb_k).  Both chains always run; a caller without a second
+// block passes the first block's operands twice and drops c1.
+constexpr int kSwMaxKSteps = 16;  // K <= 64 on both stages
+
+__device__ __forceinline__ void mfma_pair(const double *a0, const double *b0, const double *a1, const double *b1,
+                                          int lda_k, int ldb_k, int ksteps, d4_t &c0, d4_t &c1) {
+#pragma unroll
+  for (int k = 0; k < kSwMaxKSteps; ++k) {
+    if (k < ksteps) {
+      const double x0 = a0[k * lda_k], y0 = b0[k * ldb_k];
+      const double x1 = a1[k * lda_k], y1 = b1[k * ldb_k];
+      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, c1, 0, 0, 0);
+    }
+  }
+}
+
+template <bool LG>
+__global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPlan pl) {
+  extern __shared__ double sm[];
+  const int RA = a.RA, RI = a.RI, SI = a.SI, SO = a.SO;
+  const int GC = pl.GC;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: tile loops stay scalar
+  const int r16 = lane & 15, q4 = lane >> 4;
+  const int64_t i0 = (int64_t)blockIdx.x * pl.ipb;
+  const int64_t i1 = std::min<int64_t>(a.n, i0 + pl.ipb);
+  const int64_t g0 = (int64_t)blockIdx.y * GC;
+  const int p = blockIdx.z;
+  const int gc = (int)std::min<int64_t>(GC, a.G - g0);
+  if (gc <= 0 || i0 >= i1) return;
+  const int yzs = pl.SI4 * pl.ldz + pl.RA16 * pl.ldy;
+  double *Cs = sm;                           // pl.M1 rows (g, a) x ldc, K = b
+  double *YZ0 = Cs + pl.M1 * pl.ldc;         // [ZR: SI4 x ldz | YL: RA16 x ldy], two buffers
+  double *Ts = YZ0 + 2 * yzs;                // RI4 rows (a) x ldt, N = stage-2 columns
+  const int M1 = gc * RI;                    // valid stage-1 rows
+  const int M1p = rup(M1, 16);
+
+  // ---- C chunk (fixed for all slices of this block), zero K padding
+  const double *cbase = a.c + p * a.cb + g0 * a.cg;
+  if (a.cg == 1) {  // g fastest in memory: consecutive threads take consecutive g
+    stage_lds<8>(gc * RI * pl.SI4, Rad3(tid, 256, gc, pl.SI4), Cs,  // digits (g, b, a)
+                 [&](const Rad3 &d) {
+                   return (d.i1 < SI) ? cbase[d.i0 * a.cg + d.i2 * a.ca + d.i1 * a.cbb] : 0.0;
+                 },
+                 [&](const Rad3 &d) { return (d.i0 * RI + d.i2) * pl.ldc + d.i1; });
+  } else {
+    stage_lds<8>(gc * RI * pl.SI4, Rad3(tid, 256, pl.SI4, RI), Cs,  // digits (b, a, g)
+                 [&](const Rad3 &d) {
+                   return (d.i0 < SI) ? cbase[d.i2 * a.cg + d.i1 * a.ca + d.i0 * a.cbb] : 0.0;
+                 },
+                 [&](const Rad3 &d) { return (d.i2 * RI + d.i1) * pl.ldc + d.i0; });
+  }
+  for (int e = tid; e < (M1p - M1) * pl.SI4; e += 256) {
+    const int r = M1 + e / pl.SI4, k = e - (e / pl.SI4) * pl.SI4;
+    Cs[r * pl.ldc + k] = 0.0;
+  }
+  // rows a >= RI of T are K padding of stage 2: zero once
+  for (int e = tid; e < (pl.RI4 - RI) * pl.ldt; e += 256) Ts[RI * pl.ldt + e] = 0.0;
+
+  // ---- YL / ZR slots of this thread: slot u is element tid + 256 u of the
+  // padded [ZR | YL] grid; kind 0 = zero padding, 1 = ZR entry, 2 = YL entry
+  int pf_lds[kSwPrefetch], pf_off[kSwPrefetch];
+  int pf_kind = 0;
+  const int nz = pl.SI4 * pl.SO16, ny = pl.RA16 * pl.RI4;
+#pragma unroll
+  for (int u = 0; u < kSwPrefetch; ++u) {
+    const int e = tid + 256 * u;
+    pf_lds[u] = -1;
+    pf_off[u] = 0;
+    if (e < nz) {
+      const int b = e / pl.SO16, bp = e - b * pl.SO16;
+      pf_lds[u] = b * pl.ldz + bp;
+      if (b < SI && bp < SO) {
+        pf_kind |= 1 << (2 * u);
+        pf_off[u] = (int)(b * a.zrr + bp * a.zrc);
+      }
+    } else if (e < nz + ny) {
+      const int f = e - nz, ap = f / pl.RI4, k = f - ap * pl.RI4;
+      pf_lds[u] = pl.SI4 * pl.ldz + ap * pl.ldy + k;
+      if (ap < RA && k < RI) {
+        pf_kind |= 2 << (2 * u);
+        pf_off[u] = (int)(ap * a.ylr + k * a.ylc);
+      }
+    }
+  }
+  const double *zrp = a.zr + p * a.zrb;
+  const double *ylp = a.yl + p * a.ylb;
+  double pf[kSwPrefetch];
+  auto fetch = [&](int64_t i) {
+    const double *zr = zrp + i * a.zri, *yl = ylp + i * a.yli;
+#pragma unroll
+    for (int u = 0; u < kSwPrefetch; ++u) {
+      const int k = (pf_kind >> (2 * u)) & 3;
+      pf[u] = (k == 1) ? zr[pf_off[u]] : ((k == 2) ? yl[pf_off[u]] : 0.0);
+    }
+  };
+  auto park = [&](double *buf) {
+#pragma unroll
+    for (int u = 0; u < kSwPrefetch; ++u)
+      if (pf_lds[u] >= 0) buf[pf_lds[u]] = pf[u];
+  };
+  fetch(i0);
+  park(YZ0);
+  __syncthreads();
+
+  const int nt1 = pl.SO16 / 16, tiles1 = (M1p / 16) * nt1;
+  const int ncols = LG ? SO * GC : gc * SO;
+  const int nt2 = rup(ncols, 16) / 16, tiles2 = (pl.RA16 / 16) * nt2;
+  int buf = 0;
+  for (int64_t i = i0; i < i1; ++i) {
+    const bool more = i + 1 < i1;
+    if (more) fetch(i + 1);  // in flight during the MFMAs below
+    const double *ZRs = YZ0 + buf * yzs;
+    const double *YLs = ZRs + pl.SI4 * pl.ldz;
+
+    // ---- stage 1: T(g, a; b') = sum_b C_g(a, b) ZR(b, b'), scattered into Ts
+    for (int t = wave; t < tiles1; t += 8) {
+      const int t2 = t + 4;
+      const bool two = t2 < tiles1;
+      const int tm0 = (t / nt1) * 16, tn0 = (t - (t / nt1) * nt1) * 16;
+      const int tm1 = two ? (t2 / nt1) * 16 : tm0, tn1 = two ? (t2 - (t2 / nt1) * nt1) * 16 : tn0;
+      d4_t c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+      mfma_pair(Cs + (tm0 + r16) * pl.ldc + q4, ZRs + q4 * pl.ldz + tn0 + r16, Cs + (tm1 + r16) * pl.ldc + q4,
+                ZRs + q4 * pl.ldz + tn1 + r16, 4, 4 * pl.ldz, pl.SI4 / 4, c0, c1);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (u == 1 && !two) break;
+        const d4_t &c = u ? c1 : c0;
+        const int tm = u ? tm1 : tm0, bq = (u ? tn1 : tn0) + r16;
+        if (bq < SO) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = tm + q4 + 4 * v;
+            if (row < M1) {
+              const int g = fdiv(row, pl.fd_ri), aa = row - g * RI;
+              const int col = LG ? bq * GC + g : g * SO + bq;
+              Ts[aa * pl.ldt + col] = c[v];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- stage 2: out(a', col) = sum_a YL(a', a) T(a, col)
+    double *obase = a.o + p * a.ob + i * a.oi + g0 * a.og;
+    for (int t = wave; t < tiles2; t += 8) {
+      const int t2 = t + 4;
+      const bool two = t2 < tiles2;
+      const int tm0 = (t / nt2) * 16, tn0 = (t - (t / nt2) * nt2) * 16;
+      const int tm1 = two ? (t2 / nt2) * 16 : tm0, tn1 = two ? (t2 - (t2 / nt2) * nt2) * 16 : tn0;
+      d4_t c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+      mfma_pair(YLs + (tm0 + r16) * pl.ldy + q4, Ts + q4 * pl.ldt + tn0 + r16, YLs + (tm1 + r16) * pl.ldy + q4,
+                Ts + q4 * pl.ldt + tn1 + r16, 4, 4 * pl.ldt, pl.RI4 / 4, c0, c1);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (u == 1 && !two) break;
+        const d4_t &c = u ? c1 : c0;
+        const int tm = u ? tm1 : tm0, col = (u ? tn1 : tn0) + r16;
+        int g, bq;
+        if (LG) {
+          bq = fdiv(col, pl.fd_gc);
+          g = col - bq * GC;
+        } else {
+          g = fdiv(col, pl.fd_so);
+          bq = col - g * SO;
+        }
+        if (col < ncols && g < gc) {
+          double *o = obase + g * a.og + bq * a.obb + (int64_t)(tm + q4) * a.oa;
+          const int64_t s4 = 4 * a.oa;
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (tm + q4 + 4 * v < RA) o[v * s4] = c[v];
+        }
+      }
+    }
+    if (more) park(YZ0 + (buf ^ 1) * yzs);
+    __syncthreads();  // Ts and the YL / ZR buffer are reused by the next slice
+    buf ^= 1;
+  }
+}
+
+hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStream_t s) {
+  const size_t lds = (size_t)pl.lds_doubles * sizeof(double);
+  static bool attr_done = false;  // set once: the maximum a launch may ask for
+  if (!attr_done) {
+    (void)hipFuncSetAttribute((const void *)sandwich_mfma_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(kSandwichLdsDoubles * sizeof(double)));
+    (void)hipFuncSetAttribute((const void *)sandwich_mfma_kernel<false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(kSandwichLdsDoubles * sizeof(double)));
+    attr_done = true;
+  }
+  dim3 grid((unsigned)pl.iblocks, (unsigned)pl.chunks, (unsigned)a.batch);
+  if (a.og == 1) sandwich_mfma_kernel<true><<<grid, 256, lds, s>>>(a, pl);
+  else sandwich_mfma_kernel<false><<<grid, 256, lds, s>>>(a, pl);
+  return hipGetLastError();
+}
+
+}  // namespace hatt
