@@ -110,6 +110,32 @@ HATT_API hatt_status hatt_recompress(const hatt_tt *x, const hatt_tt *y, const h
                             int64_t *out_rank, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Uneven batches: npairs independent recompressions x[p] (.) y[p] whose
+ * shapes (order, mode sizes, ranks, batch) differ from pair to pair; each
+ * pair is the hatt_recompress problem above.  opts applies to every pair
+ * (opts->ell_bond must be NULL): widths are clamped per pair; opts->ell <= 0
+ * asks for l_k = max(r_k, s_k) + 8 per bond; pair p draws its Philox sketch
+ * with key opts->seed + p.  Outputs go to one flat device buffer: pair p's
+ * trains at element offset out_offset[p] (packed, capacity shape as
+ * hatt_plan would report), its kept ranks ([batch_p][d_p + 1] int64) at
+ * element offset rank_offset[p] of out_rank.
+ * hatt_batched_plan: out_offset and rank_offset (host [npairs + 1], the last
+ * entry is the total), ell_out (host, may be NULL: the clamped widths of
+ * every pair, d_p + 1 entries per pair, concatenated in pair order) and
+ * ws_bytes.  The pairs are enqueued on up to four
+ * library-owned streams forked from `stream` and joined back to it (so the
+ * call composes with stream order and graph capture); concurrent pairs use
+ * separate workspace slots.  No host synchronisation.  Errors of any pair
+ * are reported before anything is enqueued.
+ */
+HATT_API hatt_status hatt_batched_plan(int32_t npairs, const hatt_tt *x, const hatt_tt *y,
+                                       const hatt_opts *opts, int64_t *out_offset,
+                                       int64_t *rank_offset, int64_t *ell_out, size_t *ws_bytes);
+HATT_API hatt_status hatt_recompress_batched(int32_t npairs, const hatt_tt *x, const hatt_tt *y,
+                                             const hatt_opts *opts, double *out, int64_t *out_rank,
+                                             void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Tolerance-driven recompression.  The paper fixes target ranks and leaves
  * tolerance control open (Sec. 6); it suggests enlarging l when a sketch's
  * smallest singular value is not small enough (Sec. 5.1.1).  Rule:

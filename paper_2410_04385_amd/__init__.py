@@ -10,6 +10,7 @@ library; the first call does, and fails loudly if it has not been built.
 from .api import (  # noqa: F401
     TT,
     Result,
+    batched_plan,
     hadamard_explicit,
     norm,
     plan,
@@ -18,6 +19,7 @@ from .api import (  # noqa: F401
     profile_stop,
     recompress,
     recompress_adaptive,
+    recompress_batched,
     round,
     round_plan,
     set_qr_method,

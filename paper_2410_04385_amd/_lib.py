@@ -20,7 +20,7 @@ EXPORTED = [
     "hatt_plan", "hatt_recompress", "hatt_adaptive_plan", "hatt_recompress_adaptive", "tt_hadamard_explicit", "tt_round_plan", "tt_round",
     "tt_norm_plan", "tt_norm", "hatt_sketch_fill", "hatt_profile_start", "hatt_profile_stop",
     "hatt_profile_class_name", "hatt_last_error", "hatt_version", "hatt_set_qr_method",
-    "hatt_profile_report",
+    "hatt_profile_report", "hatt_batched_plan", "hatt_recompress_batched",
 ]
 PROFILE_CLASSES = 8
 

@@ -155,6 +155,57 @@ def recompress(x: TT, y: TT, ell, *, max_rank: int = 0, tol: float = 0.0, seed: 
     return Result(out, ranks)
 
 
+def batched_plan(pairs, ell: int = 0, *, max_rank: int = 0, tol: float = 0.0, seed: int = 0, variant: int = 1,
+                 ep: float = 0.0):
+    """Plan of recompress_batched: per-pair output and rank offsets, widths,
+    workspace bytes."""
+    npairs = len(pairs)
+    views = [(x.view(), y.view()) for x, y in pairs]
+    xs = (HattTT * npairs)(*[v[0][0] for v in views])
+    ys = (HattTT * npairs)(*[v[1][0] for v in views])
+    o, _ = _opts(int(ell), max_rank, tol, seed, variant, ep, 0)
+    oo = (ctypes.c_int64 * (npairs + 1))()
+    ro = (ctypes.c_int64 * (npairs + 1))()
+    ne = sum(x.d + 1 for x, _ in pairs)
+    eo = (ctypes.c_int64 * ne)()
+    ws = ctypes.c_size_t(0)
+    check("hatt_batched_plan", lib().hatt_batched_plan(npairs, xs, ys, ctypes.byref(o), oo, ro, eo,
+                                                       ctypes.byref(ws)))
+    ells, e = [], 0
+    for x, _ in pairs:
+        ells.append(list(eo[e:e + x.d + 1]))
+        e += x.d + 1
+    return {"out_offset": list(oo), "rank_offset": list(ro), "ell": ells, "ws_bytes": int(ws.value),
+            "_keep": (views, xs, ys)}
+
+
+def recompress_batched(pairs, ell: int = 0, *, max_rank: int = 0, tol: float = 0.0, seed: int = 0,
+                       variant: int = 1, ep: float = 0.0, workspace: Optional[torch.Tensor] = None,
+                       stream=None) -> List[Result]:
+    """Uneven batch: ``pairs`` is a list of (x, y) TT pairs of any shapes;
+    pair p uses the sketch keyed by seed + p; ell <= 0 asks for
+    l_k = max(r_k, s_k) + 8.  Returns one Result per pair (views into one
+    output buffer)."""
+    p = batched_plan(pairs, ell, max_rank=max_rank, tol=tol, seed=seed, variant=variant, ep=ep)
+    views, xs, ys = p["_keep"]
+    dev = pairs[0][0].data.device
+    out = torch.zeros(max(p["out_offset"][-1], 1), dtype=torch.float64, device=dev)
+    ranks = torch.empty(max(p["rank_offset"][-1], 1), dtype=torch.int64, device=dev)
+    if workspace is None or workspace.numel() < p["ws_bytes"]:
+        workspace = torch.empty(max(p["ws_bytes"], 1), dtype=torch.uint8, device=dev)
+    o, _ = _opts(int(ell), max_rank, tol, seed, variant, ep, 0)
+    check("hatt_recompress_batched", lib().hatt_recompress_batched(
+        len(pairs), xs, ys, ctypes.byref(o), ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ranks.data_ptr()),
+        ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr(stream)))
+    res = []
+    for k, (x, _) in enumerate(pairs):
+        a, b = p["out_offset"][k], p["out_offset"][k + 1]
+        tt = TT(out[a:b], x.n, p["ell"][k], x.batch)
+        ra, rb = p["rank_offset"][k], p["rank_offset"][k + 1]
+        res.append(Result(tt, ranks[ra:rb].view(x.batch, x.d + 1)))
+    return res
+
+
 def recompress_adaptive(x: TT, y: TT, tol: float, *, seed: int = 0, oversample: int = 8,
                         max_attempts: int = 8, variant: int = 1, ep: float = 0.0,
                         workspace: Optional[torch.Tensor] = None, stream=None):

@@ -1072,6 +1072,151 @@ hatt_status hatt_recompress(const hatt_tt *x, const hatt_tt *y, const hatt_tt *s
 }
 
 // ---------------------------------------------------------------------------
+// Uneven batches: every pair has its own shape.  Pairs are planned one by one
+// and run on up to kBatchStreams library streams forked from the caller's
+// stream (event wait) and joined back; stream s takes pairs s, s + S, ... in
+// order and reuses one workspace slot, so concurrent pairs never share
+// scratch memory.
+constexpr int kBatchStreams = 4;
+
+struct BatchStreams {
+  int device = -1;
+  hipStream_t s[kBatchStreams] = {};
+  hipEvent_t fork = nullptr, join[kBatchStreams] = {};
+};
+std::vector<BatchStreams> g_bstreams;
+
+static hatt_status batch_streams(BatchStreams **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(HATT_EDEVICE, "hipGetDevice failed");
+  for (auto &b : g_bstreams)
+    if (b.device == dev) {
+      *out = &b;
+      return HATT_OK;
+    }
+  BatchStreams b;
+  b.device = dev;
+  for (int k = 0; k < kBatchStreams; ++k) {
+    if (hipStreamCreateWithFlags(&b.s[k], hipStreamNonBlocking) != hipSuccess)
+      return fail(HATT_EDEVICE, "stream creation failed");
+    if (hipEventCreateWithFlags(&b.join[k], hipEventDisableTiming) != hipSuccess)
+      return fail(HATT_EDEVICE, "event creation failed");
+  }
+  if (hipEventCreateWithFlags(&b.fork, hipEventDisableTiming) != hipSuccess)
+    return fail(HATT_EDEVICE, "event creation failed");
+  g_bstreams.push_back(b);
+  *out = &g_bstreams.back();
+  return HATT_OK;
+}
+
+struct BatchPlan {
+  std::vector<HattSpec> sp;
+  std::vector<std::vector<int64_t>> req;  // per-pair width requests (rule widths)
+  std::vector<int64_t> out_off, rank_off;
+  size_t slot = 0;                        // workspace bytes of one slot
+  int streams = 1;
+};
+
+static hatt_status batch_prepare(int32_t npairs, const hatt_tt *x, const hatt_tt *y, const hatt_opts *o,
+                                 bool need_data, BatchPlan *bp) {
+  if (npairs < 1) return fail(HATT_EINVAL, "npairs must be >= 1");
+  if (x == nullptr || y == nullptr || o == nullptr) return fail(HATT_EINVAL, "NULL argument");
+  if (o->ell_bond != nullptr) return fail(HATT_EINVAL, "per-bond widths are not taken by the uneven batch");
+  bp->sp.assign(npairs, HattSpec{});
+  bp->req.assign(npairs, {});
+  bp->out_off.assign(npairs + 1, 0);
+  bp->rank_off.assign(npairs + 1, 0);
+  size_t slot = 0;
+  for (int32_t p = 0; p < npairs; ++p) {
+    hatt_opts op = *o;
+    op.seed = o->seed + (uint64_t)p;
+    if (o->ell <= 0) {
+      // width rule: l_k = max(r_k, s_k) + 8 (clamped by hatt_prepare)
+      if (x[p].d < 1 || x[p].rank == nullptr || y[p].rank == nullptr || x[p].d != y[p].d)
+        return fail(HATT_ESHAPE, "pair " + std::to_string(p) + ": bad order or ranks");
+      auto &rq = bp->req[p];
+      rq.assign(x[p].d + 1, 1);
+      for (int k = 1; k < x[p].d; ++k) rq[k] = std::max(x[p].rank[k], y[p].rank[k]) + 8;
+      op.ell = 1;
+      op.ell_bond = rq.data();
+    }
+    HattSpec &sp = bp->sp[p];
+    hatt_status st = hatt_prepare(&x[p], &y[p], &op, &sp, need_data);
+    if (st != HATT_OK) return fail(st, "pair " + std::to_string(p) + ": " + g_err);
+    sp.o.ell_bond = nullptr;
+    sp.sketch = nullptr;
+    sp.sketch_stride = 0;
+    sp.out = nullptr;
+    sp.orank = nullptr;
+    Ws meas(nullptr);
+    st = hatt_run(false, sp, meas, nullptr);
+    if (st != HATT_OK) return fail(st, "pair " + std::to_string(p) + ": " + g_err);
+    slot = std::max(slot, (size_t)((meas.off + 255) / 256 * 256));
+    std::vector<int64_t> off;
+    int64_t tot;
+    make_offsets(sp.X.n, sp.ell, &off, &tot);
+    sp.ostride = tot;
+    bp->out_off[p + 1] = bp->out_off[p] + tot * sp.X.batch;
+    bp->rank_off[p + 1] = bp->rank_off[p] + (int64_t)sp.X.batch * (sp.X.d + 1);
+  }
+  bp->slot = std::max<size_t>(slot, 256);
+  bp->streams = std::min<int>(kBatchStreams, npairs);
+  return HATT_OK;
+}
+
+hatt_status hatt_batched_plan(int32_t npairs, const hatt_tt *x, const hatt_tt *y, const hatt_opts *opts,
+                              int64_t *out_offset, int64_t *rank_offset, int64_t *ell_out, size_t *ws_bytes) {
+  BatchPlan bp;
+  hatt_status st = batch_prepare(npairs, x, y, opts, false, &bp);
+  if (st != HATT_OK) return st;
+  if (out_offset)
+    for (int32_t p = 0; p <= npairs; ++p) out_offset[p] = bp.out_off[p];
+  if (rank_offset)
+    for (int32_t p = 0; p <= npairs; ++p) rank_offset[p] = bp.rank_off[p];
+  if (ell_out) {
+    int64_t e = 0;
+    for (int32_t p = 0; p < npairs; ++p)
+      for (int64_t v : bp.sp[p].ell) ell_out[e++] = v;
+  }
+  if (ws_bytes) *ws_bytes = bp.slot * (size_t)bp.streams;
+  g_err.clear();
+  return HATT_OK;
+}
+
+hatt_status hatt_recompress_batched(int32_t npairs, const hatt_tt *x, const hatt_tt *y, const hatt_opts *opts,
+                                    double *out, int64_t *out_rank, void *ws, size_t ws_bytes, void *stream) {
+  BatchPlan bp;
+  hatt_status st = batch_prepare(npairs, x, y, opts, true, &bp);
+  if (st != HATT_OK) return st;
+  if (out == nullptr || out_rank == nullptr) return fail(HATT_EINVAL, "out or out_rank is NULL");
+  const size_t need = bp.slot * (size_t)bp.streams;
+  if (ws == nullptr || ws_bytes < need)
+    return fail(HATT_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  BatchStreams *bs = nullptr;
+  st = batch_streams(&bs);
+  if (st != HATT_OK) return st;
+  hipStream_t caller = (hipStream_t)stream;
+  if (hipEventRecord(bs->fork, caller) != hipSuccess) return fail(HATT_EDEVICE, "event record failed");
+  for (int k = 0; k < bp.streams; ++k)
+    if (hipStreamWaitEvent(bs->s[k], bs->fork, 0) != hipSuccess) return fail(HATT_EDEVICE, "stream wait failed");
+  for (int32_t p = 0; p < npairs; ++p) {
+    const int k = p % bp.streams;
+    HattSpec &sp = bp.sp[p];
+    sp.out = out + bp.out_off[p];
+    sp.orank = out_rank + bp.rank_off[p];
+    Ws w((char *)ws + (size_t)k * bp.slot);
+    st = hatt_run(true, sp, w, bs->s[k]);
+    if (st != HATT_OK) return fail(st, "pair " + std::to_string(p) + ": " + g_err);
+  }
+  for (int k = 0; k < bp.streams; ++k) {
+    if (hipEventRecord(bs->join[k], bs->s[k]) != hipSuccess) return fail(HATT_EDEVICE, "event record failed");
+    if (hipStreamWaitEvent(caller, bs->join[k], 0) != hipSuccess) return fail(HATT_EDEVICE, "stream wait failed");
+  }
+  g_err.clear();
+  return HATT_OK;
+}
+
+// ---------------------------------------------------------------------------
 static hatt_status adapt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_adapt_opts *ao, HattSpec *sp,
                                  std::vector<int64_t> *cap, std::vector<int64_t> *ell0, int *p, int *maxa,
                                  bool need_data) {

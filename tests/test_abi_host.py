@@ -176,3 +176,35 @@ def test_qr_method_switch_and_workspace():
     assert _lib.lib().hatt_set_qr_method(2) == -1
     with pytest.raises(ValueError):
         api.set_qr_method("qr")
+
+
+def test_batched_plan_matches_per_pair_plans():
+    """Uneven batch plan: per-pair widths and output sizes equal the single
+    pair plans (seed + p per pair); the width rule max(r, s) + 8; offsets are
+    cumulative; the workspace covers one slot per stream."""
+    shapes = [([5, 6, 4], [1, 3, 4, 1], [1, 2, 5, 1], 1), ([8] * 6, [1, 6, 7, 8, 7, 6, 1], [1, 5] + [6] * 4 + [1], 2),
+              ([4, 4], [1, 3, 1], [1, 3, 1], 1)]
+    pairs = [(_cpu_tt(n, rx, b), _cpu_tt(n, ry, b)) for n, rx, ry, b in shapes]
+    p = api.batched_plan(pairs, 0, max_rank=5)
+    off, roff = p["out_offset"], p["rank_offset"]
+    assert off[0] == 0 and roff[0] == 0
+    for k, ((x, y), (n, rx, ry, b)) in enumerate(zip(pairs, shapes)):
+        req = [1] + [max(rx[j], ry[j]) + 8 for j in range(1, len(n))] + [1]
+        single = api.plan(x, y, req, max_rank=5, seed=k)
+        assert p["ell"][k] == single["ell"] == oplan.clamp_ell(n, rx, ry, req)
+        assert off[k + 1] - off[k] == b * single["out_elems"]
+        assert roff[k + 1] - roff[k] == b * (len(n) + 1)
+        assert p["ws_bytes"] >= single["ws_bytes"]
+    q = api.batched_plan(pairs, 7)
+    for k, (n, rx, ry, b) in enumerate(shapes):
+        assert q["ell"][k] == oplan.clamp_ell(n, rx, ry, 7)
+
+
+def test_batched_plan_errors():
+    x = _cpu_tt([4, 5], [1, 3, 1])
+    y = _cpu_tt([4, 6], [1, 3, 1])
+    with pytest.raises(HattError) as e:
+        api.batched_plan([(x, x), (x, y)], 4)
+    assert e.value.status == -2
+    assert b"pair 1" in _lib.lib().hatt_last_error()
+    assert _lib.lib().hatt_batched_plan(0, None, None, None, None, None, None, None) == -1

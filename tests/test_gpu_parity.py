@@ -383,3 +383,65 @@ def test_qr_methods_agree_with_oracle(method):
     got = res.train(0)
     assert tt.ranks(got) == tt.ranks(ref)
     assert tt.rel_err(got, ref) <= 1e-10
+
+
+def _rule_ell(y, z):
+    rx, ry = tt.ranks(y), tt.ranks(z)
+    req = [1] + [max(rx[k], ry[k]) + 8 for k in range(1, len(rx) - 1)] + [1]
+    return plan.clamp_ell(tt.modes(y), rx, ry, req)
+
+
+def test_batched_uneven_pairs_match_oracle():
+    """Uneven batch of 10 pairs (orders 2..7, modes 3..8, ranks 1..9, some
+    pairs with two trains): every train matches the oracle run with the
+    pair's own sketch (key seed + p), truncated to rank 6."""
+    rng = np.random.default_rng(17)
+    pairs, trains = [], []
+    for p in range(10):
+        d = int(rng.integers(2, 8))
+        n = [int(rng.choice([3, 4, 8])) for _ in range(d)]
+        rx = wk.feasible_ranks(n, int(rng.integers(1, 10)))
+        ry = wk.feasible_ranks(n, int(rng.integers(1, 10)))
+        b = 2 if p % 3 == 0 else 1
+        ys = [wk.gaussian_tt(rng, n, rx) for _ in range(b)]
+        zs = [wk.gaussian_tt(rng, n, ry) for _ in range(b)]
+        pairs.append((H.TT.from_cores(ys), H.TT.from_cores(zs)))
+        trains.append((ys, zs))
+    _say("hatt_recompress_batched: 10 uneven pairs, rule widths, max_rank 6")
+    res = H.recompress_batched(pairs, 0, max_rank=6, seed=500)
+    torch.cuda.synchronize()
+    for p, (ys, zs) in enumerate(trains):
+        ell = _rule_ell(ys[0], zs[0])
+        R = philox.sketch(500 + p, tt.modes(ys[0]), ell)
+        for b in range(len(ys)):
+            ref = rounding.tt_round(ohatt.hatt(ys[b], zs[b], R), max_rank=6)
+            got = res[p].train(b)
+            assert tt.ranks(got) == tt.ranks(ref), p
+            assert tt.rel_err(got, ref) <= 1e-10, p
+
+
+def test_batched_workload_sample():
+    """The 512-pair uneven workload's distribution (d in 8..32, n in
+    {16, 32, 64}, ranks 8..48, spectral cores), first 24 pairs at full size,
+    tol 1e-6: the three cheapest pairs match the oracle; every pair's kept
+    ranks respect the planned capacities."""
+    shapes = wk.batched_pair_shapes(3, 24)
+    pairs, cores = [], []
+    for p, (d, n, rx, ry) in enumerate(shapes):
+        y, z = wk.spectral_pair(7000 + p, d, n, rx, ry)
+        pairs.append((H.TT.from_cores([y]), H.TT.from_cores([z])))
+        cores.append((y, z))
+    _say("hatt_recompress_batched: 24 pairs of the uneven workload, tol 1e-6")
+    res = H.recompress_batched(pairs, 0, tol=1e-6, seed=900)
+    torch.cuda.synchronize()
+    cost = [d * n * rx * ry for (d, n, rx, ry) in shapes]
+    for p in np.argsort(cost)[:3]:
+        y, z = cores[p]
+        ell = _rule_ell(y, z)
+        ref = rounding.tt_round(ohatt.hatt(y, z, philox.sketch(900 + int(p), tt.modes(y), ell)), tol=1e-6)
+        got = res[p].train(0)
+        assert tt.ranks(got) == tt.ranks(ref)
+        assert tt.rel_err(got, ref) <= 1e-9
+    for p in range(len(pairs)):
+        kept = res[p].ranks[0].cpu().tolist()
+        assert all(1 <= k <= c for k, c in zip(kept, res[p].out.ranks))
