@@ -20,6 +20,8 @@ import re
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -30,11 +32,13 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=128, help="pairs recompressed per step")
+    ap.add_argument("--batch", type=int, default=512, help="pairs recompressed per step")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-explicit", action="store_true")
     ap.add_argument("--eager", action="store_true", help="launch kernels directly instead of replaying a HIP graph")
+    ap.add_argument("--workload", choices=["spectral", "batched"], default="spectral",
+                    help="spectral: the metric's workload; batched: the 512-pair uneven workload (own JSON line)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (reference dispatch for "
                          "hardware byte counters)")
@@ -99,28 +103,66 @@ def _roofline(report, batch, steps, perfmodel):
     achieved = per_launch / avg_s / 1e12
     peak = perfmodel.PEAK_FP64_TFLOPS
     return {"kernel": dom, "bound": gr["bound"], "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": _traffic(dom),
+            "frac": achieved / peak, "traffic": _traffic(dom, batch),
             "avg_launch_us": 1e6 * avg_s, "launches_per_step": gr["calls"] / steps,
             "algorithmic_flop_per_launch": per_launch}
 
 
-def _traffic(kernel):
+def _traffic(kernel, batch):
     """HBM bytes per launch of `kernel` from the committed hardware-counter
-    summary, or None when none was taken or the kernel source has changed
-    since."""
+    summary, or None when none was taken at this batch size or the kernel
+    source has changed since."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         data = json.load(fh)
     ent = data.get(kernel)
-    if not ent:
+    if not ent or ent.get("batch") != batch:
         return None
     src = os.path.join(ROOT, ent["source"])
     with open(src, "rb") as fh:
         if hashlib.sha256(fh.read()).hexdigest() != ent["source_sha256"]:
             return None
     return ent["hbm_bytes_per_launch"]
+
+
+def _bench_batched(args, torch, wk, H) -> int:
+    """512 independent pairs of uneven shapes (d in 8..32, n in {16, 32, 64},
+    ranks 8..48, spectral cores), widths max(r, s) + 8, truncation at tol
+    1e-6; one step recompresses all of them."""
+    cfg = wk.WORKLOADS["batched"]
+    shapes = wk.batched_pair_shapes(1, cfg["pairs"])
+    print(f"[bench] generating {len(shapes)} uneven pairs", file=sys.stderr, flush=True)
+    pairs = []
+    for p, (d, n, rx, ry) in enumerate(shapes):
+        y, z = wk.spectral_pair(20000 + p, d, n, rx, ry)
+        pairs.append((H.TT.from_cores([y]), H.TT.from_cores([z])))
+    plan = H.batched_plan(pairs, 0, tol=cfg["tol"], seed=77)
+    ws = torch.empty(plan["ws_bytes"], dtype=torch.uint8, device="cuda")
+    print(f"[bench] workspace {plan['ws_bytes'] / 2**20:.1f} MiB, output {plan['out_offset'][-1] * 8 / 2**20:.1f} MiB",
+          file=sys.stderr, flush=True)
+
+    def step():
+        return H.recompress_batched(pairs, 0, tol=cfg["tol"], seed=77, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    gpu_s, wall_s = _time_steps(step, args.steps, torch)
+    res = step()
+    torch.cuda.synchronize()
+    kept = [r.ranks[0].cpu().tolist() for r in res]
+    value = len(pairs) * args.steps / wall_s
+    line = {"metric": "HaTT recompressions/s, uneven batch of 512 pairs", "value": value,
+            "unit": "recompressions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": 1000.0 * wall_s / args.steps, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "batched: 512 pairs, d 8..32, n {16,32,64}, r 8..48, l = max(r,s)+8, tol 1e-6",
+                       "launch": "eager, 4 library streams"},
+            "mean_kept_rank": float(np.mean([max(k) for k in kept]))}
+    print(json.dumps(line), flush=True)
+    return 0
 
 
 def main() -> int:
@@ -141,6 +183,8 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.workload == "batched":
+        return _bench_batched(args, torch, wk, H)
     cfg = wk.WORKLOADS["spectral"]
     d, n, r, ell, cap = cfg["d"], cfg["n"], cfg["r"], cfg["ell"], cfg["max_rank"]
     B = args.batch

@@ -48,3 +48,13 @@ def test_sandwich_site_flops():
     # per (i, g): T = C ZR (RI x SI x SO) then YL T (RA x RI x SO), 2 flops per multiply-add
     assert f == 2.0 * 32 * 40 * (20 * 20 * 20 + 20 * 20 * 20) * 2
     assert b._site_group("qr: chol 40", 1) is None
+
+
+def test_traffic_record_is_tied_to_batch_and_source():
+    b = _bench()
+    import json
+    data = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    for kernel, ent in data.items():
+        assert b._traffic(kernel, ent["batch"]) == ent["hbm_bytes_per_launch"]
+        assert b._traffic(kernel, ent["batch"] + 1) is None
+    assert b._traffic("no_such_kernel", 512) is None
