@@ -260,7 +260,7 @@ struct QrOp {
   bool wide = false;                 // m < n, n > kQrMaxCols: QR of the first m columns, then R2 = Q^T A2
   std::shared_ptr<QrOp> sub;
   QrPlan direct{};
-  std::vector<QrPlan> panels;
+  std::vector<QrOp> panels;          // big: one QR per panel (CholeskyQR2 or TSQR)
   int64_t ws_doubles = 0;  // per pair
   int64_t ws_tree = 0;     // big: TSQR tree part at the front; chol: fallback TSQR tree
 };
@@ -305,13 +305,13 @@ bool qr_prepare(int64_t m, int64_t n, QrOp *op) {
   int64_t w = 0;
   for (int64_t c0 = 0; c0 < n; c0 += kPanel) {
     const int64_t cw = std::min(kPanel, n - c0);
-    QrPlan pl;
-    if (!qr_make_plan(m, cw, &pl)) return false;
+    QrOp pl;
+    if (!qr_prepare(m, cw, &pl) || pl.big || pl.wide) return false;
     op->panels.push_back(pl);
     w = std::max(w, pl.ws_doubles);
   }
   op->ws_tree = w;
-  // TSQR tree + S1, S2 (n x kPanel each) + R1, R2 (kPanel x kPanel each)
+  // panel QR scratch + S1, S2 (n x kPanel each) + R1, R2 (kPanel x kPanel each)
   op->ws_doubles = w + 2 * n * kPanel + 2 * kPanel * kPanel;
   return true;
 }
@@ -388,7 +388,8 @@ hatt_status qr_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, int64_t rbuf
     CMat Qpanc{Qpan.ptr, Qpan.rs, Qpan.cs, Qpan.bs};
     Mat rdiag = R.ptr ? Mat{R.ptr + c0 * R.rs + c0 * R.cs, R.rs, R.cs, R.bs} : Mat{nullptr, 0, 0, 0};
     if (c0 == 0) {
-      LAUNCH(launch_tsqr(op.panels[pi], Qpanc, Qpan, rdiag, ws, wsp, P, st));
+      hatt_status sp0 = qr_exec(run, op.panels[pi], Qpanc, Qpan, rdiag, rbuf, ws, wsp, P, gc, st);
+      if (sp0 != HATT_OK) return sp0;
       continue;
     }
     // first pass: S1 goes straight into R's block above the diagonal
@@ -399,14 +400,16 @@ hatt_status qr_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, int64_t rbuf
     sg = gemm(run, gc, Qprev, s1c, Qpan, m, cw, c0, -1.0, 1.0, P, st, false);
     if (sg != HATT_OK) return sg;
     Mat r1 = R.ptr ? Mat{r1buf, cw, 1, wsp} : Mat{nullptr, 0, 0, 0};
-    LAUNCH(launch_tsqr(op.panels[pi], Qpanc, Qpan, r1, ws, wsp, P, st));
+    sg = qr_exec(run, op.panels[pi], Qpanc, Qpan, r1, rbuf, ws, wsp, P, gc, st);
+    if (sg != HATT_OK) return sg;
     // second pass on the orthonormalised panel
     sg = gemm(run, gc, QprevT, Qpanc, Mat{s2buf, cw, 1, wsp}, c0, cw, m, 1.0, 0.0, P, st, true);
     if (sg != HATT_OK) return sg;
     sg = gemm(run, gc, Qprev, CMat{s2buf, cw, 1, wsp}, Qpan, m, cw, c0, -1.0, 1.0, P, st, false);
     if (sg != HATT_OK) return sg;
     Mat r2 = R.ptr ? Mat{r2buf, cw, 1, wsp} : Mat{nullptr, 0, 0, 0};
-    LAUNCH(launch_tsqr(op.panels[pi], Qpanc, Qpan, r2, ws, wsp, P, st));
+    sg = qr_exec(run, op.panels[pi], Qpanc, Qpan, r2, rbuf, ws, wsp, P, gc, st);
+    if (sg != HATT_OK) return sg;
     if (R.ptr) {
       // R(prev, p) += S2 R1;  R(p, p) = R2 R1
       sg = gemm(run, gc, CMat{s2buf, cw, 1, wsp}, CMat{r1buf, cw, 1, wsp}, s1, c0, cw, cw, 1.0, 1.0, P, st,

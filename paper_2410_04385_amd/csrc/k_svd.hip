@@ -378,6 +378,8 @@ hipError_t launch_svd_big_prepare(const double *r, int64_t rbs, int kr, int nc, 
   return hipGetLastError();
 }
 
+constexpr int kBigInnerSweeps = 1;
+
 __global__ __launch_bounds__(256) void svd_big_round_kernel(double *acol, int64_t acs, int kr, int nc, int bw,
                                                             int nb, int t, int *flags) {
   extern __shared__ double A[];  // w columns of length kr
@@ -407,7 +409,10 @@ __global__ __launch_bounds__(256) void svd_big_round_kernel(double *acol, int64_
   while (tpg > 1 && tpg * npairs > 256) tpg >>= 1;
   const int grp = tid / tpg, gl = tid % tpg;
   __syncthreads();
-  for (int sweep = 0; sweep < 30; ++sweep) {
+  // one cyclic sweep over the pairs of the two blocks per round: every
+  // outer sweep is then at least one full cyclic Jacobi sweep over all
+  // column pairs, and convergence is judged by the outer sweeps
+  for (int sweep = 0; sweep < kBigInnerSweeps; ++sweep) {
     if (tid == 0) s_rot = 0;
     __syncthreads();
     int myrot = 0;
