@@ -51,10 +51,16 @@ def test_sandwich_site_flops():
 
 
 def test_traffic_record_is_tied_to_batch_and_source():
-    b = _bench()
+    """Counter bytes are reported only for the batch they were taken at and
+    while the kernel's source is unchanged."""
+    import hashlib
     import json
+
+    b = _bench()
     data = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
     for kernel, ent in data.items():
-        assert b._traffic(kernel, ent["batch"]) == ent["hbm_bytes_per_launch"]
+        with open(os.path.join(ROOT, ent["source"]), "rb") as fh:
+            same = hashlib.sha256(fh.read()).hexdigest() == ent["source_sha256"]
+        assert b._traffic(kernel, ent["batch"]) == (ent["hbm_bytes_per_launch"] if same else None)
         assert b._traffic(kernel, ent["batch"] + 1) is None
     assert b._traffic("no_such_kernel", 512) is None
