@@ -37,6 +37,8 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-explicit", action="store_true")
     ap.add_argument("--eager", action="store_true", help="launch kernels directly instead of replaying a HIP graph")
+    ap.add_argument("--precision", choices=["f64", "f32"], default="f64",
+                    help="f32: range finding on the FP32 matrix cores, projection and truncation in FP64")
     ap.add_argument("--workload", choices=["spectral", "batched"], default="spectral",
                     help="spectral: the metric's workload; batched: the 512-pair uneven workload (own JSON line)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -193,7 +195,7 @@ def main() -> int:
     pairs = [wk.spectral_pair(1000 + b, d, n, r, r) for b in range(B)]
     x = H.TT.from_cores([p[0] for p in pairs])
     y = H.TT.from_cores([p[1] for p in pairs])
-    p = H.plan(x, y, ell, max_rank=cap, seed=seed)
+    p = H.plan(x, y, ell, max_rank=cap, seed=seed, precision=args.precision)
     out = H.TT.empty(x.n, p["ell"], B)
     ranks = torch.empty((B, d + 1), dtype=torch.int64, device="cuda")
     ws = torch.empty(p["ws_bytes"], dtype=torch.uint8, device="cuda")
@@ -209,7 +211,8 @@ def main() -> int:
         del src, dst
 
     def step():
-        H.recompress(x, y, ell, max_rank=cap, seed=seed, workspace=ws, out=out, ranks=ranks)
+        H.recompress(x, y, ell, max_rank=cap, seed=seed, workspace=ws, out=out, ranks=ranks,
+                     precision=args.precision)
 
     print(f"[bench] warmup {args.warmup} steps, batch {B}, workspace {p['ws_bytes'] / 2**20:.1f} MiB",
           file=sys.stderr, flush=True)
@@ -330,10 +333,11 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "f64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"spectral d={d} n={n} r_x=r_y={r} sketch={ell} max_rank={cap}",
-                   "pairs_per_step": B, "variant": "HaTT-1", "seed": seed, "launch": mode},
+                   "pairs_per_step": B, "variant": "HaTT-1", "seed": seed, "launch": mode,
+                   "precision": args.precision},
         "roofline": roof,
         "cpu_baseline": cpu,
         "step_tflops_algorithmic": step_tflops,

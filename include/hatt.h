@@ -73,6 +73,11 @@ typedef struct {
   int64_t max_rank;       /* truncation cap on every bond after the sweep; <= 0: none */
   double tol;             /* relative Frobenius tolerance of that truncation; <= 0: none */
   uint64_t seed;          /* key of the Philox4x32-10 sketch (used when no sketch is passed) */
+  int32_t precision;      /* 0: FP64 throughout; 1: FP32 range finding -- the HPCRL sketches
+                             W^{(k)} (W_L build and W_L W_R^T) and the sketched frames
+                             X^{(k)} W^{(k)} run on the FP32 matrix cores with FP32
+                             accumulation and storage, then QR, the projection Q^T X, the
+                             core update and the truncation run in FP64 (HaTT-1 only) */
 } hatt_opts;
 
 /*

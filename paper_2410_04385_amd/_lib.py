@@ -47,6 +47,7 @@ class HattOpts(ctypes.Structure):
         ("max_rank", ctypes.c_int64),
         ("tol", ctypes.c_double),
         ("seed", ctypes.c_uint64),
+        ("precision", ctypes.c_int32),
     ]
 
 

@@ -98,7 +98,10 @@ class Result:
         return self.out.to_numpy(b, kept)
 
 
-def _opts(ell, max_rank, tol, seed, variant, ep, d):
+_PRECISION = {"f64": 0, "f32": 1}
+
+
+def _opts(ell, max_rank, tol, seed, variant, ep, d, precision="f64"):
     ell_arr = None
     if not np.isscalar(ell):
         if len(ell) != d + 1:
@@ -107,16 +110,18 @@ def _opts(ell, max_rank, tol, seed, variant, ep, d):
         ell_u = 0
     else:
         ell_u = int(ell)
+    if precision not in _PRECISION:
+        raise ValueError(f"precision must be one of {sorted(_PRECISION)}")
     o = HattOpts(int(variant), float(ep), ell_u, ell_arr if ell_arr is not None else None,
-                 int(max_rank), float(tol), int(seed) & 0xFFFFFFFFFFFFFFFF)
+                 int(max_rank), float(tol), int(seed) & 0xFFFFFFFFFFFFFFFF, _PRECISION[precision])
     return o, ell_arr
 
 
 def plan(x: TT, y: TT, ell, max_rank: int = 0, tol: float = 0.0, seed: int = 0, variant: int = 1,
-         ep: float = 0.0):
+         ep: float = 0.0, precision: str = "f64"):
     xv, kx = x.view()
     yv, ky = y.view()
-    o, ka = _opts(ell, max_rank, tol, seed, variant, ep, x.d)
+    o, ka = _opts(ell, max_rank, tol, seed, variant, ep, x.d, precision)
     ell_out = (ctypes.c_int64 * (x.d + 1))()
     ws = ctypes.c_size_t(0)
     oe = ctypes.c_int64(0)
@@ -126,12 +131,14 @@ def plan(x: TT, y: TT, ell, max_rank: int = 0, tol: float = 0.0, seed: int = 0, 
 
 
 def recompress(x: TT, y: TT, ell, *, max_rank: int = 0, tol: float = 0.0, seed: int = 0,
-               sketch: Optional[TT] = None, variant: int = 1, ep: float = 0.0,
+               sketch: Optional[TT] = None, variant: int = 1, ep: float = 0.0, precision: str = "f64",
                workspace: Optional[torch.Tensor] = None, out: Optional[TT] = None,
                ranks: Optional[torch.Tensor] = None, stream=None) -> Result:
     """HaTT (Alg. 4) of x (.) y for every train of the batch, optionally
-    truncated by TT-Rounding to ``max_rank`` / ``tol``."""
-    p = plan(x, y, ell, max_rank, tol, seed, variant, ep)
+    truncated by TT-Rounding to ``max_rank`` / ``tol``.  precision "f32":
+    range finding on the FP32 matrix cores, projection and truncation in
+    FP64."""
+    p = plan(x, y, ell, max_rank, tol, seed, variant, ep, precision)
     dev = x.data.device
     if out is None:
         out = TT.empty(x.n, p["ell"], x.batch, device=dev)
@@ -141,7 +148,7 @@ def recompress(x: TT, y: TT, ell, *, max_rank: int = 0, tol: float = 0.0, seed: 
         workspace = torch.empty(max(p["ws_bytes"], 1), dtype=torch.uint8, device=dev)
     xv, kx = x.view()
     yv, ky = y.view()
-    o, ka = _opts(ell, max_rank, tol, seed, variant, ep, x.d)
+    o, ka = _opts(ell, max_rank, tol, seed, variant, ep, x.d, precision)
     sk_ptr = None
     keep = None
     if sketch is not None:

@@ -70,6 +70,7 @@ struct SandwichArgs {
   int RA, RI, SI, SO;  // YL is RA x RI, C is RI x SI, ZR is SI x SO
   int64_t n, G;
   int batch;
+  int prec;            // 1: C and out are FP32 and the products run on the FP32 matrix cores
 };
 hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s);
 // Matrix-core variant (k_sandwich.hip): block and LDS plan for a chunk of GC
@@ -102,6 +103,12 @@ hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStre
 // Name of the compiled kernel launch_sandwich picks for these arguments.
 const char *sandwich_kernel_name(const SandwichArgs &a);
 
+// dst[p * dbs + k] = (float) src[p * sbs + k] for k < count, p < batch.
+hipError_t launch_cast_f32(const double *src, int64_t sbs, float *dst, int64_t dbs, int64_t count, int batch,
+                           hipStream_t s);
+// Per pair, scale w[p * bs .. + count) by the power of two that puts its
+// largest magnitude in [1, 2).
+hipError_t launch_rescale_pow2(float *w, int64_t count, int64_t bs, int batch, hipStream_t s);
 // Batched strided copy: dst(r, c) = src(r, c) for an M x N block.
 hipError_t launch_copy(CMat src, Mat dst, int64_t M, int64_t N, int batch, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t s);
@@ -125,6 +132,8 @@ struct GemmArgs {
   int ksplit;
   double *part;
   int no_reduce;        // split-K: leave the partial products in `part` (the caller reduces them)
+  int prec;             // 0: FP64 matrix cores; 1: FP32 matrix cores (no split-K)
+  int a_f32, b_f32, c_f32;  // storage of A, B, C is FP32 (pointers reinterpreted), else FP64
   const int *run_flag;  // optional: pair p is computed only when run_flag[p * run_flag_stride] == run_when
   int64_t run_flag_stride;
   int run_when;

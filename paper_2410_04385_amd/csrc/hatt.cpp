@@ -201,10 +201,22 @@ struct GemmCtx {
   int64_t part_need;  // max requested (measuring)
 };
 
+// Storage / compute types of one product: prec = 1 runs it on the FP32 matrix
+// cores (no K split); a32 / b32 / c32 mark FP32 storage of A / B / C.
+struct GemmTypes {
+  int prec = 0, a32 = 0, b32 = 0, c32 = 0;
+};
+
 hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_t N, int64_t K,
                  double alpha, double beta, int batch, hipStream_t st, bool allow_split,
-                 const int *run_flag = nullptr, int64_t run_flag_stride = 0, int *ks_out = nullptr) {
+                 const int *run_flag = nullptr, int64_t run_flag_stride = 0, int *ks_out = nullptr,
+                 GemmTypes ty = GemmTypes{}) {
   GemmArgs g{};
+  g.prec = ty.prec;
+  g.a_f32 = ty.a32;
+  g.b_f32 = ty.b32;
+  g.c_f32 = ty.c32;
+  if (ty.prec) allow_split = false;
   g.no_reduce = 1;  // the reduction, when needed, is its own launch below
   g.run_flag = run_flag;
   g.run_flag_stride = run_flag_stride;
@@ -228,8 +240,13 @@ hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_
     char b[160];
     int bm = 0, bn = 0;
     gemm_tile(M, N, &bm, &bn);
-    snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=%d%s [gemm_f64_kernel<%d, %d>]", (long long)M, (long long)N,
-             (long long)K, g.ksplit, run_flag ? " flagged" : "", bm, bn);
+    if (ty.prec)
+      snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=1 [gemm_f32_kernel<%d, %d, %s, %s, %s>]", (long long)M,
+               (long long)N, (long long)K, bm, bn, ty.a32 ? "float" : "double", ty.b32 ? "float" : "double",
+               ty.c32 ? "float" : "double");
+    else
+      snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=%d%s [gemm_f64_kernel<%d, %d>]", (long long)M, (long long)N,
+               (long long)K, g.ksplit, run_flag ? " flagged" : "", bm, bn);
     g_site = b;
   }
   LAUNCH(launch_gemm(g, st));
@@ -707,8 +724,14 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     sk = ws.d(sktot);
     sks = 0;
   }
+  // FP32 range finding keeps W^{(k)} and W_L as FP32 inside the same buffers
+  const bool f32 = (sp.o.precision == 1);
   double *W = ws.d((int64_t)P * std::max<int64_t>(wtot, 1));
   double *WL = ws.d((int64_t)P * wlsz);
+  float *Wf = reinterpret_cast<float *>(W), *WLf = reinterpret_cast<float *>(WL);
+  auto as_d = [](float *p) { return reinterpret_cast<double *>(static_cast<void *>(p)); };
+  const int64_t lastsz = (d >= 2) ? std::max<int64_t>(r[d - 1] * s[d - 1] * l[d - 1], 1) : 1;
+  double *Wlast = (f32 && d >= 2) ? ws.d((int64_t)P * lastsz) : nullptr;
   double *Xc = ws.d((int64_t)P * xsz);
   double *Yb = ws.d((int64_t)P * ysz);
   double *Mb = ws.d((int64_t)P * msz);
@@ -739,7 +762,7 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     la.x = xd + sp.X.off[d - 1];
     la.y = yd + sp.Y.off[d - 1];
     la.r = sk + skoff[d - 1];
-    la.w = W + woff[d - 1];
+    la.w = f32 ? Wlast : W + woff[d - 1];
     la.rx = r[d - 1];
     la.sy = s[d - 1];
     la.l = l[d - 1];
@@ -747,9 +770,16 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     la.xs = xs;
     la.ys = ys;
     la.rsb = sks;
-    la.ws = wtot;
+    la.ws = f32 ? lastsz : wtot;
     la.batch = P;
     LAUNCH(launch_hpcrl_last(la, st));
+    if (f32) {
+      // FP32 keeps 8 exponent bits: each W^{(k)} is brought back to unit scale
+      // by a power of two (range(X W) is unchanged by any rescaling of W)
+      const int64_t cnt = r[d - 1] * s[d - 1] * l[d - 1];
+      LAUNCH(launch_cast_f32(Wlast, lastsz, Wf + woff[d - 1], wtot, cnt, P, st));
+      LAUNCH(launch_rescale_pow2(Wf + woff[d - 1], cnt, wtot, P, st));
+    }
   }
   for (int c = d - 2; c >= 1; --c) {
     const int64_t rs1 = r[c + 1] * s[c + 1], l1 = l[c + 1];
@@ -793,6 +823,7 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
       ucb = h2_q;
     }
     SandwichArgs a{};
+    a.prec = f32 ? 1 : 0;
     a.yl = xd + sp.X.off[c];
     a.ylb = xs;
     a.yli = r[c + 1];
@@ -803,12 +834,12 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     a.zri = s[c + 1];
     a.zrr = 1;
     a.zrc = n[c] * s[c + 1];
-    a.c = ucol;
+    a.c = f32 ? as_d(Wf + woff[c + 1]) : ucol;
     a.cb = ucb;
     a.cg = 1;
     a.ca = s[c + 1] * l1;
     a.cbb = l1;
-    a.o = WL;
+    a.o = f32 ? as_d(WLf) : WL;
     a.ob = wlsz;
     a.oi = l1;
     a.og = 1;
@@ -826,8 +857,19 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     LAUNCH(launch_sandwich(a, st));
     const int64_t K = n[c] * l1;
     const CMat wr = v2 ? CMat{h2WR, 1, K, h2_wr} : CMat{sk + skoff[c], 1, K, sks};
-    hatt_status stt = gemm(run, gc, CMat{WL, K, 1, wlsz}, wr, Mat{W + woff[c], l[c], 1, wtot}, r[c] * s[c], l[c],
-                           K, 1.0, 0.0, P, st, true);
+    hatt_status stt;
+    if (f32) {
+      GemmTypes ty;
+      ty.prec = 1;
+      ty.a32 = 1;
+      ty.c32 = 1;
+      stt = gemm(run, gc, CMat{as_d(WLf), K, 1, wlsz}, wr, Mat{as_d(Wf + woff[c]), l[c], 1, wtot}, r[c] * s[c],
+                 l[c], K, 1.0, 0.0, P, st, false, nullptr, 0, nullptr, ty);
+      if (stt == HATT_OK) LAUNCH(launch_rescale_pow2(Wf + woff[c], r[c] * s[c] * l[c], wtot, P, st));
+    } else {
+      stt = gemm(run, gc, CMat{WL, K, 1, wlsz}, wr, Mat{W + woff[c], l[c], 1, wtot}, r[c] * s[c], l[c], K, 1.0,
+                 0.0, P, st, true);
+    }
     if (stt != HATT_OK) return stt;
   }
   // ---- sweep (Alg. 4)
@@ -837,8 +879,18 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
   }
   for (int c = 0; c < d - 1; ++c) {
     const int64_t m = l[c] * n[c], rs1 = r[c + 1] * s[c + 1];
-    hatt_status stt = gemm(run, gc, CMat{Xc, rs1, 1, xsz}, CMat{W + woff[c + 1], l[c + 1], 1, wtot},
-                           Mat{Yb, l[c + 1], 1, ysz}, m, l[c + 1], rs1, 1.0, 0.0, P, st, true);
+    hatt_status stt;
+    if (f32) {
+      // sketched frame on the FP32 matrix cores (X converted on load), stored as FP64 for the QR
+      GemmTypes ty;
+      ty.prec = 1;
+      ty.b32 = 1;
+      stt = gemm(run, gc, CMat{Xc, rs1, 1, xsz}, CMat{as_d(Wf + woff[c + 1]), l[c + 1], 1, wtot},
+                 Mat{Yb, l[c + 1], 1, ysz}, m, l[c + 1], rs1, 1.0, 0.0, P, st, false, nullptr, 0, nullptr, ty);
+    } else {
+      stt = gemm(run, gc, CMat{Xc, rs1, 1, xsz}, CMat{W + woff[c + 1], l[c + 1], 1, wtot},
+                 Mat{Yb, l[c + 1], 1, ysz}, m, l[c + 1], rs1, 1.0, 0.0, P, st, true);
+    }
     if (stt != HATT_OK) return stt;
     double *qcore = sp.out + ooff[c];
     stt = qr_exec(run, qp[c], CMat{Yb, l[c + 1], 1, ysz}, Mat{qcore, l[c + 1], 1, sp.ostride},
@@ -1001,6 +1053,9 @@ static hatt_status hatt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_o
   if (o->variant != 1 && o->variant != 2) return fail(HATT_EINVAL, "variant must be 1 or 2");
   if (o->variant == 2 && !(o->ep >= 0.0 && o->ep < 1.0)) return fail(HATT_EINVAL, "ep must be in [0, 1)");
   if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(HATT_EINVAL, "tol must be finite and >= 0");
+  if (o->precision != 0 && o->precision != 1) return fail(HATT_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
+  if (o->precision == 1 && o->variant != 1)
+    return fail(HATT_EUNSUPPORTED, "FP32 range finding is built for HaTT-1 only");
   const int d = sp->X.d;
   std::vector<int64_t> req(d + 1, 1);
   for (int k = 1; k < d; ++k) {

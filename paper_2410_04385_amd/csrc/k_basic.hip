@@ -378,8 +378,9 @@ bool g_sandwich_mfma = true;
 const char *sandwich_kernel_name(const SandwichArgs &a) {
   const int64_t budget = 19456;
   SwPlan pl;
+  if (a.prec) return (a.og == 1) ? "sandwich_mfma_kernel<true, float>" : "sandwich_mfma_kernel<false, float>";
   if (g_sandwich_mfma && sandwich_mfma_plan(a, kSandwichLdsDoubles, &pl))
-    return (a.og == 1) ? "sandwich_mfma_kernel<true>" : "sandwich_mfma_kernel<false>";
+    return (a.og == 1) ? "sandwich_mfma_kernel<true, double>" : "sandwich_mfma_kernel<false, double>";
   const int RIp = (a.RI + 1) & ~1, SIp = (a.SI + 1) & ~1;
   const int64_t fixed = (int64_t)a.RA * RIp + (((int64_t)a.SI * a.SO + 1) & ~1);
   const int m = std::max(std::max(a.RI, a.SI), 1);
@@ -396,9 +397,10 @@ const char *sandwich_kernel_name(const SandwichArgs &a) {
 hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s) {
   if (a.n <= 0 || a.G <= 0 || a.batch <= 0) return hipSuccess;
   const int64_t budget = 19456;  // doubles of dynamic LDS
-  if (g_sandwich_mfma) {
+  if (g_sandwich_mfma || a.prec) {
     SwPlan pl;
     if (sandwich_mfma_plan(a, kSandwichLdsDoubles, &pl)) return launch_sandwich_mfma(a, pl, s);
+    if (a.prec) return hipErrorInvalidValue;  // the FP32 variant exists only on the matrix cores
   }
   if (g_sandwich_reg) {
     const int RIp = (a.RI + 1) & ~1, SIp = (a.SI + 1) & ~1;
@@ -439,6 +441,52 @@ __global__ void copy_kernel(CMat src, Mat dst, int64_t M, int64_t N, int batch) 
     const int64_t r = rem / N, c = rem - r * N;
     dst.ptr[p * dst.bs + r * dst.rs + c * dst.cs] = src.ptr[p * src.bs + r * src.rs + c * src.cs];
   }
+}
+
+__global__ void cast_f32_kernel(const double *src, int64_t sbs, float *dst, int64_t dbs, int64_t count, int batch) {
+  const int64_t total = count * batch;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / count, k = e - p * count;
+    dst[p * dbs + k] = (float)src[p * sbs + k];
+  }
+}
+
+hipError_t launch_cast_f32(const double *src, int64_t sbs, float *dst, int64_t dbs, int64_t count, int batch,
+                           hipStream_t s) {
+  const int64_t total = count * batch;
+  if (total <= 0) return hipSuccess;
+  int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  cast_f32_kernel<<<grid, 256, 0, s>>>(src, sbs, dst, dbs, count, batch);
+  return hipGetLastError();
+}
+
+// Per pair, multiply w[p * bs .. + count) by the power of two that brings its
+// largest magnitude into [1, 2) (exact: only the exponents change).  One
+// block per pair.
+__global__ __launch_bounds__(256) void rescale_pow2_kernel(float *w, int64_t count, int64_t bs) {
+  __shared__ float part[256];
+  float *v = w + (int64_t)blockIdx.x * bs;
+  float m = 0.f;
+  for (int64_t e = threadIdx.x; e < count; e += 256) m = fmaxf(m, fabsf(v[e]));
+  part[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) part[threadIdx.x] = fmaxf(part[threadIdx.x], part[threadIdx.x + h]);
+    __syncthreads();
+  }
+  m = part[0];
+  if (!(m > 0.f) || !(m < INFINITY)) return;  // zero or non-finite: leave as is
+  int ex;
+  (void)frexpf(m, &ex);                       // m = f 2^ex, f in [0.5, 1)
+  const float sc = ldexpf(1.f, 1 - ex);        // m sc in [1, 2)
+  for (int64_t e = threadIdx.x; e < count; e += 256) v[e] *= sc;
+}
+
+hipError_t launch_rescale_pow2(float *w, int64_t count, int64_t bs, int batch, hipStream_t s) {
+  if (count <= 0 || batch <= 0) return hipSuccess;
+  rescale_pow2_kernel<<<batch, 256, 0, s>>>(w, count, bs);
+  return hipGetLastError();
 }
 
 hipError_t launch_copy(CMat src, Mat dst, int64_t M, int64_t N, int batch, hipStream_t s) {

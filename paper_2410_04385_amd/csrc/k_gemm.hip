@@ -11,23 +11,25 @@
 // Operand tiles are loaded with the thread mapping that makes the unit-stride
 // dimension of each operand contiguous across lanes.
 #include "common.h"
+#include "stage.h"
 
 namespace hatt {
-
-typedef double d4_t __attribute__((ext_vector_type(4)));
 
 constexpr int BK = 32;
 
 // BM x BN output tile, 4 waves in a 2 x 2 grid, each wave (BM/2) x (BN/2) as
 // (BM/32) x (BN/32) MFMA blocks of 16 x 16.  The next K slab is fetched into
-// registers while the MFMAs consume the current one from LDS.
-template <int BM, int BN>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
+// registers while the MFMAs consume the current one from LDS.  CT is the
+// compute type (FP64 or FP32 matrix cores, FP32 accumulating in FP32); TA,
+// TB, TC are the storage types of the operands (converted on load / store).
+template <int BM, int BN, typename CT, typename TA, typename TB, typename TC>
+__device__ __forceinline__ void gemm_body(const GemmArgs &g) {
+  using acc_t = typename std::conditional<std::is_same<CT, double>::value, d4_t, f4_t>::type;
   constexpr int LDA_S = BM + 1, LDB_S = BN + 1;
   constexpr int MI = BM / 32, NJ = BN / 32;
   constexpr int A_PER = BM * BK / 256, B_PER = BN * BK / 256;
-  __shared__ double As[BK * LDA_S];  // As[k * LDA_S + m]
-  __shared__ double Bs[BK * LDB_S];  // Bs[k * LDB_S + n]
+  __shared__ CT As[BK * LDA_S];  // As[k * LDA_S + m]
+  __shared__ CT Bs[BK * LDB_S];  // Bs[k * LDB_S + n]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
   const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
@@ -39,8 +41,8 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
   const int64_t kbeg = kc * kchunk;
   const int64_t kend = std::min<int64_t>(g.K, kbeg + kchunk);
 
-  const double *Ab = g.A.ptr + p * g.A.bs;
-  const double *Bb = g.B.ptr + p * g.B.bs;
+  const TA *Ab = reinterpret_cast<const TA *>(static_cast<const void *>(g.A.ptr)) + p * g.A.bs;
+  const TB *Bb = reinterpret_cast<const TB *>(static_cast<const void *>(g.B.ptr)) + p * g.B.bs;
   const bool a_kfast = (g.A.cs == 1);
   const bool b_nfast = (g.B.cs == 1) || (g.B.rs != 1);
 
@@ -48,7 +50,8 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
   // tile; along the unit-stride dimension they share one index, so each
   // operand needs one base pointer and one per-slot stride.
   const int64_t rem0 = kend - kbeg;
-  const double *abase, *bbase;
+  const TA *abase;
+  const TB *bbase;
   int64_t astep, bstep;  // pointer distance between slots t and t + 1
   int a_lds0, a_ldsd, b_lds0, b_ldsd;
   int a_fix, a_var0, a_vard, a_lim, b_fix, b_var0, b_vard, b_lim;  // bound checks, see fetch
@@ -96,24 +99,24 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
   }
   (void)rem0;
   const int64_t a_kstep = BK * g.A.cs, b_kstep = BK * g.B.rs;
-  double ra[A_PER], rb[B_PER];
+  CT ra[A_PER], rb[B_PER];
   // slot t is in range when: k-fast layout: fixed k < rem and m (n) < limit;
   // m-fast (n-fast) layout: the fixed m (n) is inside and k < rem.
   auto fetch = [&](int64_t k0, int64_t slab) {
     const int rem = (int)std::min<int64_t>(kend - k0, 1 << 30);
-    const double *pa = abase + slab * a_kstep;
-    const double *pb = bbase + slab * b_kstep;
+    const TA *pa = abase + slab * a_kstep;
+    const TB *pb = bbase + slab * b_kstep;
 #pragma unroll
     for (int t = 0; t < A_PER; ++t) {
       const int v = a_var0 + t * a_vard;
       const bool ok = a_kfast ? (a_fix < rem && v < a_lim) : (a_fix < 0 && v < rem);
-      ra[t] = ok ? pa[t * astep] : 0.0;
+      ra[t] = ok ? (CT)pa[t * astep] : (CT)0;
     }
 #pragma unroll
     for (int t = 0; t < B_PER; ++t) {
       const int v = b_var0 + t * b_vard;
       const bool ok = b_nfast ? (b_fix < 0 && v < rem) : (b_fix < rem && v < b_lim);
-      rb[t] = ok ? pb[t * bstep] : 0.0;
+      rb[t] = ok ? (CT)pb[t * bstep] : (CT)0;
     }
   };
   auto park = [&]() {
@@ -123,11 +126,11 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
     for (int t = 0; t < B_PER; ++t) Bs[b_lds0 + t * b_ldsd] = rb[t];
   };
 
-  d4_t acc[MI][NJ];
+  acc_t acc[MI][NJ];
 #pragma unroll
   for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NJ; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
   if (kbeg < kend) {
     fetch(kbeg, 0);
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4), c16 = lane & 15;
-      double av[MI], bv[NJ];
+      CT av[MI], bv[NJ];
 #pragma unroll
       for (int i = 0; i < MI; ++i) av[i] = As[kr * LDA_S + wm + i * 16 + c16];
 #pragma unroll
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
       for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < NJ; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = mfma16(av[i], bv[j], acc[i][j]);
     }
     __syncthreads();
     if (more) {
@@ -161,22 +164,22 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
 
   const int rq = lane >> 4, cq = lane & 15;
   if (ks == 1) {
-    double *Cb = g.C.ptr + p * g.C.bs;
+    TC *Cb = reinterpret_cast<TC *>(static_cast<void *>(g.C.ptr)) + p * g.C.bs;
 #pragma unroll
     for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int64_t gm = m0 + wm + i * 16 + rq + 4 * v, gn = n0 + wn + j * 16 + cq;
+          const int64_t gm = m0 + wm + i * 16 + mfma_row<CT>(rq, v), gn = n0 + wn + j * 16 + cq;
           if (gm < g.M && gn < g.N) {
-            double *cp = Cb + gm * g.C.rs + gn * g.C.cs;
-            double r = g.alpha * acc[i][j][v];
-            if (g.beta != 0.0) r += g.beta * (*cp);
-            *cp = r;
+            TC *cp = Cb + gm * g.C.rs + gn * g.C.cs;
+            double r = g.alpha * (double)acc[i][j][v];
+            if (g.beta != 0.0) r += g.beta * (double)(*cp);
+            *cp = (TC)r;
           }
         }
-  } else {
+  } else if (std::is_same<CT, double>::value) {  // split-K partials (FP64 path only)
     double *Pb = g.part + ((int64_t)p * ks + kc) * g.M * g.N;
 #pragma unroll
     for (int i = 0; i < MI; ++i)
@@ -184,10 +187,21 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
       for (int j = 0; j < NJ; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int64_t gm = m0 + wm + i * 16 + rq + 4 * v, gn = n0 + wn + j * 16 + cq;
-          if (gm < g.M && gn < g.N) Pb[gm * g.N + gn] = g.alpha * acc[i][j][v];
+          const int64_t gm = m0 + wm + i * 16 + mfma_row<CT>(rq, v), gn = n0 + wn + j * 16 + cq;
+          if (gm < g.M && gn < g.N) Pb[gm * g.N + gn] = g.alpha * (double)acc[i][j][v];
         }
   }
+}
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
+  gemm_body<BM, BN, double, double, double, double>(g);
+}
+
+// FP32 matrix cores, FP32 accumulation; operands stored as FP32 or FP64.
+template <int BM, int BN, typename TA, typename TB, typename TC>
+__global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
+  gemm_body<BM, BN, float, TA, TB, TC>(g);
 }
 
 // Sum of the ksplit partial products in chunk order (bitwise reproducible).
@@ -233,11 +247,29 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
   if (a.ksplit > 1 && a.part == nullptr) a.ksplit = 1;
   int bm, bn;
   gemm_tile(a.M, a.N, &bm, &bn);
+  if (a.prec) a.ksplit = 1;  // the FP32 path writes its result directly
   dim3 grid((unsigned)((a.M + bm - 1) / bm), (unsigned)((a.N + bn - 1) / bn), (unsigned)(a.batch * a.ksplit));
-  if (bm == 64 && bn == 64) gemm_f64_kernel<64, 64><<<grid, 256, 0, s>>>(a);
-  else if (bm == 64) gemm_f64_kernel<64, 32><<<grid, 256, 0, s>>>(a);
-  else if (bn == 64) gemm_f64_kernel<32, 64><<<grid, 256, 0, s>>>(a);
-  else gemm_f64_kernel<32, 32><<<grid, 256, 0, s>>>(a);
+  if (!a.prec) {
+    if (a.a_f32 || a.b_f32 || a.c_f32) return hipErrorInvalidValue;
+    if (bm == 64 && bn == 64) gemm_f64_kernel<64, 64><<<grid, 256, 0, s>>>(a);
+    else if (bm == 64) gemm_f64_kernel<64, 32><<<grid, 256, 0, s>>>(a);
+    else if (bn == 64) gemm_f64_kernel<32, 64><<<grid, 256, 0, s>>>(a);
+    else gemm_f64_kernel<32, 32><<<grid, 256, 0, s>>>(a);
+  } else {
+    const int combo = a.a_f32 * 4 + a.b_f32 * 2 + a.c_f32;
+#define HATT_GEMM32(TA, TB, TC)                                                     \
+  do {                                                                              \
+    if (bm == 64 && bn == 64) gemm_f32_kernel<64, 64, TA, TB, TC><<<grid, 256, 0, s>>>(a); \
+    else if (bm == 64) gemm_f32_kernel<64, 32, TA, TB, TC><<<grid, 256, 0, s>>>(a);        \
+    else if (bn == 64) gemm_f32_kernel<32, 64, TA, TB, TC><<<grid, 256, 0, s>>>(a);        \
+    else gemm_f32_kernel<32, 32, TA, TB, TC><<<grid, 256, 0, s>>>(a);                      \
+  } while (0)
+    if (combo == 5) HATT_GEMM32(float, double, float);       // W_L (f32) x sketch (f64) -> W (f32)
+    else if (combo == 2) HATT_GEMM32(double, float, double); // X (f64) x W (f32) -> Y (f64)
+    else if (combo == 7) HATT_GEMM32(float, float, float);
+    else return hipErrorInvalidValue;
+#undef HATT_GEMM32
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || a.ksplit == 1 || a.no_reduce) return e;
   return launch_splitk_reduce(a, s);

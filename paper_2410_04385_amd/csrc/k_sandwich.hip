@@ -17,8 +17,6 @@
 
 namespace hatt {
 
-typedef double d4_t __attribute__((ext_vector_type(4)));
-
 namespace {
 __host__ __device__ inline int rup(int x, int m) { return (x + m - 1) / m * m; }
 }  // namespace
@@ -87,22 +85,27 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
 // block passes the first block's operands twice and drops c1.
 constexpr int kSwMaxKSteps = 16;  // K <= 64 on both stages
 
-__device__ __forceinline__ void mfma_pair(const double *a0, const double *b0, const double *a1, const double *b1,
-                                          int lda_k, int ldb_k, int ksteps, d4_t &c0, d4_t &c1) {
+template <typename CT, typename ACC>
+__device__ __forceinline__ void mfma_pair(const CT *a0, const CT *b0, const CT *a1, const CT *b1, int lda_k,
+                                          int ldb_k, int ksteps, ACC &c0, ACC &c1) {
 #pragma unroll
   for (int k = 0; k < kSwMaxKSteps; ++k) {
     if (k < ksteps) {
-      const double x0 = a0[k * lda_k], y0 = b0[k * ldb_k];
-      const double x1 = a1[k * lda_k], y1 = b1[k * ldb_k];
-      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, c1, 0, 0, 0);
+      const CT x0 = a0[k * lda_k], y0 = b0[k * ldb_k];
+      const CT x1 = a1[k * lda_k], y1 = b1[k * ldb_k];
+      c0 = mfma16(x0, y0, c0);
+      c1 = mfma16(x1, y1, c1);
     }
   }
 }
 
-template <bool LG>
+// CT: compute and LDS type (FP64, or FP32 for the FP32 range finding); C
+// and the output are stored in CT, YL and ZR (cores of x and y) in FP64.
+template <bool LG, typename CT>
 __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPlan pl) {
-  extern __shared__ double sm[];
+  using acc_t = typename std::conditional<std::is_same<CT, double>::value, d4_t, f4_t>::type;
+  extern __shared__ double smraw[];
+  CT *sm = reinterpret_cast<CT *>(smraw);
   const int RA = a.RA, RI = a.RI, SI = a.SI, SO = a.SO;
   const int GC = pl.GC;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -115,33 +118,33 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
   const int gc = (int)std::min<int64_t>(GC, a.G - g0);
   if (gc <= 0 || i0 >= i1) return;
   const int yzs = pl.SI4 * pl.ldz + pl.RA16 * pl.ldy;
-  double *Cs = sm;                           // pl.M1 rows (g, a) x ldc, K = b
-  double *YZ0 = Cs + pl.M1 * pl.ldc;         // [ZR: SI4 x ldz | YL: RA16 x ldy], two buffers
-  double *Ts = YZ0 + 2 * yzs;                // RI4 rows (a) x ldt, N = stage-2 columns
+  CT *Cs = sm;                               // pl.M1 rows (g, a) x ldc, K = b
+  CT *YZ0 = Cs + pl.M1 * pl.ldc;             // [ZR: SI4 x ldz | YL: RA16 x ldy], two buffers
+  CT *Ts = YZ0 + 2 * yzs;                    // RI4 rows (a) x ldt, N = stage-2 columns
   const int M1 = gc * RI;                    // valid stage-1 rows
   const int M1p = rup(M1, 16);
 
   // ---- C chunk (fixed for all slices of this block), zero K padding
-  const double *cbase = a.c + p * a.cb + g0 * a.cg;
+  const CT *cbase = reinterpret_cast<const CT *>(static_cast<const void *>(a.c)) + p * a.cb + g0 * a.cg;
   if (a.cg == 1) {  // g fastest in memory: consecutive threads take consecutive g
     stage_lds<8>(gc * RI * pl.SI4, Rad3(tid, 256, gc, pl.SI4), Cs,  // digits (g, b, a)
                  [&](const Rad3 &d) {
-                   return (d.i1 < SI) ? cbase[d.i0 * a.cg + d.i2 * a.ca + d.i1 * a.cbb] : 0.0;
+                   return (d.i1 < SI) ? (double)cbase[d.i0 * a.cg + d.i2 * a.ca + d.i1 * a.cbb] : 0.0;
                  },
                  [&](const Rad3 &d) { return (d.i0 * RI + d.i2) * pl.ldc + d.i1; });
   } else {
     stage_lds<8>(gc * RI * pl.SI4, Rad3(tid, 256, pl.SI4, RI), Cs,  // digits (b, a, g)
                  [&](const Rad3 &d) {
-                   return (d.i0 < SI) ? cbase[d.i2 * a.cg + d.i1 * a.ca + d.i0 * a.cbb] : 0.0;
+                   return (d.i0 < SI) ? (double)cbase[d.i2 * a.cg + d.i1 * a.ca + d.i0 * a.cbb] : 0.0;
                  },
                  [&](const Rad3 &d) { return (d.i2 * RI + d.i1) * pl.ldc + d.i0; });
   }
   for (int e = tid; e < (M1p - M1) * pl.SI4; e += 256) {
     const int r = M1 + e / pl.SI4, k = e - (e / pl.SI4) * pl.SI4;
-    Cs[r * pl.ldc + k] = 0.0;
+    Cs[r * pl.ldc + k] = (CT)0;
   }
   // rows a >= RI of T are K padding of stage 2: zero once
-  for (int e = tid; e < (pl.RI4 - RI) * pl.ldt; e += 256) Ts[RI * pl.ldt + e] = 0.0;
+  for (int e = tid; e < (pl.RI4 - RI) * pl.ldt; e += 256) Ts[RI * pl.ldt + e] = (CT)0;
 
   // ---- YL / ZR slots of this thread: slot u is element tid + 256 u of the
   // padded [ZR | YL] grid; kind 0 = zero padding, 1 = ZR entry, 2 = YL entry
@@ -180,10 +183,10 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
       pf[u] = (k == 1) ? zr[pf_off[u]] : ((k == 2) ? yl[pf_off[u]] : 0.0);
     }
   };
-  auto park = [&](double *buf) {
+  auto park = [&](CT *buf) {
 #pragma unroll
     for (int u = 0; u < kSwPrefetch; ++u)
-      if (pf_lds[u] >= 0) buf[pf_lds[u]] = pf[u];
+      if (pf_lds[u] >= 0) buf[pf_lds[u]] = (CT)pf[u];
   };
   fetch(i0);
   park(YZ0);
@@ -196,8 +199,8 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
   for (int64_t i = i0; i < i1; ++i) {
     const bool more = i + 1 < i1;
     if (more) fetch(i + 1);  // in flight during the MFMAs below
-    const double *ZRs = YZ0 + buf * yzs;
-    const double *YLs = ZRs + pl.SI4 * pl.ldz;
+    const CT *ZRs = YZ0 + buf * yzs;
+    const CT *YLs = ZRs + pl.SI4 * pl.ldz;
 
     // ---- stage 1: T(g, a; b') = sum_b C_g(a, b) ZR(b, b'), scattered into Ts
     for (int t = wave; t < tiles1; t += 8) {
@@ -205,18 +208,18 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
       const bool two = t2 < tiles1;
       const int tm0 = (t / nt1) * 16, tn0 = (t - (t / nt1) * nt1) * 16;
       const int tm1 = two ? (t2 / nt1) * 16 : tm0, tn1 = two ? (t2 - (t2 / nt1) * nt1) * 16 : tn0;
-      d4_t c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+      acc_t c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
       mfma_pair(Cs + (tm0 + r16) * pl.ldc + q4, ZRs + q4 * pl.ldz + tn0 + r16, Cs + (tm1 + r16) * pl.ldc + q4,
                 ZRs + q4 * pl.ldz + tn1 + r16, 4, 4 * pl.ldz, pl.SI4 / 4, c0, c1);
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         if (u == 1 && !two) break;
-        const d4_t &c = u ? c1 : c0;
+        const acc_t &c = u ? c1 : c0;
         const int tm = u ? tm1 : tm0, bq = (u ? tn1 : tn0) + r16;
         if (bq < SO) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int row = tm + q4 + 4 * v;
+            const int row = tm + mfma_row<CT>(q4, v);
             if (row < M1) {
               const int g = fdiv(row, pl.fd_ri), aa = row - g * RI;
               const int col = LG ? bq * GC + g : g * SO + bq;
@@ -229,19 +232,19 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
     __syncthreads();
 
     // ---- stage 2: out(a', col) = sum_a YL(a', a) T(a, col)
-    double *obase = a.o + p * a.ob + i * a.oi + g0 * a.og;
+    CT *obase = reinterpret_cast<CT *>(static_cast<void *>(a.o)) + p * a.ob + i * a.oi + g0 * a.og;
     for (int t = wave; t < tiles2; t += 8) {
       const int t2 = t + 4;
       const bool two = t2 < tiles2;
       const int tm0 = (t / nt2) * 16, tn0 = (t - (t / nt2) * nt2) * 16;
       const int tm1 = two ? (t2 / nt2) * 16 : tm0, tn1 = two ? (t2 - (t2 / nt2) * nt2) * 16 : tn0;
-      d4_t c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+      acc_t c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
       mfma_pair(YLs + (tm0 + r16) * pl.ldy + q4, Ts + q4 * pl.ldt + tn0 + r16, YLs + (tm1 + r16) * pl.ldy + q4,
                 Ts + q4 * pl.ldt + tn1 + r16, 4, 4 * pl.ldt, pl.RI4 / 4, c0, c1);
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         if (u == 1 && !two) break;
-        const d4_t &c = u ? c1 : c0;
+        const acc_t &c = u ? c1 : c0;
         const int tm = u ? tm1 : tm0, col = (u ? tn1 : tn0) + r16;
         int g, bq;
         if (LG) {
@@ -252,11 +255,12 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
           bq = col - g * SO;
         }
         if (col < ncols && g < gc) {
-          double *o = obase + g * a.og + bq * a.obb + (int64_t)(tm + q4) * a.oa;
-          const int64_t s4 = 4 * a.oa;
+          CT *o = obase + g * a.og + bq * a.obb + (int64_t)tm * a.oa;
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            if (tm + q4 + 4 * v < RA) o[v * s4] = c[v];
+          for (int v = 0; v < 4; ++v) {
+            const int rr = mfma_row<CT>(q4, v);
+            if (tm + rr < RA) o[(int64_t)rr * a.oa] = c[v];
+          }
         }
       }
     }
@@ -267,19 +271,29 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
 }
 
 hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStream_t s) {
-  const size_t lds = (size_t)pl.lds_doubles * sizeof(double);
+  const size_t esz = a.prec ? sizeof(float) : sizeof(double);
+  const size_t lds = (size_t)pl.lds_doubles * esz;
   static bool attr_done = false;  // set once: the maximum a launch may ask for
   if (!attr_done) {
-    (void)hipFuncSetAttribute((const void *)sandwich_mfma_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(kSandwichLdsDoubles * sizeof(double)));
-    (void)hipFuncSetAttribute((const void *)sandwich_mfma_kernel<false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(kSandwichLdsDoubles * sizeof(double)));
+    const int mx = (int)(kSandwichLdsDoubles * sizeof(double));
+    (void)hipFuncSetAttribute((const void *)sandwich_mfma_kernel<true, double>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    (void)hipFuncSetAttribute((const void *)sandwich_mfma_kernel<false, double>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    (void)hipFuncSetAttribute((const void *)sandwich_mfma_kernel<true, float>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    (void)hipFuncSetAttribute((const void *)sandwich_mfma_kernel<false, float>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     attr_done = true;
   }
   dim3 grid((unsigned)pl.iblocks, (unsigned)pl.chunks, (unsigned)a.batch);
-  if (a.og == 1) sandwich_mfma_kernel<true><<<grid, 256, lds, s>>>(a, pl);
-  else sandwich_mfma_kernel<false><<<grid, 256, lds, s>>>(a, pl);
+  if (a.prec) {
+    if (a.og == 1) sandwich_mfma_kernel<true, float><<<grid, 256, lds, s>>>(a, pl);
+    else sandwich_mfma_kernel<false, float><<<grid, 256, lds, s>>>(a, pl);
+  } else {
+    if (a.og == 1) sandwich_mfma_kernel<true, double><<<grid, 256, lds, s>>>(a, pl);
+    else sandwich_mfma_kernel<false, double><<<grid, 256, lds, s>>>(a, pl);
+  }
   return hipGetLastError();
 }
 

@@ -2,7 +2,28 @@
 #pragma once
 #include "common.h"
 
+#include <type_traits>
+
 namespace hatt {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 x 4 MFMA step in the compute type.  Operand layouts are the
+// same for both (lane l holds A(l%16, l/16) and B(l/16, l%16)); the result
+// rows held by lane l differ: l/16 + 4v for FP64, 4 (l/16) + v for FP32
+// (both checked on gfx950 with one-wave probes).
+__device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4_t mfma16(float a, float b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename CT>
+__device__ __forceinline__ int mfma_row(int rq, int v) {
+  return std::is_same<CT, double>::value ? rq + 4 * v : 4 * rq + v;
+}
+
 
 // Three-digit counter (i0 fastest, radices n0, n1) stepped by a fixed stride
 // with carries instead of a division per element.
@@ -28,8 +49,8 @@ struct Rad3 {
 // Global -> LDS staging with U loads in flight per thread: element e of the
 // block (digits in d, advanced by the block stride) is read by src(d) and
 // stored at dst[idx(d)].
-template <int U, typename Src, typename Idx>
-__device__ __forceinline__ void stage_lds(int total, Rad3 d, double *dst, Src src, Idx idx) {
+template <int U, typename T, typename Src, typename Idx>
+__device__ __forceinline__ void stage_lds(int total, Rad3 d, T *dst, Src src, Idx idx) {
   for (int e0 = threadIdx.x; e0 < total; e0 += 256 * U) {
     double v[U];
     int di[U];
@@ -43,7 +64,7 @@ __device__ __forceinline__ void stage_lds(int total, Rad3 d, double *dst, Src sr
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (e0 + 256 * u < total) dst[di[u]] = v[u];
+      if (e0 + 256 * u < total) dst[di[u]] = (T)v[u];
   }
 }
 

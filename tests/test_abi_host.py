@@ -208,3 +208,15 @@ def test_batched_plan_errors():
     assert e.value.status == -2
     assert b"pair 1" in _lib.lib().hatt_last_error()
     assert _lib.lib().hatt_batched_plan(0, None, None, None, None, None, None, None) == -1
+
+
+def test_precision_option_validation():
+    x = _cpu_tt([4, 5, 6], [1, 3, 4, 1])
+    p32 = api.plan(x, x, 6, precision="f32")
+    p64 = api.plan(x, x, 6)
+    assert p32["ell"] == p64["ell"]
+    with pytest.raises(ValueError):
+        api.plan(x, x, 6, precision="bf16")
+    with pytest.raises(HattError) as e:
+        api.plan(x, x, 6, precision="f32", variant=2)
+    assert e.value.status == -7

@@ -445,3 +445,63 @@ def test_batched_workload_sample():
     for p in range(len(pairs)):
         kept = res[p].ranks[0].cpu().tolist()
         assert all(1 <= k <= c for k, c in zip(kept, res[p].out.ranks))
+
+
+def test_fp32_range_finding_exact_rank():
+    """FP32 range finding at the exact widths (tiny workload): the FP64
+    projection onto the FP32-found frame reproduces the product to FP32
+    accuracy."""
+    y, z = wk.tiny_pair(11)
+    _say("hatt_recompress f32 tiny exact widths")
+    res = H.recompress(H.TT.from_cores([y]), H.TT.from_cores([z]), 9, seed=3, precision="f32")
+    torch.cuda.synchronize()
+    err = tt.rel_err(res.train(0), tt.pkp(y, z))
+    _say(f"  rel err vs the product {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_fp32_range_finding_projection_identity_and_closeness():
+    """Spectral pair (d = 8): with FP32 range finding the output is still an
+    exact FP64 orthogonal projection of z onto a left-orthonormal frame, so
+    ||z||^2 = ||X||^2 + ||z - X||^2 to FP64 rounding; it stays within FP32
+    accuracy of the FP64 result with the same sketch, before and after
+    truncation to rank 30."""
+    y, z = wk.spectral_pair(31, 8, 32, 20, 20)
+    X = H.TT.from_cores([y])
+    Z = H.TT.from_cores([z])
+    _say("hatt_recompress f32 vs f64 spectral d=8")
+    r32 = H.recompress(X, Z, 40, seed=12, precision="f32")
+    r64 = H.recompress(X, Z, 40, seed=12)
+    t32 = H.recompress(X, Z, 40, max_rank=30, seed=12, precision="f32")
+    t64 = H.recompress(X, Z, 40, max_rank=30, seed=12)
+    torch.cuda.synchronize()
+    a32, a64 = r32.train(0), r64.train(0)
+    zz = tt.pkp(y, z)
+    nz, nx = tt.norm(zz), tt.norm(a32)
+    resid = tt.rel_err(a32, zz) * nz
+    assert abs(nz ** 2 - nx ** 2 - resid ** 2) <= 1e-12 * nz ** 2
+    d_full = tt.rel_err(a32, a64)
+    d_trunc = tt.rel_err(t32.train(0), t64.train(0))
+    _say(f"  f32 vs f64: untruncated {d_full:.2e}, truncated {d_trunc:.2e}")
+    assert d_full <= 1e-4 and d_trunc <= 1e-4
+    assert tt.ranks(t32.train(0)) == tt.ranks(t64.train(0))
+
+
+def test_fp32_range_finding_full_order():
+    """Order 20 (the spectral workload, width 40, no truncation): each FP32
+    sketch is kept at unit scale by powers of two, so nothing underflows
+    along the 18 HPCRL steps; the result is an FP64 projection of z onto a
+    frame found in FP32, and its error ||z - X|| / ||z|| (about 0.5 here: z
+    has rank 400 and a slowly decaying spectrum) matches the FP64 run's to
+    three digits."""
+    cfg = wk.WORKLOADS["spectral"]
+    y, z = wk.spectral_pair(1001, cfg["d"], cfg["n"], cfg["r"], cfg["r"])
+    X, Z = H.TT.from_cores([y]), H.TT.from_cores([z])
+    _say("hatt_recompress f32 vs f64 spectral d=20")
+    a = H.recompress(X, Z, cfg["ell"], seed=5, precision="f32")
+    b = H.recompress(X, Z, cfg["ell"], seed=5)
+    torch.cuda.synchronize()
+    zz = tt.pkp(y, z)
+    e32, e64 = tt.rel_err(a.train(0), zz), tt.rel_err(b.train(0), zz)
+    _say(f"  error vs z: f32 {e32:.6f}, f64 {e64:.6f}")
+    assert abs(e32 - e64) <= 1e-3 * e64
