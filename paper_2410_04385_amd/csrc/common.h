@@ -93,6 +93,7 @@ constexpr int kSwPrefetch = 8;  // register slots per thread for the next slice'
 struct SwPlan {
   int GC, chunks;
   int ipb, iblocks;           // mode indices per block, blocks along i
+  int pf;                     // 1: next slice's YL / ZR prefetched into registers
   int RI4, SI4, SO16, RA16;   // padded sizes (K edges to 4, M/N edges to 16)
   int ldc, ldz, ldy, ldt, M1; // LDS row strides; padded stage-1 row count
   int64_t lds_doubles;

@@ -172,6 +172,7 @@ std::string site_of(const char *expr) {
         pb_ = g_prof.get();                                                     \
         if (pa_) (void)hipEventRecord(pa_, st);                                       \
       }                                                                         \
+      (void)hipGetLastError(); /* report only this launch's own error */        \
       hipError_t e_ = (expr);                                                   \
       if (g_prof.on && pa_ && pb_) {                                            \
         (void)hipEventRecord(pb_, st);                                          \
@@ -852,6 +853,11 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     a.n = n[c];
     a.G = l1;
     a.batch = P;
+    if (f32) {
+      SwPlan swp;
+      if (!sandwich_mfma_plan(a, kSandwichLdsDoubles, &swp))
+        return fail(HATT_EUNSUPPORTED, "FP32 range finding: ranks above 64 are not built (use FP64)");
+    }
     site("sandwich W_L n=%lld G=%lld RA=%d RI=%d SI=%d SO=%d [%s]", (long long)n[c], (long long)l1, a.RA, a.RI,
          a.SI, a.SO, sandwich_kernel_name(a));
     LAUNCH(launch_sandwich(a, st));

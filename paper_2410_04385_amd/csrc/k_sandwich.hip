@@ -26,8 +26,9 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
   const int SO16 = rup(a.SO, 16), RA16 = rup(a.RA, 16);
   const int ldc = SI4 + 1, ldz = SO16 + 1, ldy = RI4 + 1;
   const int64_t yz = (int64_t)SI4 * ldz + (int64_t)RA16 * ldy;  // one YL + ZR buffer
-  // the register prefetch of the next slice covers every YL / ZR slot
-  if ((int64_t)RA16 * RI4 + (int64_t)SI4 * SO16 > kSwPrefetch * 256) return false;
+  // the register prefetch of the next slice needs every YL / ZR slot to fit
+  // kSwPrefetch slots per thread (else each slice is staged directly)
+  bool pf = (int64_t)RA16 * RI4 + (int64_t)SI4 * SO16 <= kSwPrefetch * 256;
   auto lds_for = [&](int gc, int *ldt, int *m1) {
     *m1 = rup(gc * a.RI, 16);
     *ldt = rup(gc * a.SO, 16) + 1;
@@ -76,7 +77,9 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
   // prefetch offsets are 32-bit
   const int64_t ymax = (int64_t)(a.RA - 1) * std::llabs(a.ylr) + (int64_t)(a.RI - 1) * std::llabs(a.ylc);
   const int64_t zmax = (int64_t)(a.SI - 1) * std::llabs(a.zrr) + (int64_t)(a.SO - 1) * std::llabs(a.zrc);
-  return ymax < (1LL << 31) && zmax < (1LL << 31);
+  pf = pf && ymax < (1LL << 31) && zmax < (1LL << 31);
+  pl->pf = pf ? 1 : 0;
+  return true;
 }
 
 // Two 16 x 16 output blocks per pass (two accumulation chains in flight):
@@ -188,8 +191,27 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
     for (int u = 0; u < kSwPrefetch; ++u)
       if (pf_lds[u] >= 0) buf[pf_lds[u]] = (CT)pf[u];
   };
-  fetch(i0);
-  park(YZ0);
+  // without the register prefetch: stage slice i straight into buf
+  auto stage_direct = [&](int64_t i, CT *buf) {
+    const double *zr = zrp + i * a.zri, *yl = ylp + i * a.yli;
+    stage_lds<4>(pl.SI4 * pl.SO16, Rad3(tid, 256, pl.SO16, pl.SI4), buf,  // digits (b', b)
+                 [&](const Rad3 &d) {
+                   return (d.i1 < SI && d.i0 < SO) ? zr[(int64_t)d.i1 * a.zrr + (int64_t)d.i0 * a.zrc] : 0.0;
+                 },
+                 [&](const Rad3 &d) { return d.i1 * pl.ldz + d.i0; });
+    stage_lds<4>(pl.RA16 * pl.RI4, Rad3(tid, 256, pl.RI4, pl.RA16), buf + pl.SI4 * pl.ldz,  // digits (a, a')
+                 [&](const Rad3 &d) {
+                   return (d.i1 < RA && d.i0 < RI) ? yl[(int64_t)d.i1 * a.ylr + (int64_t)d.i0 * a.ylc] : 0.0;
+                 },
+                 [&](const Rad3 &d) { return d.i1 * pl.ldy + d.i0; });
+  };
+  const bool pfr = pl.pf != 0;
+  if (pfr) {
+    fetch(i0);
+    park(YZ0);
+  } else {
+    stage_direct(i0, YZ0);
+  }
   __syncthreads();
 
   const int nt1 = pl.SO16 / 16, tiles1 = (M1p / 16) * nt1;
@@ -198,7 +220,7 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
   int buf = 0;
   for (int64_t i = i0; i < i1; ++i) {
     const bool more = i + 1 < i1;
-    if (more) fetch(i + 1);  // in flight during the MFMAs below
+    if (more && pfr) fetch(i + 1);  // in flight during the MFMAs below
     const CT *ZRs = YZ0 + buf * yzs;
     const CT *YLs = ZRs + pl.SI4 * pl.ldz;
 
@@ -264,7 +286,10 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
         }
       }
     }
-    if (more) park(YZ0 + (buf ^ 1) * yzs);
+    if (more) {
+      if (pfr) park(YZ0 + (buf ^ 1) * yzs);
+      else stage_direct(i + 1, YZ0 + (buf ^ 1) * yzs);
+    }
     __syncthreads();  // Ts and the YL / ZR buffer are reused by the next slice
     buf ^= 1;
   }

@@ -220,3 +220,11 @@ def test_precision_option_validation():
     with pytest.raises(HattError) as e:
         api.plan(x, x, 6, precision="f32", variant=2)
     assert e.value.status == -7
+
+
+def test_fp32_unsupported_ranks_fail_at_plan():
+    x = _cpu_tt([4, 80, 80, 4], [1, 4, 70, 4, 1])
+    with pytest.raises(HattError) as e:
+        api.plan(x, x, 90, precision="f32")
+    assert e.value.status == -7
+    api.plan(x, x, 90)  # FP64 takes it
