@@ -300,7 +300,11 @@ bool qr_prepare(int64_t m, int64_t n, QrOp *op) {
   op->n = n;
   op->k = std::min(m, n);
   op->big = op->wide = op->chol = false;
-  if (n <= kQrMaxCols && qr_make_plan(m, n, &op->direct)) {
+  // tall frames wider than one Cholesky panel go to BCGS2 over CholeskyQR2
+  // panels: the one-shot tree for them has blocks of barely n rows, so it
+  // needs many levels and forms Q a few columns at a time
+  const bool panelled = g_use_chol && m >= n && n > kCholMaxN;
+  if (n <= kQrMaxCols && !panelled && qr_make_plan(m, n, &op->direct)) {
     op->ws_doubles = op->direct.ws_doubles;
     if (g_use_chol && m >= n && n <= kCholMaxN) {
       op->chol = true;
