@@ -17,6 +17,10 @@ Everything here is plain, slow and written to be read against the paper
 * ``plan``      the sketch-width clamps applied before a recompression.
 * ``philox``    the counter-based generator of the seeded Gaussian sketch.
 * ``flops``     the paper's operation counts (Sec. 4, Table 4.1).
+* ``adapt``     tolerance-driven widths (grow l until the truncation leaves
+                slack; Sec. 5.1.1 and Sec. 6 leave the rule open).
+* ``rankpred``  the per-bond width predictor: core statistics, a small tanh
+                MLP, its gradient and the Adam update.
 
 All arithmetic is numpy float64; QR and SVD are LAPACK calls (Householder QR
 and divide-and-conquer SVD), used only as library steps.
@@ -26,4 +30,4 @@ Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 inequalities); none is "parity unpinned".
 """
 
-from . import tt, rounding, randorth, hatt, plan, philox, flops  # noqa: F401
+from . import tt, rounding, randorth, hatt, plan, philox, flops, adapt, rankpred  # noqa: F401

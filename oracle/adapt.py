@@ -54,17 +54,19 @@ def failing_bonds(kept: Sequence[Sequence[int]], ell: Sequence[int], cap: Sequen
 
 
 def hatt_adaptive(pairs, tol: float, seed: int, p: int = 8, max_attempts: int = 8, variant: int = 1,
-                  ep: float = 0.0):
-    """``pairs``: list of (y, z) of one shape.  Returns (outputs, widths used,
-    attempts, converged)."""
+                  ep: float = 0.0, ell0: Sequence[int] | None = None, seed_step: int = 1):
+    """``pairs``: list of (y, z) of one shape.  Attempt a uses the sketch
+    keyed by seed + a * seed_step; ``ell0`` replaces the starting widths
+    (a predicted start).  Returns (outputs, widths used, attempts,
+    converged)."""
     y0, z0 = pairs[0]
     n, rx, ry = tt.modes(y0), tt.ranks(y0), tt.ranks(z0)
     cap = plan.clamp_ell(n, rx, ry, BIG)
-    ell = initial_widths(n, rx, ry, p)
+    ell = initial_widths(n, rx, ry, p) if ell0 is None else list(ell0)
     outs = None
     for attempt in range(max_attempts):
         l = plan.clamp_ell(n, rx, ry, ell)
-        R = philox.sketch(seed + attempt, n, l)
+        R = philox.sketch(seed + attempt * seed_step, n, l)
         outs = [rounding.tt_round(hatt(y, z, R, variant, ep), tol=tol) for (y, z) in pairs]
         bad = failing_bonds([tt.ranks(o) for o in outs], l, cap, p)
         if not bad:

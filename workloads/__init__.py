@@ -23,4 +23,5 @@ from .gen import (  # noqa: F401
     ranks_of,
     modes_of,
     feasible_ranks,
+    mlp_init,
 )

@@ -138,3 +138,16 @@ def batched_pair_shapes(seed: int, pairs: int = 512):
         n = int(rng.choice([16, 32, 64]))
         out.append((d, n, int(rng.integers(8, 49)), int(rng.integers(8, 49))))
     return out
+
+
+def mlp_init(seed: int, sizes=((128, 21), (128, 128), (2, 128))) -> np.ndarray:
+    """Initial parameters of the width predictor, packed as W1 b1 W2 b2 W3
+    b3 (row-major): weights uniform in +-sqrt(6 / (fan_in + fan_out))
+    (Glorot and Bengio, 2010), biases zero.  FP64; callers cast."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fo, fi in sizes:
+        a = np.sqrt(6.0 / (fi + fo))
+        parts.append(rng.uniform(-a, a, size=fo * fi))
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts)
