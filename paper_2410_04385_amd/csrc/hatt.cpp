@@ -455,7 +455,8 @@ int64_t svd_ws_doubles(int kr, int nc) {
   return (int64_t)kr * nc + 1;
 }
 
-hatt_status svd_exec(bool run, const SvdArgs &sa, double *big, int64_t bigp, int *flags, hipStream_t st) {
+hatt_status svd_exec(bool run, const SvdArgs &sa, double *big, int64_t bigp, int *flags, GemmCtx &gc,
+                     hipStream_t st) {
   if (sa.nc <= kSvdMaxN && (int64_t)sa.kr * sa.nc <= kQrLdsDoubles) {
     site("svd %dx%d", sa.kr, sa.nc);
     LAUNCH(launch_svd_trunc(sa, st));
@@ -473,7 +474,9 @@ hatt_status svd_exec(bool run, const SvdArgs &sa, double *big, int64_t bigp, int
     LAUNCH(launch_svd_big_sweep_end(flags, sa.batch, st));
   }
   LAUNCH(launch_svd_big_finish(sa, big, bigp, st));
-  return HATT_OK;
+  // S V^T = U^T R (rows beyond the kept rank are zero because U's columns are)
+  return gemm(run, gc, CMat{sa.u, 1, sa.ucap, sa.ubs}, CMat{sa.r, sa.nc, 1, sa.rbs}, Mat{sa.svt, sa.nc, 1, sa.sbs},
+              sa.ucap, sa.nc, sa.kr, 1.0, 0.0, sa.batch, st, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -630,7 +633,7 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
     sa.rank_out = sp.orank + c + 1;
     sa.rank_bs = d + 1;
     if (k > nc) return fail(HATT_EUNSUPPORTED, "internal: QR rank exceeds columns");
-    s = svd_exec(run, sa, svdbig, svd_ws, flags, st);
+    s = svd_exec(run, sa, svdbig, svd_ws, flags, gc, st);
     if (s != HATT_OK) return s;
     // out core c = Q U  (m x cap_{c+1})
     s = gemm(run, gc, CMat{Qb, k, 1, qbuf}, CMat{Ub, cap[c + 1], 1, ubuf},
@@ -815,7 +818,7 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
       sa.rank_out = (int64_t *)(h2misc + 2 * P);
       sa.rank_bs = 1;
       sa.rel_keep = std::max(sp.o.ep, 1e-300);
-      s2 = svd_exec(run, sa, h2big, h2_svd, (int *)(h2misc + P), st);
+      s2 = svd_exec(run, sa, h2big, h2_svd, (int *)(h2misc + P), gc, st);
       if (s2 != HATT_OK) return s2;
       s2 = gemm(run, gc, CMat{h2Q, l1, 1, h2_q}, CMat{h2Ur, l1, 1, h2_r}, Mat{h2U, l1, 1, h2_q}, rs1, l1, l1,
                 1.0, 0.0, P, st, true);

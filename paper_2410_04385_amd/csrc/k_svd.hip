@@ -492,20 +492,24 @@ hipError_t launch_svd_big_sweep_end(int *flags, int batch, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Singular values are the column norms of the rotated matrix A V = U S.
+// This kernel sorts them, chooses the rank and writes U (kr x ucap, zero
+// beyond the kept rank); S V^T = U^T R is a GEMM the caller issues next.
 __global__ __launch_bounds__(256) void svd_big_finish_kernel(SvdArgs a, const double *acol, int64_t acs) {
   __shared__ double sig[kSvdBigMaxN];
   __shared__ double sigs[kSvdBigMaxN];
   __shared__ int perm[kSvdBigMaxN];
   __shared__ int s_rho;
   const int kr = a.kr, nc = a.nc;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int p = blockIdx.x;
   const double *A = acol + p * acs;
-  const double *R = a.r + p * a.rbs;
-  for (int c = tid; c < nc; c += 256) {
+  for (int c = wv; c < nc; c += 4) {  // one wave per column, coalesced
+    const double *col = A + (int64_t)c * kr;
     double s2 = 0.0;
-    for (int r = 0; r < kr; ++r) s2 += A[(int64_t)c * kr + r] * A[(int64_t)c * kr + r];
-    sig[c] = sqrt(s2);
+    for (int r = lane; r < kr; r += 64) s2 += col[r] * col[r];
+    for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+    if (lane == 0) sig[c] = sqrt(s2);
   }
   __syncthreads();
   for (int c = tid; c < nc; c += 256) {
@@ -528,20 +532,6 @@ __global__ __launch_bounds__(256) void svd_big_finish_kernel(SvdArgs a, const do
       v = (sc > 0.0) ? A[(int64_t)perm[j] * kr + r] / sc : 0.0;
     }
     U[e] = v;
-  }
-  double *S = a.svt + p * a.sbs;
-  for (int e = tid; e < a.ucap * nc; e += 256) {
-    const int j = e / nc, c = e - j * nc;
-    double v = 0.0;
-    if (j < rho) {
-      const double sc = sigs[j];
-      if (sc > 0.0) {
-        const double *u = A + (int64_t)perm[j] * kr;
-        for (int r = 0; r < kr; ++r) v += u[r] * R[(int64_t)r * nc + c];
-        v /= sc;
-      }
-    }
-    S[e] = v;
   }
 }
 
