@@ -380,7 +380,9 @@ hipError_t launch_svd_big_prepare(const double *r, int64_t rbs, int kr, int nc, 
 
 constexpr int kBigInnerSweeps = 1;
 
-__global__ __launch_bounds__(256) void svd_big_round_kernel(double *acol, int64_t acs, int kr, int nc, int bw,
+constexpr int kBigRoundThreads = 1024;
+
+__global__ __launch_bounds__(kBigRoundThreads) void svd_big_round_kernel(double *acol, int64_t acs, int kr, int nc, int bw,
                                                             int nb, int t, int *flags) {
   extern __shared__ double A[];  // w columns of length kr
   __shared__ int s_any, s_rot;
@@ -397,7 +399,7 @@ __global__ __launch_bounds__(256) void svd_big_round_kernel(double *acol, int64_
   const int w = wa + wb;
   if (w < 2) return;
   double *base = acol + p * acs;
-  for (int e = tid; e < w * kr; e += 256) {
+  for (int e = tid; e < w * kr; e += kBigRoundThreads) {
     const int c = e / kr, r = e - c * kr;
     const int gc = (c < wa) ? a0 + c : b0 + (c - wa);
     A[e] = base[(int64_t)gc * kr + r];
@@ -405,8 +407,14 @@ __global__ __launch_bounds__(256) void svd_big_round_kernel(double *acol, int64_
   if (tid == 0) s_any = 0;
   const int np = w + (w & 1);
   const int npairs = np / 2;
+  // up to a full wave per column pair: the pair's dot products and rotation
+  // then take few steps per lane and the block has enough waves to hide
+  // the LDS latency
   int tpg = 64;
-  while (tpg > 1 && tpg * npairs > 256) tpg >>= 1;
+  while (tpg > 1 && tpg * npairs > kBigRoundThreads) tpg >>= 1;
+  // rotate while |cos| of the pair's angle exceeds sqrt(kr) * eps (the usual
+  // one-sided Jacobi stopping rule); tighter thresholds chase rounding noise
+  const double thr = fmax(1e-15, sqrt((double)kr) * 2.220446049250313e-16);
   const int grp = tid / tpg, gl = tid % tpg;
   __syncthreads();
   // one cyclic sweep over the pairs of the two blocks per round: every
@@ -436,7 +444,7 @@ __global__ __launch_bounds__(256) void svd_big_round_kernel(double *acol, int64_
             be += __shfl_xor(be, off, tpg);
             ga += __shfl_xor(ga, off, tpg);
           }
-          if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+          if (ga != 0.0 && fabs(ga) > thr * sqrt(al * be)) {
             const double zeta = (be - al) / (2.0 * ga);
             const double t2 = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             const double cs = 1.0 / sqrt(1.0 + t2 * t2), sn = cs * t2;
@@ -457,7 +465,7 @@ __global__ __launch_bounds__(256) void svd_big_round_kernel(double *acol, int64_
     if (tid == 0) s_any = 1;
     __syncthreads();
   }
-  for (int e = tid; e < w * kr; e += 256) {
+  for (int e = tid; e < w * kr; e += kBigRoundThreads) {
     const int c = e / kr, r = e - c * kr;
     const int gc = (c < wa) ? a0 + c : b0 + (c - wa);
     base[(int64_t)gc * kr + r] = A[e];
@@ -474,7 +482,7 @@ hipError_t launch_svd_big_round(double *acol, int64_t acs, int kr, int nc, int b
                         (int)(kQrLdsDoubles * sizeof(double)));
     attr_done = true;
   }
-  svd_big_round_kernel<<<dim3((unsigned)(nb / 2), (unsigned)batch), 256, lds, s>>>(acol, acs, kr, nc, bw, nb, t,
+  svd_big_round_kernel<<<dim3((unsigned)(nb / 2), (unsigned)batch), kBigRoundThreads, lds, s>>>(acol, acs, kr, nc, bw, nb, t,
                                                                                  flags);
   return hipGetLastError();
 }
