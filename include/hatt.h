@@ -167,6 +167,8 @@ typedef struct {
   int32_t max_attempts;   /* <= 0 means 8 */
   int32_t variant;        /* 1 or 2 as in hatt_opts */
   double ep;              /* HaTT-2 threshold */
+  const int64_t *ell_init;/* optional host [d+1]: start widths instead of max(r_k, s_k) + p
+                             (e.g. hatt_rankpred_widths); clamped like any request */
 } hatt_adapt_opts;
 
 HATT_API hatt_status hatt_adaptive_plan(const hatt_tt *x, const hatt_tt *y, const hatt_adapt_opts *opts,
@@ -253,6 +255,74 @@ HATT_API const char *hatt_profile_class_name(int32_t cls);
  * site ("class: label", GEMMs labelled with M x N x K and split), with its
  * summed milliseconds and calls, largest first.  Valid until the next stop. */
 HATT_API const char *hatt_profile_report(void);
+
+/*
+ * Learned start widths (a per-bond predictor; not part of the paper, which
+ * picks l by hand and only suggests enlarging a sketch that is too narrow,
+ * Sec. 5.1.1).  For every bond k = 1..d-1 of a pair (x, y) a small network
+ * predicts the rank the truncation at the requested tolerance keeps (rho_k)
+ * and the narrowest width the adaptive rule of hatt_recompress_adaptive
+ * accepts (min(cap_k, rho_k + p)); hatt_recompress_adaptive started at
+ * those widths (ell_init) then falls back to growing them when the
+ * prediction was short, and its acceptance rule judges the result.
+ *
+ * Rows: the bonds of pair 0 (k = 1..d_0-1), then those of pair 1, ...
+ * (sum over pairs of d_p - 1 rows); statistics come from train 0 of a pair.
+ * Feature row (FP32, 21 values): ln r_k(x), ln r_k(y), ln n_k, k/d, ln d,
+ * then the quantiles at q = j/7 (j = 0..7, linear interpolation between
+ * order statistics) of ln max(c_a, 1e-300) over the r_k columns a of V(x_k)
+ * (c_a = squared column norm, the diagonal of V(x_k)^T V(x_k)), then the
+ * same 8 for y.  Bond ranks up to 2048.
+ * Network (FP32): x^ = (f - mu_x) / sd_x; h1 = tanh(W1 x^ + b1);
+ * h2 = tanh(W2 h1 + b2); o = W3 h2 + b3; prediction = o * sd_y + mu_y
+ * (in ln units: ln rho_k, ln l*_k).
+ * theta (HATT_RANKPRED_NTHETA floats): W1[128][21] b1[128] W2[128][128]
+ * b2[128] W3[2][128] b3[2], row-major; stats (HATT_RANKPRED_NSTATS floats):
+ * mu_x[21] sd_x[21] mu_y[2] sd_y[2].  All buffers are device FP32 and owned
+ * by the caller; every call only enqueues work on `stream`.
+ */
+#define HATT_RANKPRED_NIN 21
+#define HATT_RANKPRED_NTHETA 19586
+#define HATT_RANKPRED_NSTATS 46
+
+/* feat: device float [rows][21], rows as above. */
+HATT_API hatt_status hatt_rankpred_features(int32_t npairs, const hatt_tt *x, const hatt_tt *y, float *feat,
+                                           void *stream);
+/* stats = column means and population standard deviations of feat [rows][21]
+ * and label [rows][2] (a deviation below 1e-8 is stored as 1). */
+HATT_API hatt_status hatt_rankpred_fit_stats(const float *feat, const float *label, int64_t rows, float *stats,
+                                            void *stream);
+/* pred: device float [rows][2], the network's predictions (ln rho, ln l*). */
+HATT_API hatt_status hatt_rankpred_forward(const float *theta, const float *stats, const float *feat,
+                                          int64_t rows, float *pred, void *stream);
+/* Workspace bytes of hatt_rankpred_grad / hatt_rankpred_train_step for a
+ * minibatch of `batch` rows. */
+HATT_API size_t hatt_rankpred_ws_bytes(int64_t batch);
+/* Gradient (grad: device float [NTHETA]) and value (loss: device float [1])
+ * of L = 1/(2B) sum over the B = batch rows idx[0..B) (device int32 row
+ * numbers into feat/label) of |o - (label - mu_y) / sd_y|^2. */
+HATT_API hatt_status hatt_rankpred_grad(const float *theta, const float *stats, const float *feat,
+                                       const float *label, const int32_t *idx, int64_t batch, float *grad,
+                                       float *loss, void *ws, size_t ws_bytes, void *stream);
+typedef struct {
+  double lr, beta1, beta2, eps;  /* Kingma and Ba's Adam; <= 0 picks 1e-3, 0.9, 0.999, 1e-8 */
+} hatt_adam_opts;
+/* One Adam step (Kingma and Ba, ICLR 2015, Alg. 1) on the same loss: theta,
+ * m and v (device float [NTHETA]) are updated in place; step counts from 1;
+ * loss (device float [1], may be NULL) receives the minibatch loss before
+ * the update. */
+HATT_API hatt_status hatt_rankpred_train_step(float *theta, float *adam_m, float *adam_v, int64_t step,
+                                             const hatt_adam_opts *opts, const float *stats, const float *feat,
+                                             const float *label, const int32_t *idx, int64_t batch, float *loss,
+                                             void *ws, size_t ws_bytes, void *stream);
+/* Host only: widths and predicted kept ranks from predictions (host float
+ * [rows][2], e.g. copied back from hatt_rankpred_forward).  Per bond
+ * l_k = ceil((1 + margin) max(e^{pred_1}, e^{pred_0} + p)) and
+ * rho_k = ceil(e^{pred_0}), both >= 1; l is then clamped as in hatt_plan.
+ * ell_out / rho_out: host, d_p + 1 entries per pair, concatenated in pair
+ * order (entries 0 and d_p are 1). */
+HATT_API hatt_status hatt_rankpred_widths(int32_t npairs, const hatt_tt *x, const hatt_tt *y, const float *pred,
+                                         double margin, int32_t oversample, int64_t *ell_out, int64_t *rho_out);
 
 /* Message describing the last error of the calling thread ("" if none). */
 HATT_API const char *hatt_last_error(void);

@@ -17,6 +17,13 @@ from .api import (  # noqa: F401
     profile_report,
     profile_start,
     profile_stop,
+    rankpred_features,
+    rankpred_fit_stats,
+    rankpred_forward,
+    rankpred_grad,
+    rankpred_rows,
+    rankpred_train_step,
+    rankpred_widths,
     recompress,
     recompress_adaptive,
     recompress_batched,

@@ -21,7 +21,10 @@ EXPORTED = [
     "tt_norm_plan", "tt_norm", "hatt_sketch_fill", "hatt_profile_start", "hatt_profile_stop",
     "hatt_profile_class_name", "hatt_last_error", "hatt_version", "hatt_set_qr_method",
     "hatt_profile_report", "hatt_batched_plan", "hatt_recompress_batched",
+    "hatt_rankpred_features", "hatt_rankpred_fit_stats", "hatt_rankpred_forward", "hatt_rankpred_ws_bytes",
+    "hatt_rankpred_grad", "hatt_rankpred_train_step", "hatt_rankpred_widths",
 ]
+RANKPRED_NIN, RANKPRED_NTHETA, RANKPRED_NSTATS = 21, 19586, 46
 PROFILE_CLASSES = 8
 
 i64p = ctypes.POINTER(ctypes.c_int64)
@@ -59,7 +62,13 @@ class HattAdaptOpts(ctypes.Structure):
         ("max_attempts", ctypes.c_int32),
         ("variant", ctypes.c_int32),
         ("ep", ctypes.c_double),
+        ("ell_init", i64p),
     ]
+
+
+class HattAdamOpts(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double)]
 
 
 class HattError(RuntimeError):
@@ -94,16 +103,27 @@ def lib() -> ctypes.CDLL:
     L.tt_norm_plan.argtypes = [ttp, szp]
     L.tt_norm.argtypes = [ttp, vp, vp, ctypes.c_size_t, vp]
     L.hatt_sketch_fill.argtypes = [ctypes.c_uint64, ctypes.c_int32, i64p, i64p, vp, vp]
+    i64, sz = ctypes.c_int64, ctypes.c_size_t
+    L.hatt_rankpred_features.argtypes = [ctypes.c_int32, ttp, ttp, vp, vp]
+    L.hatt_rankpred_fit_stats.argtypes = [vp, vp, i64, vp, vp]
+    L.hatt_rankpred_forward.argtypes = [vp, vp, vp, i64, vp, vp]
+    L.hatt_rankpred_ws_bytes.argtypes = [i64]
+    L.hatt_rankpred_grad.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, sz, vp]
+    L.hatt_rankpred_train_step.argtypes = [vp, vp, vp, i64, ctypes.POINTER(HattAdamOpts), vp, vp, vp, vp, i64, vp,
+                                           vp, sz, vp]
+    L.hatt_rankpred_widths.argtypes = [ctypes.c_int32, ttp, ttp, vp, ctypes.c_double, ctypes.c_int32, i64p, i64p]
     L.hatt_profile_start.argtypes = []
     L.hatt_profile_stop.argtypes = [ctypes.POINTER(ctypes.c_double), i64p]
     L.hatt_profile_class_name.argtypes = [ctypes.c_int32]
     L.hatt_profile_class_name.restype = ctypes.c_char_p
     for fn in EXPORTED:
-        if fn not in ("hatt_profile_class_name", "hatt_last_error", "hatt_version", "hatt_profile_report"):
+        if fn not in ("hatt_profile_class_name", "hatt_last_error", "hatt_version", "hatt_profile_report",
+                      "hatt_rankpred_ws_bytes"):
             getattr(L, fn).restype = ctypes.c_int
     L.hatt_last_error.restype = ctypes.c_char_p
     L.hatt_version.restype = ctypes.c_char_p
     L.hatt_profile_report.restype = ctypes.c_char_p
+    L.hatt_rankpred_ws_bytes.restype = ctypes.c_size_t
     _lib = L
     return L
 

@@ -11,7 +11,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import HattAdaptOpts, HattOpts, HattTT, check, i64_array, lib
+from ._lib import HattAdamOpts, HattAdaptOpts, HattOpts, HattTT, check, i64_array, lib
 
 
 def _offsets(n: Sequence[int], r: Sequence[int]):
@@ -215,14 +215,21 @@ def recompress_batched(pairs, ell: int = 0, *, max_rank: int = 0, tol: float = 0
 
 def recompress_adaptive(x: TT, y: TT, tol: float, *, seed: int = 0, oversample: int = 8,
                         max_attempts: int = 8, variant: int = 1, ep: float = 0.0,
+                        ell_init: Optional[Sequence[int]] = None,
                         workspace: Optional[torch.Tensor] = None, stream=None):
     """Tolerance-driven HaTT: grows the sketch widths until the truncation
-    at ``tol`` leaves slack on every bond.  Returns (Result, widths used,
-    attempts)."""
+    at ``tol`` leaves slack on every bond, starting from ``ell_init`` (d+1
+    widths, e.g. predicted ones) or from max(r_k, s_k) + oversample.
+    Returns (Result, widths used, attempts)."""
     xv, kx = x.view()
     yv, ky = y.view()
+    init = None
+    if ell_init is not None:
+        if len(ell_init) != x.d + 1:
+            raise ValueError("ell_init needs d+1 entries")
+        init = i64_array(ell_init)
     o = HattAdaptOpts(float(tol), int(seed) & 0xFFFFFFFFFFFFFFFF, int(oversample), int(max_attempts),
-                      int(variant), float(ep))
+                      int(variant), float(ep), init)
     cap = (ctypes.c_int64 * (x.d + 1))()
     ws = ctypes.c_size_t(0)
     oe = ctypes.c_int64(0)
@@ -336,3 +343,123 @@ def set_qr_method(method: str) -> None:
 
 def version() -> str:
     return lib().hatt_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# Learned start widths (hatt_rankpred_*): FP32 device tensors in and out.
+
+def _f32(t: torch.Tensor, name: str, numel: Optional[int] = None) -> ctypes.c_void_p:
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a contiguous float32 device tensor")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} needs {numel} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _pair_views(pairs):
+    views = [(x.view(), y.view()) for x, y in pairs]
+    xs = (HattTT * len(pairs))(*[v[0][0] for v in views])
+    ys = (HattTT * len(pairs))(*[v[1][0] for v in views])
+    return views, xs, ys
+
+
+def rankpred_rows(pairs) -> int:
+    return sum(x.d - 1 for x, _ in pairs)
+
+
+def rankpred_features(pairs, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """[rows, 21] statistics of every bond of every pair (train 0)."""
+    rows = rankpred_rows(pairs)
+    dev = pairs[0][0].data.device
+    if out is None:
+        out = torch.empty((max(rows, 1), _lib.RANKPRED_NIN), dtype=torch.float32, device=dev)
+    keep, xs, ys = _pair_views(pairs)
+    check("hatt_rankpred_features", lib().hatt_rankpred_features(
+        len(pairs), xs, ys, _f32(out, "out", rows * _lib.RANKPRED_NIN), _stream_ptr(stream)))
+    return out[:rows]
+
+
+def rankpred_fit_stats(feat: torch.Tensor, label: torch.Tensor, stream=None) -> torch.Tensor:
+    stats = torch.empty(_lib.RANKPRED_NSTATS, dtype=torch.float32, device=feat.device)
+    rows = feat.shape[0]
+    check("hatt_rankpred_fit_stats", lib().hatt_rankpred_fit_stats(
+        _f32(feat, "feat", rows * 21), _f32(label, "label", rows * 2), rows, _f32(stats, "stats"),
+        _stream_ptr(stream)))
+    return stats
+
+
+def rankpred_forward(theta: torch.Tensor, stats: torch.Tensor, feat: torch.Tensor, stream=None) -> torch.Tensor:
+    rows = feat.shape[0]
+    pred = torch.empty((max(rows, 1), 2), dtype=torch.float32, device=feat.device)
+    check("hatt_rankpred_forward", lib().hatt_rankpred_forward(
+        _f32(theta, "theta", _lib.RANKPRED_NTHETA), _f32(stats, "stats", _lib.RANKPRED_NSTATS),
+        _f32(feat, "feat", rows * 21), rows, _f32(pred, "pred"), _stream_ptr(stream)))
+    return pred[:rows]
+
+
+def _idx(idx: torch.Tensor) -> ctypes.c_void_p:
+    if idx.dtype != torch.int32 or not idx.is_contiguous() or idx.device.type != "cuda":
+        raise ValueError("idx must be a contiguous int32 device tensor")
+    return ctypes.c_void_p(idx.data_ptr())
+
+
+def _rp_ws(batch: int, workspace: Optional[torch.Tensor], dev) -> torch.Tensor:
+    need = int(lib().hatt_rankpred_ws_bytes(int(batch)))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    return workspace
+
+
+def rankpred_grad(theta, stats, feat, label, idx, workspace=None, stream=None):
+    """(gradient [NTHETA], loss [1]) of the mean loss over the rows idx."""
+    B = idx.numel()
+    grad = torch.empty(_lib.RANKPRED_NTHETA, dtype=torch.float32, device=feat.device)
+    loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+    ws = _rp_ws(B, workspace, feat.device)
+    rows = feat.shape[0]
+    check("hatt_rankpred_grad", lib().hatt_rankpred_grad(
+        _f32(theta, "theta", _lib.RANKPRED_NTHETA), _f32(stats, "stats", _lib.RANKPRED_NSTATS),
+        _f32(feat, "feat", rows * 21), _f32(label, "label", rows * 2), _idx(idx), B, _f32(grad, "grad"),
+        _f32(loss, "loss"), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+    return grad, loss
+
+
+def rankpred_train_step(theta, m, v, step: int, stats, feat, label, idx, *, lr: float = 1e-3,
+                        beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, loss=None,
+                        workspace=None, stream=None):
+    """One Adam step in place on theta (m, v: its moments); returns the
+    minibatch loss (device [1]) before the step."""
+    B = idx.numel()
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+    ws = _rp_ws(B, workspace, feat.device)
+    rows = feat.shape[0]
+    o = HattAdamOpts(float(lr), float(beta1), float(beta2), float(eps))
+    n = _lib.RANKPRED_NTHETA
+    check("hatt_rankpred_train_step", lib().hatt_rankpred_train_step(
+        _f32(theta, "theta", n), _f32(m, "m", n), _f32(v, "v", n), int(step), ctypes.byref(o),
+        _f32(stats, "stats", _lib.RANKPRED_NSTATS), _f32(feat, "feat", rows * 21), _f32(label, "label", rows * 2),
+        _idx(idx), B, _f32(loss, "loss"), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+    return loss
+
+
+def rankpred_widths(pairs, pred, margin: float = 0.0, oversample: int = 8):
+    """Host: per pair (widths [d+1], predicted kept ranks [d+1]) from the
+    predictions (host float32 array or device tensor [rows, 2])."""
+    if isinstance(pred, torch.Tensor):
+        pred = pred.detach().float().cpu().numpy()
+    pred = np.ascontiguousarray(pred, dtype=np.float32)
+    rows = rankpred_rows(pairs)
+    if pred.shape != (rows, 2):
+        raise ValueError(f"pred must be [{rows}, 2]")
+    keep, xs, ys = _pair_views(pairs)
+    ne = sum(x.d + 1 for x, _ in pairs)
+    ell = (ctypes.c_int64 * ne)()
+    rho = (ctypes.c_int64 * ne)()
+    check("hatt_rankpred_widths", lib().hatt_rankpred_widths(
+        len(pairs), xs, ys, ctypes.c_void_p(pred.ctypes.data), float(margin), int(oversample), ell, rho))
+    out, e = [], 0
+    for x, _ in pairs:
+        out.append((list(ell[e:e + x.d + 1]), list(rho[e:e + x.d + 1])))
+        e += x.d + 1
+    return out

@@ -215,11 +215,39 @@ hipError_t launch_svd_big_prepare(const double *r, int64_t rbs, int kr, int nc, 
 hipError_t launch_svd_big_round(double *acol, int64_t acs, int kr, int nc, int bw, int nb, int t, int *flags,
                                 int batch, hipStream_t s);
 hipError_t launch_svd_big_sweep_end(int *flags, int batch, hipStream_t s);
-// sigma, order, rank choice, U and S V^T (= U^T R) from the rotated columns.
+// sigma, order, rank choice and U from the rotated columns (S V^T = U^T R is
+// the caller's GEMM).
 hipError_t launch_svd_big_finish(const SvdArgs &a, const double *acol, int64_t acs, hipStream_t s);
 
 // Frobenius norm of a batch of contiguous blocks: out[p] = ||x_p||.
 hipError_t launch_block_norm(const double *x, int64_t count, int64_t bs, double *out, int batch,
                              hipStream_t s);
+
+// Width predictor (k_rankpred.hip): 21 features per bond, a 21-128-128-2
+// tanh MLP in FP32.
+constexpr int kRpIn = 21, kRpH = 128, kRpOut = 2;
+constexpr int kRpTheta = kRpH * kRpIn + kRpH + kRpH * kRpH + kRpH + kRpOut * kRpH + kRpOut;  // 19586
+constexpr int kRpStats = 2 * kRpIn + 2 * kRpOut;                                            // 46
+constexpr int kRpRowsPerBlock = 64;  // rows per gradient block
+constexpr int kRpMaxBonds = 32;      // bonds per feature launch
+constexpr int kRpMaxRank = 2048;     // largest bond rank the statistics kernel sorts
+struct RpFeatArgs {
+  const double *cx[kRpMaxBonds], *cy[kRpMaxBonds];  // core k of x and y (train 0)
+  int rxp[kRpMaxBonds], rxn[kRpMaxBonds], ryp[kRpMaxBonds], ryn[kRpMaxBonds], n[kRpMaxBonds];
+  int k0;      // 1-based bond index of the first bond of this launch
+  int d;       // order of the pair
+  float *out;  // feature row of bond k0
+};
+struct RpAdam {
+  float *theta, *m, *v;  // theta == nullptr: no update
+  float lr, b1, b2, eps, c1, c2;
+};
+hipError_t launch_rp_features(const RpFeatArgs &a, int bonds, hipStream_t s);
+hipError_t launch_rp_forward(const float *theta, const float *stats, const float *feat, int64_t rows, float *pred,
+                             hipStream_t s);
+hipError_t launch_rp_grad(const float *theta, const float *stats, const float *feat, const float *label,
+                          const int32_t *idx, int64_t batch, float *part, float *loss_part, float *grad,
+                          float *loss, const RpAdam &ad, hipStream_t s);
+hipError_t launch_rp_stats(const float *feat, const float *label, int64_t rows, float *stats, hipStream_t s);
 
 }  // namespace hatt

@@ -338,6 +338,8 @@ bool qr_prepare(int64_t m, int64_t n, QrOp *op) {
   return true;
 }
 
+constexpr int kCholFuseMinPairs = 32;
+
 hatt_status cholqr2_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double *ws, int64_t wsp, int P,
                          GemmCtx &gc, hipStream_t st) {
   const int64_t m = op.m, n = op.n;
@@ -348,16 +350,19 @@ hatt_status cholqr2_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double 
   const int64_t fst = 2 * wsp;  // flag stride in ints
   CMat At{A.ptr, A.cs, A.rs, A.bs};
   CMat q1c{q1, n, 1, wsp}, q1t{q1, 1, n, wsp};
-  // G = A^T A: with a K split the Cholesky kernel sums the partials itself
+  // G = A^T A: with a K split and many pairs the Cholesky kernel (one
+  // workgroup per pair) sums the partials itself; with few pairs the split
+  // is deep and the GEMM's own parallel reduction is faster
   int ks = 1;
-  hatt_status sg = gemm(run, gc, At, A, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true, nullptr, 0, &ks);
+  int *ksp = (P >= kCholFuseMinPairs) ? &ks : nullptr;
+  hatt_status sg = gemm(run, gc, At, A, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true, nullptr, 0, ksp);
   if (sg != HATT_OK) return sg;
   site("chol %lld", (long long)n);
   if (ks > 1) LAUNCH(launch_chol(gc.part, ks * n * n, ks, n * n, r1, r1i, wsp, (int)n, flag, fst, 1, kCholThr1, P, st));
   else LAUNCH(launch_chol(g, wsp, 1, 0, r1, r1i, wsp, (int)n, flag, fst, 1, kCholThr1, P, st));
   sg = gemm(run, gc, A, CMat{r1i, n, 1, wsp}, Mat{q1, n, 1, wsp}, m, n, n, 1.0, 0.0, P, st, false);
   if (sg != HATT_OK) return sg;
-  sg = gemm(run, gc, q1t, q1c, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true, nullptr, 0, &ks);
+  sg = gemm(run, gc, q1t, q1c, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true, nullptr, 0, ksp);
   if (sg != HATT_OK) return sg;
   site("chol %lld", (long long)n);
   if (ks > 1) LAUNCH(launch_chol(gc.part, ks * n * n, ks, n * n, r2, r2i, wsp, (int)n, flag, fst, 0, kCholThr2, P, st));
@@ -1307,6 +1312,8 @@ static hatt_status adapt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_
   std::vector<int64_t> big(d + 1, (int64_t)1 << 40), req(d + 1, 1);
   *cap = clamp_ell(sp->X.n, sp->X.r, sp->Y.r, big);
   for (int k = 1; k < d; ++k) req[k] = std::max(sp->X.r[k], sp->Y.r[k]) + *p;
+  if (ao->ell_init != nullptr)
+    for (int k = 1; k < d; ++k) req[k] = ao->ell_init[k];
   *ell0 = clamp_ell(sp->X.n, sp->X.r, sp->Y.r, req);
   return HATT_OK;
 }
@@ -1542,3 +1549,177 @@ hatt_status hatt_sketch_fill(uint64_t seed, int32_t d, const int64_t *n, const i
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Learned start widths (hatt_rankpred_*).
+
+static hatt_status rp_pairs(int32_t npairs, const hatt_tt *x, const hatt_tt *y, std::vector<Shape> *X,
+                            std::vector<Shape> *Y, int64_t *rows, bool need_data) {
+  if (npairs < 1) return fail(HATT_EINVAL, "npairs must be >= 1");
+  if (x == nullptr || y == nullptr) return fail(HATT_EINVAL, "NULL argument");
+  X->assign(npairs, Shape{});
+  Y->assign(npairs, Shape{});
+  *rows = 0;
+  for (int32_t p = 0; p < npairs; ++p) {
+    hatt_status st = read_tt(&x[p], "x", &(*X)[p], need_data);
+    if (st == HATT_OK) st = read_tt(&y[p], "y", &(*Y)[p], need_data);
+    if (st != HATT_OK) return fail(st, "pair " + std::to_string(p) + ": " + g_err);
+    const Shape &a = (*X)[p], &b = (*Y)[p];
+    if (a.d != b.d || a.n != b.n) return fail(HATT_ESHAPE, "pair " + std::to_string(p) + ": x and y shapes differ");
+    for (int k = 1; k < a.d; ++k)
+      if (a.r[k] > kRpMaxRank || b.r[k] > kRpMaxRank)
+        return fail(HATT_EUNSUPPORTED, "pair " + std::to_string(p) + ": bond rank above 2048");
+    *rows += a.d - 1;
+  }
+  return HATT_OK;
+}
+
+hatt_status hatt_rankpred_features(int32_t npairs, const hatt_tt *x, const hatt_tt *y, float *feat, void *stream) {
+  std::vector<Shape> X, Y;
+  int64_t rows;
+  hatt_status st = rp_pairs(npairs, x, y, &X, &Y, &rows, true);
+  if (st != HATT_OK) return st;
+  if (feat == nullptr && rows > 0) return fail(HATT_EINVAL, "feat is NULL");
+  const bool run = true;
+  hipStream_t strm = (hipStream_t)stream;
+  hipStream_t st_ = strm;
+  int64_t row = 0;
+  for (int32_t p = 0; p < npairs; ++p) {
+    const Shape &a = X[p], &b = Y[p];
+    for (int k0 = 1; k0 < a.d; k0 += kRpMaxBonds) {
+      const int nb = std::min(kRpMaxBonds, a.d - k0);
+      RpFeatArgs fa{};
+      for (int t = 0; t < nb; ++t) {
+        const int c = k0 + t - 1;  // 0-based core of bond k0 + t
+        fa.cx[t] = a.data + a.off[c];
+        fa.cy[t] = b.data + b.off[c];
+        fa.rxp[t] = (int)a.r[c];
+        fa.rxn[t] = (int)a.r[c + 1];
+        fa.ryp[t] = (int)b.r[c];
+        fa.ryn[t] = (int)b.r[c + 1];
+        fa.n[t] = (int)a.n[c];
+      }
+      fa.k0 = k0;
+      fa.d = a.d;
+      fa.out = feat + (row + k0 - 1) * kRpIn;
+      {
+        hipStream_t st = st_;
+        LAUNCH(launch_rp_features(fa, nb, st));
+      }
+    }
+    row += a.d - 1;
+  }
+  g_err.clear();
+  return HATT_OK;
+}
+
+hatt_status hatt_rankpred_fit_stats(const float *feat, const float *label, int64_t rows, float *stats, void *stream) {
+  if (feat == nullptr || label == nullptr || stats == nullptr) return fail(HATT_EINVAL, "NULL argument");
+  if (rows < 1) return fail(HATT_EINVAL, "rows must be >= 1");
+  const bool run = true;
+  hipStream_t st = (hipStream_t)stream;
+  LAUNCH(launch_rp_stats(feat, label, rows, stats, st));
+  g_err.clear();
+  return HATT_OK;
+}
+
+hatt_status hatt_rankpred_forward(const float *theta, const float *stats, const float *feat, int64_t rows,
+                                  float *pred, void *stream) {
+  if (rows < 0) return fail(HATT_EINVAL, "rows must be >= 0");
+  if (rows == 0) {
+    g_err.clear();
+    return HATT_OK;
+  }
+  if (theta == nullptr || stats == nullptr || feat == nullptr || pred == nullptr)
+    return fail(HATT_EINVAL, "NULL argument");
+  const bool run = true;
+  hipStream_t st = (hipStream_t)stream;
+  LAUNCH(launch_rp_forward(theta, stats, feat, rows, pred, st));
+  g_err.clear();
+  return HATT_OK;
+}
+
+size_t hatt_rankpred_ws_bytes(int64_t batch) {
+  if (batch < 1) return 0;
+  const int64_t nblk = (batch + kRpRowsPerBlock - 1) / kRpRowsPerBlock;
+  return (size_t)nblk * (kRpTheta + 1) * sizeof(float);
+}
+
+static hatt_status rp_grad_common(const float *theta, const float *stats, const float *feat, const float *label,
+                                  const int32_t *idx, int64_t batch, float *grad, float *loss, const RpAdam &ad,
+                                  void *ws, size_t ws_bytes, void *stream) {
+  if (theta == nullptr || stats == nullptr || feat == nullptr || label == nullptr || idx == nullptr)
+    return fail(HATT_EINVAL, "NULL argument");
+  if (batch < 1 || batch > ((int64_t)1 << 31)) return fail(HATT_EINVAL, "batch must be in [1, 2^31]");
+  const size_t need = hatt_rankpred_ws_bytes(batch);
+  if (ws == nullptr || ws_bytes < need)
+    return fail(HATT_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  const int64_t nblk = (batch + kRpRowsPerBlock - 1) / kRpRowsPerBlock;
+  float *part = (float *)ws;
+  float *lpart = part + nblk * kRpTheta;
+  const bool run = true;
+  hipStream_t st = (hipStream_t)stream;
+  LAUNCH(launch_rp_grad(theta, stats, feat, label, idx, batch, part, lpart, grad, loss, ad, st));
+  g_err.clear();
+  return HATT_OK;
+}
+
+hatt_status hatt_rankpred_grad(const float *theta, const float *stats, const float *feat, const float *label,
+                               const int32_t *idx, int64_t batch, float *grad, float *loss, void *ws,
+                               size_t ws_bytes, void *stream) {
+  if (grad == nullptr) return fail(HATT_EINVAL, "grad is NULL");
+  RpAdam ad{};
+  return rp_grad_common(theta, stats, feat, label, idx, batch, grad, loss, ad, ws, ws_bytes, stream);
+}
+
+hatt_status hatt_rankpred_train_step(float *theta, float *adam_m, float *adam_v, int64_t step,
+                                     const hatt_adam_opts *opts, const float *stats, const float *feat,
+                                     const float *label, const int32_t *idx, int64_t batch, float *loss, void *ws,
+                                     size_t ws_bytes, void *stream) {
+  if (adam_m == nullptr || adam_v == nullptr) return fail(HATT_EINVAL, "NULL Adam state");
+  if (step < 1) return fail(HATT_EINVAL, "step counts from 1");
+  double lr = 1e-3, b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  if (opts != nullptr) {
+    if (opts->lr > 0) lr = opts->lr;
+    if (opts->beta1 > 0) b1 = opts->beta1;
+    if (opts->beta2 > 0) b2 = opts->beta2;
+    if (opts->eps > 0) eps = opts->eps;
+  }
+  if (!(b1 < 1.0) || !(b2 < 1.0)) return fail(HATT_EINVAL, "Adam betas must be < 1");
+  RpAdam ad{theta, adam_m, adam_v, (float)lr, (float)b1, (float)b2, (float)eps,
+            (float)(1.0 / (1.0 - std::pow(b1, (double)step))), (float)(1.0 / (1.0 - std::pow(b2, (double)step)))};
+  return rp_grad_common(theta, stats, feat, label, idx, batch, nullptr, loss, ad, ws, ws_bytes, stream);
+}
+
+hatt_status hatt_rankpred_widths(int32_t npairs, const hatt_tt *x, const hatt_tt *y, const float *pred,
+                                 double margin, int32_t oversample, int64_t *ell_out, int64_t *rho_out) {
+  std::vector<Shape> X, Y;
+  int64_t rows;
+  hatt_status st = rp_pairs(npairs, x, y, &X, &Y, &rows, false);
+  if (st != HATT_OK) return st;
+  if (pred == nullptr || ell_out == nullptr) return fail(HATT_EINVAL, "NULL argument");
+  if (!(margin >= 0.0) || !std::isfinite(margin)) return fail(HATT_EINVAL, "margin must be finite and >= 0");
+  const int p = oversample > 0 ? oversample : 8;
+  int64_t row = 0, e = 0;
+  for (int32_t q = 0; q < npairs; ++q) {
+    const Shape &a = X[q], &b = Y[q];
+    const int d = a.d;
+    std::vector<int64_t> req(d + 1, 1), rho(d + 1, 1);
+    for (int k = 1; k < d; ++k, ++row) {
+      const double la = (double)pred[2 * row], lb = (double)pred[2 * row + 1];
+      if (!std::isfinite(la) || !std::isfinite(lb))
+        return fail(HATT_EINVAL, "non-finite prediction in row " + std::to_string(row));
+      const double w = std::max(std::exp(lb), std::exp(la) + (double)p);
+      const double lw = std::ceil((1.0 + margin) * w), lr = std::ceil(std::exp(la));
+      req[k] = (int64_t)std::max(1.0, std::min(lw, 9.0e15));
+      rho[k] = (int64_t)std::max(1.0, std::min(lr, 9.0e15));
+    }
+    const std::vector<int64_t> ell = clamp_ell(a.n, a.r, b.r, req);
+    for (int k = 0; k <= d; ++k, ++e) {
+      ell_out[e] = ell[k];
+      if (rho_out) rho_out[e] = rho[k];
+    }
+  }
+  g_err.clear();
+  return HATT_OK;
+}

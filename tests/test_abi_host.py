@@ -228,3 +228,67 @@ def test_fp32_unsupported_ranks_fail_at_plan():
         api.plan(x, x, 90, precision="f32")
     assert e.value.status == -7
     api.plan(x, x, 90)  # FP64 takes it
+
+
+def _uneven_pairs(seed, count):
+    g = np.random.default_rng(seed)
+    pairs = []
+    for _ in range(count):
+        d = int(g.integers(2, 9))
+        n = [int(g.choice([2, 4, 8])) for _ in range(d)]
+        rx = oplan.clamp_ell(n, [1] * (d + 1), [1] * (d + 1), [1] + [int(g.integers(1, 9))] * (d - 1) + [1])
+        ry = oplan.clamp_ell(n, [1] * (d + 1), [1] * (d + 1), [1] + [int(g.integers(1, 9))] * (d - 1) + [1])
+        rx = wk.feasible_ranks(n, max(rx))
+        ry = wk.feasible_ranks(n, max(ry))
+        pairs.append((_cpu_tt(n, rx), _cpu_tt(n, ry)))
+    return pairs
+
+
+def test_rankpred_widths_match_oracle():
+    from oracle import rankpred as orp
+    pairs = _uneven_pairs(3, 12)
+    rows = api.rankpred_rows(pairs)
+    g = np.random.default_rng(4)
+    pred = np.log(g.uniform(0.5, 80.0, size=(rows, 2))).astype(np.float32)
+    for margin, p in ((0.0, 8), (0.15, 8), (0.3, 4)):
+        got = api.rankpred_widths(pairs, pred, margin=margin, oversample=p)
+        r = 0
+        for (x, y), (ell, rho) in zip(pairs, got):
+            want_ell, want_rho = orp.widths(pred[r:r + x.d - 1].astype(np.float64), x.n, x.ranks, y.ranks,
+                                            margin, p)
+            assert ell == want_ell and rho == want_rho
+            r += x.d - 1
+
+
+def test_rankpred_host_errors_and_workspace():
+    pairs = _uneven_pairs(5, 3)
+    rows = api.rankpred_rows(pairs)
+    pred = np.zeros((rows, 2), np.float32)
+    with pytest.raises(HattError) as e:
+        api.rankpred_widths(pairs, pred, margin=-0.1)
+    assert e.value.status == -1
+    bad = pred.copy()
+    bad[0, 0] = np.nan
+    with pytest.raises(HattError):
+        api.rankpred_widths(pairs, bad)
+    with pytest.raises(ValueError):
+        api.rankpred_widths(pairs, pred[:-1])
+    x = _cpu_tt([2, 4, 2], [1, 2, 2, 1])
+    y = _cpu_tt([2, 4, 4], [1, 2, 2, 1])
+    with pytest.raises(HattError) as e:
+        api.rankpred_widths([(x, y)], np.zeros((2, 2), np.float32))
+    assert e.value.status == -2
+    big = _cpu_tt([4096, 4096], [1, 3000, 1])
+    with pytest.raises(HattError) as e:
+        api.rankpred_widths([(big, big)], np.zeros((1, 2), np.float32))
+    assert e.value.status == -7
+    L = _lib.lib()
+    for b in (1, 63, 64, 65, 1000):
+        assert L.hatt_rankpred_ws_bytes(b) == -(-b // 64) * (19586 + 1) * 4
+    assert L.hatt_rankpred_ws_bytes(0) == 0
+
+
+def test_adaptive_start_widths_are_validated():
+    x = _cpu_tt([4, 4, 4], [1, 3, 3, 1])
+    with pytest.raises(ValueError):
+        api.recompress_adaptive(x, x, 1e-6, ell_init=[1, 5, 1])
