@@ -39,7 +39,10 @@ def _parse():
     ap.add_argument("--eager", action="store_true", help="launch kernels directly instead of replaying a HIP graph")
     ap.add_argument("--precision", choices=["f64", "f32"], default="f64",
                     help="f32: range finding on the FP32 matrix cores, projection and truncation in FP64")
-    ap.add_argument("--workload", choices=["spectral", "batched"], default="spectral",
+    ap.add_argument("--rp-train", type=int, default=48, help="rankpred: training recompressions")
+    ap.add_argument("--rp-eval", type=int, default=16, help="rankpred: fresh pairs evaluated")
+    ap.add_argument("--rp-margin", type=float, default=0.1, help="rankpred: width safety margin")
+    ap.add_argument("--workload", choices=["spectral", "batched", "rankpred"], default="spectral",
                     help="spectral: the metric's workload; batched: the 512-pair uneven workload (own JSON line)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (reference dispatch for "
@@ -167,6 +170,106 @@ def _bench_batched(args, torch, wk, H) -> int:
     return 0
 
 
+def _rp_pairs(wk, H, seed, count, max_rs=1024):
+    """Pairs of the uneven 512-pair distribution (spectral cores), leaving
+    out those whose exact rank r_x r_y exceeds the 1024-column SVD limit."""
+    out = []
+    for p, (d, n, rx, ry) in enumerate(wk.batched_pair_shapes(seed, 8 * count)):
+        if rx * ry > max_rs:
+            continue
+        x, y = wk.spectral_pair(seed * 100000 + p, d, n, rx, ry)
+        out.append(((d, n, rx, ry), H.TT.from_cores([x]), H.TT.from_cores([y])))
+        if len(out) == count:
+            break
+    return out
+
+
+def _bench_rankpred(args, torch, wk, H) -> int:
+    """Learned start widths on the uneven distribution at tol 1e-6: label
+    recompressions from the adaptive method, GPU training of the width
+    network, then fresh pairs recompressed adaptively from the default and
+    from the predicted widths (the adaptive rule accepts or grows either)."""
+    import numpy as np
+    tol = wk.WORKLOADS["batched"]["tol"]
+    say = lambda m: print(f"[rankpred] {m}", file=sys.stderr, flush=True)  # noqa: E731
+    train = _rp_pairs(wk, H, 101, args.rp_train)
+    say(f"{len(train)} training pairs")
+    labels, t_label = [], 0.0
+    for i, (shape, x, y) in enumerate(train):
+        t0 = time.perf_counter()
+        res, ell, att = H.recompress_adaptive(x, y, tol, seed=1000 + i, max_attempts=12)
+        torch.cuda.synchronize()
+        t_label += time.perf_counter() - t0
+        labels.append(H.rankpred_labels(res.ranks[0].tolist(), H.adaptive_caps(x, y)))
+        say(f"label {i} {shape} attempts {att} max width {max(ell)} ({time.perf_counter() - t0:.2f} s)")
+        del res
+    pairs = [(x, y) for _, x, y in train]
+    feat = H.rankpred_features(pairs)
+    lab = torch.tensor(np.concatenate(labels), device="cuda")
+    stats = H.rankpred_fit_stats(feat, lab)
+    theta = torch.tensor(wk.mlp_init(7).astype(np.float32), device="cuda")
+    m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+    rows = feat.shape[0]
+    g = np.random.default_rng(11)
+    steps, bsz = 3000, 128
+    idx_all = torch.tensor(g.integers(0, rows, steps * bsz).astype(np.int32), device="cuda")
+    loss = torch.empty(steps, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for st in range(steps):
+        H.rankpred_train_step(theta, m, v, st + 1, stats, feat, lab, idx_all[st * bsz:(st + 1) * bsz], lr=2e-3,
+                              loss=loss[st:st + 1])
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    lh = loss.cpu().numpy()
+    say(f"trained {steps} Adam steps on {rows} bond rows in {t_train:.2f} s; loss {lh[:20].mean():.3g} -> "
+        f"{lh[-100:].mean():.3g}")
+    fresh = _rp_pairs(wk, H, 202, args.rp_eval)
+    rec = []
+    for i, (shape, x, y) in enumerate(fresh):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r0, ell0, a0 = H.recompress_adaptive(x, y, tol, seed=5000 + i, max_attempts=12)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        pred = H.rankpred_forward(theta, stats, H.rankpred_features([(x, y)]))
+        (ell_p, rho_p), = H.rankpred_widths([(x, y)], pred, margin=args.rp_margin)
+        r1, ell1, a1 = H.recompress_adaptive(x, y, tol, seed=5000 + i, ell_init=ell_p, max_attempts=12)
+        torch.cuda.synchronize()
+        t_pred = time.perf_counter() - t0
+        k0, k1 = r0.ranks[0].tolist(), r1.ranks[0].tolist()
+        # the difference TT has ranks rho_0 + rho_1: measured where that stays moderate
+        err = H.rel_err(H.kept_cores(r1), H.kept_cores(r0)) if max(k0) + max(k1) <= 1200 else None
+        rec.append(dict(shape=shape, attempts_plain=a0, attempts_pred=a1, t_plain=t_plain, t_pred=t_pred,
+                        err_vs_plain=err, width_plain=max(ell0), width_pred=max(ell1), kept_plain=max(k0),
+                        kept_pred=max(k1), rho_pred=max(rho_p)))
+        say(f"eval {i} {shape}: plain {a0} attempts {t_plain:.2f} s, predicted {a1} attempts {t_pred:.2f} s, "
+            f"kept {max(k0)}/{max(k1)} (predicted {max(rho_p)}), rel err vs plain {err}")
+        del r0, r1
+        torch.cuda.empty_cache()
+    tp, tq = sum(r["t_plain"] for r in rec), sum(r["t_pred"] for r in rec)
+    line = {"metric": "learned start widths: adaptive recompression time without / with the predictor",
+            "value": tp / tq, "unit": "x", "n_gpus": 1, "higher_is_better": True, "dtype": "f64 (network f32)",
+            "data": "synthetic",
+            "config": {"workload": f"uneven pairs d 8..32, n {{16,32,64}}, r 8..48 with r_x r_y <= 1024, spectral "
+                                   f"cores, tol {tol:g}, margin {args.rp_margin}",
+                       "train_pairs": len(train), "train_rows": int(rows), "eval_pairs": len(fresh)},
+            "train": {"label_s": t_label, "train_s": t_train, "steps": steps, "minibatch": bsz,
+                      "loss_first": float(lh[:20].mean()), "loss_last": float(lh[-100:].mean())},
+            "eval": {"pairs_per_s_plain": len(rec) / tp, "pairs_per_s_pred": len(rec) / tq,
+                     "mean_attempts_plain": float(np.mean([r["attempts_plain"] for r in rec])),
+                     "mean_attempts_pred": float(np.mean([r["attempts_pred"] for r in rec])),
+                     "first_attempt_accepted": sum(r["attempts_pred"] == 1 for r in rec),
+                     "max_rel_err_vs_plain": max((r["err_vs_plain"] for r in rec if r["err_vs_plain"] is not None),
+                                                 default=None),
+                     "pairs_with_err": sum(r["err_vs_plain"] is not None for r in rec),
+                     "tol": tol},
+            "pairs": rec}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     args = _parse()
     if args.gpus != 1:
@@ -187,6 +290,8 @@ def main() -> int:
         return 1
     if args.workload == "batched":
         return _bench_batched(args, torch, wk, H)
+    if args.workload == "rankpred":
+        return _bench_rankpred(args, torch, wk, H)
     cfg = wk.WORKLOADS["spectral"]
     d, n, r, ell, cap = cfg["d"], cfg["n"], cfg["r"], cfg["ell"], cfg["max_rank"]
     B = args.batch

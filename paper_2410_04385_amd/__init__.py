@@ -10,6 +10,10 @@ library; the first call does, and fails loudly if it has not been built.
 from .api import (  # noqa: F401
     TT,
     Result,
+    adaptive_caps,
+    kept_cores,
+    rankpred_labels,
+    rel_err,
     batched_plan,
     hadamard_explicit,
     norm,

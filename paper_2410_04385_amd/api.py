@@ -463,3 +463,59 @@ def rankpred_widths(pairs, pred, margin: float = 0.0, oversample: int = 8):
         out.append((list(ell[e:e + x.d + 1]), list(rho[e:e + x.d + 1])))
         e += x.d + 1
     return out
+
+
+def adaptive_caps(x: TT, y: TT) -> List[int]:
+    """Largest feasible widths of a pair (the clamp of r_k s_k), as the
+    adaptive rule uses them."""
+    xv, kx = x.view()
+    yv, ky = y.view()
+    o = HattAdaptOpts(1.0, 0, 8, 1, 1, 0.0, None)
+    cap = (ctypes.c_int64 * (x.d + 1))()
+    ws = ctypes.c_size_t(0)
+    oe = ctypes.c_int64(0)
+    check("hatt_adaptive_plan", lib().hatt_adaptive_plan(ctypes.byref(xv), ctypes.byref(yv), ctypes.byref(o),
+                                                         cap, ctypes.byref(ws), ctypes.byref(oe)))
+    return list(cap)
+
+
+def rankpred_labels(kept: Sequence[int], cap: Sequence[int], oversample: int = 8) -> np.ndarray:
+    """Targets of the width predictor for one accepted recompression: per
+    bond (ln rho_k, ln min(cap_k, rho_k + p))."""
+    d = len(kept) - 1
+    return np.array([[np.log(kept[k]), np.log(min(int(cap[k]), int(kept[k]) + oversample))] for k in range(1, d)],
+                    dtype=np.float32).reshape(d - 1, 2)
+
+
+def kept_cores(res: Result, b: int = 0) -> List[torch.Tensor]:
+    """Device cores of train b of a result, cut to its kept ranks."""
+    kept = [int(v) for v in res.ranks[b].tolist()]
+    return [res.out.core(k, b)[:kept[k], :, :kept[k + 1]] for k in range(res.out.d)]
+
+
+def rel_err(a: Sequence[torch.Tensor], b: Sequence[torch.Tensor]) -> float:
+    """||a - b||_F / ||b||_F of two TTs given as device core lists (the error
+    measure of Sec. 5), through the difference TT [a | -b] (interior cores
+    block-diagonal, ranks r_a + r_b) and tt_norm."""
+    d = len(a)
+    n = [int(c.shape[1]) for c in a]
+    ra = [1] + [int(c.shape[2]) for c in a]
+    rb = [1] + [int(c.shape[2]) for c in b]
+    flat = []
+    for k in range(d):
+        A, B = a[k], b[k]
+        if d == 1:
+            c = A - B
+        elif k == 0:
+            c = torch.cat([A, -B], dim=2)
+        elif k == d - 1:
+            c = torch.cat([A, B], dim=0)
+        else:
+            c = torch.zeros((ra[k] + rb[k], n[k], ra[k + 1] + rb[k + 1]), dtype=torch.float64, device=A.device)
+            c[:ra[k], :, :ra[k + 1]] = A
+            c[ra[k]:, :, ra[k + 1]:] = B
+        flat.append(c.reshape(-1))
+    ranks = [1] + [ra[k] + rb[k] for k in range(1, d)] + [1] if d > 1 else [1, 1]
+    diff = TT(torch.cat(flat), n, ranks)
+    base = TT(torch.cat([c.reshape(-1) for c in b]), n, rb)
+    return float(norm(diff)[0].item() / norm(base)[0].item())

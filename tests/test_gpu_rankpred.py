@@ -188,3 +188,17 @@ def test_trained_predictor_saves_attempts():
     _say(f"attempts plain {att_plain} predicted {att_pred}")
     assert np.mean(att_pred) < np.mean(att_plain)
     assert sum(a == 1 for a in att_pred) >= 9
+
+
+def test_rel_err_and_labels_match_oracle():
+    _say("rel_err through the difference TT; labels")
+    g = np.random.default_rng(12)
+    for d in (1, 2, 5):
+        n = [3] * d
+        a = wk.gaussian_tt(g, n, wk.feasible_ranks(n, 4))
+        b = [c + 1e-3 * g.standard_normal(c.shape) for c in a]
+        da = [torch.tensor(c, device="cuda") for c in a]
+        db = [torch.tensor(c, device="cuda") for c in b]
+        assert H.rel_err(da, db) == pytest.approx(tt.rel_err(a, b), rel=1e-8)
+    kept, cap = [1, 5, 20, 7, 1], [1, 8, 24, 7, 1]
+    assert np.allclose(H.rankpred_labels(kept, cap), orp.labels(kept, cap).astype(np.float32))
