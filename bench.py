@@ -72,15 +72,18 @@ _GEMM = re.compile(r"gemm (\d+)x(\d+)x(\d+) .*\[(.+)\]")
 
 def _site_group(label, batch):
     """Compiled kernel a launch site runs (named as in a rocprofv3 trace),
-    its bound, and its algorithmic FP64 flops per launch (whole batch)."""
+    its bound, and its algorithmic FP64 flops and compulsory HBM bytes per
+    launch (whole batch: every operand read once, the result written once)."""
     m = _SW.match(label)
     if m:
         n, G, RA, RI, SI, SO = (int(v) for v in m.groups()[1:7])
-        return m.group(8), "alu", 2.0 * n * G * (RI * SI * SO + RA * RI * SO) * batch
+        flops = 2.0 * n * G * (RI * SI * SO + RA * RI * SO) * batch
+        nbytes = 8.0 * (G * RI * SI + n * RA * RI + n * SI * SO + n * G * RA * SO) * batch
+        return m.group(8), "alu", flops, nbytes
     m = _GEMM.match(label)
     if m:
         M, N, K = (int(v) for v in m.groups()[:3])
-        return m.group(4), "mfma", 2.0 * M * N * K * batch
+        return m.group(4), "mfma", 2.0 * M * N * K * batch, 8.0 * (M * K + K * N + M * N) * batch
     return None
 
 
@@ -94,11 +97,12 @@ def _roofline(report, batch, steps, perfmodel):
         g = _site_group(label, batch)
         if g is None:
             continue
-        kernel, bound, f = g
-        acc = groups.setdefault(kernel, {"ms": 0.0, "calls": 0, "flops": 0.0, "bound": bound})
+        kernel, bound, f, nb = g
+        acc = groups.setdefault(kernel, {"ms": 0.0, "calls": 0, "flops": 0.0, "bytes": 0.0, "bound": bound})
         acc["ms"] += ms
         acc["calls"] += calls
         acc["flops"] += f * calls
+        acc["bytes"] += nb * calls
     if not groups:
         return None
     dom = max(groups, key=lambda k: groups[k]["ms"])
@@ -110,7 +114,9 @@ def _roofline(report, batch, steps, perfmodel):
     return {"kernel": dom, "bound": gr["bound"], "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": _traffic(dom, batch),
             "avg_launch_us": 1e6 * avg_s, "launches_per_step": gr["calls"] / steps,
-            "algorithmic_flop_per_launch": per_launch}
+            "algorithmic_flop_per_launch": per_launch,
+            "algorithmic_bytes_per_launch": gr["bytes"] / gr["calls"],
+            "algorithmic_GBs": gr["bytes"] / gr["calls"] / avg_s / 1e9}
 
 
 def _traffic(kernel, batch):

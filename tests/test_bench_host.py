@@ -42,11 +42,15 @@ def test_roofline_groups_sites_by_compiled_kernel():
 
 def test_sandwich_site_flops():
     b = _bench()
-    kern, bound, f = b._site_group(
+    kern, bound, f, nb = b._site_group(
         "sandwich W_L n=32 G=40 RA=20 RI=20 SI=20 SO=20 [sandwich_reg_kernel<24, 2, true>]", 2)
     assert kern == "sandwich_reg_kernel<24, 2, true>" and bound == "alu"
     # per (i, g): T = C ZR (RI x SI x SO) then YL T (RA x RI x SO), 2 flops per multiply-add
     assert f == 2.0 * 32 * 40 * (20 * 20 * 20 + 20 * 20 * 20) * 2
+    # W^{(k)} (r s x l), the n slices of both cores, W_L (r s x n l), once each
+    assert nb == 8.0 * (20 * 20 * 40 + 32 * 400 + 32 * 400 + 400 * 32 * 40) * 2
+    kern, bound, f, nb = b._site_group("gemm 1280x40x400 ks=1 [gemm_f64_kernel<64, 32>]", 3)
+    assert (f, nb) == (2.0 * 1280 * 40 * 400 * 3, 8.0 * (1280 * 400 + 400 * 40 + 1280 * 40) * 3)
     assert b._site_group("qr: chol 40", 1) is None
 
 
