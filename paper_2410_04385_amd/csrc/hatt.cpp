@@ -465,7 +465,10 @@ hatt_status svd_exec(bool run, const SvdArgs &sa, double *big, int64_t bigp, int
   if (sa.nc <= kSvdMaxN && (int64_t)sa.kr * sa.nc <= kQrLdsDoubles) {
     site("svd %dx%d", sa.kr, sa.nc);
     LAUNCH(launch_svd_trunc(sa, st));
-    return HATT_OK;
+    if (sa.nc <= 64) return HATT_OK;
+    // the one-workgroup Jacobi above 64 columns leaves S V^T = U^T R to a GEMM
+    return gemm(run, gc, CMat{sa.u, 1, sa.ucap, sa.ubs}, CMat{sa.r, sa.nc, 1, sa.rbs}, Mat{sa.svt, sa.nc, 1, sa.sbs},
+                sa.ucap, sa.nc, sa.kr, 1.0, 0.0, sa.batch, st, true);
   }
   if (sa.nc > kSvdBigMaxN) return fail(HATT_EUNSUPPORTED, "SVD of more than 1024 columns is not built");
   const int bw = svd_big_block_width(sa.kr);

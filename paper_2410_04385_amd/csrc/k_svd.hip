@@ -212,7 +212,13 @@ hipError_t svd_quad_launch(const SvdArgs &a, hipStream_t s) {
 }
 }  // namespace
 
-__global__ __launch_bounds__(256) void svd_block_kernel(SvdArgs a, int tpg) {
+constexpr int kBlockThreads = 1024;
+
+// One workgroup of kBlockThreads per matrix (64 < nc <= kSvdMaxN, the matrix
+// in LDS): up to 16 lanes per column pair, so a rotation step takes a few rows
+// per lane.  Writes sigma order, rank and U; S V^T = U^T R is the caller's
+// GEMM.
+__global__ __launch_bounds__(kBlockThreads) void svd_block_kernel(SvdArgs a, int tpg) {
   extern __shared__ double A[];  // A[c * kr + r]
   __shared__ double sig[kSvdMaxN];
   __shared__ double sigs[kSvdMaxN];
@@ -223,13 +229,15 @@ __global__ __launch_bounds__(256) void svd_block_kernel(SvdArgs a, int tpg) {
   const int tid = threadIdx.x;
   const int p = blockIdx.x;
   const double *R = a.r + p * a.rbs;
-  for (int e = tid; e < kr * nc; e += 256) {
+  for (int e = tid; e < kr * nc; e += kBlockThreads) {
     int r = e / nc, c = e - r * nc;
     A[c * kr + r] = R[e];
   }
   const int np = nc + (nc & 1);
   const int npairs = np / 2;
   const int grp = tid / tpg, gl = tid % tpg;
+  // rotate while |cos| of a pair's angle exceeds sqrt(kr) * eps
+  const double thr = fmax(1e-15, sqrt((double)kr) * 2.220446049250313e-16);
   __syncthreads();
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (tid == 0) s_rot = 0;
@@ -255,7 +263,7 @@ __global__ __launch_bounds__(256) void svd_block_kernel(SvdArgs a, int tpg) {
             be += __shfl_xor(be, off, tpg);
             ga += __shfl_xor(ga, off, tpg);
           }
-          if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+          if (ga != 0.0 && fabs(ga) > thr * sqrt(al * be)) {
             const double zeta = (be - al) / (2.0 * ga);
             const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -275,13 +283,13 @@ __global__ __launch_bounds__(256) void svd_block_kernel(SvdArgs a, int tpg) {
     if (s_rot == 0) break;
     __syncthreads();
   }
-  for (int c = tid; c < nc; c += 256) {
+  for (int c = tid; c < nc; c += kBlockThreads) {
     double s2 = 0.0;
     for (int r = 0; r < kr; ++r) s2 += A[c * kr + r] * A[c * kr + r];
     sig[c] = sqrt(s2);
   }
   __syncthreads();
-  for (int c = tid; c < nc; c += 256) {
+  for (int c = tid; c < nc; c += kBlockThreads) {
     int rk = 0;
     const double sc = sig[c];
     for (int j = 0; j < nc; ++j) rk += (sig[j] > sc) || (sig[j] == sc && j < c);
@@ -293,7 +301,7 @@ __global__ __launch_bounds__(256) void svd_block_kernel(SvdArgs a, int tpg) {
   __syncthreads();
   const int rho = s_rho;
   double *U = a.u + p * a.ubs;
-  for (int e = tid; e < kr * a.ucap; e += 256) {
+  for (int e = tid; e < kr * a.ucap; e += kBlockThreads) {
     int r = e / a.ucap, j = e - r * a.ucap;
     double v = 0.0;
     if (j < rho) {
@@ -302,20 +310,6 @@ __global__ __launch_bounds__(256) void svd_block_kernel(SvdArgs a, int tpg) {
       v = (sc > 0.0) ? A[c * kr + r] / sc : 0.0;
     }
     U[e] = v;
-  }
-  double *S = a.svt + p * a.sbs;
-  for (int e = tid; e < a.ucap * nc; e += 256) {
-    int j = e / nc, c = e - j * nc;
-    double v = 0.0;
-    if (j < rho) {
-      const int cj = perm[j];
-      const double sc = sigs[j];
-      if (sc > 0.0) {
-        for (int r = 0; r < kr; ++r) v += A[cj * kr + r] * R[r * nc + c];
-        v /= sc;
-      }
-    }
-    S[e] = v;
   }
 }
 
@@ -332,8 +326,8 @@ hipError_t launch_svd_trunc(const SvdArgs &a, hipStream_t s) {
   if (a.nc > kSvdMaxN || (int64_t)a.nc * a.kr > kQrLdsDoubles) return hipErrorInvalidValue;
   const int np = a.nc + (a.nc & 1);
   const int npairs = np / 2;
-  int tpg = 64;
-  while (tpg > 1 && tpg * npairs > 256) tpg >>= 1;
+  int tpg = 16;
+  while (tpg > 1 && tpg * npairs > kBlockThreads) tpg >>= 1;
   const size_t lds = (size_t)a.nc * a.kr * sizeof(double);
   static bool attr_done = false;  // set once: the maximum a launch may ask for
   if (!attr_done) {
@@ -341,7 +335,7 @@ hipError_t launch_svd_trunc(const SvdArgs &a, hipStream_t s) {
                         (int)(kQrLdsDoubles * sizeof(double)));
     attr_done = true;
   }
-  svd_block_kernel<<<a.batch, 256, lds, s>>>(a, tpg);
+  svd_block_kernel<<<a.batch, kBlockThreads, lds, s>>>(a, tpg);
   return hipGetLastError();
 }
 
