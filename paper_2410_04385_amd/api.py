@@ -188,16 +188,25 @@ def batched_plan(pairs, ell: int = 0, *, max_rank: int = 0, tol: float = 0.0, se
 
 def recompress_batched(pairs, ell: int = 0, *, max_rank: int = 0, tol: float = 0.0, seed: int = 0,
                        variant: int = 1, ep: float = 0.0, workspace: Optional[torch.Tensor] = None,
+                       out: Optional[torch.Tensor] = None, ranks: Optional[torch.Tensor] = None,
                        stream=None) -> List[Result]:
     """Uneven batch: ``pairs`` is a list of (x, y) TT pairs of any shapes;
     pair p uses the sketch keyed by seed + p; ell <= 0 asks for
-    l_k = max(r_k, s_k) + 8.  Returns one Result per pair (views into one
-    output buffer)."""
+    l_k = max(r_k, s_k) + 8.  ``out`` / ``ranks`` (flat float64 / int64
+    device tensors of at least out_offset[-1] / rank_offset[-1] elements of
+    batched_plan) may be passed in, e.g. for graph capture.  Returns one
+    Result per pair (views into one output buffer)."""
     p = batched_plan(pairs, ell, max_rank=max_rank, tol=tol, seed=seed, variant=variant, ep=ep)
     views, xs, ys = p["_keep"]
     dev = pairs[0][0].data.device
-    out = torch.zeros(max(p["out_offset"][-1], 1), dtype=torch.float64, device=dev)
-    ranks = torch.empty(max(p["rank_offset"][-1], 1), dtype=torch.int64, device=dev)
+    if out is None:
+        out = torch.zeros(max(p["out_offset"][-1], 1), dtype=torch.float64, device=dev)
+    elif out.dtype != torch.float64 or out.numel() < p["out_offset"][-1]:
+        raise ValueError("out must be float64 with out_offset[-1] elements")
+    if ranks is None:
+        ranks = torch.empty(max(p["rank_offset"][-1], 1), dtype=torch.int64, device=dev)
+    elif ranks.dtype != torch.int64 or ranks.numel() < p["rank_offset"][-1]:
+        raise ValueError("ranks must be int64 with rank_offset[-1] elements")
     if workspace is None or workspace.numel() < p["ws_bytes"]:
         workspace = torch.empty(max(p["ws_bytes"], 1), dtype=torch.uint8, device=dev)
     o, _ = _opts(int(ell), max_rank, tol, seed, variant, ep, 0)
