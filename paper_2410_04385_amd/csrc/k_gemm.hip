@@ -137,12 +137,23 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g) {
     park();
   }
   __syncthreads();
+  // 16 x 16 blocks of this wave that lie wholly in the padding beyond M or N
+  // are skipped (their products are zero and never stored); so are the K
+  // steps of a partial last slab past the valid K.  Both tests are uniform
+  // across the wave.
+  bool live_m[MI], live_n[NJ];
+#pragma unroll
+  for (int i = 0; i < MI; ++i) live_m[i] = m0 + wm + i * 16 < g.M;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) live_n[j] = n0 + wn + j * 16 < g.N;
   int64_t slab = 0;
   for (int64_t k0 = kbeg; k0 < kend; k0 += BK, ++slab) {
     const bool more = k0 + BK < kend;
     if (more) fetch(k0 + BK, slab + 1);
+    const int kval = (int)std::min<int64_t>(BK, kend - k0);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
+      if (kk >= kval) break;
       const int kr = kk + (lane >> 4), c16 = lane & 15;
       CT av[MI], bv[NJ];
 #pragma unroll
@@ -153,7 +164,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g) {
       for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < NJ; ++j)
-          acc[i][j] = mfma16(av[i], bv[j], acc[i][j]);
+          if (live_m[i] && live_n[j]) acc[i][j] = mfma16(av[i], bv[j], acc[i][j]);
     }
     __syncthreads();
     if (more) {
