@@ -102,6 +102,15 @@ __device__ __forceinline__ void mfma_pair(const CT *a0, const CT *b0, const CT *
   }
 }
 
+// One chain, for a wave whose last tile has no partner.
+template <typename CT, typename ACC>
+__device__ __forceinline__ void mfma_one(const CT *a0, const CT *b0, int lda_k, int ldb_k, int ksteps, ACC &c0) {
+#pragma unroll
+  for (int k = 0; k < kSwMaxKSteps; ++k) {
+    if (k < ksteps) c0 = mfma16(a0[k * lda_k], b0[k * ldb_k], c0);
+  }
+}
+
 // CT: compute and LDS type (FP64, or FP32 for the FP32 range finding); C
 // and the output are stored in CT, YL and ZR (cores of x and y) in FP64.
 template <bool LG, typename CT>
@@ -231,8 +240,11 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
       const int tm0 = (t / nt1) * 16, tn0 = (t - (t / nt1) * nt1) * 16;
       const int tm1 = two ? (t2 / nt1) * 16 : tm0, tn1 = two ? (t2 - (t2 / nt1) * nt1) * 16 : tn0;
       acc_t c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
-      mfma_pair(Cs + (tm0 + r16) * pl.ldc + q4, ZRs + q4 * pl.ldz + tn0 + r16, Cs + (tm1 + r16) * pl.ldc + q4,
-                ZRs + q4 * pl.ldz + tn1 + r16, 4, 4 * pl.ldz, pl.SI4 / 4, c0, c1);
+      if (two)  // wave-uniform: the tile index derives from the wave number only
+        mfma_pair(Cs + (tm0 + r16) * pl.ldc + q4, ZRs + q4 * pl.ldz + tn0 + r16, Cs + (tm1 + r16) * pl.ldc + q4,
+                  ZRs + q4 * pl.ldz + tn1 + r16, 4, 4 * pl.ldz, pl.SI4 / 4, c0, c1);
+      else
+        mfma_one(Cs + (tm0 + r16) * pl.ldc + q4, ZRs + q4 * pl.ldz + tn0 + r16, 4, 4 * pl.ldz, pl.SI4 / 4, c0);
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         if (u == 1 && !two) break;
@@ -261,8 +273,11 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
       const int tm0 = (t / nt2) * 16, tn0 = (t - (t / nt2) * nt2) * 16;
       const int tm1 = two ? (t2 / nt2) * 16 : tm0, tn1 = two ? (t2 - (t2 / nt2) * nt2) * 16 : tn0;
       acc_t c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
-      mfma_pair(YLs + (tm0 + r16) * pl.ldy + q4, Ts + q4 * pl.ldt + tn0 + r16, YLs + (tm1 + r16) * pl.ldy + q4,
-                Ts + q4 * pl.ldt + tn1 + r16, 4, 4 * pl.ldt, pl.RI4 / 4, c0, c1);
+      if (two)
+        mfma_pair(YLs + (tm0 + r16) * pl.ldy + q4, Ts + q4 * pl.ldt + tn0 + r16, YLs + (tm1 + r16) * pl.ldy + q4,
+                  Ts + q4 * pl.ldt + tn1 + r16, 4, 4 * pl.ldt, pl.RI4 / 4, c0, c1);
+      else
+        mfma_one(YLs + (tm0 + r16) * pl.ldy + q4, Ts + q4 * pl.ldt + tn0 + r16, 4, 4 * pl.ldt, pl.RI4 / 4, c0);
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         if (u == 1 && !two) break;
