@@ -239,15 +239,15 @@ hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_
   if (ks_out != nullptr) *ks_out = g.ksplit;
   if (g_prof.on) {
     char b[160];
-    int bm = 0, bn = 0;
-    gemm_tile(M, N, &bm, &bn);
+    int bm = 0, bn = 0, wl = 0;
+    gemm_tile(M, N, &bm, &bn, &wl);
     if (ty.prec)
       snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=1 [gemm_f32_kernel<%d, %d, %s, %s, %s>]", (long long)M,
                (long long)N, (long long)K, bm, bn, ty.a32 ? "float" : "double", ty.b32 ? "float" : "double",
                ty.c32 ? "float" : "double");
     else
-      snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=%d%s [gemm_f64_kernel<%d, %d>]", (long long)M, (long long)N,
-               (long long)K, g.ksplit, run_flag ? " flagged" : "", bm, bn);
+      snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=%d%s [gemm_f64_kernel<%d, %d, %d>]", (long long)M,
+               (long long)N, (long long)K, g.ksplit, run_flag ? " flagged" : "", bm, bn, wl);
     g_site = b;
   }
   LAUNCH(launch_gemm(g, st));

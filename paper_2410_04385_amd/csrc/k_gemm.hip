@@ -22,16 +22,23 @@ constexpr int BK = 32;
 // registers while the MFMAs consume the current one from LDS.  CT is the
 // compute type (FP64 or FP32 matrix cores, FP32 accumulating in FP32); TA,
 // TB, TC are the storage types of the operands (converted on load / store).
-template <int BM, int BN, typename CT, typename TA, typename TB, typename TC>
+template <int BM, int BN, typename CT, typename TA, typename TB, typename TC, int WL = 0>
 __device__ __forceinline__ void gemm_body(const GemmArgs &g) {
   using acc_t = typename std::conditional<std::is_same<CT, double>::value, d4_t, f4_t>::type;
   constexpr int LDA_S = BM + 1, LDB_S = BN + 1;
-  constexpr int MI = BM / 32, NJ = BN / 32;
+  // wave layout WL: 0 = 2 x 2 quadrants; 1 = four waves stacked along M
+  // (each BM/4 rows x BN), for thin N; 2 = side by side along N, for thin M.
+  // With a thin side whole 16-wide blocks are dead padding; these layouts
+  // give every wave the same number of live blocks.
+  static_assert(WL == 0 || (WL == 1 && BM == 64) || (WL == 2 && BN == 64), "wave layout");
+  constexpr int MI = WL == 0 ? BM / 32 : (WL == 1 ? BM / 64 : BM / 16);
+  constexpr int NJ = WL == 0 ? BN / 32 : (WL == 1 ? BN / 16 : BN / 64);
   constexpr int A_PER = BM * BK / 256, B_PER = BN * BK / 256;
   __shared__ CT As[BK * LDA_S];  // As[k * LDA_S + m]
   __shared__ CT Bs[BK * LDB_S];  // Bs[k * LDB_S + n]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  const int wm = WL == 0 ? (wave >> 1) * (BM / 2) : (WL == 1 ? wave * (BM / 4) : 0);
+  const int wn = WL == 0 ? (wave & 1) * (BN / 2) : (WL == 2 ? wave * (BN / 4) : 0);
   const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
   const int ks = g.ksplit;
   const int p = blockIdx.z / ks, kc = blockIdx.z - (blockIdx.z / ks) * ks;
@@ -204,9 +211,9 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g) {
   }
 }
 
-template <int BM, int BN>
+template <int BM, int BN, int WL>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
-  gemm_body<BM, BN, double, double, double, double>(g);
+  gemm_body<BM, BN, double, double, double, double, WL>(g);
 }
 
 // FP32 matrix cores, FP32 accumulation; operands stored as FP32 or FP64.
@@ -234,15 +241,19 @@ __global__ void splitk_reduce_kernel(GemmArgs g) {
 
 // Tile shape: 32 rows or columns when that side of C is at most 32 wide
 // (less padding for the thin operands of the sweep), else 64.
-void gemm_tile(int64_t M, int64_t N, int *bm, int *bn) {
+void gemm_tile(int64_t M, int64_t N, int *bm, int *bn, int *wl) {
   *bm = (M <= 32) ? 32 : 64;
   *bn = (N <= 32) ? 32 : 64;
-  if (*bm == 64 && *bn == 64 && N <= 48 && M >= 256) *bn = 32;  // e.g. N = 40: 2 tiles of 32
+  // one 64-wide tile for 32 < N <= 48 (A is fetched once; the dead fourth
+  // column block is skipped), its waves stacked along M; likewise along N for
+  // 32 < M <= 48
+  *wl = 0;
+  if (*bm == 64 && *bn == 64) *wl = (N <= 48) ? 1 : ((M <= 48) ? 2 : 0);
 }
 
 int gemm_pick_ksplit(int64_t M, int64_t N, int64_t K, int batch) {
-  int bm, bn;
-  gemm_tile(M, N, &bm, &bn);
+  int bm, bn, wl;
+  gemm_tile(M, N, &bm, &bn, &wl);
   const int64_t tiles = ((M + bm - 1) / bm) * ((N + bn - 1) / bn) * (int64_t)batch;
   int ks = 1;
   // aim for ~8 workgroups per CU (latency hiding) while keeping >= 4 K slabs per chunk
@@ -256,16 +267,19 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
   if (a.K <= 0) a.ksplit = 1;  // C = beta C
   if (a.ksplit < 1) a.ksplit = 1;
   if (a.ksplit > 1 && a.part == nullptr) a.ksplit = 1;
-  int bm, bn;
-  gemm_tile(a.M, a.N, &bm, &bn);
+  int bm, bn, wl;
+  gemm_tile(a.M, a.N, &bm, &bn, &wl);
   if (a.prec) a.ksplit = 1;  // the FP32 path writes its result directly
   dim3 grid((unsigned)((a.M + bm - 1) / bm), (unsigned)((a.N + bn - 1) / bn), (unsigned)(a.batch * a.ksplit));
   if (!a.prec) {
     if (a.a_f32 || a.b_f32 || a.c_f32) return hipErrorInvalidValue;
-    if (bm == 64 && bn == 64) gemm_f64_kernel<64, 64><<<grid, 256, 0, s>>>(a);
-    else if (bm == 64) gemm_f64_kernel<64, 32><<<grid, 256, 0, s>>>(a);
-    else if (bn == 64) gemm_f64_kernel<32, 64><<<grid, 256, 0, s>>>(a);
-    else gemm_f64_kernel<32, 32><<<grid, 256, 0, s>>>(a);
+    if (bm == 64 && bn == 64) {
+      if (wl == 1) gemm_f64_kernel<64, 64, 1><<<grid, 256, 0, s>>>(a);
+      else if (wl == 2) gemm_f64_kernel<64, 64, 2><<<grid, 256, 0, s>>>(a);
+      else gemm_f64_kernel<64, 64, 0><<<grid, 256, 0, s>>>(a);
+    } else if (bm == 64) gemm_f64_kernel<64, 32, 0><<<grid, 256, 0, s>>>(a);
+    else if (bn == 64) gemm_f64_kernel<32, 64, 0><<<grid, 256, 0, s>>>(a);
+    else gemm_f64_kernel<32, 32, 0><<<grid, 256, 0, s>>>(a);
   } else {
     const int combo = a.a_f32 * 4 + a.b_f32 * 2 + a.c_f32;
 #define HATT_GEMM32(TA, TB, TC)                                                     \
