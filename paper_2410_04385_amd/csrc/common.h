@@ -177,6 +177,10 @@ constexpr int kCholMaxN = 64;
 hipError_t launch_chol(const double *g, int64_t gbs, int ks, int64_t kstride, double *r, double *rinv,
                        int64_t rbs, int n, int *flag, int64_t fstride, int first, double thr_rel, int batch,
                        hipStream_t s);
+// The same factorisation with the Gram matrix A^T A formed in the kernel from
+// A (m x n per pair, any strides; one block per pair streams all of A).
+hipError_t launch_gram_chol(CMat A, int64_t m, int n, double *r, double *rinv, int64_t rbs, int *flag,
+                            int64_t fstride, int first, double thr_rel, int batch, hipStream_t s);
 
 // ---- Jacobi SVD + rank choice (k_svd.hip) ----------------------------------
 // For each pair: R (kr x nc, row-major, kr <= nc <= kSvdMaxN) = U S V^T by

@@ -350,23 +350,30 @@ hatt_status cholqr2_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double 
   const int64_t fst = 2 * wsp;  // flag stride in ints
   CMat At{A.ptr, A.cs, A.rs, A.bs};
   CMat q1c{q1, n, 1, wsp}, q1t{q1, 1, n, wsp};
-  // G = A^T A: with a K split and many pairs the Cholesky kernel (one
-  // workgroup per pair) sums the partials itself; with few pairs the split
-  // is deep and the GEMM's own parallel reduction is faster
-  int ks = 1;
-  int *ksp = (P >= kCholFuseMinPairs) ? &ks : nullptr;
-  hatt_status sg = gemm(run, gc, At, A, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true, nullptr, 0, ksp);
-  if (sg != HATT_OK) return sg;
-  site("chol %lld", (long long)n);
-  if (ks > 1) LAUNCH(launch_chol(gc.part, ks * n * n, ks, n * n, r1, r1i, wsp, (int)n, flag, fst, 1, kCholThr1, P, st));
-  else LAUNCH(launch_chol(g, wsp, 1, 0, r1, r1i, wsp, (int)n, flag, fst, 1, kCholThr1, P, st));
-  sg = gemm(run, gc, A, CMat{r1i, n, 1, wsp}, Mat{q1, n, 1, wsp}, m, n, n, 1.0, 0.0, P, st, false);
-  if (sg != HATT_OK) return sg;
-  sg = gemm(run, gc, q1t, q1c, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true, nullptr, 0, ksp);
-  if (sg != HATT_OK) return sg;
-  site("chol %lld", (long long)n);
-  if (ks > 1) LAUNCH(launch_chol(gc.part, ks * n * n, ks, n * n, r2, r2i, wsp, (int)n, flag, fst, 0, kCholThr2, P, st));
-  else LAUNCH(launch_chol(g, wsp, 1, 0, r2, r2i, wsp, (int)n, flag, fst, 0, kCholThr2, P, st));
+  hatt_status sg;
+  if (P >= kCholFuseMinPairs) {
+    // many pairs fill the GPU with one block per pair: each block forms its
+    // pair's Gram matrix on the matrix cores and factors it in place
+    site("gram+chol %lldx%lld", (long long)m, (long long)n);
+    LAUNCH(launch_gram_chol(A, m, (int)n, r1, r1i, wsp, flag, fst, 1, kCholThr1, P, st));
+    sg = gemm(run, gc, A, CMat{r1i, n, 1, wsp}, Mat{q1, n, 1, wsp}, m, n, n, 1.0, 0.0, P, st, false);
+    if (sg != HATT_OK) return sg;
+    site("gram+chol %lldx%lld", (long long)m, (long long)n);
+    LAUNCH(launch_gram_chol(q1c, m, (int)n, r2, r2i, wsp, flag, fst, 0, kCholThr2, P, st));
+  } else {
+    // few pairs: a split-K Gram GEMM (with its parallel reduction) spreads the
+    // long K over the GPU, then one block per pair factors G
+    sg = gemm(run, gc, At, A, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true);
+    if (sg != HATT_OK) return sg;
+    site("chol %lld", (long long)n);
+    LAUNCH(launch_chol(g, wsp, 1, 0, r1, r1i, wsp, (int)n, flag, fst, 1, kCholThr1, P, st));
+    sg = gemm(run, gc, A, CMat{r1i, n, 1, wsp}, Mat{q1, n, 1, wsp}, m, n, n, 1.0, 0.0, P, st, false);
+    if (sg != HATT_OK) return sg;
+    sg = gemm(run, gc, q1t, q1c, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true);
+    if (sg != HATT_OK) return sg;
+    site("chol %lld", (long long)n);
+    LAUNCH(launch_chol(g, wsp, 1, 0, r2, r2i, wsp, (int)n, flag, fst, 0, kCholThr2, P, st));
+  }
   sg = gemm(run, gc, q1c, CMat{r2i, n, 1, wsp}, Q, m, n, n, 1.0, 0.0, P, st, false, flag, fst);
   if (sg != HATT_OK) return sg;
   if (R.ptr) {

@@ -21,6 +21,7 @@
 // diag(R) are made non-negative (columns of Q and rows of R flipped
 // together).
 #include "common.h"
+#include "stage.h"
 
 namespace hatt {
 
@@ -386,33 +387,13 @@ hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_
 // step j is read from row j).  G is read as the in-order sum of ks split-K
 // partial products (ks = 1: G itself), the same order a split-K reduction
 // uses.  One 256-thread block per pair; W has n rows of 2n + 1 doubles.
-__global__ __launch_bounds__(256) void chol_kernel(const double *g, int64_t gbs, int ks, int64_t kstride,
-                                                   double *r, double *rinv, int64_t rbs, int n, int *flag,
-                                                   int64_t fstride, int first, double thr_rel) {
-  extern __shared__ double W[];
-  __shared__ double piv[kCholMaxN];
-  __shared__ double dmax_s;
+// Elimination of [G | I] held in W (n rows of 2n + 1; only the upper
+// triangle of the left half need be set), then R, R^{-1} and the pair's flag.
+// Every thread of the 256-thread block calls it.
+__device__ void chol_eliminate(double *W, double *piv, double &dmax_s, int n, double *ro, double *ri, int *f,
+                               int first, double thr_rel) {
   const int ld = 2 * n + 1;
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
-  const int p = blockIdx.x;
-  const double *G = g + p * gbs;
-  for (int i = ty; i < n; i += 4) {
-    for (int c = tx; c < n; c += 64) {
-      // partials fetched 8 at a time, summed in chunk order
-      double v = 0.0;
-      for (int t0 = 0; t0 < ks; t0 += 8) {
-        double x[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = (t0 + u < ks) ? G[(t0 + u) * kstride + i * n + c] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (t0 + u < ks) v += x[u];
-      }
-      W[i * ld + c] = v;
-      W[i * ld + n + c] = (i == c) ? 1.0 : 0.0;
-    }
-  }
-  __syncthreads();
   if (tid == 0) {
     double m = 0.0;
     for (int j = 0; j < n; ++j) m = fmax(m, W[j * ld + j]);
@@ -463,8 +444,6 @@ __global__ __launch_bounds__(256) void chol_kernel(const double *g, int64_t gbs,
     }
     __syncthreads();
   }
-  double *ro = r + p * rbs;
-  double *ri = rinv + p * rbs;
   for (int i = ty; i < n; i += 4) {
     const double si = sqrt(piv[i]);
     for (int c = tx; c < n; c += 64) {
@@ -476,9 +455,107 @@ __global__ __launch_bounds__(256) void chol_kernel(const double *g, int64_t gbs,
   }
   if (tid == 0) {
     const int ok = bad ? 0 : 1;
-    int *f = flag + p * fstride;
     *f = first ? ok : (*f & ok);
   }
+}
+
+
+__global__ __launch_bounds__(256) void chol_kernel(const double *g, int64_t gbs, int ks, int64_t kstride,
+                                                   double *r, double *rinv, int64_t rbs, int n, int *flag,
+                                                   int64_t fstride, int first, double thr_rel) {
+  extern __shared__ double W[];
+  __shared__ double piv[kCholMaxN];
+  __shared__ double dmax_s;
+  const int ld = 2 * n + 1;
+  const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+  const int p = blockIdx.x;
+  const double *G = g + p * gbs;
+  for (int i = ty; i < n; i += 4) {
+    for (int c = tx; c < n; c += 64) {
+      // partials fetched 8 at a time, summed in chunk order
+      double v = 0.0;
+      for (int t0 = 0; t0 < ks; t0 += 8) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = (t0 + u < ks) ? G[(t0 + u) * kstride + i * n + c] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (t0 + u < ks) v += x[u];
+      }
+      W[i * ld + c] = v;
+      W[i * ld + n + c] = (i == c) ? 1.0 : 0.0;
+    }
+  }
+  __syncthreads();
+  chol_eliminate(W, piv, dmax_s, n, r + p * rbs, rinv + p * rbs, flag + p * fstride, first, thr_rel);
+}
+
+// CholeskyQR step fused with its Gram matrix, for batches of many pairs: the
+// block of pair p streams A_p (m x n, n <= 64) once; the four waves take
+// interleaved groups of 4 rows and accumulate the upper-triangle 16 x 16
+// blocks of A^T A on the matrix cores (a lane's fragment of rows 4s..4s+3 is
+// both operands: A(l%16, l/16) of block i is A(4s + l/16, 16 i + l%16), the
+// same element as B(l/16, l%16) of block j); the waves then add their
+// partial blocks into W in wave order (deterministic) and the block runs the
+// elimination above.
+template <int NB>
+__global__ __launch_bounds__(256) void gram_chol_kernel(CMat A, int64_t m, double *r, double *rinv, int64_t rbs,
+                                                        int n, int *flag, int64_t fstride, int first,
+                                                        double thr_rel) {
+  extern __shared__ double W[];
+  __shared__ double piv[kCholMaxN];
+  __shared__ double dmax_s;
+  constexpr int U = 4;  // row groups of 4 fetched before their MFMAs
+  const int ld = 2 * n + 1;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int r16 = lane & 15, q4 = lane >> 4;
+  const int p = blockIdx.x;
+  const double *Ab = A.ptr + p * A.bs;
+  d4_t acc[NB][NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = d4_t{0, 0, 0, 0};
+  const int64_t groups = (m + 3) / 4;
+  for (int64_t s0 = (int64_t)wave * U; s0 < groups; s0 += 4 * U) {
+    double v[U][NB];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t row = 4 * (s0 + u) + q4;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int col = 16 * b + r16;
+        v[u][b] = (row < m && col < n) ? Ab[row * A.rs + (int64_t)col * A.cs] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = i; j < NB; ++j) acc[i][j] = mfma16(v[u][i], v[u][j], acc[i][j]);
+  }
+  for (int e = tid; e < n * ld; e += 256) {
+    const int i = e / ld, c = e - i * ld;
+    W[e] = (c == n + i) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = i; j < NB; ++j)
+#pragma unroll
+          for (int vv = 0; vv < 4; ++vv) {
+            const int row = 16 * i + mfma_row<double>(q4, vv), col = 16 * j + r16;
+            if (row < n && col < n && col >= row) W[row * ld + col] += acc[i][j][vv];
+          }
+    }
+    __syncthreads();
+  }
+  chol_eliminate(W, piv, dmax_s, n, r + p * rbs, rinv + p * rbs, flag + p * fstride, first, thr_rel);
 }
 
 hipError_t launch_chol(const double *g, int64_t gbs, int ks, int64_t kstride, double *r, double *rinv,
@@ -493,6 +570,27 @@ hipError_t launch_chol(const double *g, int64_t gbs, int ks, int64_t kstride, do
     attr_done = true;
   }
   chol_kernel<<<batch, 256, lds, s>>>(g, gbs, ks, kstride, r, rinv, rbs, n, flag, fstride, first, thr_rel);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_chol(CMat A, int64_t m, int n, double *r, double *rinv, int64_t rbs, int *flag,
+                            int64_t fstride, int first, double thr_rel, int batch, hipStream_t s) {
+  if (n > kCholMaxN || n < 1 || m < 1) return hipErrorInvalidValue;
+  const size_t lds = (size_t)n * (2 * n + 1) * sizeof(double);
+  static bool attr_done = false;
+  if (!attr_done) {
+    const int mx = (int)(kCholMaxN * (2 * kCholMaxN + 1) * sizeof(double));
+    hipFuncSetAttribute((const void *)gram_chol_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    hipFuncSetAttribute((const void *)gram_chol_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    hipFuncSetAttribute((const void *)gram_chol_kernel<3>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    hipFuncSetAttribute((const void *)gram_chol_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    attr_done = true;
+  }
+  const int nb = (n + 15) / 16;
+  if (nb == 1) gram_chol_kernel<1><<<batch, 256, lds, s>>>(A, m, r, rinv, rbs, n, flag, fstride, first, thr_rel);
+  else if (nb == 2) gram_chol_kernel<2><<<batch, 256, lds, s>>>(A, m, r, rinv, rbs, n, flag, fstride, first, thr_rel);
+  else if (nb == 3) gram_chol_kernel<3><<<batch, 256, lds, s>>>(A, m, r, rinv, rbs, n, flag, fstride, first, thr_rel);
+  else gram_chol_kernel<4><<<batch, 256, lds, s>>>(A, m, r, rinv, rbs, n, flag, fstride, first, thr_rel);
   return hipGetLastError();
 }
 

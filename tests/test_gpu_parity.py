@@ -505,3 +505,31 @@ def test_fp32_range_finding_full_order():
     e32, e64 = tt.rel_err(a.train(0), zz), tt.rel_err(b.train(0), zz)
     _say(f"  error vs z: f32 {e32:.6f}, f64 {e64:.6f}")
     assert abs(e32 - e64) <= 1e-3 * e64
+
+
+def test_many_pairs_fused_gram_cholesky():
+    """40 pairs in one batch (the CholeskyQR2 Gram matrices are then formed
+    inside the factorisation kernel): every pair matches the oracle, also
+    the two whose second factor has bond rank 1 in disguise (zero columns), so
+    their sketched frames are rank deficient and the Householder fallback
+    takes over for those pairs only."""
+    B = 40
+    n = [8, 8, 8, 8, 8, 8]
+    pairs = [wk.spectral_pair(4000 + b, d=6, n=8, rx=6, ry=5) for b in range(B)]
+    for b in (3, 17):
+        y, z = pairs[b]
+        z = [c.copy() for c in z]
+        for c in z[:-1]:
+            c[:, :, 1:] = 0.0
+        pairs[b] = (y, z)
+    ys = [p[0] for p in pairs]
+    zs = [p[1] for p in pairs]
+    l = _ell(ys[0], zs[0], 24)
+    R = wk.gaussian_sketch(np.random.default_rng(6), n, l)
+    _say("hatt_recompress batch=40 ell=24 max_rank=10 (fused Gram + Cholesky, two rank-deficient pairs)")
+    res = _gpu_hatt(ys, zs, 24, sketch=H.TT.from_cores(R), max_rank=10)
+    for b in range(B):
+        ref = rounding.tt_round(ohatt.hatt(ys[b], zs[b], R), max_rank=10)
+        got = res.train(b)
+        assert tt.ranks(got) == tt.ranks(ref), b
+        assert tt.rel_err(got, ref) <= TOL, b
