@@ -11,16 +11,20 @@
 //
 // A sweep visits every column pair once in the round-robin (circle) order:
 // nc' - 1 rounds (nc' = nc rounded up to even) of nc'/2 disjoint pairs.  A
-// pair is rotated when |a_p . a_q| > 1e-15 ||a_p|| ||a_q||; sweeps stop when
+// pair is rotated when |a_p . a_q| > tau ||a_p|| ||a_q|| with
+// tau = max(1e-15, kr eps) (below the rounding noise of a kr-term dot product
+// the test would keep firing and the sweeps never end); sweeps stop when
 // none is.
-//   * nc <= 64: one 256-thread workgroup per matrix, lane c of each of the
-//     four waves keeps a quarter of column c in registers; partners are read
-//     through LDS and the dot products are reduced over the waves.
+//   * nc <= 64: one wavefront per matrix, lane c keeps column c in
+//     registers; partners are read through LDS.
 //   * larger nc: one 256-thread workgroup per matrix, A in LDS, each pair
 //     handled by a group of lanes that reduce with shuffles.
 #include "common.h"
 
 namespace hatt {
+
+// Rotation threshold on |cos| of a column pair's angle (see above).
+__device__ __forceinline__ double jacobi_tau(int kr) { return fmax(1e-15, (double)kr * 2.220446049250313e-16); }
 
 __device__ __forceinline__ int rr_partner(int c, int t, int np) {
   // round t: position 0 holds index 0, position j >= 1 holds 1 + (j - 1 + t) mod (np - 1);
@@ -69,31 +73,27 @@ __device__ int choose_rank(const double *sig_sorted, int kr, int nc, const SvdAr
   return rho;
 }
 
-// nc <= 64: four wavefronts per matrix.  Lane c of every wave holds column c;
-// wave w holds rows w*KR4 .. w*KR4 + KR4 - 1 of it in registers.  A round
-// publishes the rows through LDS (double-buffered by round parity), each wave
-// forms partial dot products with the partner column, and the partials are
-// summed over the waves in a fixed order, so both lanes of a pair, in every
-// wave, derive bit-identical rotations.
-template <int KR4>
-__global__ __launch_bounds__(256) void svd_quad_kernel(SvdArgs a) {
+// nc <= 64: one wavefront per matrix (a 64-thread block).  Lane c holds all
+// of column c in registers; a round publishes the columns through LDS
+// (double-buffered by round parity) and both lanes of a pair form the same
+// full-length dot products (the same products summed in the same order), so
+// they derive bit-identical rotations without any cross-wave reduction.
+template <int KR>
+__global__ __launch_bounds__(64) void svd_wave_kernel(SvdArgs a) {
   extern __shared__ double sm[];
-  constexpr int ROWS = 4 * KR4;
-  double *xb0 = sm;                   // ROWS x 64, xb[r * 64 + c]
-  double *xb1 = sm + ROWS * 64;
-  double *part = sm + 2 * ROWS * 64;  // part[(w * 3 + k) * 64 + c]
+  double *xb0 = sm;            // KR x 64, xb[r * 64 + c]
+  double *xb1 = sm + KR * 64;
   __shared__ double sig[64];
   __shared__ double sigs[64];
   __shared__ int perm[64];
   __shared__ int s_rho;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lane = threadIdx.x;
   const int p = blockIdx.x;
   const int kr = a.kr, nc = a.nc;
   const double *R = a.r + p * a.rbs;
-  const int r0 = w * KR4;
-  double col[KR4];
+  double col[KR];
 #pragma unroll
-  for (int i = 0; i < KR4; ++i) col[i] = (lane < nc && r0 + i < kr) ? R[(r0 + i) * nc + lane] : 0.0;
+  for (int i = 0; i < KR; ++i) col[i] = (lane < nc && i < kr) ? R[i * nc + lane] : 0.0;
   const int np = nc + (nc & 1);
   int buf = 0;
   for (int sweep = 0; sweep < 60; ++sweep) {
@@ -102,43 +102,32 @@ __global__ __launch_bounds__(256) void svd_quad_kernel(SvdArgs a) {
       double *xb = buf ? xb1 : xb0;
       buf ^= 1;
 #pragma unroll
-      for (int i = 0; i < KR4; ++i) xb[(r0 + i) * 64 + lane] = col[i];
+      for (int i = 0; i < KR; ++i) xb[i * 64 + lane] = col[i];
       __syncthreads();
       const int q = rr_partner(lane, t, np);
-      const bool act = lane < nc && q < nc;
-      double y[KR4];
-      double al = 0.0, be = 0.0, ga = 0.0;
-      if (act) {
-        const double *pc = xb + r0 * 64 + q;
+      if (lane < nc && q < nc) {
+        double y[KR];
+        double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-        for (int i = 0; i < KR4; ++i) {
-          y[i] = pc[i * 64];
+        for (int i = 0; i < KR; ++i) {
+          y[i] = xb[i * 64 + q];
           al += col[i] * col[i];
           be += y[i] * y[i];
           ga += col[i] * y[i];
         }
-      }
-      part[(w * 3 + 0) * 64 + lane] = al;
-      part[(w * 3 + 1) * 64 + lane] = be;
-      part[(w * 3 + 2) * 64 + lane] = ga;
-      __syncthreads();
-      if (act) {
-        al = ((part[0 * 64 + lane] + part[3 * 64 + lane]) + part[6 * 64 + lane]) + part[9 * 64 + lane];
-        be = ((part[1 * 64 + lane] + part[4 * 64 + lane]) + part[7 * 64 + lane]) + part[10 * 64 + lane];
-        ga = ((part[2 * 64 + lane] + part[5 * 64 + lane]) + part[8 * 64 + lane]) + part[11 * 64 + lane];
         // roles: the lower index is "p"
         const bool isp = lane < q;
         const double ap = isp ? al : be, aq = isp ? be : al;
-        if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(ap * aq)) {
+        if (ga != 0.0 && fabs(ga) > jacobi_tau(kr) * sqrt(ap * aq)) {
           const double zeta = (aq - ap) / (2.0 * ga);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
           if (isp) {
 #pragma unroll
-            for (int i = 0; i < KR4; ++i) col[i] = cs * col[i] - sn * y[i];
+            for (int i = 0; i < KR; ++i) col[i] = cs * col[i] - sn * y[i];
           } else {
 #pragma unroll
-            for (int i = 0; i < KR4; ++i) col[i] = sn * y[i] + cs * col[i];
+            for (int i = 0; i < KR; ++i) col[i] = sn * y[i] + cs * col[i];
           }
           rot = 1;
         }
@@ -146,21 +135,17 @@ __global__ __launch_bounds__(256) void svd_quad_kernel(SvdArgs a) {
     }
     if (!__syncthreads_or(rot)) break;
   }
-  // column norms (partials summed in wave order), final columns to xb0, R to xb1
+  // final columns to xb0, R to xb1, column norms
   double s2 = 0.0;
 #pragma unroll
-  for (int i = 0; i < KR4; ++i) s2 += col[i] * col[i];
-  part[w * 64 + lane] = s2;
-#pragma unroll
-  for (int i = 0; i < KR4; ++i) xb0[(r0 + i) * 64 + lane] = col[i];
-  for (int e = tid; e < kr * nc; e += 256) xb1[e] = R[e];
-  __syncthreads();
-  if (w == 0) {
-    const double t2 = ((part[lane] + part[64 + lane]) + part[128 + lane]) + part[192 + lane];
-    sig[lane] = (lane < nc) ? sqrt(t2) : -1.0;
+  for (int i = 0; i < KR; ++i) {
+    s2 += col[i] * col[i];
+    xb0[i * 64 + lane] = col[i];
   }
+  for (int e = lane; e < kr * nc; e += 64) xb1[e] = R[e];
+  sig[lane] = (lane < nc) ? sqrt(s2) : -1.0;
   __syncthreads();
-  if (w == 0 && lane < nc) {
+  if (lane < nc) {
     int rk = 0;
     const double sc = sig[lane];
     for (int j = 0; j < nc; ++j) rk += (sig[j] > sc) || (sig[j] == sc && j < lane);
@@ -168,11 +153,11 @@ __global__ __launch_bounds__(256) void svd_quad_kernel(SvdArgs a) {
     sigs[rk] = sc;
   }
   __syncthreads();
-  if (tid == 0) s_rho = choose_rank(sigs, kr, nc, a, p);
+  if (lane == 0) s_rho = choose_rank(sigs, kr, nc, a, p);
   __syncthreads();
   const int rho = s_rho;
   double *U = a.u + p * a.ubs;
-  for (int e = tid; e < kr * a.ucap; e += 256) {
+  for (int e = lane; e < kr * a.ucap; e += 64) {
     const int r = e / a.ucap, j = e - r * a.ucap;
     double v = 0.0;
     if (j < rho) {
@@ -183,7 +168,7 @@ __global__ __launch_bounds__(256) void svd_quad_kernel(SvdArgs a) {
   }
   // S V^T rows = U_rho^T R
   double *S = a.svt + p * a.sbs;
-  for (int e = tid; e < a.ucap * nc; e += 256) {
+  for (int e = lane; e < a.ucap * nc; e += 64) {
     const int j = e / nc, c = e - j * nc;
     double v = 0.0;
     if (j < rho) {
@@ -199,15 +184,15 @@ __global__ __launch_bounds__(256) void svd_quad_kernel(SvdArgs a) {
 }
 
 namespace {
-template <int KR4>
-hipError_t svd_quad_launch(const SvdArgs &a, hipStream_t s) {
-  const size_t lds = (size_t)(2 * 4 * KR4 * 64 + 12 * 64) * sizeof(double);
+template <int KR>
+hipError_t svd_wave_launch(const SvdArgs &a, hipStream_t s) {
+  const size_t lds = (size_t)(2 * KR * 64) * sizeof(double);
   static bool attr_done = false;
   if (!attr_done) {
-    hipFuncSetAttribute((const void *)svd_quad_kernel<KR4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipFuncSetAttribute((const void *)svd_wave_kernel<KR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     attr_done = true;
   }
-  svd_quad_kernel<KR4><<<a.batch, 256, lds, s>>>(a);
+  svd_wave_kernel<KR><<<a.batch, 64, lds, s>>>(a);
   return hipGetLastError();
 }
 }  // namespace
@@ -236,8 +221,7 @@ __global__ __launch_bounds__(kBlockThreads) void svd_block_kernel(SvdArgs a, int
   const int np = nc + (nc & 1);
   const int npairs = np / 2;
   const int grp = tid / tpg, gl = tid % tpg;
-  // rotate while |cos| of a pair's angle exceeds sqrt(kr) * eps
-  const double thr = fmax(1e-15, sqrt((double)kr) * 2.220446049250313e-16);
+  const double thr = jacobi_tau(kr);
   __syncthreads();
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (tid == 0) s_rot = 0;
@@ -317,11 +301,11 @@ hipError_t launch_svd_trunc(const SvdArgs &a, hipStream_t s) {
   if (a.batch <= 0) return hipSuccess;
   if (a.kr > a.nc || a.kr < 1) return hipErrorInvalidValue;
   if (a.nc <= 64) {
-    if (a.kr <= 16) return svd_quad_launch<4>(a, s);
-    if (a.kr <= 32) return svd_quad_launch<8>(a, s);
-    if (a.kr <= 40) return svd_quad_launch<10>(a, s);
-    if (a.kr <= 48) return svd_quad_launch<12>(a, s);
-    return svd_quad_launch<16>(a, s);
+    if (a.kr <= 16) return svd_wave_launch<16>(a, s);
+    if (a.kr <= 32) return svd_wave_launch<32>(a, s);
+    if (a.kr <= 40) return svd_wave_launch<40>(a, s);
+    if (a.kr <= 48) return svd_wave_launch<48>(a, s);
+    return svd_wave_launch<64>(a, s);
   }
   if (a.nc > kSvdMaxN || (int64_t)a.nc * a.kr > kQrLdsDoubles) return hipErrorInvalidValue;
   const int np = a.nc + (a.nc & 1);
@@ -406,9 +390,7 @@ __global__ __launch_bounds__(kBigRoundThreads) void svd_big_round_kernel(double 
   // the LDS latency
   int tpg = 64;
   while (tpg > 1 && tpg * npairs > kBigRoundThreads) tpg >>= 1;
-  // rotate while |cos| of the pair's angle exceeds sqrt(kr) * eps (the usual
-  // one-sided Jacobi stopping rule); tighter thresholds chase rounding noise
-  const double thr = fmax(1e-15, sqrt((double)kr) * 2.220446049250313e-16);
+  const double thr = jacobi_tau(kr);
   const int grp = tid / tpg, gl = tid % tpg;
   __syncthreads();
   // one cyclic sweep over the pairs of the two blocks per round: every
