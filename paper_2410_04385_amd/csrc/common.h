@@ -144,7 +144,7 @@ int gemm_pick_ksplit(int64_t M, int64_t N, int64_t K, int batch);
 // Sum of the split-K partials of a launch made with no_reduce set, into C.
 hipError_t launch_splitk_reduce(const GemmArgs &g, hipStream_t s);
 // Output tile (BM x BN) and wave layout (0: 2 x 2, 1: waves along M, 2: along
-// N; the FP32 kernels use 0) the launcher uses for an M x N product.
+// N) the launcher uses for an M x N product.
 void gemm_tile(int64_t M, int64_t N, int *bm, int *bn, int *wl);
 // Layout of the split-K partials: pair p, chunk t at part + (p * ksplit + t) * M * N.
 

@@ -242,9 +242,9 @@ hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_
     int bm = 0, bn = 0, wl = 0;
     gemm_tile(M, N, &bm, &bn, &wl);
     if (ty.prec)
-      snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=1 [gemm_f32_kernel<%d, %d, %s, %s, %s>]", (long long)M,
+      snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=1 [gemm_f32_kernel<%d, %d, %s, %s, %s, %d>]", (long long)M,
                (long long)N, (long long)K, bm, bn, ty.a32 ? "float" : "double", ty.b32 ? "float" : "double",
-               ty.c32 ? "float" : "double");
+               ty.c32 ? "float" : "double", wl);
     else
       snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=%d%s [gemm_f64_kernel<%d, %d, %d>]", (long long)M,
                (long long)N, (long long)K, g.ksplit, run_flag ? " flagged" : "", bm, bn, wl);
@@ -1160,10 +1160,11 @@ hatt_status hatt_recompress(const hatt_tt *x, const hatt_tt *y, const hatt_tt *s
 // ---------------------------------------------------------------------------
 // Uneven batches: every pair has its own shape.  Pairs are planned one by one
 // and run on up to kBatchStreams library streams forked from the caller's
-// stream (event wait) and joined back; stream s takes pairs s, s + S, ... in
-// order and reuses one workspace slot, so concurrent pairs never share
-// scratch memory.
-constexpr int kBatchStreams = 4;
+// stream (event wait) and joined back; pairs go largest first to the least
+// loaded stream, and each stream reuses one workspace slot, so concurrent
+// pairs never share scratch memory.  How many streams run at once is set by
+// the process's hardware queues (HIP's GPU_MAX_HW_QUEUES, 4 by default).
+constexpr int kBatchStreams = 16;
 
 struct BatchStreams {
   int device = -1;
@@ -1201,7 +1202,43 @@ struct BatchPlan {
   std::vector<int64_t> out_off, rank_off;
   size_t slot = 0;                        // workspace bytes of one slot
   int streams = 1;
+  std::vector<int> stream_of;             // library stream of each pair
 };
+
+// Sec. 4 cost of one recompression at its widths (per train): the HaTT-1
+// terms n r s l (4r + 4s + 6l) per interior core; a relative measure for
+// ordering pairs.
+static double batch_pair_cost(const HattSpec &sp) {
+  double c = 0.0;
+  for (int k = 0; k + 1 < sp.X.d; ++k) {
+    const double n = (double)sp.X.n[k], r = (double)sp.X.r[k + 1], q = (double)sp.Y.r[k + 1],
+                 l = (double)sp.ell[k + 1];
+    c += n * r * q * l * (4.0 * r + 4.0 * q + 6.0 * l);
+  }
+  return (c + 1.0) * (double)sp.X.batch;
+}
+
+// Longest first onto the least loaded stream (each stream runs its pairs in
+// order): the slowest stream finishes earlier than with a round robin.
+static void batch_assign(BatchPlan *bp) {
+  const int np = (int)bp->sp.size(), S = bp->streams;
+  std::vector<int> order(np);
+  std::vector<double> cost(np);
+  for (int p = 0; p < np; ++p) {
+    order[p] = p;
+    cost[p] = batch_pair_cost(bp->sp[p]);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<double> load(S, 0.0);
+  bp->stream_of.assign(np, 0);
+  for (int p : order) {
+    int k = 0;
+    for (int t = 1; t < S; ++t)
+      if (load[t] < load[k]) k = t;
+    bp->stream_of[p] = k;
+    load[k] += cost[p];
+  }
+}
 
 static hatt_status batch_prepare(int32_t npairs, const hatt_tt *x, const hatt_tt *y, const hatt_opts *o,
                                  bool need_data, BatchPlan *bp) {
@@ -1247,6 +1284,7 @@ static hatt_status batch_prepare(int32_t npairs, const hatt_tt *x, const hatt_tt
   }
   bp->slot = std::max<size_t>(slot, 256);
   bp->streams = std::min<int>(kBatchStreams, npairs);
+  batch_assign(bp);
   return HATT_OK;
 }
 
@@ -1285,8 +1323,13 @@ hatt_status hatt_recompress_batched(int32_t npairs, const hatt_tt *x, const hatt
   if (hipEventRecord(bs->fork, caller) != hipSuccess) return fail(HATT_EDEVICE, "event record failed");
   for (int k = 0; k < bp.streams; ++k)
     if (hipStreamWaitEvent(bs->s[k], bs->fork, 0) != hipSuccess) return fail(HATT_EDEVICE, "stream wait failed");
-  for (int32_t p = 0; p < npairs; ++p) {
-    const int k = p % bp.streams;
+  // enqueue in decreasing cost so each stream starts with its largest pair
+  std::vector<int> order(npairs);
+  for (int32_t p = 0; p < npairs; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return batch_pair_cost(bp.sp[a]) > batch_pair_cost(bp.sp[b]); });
+  for (int32_t p : order) {
+    const int k = bp.stream_of[p];
     HattSpec &sp = bp.sp[p];
     sp.out = out + bp.out_off[p];
     sp.orank = out_rank + bp.rank_off[p];

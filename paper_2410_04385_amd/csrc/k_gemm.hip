@@ -217,9 +217,9 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
 }
 
 // FP32 matrix cores, FP32 accumulation; operands stored as FP32 or FP64.
-template <int BM, int BN, typename TA, typename TB, typename TC>
+template <int BM, int BN, typename TA, typename TB, typename TC, int WL>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
-  gemm_body<BM, BN, float, TA, TB, TC>(g);
+  gemm_body<BM, BN, float, TA, TB, TC, WL>(g);
 }
 
 // Sum of the ksplit partial products in chunk order (bitwise reproducible).
@@ -282,12 +282,15 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
     else gemm_f64_kernel<32, 32, 0><<<grid, 256, 0, s>>>(a);
   } else {
     const int combo = a.a_f32 * 4 + a.b_f32 * 2 + a.c_f32;
-#define HATT_GEMM32(TA, TB, TC)                                                     \
-  do {                                                                              \
-    if (bm == 64 && bn == 64) gemm_f32_kernel<64, 64, TA, TB, TC><<<grid, 256, 0, s>>>(a); \
-    else if (bm == 64) gemm_f32_kernel<64, 32, TA, TB, TC><<<grid, 256, 0, s>>>(a);        \
-    else if (bn == 64) gemm_f32_kernel<32, 64, TA, TB, TC><<<grid, 256, 0, s>>>(a);        \
-    else gemm_f32_kernel<32, 32, TA, TB, TC><<<grid, 256, 0, s>>>(a);                      \
+#define HATT_GEMM32(TA, TB, TC)                                                              \
+  do {                                                                                       \
+    if (bm == 64 && bn == 64) {                                                              \
+      if (wl == 1) gemm_f32_kernel<64, 64, TA, TB, TC, 1><<<grid, 256, 0, s>>>(a);           \
+      else if (wl == 2) gemm_f32_kernel<64, 64, TA, TB, TC, 2><<<grid, 256, 0, s>>>(a);      \
+      else gemm_f32_kernel<64, 64, TA, TB, TC, 0><<<grid, 256, 0, s>>>(a);                   \
+    } else if (bm == 64) gemm_f32_kernel<64, 32, TA, TB, TC, 0><<<grid, 256, 0, s>>>(a);     \
+    else if (bn == 64) gemm_f32_kernel<32, 64, TA, TB, TC, 0><<<grid, 256, 0, s>>>(a);       \
+    else gemm_f32_kernel<32, 32, TA, TB, TC, 0><<<grid, 256, 0, s>>>(a);                     \
   } while (0)
     if (combo == 5) HATT_GEMM32(float, double, float);       // W_L (f32) x sketch (f64) -> W (f32)
     else if (combo == 2) HATT_GEMM32(double, float, double); // X (f64) x W (f32) -> Y (f64)
