@@ -177,7 +177,7 @@ def _bench_batched(args, torch, wk, H) -> int:
             "ms_per_step": 1000.0 * wall_s / args.steps, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": "batched: 512 pairs, d 8..32, n {16,32,64}, r 8..48, l = max(r,s)+8, tol 1e-6",
-                       "launch": "eager, 16 library streams, GPU_MAX_HW_QUEUES="
+                       "launch": "eager, 32 library streams, GPU_MAX_HW_QUEUES="
                                  + os.environ.get("GPU_MAX_HW_QUEUES", "default")},
             "mean_kept_rank": float(np.mean([max(k) for k in kept]))}
     print(json.dumps(line), flush=True)
@@ -292,9 +292,9 @@ def main() -> int:
               "(see DESIGN.md).", file=sys.stderr)
         return 2
     if args.workload == "batched":
-        # independent pairs run on the library's 16 streams; HIP's default of 4
+        # independent pairs run on the library's 32 streams; HIP's default of 4
         # hardware queues per process would run only 4 of them at a time
-        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "32")
     import numpy as np
     import torch
 

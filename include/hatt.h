@@ -127,7 +127,7 @@ HATT_API hatt_status hatt_recompress(const hatt_tt *x, const hatt_tt *y, const h
  * hatt_batched_plan: out_offset and rank_offset (host [npairs + 1], the last
  * entry is the total), ell_out (host, may be NULL: the clamped widths of
  * every pair, d_p + 1 entries per pair, concatenated in pair order) and
- * ws_bytes.  The pairs are enqueued, largest first, on up to sixteen
+ * ws_bytes.  The pairs are enqueued, largest first, on up to 32
  * library-owned streams forked from `stream` and joined back to it (so the
  * call composes with stream order and graph capture); concurrent pairs use
  * separate workspace slots.  How many streams run concurrently is bounded by

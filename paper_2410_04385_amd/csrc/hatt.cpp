@@ -1164,7 +1164,7 @@ hatt_status hatt_recompress(const hatt_tt *x, const hatt_tt *y, const hatt_tt *s
 // loaded stream, and each stream reuses one workspace slot, so concurrent
 // pairs never share scratch memory.  How many streams run at once is set by
 // the process's hardware queues (HIP's GPU_MAX_HW_QUEUES, 4 by default).
-constexpr int kBatchStreams = 16;
+constexpr int kBatchStreams = 32;
 
 struct BatchStreams {
   int device = -1;
