@@ -98,9 +98,13 @@ struct SwPlan {
   int ldc, ldz, ldy, ldt, M1; // LDS row strides; padded stage-1 row count
   int64_t lds_doubles;
   FastDiv fd_ri, fd_so, fd_gc; // index decodes of the stage-1 rows and stage-2 columns
+  int ks;                     // K steps of both products when they are equal and a
+                              // register-blocked instantiation covers them, else 0
 };
 bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl);
 hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStream_t s);
+// Name of the compiled kernel launch_sandwich_mfma runs for this plan.
+const char *sandwich_mfma_name(const SandwichArgs &a, const SwPlan &pl);
 // Name of the compiled kernel launch_sandwich picks for these arguments.
 const char *sandwich_kernel_name(const SandwichArgs &a);
 

@@ -378,9 +378,8 @@ bool g_sandwich_mfma = true;
 const char *sandwich_kernel_name(const SandwichArgs &a) {
   const int64_t budget = 19456;
   SwPlan pl;
-  if (a.prec) return (a.og == 1) ? "sandwich_mfma_kernel<true, float>" : "sandwich_mfma_kernel<false, float>";
-  if (g_sandwich_mfma && sandwich_mfma_plan(a, kSandwichLdsDoubles, &pl))
-    return (a.og == 1) ? "sandwich_mfma_kernel<true, double>" : "sandwich_mfma_kernel<false, double>";
+  if ((a.prec || g_sandwich_mfma) && sandwich_mfma_plan(a, kSandwichLdsDoubles, &pl)) return sandwich_mfma_name(a, pl);
+  if (a.prec) return "none (FP32 sandwich needs the matrix-core plan)";
   const int RIp = (a.RI + 1) & ~1, SIp = (a.SI + 1) & ~1;
   const int64_t fixed = (int64_t)a.RA * RIp + (((int64_t)a.SI * a.SO + 1) & ~1);
   const int m = std::max(std::max(a.RI, a.SI), 1);

@@ -21,6 +21,11 @@ namespace {
 __host__ __device__ inline int rup(int x, int m) { return (x + m - 1) / m * m; }
 }  // namespace
 
+// Largest K-step count with a register-blocked instantiation, and its fetch
+// slots per thread for the next slice's YL / ZR entries.
+constexpr int kSwKsMax = 8;
+__host__ __device__ constexpr int sw_ks_slots(int ks) { return ks <= 2 ? 2 : (ks <= 4 ? 4 : 8); }
+
 bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
   const int RI4 = rup(a.RI, 4), SI4 = rup(a.SI, 4);
   const int SO16 = rup(a.SO, 16), RA16 = rup(a.RA, 16);
@@ -77,8 +82,14 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
   // prefetch offsets are 32-bit
   const int64_t ymax = (int64_t)(a.RA - 1) * std::llabs(a.ylr) + (int64_t)(a.RI - 1) * std::llabs(a.ylc);
   const int64_t zmax = (int64_t)(a.SI - 1) * std::llabs(a.zrr) + (int64_t)(a.SO - 1) * std::llabs(a.zrc);
-  pf = pf && ymax < (1LL << 31) && zmax < (1LL << 31);
+  const bool off32 = ymax < (1LL << 31) && zmax < (1LL << 31);
+  pf = pf && off32;
   pl->pf = pf ? 1 : 0;
+  // the register-blocked kernel: equal K steps, and every valid YL / ZR entry in a fetch slot
+  pl->ks = 0;
+  if (off32 && RI4 == SI4 && RI4 / 4 <= kSwKsMax &&
+      (int64_t)a.RA * a.RI + (int64_t)a.SI * a.SO <= 256LL * sw_ks_slots(RI4 / 4))
+    pl->ks = RI4 / 4;
   return true;
 }
 
@@ -310,6 +321,282 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
   }
 }
 
+// Register-blocked variant for KS K steps on both products (K padded to
+// 4 KS), same LDS layout and grid as sandwich_mfma_kernel.  A wave takes
+// every fourth 16 x 16 output block of a product; the operand that is the
+// same for all of a wave's blocks (the ZR block column of stage 1 when the
+// stage-1 column-block count divides 4, the YL block row of stage 2 when the
+// stage-2 row-block count divides 4) is read from LDS once per slice, and the
+// fragments of the wave's next block are read while the KS MFMAs of the
+// current one run.  Only the valid YL / ZR entries are fetched (the padding of
+// both buffers is zeroed once).  The next slice's entries are parked after
+// stage 1 and the one after that is fetched before stage 2, so the fetch
+// registers stay live across the stage-2 stores and the wait for them (vector
+// loads and stores share one counter) comes a whole stage 1 after the last
+// store.
+
+// Blocks u, u + 4, ... < units of one product, on one wave.  pa(u) / pb(u)
+// point at lane's first A / B element of block u (K steps sa / sb apart);
+// with HA / HB the operand is the same for every block and held in ha / hb.
+template <int KS, bool HA, bool HB, typename ACC, typename CT, class PA, class PB, class EP>
+__device__ __forceinline__ void ks_blocks(int u, int units, const CT (&ha)[KS], const CT (&hb)[KS], PA pa, int sa,
+                                          PB pb, int sb, EP ep) {
+  CT a0[KS], b0[KS], a1[KS], b1[KS];
+  auto load = [&](int uu, CT(&av)[KS], CT(&bv)[KS]) {
+    const CT *xa = pa(uu);
+    const CT *xb = pb(uu);
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      if (!HA) av[k] = xa[k * sa];
+      if (!HB) bv[k] = xb[k * sb];
+    }
+  };
+  auto mma = [&](const CT(&av)[KS], const CT(&bv)[KS]) {
+    ACC c = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < KS; ++k) c = mfma16(HA ? ha[k] : av[k], HB ? hb[k] : bv[k], c);
+    return c;
+  };
+  if (u >= units) return;
+  load(u, a0, b0);
+  for (;;) {
+    const int u1 = u + 4;
+    if (u1 < units) load(u1, a1, b1);
+    ep(u, mma(a0, b0));
+    if (u1 >= units) return;
+    const int u2 = u1 + 4;
+    if (u2 < units) load(u2, a0, b0);
+    ep(u1, mma(a1, b1));
+    if (u2 >= units) return;
+    u = u2;
+  }
+}
+
+template <bool LG, typename CT, int KS>
+__global__ __launch_bounds__(256) void sandwich_ks_kernel(SandwichArgs a, SwPlan pl) {
+  using acc_t = typename std::conditional<std::is_same<CT, double>::value, d4_t, f4_t>::type;
+  constexpr int K4 = 4 * KS, NSL = sw_ks_slots(KS);
+  extern __shared__ double smraw[];
+  CT *sm = reinterpret_cast<CT *>(smraw);
+  const int RA = a.RA, RI = a.RI, SI = a.SI, SO = a.SO;
+  const int GC = pl.GC;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int r16 = lane & 15, q4 = lane >> 4;
+  const int64_t i0 = (int64_t)blockIdx.x * pl.ipb;
+  const int64_t i1 = std::min<int64_t>(a.n, i0 + pl.ipb);
+  const int64_t g0 = (int64_t)blockIdx.y * GC;
+  const int p = blockIdx.z;
+  const int gc = (int)std::min<int64_t>(GC, a.G - g0);
+  if (gc <= 0 || i0 >= i1) return;
+  const int ldc = pl.ldc, ldz = pl.ldz, ldy = pl.ldy, ldt = pl.ldt;
+  const int yzs = K4 * ldz + pl.RA16 * ldy;
+  CT *Cs = sm;                    // pl.M1 rows (g, a) x ldc, K = b
+  CT *YZ0 = Cs + pl.M1 * ldc;     // [ZR: K4 x ldz | YL: RA16 x ldy], two buffers
+  CT *Ts = YZ0 + 2 * yzs;         // K4 rows (a) x ldt, N = stage-2 columns
+  const int M1 = gc * RI, M1p = rup(M1, 16);
+
+  // ---- C chunk, zero K padding (as in sandwich_mfma_kernel)
+  const CT *cbase = reinterpret_cast<const CT *>(static_cast<const void *>(a.c)) + p * a.cb + g0 * a.cg;
+  if (a.cg == 1) {
+    stage_lds<8>(gc * RI * K4, Rad3(tid, 256, gc, K4), Cs,
+                 [&](const Rad3 &d) {
+                   return (d.i1 < SI) ? (double)cbase[d.i0 * a.cg + d.i2 * a.ca + d.i1 * a.cbb] : 0.0;
+                 },
+                 [&](const Rad3 &d) { return (d.i0 * RI + d.i2) * ldc + d.i1; });
+  } else {
+    stage_lds<8>(gc * RI * K4, Rad3(tid, 256, K4, RI), Cs,
+                 [&](const Rad3 &d) {
+                   return (d.i0 < SI) ? (double)cbase[d.i2 * a.cg + d.i1 * a.ca + d.i0 * a.cbb] : 0.0;
+                 },
+                 [&](const Rad3 &d) { return (d.i2 * RI + d.i1) * ldc + d.i0; });
+  }
+  for (int e = tid; e < (M1p - M1) * K4; e += 256) {
+    const int r = M1 + e / K4, k = e - (e / K4) * K4;
+    Cs[r * ldc + k] = (CT)0;
+  }
+  for (int e = tid; e < (K4 - RI) * ldt; e += 256) Ts[RI * ldt + e] = (CT)0;
+  for (int e = tid; e < 2 * yzs; e += 256) YZ0[e] = (CT)0;
+
+  // ---- fetch slots: slot u of this thread is valid entry tid + 256 u of
+  // [ZR (SI x SO) | YL (RA x RI)]
+  const int nz = SI * SO, nv = nz + RA * RI;
+  int s_lds[NSL], s_off[NSL];
+  unsigned s_zr = 0;
+#pragma unroll
+  for (int u = 0; u < NSL; ++u) {
+    const int e = tid + 256 * u;
+    s_lds[u] = -1;
+    s_off[u] = 0;
+    if (e < nz) {
+      const int b = e / SO, bp = e - b * SO;
+      s_lds[u] = b * ldz + bp;
+      s_off[u] = (int)(b * a.zrr + bp * a.zrc);
+      s_zr |= 1u << u;
+    } else if (e < nv) {
+      const int f = e - nz, ap = f / RI, k = f - ap * RI;
+      s_lds[u] = K4 * ldz + ap * ldy + k;
+      s_off[u] = (int)(ap * a.ylr + k * a.ylc);
+    }
+  }
+  const double *zrp = a.zr + p * a.zrb;
+  const double *ylp = a.yl + p * a.ylb;
+  double pf[NSL];
+  auto fetch = [&](int64_t i) {
+    const double *zr = zrp + i * a.zri, *yl = ylp + i * a.yli;
+#pragma unroll
+    for (int u = 0; u < NSL; ++u)
+      if (256 * u < nv) pf[u] = (((s_zr >> u) & 1u) ? zr : yl)[s_off[u]];
+  };
+  auto park = [&](CT *buf) {
+#pragma unroll
+    for (int u = 0; u < NSL; ++u)
+      if (256 * u < nv && s_lds[u] >= 0) buf[s_lds[u]] = (CT)pf[u];
+  };
+  __syncthreads();  // padding zeroed before the first valid entries land
+  fetch(i0);
+  park(YZ0);
+  if (i0 + 1 < i1) fetch(i0 + 1);
+  __syncthreads();
+
+  const int nt1 = pl.SO16 / 16, units1 = (M1p / 16) * nt1;
+  const bool hold_b1 = (4 % nt1) == 0;  // every block of a wave in one ZR block column
+  const int ncols = LG ? SO * GC : gc * SO;
+  const int mt2 = pl.RA16 / 16, units2 = mt2 * (rup(ncols, 16) / 16);
+  const bool hold_a2 = (4 % mt2) == 0;  // every block of a wave in one YL block row
+  CT none[KS];
+  int buf = 0;
+  for (int64_t i = i0; i < i1; ++i) {
+    const CT *ZRs = YZ0 + buf * yzs;
+    const CT *YLs = ZRs + K4 * ldz;
+
+    // ---- stage 1: T(g, a; b') = sum_b C_g(a, b) ZR(b, b'), blocks (tm, tn) row-major
+    {
+      auto pa = [&](int u) { return Cs + ((u / nt1) * 16 + r16) * ldc + q4; };
+      auto pb = [&](int u) { return ZRs + q4 * ldz + (u - (u / nt1) * nt1) * 16 + r16; };
+      auto ep = [&](int u, const acc_t &c) {
+        const int tm = (u / nt1) * 16, bq = (u - (u / nt1) * nt1) * 16 + r16;
+        if (bq < SO) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = tm + mfma_row<CT>(q4, v);
+            if (row < M1) {
+              const int g = fdiv(row, pl.fd_ri), aa = row - g * RI;
+              Ts[aa * ldt + (LG ? bq * GC + g : g * SO + bq)] = c[v];
+            }
+          }
+        }
+      };
+      if (hold_b1) {
+        CT hb[KS];
+        const CT *xb = pb(wave);
+#pragma unroll
+        for (int k = 0; k < KS; ++k) hb[k] = xb[k * 4 * ldz];
+        ks_blocks<KS, false, true, acc_t>(wave, units1, none, hb, pa, 4, pb, 4 * ldz, ep);
+      } else {
+        ks_blocks<KS, false, false, acc_t>(wave, units1, none, none, pa, 4, pb, 4 * ldz, ep);
+      }
+    }
+    if (i + 1 < i1) {
+      park(YZ0 + (buf ^ 1) * yzs);
+      if (i + 2 < i1) fetch(i + 2);
+    }
+    __syncthreads();
+
+    // ---- stage 2: out(a', col) = sum_a YL(a', a) T(a, col), blocks (tm, tn) column-major
+    {
+      CT *obase = reinterpret_cast<CT *>(static_cast<void *>(a.o)) + p * a.ob + i * a.oi + g0 * a.og;
+      auto pa = [&](int u) { return YLs + ((u - (u / mt2) * mt2) * 16 + r16) * ldy + q4; };
+      auto pb = [&](int u) { return Ts + q4 * ldt + (u / mt2) * 16 + r16; };
+      auto ep = [&](int u, const acc_t &c) {
+        const int tm = (u - (u / mt2) * mt2) * 16, col = (u / mt2) * 16 + r16;
+        int g, bq;
+        if (LG) {
+          bq = fdiv(col, pl.fd_gc);
+          g = col - bq * GC;
+        } else {
+          g = fdiv(col, pl.fd_so);
+          bq = col - g * SO;
+        }
+        if (col < ncols && g < gc) {
+          CT *o = obase + g * a.og + bq * a.obb + (int64_t)tm * a.oa;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int rr = mfma_row<CT>(q4, v);
+            if (tm + rr < RA) o[(int64_t)rr * a.oa] = c[v];
+          }
+        }
+      };
+      if (hold_a2) {
+        CT ha[KS];
+        const CT *xa = pa(wave);
+#pragma unroll
+        for (int k = 0; k < KS; ++k) ha[k] = xa[k * 4];
+        ks_blocks<KS, true, false, acc_t>(wave, units2, ha, none, pa, 4, pb, 4 * ldt, ep);
+      } else {
+        ks_blocks<KS, false, false, acc_t>(wave, units2, none, none, pa, 4, pb, 4 * ldt, ep);
+      }
+    }
+    __syncthreads();  // Ts and this slice's buffer are rewritten next
+    buf ^= 1;
+  }
+}
+
+namespace {
+template <bool LG, typename CT, int KS>
+void ks_attr(int mx) {
+  (void)hipFuncSetAttribute((const void *)sandwich_ks_kernel<LG, CT, KS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            mx);
+}
+template <int KS>
+void ks_attrs(int mx) {
+  ks_attr<true, double, KS>(mx);
+  ks_attr<false, double, KS>(mx);
+  ks_attr<true, float, KS>(mx);
+  ks_attr<false, float, KS>(mx);
+}
+template <bool LG, typename CT>
+void ks_launch(const SandwichArgs &a, const SwPlan &pl, dim3 grid, size_t lds, hipStream_t s) {
+  switch (pl.ks) {
+    case 1: sandwich_ks_kernel<LG, CT, 1><<<grid, 256, lds, s>>>(a, pl); break;
+    case 2: sandwich_ks_kernel<LG, CT, 2><<<grid, 256, lds, s>>>(a, pl); break;
+    case 3: sandwich_ks_kernel<LG, CT, 3><<<grid, 256, lds, s>>>(a, pl); break;
+    case 4: sandwich_ks_kernel<LG, CT, 4><<<grid, 256, lds, s>>>(a, pl); break;
+    case 5: sandwich_ks_kernel<LG, CT, 5><<<grid, 256, lds, s>>>(a, pl); break;
+    case 6: sandwich_ks_kernel<LG, CT, 6><<<grid, 256, lds, s>>>(a, pl); break;
+    case 7: sandwich_ks_kernel<LG, CT, 7><<<grid, 256, lds, s>>>(a, pl); break;
+    default: sandwich_ks_kernel<LG, CT, 8><<<grid, 256, lds, s>>>(a, pl); break;
+  }
+}
+static_assert(kSwKsMax == 8, "ks_launch instantiates K-step counts 1 to 8");
+}  // namespace
+
+bool g_sandwich_ks = true;
+
+const char *sandwich_mfma_name(const SandwichArgs &a, const SwPlan &pl) {
+  static const char *const ks_names[2][2][kSwKsMax] = {
+      {{"sandwich_ks_kernel<false, double, 1>", "sandwich_ks_kernel<false, double, 2>",
+        "sandwich_ks_kernel<false, double, 3>", "sandwich_ks_kernel<false, double, 4>",
+        "sandwich_ks_kernel<false, double, 5>", "sandwich_ks_kernel<false, double, 6>",
+        "sandwich_ks_kernel<false, double, 7>", "sandwich_ks_kernel<false, double, 8>"},
+       {"sandwich_ks_kernel<true, double, 1>", "sandwich_ks_kernel<true, double, 2>",
+        "sandwich_ks_kernel<true, double, 3>", "sandwich_ks_kernel<true, double, 4>",
+        "sandwich_ks_kernel<true, double, 5>", "sandwich_ks_kernel<true, double, 6>",
+        "sandwich_ks_kernel<true, double, 7>", "sandwich_ks_kernel<true, double, 8>"}},
+      {{"sandwich_ks_kernel<false, float, 1>", "sandwich_ks_kernel<false, float, 2>",
+        "sandwich_ks_kernel<false, float, 3>", "sandwich_ks_kernel<false, float, 4>",
+        "sandwich_ks_kernel<false, float, 5>", "sandwich_ks_kernel<false, float, 6>",
+        "sandwich_ks_kernel<false, float, 7>", "sandwich_ks_kernel<false, float, 8>"},
+       {"sandwich_ks_kernel<true, float, 1>", "sandwich_ks_kernel<true, float, 2>",
+        "sandwich_ks_kernel<true, float, 3>", "sandwich_ks_kernel<true, float, 4>",
+        "sandwich_ks_kernel<true, float, 5>", "sandwich_ks_kernel<true, float, 6>",
+        "sandwich_ks_kernel<true, float, 7>", "sandwich_ks_kernel<true, float, 8>"}}};
+  const int lg = a.og == 1 ? 1 : 0, f = a.prec ? 1 : 0;
+  if (g_sandwich_ks && pl.ks >= 1 && pl.ks <= kSwKsMax) return ks_names[f][lg][pl.ks - 1];
+  if (a.prec) return lg ? "sandwich_mfma_kernel<true, float>" : "sandwich_mfma_kernel<false, float>";
+  return lg ? "sandwich_mfma_kernel<true, double>" : "sandwich_mfma_kernel<false, double>";
+}
+
 hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStream_t s) {
   const size_t esz = a.prec ? sizeof(float) : sizeof(double);
   const size_t lds = (size_t)pl.lds_doubles * esz;
@@ -324,15 +611,36 @@ hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStre
                               hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     (void)hipFuncSetAttribute((const void *)sandwich_mfma_kernel<false, float>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    ks_attrs<1>(mx);
+    ks_attrs<2>(mx);
+    ks_attrs<3>(mx);
+    ks_attrs<4>(mx);
+    ks_attrs<5>(mx);
+    ks_attrs<6>(mx);
+    ks_attrs<7>(mx);
+    ks_attrs<8>(mx);
     attr_done = true;
   }
   dim3 grid((unsigned)pl.iblocks, (unsigned)pl.chunks, (unsigned)a.batch);
+  const bool ks = g_sandwich_ks && pl.ks >= 1 && pl.ks <= kSwKsMax;
   if (a.prec) {
-    if (a.og == 1) sandwich_mfma_kernel<true, float><<<grid, 256, lds, s>>>(a, pl);
-    else sandwich_mfma_kernel<false, float><<<grid, 256, lds, s>>>(a, pl);
+    if (ks) {
+      if (a.og == 1) ks_launch<true, float>(a, pl, grid, lds, s);
+      else ks_launch<false, float>(a, pl, grid, lds, s);
+    } else if (a.og == 1) {
+      sandwich_mfma_kernel<true, float><<<grid, 256, lds, s>>>(a, pl);
+    } else {
+      sandwich_mfma_kernel<false, float><<<grid, 256, lds, s>>>(a, pl);
+    }
   } else {
-    if (a.og == 1) sandwich_mfma_kernel<true, double><<<grid, 256, lds, s>>>(a, pl);
-    else sandwich_mfma_kernel<false, double><<<grid, 256, lds, s>>>(a, pl);
+    if (ks) {
+      if (a.og == 1) ks_launch<true, double>(a, pl, grid, lds, s);
+      else ks_launch<false, double>(a, pl, grid, lds, s);
+    } else if (a.og == 1) {
+      sandwich_mfma_kernel<true, double><<<grid, 256, lds, s>>>(a, pl);
+    } else {
+      sandwich_mfma_kernel<false, double><<<grid, 256, lds, s>>>(a, pl);
+    }
   }
   return hipGetLastError();
 }
