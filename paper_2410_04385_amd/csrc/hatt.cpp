@@ -862,12 +862,14 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     a.cg = 1;
     a.ca = s[c + 1] * l1;
     a.cbb = l1;
+    // W_L column-major (rows (a', b') fastest): each (i, gamma) column is one
+    // contiguous block of r s entries, so the sandwich writes whole blocks
     a.o = f32 ? as_d(WLf) : WL;
     a.ob = wlsz;
-    a.oi = l1;
-    a.og = 1;
-    a.oa = s[c] * n[c] * l1;
-    a.obb = n[c] * l1;
+    a.oi = l1 * r[c] * s[c];
+    a.og = r[c] * s[c];
+    a.oa = s[c];
+    a.obb = 1;
     a.RA = (int)r[c];
     a.RI = (int)r[c + 1];
     a.SI = (int)s[c + 1];
@@ -891,11 +893,11 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
       ty.prec = 1;
       ty.a32 = 1;
       ty.c32 = 1;
-      stt = gemm(run, gc, CMat{as_d(WLf), K, 1, wlsz}, wr, Mat{as_d(Wf + woff[c]), l[c], 1, wtot}, r[c] * s[c],
+      stt = gemm(run, gc, CMat{as_d(WLf), 1, r[c] * s[c], wlsz}, wr, Mat{as_d(Wf + woff[c]), l[c], 1, wtot}, r[c] * s[c],
                  l[c], K, 1.0, 0.0, P, st, false, nullptr, 0, nullptr, ty);
       if (stt == HATT_OK) LAUNCH(launch_rescale_pow2(Wf + woff[c], r[c] * s[c] * l[c], wtot, P, st));
     } else {
-      stt = gemm(run, gc, CMat{WL, K, 1, wlsz}, wr, Mat{W + woff[c], l[c], 1, wtot}, r[c] * s[c], l[c], K, 1.0,
+      stt = gemm(run, gc, CMat{WL, 1, r[c] * s[c], wlsz}, wr, Mat{W + woff[c], l[c], 1, wtot}, r[c] * s[c], l[c], K, 1.0,
                  0.0, P, st, true);
     }
     if (stt != HATT_OK) return stt;

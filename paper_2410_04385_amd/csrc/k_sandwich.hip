@@ -10,8 +10,8 @@
 // g blocks along M and stage 2 along N, so only the short dimension of each
 // product is padded to 16.  The column order of stage 2 is chosen so that the
 // 16 lanes of an output row segment store to consecutive addresses:
-// (b', g) with g fastest when the output is contiguous in g (the W_L columns
-// of HPCRL), (g, b') otherwise (the core update).
+// (b', g) with g fastest when the output is contiguous in g, (g, b') otherwise
+// (the column-major W_L of HPCRL and the core update, both contiguous in b').
 #include "common.h"
 #include "stage.h"
 
