@@ -86,9 +86,13 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
   pf = pf && off32;
   pl->pf = pf ? 1 : 0;
   // the register-blocked kernel: equal K steps, and every valid YL / ZR entry in a fetch slot
+  // register-blocked kernel: equal K steps, every valid YL / ZR entry in a
+  // fetch slot, block counts that divide the four waves, 32-bit output offsets
   pl->ks = 0;
-  if (off32 && RI4 == SI4 && RI4 / 4 <= kSwKsMax &&
-      (int64_t)a.RA * a.RI + (int64_t)a.SI * a.SO <= 256LL * sw_ks_slots(RI4 / 4))
+  const int64_t omax = (a.G - 1) * std::llabs(a.og) + (int64_t)(a.SO - 1) * std::llabs(a.obb) +
+                       (int64_t)(a.RA - 1) * std::llabs(a.oa);
+  if (off32 && omax < (1LL << 31) && RI4 == SI4 && RI4 / 4 <= kSwKsMax && 4 % (SO16 / 16) == 0 &&
+      4 % (RA16 / 16) == 0 && (int64_t)a.RA * a.RI + (int64_t)a.SI * a.SO <= 256LL * sw_ks_slots(RI4 / 4))
     pl->ks = RI4 / 4;
   return true;
 }
@@ -322,60 +326,57 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
 }
 
 // Register-blocked variant for KS K steps on both products (K padded to
-// 4 KS), same LDS layout and grid as sandwich_mfma_kernel.  A wave takes
-// every fourth 16 x 16 output block of a product; the operand that is the
-// same for all of a wave's blocks (the ZR block column of stage 1 when the
-// stage-1 column-block count divides 4, the YL block row of stage 2 when the
-// stage-2 row-block count divides 4) is read from LDS once per slice, and the
-// fragments of the wave's next block are read while the KS MFMAs of the
-// current one run.  Only the valid YL / ZR entries are fetched (the padding of
-// both buffers is zeroed once).  The next slice's entries are parked after
-// stage 1 and the one after that is fetched before stage 2, so the fetch
-// registers stay live across the stage-2 stores and the wait for them (vector
-// loads and stores share one counter) comes a whole stage 1 after the last
-// store.
+// 4 KS), same LDS layout and grid as sandwich_mfma_kernel, for shapes whose
+// stage-1 column-block count and stage-2 row-block count divide 4.  Wave w
+// keeps one ZR block column (stage 1) and one YL block row (stage 2) in
+// registers for the whole slice and takes every fourth block of the other
+// operand; the fragments of its next block are read while the KS MFMAs of
+// the current one run.  Block walks advance by fixed pointer steps and the
+// epilogues decode one index per block (a row's (g, a) changes by at most
+// one wrap between the four rows a lane holds), so address arithmetic stays
+// well below the MFMA time.  Only the valid YL / ZR entries are fetched (the
+// padding of both buffers is zeroed once).  The next slice's entries are
+// parked after stage 1 and the one after that is fetched before stage 2, so
+// the fetch registers stay live across the stage-2 stores and the wait for
+// them (vector loads and stores share one counter) comes a whole stage 1
+// after the last store.
 
-// Blocks u, u + 4, ... < units of one product, on one wave.  pa(u) / pb(u)
-// point at lane's first A / B element of block u (K steps sa / sb apart);
-// with HA / HB the operand is the same for every block and held in ha / hb.
-template <int KS, bool HA, bool HB, typename ACC, typename CT, class PA, class PB, class EP>
-__device__ __forceinline__ void ks_blocks(int u, int units, const CT (&ha)[KS], const CT (&hb)[KS], PA pa, int sa,
-                                          PB pb, int sb, EP ep) {
-  CT a0[KS], b0[KS], a1[KS], b1[KS];
-  auto load = [&](int uu, CT(&av)[KS], CT(&bv)[KS]) {
-    const CT *xa = pa(uu);
-    const CT *xb = pb(uu);
+// Blocks j = 0 .. count-1 of one product on one wave: the moving operand's
+// fragment of block j starts at p + j dp (K steps sk apart), the held operand
+// is h; MA: the moving operand is A.
+template <int KS, bool MA, typename ACC, typename CT, class EP>
+__device__ __forceinline__ void ks_blocks(int count, const CT (&h)[KS], const CT *p, int dp, int sk, EP ep) {
+  CT x0[KS], x1[KS];
+  auto load = [&](int j, CT(&x)[KS]) {
+    const CT *q = p + j * dp;
 #pragma unroll
-    for (int k = 0; k < KS; ++k) {
-      if (!HA) av[k] = xa[k * sa];
-      if (!HB) bv[k] = xb[k * sb];
-    }
+    for (int k = 0; k < KS; ++k) x[k] = q[k * sk];
   };
-  auto mma = [&](const CT(&av)[KS], const CT(&bv)[KS]) {
+  auto mma = [&](const CT(&x)[KS]) {
     ACC c = {0, 0, 0, 0};
 #pragma unroll
-    for (int k = 0; k < KS; ++k) c = mfma16(HA ? ha[k] : av[k], HB ? hb[k] : bv[k], c);
+    for (int k = 0; k < KS; ++k) c = MA ? mfma16(x[k], h[k], c) : mfma16(h[k], x[k], c);
     return c;
   };
-  if (u >= units) return;
-  load(u, a0, b0);
-  for (;;) {
-    const int u1 = u + 4;
-    if (u1 < units) load(u1, a1, b1);
-    ep(u, mma(a0, b0));
-    if (u1 >= units) return;
-    const int u2 = u1 + 4;
-    if (u2 < units) load(u2, a0, b0);
-    ep(u1, mma(a1, b1));
-    if (u2 >= units) return;
-    u = u2;
+  if (count <= 0) return;
+  load(0, x0);
+  for (int j = 0;; j += 2) {
+    if (j + 1 < count) load(j + 1, x1);
+    ep(j, mma(x0));
+    if (j + 1 >= count) return;
+    if (j + 2 < count) load(j + 2, x0);
+    ep(j + 1, mma(x1));
+    if (j + 2 >= count) return;
   }
 }
 
 template <bool LG, typename CT, int KS>
 __global__ __launch_bounds__(256) void sandwich_ks_kernel(SandwichArgs a, SwPlan pl) {
   using acc_t = typename std::conditional<std::is_same<CT, double>::value, d4_t, f4_t>::type;
+  constexpr bool F64 = std::is_same<CT, double>::value;
   constexpr int K4 = 4 * KS, NSL = sw_ks_slots(KS);
+  constexpr int DV = F64 ? 4 : 1;                  // row step between a lane's four results
+  constexpr bool ONE_WRAP = 4 * KS - 3 > 3 * DV;   // RI >= 4 KS - 3 exceeds the largest step
   extern __shared__ double smraw[];
   CT *sm = reinterpret_cast<CT *>(smraw);
   const int RA = a.RA, RI = a.RI, SI = a.SI, SO = a.SO;
@@ -383,6 +384,7 @@ __global__ __launch_bounds__(256) void sandwich_ks_kernel(SandwichArgs a, SwPlan
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int r16 = lane & 15, q4 = lane >> 4;
+  const int r0 = F64 ? q4 : 4 * q4;                // first result row of this lane
   const int64_t i0 = (int64_t)blockIdx.x * pl.ipb;
   const int64_t i1 = std::min<int64_t>(a.n, i0 + pl.ipb);
   const int64_t g0 = (int64_t)blockIdx.y * GC;
@@ -459,43 +461,56 @@ __global__ __launch_bounds__(256) void sandwich_ks_kernel(SandwichArgs a, SwPlan
   if (i0 + 1 < i1) fetch(i0 + 1);
   __syncthreads();
 
-  const int nt1 = pl.SO16 / 16, units1 = (M1p / 16) * nt1;
-  const bool hold_b1 = (4 % nt1) == 0;  // every block of a wave in one ZR block column
+  // ---- stage-1 walk: ZR block column tn1 held, block rows tm1 + j st1
+  const int nt1 = pl.SO16 / 16, mt1 = M1p / 16;
+  const int tn1 = wave % nt1, st1 = 4 / nt1, tm1 = wave / nt1;
+  const int cnt1 = tm1 < mt1 ? (mt1 - tm1 + st1 - 1) / st1 : 0;
+  const int bq1 = tn1 * 16 + r16;               // this lane's b'
+  const int col1 = LG ? bq1 * GC : bq1;          // T column of (g = 0, b')
+  const int gst1 = LG ? 1 : SO;                  // T column step per g
+  const int tdelta = gst1 - RI * ldt;            // T offset change of one wrap (a -= RI, g += 1)
+  // ---- stage-2 walk: YL block row tm2 held, block columns tn2 + j st2
   const int ncols = LG ? SO * GC : gc * SO;
-  const int mt2 = pl.RA16 / 16, units2 = mt2 * (rup(ncols, 16) / 16);
-  const bool hold_a2 = (4 % mt2) == 0;  // every block of a wave in one YL block row
-  CT none[KS];
+  const int mt2 = pl.RA16 / 16, nt2 = rup(ncols, 16) / 16;
+  const int tm2 = wave % mt2, st2 = 4 / mt2, tn2 = wave / mt2;
+  const int cnt2 = tn2 < nt2 ? (nt2 - tn2 + st2 - 1) / st2 : 0;
+  const int og = (int)a.og, obb = (int)a.obb, oa = (int)a.oa;  // 32-bit: checked by the plan
+  unsigned rows2 = 0;  // results v of this lane inside RA
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    if (tm2 * 16 + r0 + v * DV < RA) rows2 |= 1u << v;
+
   int buf = 0;
   for (int64_t i = i0; i < i1; ++i) {
     const CT *ZRs = YZ0 + buf * yzs;
     const CT *YLs = ZRs + K4 * ldz;
 
-    // ---- stage 1: T(g, a; b') = sum_b C_g(a, b) ZR(b, b'), blocks (tm, tn) row-major
+    // ---- stage 1: T(g, a; b') = sum_b C_g(a, b) ZR(b, b')
     {
-      auto pa = [&](int u) { return Cs + ((u / nt1) * 16 + r16) * ldc + q4; };
-      auto pb = [&](int u) { return ZRs + q4 * ldz + (u - (u / nt1) * nt1) * 16 + r16; };
-      auto ep = [&](int u, const acc_t &c) {
-        const int tm = (u / nt1) * 16, bq = (u - (u / nt1) * nt1) * 16 + r16;
-        if (bq < SO) {
+      CT hb[KS];
+      const CT *xb = ZRs + q4 * ldz + bq1;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = tm + mfma_row<CT>(q4, v);
-            if (row < M1) {
-              const int g = fdiv(row, pl.fd_ri), aa = row - g * RI;
-              Ts[aa * ldt + (LG ? bq * GC + g : g * SO + bq)] = c[v];
-            }
+      for (int k = 0; k < KS; ++k) hb[k] = xb[k * 4 * ldz];
+      auto ep = [&](int j, const acc_t &c) {
+        if (bq1 >= SO) return;
+        const int tm = (tm1 + j * st1) * 16, row0 = tm + r0;
+        const int g = fdiv(row0, pl.fd_ri), aa = row0 - g * RI;
+        const int t0 = aa * ldt + col1 + g * gst1;
+        const bool full = tm + 16 <= M1;  // wave-uniform
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = row0 + v * DV;
+          int t;
+          if (ONE_WRAP) {
+            t = t0 + v * DV * ldt + ((aa + v * DV >= RI) ? tdelta : 0);
+          } else {
+            const int gv = fdiv(row, pl.fd_ri);
+            t = (row - gv * RI) * ldt + col1 + gv * gst1;
           }
+          if (full || row < M1) Ts[t] = c[v];
         }
       };
-      if (hold_b1) {
-        CT hb[KS];
-        const CT *xb = pb(wave);
-#pragma unroll
-        for (int k = 0; k < KS; ++k) hb[k] = xb[k * 4 * ldz];
-        ks_blocks<KS, false, true, acc_t>(wave, units1, none, hb, pa, 4, pb, 4 * ldz, ep);
-      } else {
-        ks_blocks<KS, false, false, acc_t>(wave, units1, none, none, pa, 4, pb, 4 * ldz, ep);
-      }
+      ks_blocks<KS, true, acc_t>(cnt1, hb, Cs + (tm1 * 16 + r16) * ldc + q4, st1 * 16 * ldc, 4, ep);
     }
     if (i + 1 < i1) {
       park(YZ0 + (buf ^ 1) * yzs);
@@ -503,13 +518,16 @@ __global__ __launch_bounds__(256) void sandwich_ks_kernel(SandwichArgs a, SwPlan
     }
     __syncthreads();
 
-    // ---- stage 2: out(a', col) = sum_a YL(a', a) T(a, col), blocks (tm, tn) column-major
+    // ---- stage 2: out(a', col) = sum_a YL(a', a) T(a, col)
     {
-      CT *obase = reinterpret_cast<CT *>(static_cast<void *>(a.o)) + p * a.ob + i * a.oi + g0 * a.og;
-      auto pa = [&](int u) { return YLs + ((u - (u / mt2) * mt2) * 16 + r16) * ldy + q4; };
-      auto pb = [&](int u) { return Ts + q4 * ldt + (u / mt2) * 16 + r16; };
-      auto ep = [&](int u, const acc_t &c) {
-        const int tm = (u - (u / mt2) * mt2) * 16, col = (u / mt2) * 16 + r16;
+      CT ha[KS];
+      const CT *xa = YLs + (tm2 * 16 + r16) * ldy + q4;
+#pragma unroll
+      for (int k = 0; k < KS; ++k) ha[k] = xa[k * 4];
+      CT *ob = reinterpret_cast<CT *>(static_cast<void *>(a.o)) + p * a.ob + i * a.oi + g0 * a.og +
+               (int64_t)(tm2 * 16 + r0) * a.oa;
+      auto ep = [&](int j, const acc_t &c) {
+        const int col = (tn2 + j * st2) * 16 + r16;
         int g, bq;
         if (LG) {
           bq = fdiv(col, pl.fd_gc);
@@ -519,23 +537,13 @@ __global__ __launch_bounds__(256) void sandwich_ks_kernel(SandwichArgs a, SwPlan
           bq = col - g * SO;
         }
         if (col < ncols && g < gc) {
-          CT *o = obase + g * a.og + bq * a.obb + (int64_t)tm * a.oa;
+          CT *o = ob + (g * og + bq * obb);
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int rr = mfma_row<CT>(q4, v);
-            if (tm + rr < RA) o[(int64_t)rr * a.oa] = c[v];
-          }
+          for (int v = 0; v < 4; ++v)
+            if ((rows2 >> v) & 1u) o[v * DV * oa] = c[v];
         }
       };
-      if (hold_a2) {
-        CT ha[KS];
-        const CT *xa = pa(wave);
-#pragma unroll
-        for (int k = 0; k < KS; ++k) ha[k] = xa[k * 4];
-        ks_blocks<KS, true, false, acc_t>(wave, units2, ha, none, pa, 4, pb, 4 * ldt, ep);
-      } else {
-        ks_blocks<KS, false, false, acc_t>(wave, units2, none, none, pa, 4, pb, 4 * ldt, ep);
-      }
+      ks_blocks<KS, false, acc_t>(cnt2, ha, Ts + q4 * ldt + tn2 * 16 + r16, st2 * 16, 4 * ldt, ep);
     }
     __syncthreads();  // Ts and this slice's buffer are rewritten next
     buf ^= 1;
