@@ -100,6 +100,8 @@ struct SwPlan {
   FastDiv fd_ri, fd_so, fd_gc; // index decodes of the stage-1 rows and stage-2 columns
   int ks;                     // K steps of both products when they are equal and a
                               // register-blocked instantiation covers them, else 0
+  int rem;                    // 1: FP64, b' and a' ranges of 17 to 20 (one full 16-block and a
+                              // remainder of at most 4, formed by the 4 x 4 x 4 MFMA)
 };
 bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl);
 hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStream_t s);

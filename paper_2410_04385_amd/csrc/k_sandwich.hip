@@ -94,6 +94,7 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
   if (off32 && omax < (1LL << 31) && RI4 == SI4 && RI4 / 4 <= kSwKsMax && 4 % (SO16 / 16) == 0 &&
       4 % (RA16 / 16) == 0 && (int64_t)a.RA * a.RI + (int64_t)a.SI * a.SO <= 256LL * sw_ks_slots(RI4 / 4))
     pl->ks = RI4 / 4;
+  pl->rem = (pl->ks > 0 && a.prec == 0 && a.og != 1 && a.SO >= 17 && a.SO <= 20 && a.RA >= 17 && a.RA <= 20) ? 1 : 0;
   return true;
 }
 
@@ -370,13 +371,53 @@ __device__ __forceinline__ void ks_blocks(int count, const CT (&h)[KS], const CT
   }
 }
 
-template <bool LG, typename CT, int KS>
+// As ks_blocks, for FP64 products with one full 16-block and a remainder of
+// at most 4 on the held side: each block of the moving operand feeds a
+// 16 x 16 x 4 chain with h and a 4 x 4 x 4 chain with hr (the held
+// remainder, laid out for the four-block MFMA), interleaved step by step so
+// the short chain's latency hides behind the long one.
+template <int KS, bool MA, class EP>
+__device__ __forceinline__ void ks_blocks_rem(int count, const double (&h)[KS], const double (&hr)[KS],
+                                              const double *p, int dp, int sk, EP ep) {
+  double x0[KS], x1[KS];
+  auto load = [&](int j, double(&x)[KS]) {
+    const double *q = p + j * dp;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) x[k] = q[k * sk];
+  };
+  auto mma = [&](const double(&x)[KS], d4_t &c, double &cr) {
+    c = d4_t{0, 0, 0, 0};
+    cr = 0.0;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      c = MA ? mfma16(x[k], h[k], c) : mfma16(h[k], x[k], c);
+      cr = MA ? mfma4(x[k], hr[k], cr) : mfma4(hr[k], x[k], cr);
+    }
+  };
+  if (count <= 0) return;
+  d4_t c;
+  double cr;
+  load(0, x0);
+  for (int j = 0;; j += 2) {
+    if (j + 1 < count) load(j + 1, x1);
+    mma(x0, c, cr);
+    ep(j, c, cr);
+    if (j + 1 >= count) return;
+    if (j + 2 < count) load(j + 2, x0);
+    mma(x1, c, cr);
+    ep(j + 1, c, cr);
+    if (j + 2 >= count) return;
+  }
+}
+
+template <bool LG, typename CT, int KS, bool REM>
 __global__ __launch_bounds__(256) void sandwich_ks_kernel(SandwichArgs a, SwPlan pl) {
   using acc_t = typename std::conditional<std::is_same<CT, double>::value, d4_t, f4_t>::type;
   constexpr bool F64 = std::is_same<CT, double>::value;
   constexpr int K4 = 4 * KS, NSL = sw_ks_slots(KS);
   constexpr int DV = F64 ? 4 : 1;                  // row step between a lane's four results
   constexpr bool ONE_WRAP = 4 * KS - 3 > 3 * DV;   // RI >= 4 KS - 3 exceeds the largest step
+  static_assert(!REM || (F64 && !LG), "the remainder form is built for FP64 with the (g, b') column order");
   extern __shared__ double smraw[];
   CT *sm = reinterpret_cast<CT *>(smraw);
   const int RA = a.RA, RI = a.RI, SI = a.SI, SO = a.SO;
@@ -486,7 +527,41 @@ __global__ __launch_bounds__(256) void sandwich_ks_kernel(SandwichArgs a, SwPlan
     const CT *YLs = ZRs + K4 * ldz;
 
     // ---- stage 1: T(g, a; b') = sum_b C_g(a, b) ZR(b, b')
-    {
+    if constexpr (REM) {
+      // block rows wave + 4 j, each with columns 0..15 (16 x 16) and 16..SO-1 (4 x 4)
+      double hb[KS], hr[KS];
+#pragma unroll
+      for (int k = 0; k < KS; ++k) {
+        hb[k] = ZRs[(4 * k + q4) * ldz + r16];
+        hr[k] = ZRs[(4 * k + q4) * ldz + 16 + (lane & 3)];
+      }
+      const int cnt = wave < mt1 ? (mt1 - wave + 3) / 4 : 0;
+      const int rrow = 4 * ((lane >> 2) & 3) + q4, rcol = 16 + (lane & 3);  // remainder result of this lane
+      auto ep = [&](int j, const d4_t &c, double cr) {
+        const int tm = (wave + 4 * j) * 16, row0 = tm + q4;
+        const int g = fdiv(row0, pl.fd_ri), aa = row0 - g * RI;
+        const int t0 = aa * ldt + r16 + g * SO;
+        const bool full = tm + 16 <= M1;  // wave-uniform
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = row0 + 4 * v;
+          int t;
+          if (ONE_WRAP) {
+            t = t0 + 4 * v * ldt + ((aa + 4 * v >= RI) ? tdelta : 0);
+          } else {
+            const int gv = fdiv(row, pl.fd_ri);
+            t = (row - gv * RI) * ldt + gv * SO + r16;
+          }
+          if (full || row < M1) Ts[t] = c[v];
+        }
+        const int row = tm + rrow;
+        if (rcol < SO && row < M1) {
+          const int gr = fdiv(row, pl.fd_ri);
+          Ts[(row - gr * RI) * ldt + gr * SO + rcol] = cr;
+        }
+      };
+      ks_blocks_rem<KS, true>(cnt, hb, hr, Cs + (wave * 16 + r16) * ldc + q4, 64 * ldc, 4, ep);
+    } else {
       CT hb[KS];
       const CT *xb = ZRs + q4 * ldz + bq1;
 #pragma unroll
@@ -519,7 +594,29 @@ __global__ __launch_bounds__(256) void sandwich_ks_kernel(SandwichArgs a, SwPlan
     __syncthreads();
 
     // ---- stage 2: out(a', col) = sum_a YL(a', a) T(a, col)
-    {
+    if constexpr (REM) {
+      // block columns wave + 4 j, each with rows 0..15 (16 x 16) and 16..RA-1 (4 x 4)
+      double ha[KS], har[KS];
+#pragma unroll
+      for (int k = 0; k < KS; ++k) {
+        ha[k] = YLs[r16 * ldy + 4 * k + q4];
+        har[k] = YLs[(16 + (lane & 3)) * ldy + 4 * k + q4];
+      }
+      const int cnt = wave < nt2 ? (nt2 - wave + 3) / 4 : 0;
+      double *ob = a.o + p * a.ob + i * a.oi + g0 * a.og + (int64_t)q4 * a.oa;
+      const bool rrow_ok = 16 + q4 < RA;  // remainder result row of this lane
+      auto ep = [&](int j, const d4_t &c, double cr) {
+        const int col = (wave + 4 * j) * 16 + r16;
+        const int g = fdiv(col, pl.fd_so), bq = col - g * SO;
+        if (col < ncols) {
+          double *o = ob + (g * og + bq * obb);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) o[v * 4 * oa] = c[v];
+          if (rrow_ok) o[16 * oa] = cr;
+        }
+      };
+      ks_blocks_rem<KS, false>(cnt, ha, har, Ts + q4 * ldt + wave * 16 + r16, 64, 4 * ldt, ep);
+    } else {
       CT ha[KS];
       const CT *xa = YLs + (tm2 * 16 + r16) * ldy + q4;
 #pragma unroll
@@ -551,29 +648,30 @@ __global__ __launch_bounds__(256) void sandwich_ks_kernel(SandwichArgs a, SwPlan
 }
 
 namespace {
-template <bool LG, typename CT, int KS>
+template <bool LG, typename CT, int KS, bool REM>
 void ks_attr(int mx) {
-  (void)hipFuncSetAttribute((const void *)sandwich_ks_kernel<LG, CT, KS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            mx);
+  (void)hipFuncSetAttribute((const void *)sandwich_ks_kernel<LG, CT, KS, REM>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
 }
 template <int KS>
 void ks_attrs(int mx) {
-  ks_attr<true, double, KS>(mx);
-  ks_attr<false, double, KS>(mx);
-  ks_attr<true, float, KS>(mx);
-  ks_attr<false, float, KS>(mx);
+  ks_attr<true, double, KS, false>(mx);
+  ks_attr<false, double, KS, false>(mx);
+  ks_attr<true, float, KS, false>(mx);
+  ks_attr<false, float, KS, false>(mx);
+  ks_attr<false, double, KS, true>(mx);
 }
-template <bool LG, typename CT>
+template <bool LG, typename CT, bool REM>
 void ks_launch(const SandwichArgs &a, const SwPlan &pl, dim3 grid, size_t lds, hipStream_t s) {
   switch (pl.ks) {
-    case 1: sandwich_ks_kernel<LG, CT, 1><<<grid, 256, lds, s>>>(a, pl); break;
-    case 2: sandwich_ks_kernel<LG, CT, 2><<<grid, 256, lds, s>>>(a, pl); break;
-    case 3: sandwich_ks_kernel<LG, CT, 3><<<grid, 256, lds, s>>>(a, pl); break;
-    case 4: sandwich_ks_kernel<LG, CT, 4><<<grid, 256, lds, s>>>(a, pl); break;
-    case 5: sandwich_ks_kernel<LG, CT, 5><<<grid, 256, lds, s>>>(a, pl); break;
-    case 6: sandwich_ks_kernel<LG, CT, 6><<<grid, 256, lds, s>>>(a, pl); break;
-    case 7: sandwich_ks_kernel<LG, CT, 7><<<grid, 256, lds, s>>>(a, pl); break;
-    default: sandwich_ks_kernel<LG, CT, 8><<<grid, 256, lds, s>>>(a, pl); break;
+    case 1: sandwich_ks_kernel<LG, CT, 1, REM><<<grid, 256, lds, s>>>(a, pl); break;
+    case 2: sandwich_ks_kernel<LG, CT, 2, REM><<<grid, 256, lds, s>>>(a, pl); break;
+    case 3: sandwich_ks_kernel<LG, CT, 3, REM><<<grid, 256, lds, s>>>(a, pl); break;
+    case 4: sandwich_ks_kernel<LG, CT, 4, REM><<<grid, 256, lds, s>>>(a, pl); break;
+    case 5: sandwich_ks_kernel<LG, CT, 5, REM><<<grid, 256, lds, s>>>(a, pl); break;
+    case 6: sandwich_ks_kernel<LG, CT, 6, REM><<<grid, 256, lds, s>>>(a, pl); break;
+    case 7: sandwich_ks_kernel<LG, CT, 7, REM><<<grid, 256, lds, s>>>(a, pl); break;
+    default: sandwich_ks_kernel<LG, CT, 8, REM><<<grid, 256, lds, s>>>(a, pl); break;
   }
 }
 static_assert(kSwKsMax == 8, "ks_launch instantiates K-step counts 1 to 8");
@@ -582,25 +680,36 @@ static_assert(kSwKsMax == 8, "ks_launch instantiates K-step counts 1 to 8");
 bool g_sandwich_ks = true;
 
 const char *sandwich_mfma_name(const SandwichArgs &a, const SwPlan &pl) {
-  static const char *const ks_names[2][2][kSwKsMax] = {
-      {{"sandwich_ks_kernel<false, double, 1>", "sandwich_ks_kernel<false, double, 2>",
-        "sandwich_ks_kernel<false, double, 3>", "sandwich_ks_kernel<false, double, 4>",
-        "sandwich_ks_kernel<false, double, 5>", "sandwich_ks_kernel<false, double, 6>",
-        "sandwich_ks_kernel<false, double, 7>", "sandwich_ks_kernel<false, double, 8>"},
-       {"sandwich_ks_kernel<true, double, 1>", "sandwich_ks_kernel<true, double, 2>",
-        "sandwich_ks_kernel<true, double, 3>", "sandwich_ks_kernel<true, double, 4>",
-        "sandwich_ks_kernel<true, double, 5>", "sandwich_ks_kernel<true, double, 6>",
-        "sandwich_ks_kernel<true, double, 7>", "sandwich_ks_kernel<true, double, 8>"}},
-      {{"sandwich_ks_kernel<false, float, 1>", "sandwich_ks_kernel<false, float, 2>",
-        "sandwich_ks_kernel<false, float, 3>", "sandwich_ks_kernel<false, float, 4>",
-        "sandwich_ks_kernel<false, float, 5>", "sandwich_ks_kernel<false, float, 6>",
-        "sandwich_ks_kernel<false, float, 7>", "sandwich_ks_kernel<false, float, 8>"},
-       {"sandwich_ks_kernel<true, float, 1>", "sandwich_ks_kernel<true, float, 2>",
-        "sandwich_ks_kernel<true, float, 3>", "sandwich_ks_kernel<true, float, 4>",
-        "sandwich_ks_kernel<true, float, 5>", "sandwich_ks_kernel<true, float, 6>",
-        "sandwich_ks_kernel<true, float, 7>", "sandwich_ks_kernel<true, float, 8>"}}};
+  // [remainder form, FP32, (b', g) order][K steps - 1]
+  static const char *const ks_names[2][2][2][kSwKsMax] = {
+      {{{"sandwich_ks_kernel<false, double, 1, false>", "sandwich_ks_kernel<false, double, 2, false>",
+         "sandwich_ks_kernel<false, double, 3, false>", "sandwich_ks_kernel<false, double, 4, false>",
+         "sandwich_ks_kernel<false, double, 5, false>", "sandwich_ks_kernel<false, double, 6, false>",
+         "sandwich_ks_kernel<false, double, 7, false>", "sandwich_ks_kernel<false, double, 8, false>"},
+        {"sandwich_ks_kernel<true, double, 1, false>", "sandwich_ks_kernel<true, double, 2, false>",
+         "sandwich_ks_kernel<true, double, 3, false>", "sandwich_ks_kernel<true, double, 4, false>",
+         "sandwich_ks_kernel<true, double, 5, false>", "sandwich_ks_kernel<true, double, 6, false>",
+         "sandwich_ks_kernel<true, double, 7, false>", "sandwich_ks_kernel<true, double, 8, false>"}},
+       {{"sandwich_ks_kernel<false, float, 1, false>", "sandwich_ks_kernel<false, float, 2, false>",
+         "sandwich_ks_kernel<false, float, 3, false>", "sandwich_ks_kernel<false, float, 4, false>",
+         "sandwich_ks_kernel<false, float, 5, false>", "sandwich_ks_kernel<false, float, 6, false>",
+         "sandwich_ks_kernel<false, float, 7, false>", "sandwich_ks_kernel<false, float, 8, false>"},
+        {"sandwich_ks_kernel<true, float, 1, false>", "sandwich_ks_kernel<true, float, 2, false>",
+         "sandwich_ks_kernel<true, float, 3, false>", "sandwich_ks_kernel<true, float, 4, false>",
+         "sandwich_ks_kernel<true, float, 5, false>", "sandwich_ks_kernel<true, float, 6, false>",
+         "sandwich_ks_kernel<true, float, 7, false>", "sandwich_ks_kernel<true, float, 8, false>"}}},
+      {{{"sandwich_ks_kernel<false, double, 1, true>", "sandwich_ks_kernel<false, double, 2, true>",
+         "sandwich_ks_kernel<false, double, 3, true>", "sandwich_ks_kernel<false, double, 4, true>",
+         "sandwich_ks_kernel<false, double, 5, true>", "sandwich_ks_kernel<false, double, 6, true>",
+         "sandwich_ks_kernel<false, double, 7, true>", "sandwich_ks_kernel<false, double, 8, true>"},
+        {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr}},
+       {{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr},
+        {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr}}}};
   const int lg = a.og == 1 ? 1 : 0, f = a.prec ? 1 : 0;
-  if (g_sandwich_ks && pl.ks >= 1 && pl.ks <= kSwKsMax) return ks_names[f][lg][pl.ks - 1];
+  if (g_sandwich_ks && pl.ks >= 1 && pl.ks <= kSwKsMax) {
+    const int r = (pl.rem && !f && !lg) ? 1 : 0;
+    return ks_names[r][f][lg][pl.ks - 1];
+  }
   if (a.prec) return lg ? "sandwich_mfma_kernel<true, float>" : "sandwich_mfma_kernel<false, float>";
   return lg ? "sandwich_mfma_kernel<true, double>" : "sandwich_mfma_kernel<false, double>";
 }
@@ -633,8 +742,8 @@ hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStre
   const bool ks = g_sandwich_ks && pl.ks >= 1 && pl.ks <= kSwKsMax;
   if (a.prec) {
     if (ks) {
-      if (a.og == 1) ks_launch<true, float>(a, pl, grid, lds, s);
-      else ks_launch<false, float>(a, pl, grid, lds, s);
+      if (a.og == 1) ks_launch<true, float, false>(a, pl, grid, lds, s);
+      else ks_launch<false, float, false>(a, pl, grid, lds, s);
     } else if (a.og == 1) {
       sandwich_mfma_kernel<true, float><<<grid, 256, lds, s>>>(a, pl);
     } else {
@@ -642,8 +751,9 @@ hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStre
     }
   } else {
     if (ks) {
-      if (a.og == 1) ks_launch<true, double>(a, pl, grid, lds, s);
-      else ks_launch<false, double>(a, pl, grid, lds, s);
+      if (a.og == 1) ks_launch<true, double, false>(a, pl, grid, lds, s);
+      else if (pl.rem) ks_launch<false, double, true>(a, pl, grid, lds, s);
+      else ks_launch<false, double, false>(a, pl, grid, lds, s);
     } else if (a.og == 1) {
       sandwich_mfma_kernel<true, double><<<grid, 256, lds, s>>>(a, pl);
     } else {

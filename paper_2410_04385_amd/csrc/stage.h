@@ -19,6 +19,16 @@ __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
 __device__ __forceinline__ f4_t mfma16(float a, float b, f4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+// The four-block FP64 4 x 4 x 4 MFMA reads the same operand registers as the
+// 16 x 16 x 4 one (lane 16k + 4b + i holds A(4b + i, k), lane 16k + 4b + j
+// holds B(k, 4b + j)) and forms only the four diagonal 4 x 4 blocks of that
+// product: lane 16i + 4b + j receives C(4b + i, 4b + j) (probed on gfx950).
+// It issues a quarter of the work in a quarter of the time, but a dependent
+// chain of them waits about 52 cycles per step, so chains are interleaved
+// with 16 x 16 x 4 MFMAs.
+__device__ __forceinline__ double mfma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
 template <typename CT>
 __device__ __forceinline__ int mfma_row(int rq, int v) {
   return std::is_same<CT, double>::value ? rq + 4 * v : 4 * rq + v;

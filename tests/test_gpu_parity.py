@@ -118,6 +118,8 @@ CASES = [
     ([1, 4, 1, 3], 2, 2, 3),          # modes of size 1
     ([9], 1, 1, 1),                   # d = 1
     ([17, 33, 65, 9], 6, 7, 30),      # ragged tiles in every kernel
+    ([5, 6, 7, 6, 5], 19, 17, 23),    # bond ranks 17..20: 4 x 4 x 4 remainder blocks, ragged chunks
+    ([4, 8, 8, 8, 4], 20, 18, 40),    # same, r != s on both sandwich sides
 ]
 
 
