@@ -153,6 +153,30 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g) {
   for (int i = 0; i < MI; ++i) live_m[i] = m0 + wm + i * 16 < g.M;
 #pragma unroll
   for (int j = 0; j < NJ; ++j) live_n[j] = n0 + wn + j * 16 < g.N;
+  // FP64 with a thin side (wave layouts 1 and 2): a last block of that side
+  // with at most 8 live columns (rows) is formed as one or two 4-wide strips
+  // by the four-block 4 x 4 x 4 MFMA (the wave's other operand fragment is
+  // reused as is; the strip's operand is read replicated across the four
+  // blocks) at a quarter of a 16 x 16 block's cost per strip.
+  constexpr bool REM = std::is_same<CT, double>::value && WL != 0;
+  int rem_blk = 0, rem_cnt = 0;  // wave-uniform
+  double racc[2] = {0.0, 0.0};
+  if constexpr (REM) {
+    const int64_t edge = (WL == 1) ? g.N - n0 - wn : g.M - m0 - wm;
+    if (edge > 0 && edge < 64 && (edge & 15) >= 1 && (edge & 15) <= 8) {
+      rem_blk = (int)(edge >> 4);
+      rem_cnt = (int)(((edge & 15) + 3) >> 2);
+      if (WL == 1) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+          if (j == rem_blk) live_n[j] = false;
+      } else {
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+          if (i == rem_blk) live_m[i] = false;
+      }
+    }
+  }
   int64_t slab = 0;
   for (int64_t k0 = kbeg; k0 < kend; k0 += BK, ++slab) {
     const bool more = k0 + BK < kend;
@@ -172,6 +196,20 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g) {
 #pragma unroll
         for (int j = 0; j < NJ; ++j)
           if (live_m[i] && live_n[j]) acc[i][j] = mfma16(av[i], bv[j], acc[i][j]);
+      if constexpr (REM) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          if (q < rem_cnt) {
+            if (WL == 1) {
+              const double x = (double)Bs[kr * LDB_S + wn + rem_blk * 16 + 4 * q + (lane & 3)];
+              racc[q] = mfma4((double)av[0], x, racc[q]);
+            } else {
+              const double x = (double)As[kr * LDA_S + wm + rem_blk * 16 + 4 * q + (lane & 3)];
+              racc[q] = mfma4(x, (double)bv[0], racc[q]);
+            }
+          }
+        }
+      }
     }
     __syncthreads();
     if (more) {
@@ -181,6 +219,16 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g) {
   }
 
   const int rq = lane >> 4, cq = lane & 15;
+  // strip q's result of this lane (row, column within the tile)
+  auto rem_at = [&](int q, int64_t *gm, int64_t *gn) {
+    if (WL == 1) {
+      *gm = m0 + wm + 4 * ((lane >> 2) & 3) + rq;
+      *gn = n0 + wn + rem_blk * 16 + 4 * q + (lane & 3);
+    } else {
+      *gm = m0 + wm + rem_blk * 16 + 4 * q + rq;
+      *gn = n0 + wn + cq;
+    }
+  };
   if (ks == 1) {
     TC *Cb = reinterpret_cast<TC *>(static_cast<void *>(g.C.ptr)) + p * g.C.bs;
 #pragma unroll
@@ -190,13 +238,27 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t gm = m0 + wm + i * 16 + mfma_row<CT>(rq, v), gn = n0 + wn + j * 16 + cq;
-          if (gm < g.M && gn < g.N) {
+          // a strip-formed block is stored by the strips alone
+          if (live_m[i] && live_n[j] && gm < g.M && gn < g.N) {
             TC *cp = Cb + gm * g.C.rs + gn * g.C.cs;
             double r = g.alpha * (double)acc[i][j][v];
             if (g.beta != 0.0) r += g.beta * (double)(*cp);
             *cp = (TC)r;
           }
         }
+    if constexpr (REM) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        int64_t gm, gn;
+        rem_at(q, &gm, &gn);
+        if (q < rem_cnt && gm < g.M && gn < g.N) {
+          TC *cp = Cb + gm * g.C.rs + gn * g.C.cs;
+          double r = g.alpha * racc[q];
+          if (g.beta != 0.0) r += g.beta * (double)(*cp);
+          *cp = (TC)r;
+        }
+      }
+    }
   } else if (std::is_same<CT, double>::value) {  // split-K partials (FP64 path only)
     double *Pb = g.part + ((int64_t)p * ks + kc) * g.M * g.N;
 #pragma unroll
@@ -206,8 +268,16 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t gm = m0 + wm + i * 16 + mfma_row<CT>(rq, v), gn = n0 + wn + j * 16 + cq;
-          if (gm < g.M && gn < g.N) Pb[gm * g.N + gn] = g.alpha * (double)acc[i][j][v];
+          if (live_m[i] && live_n[j] && gm < g.M && gn < g.N) Pb[gm * g.N + gn] = g.alpha * (double)acc[i][j][v];
         }
+    if constexpr (REM) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        int64_t gm, gn;
+        rem_at(q, &gm, &gn);
+        if (q < rem_cnt && gm < g.M && gn < g.N) Pb[gm * g.N + gn] = g.alpha * racc[q];
+      }
+    }
   }
 }
 
