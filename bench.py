@@ -294,7 +294,13 @@ def main() -> int:
     if args.workload == "batched":
         # independent pairs run on the library's 32 streams; HIP's default of 4
         # hardware queues per process would run only 4 of them at a time
-        os.environ.setdefault("GPU_MAX_HW_QUEUES", "32")
+        # (raised to 32 where the environment sets fewer; HIP reads it at start-up)
+        try:
+            q = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
+        except ValueError:
+            q = 0
+        if q < 32:
+            os.environ["GPU_MAX_HW_QUEUES"] = "32"
     import numpy as np
     import torch
 

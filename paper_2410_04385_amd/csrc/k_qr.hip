@@ -505,7 +505,7 @@ __global__ __launch_bounds__(256) void gram_chol_kernel(CMat A, int64_t m, doubl
   extern __shared__ double W[];
   __shared__ double piv[kCholMaxN];
   __shared__ double dmax_s;
-  constexpr int U = 4;  // row groups of 4 fetched before their MFMAs
+  constexpr int U = 3;  // row groups of 4 per load batch (two batches in flight)
   const int ld = 2 * n + 1;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -518,8 +518,8 @@ __global__ __launch_bounds__(256) void gram_chol_kernel(CMat A, int64_t m, doubl
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[i][j] = d4_t{0, 0, 0, 0};
   const int64_t groups = (m + 3) / 4;
-  for (int64_t s0 = (int64_t)wave * U; s0 < groups; s0 += 4 * U) {
-    double v[U][NB];
+  // the next iteration's rows are loaded while this iteration's MFMAs run
+  auto load = [&](int64_t s0, double (&v)[U][NB]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t row = 4 * (s0 + u) + q4;
@@ -529,12 +529,27 @@ __global__ __launch_bounds__(256) void gram_chol_kernel(CMat A, int64_t m, doubl
         v[u][b] = (row < m && col < n) ? Ab[row * A.rs + (int64_t)col * A.cs] : 0.0;
       }
     }
+  };
+  auto gram = [&](const double (&v)[U][NB]) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int i = 0; i < NB; ++i)
 #pragma unroll
         for (int j = i; j < NB; ++j) acc[i][j] = mfma16(v[u][i], v[u][j], acc[i][j]);
+  };
+  {
+    double va[U][NB], vb[U][NB];
+    int64_t s0 = (int64_t)wave * U;
+    if (s0 < groups) load(s0, va);
+    for (; s0 < groups; s0 += 8 * U) {
+      const int64_t s1 = s0 + 4 * U;
+      if (s1 < groups) load(s1, vb);
+      gram(va);
+      if (s1 >= groups) break;
+      if (s1 + 4 * U < groups) load(s1 + 4 * U, va);
+      gram(vb);
+    }
   }
   for (int e = tid; e < n * ld; e += 256) {
     const int i = e / ld, c = e - i * ld;
