@@ -390,60 +390,89 @@ hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_
 // Elimination of [G | I] held in W (n rows of 2n + 1; only the upper
 // triangle of the left half need be set), then R, R^{-1} and the pair's flag.
 // Every thread of the 256-thread block calls it.
+template <int KMAX>
 __device__ void chol_eliminate(double *W, double *piv, double &dmax_s, int n, double *ro, double *ri, int *f,
                                int first, double thr_rel) {
-  const int ld = 2 * n + 1;
+  // The matrix [G | I] lives in registers during the elimination: thread
+  // (ty, tx) holds rows ty + 4k of columns tx and tx + 64.  By symmetry the
+  // multipliers of pivot j are its pivot row, so only that row travels, through
+  // a double-buffered LDS row published by its owner wave (one barrier per
+  // pivot); every entry gets the same update W(i,c) -= W(j,i) (W(j,c) / d_j)
+  // as in place.
+  __shared__ double prow[2][2 * kCholMaxN];
+  const int ld = 2 * n + 1, n2 = 2 * n;
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+  static_assert(KMAX >= 1 && 4 * KMAX <= kCholMaxN, "rows per thread");  // n <= 4 KMAX
+  const int c0 = tx, c1 = tx + 64;
+  double w0[KMAX], w1[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int i = ty + 4 * k;
+    w0[k] = (i < n && c0 < n2) ? W[i * ld + c0] : 0.0;
+    w1[k] = (i < n && c1 < n2) ? W[i * ld + c1] : 0.0;
+  }
   if (tid == 0) {
     double m = 0.0;
     for (int j = 0; j < n; ++j) m = fmax(m, W[j * ld + j]);
     dmax_s = m;
+  }
+  if (ty == 0) {  // pivot row 0
+    if (c0 < n2) prow[0][c0] = w0[0];
+    if (c1 < n2) prow[0][c1] = w1[0];
   }
   __syncthreads();
   const double dmax = dmax_s;
   const bool dmax_ok = (dmax > 0.0) && (dmax < 1e300);
   const double thr = thr_rel * dmax;
   int bad = dmax_ok ? 0 : 1;
+  // rows updated in column c: left half up to the diagonal, right half all
+  const int lim0 = (c0 < n) ? c0 : n - 1, lim1 = (c1 < n) ? c1 : n - 1;
   for (int j = 0; j < n; ++j) {
-    double d = W[j * ld + j];
+    const double *pr = prow[j & 1];
+    double d = pr[j];
     if (!(d > thr)) {  // also catches NaN; every thread takes the same decision
       bad = 1;
       d = (thr > 0.0 && thr < 1e300) ? thr : 1.0;
     }
     if (tid == 0) piv[j] = d;
     const double inv = 1.0 / d;
-    const double *wj = W + j * ld;
-    // this thread's rows i = j + 1 + ty + 4k: multipliers W(j, i) in registers
-    constexpr int KMAX = kCholMaxN / 4;
-    double mul[KMAX];
+    // left columns <= j are final; right columns beyond n + j are still zero
+    const bool a0 = (c0 < n) ? (c0 > j) : (c0 < n2 && c0 <= n + j);
+    const bool a1 = (c1 < n) ? (c1 > j) : (c1 < n2 && c1 <= n + j);
+    const double p0 = a0 ? pr[c0] * inv : 0.0;
+    const double p1 = a1 ? pr[c1] * inv : 0.0;
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
-      const int i = j + 1 + ty + 4 * k;
-      mul[k] = (i < n) ? wj[i] : 0.0;
-    }
-#pragma unroll
-    for (int cc = 0; cc < 2; ++cc) {
-      const int c = tx + 64 * cc;
-      if (c >= 2 * n) continue;
-      const bool left = c < n;
-      if (left ? (c <= j) : (c > n + j)) continue;
-      const double wjc = wj[c] * inv;
-      // rows i in (j, n); left-half entries only on or above the diagonal
-      const int ilim = left ? min(c, n - 1) : n - 1;
-      double x[KMAX];
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k) {
-        const int i = j + 1 + ty + 4 * k;
-        x[k] = (i <= ilim) ? W[i * ld + c] : 0.0;
+      const int i = ty + 4 * k;
+      if (i > j && i < n) {
+        const double mul = pr[i];
+        if (a0 && i <= lim0) w0[k] = w0[k] - mul * p0;
+        if (a1 && i <= lim1) w1[k] = w1[k] - mul * p1;
       }
+    }
+    // the owner of row j + 1 publishes it, updated through pivot j
+    if (j + 1 < n && ty == ((j + 1) & 3)) {
+      const int kk = (j + 1) >> 2;
+      double *nr = prow[(j + 1) & 1];
 #pragma unroll
       for (int k = 0; k < KMAX; ++k) {
-        const int i = j + 1 + ty + 4 * k;
-        if (i <= ilim) W[i * ld + c] = x[k] - mul[k] * wjc;
+        if (k == kk) {
+          if (c0 < n2) nr[c0] = w0[k];
+          if (c1 < n2) nr[c1] = w1[k];
+        }
       }
     }
     __syncthreads();
   }
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int i = ty + 4 * k;
+    if (i < n) {
+      if (c0 < n2) W[i * ld + c0] = w0[k];
+      if (c1 < n2) W[i * ld + c1] = w1[k];
+    }
+  }
+  __syncthreads();
   for (int i = ty; i < n; i += 4) {
     const double si = sqrt(piv[i]);
     for (int c = tx; c < n; c += 64) {
@@ -487,7 +516,7 @@ __global__ __launch_bounds__(256) void chol_kernel(const double *g, int64_t gbs,
     }
   }
   __syncthreads();
-  chol_eliminate(W, piv, dmax_s, n, r + p * rbs, rinv + p * rbs, flag + p * fstride, first, thr_rel);
+  chol_eliminate<kCholMaxN / 4>(W, piv, dmax_s, n, r + p * rbs, rinv + p * rbs, flag + p * fstride, first, thr_rel);
 }
 
 // CholeskyQR step fused with its Gram matrix, for batches of many pairs: the
@@ -499,13 +528,15 @@ __global__ __launch_bounds__(256) void chol_kernel(const double *g, int64_t gbs,
 // partial blocks into W in wave order (deterministic) and the block runs the
 // elimination above.
 template <int NB>
-__global__ __launch_bounds__(256) void gram_chol_kernel(CMat A, int64_t m, double *r, double *rinv, int64_t rbs,
+__global__ __launch_bounds__(256, 2) void gram_chol_kernel(CMat A, int64_t m, double *r, double *rinv, int64_t rbs,
                                                         int n, int *flag, int64_t fstride, int first,
                                                         double thr_rel) {
   extern __shared__ double W[];
   __shared__ double piv[kCholMaxN];
   __shared__ double dmax_s;
-  constexpr int U = 3;  // row groups of 4 per load batch (two batches in flight)
+  // row groups of 4 per load batch: two batches of 3 in flight up to 48
+  // columns; one batch of 4 beyond (two would exceed 256 VGPRs)
+  constexpr int U = NB <= 3 ? 3 : 4;
   const int ld = 2 * n + 1;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -538,7 +569,7 @@ __global__ __launch_bounds__(256) void gram_chol_kernel(CMat A, int64_t m, doubl
 #pragma unroll
         for (int j = i; j < NB; ++j) acc[i][j] = mfma16(v[u][i], v[u][j], acc[i][j]);
   };
-  {
+  if constexpr (NB <= 3) {
     double va[U][NB], vb[U][NB];
     int64_t s0 = (int64_t)wave * U;
     if (s0 < groups) load(s0, va);
@@ -549,6 +580,12 @@ __global__ __launch_bounds__(256) void gram_chol_kernel(CMat A, int64_t m, doubl
       if (s1 >= groups) break;
       if (s1 + 4 * U < groups) load(s1 + 4 * U, va);
       gram(vb);
+    }
+  } else {
+    for (int64_t s0 = (int64_t)wave * U; s0 < groups; s0 += 4 * U) {
+      double v[U][NB];
+      load(s0, v);
+      gram(v);
     }
   }
   for (int e = tid; e < n * ld; e += 256) {
@@ -570,7 +607,7 @@ __global__ __launch_bounds__(256) void gram_chol_kernel(CMat A, int64_t m, doubl
     }
     __syncthreads();
   }
-  chol_eliminate(W, piv, dmax_s, n, r + p * rbs, rinv + p * rbs, flag + p * fstride, first, thr_rel);
+  chol_eliminate<4 * NB>(W, piv, dmax_s, n, r + p * rbs, rinv + p * rbs, flag + p * fstride, first, thr_rel);
 }
 
 hipError_t launch_chol(const double *g, int64_t gbs, int ks, int64_t kstride, double *r, double *rinv,
