@@ -139,6 +139,24 @@ def test_hatt_explicit_sketch_matches_oracle(n, r, s, ell):
         assert np.allclose(v.T @ v, np.eye(v.shape[1]), atol=1e-12)
 
 
+# Middle-bond ranks chosen so the sandwich contractions run the
+# register-blocked kernel at every K-step count from 1 to 8 (K = bond rank
+# padded to 4 on both factors), plus unequal K steps and K beyond 32, which
+# take the runtime-K kernel.
+SANDWICH_SHAPES = [(4, 3), (8, 7), (12, 10), (16, 14), (24, 21), (28, 26), (32, 30), (22, 26), (36, 33)]
+
+
+@pytest.mark.parametrize("r,s", SANDWICH_SHAPES)
+def test_sandwich_k_steps_match_oracle(r, s):
+    n = [6, 6, 6, 6]
+    y, z = _pair(100 * r + s, n, r, s)
+    l = _ell(y, z, 13)
+    R = wk.gaussian_sketch(np.random.default_rng(r + s), n, l)
+    _say(f"hatt_recompress sandwich shapes ranks {tt.ranks(y)} / {tt.ranks(z)} ell={l}")
+    res = _gpu_hatt(y, z, 13, sketch=H.TT.from_cores(R))
+    assert tt.rel_err(res.train(0), ohatt.hatt(y, z, R)) <= TOL
+
+
 def test_hatt_exact_rank_reproduces_product():
     y, z = wk.tiny_pair(0)
     _say("hatt_recompress tiny exact rank, seeded")
