@@ -79,7 +79,10 @@ def _site_group(label, batch):
         n, G, RA, RI, SI, SO = (int(v) for v in m.groups()[1:7])
         flops = 2.0 * n * G * (RI * SI * SO + RA * RI * SO) * batch
         nbytes = 8.0 * (G * RI * SI + n * RA * RI + n * SI * SO + n * G * RA * SO) * batch
-        return m.group(8), "alu", flops, nbytes
+        kern = m.group(8)
+        # the sandwich_ks / sandwich_mfma kernels run on the matrix cores
+        unit = "mfma" if ("_ks_" in kern or "_mfma_" in kern) else "alu"
+        return kern, unit, flops, nbytes
     m = _GEMM.match(label)
     if m:
         M, N, K = (int(v) for v in m.groups()[:3])
@@ -109,14 +112,28 @@ def _roofline(report, batch, steps, perfmodel):
     gr = groups[dom]
     avg_s = gr["ms"] / gr["calls"] / 1000.0
     per_launch = gr["flops"] / gr["calls"]
-    achieved = per_launch / avg_s / 1e12
-    peak = perfmodel.PEAK_FP64_TFLOPS
-    return {"kernel": dom, "bound": gr["bound"], "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+    bytes_launch = gr["bytes"] / gr["calls"]
+    tflops = per_launch / avg_s / 1e12
+    gbs = bytes_launch / avg_s / 1e9
+    bound = gr["bound"]
+    if bound == "mfma" and bytes_launch > 0:
+        # roofline: below the ridge (peak flops / peak bandwidth, ~9.8 flop/B
+        # in FP64) the compulsory bytes, not the matrix cores, set the bound
+        ridge = perfmodel.PEAK_FP64_TFLOPS * 1e12 / (perfmodel.PEAK_HBM_GBS * 1e9)
+        if per_launch / bytes_launch < ridge:
+            bound = "hbm"
+    if bound == "hbm":
+        achieved, peak, unit = gbs, perfmodel.PEAK_HBM_GBS, "GB/s"
+    else:
+        achieved, peak, unit = tflops, perfmodel.PEAK_FP64_TFLOPS, "TFLOP/s"
+    return {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak, "traffic": _traffic(dom, batch),
             "avg_launch_us": 1e6 * avg_s, "launches_per_step": gr["calls"] / steps,
             "algorithmic_flop_per_launch": per_launch,
-            "algorithmic_bytes_per_launch": gr["bytes"] / gr["calls"],
-            "algorithmic_GBs": gr["bytes"] / gr["calls"] / avg_s / 1e9}
+            "algorithmic_bytes_per_launch": bytes_launch,
+            "algorithmic_intensity_flop_per_byte": per_launch / bytes_launch if bytes_launch else None,
+            "algorithmic_TFLOPs": tflops,
+            "algorithmic_GBs": gbs}
 
 
 def _traffic(kernel, batch):

@@ -32,12 +32,25 @@ def test_roofline_groups_sites_by_compiled_kernel():
     roof = b._roofline(REPORT, 128, 10, perfmodel)
     # gemm_f64_kernel<64, 32>: 110 ms over 20 launches beats the sandwich's 100 ms
     assert roof["kernel"] == "gemm_f64_kernel<64, 32>"
-    assert roof["bound"] == "mfma"
     assert roof["avg_launch_us"] == pytest.approx(110.0 / 20 * 1000)
     flops = (2 * 400 * 40 * 1280 * 10 + 2 * 1280 * 40 * 40 * 10) * 128
+    nbytes = 8 * ((400 * 1280 + 1280 * 40 + 400 * 40) * 10 + (1280 * 40 + 40 * 40 + 1280 * 40) * 10) * 128
     assert roof["algorithmic_flop_per_launch"] == pytest.approx(flops / 20)
-    assert roof["achieved"] == pytest.approx(flops / 0.110 / 1e12)
-    assert roof["frac"] == pytest.approx(roof["achieved"] / 78.6)
+    assert roof["algorithmic_TFLOPs"] == pytest.approx(flops / 0.110 / 1e12)
+    # 8.2 flop/B is below the FP64 ridge (78.6 TFLOP/s / 8 TB/s = 9.8): HBM-bound
+    assert roof["algorithmic_intensity_flop_per_byte"] == pytest.approx(flops / nbytes)
+    assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
+    assert roof["achieved"] == pytest.approx(nbytes / 0.110 / 1e9)
+    assert roof["frac"] == pytest.approx(roof["achieved"] / 8000.0)
+
+
+def test_roofline_above_the_ridge_is_matrix_core_bound():
+    b = _bench()
+    rep = "      10.000 ms        5 calls  gemm_f64: gemm 1024x1024x1024 ks=1 [gemm_f64_kernel<64, 64, 0>]\n"
+    roof = b._roofline(rep, 4, 5, perfmodel)
+    flops = 2.0 * 1024 ** 3 * 4
+    assert roof["bound"] == "mfma" and roof["unit"] == "TFLOP/s" and roof["peak"] == 78.6
+    assert roof["achieved"] == pytest.approx(flops / 0.002 / 1e12)
 
 
 def test_sandwich_site_flops():
