@@ -594,25 +594,28 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
     }
     return HATT_OK;
   }
-  // --- right-to-left orthogonalisation; core c layout: [*][n_c][rb_{c+1}] compact
+  // --- right-to-left orthogonalisation; core c layout: [*][n_c][rb_{c+1}] compact.
+  // V(B_{c-1}) R^T lands in Tm in that same compact layout, and the next QR
+  // reads it there (writing its Q into the core's slot), so no copy-back.
   for (int c = d - 1; c >= 1; --c) {
     const QrOp &op = op_rl[c];
     const int64_t m = n[c] * rb[c + 1], nc = sp.rin[c], k = op.k;
     double *core = work + soff[c];
-    // H(B_c)^T is m x nc: element (j, a) = core[a * m + j]
-    hatt_status s = qr_exec(run, op, CMat{core, 1, m, wstride}, Mat{core, 1, m, wstride}, Mat{Rb, nc, 1, rbuf},
-                            rbuf, wqr, qr_ws, P, gc, st);
+    // H(B_c)^T is m x nc: element (j, a) = src[a * m + j]
+    const CMat src = (c == d - 1) ? CMat{core, 1, m, wstride} : CMat{Tm, 1, m, tmp};
+    hatt_status s = qr_exec(run, op, src, Mat{core, 1, m, wstride}, Mat{Rb, nc, 1, rbuf}, rbuf, wqr, qr_ws, P, gc,
+                            st);
     if (s != HATT_OK) return s;
     // V(B_{c-1}) R^T, V(B_{c-1}) is (rin_{c-1} n_{c-1}) x nc with row stride nc
-    double *prev = work + soff[c - 1];
+    const double *prev = work + soff[c - 1];
     const int64_t mp = sp.rin[c - 1] * n[c - 1];
     s = gemm(run, gc, CMat{prev, nc, 1, wstride}, CMat{Rb, 1, nc, rbuf}, Mat{Tm, k, 1, tmp}, mp, k, nc, 1.0,
              0.0, P, st, true);
     if (s != HATT_OK) return s;
-    LAUNCH(launch_copy(CMat{Tm, k, 1, tmp}, Mat{prev, k, 1, wstride}, mp, k, P, st));
   }
+  // the orthogonalised first core lives in Tm (rin_0 = 1 row of n_0 rb_1 entries)
   if (sp.norm_only) {
-    LAUNCH(launch_block_norm(work + soff[0], n[0] * rb[1], wstride, sp.norm_out, P, st));
+    LAUNCH(launch_block_norm(Tm, n[0] * rb[1], tmp, sp.norm_out, P, st));
     return HATT_OK;
   }
   // --- left-to-right truncation
@@ -625,7 +628,7 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
   for (int c = 0; c < d - 1; ++c) {
     const QrOp &op = op_lr[c];
     const int64_t m = cap[c] * n[c], nc = rb[c + 1], k = op.k;
-    CMat V = (c == 0) ? CMat{work + soff[0], nc, 1, wstride} : CMat{Tcur, nc, 1, tbuf};
+    CMat V = (c == 0) ? CMat{Tm, nc, 1, tmp} : CMat{Tcur, nc, 1, tbuf};
     hatt_status s = qr_exec(run, op, V, Mat{Qb, k, 1, qbuf}, Mat{Rb, nc, 1, rbuf}, rbuf, wqr, qr_ws, P, gc, st);
     if (s != HATT_OK) return s;
     SvdArgs sa{};
