@@ -39,9 +39,9 @@ def _parse():
     ap.add_argument("--eager", action="store_true", help="launch kernels directly instead of replaying a HIP graph")
     ap.add_argument("--precision", choices=["f64", "f32"], default="f64",
                     help="f32: range finding on the FP32 matrix cores, projection and truncation in FP64")
-    ap.add_argument("--rp-train", type=int, default=48, help="rankpred: training recompressions")
-    ap.add_argument("--rp-eval", type=int, default=16, help="rankpred: fresh pairs evaluated")
-    ap.add_argument("--rp-margin", type=float, default=0.1, help="rankpred: width safety margin")
+    ap.add_argument("--rp-train", type=int, default=128, help="rankpred: training recompressions")
+    ap.add_argument("--rp-eval", type=int, default=24, help="rankpred: fresh pairs evaluated")
+    ap.add_argument("--rp-margin", type=float, default=0.15, help="rankpred: width safety margin")
     ap.add_argument("--workload", choices=["spectral", "batched", "rankpred"], default="spectral",
                     help="spectral: the metric's workload; batched: the 512-pair uneven workload (own JSON line)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
