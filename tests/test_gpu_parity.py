@@ -527,6 +527,29 @@ def test_fp32_range_finding_full_order():
     assert abs(e32 - e64) <= 1e-3 * e64
 
 
+@pytest.mark.parametrize("ell", [40, 56])
+def test_many_pairs_fused_gram_cholesky_wide_frames(ell):
+    """34 pairs with sketched frames of 40 and 56 columns: the fused Gram +
+    Cholesky kernel with three and four 16-column blocks (pipelined row
+    batches; one batch in flight), its register-resident elimination, and the
+    rounding's QRs of the same widths, every pair against the oracle."""
+    B = 34
+    n = [8] * 6
+    pairs = [wk.spectral_pair(5000 + b, d=6, n=8, rx=7, ry=8) for b in range(B)]
+    ys = [p[0] for p in pairs]
+    zs = [p[1] for p in pairs]
+    l = _ell(ys[0], zs[0], ell)
+    assert max(l) == ell
+    R = wk.gaussian_sketch(np.random.default_rng(ell), n, l)
+    _say(f"hatt_recompress batch={B} ell={l} max_rank=20 (fused Gram + Cholesky, wide frames)")
+    res = _gpu_hatt(ys, zs, ell, sketch=H.TT.from_cores(R), max_rank=20)
+    for b in range(B):
+        ref = rounding.tt_round(ohatt.hatt(ys[b], zs[b], R), max_rank=20)
+        got = res.train(b)
+        assert tt.ranks(got) == tt.ranks(ref), b
+        assert tt.rel_err(got, ref) <= TOL, b
+
+
 def test_many_pairs_fused_gram_cholesky():
     """40 pairs in one batch (the CholeskyQR2 Gram matrices are then formed
     inside the factorisation kernel): every pair matches the oracle, also
