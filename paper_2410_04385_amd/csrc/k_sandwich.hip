@@ -85,7 +85,6 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
   const bool off32 = ymax < (1LL << 31) && zmax < (1LL << 31);
   pf = pf && off32;
   pl->pf = pf ? 1 : 0;
-  // the register-blocked kernel: equal K steps, and every valid YL / ZR entry in a fetch slot
   // register-blocked kernel: equal K steps, every valid YL / ZR entry in a
   // fetch slot, block counts that divide the four waves, 32-bit output offsets
   pl->ks = 0;
