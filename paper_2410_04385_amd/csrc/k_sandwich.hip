@@ -339,7 +339,11 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
 // parked after stage 1 and the one after that is fetched before stage 2, so
 // the fetch registers stay live across the stage-2 stores and the wait for
 // them (vector loads and stores share one counter) comes a whole stage 1
-// after the last store.
+// after the last store.  In the remainder form (REM: FP64, 17 to 20 columns
+// of ZR and rows of YL) a wave holds both the full 16-block and the 4-wide
+// remainder of the held operand and takes every fourth block row (stage 1)
+// or block column (stage 2) of the other, forming the remainder with the
+// four-block 4 x 4 x 4 MFMA on the same fragments.
 
 // Blocks j = 0 .. count-1 of one product on one wave: the moving operand's
 // fragment of block j starts at p + j dp (K steps sk apart), the held operand
