@@ -146,6 +146,21 @@ def test_hatt_explicit_sketch_matches_oracle(n, r, s, ell):
 SANDWICH_SHAPES = [(4, 3), (8, 7), (12, 10), (16, 14), (24, 21), (28, 26), (32, 30), (22, 26), (36, 33)]
 
 
+def test_sandwich_wide_free_sides_match_oracle():
+    """Bond ranks 56 / 52 beside 16 / 14: the register-blocked sandwich with
+    four ZR column blocks and four YL row blocks (every wave in its own block
+    column / row) at four K steps."""
+    rng = np.random.default_rng(77)
+    n = [8, 8, 8, 8, 8]
+    y = wk.gaussian_tt(rng, n, [1, 8, 56, 16, 8, 1])
+    z = wk.gaussian_tt(rng, n, [1, 8, 52, 14, 8, 1])
+    l = _ell(y, z, 30)
+    R = wk.gaussian_sketch(np.random.default_rng(78), n, l)
+    _say(f"hatt_recompress wide free sides ranks {tt.ranks(y)} / {tt.ranks(z)} ell={l}")
+    res = _gpu_hatt([y], [z], 30, sketch=H.TT.from_cores(R))
+    assert tt.rel_err(res.train(0), ohatt.hatt(y, z, R)) <= TOL
+
+
 @pytest.mark.parametrize("r,s", SANDWICH_SHAPES)
 def test_sandwich_k_steps_match_oracle(r, s):
     n = [6, 6, 6, 6]
