@@ -7,7 +7,8 @@ Hadamard product is recompressed with a seeded Gaussian sketch of width 40
 and truncated to rank 30 by TT-Rounding.  One step recompresses a batch of
 independent pairs (inputs resident in HBM before timing starts).
 
-Prints one JSON line (see the design doc for the field definitions).
+Prints one JSON line: metric, value, unit, steps, the roofline of the kernel
+with the most time, the oracle timed on the host, and per-class timings.
 """
 
 from __future__ import annotations
@@ -304,9 +305,9 @@ def _bench_rankpred(args, torch, wk, H) -> int:
 def main() -> int:
     args = _parse()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}): this build has no "
-              "multi-GPU path; independent pairs would shard across GPUs without communication "
-              "(see DESIGN.md).", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}): the library has no "
+              "multi-GPU path; independent pairs would shard across GPUs without communication.",
+              file=sys.stderr)
         return 2
     if args.workload == "batched":
         # independent pairs run on the library's 32 streams; HIP's default of 4

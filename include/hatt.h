@@ -52,7 +52,7 @@ typedef enum {
   HATT_EDEVICE = -4,     /* a HIP call or kernel launch failed */
   HATT_ENOTCONV = -5,    /* reserved: adaptive sketch growth did not converge */
   HATT_ENONFINITE = -6,  /* reserved: non-finite input detected */
-  HATT_EUNSUPPORTED = -7 /* a shape this build does not handle (see message) */
+  HATT_EUNSUPPORTED = -7 /* a shape the library does not handle (see message) */
 } hatt_status;
 
 typedef struct {

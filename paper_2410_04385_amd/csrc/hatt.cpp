@@ -545,7 +545,7 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
     const int64_t m = n[c] * rb[c + 1], nc = sp.rin[c];
     if (!qr_prepare(m, nc, &op_rl[c]))
       return fail(HATT_EUNSUPPORTED, "TT-Rounding: a right-to-left QR of " + std::to_string(m) + " x " +
-                                         std::to_string(nc) + " exceeds this build's QR limits");
+                                         std::to_string(nc) + " exceeds the library's QR limits");
     qr_ws = std::max(qr_ws, op_rl[c].ws_doubles);
     rbuf = std::max(rbuf, op_rl[c].k * nc);
     tmp = std::max(tmp, sp.rin[c - 1] * n[c - 1] * op_rl[c].k);
@@ -555,10 +555,10 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
       const int64_t m = cap[c] * n[c], nc = rb[c + 1];
       if (!qr_prepare(m, nc, &op_lr[c]))
         return fail(HATT_EUNSUPPORTED, "TT-Rounding: a left-to-right QR of " + std::to_string(m) + " x " +
-                                           std::to_string(nc) + " exceeds this build's QR limits");
+                                           std::to_string(nc) + " exceeds the library's QR limits");
       if (nc > kSvdBigMaxN)
         return fail(HATT_EUNSUPPORTED, "TT-Rounding: bond rank " + std::to_string(nc) +
-                                           " exceeds this build's SVD limit (" + std::to_string(kSvdBigMaxN) + ")");
+                                           " exceeds the library's SVD limit (" + std::to_string(kSvdBigMaxN) + ")");
       const int64_t k = op_lr[c].k;
       qr_ws = std::max(qr_ws, op_lr[c].ws_doubles);
       qbuf = std::max(qbuf, m * k);
@@ -976,7 +976,7 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     LAUNCH(launch_sandwich(a, st));
   }
   // ranks before truncation: the sketch widths
-  if ((int)l.size() > kMaxRankPattern) return fail(HATT_EUNSUPPORTED, "order too large for this build");
+  if ((int)l.size() > kMaxRankPattern) return fail(HATT_EUNSUPPORTED, "order too large for the library (rank pattern buffer)");
   LAUNCH(launch_rank_pattern(sp.orank, P, d + 1, l.data(), st));
   // ---- truncation (Alg. 1 on the rank-l result)
   const bool trunc = (sp.o.max_rank > 0) || (sp.o.tol > 0.0);

@@ -136,7 +136,7 @@ def test_null_arguments_are_rejected():
 
 
 def test_unsupported_widths_are_reported():
-    # truncating a sketch wider than the largest SVD this build has is refused
+    # truncating a sketch wider than the library's largest SVD is refused
     n = [2048, 2048, 2048]
     x = _cpu_tt(n, [1, 40, 40, 1])
     p = api.plan(x, x, 1100)            # no truncation: any width is fine

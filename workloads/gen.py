@@ -1,6 +1,6 @@
 """Input generators (numpy PCG64, seeded).  No recompression arithmetic here.
 
-Workloads (sizes and value laws; the recipe is restated in the design doc):
+Workloads (sizes and value laws):
 
 * ``tiny``      d=6, n=4, all ranks 3, cores i.i.d. N(0, 1/(n*r)) with r=3.
 * ``spectral``  d=20, n=32, r_x=r_y=20; every core is a Haar-random
