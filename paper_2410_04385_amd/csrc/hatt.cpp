@@ -211,7 +211,7 @@ struct GemmTypes {
 hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_t N, int64_t K,
                  double alpha, double beta, int batch, hipStream_t st, bool allow_split,
                  const int *run_flag = nullptr, int64_t run_flag_stride = 0, int *ks_out = nullptr,
-                 GemmTypes ty = GemmTypes{}) {
+                 GemmTypes ty = GemmTypes{}, int run_when = 1) {
   GemmArgs g{};
   g.prec = ty.prec;
   g.a_f32 = ty.a32;
@@ -221,7 +221,7 @@ hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_
   g.no_reduce = 1;  // the reduction, when needed, is its own launch below
   g.run_flag = run_flag;
   g.run_flag_stride = run_flag_stride;
-  g.run_when = 1;
+  g.run_when = run_when;
   g.A = A;
   g.B = B;
   g.C = C;
@@ -340,8 +340,18 @@ bool qr_prepare(int64_t m, int64_t n, QrOp *op) {
 
 constexpr int kCholFuseMinPairs = 32;
 
+// CholeskyQR2 that leaves Q = Q1 R2^{-1} unformed for the pairs it keeps:
+// the caller applies Q1 and R2^{-1} itself (Q holds the fallback's Q for the
+// flagged pairs, flag 0).
+struct QrDeferred {
+  const double *q1 = nullptr, *r2i = nullptr;  // m x n and n x n row-major, pair stride wsp
+  const int *flag = nullptr;                   // 1: CholeskyQR2 kept the pair
+  int64_t wsp = 0, fst = 0;
+  bool used = false;
+};
+
 hatt_status cholqr2_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double *ws, int64_t wsp, int P,
-                         GemmCtx &gc, hipStream_t st) {
+                         GemmCtx &gc, hipStream_t st, QrDeferred *def = nullptr) {
   const int64_t m = op.m, n = op.n;
   double *q1 = ws + op.ws_tree;  // m x n row-major
   double *g = q1 + m * n;
@@ -374,8 +384,17 @@ hatt_status cholqr2_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double 
     site("chol %lld", (long long)n);
     LAUNCH(launch_chol(g, wsp, 1, 0, r2, r2i, wsp, (int)n, flag, fst, 0, kCholThr2, P, st));
   }
-  sg = gemm(run, gc, q1c, CMat{r2i, n, 1, wsp}, Q, m, n, n, 1.0, 0.0, P, st, false, flag, fst);
-  if (sg != HATT_OK) return sg;
+  if (def != nullptr) {
+    def->q1 = q1;
+    def->r2i = r2i;
+    def->flag = flag;
+    def->wsp = wsp;
+    def->fst = fst;
+    def->used = true;
+  } else {
+    sg = gemm(run, gc, q1c, CMat{r2i, n, 1, wsp}, Q, m, n, n, 1.0, 0.0, P, st, false, flag, fst);
+    if (sg != HATT_OK) return sg;
+  }
   if (R.ptr) {
     sg = gemm(run, gc, CMat{r2, n, 1, wsp}, CMat{r1, n, 1, wsp}, R, n, n, n, 1.0, 0.0, P, st, false, flag, fst);
     if (sg != HATT_OK) return sg;
@@ -388,7 +407,7 @@ hatt_status cholqr2_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double 
 // A (m x n), Q (m x k), R (k x n row-major with row stride r.rs, or null).
 // R, when given, must be a contiguous per-pair block of rbuf doubles.
 hatt_status qr_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, int64_t rbuf, double *ws, int64_t wsp,
-                    int P, GemmCtx &gc, hipStream_t st) {
+                    int P, GemmCtx &gc, hipStream_t st, QrDeferred *def = nullptr) {
   ClassScope cls(P_QR);
   if (op.wide) {
     hatt_status s0 = qr_exec(run, *op.sub, A, Q, R, rbuf, ws, wsp, P, gc, st);
@@ -400,7 +419,7 @@ hatt_status qr_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, int64_t rbuf
     }
     return HATT_OK;
   }
-  if (op.chol) return cholqr2_exec(run, op, A, Q, R, ws, wsp, P, gc, st);
+  if (op.chol) return cholqr2_exec(run, op, A, Q, R, ws, wsp, P, gc, st, def);
   if (!op.big) {
     site("tsqr %lldx%lld", (long long)op.m, (long long)op.n);
     LAUNCH(launch_tsqr(op.direct, A, Q, R, ws, wsp, P, st));
@@ -566,6 +585,7 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
       ubuf = std::max(ubuf, k * cap[c + 1]);
       sbuf = std::max(sbuf, cap[c + 1] * nc);
       tbuf = std::max(tbuf, cap[c + 1] * n[c + 1] * rb[c + 2]);
+      tmp = std::max(tmp, k * cap[c + 1]);  // R2^{-1} U of a deferred CholeskyQR2
       svd_ws = std::max(svd_ws, svd_ws_doubles((int)k, (int)nc));
     }
   }
@@ -629,7 +649,10 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
     const QrOp &op = op_lr[c];
     const int64_t m = cap[c] * n[c], nc = rb[c + 1], k = op.k;
     CMat V = (c == 0) ? CMat{Tm, nc, 1, tmp} : CMat{Tcur, nc, 1, tbuf};
-    hatt_status s = qr_exec(run, op, V, Mat{Qb, k, 1, qbuf}, Mat{Rb, nc, 1, rbuf}, rbuf, wqr, qr_ws, P, gc, st);
+    // the output core needs Q only through Q U: CholeskyQR2 may leave it as Q1 R2^{-1}
+    QrDeferred qd;
+    hatt_status s =
+        qr_exec(run, op, V, Mat{Qb, k, 1, qbuf}, Mat{Rb, nc, 1, rbuf}, rbuf, wqr, qr_ws, P, gc, st, &qd);
     if (s != HATT_OK) return s;
     SvdArgs sa{};
     sa.r = Rb;
@@ -654,8 +677,21 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
     s = svd_exec(run, sa, svdbig, svd_ws, flags, gc, st);
     if (s != HATT_OK) return s;
     // out core c = Q U  (m x cap_{c+1})
-    s = gemm(run, gc, CMat{Qb, k, 1, qbuf}, CMat{Ub, cap[c + 1], 1, ubuf},
-             Mat{sp.out + ooff[c], cap[c + 1], 1, sp.ostride}, m, cap[c + 1], k, 1.0, 0.0, P, st, true);
+    const Mat oc{sp.out + ooff[c], cap[c + 1], 1, sp.ostride};
+    if (qd.used) {
+      // kept pairs: Q1 (R2^{-1} U); pairs the fallback recomputed: Q U
+      s = gemm(run, gc, CMat{qd.r2i, k, 1, qd.wsp}, CMat{Ub, cap[c + 1], 1, ubuf}, Mat{Tm, cap[c + 1], 1, tmp},
+               k, cap[c + 1], k, 1.0, 0.0, P, st, false, qd.flag, qd.fst, nullptr, GemmTypes{}, 1);
+      if (s != HATT_OK) return s;
+      s = gemm(run, gc, CMat{qd.q1, k, 1, qd.wsp}, CMat{Tm, cap[c + 1], 1, tmp}, oc, m, cap[c + 1], k, 1.0, 0.0,
+               P, st, true, qd.flag, qd.fst, nullptr, GemmTypes{}, 1);
+      if (s != HATT_OK) return s;
+      s = gemm(run, gc, CMat{Qb, k, 1, qbuf}, CMat{Ub, cap[c + 1], 1, ubuf}, oc, m, cap[c + 1], k, 1.0, 0.0, P,
+               st, true, qd.flag, qd.fst, nullptr, GemmTypes{}, 0);
+    } else {
+      s = gemm(run, gc, CMat{Qb, k, 1, qbuf}, CMat{Ub, cap[c + 1], 1, ubuf}, oc, m, cap[c + 1], k, 1.0, 0.0, P,
+               st, true);
+    }
     if (s != HATT_OK) return s;
     // next core = SVt H(B_{c+1}):  (cap_{c+1} x nc) (nc x n_{c+1} rb_{c+2})
     const int64_t ncol = n[c + 1] * rb[c + 2];
