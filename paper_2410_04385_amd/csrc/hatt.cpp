@@ -343,7 +343,11 @@ constexpr int kCholFuseMinPairs = 32;
 // CholeskyQR2 that leaves Q = Q1 R2^{-1} unformed for the pairs it keeps:
 // the caller applies Q1 and R2^{-1} itself (Q holds the fallback's Q for the
 // flagged pairs, flag 0).
+// With q1_in_q set (by the caller), Q1 itself is written where Q goes (the
+// fallback's Q then replaces it for the flagged pairs), so Q = Q1 R2^{-1}
+// there for the kept pairs and Q for the others.
 struct QrDeferred {
+  bool q1_in_q = false;
   const double *q1 = nullptr, *r2i = nullptr;  // m x n and n x n row-major, pair stride wsp
   const int *flag = nullptr;                   // 1: CholeskyQR2 kept the pair
   int64_t wsp = 0, fst = 0;
@@ -359,14 +363,16 @@ hatt_status cholqr2_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double 
   int *flag = reinterpret_cast<int *>(r2i + n * n);
   const int64_t fst = 2 * wsp;  // flag stride in ints
   CMat At{A.ptr, A.cs, A.rs, A.bs};
-  CMat q1c{q1, n, 1, wsp}, q1t{q1, 1, n, wsp};
+  const bool inq = def != nullptr && def->q1_in_q;
+  const Mat q1m = inq ? Q : Mat{q1, n, 1, wsp};
+  CMat q1c{q1m.ptr, q1m.rs, q1m.cs, q1m.bs}, q1t{q1m.ptr, q1m.cs, q1m.rs, q1m.bs};
   hatt_status sg;
   if (P >= kCholFuseMinPairs) {
     // many pairs fill the GPU with one block per pair: each block forms its
     // pair's Gram matrix on the matrix cores and factors it in place
     site("gram+chol %lldx%lld", (long long)m, (long long)n);
     LAUNCH(launch_gram_chol(A, m, (int)n, r1, r1i, wsp, flag, fst, 1, kCholThr1, P, st));
-    sg = gemm(run, gc, A, CMat{r1i, n, 1, wsp}, Mat{q1, n, 1, wsp}, m, n, n, 1.0, 0.0, P, st, false);
+    sg = gemm(run, gc, A, CMat{r1i, n, 1, wsp}, q1m, m, n, n, 1.0, 0.0, P, st, false);
     if (sg != HATT_OK) return sg;
     site("gram+chol %lldx%lld", (long long)m, (long long)n);
     LAUNCH(launch_gram_chol(q1c, m, (int)n, r2, r2i, wsp, flag, fst, 0, kCholThr2, P, st));
@@ -377,7 +383,7 @@ hatt_status cholqr2_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double 
     if (sg != HATT_OK) return sg;
     site("chol %lld", (long long)n);
     LAUNCH(launch_chol(g, wsp, 1, 0, r1, r1i, wsp, (int)n, flag, fst, 1, kCholThr1, P, st));
-    sg = gemm(run, gc, A, CMat{r1i, n, 1, wsp}, Mat{q1, n, 1, wsp}, m, n, n, 1.0, 0.0, P, st, false);
+    sg = gemm(run, gc, A, CMat{r1i, n, 1, wsp}, q1m, m, n, n, 1.0, 0.0, P, st, false);
     if (sg != HATT_OK) return sg;
     sg = gemm(run, gc, q1t, q1c, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true);
     if (sg != HATT_OK) return sg;
@@ -385,7 +391,7 @@ hatt_status cholqr2_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double 
     LAUNCH(launch_chol(g, wsp, 1, 0, r2, r2i, wsp, (int)n, flag, fst, 0, kCholThr2, P, st));
   }
   if (def != nullptr) {
-    def->q1 = q1;
+    def->q1 = q1m.ptr;
     def->r2i = r2i;
     def->flag = flag;
     def->wsp = wsp;
@@ -586,6 +592,7 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
       sbuf = std::max(sbuf, cap[c + 1] * nc);
       tbuf = std::max(tbuf, cap[c + 1] * n[c + 1] * rb[c + 2]);
       tmp = std::max(tmp, k * cap[c + 1]);  // R2^{-1} U of a deferred CholeskyQR2
+      tmp = std::max(tmp, cap[c + 1] * nc);  // S V^T R2^{-T} of a deferred right-to-left QR
       svd_ws = std::max(svd_ws, svd_ws_doubles((int)k, (int)nc));
     }
   }
@@ -599,6 +606,16 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
   double *T0 = ws.d((int64_t)P * tbuf);
   double *T1 = ws.d((int64_t)P * tbuf);
   double *Tm = ws.d((int64_t)P * tmp);
+  // right-to-left cores 1..d-2 whose CholeskyQR2 left Q as Q1 (kept pairs):
+  // their R2^{-1} (rin x rin) and the keep flag, per pair
+  std::vector<int64_t> keep_off(d + 1, 0);
+  int64_t keep_tot = 1;
+  for (int c = 1; c <= d - 2; ++c) {
+    keep_off[c] = keep_tot;
+    keep_tot += sp.rin[c] * sp.rin[c] + 1;
+  }
+  double *keep = ws.d((int64_t)P * keep_tot);
+  std::vector<char> deferred(d + 1, 0);
   double *dl2 = ws.d(P);
   double *svdbig = ws.d((int64_t)P * svd_ws);
   int *flags = (int *)ws.d(P);
@@ -623,9 +640,20 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
     double *core = work + soff[c];
     // H(B_c)^T is m x nc: element (j, a) = src[a * m + j]
     const CMat src = (c == d - 1) ? CMat{core, 1, m, wstride} : CMat{Tm, 1, m, tmp};
+    // below the last core the QR is not in place: CholeskyQR2 may leave Q1 in
+    // the core's slot and R2^{-1} aside (the left-to-right pass applies it)
+    QrDeferred qd;
+    qd.q1_in_q = true;
     hatt_status s = qr_exec(run, op, src, Mat{core, 1, m, wstride}, Mat{Rb, nc, 1, rbuf}, rbuf, wqr, qr_ws, P, gc,
-                            st);
+                            st, (c < d - 1 && !sp.norm_only) ? &qd : nullptr);
     if (s != HATT_OK) return s;
+    if (qd.used) {
+      if (op.k != nc) return fail(HATT_EUNSUPPORTED, "internal: deferred QR with k != n");
+      // R2^{-1} and the flag int right after it, as nc * nc + 1 doubles
+      LAUNCH(launch_copy(CMat{qd.r2i, nc * nc + 1, 1, qd.wsp}, Mat{keep + keep_off[c], nc * nc + 1, 1, keep_tot}, 1,
+                         nc * nc + 1, P, st));
+      deferred[c] = 1;
+    }
     // V(B_{c-1}) R^T, V(B_{c-1}) is (rin_{c-1} n_{c-1}) x nc with row stride nc
     const double *prev = work + soff[c - 1];
     const int64_t mp = sp.rin[c - 1] * n[c - 1];
@@ -695,8 +723,24 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
     if (s != HATT_OK) return s;
     // next core = SVt H(B_{c+1}):  (cap_{c+1} x nc) (nc x n_{c+1} rb_{c+2})
     const int64_t ncol = n[c + 1] * rb[c + 2];
-    s = gemm(run, gc, CMat{Sb, nc, 1, sbuf}, CMat{work + soff[c + 1], ncol, 1, wstride},
-             Mat{Tnext, ncol, 1, tbuf}, cap[c + 1], ncol, nc, 1.0, 0.0, P, st, true);
+    const CMat hnext{work + soff[c + 1], ncol, 1, wstride};
+    const Mat tn{Tnext, ncol, 1, tbuf};
+    if (deferred[c + 1]) {
+      // the slot holds Q1^T for the kept pairs (H = R2^{-T} Q1^T): (SVt R2^{-T}) Q1^T
+      const double *r2k = keep + keep_off[c + 1];
+      const int *kf = reinterpret_cast<const int *>(r2k + nc * nc);
+      const int64_t kfs = 2 * keep_tot;
+      s = gemm(run, gc, CMat{Sb, nc, 1, sbuf}, CMat{r2k, 1, nc, keep_tot}, Mat{Tm, nc, 1, tmp}, cap[c + 1], nc, nc,
+               1.0, 0.0, P, st, false, kf, kfs, nullptr, GemmTypes{}, 1);
+      if (s != HATT_OK) return s;
+      s = gemm(run, gc, CMat{Tm, nc, 1, tmp}, hnext, tn, cap[c + 1], ncol, nc, 1.0, 0.0, P, st, true, kf, kfs,
+               nullptr, GemmTypes{}, 1);
+      if (s != HATT_OK) return s;
+      s = gemm(run, gc, CMat{Sb, nc, 1, sbuf}, hnext, tn, cap[c + 1], ncol, nc, 1.0, 0.0, P, st, true, kf, kfs,
+               nullptr, GemmTypes{}, 0);
+    } else {
+      s = gemm(run, gc, CMat{Sb, nc, 1, sbuf}, hnext, tn, cap[c + 1], ncol, nc, 1.0, 0.0, P, st, true);
+    }
     if (s != HATT_OK) return s;
     Tcur = Tnext;
     Tnext = (Tnext == T0) ? T1 : T0;
