@@ -91,7 +91,7 @@ def _site_group(label, batch):
     return None
 
 
-def _roofline(report, batch, steps, perfmodel):
+def _roofline(report, batch, steps, perfmodel, precision="f64"):
     groups = {}
     for line in report.splitlines():
         m = _SITE.match(line)
@@ -128,7 +128,7 @@ def _roofline(report, batch, steps, perfmodel):
     else:
         achieved, peak, unit = tflops, perfmodel.PEAK_FP64_TFLOPS, "TFLOP/s"
     return {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": _traffic(dom, batch),
+            "frac": achieved / peak, "traffic": _traffic(dom, batch, precision),
             "avg_launch_us": 1e6 * avg_s, "launches_per_step": gr["calls"] / steps,
             "algorithmic_flop_per_launch": per_launch,
             "algorithmic_bytes_per_launch": bytes_launch,
@@ -137,17 +137,18 @@ def _roofline(report, batch, steps, perfmodel):
             "algorithmic_GBs": gbs}
 
 
-def _traffic(kernel, batch):
+def _traffic(kernel, batch, precision):
     """HBM bytes per launch of `kernel` from the committed hardware-counter
-    summary, or None when none was taken at this batch size or the kernel
-    source has changed since."""
+    summary, or None when none was taken at this batch size and precision
+    (the launch mix behind one kernel name differs between precisions) or the
+    kernel source has changed since."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         data = json.load(fh)
     ent = data.get(kernel)
-    if not ent or ent.get("batch") != batch:
+    if not ent or ent.get("batch") != batch or ent.get("precision") != precision:
         return None
     src = os.path.join(ROOT, ent["source"])
     with open(src, "rb") as fh:
@@ -408,7 +409,7 @@ def main() -> int:
         if f > 0:
             classes[name]["tflops"] = f / (classes[name]["ms_per_step"] / 1000.0) / 1e12
     step_tflops = flops["total"] * B / (ms_per_step / 1000.0) / 1e12
-    roof = _roofline(report, B, args.steps, perfmodel)
+    roof = _roofline(report, B, args.steps, perfmodel, args.precision)
     # explicit PKP + TT-Rounding on the GPU (the comparator of the metric),
     # timed on a batch of 8 pairs of the same workload
     explicit = None

@@ -67,9 +67,9 @@ def test_sandwich_site_flops():
     assert b._site_group("qr: chol 40", 1) is None
 
 
-def test_traffic_record_is_tied_to_batch_and_source():
-    """Counter bytes are reported only for the batch they were taken at and
-    while the kernel's source is unchanged."""
+def test_traffic_record_is_tied_to_batch_precision_and_source():
+    """Counter bytes are reported only for the batch and precision they were
+    taken at and while the kernel's source is unchanged."""
     import hashlib
     import json
 
@@ -78,6 +78,9 @@ def test_traffic_record_is_tied_to_batch_and_source():
     for kernel, ent in data.items():
         with open(os.path.join(ROOT, ent["source"]), "rb") as fh:
             same = hashlib.sha256(fh.read()).hexdigest() == ent["source_sha256"]
-        assert b._traffic(kernel, ent["batch"]) == (ent["hbm_bytes_per_launch"] if same else None)
-        assert b._traffic(kernel, ent["batch"] + 1) is None
-    assert b._traffic("no_such_kernel", 512) is None
+        prec = ent["precision"]
+        other = "f32" if prec == "f64" else "f64"
+        assert b._traffic(kernel, ent["batch"], prec) == (ent["hbm_bytes_per_launch"] if same else None)
+        assert b._traffic(kernel, ent["batch"] + 1, prec) is None
+        assert b._traffic(kernel, ent["batch"], other) is None
+    assert b._traffic("no_such_kernel", 512, "f64") is None
