@@ -245,9 +245,12 @@ hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_
       snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=1 [gemm_f32_kernel<%d, %d, %s, %s, %s, %d>]", (long long)M,
                (long long)N, (long long)K, bm, bn, ty.a32 ? "float" : "double", ty.b32 ? "float" : "double",
                ty.c32 ? "float" : "double", wl);
-    else
-      snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=%d%s [gemm_f64_kernel<%d, %d, %d>]", (long long)M,
-               (long long)N, (long long)K, g.ksplit, run_flag ? " flagged" : "", bm, bn, wl);
+    else {
+      char kn[64];
+      gemm_f64_name(g, kn, sizeof kn);
+      snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=%d%s [%s]", (long long)M, (long long)N, (long long)K,
+               g.ksplit, run_flag ? " flagged" : "", kn);
+    }
     g_site = b;
   }
   LAUNCH(launch_gemm(g, st));

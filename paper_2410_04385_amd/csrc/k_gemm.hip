@@ -309,6 +309,285 @@ __global__ void splitk_reduce_kernel(GemmArgs g) {
   }
 }
 
+// Thin-N FP64 GEMM (32 < N <= 48, C = alpha A B + beta C; the launcher also
+// runs products thin in M here, transposed): a workgroup forms 64 MI rows of
+// C, each wave 16 MI of them (MI 16-row MFMA blocks) across all N columns.  A goes from global memory straight into the MFMA operand
+// registers with no LDS round trip.  Inside each 16-wide K chunk the K order
+// is permuted so that loads stay coalesced: with A k-fast a lane's four
+// values are consecutive in memory (k = 4 (lane / 16) + t at MFMA step t),
+// with A m-fast 16 lanes read 16 consecutive rows (k = 4 t + lane / 16).  B's
+// chunk is staged through a double-buffered LDS tile and read with the same
+// permutation, so every product pairs A(m, k) with B(k, n) as in the plain
+// sum.  A's loads run two chunks ahead in a ring of three register sets, B's
+// one chunk ahead (issued first, so that waiting for B leaves A in flight);
+// one barrier per chunk.  Columns 32..N-1 form a third 16-wide block
+// (FULL2, N > 40) or one or two 4-wide strips of the four-block 4 x 4 x 4
+// MFMA (N <= 40), whose A operand is the 16 x 16 x 4 one's.
+namespace {
+constexpr int kThinCh = 16, kThinLdb = 49;
+// 16-row blocks per wave: two for k-fast A (its loads are the longer-latency
+// ones; two blocks share each B fragment read), one for m-fast A (more waves
+// per SIMD)
+constexpr int thin_mi(bool ak) { return ak ? 2 : 1; }
+}
+
+template <int MI, bool AK, bool FULL2>
+__global__ __launch_bounds__(256) void gemm_thin_f64_kernel(GemmArgs g) {
+  constexpr int CH = kThinCh, LDB = kThinLdb, NB = FULL2 ? 3 : 2;
+  __shared__ double Bs[2][CH * LDB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, kq = lane >> 4;
+  const int ks = g.ksplit;
+  const int p = blockIdx.z / ks, kc = blockIdx.z - (blockIdx.z / ks) * ks;
+  if (g.run_flag != nullptr && g.run_flag[p * g.run_flag_stride] != g.run_when) return;
+  int64_t kchunk = (g.K + ks - 1) / ks;
+  kchunk = ((kchunk + CH - 1) / CH) * CH;
+  const int64_t kbeg = kc * kchunk;
+  const int64_t kend = std::min<int64_t>(g.K, kbeg + kchunk);
+  const int nch = kend > kbeg ? (int)((kend - kbeg + CH - 1) / CH) : 0;
+  const int64_t m0 = (int64_t)blockIdx.x * (64 * MI) + wave * (16 * MI);
+  const int M = (int)g.M, N = (int)g.N;  // the launcher checks that offsets fit in 32 bits
+
+  bool live[MI];
+#pragma unroll
+  for (int i = 0; i < MI; ++i) live[i] = m0 + 16 * i < g.M;
+  // columns 32..N-1 without FULL2: strips of 4 (one or two), wave-uniform
+  const int rem_cnt = FULL2 ? 0 : (N - 32 + 3) / 4;
+
+  // A: per-lane offsets of the row part (rows past M read row M-1; their
+  // results are never stored) and of the permuted k index at step t.
+  const double *Ab = g.A.ptr + p * g.A.bs + kbeg * g.A.cs;
+  const int ars = (int)g.A.rs, acs = (int)g.A.cs;
+  int a_row[MI];
+#pragma unroll
+  for (int i = 0; i < MI; ++i) {
+    const int row = (int)std::min<int64_t>(m0 + 16 * i + r, g.M - 1);
+    a_row[i] = AK ? row * ars : row;
+  }
+  auto kidx = [&](int t) { return AK ? 4 * kq + t : 4 * t + kq; };
+
+  // B: three elements per thread per chunk; k-fast B is walked along k.
+  const double *Bb = g.B.ptr + p * g.B.bs + kbeg * g.B.rs;
+  const bool b_kfast = g.B.rs == 1 && g.B.cs != 1;
+  const int brs = (int)g.B.rs;
+  int b_k[3], b_noff[3], b_loff[3];  // b_k: the k index, or CH for a column past N
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int e = tid + 256 * u;  // 768 = 16 x 48 elements
+    const int bk = b_kfast ? (e & 15) : e / 48, bn = b_kfast ? (e >> 4) : e % 48;
+    b_k[u] = bn < N ? bk : CH;
+    b_noff[u] = std::min(bn, N - 1) * (int)g.B.cs;
+    b_loff[u] = bk * LDB + bn;
+  }
+
+  // Every load of the chunk loop is unconditional and in bounds: indices past
+  // the valid K of a partial last chunk are clamped to its last valid k, and
+  // the values they bring are zeroed where they are used (B when parked, A
+  // before its MFMAs), so no load waits on a branch.
+  auto chunk_rem = [&](int c) { return (int)std::min<int64_t>(kend - kbeg - (int64_t)CH * c, CH); };
+  typedef double Frag[MI][4];
+  auto fetchA = [&](int c, Frag &dst) {
+    const double *base = Ab + (int64_t)(CH * c) * acs;
+    const int last = chunk_rem(c) - 1;
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int kk = std::min(kidx(t), last);
+        dst[i][t] = base[a_row[i] + (AK ? kk : kk * acs)];
+      }
+  };
+  double rb[3];
+  auto fetchB = [&](int c) {
+    const double *base = Bb + (int64_t)(CH * c) * g.B.rs;
+    const int last = chunk_rem(c) - 1;
+#pragma unroll
+    for (int u = 0; u < 3; ++u) rb[u] = base[std::min(b_k[u], last) * brs + b_noff[u]];
+  };
+  auto parkB = [&](int c, int buf) {
+    double *dst = Bs[buf];
+    const int rem = chunk_rem(c);
+#pragma unroll
+    for (int u = 0; u < 3; ++u) dst[b_loff[u]] = b_k[u] < rem ? rb[u] : 0.0;
+  };
+
+  d4_t acc[MI][NB];
+  double racc[MI][2];
+#pragma unroll
+  for (int i = 0; i < MI; ++i) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = d4_t{0, 0, 0, 0};
+    racc[i][0] = racc[i][1] = 0.0;
+  }
+  auto mult = [&](int s, const Frag &a) {
+    const double *bs = Bs[s & 1];
+    const int rem = chunk_rem(s);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double *bp = bs + kidx(t) * LDB;
+      double bv[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) bv[j] = bp[16 * j + r];
+      double x[2];
+      if constexpr (!FULL2) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) x[q] = bp[32 + 4 * q + (lane & 3)];
+      }
+      const bool kin = kidx(t) < rem;
+#pragma unroll
+      for (int i = 0; i < MI; ++i) {
+        if (!live[i]) continue;  // wave-uniform
+        const double av = kin ? a[i][t] : 0.0;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[i][j] = mfma16(av, bv[j], acc[i][j]);
+        if constexpr (!FULL2) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+            if (q < rem_cnt) racc[i][q] = mfma4(av, x[q], racc[i][q]);
+        }
+      }
+    }
+  };
+
+  Frag a0, a1, a2;
+  if (nch > 0) {
+    fetchB(0);
+    fetchA(0, a0);
+    fetchA(std::min(1, nch - 1), a1);
+    parkB(0, 0);
+  }
+  __syncthreads();
+  // chunk s: B(s + 1) and A(s + 2) are fetched (the last chunk again past
+  // the end), chunk s is multiplied, B(s + 1) is parked in the other LDS
+  // buffer, one barrier
+  auto step = [&](int s, const Frag &cur, Frag &ahead) {
+    const int c1 = std::min(s + 1, nch - 1);
+    fetchB(c1);
+    fetchA(std::min(s + 2, nch - 1), ahead);
+    mult(s, cur);
+    parkB(c1, (s + 1) & 1);
+    __syncthreads();
+  };
+  for (int s = 0; s < nch; s += 3) {
+    step(s, a0, a2);
+    if (s + 1 >= nch) break;
+    step(s + 1, a1, a0);
+    if (s + 2 >= nch) break;
+    step(s + 2, a2, a1);
+  }
+
+  auto strip_at = [&](int q, int i, int64_t *gm, int *gn) {
+    *gm = m0 + 16 * i + 4 * ((lane >> 2) & 3) + kq;
+    *gn = 32 + 4 * q + (lane & 3);
+  };
+  if (ks == 1) {
+    double *Cb = g.C.ptr + p * g.C.bs;
+#pragma unroll
+    for (int i = 0; i < MI; ++i) {
+      if (!live[i]) continue;
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t gm = m0 + 16 * i + kq + 4 * v;
+          const int gn = 16 * j + r;
+          if (gm < M && gn < N) {
+            double *cp = Cb + gm * g.C.rs + gn * g.C.cs;
+            double y = g.alpha * acc[i][j][v];
+            if (g.beta != 0.0) y += g.beta * (*cp);
+            *cp = y;
+          }
+        }
+      if constexpr (!FULL2) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          int64_t gm;
+          int gn;
+          strip_at(q, i, &gm, &gn);
+          if (q < rem_cnt && gm < M && gn < N) {
+            double *cp = Cb + gm * g.C.rs + gn * g.C.cs;
+            double y = g.alpha * racc[i][q];
+            if (g.beta != 0.0) y += g.beta * (*cp);
+            *cp = y;
+          }
+        }
+      }
+    }
+  } else {
+    double *Pb = g.part + ((int64_t)p * ks + kc) * g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < MI; ++i) {
+      if (!live[i]) continue;
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t gm = m0 + 16 * i + kq + 4 * v;
+          const int gn = 16 * j + r;
+          if (gm < M && gn < N) Pb[g.part_t ? gn * g.M + gm : gm * N + gn] = g.alpha * acc[i][j][v];
+        }
+      if constexpr (!FULL2) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          int64_t gm;
+          int gn;
+          strip_at(q, i, &gm, &gn);
+          if (q < rem_cnt && gm < M && gn < N) Pb[g.part_t ? gn * g.M + gm : gm * N + gn] = g.alpha * racc[i][q];
+        }
+      }
+    }
+  }
+}
+
+// The thin kernel's variant for g (bit 1: A k-fast, bit 0: a full third
+// column block), or -1 when it does not apply: FP64 operands, 32 < N <= 48
+// with more than 32 rows, A with a unit stride, and every per-pair offset
+// within 32 bits.
+static int thin_variant(const GemmArgs &g) {
+  if (g.prec || g.a_f32 || g.b_f32 || g.c_f32) return -1;
+  if (!(g.N > 32 && g.N <= 48 && g.M > 32)) return -1;
+  const bool ak = g.A.cs == 1;
+  if (!ak && g.A.rs != 1) return -1;
+  if (g.A.rs < 0 || g.A.cs < 0 || g.B.rs < 0 || g.B.cs < 0) return -1;
+  const int64_t lim = (int64_t)1 << 30;
+  const int64_t kpad = g.K + kThinCh;
+  if (g.M >= lim || (g.M - 1) * g.A.rs + kpad * g.A.cs >= lim) return -1;
+  if (kpad * g.B.rs + 48 * g.B.cs >= lim) return -1;
+  return (ak ? 2 : 0) | (g.N > 40 ? 1 : 0);
+}
+
+// Arguments and variant of the thin kernel for g: g itself when it is thin
+// in N; for 32 < M <= 48 and N > 48 the transposed product C^T = B^T A^T
+// (operands and C with their strides swapped, split-K partials still written
+// in g's M x N layout); -1 when neither applies.
+static int thin_args(const GemmArgs &g, GemmArgs *t) {
+  *t = g;
+  int v = thin_variant(g);
+  if (v >= 0 || !(g.M > 32 && g.M <= 48 && g.N > 48)) return v;
+  t->A = CMat{g.B.ptr, g.B.cs, g.B.rs, g.B.bs};
+  t->B = CMat{g.A.ptr, g.A.cs, g.A.rs, g.A.bs};
+  t->C = Mat{g.C.ptr, g.C.cs, g.C.rs, g.C.bs};
+  t->M = g.N;
+  t->N = g.M;
+  t->part_t = 1;
+  v = thin_variant(*t);
+  if (v < 0) *t = g;
+  return v;
+}
+
+void gemm_f64_name(const GemmArgs &g, char *buf, size_t n) {
+  GemmArgs t;
+  const int v = thin_args(g, &t);
+  if (v >= 0) {
+    snprintf(buf, n, "gemm_thin_f64_kernel<%d, %s, %s>", thin_mi(v & 2), (v & 2) ? "true" : "false",
+             (v & 1) ? "true" : "false");
+    return;
+  }
+  int bm, bn, wl;
+  gemm_tile(g.M, g.N, &bm, &bn, &wl);
+  snprintf(buf, n, "gemm_f64_kernel<%d, %d, %d>", bm, bn, wl);
+}
+
 // Tile shape: 32 rows or columns when that side of C is at most 32 wide
 // (less padding for the thin operands of the sweep), else 64.
 void gemm_tile(int64_t M, int64_t N, int *bm, int *bn, int *wl) {
@@ -341,7 +620,16 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
   gemm_tile(a.M, a.N, &bm, &bn, &wl);
   if (a.prec) a.ksplit = 1;  // the FP32 path writes its result directly
   dim3 grid((unsigned)((a.M + bm - 1) / bm), (unsigned)((a.N + bn - 1) / bn), (unsigned)(a.batch * a.ksplit));
-  if (!a.prec) {
+  GemmArgs t;
+  const int thin = thin_args(a, &t);
+  if (thin >= 0) {
+    const int rows = 64 * thin_mi(thin & 2);
+    dim3 tg((unsigned)((t.M + rows - 1) / rows), 1, (unsigned)(t.batch * t.ksplit));
+    if (thin == 3) gemm_thin_f64_kernel<thin_mi(true), true, true><<<tg, 256, 0, s>>>(t);
+    else if (thin == 2) gemm_thin_f64_kernel<thin_mi(true), true, false><<<tg, 256, 0, s>>>(t);
+    else if (thin == 1) gemm_thin_f64_kernel<thin_mi(false), false, true><<<tg, 256, 0, s>>>(t);
+    else gemm_thin_f64_kernel<thin_mi(false), false, false><<<tg, 256, 0, s>>>(t);
+  } else if (!a.prec) {
     if (a.a_f32 || a.b_f32 || a.c_f32) return hipErrorInvalidValue;
     if (bm == 64 && bn == 64) {
       if (wl == 1) gemm_f64_kernel<64, 64, 1><<<grid, 256, 0, s>>>(a);

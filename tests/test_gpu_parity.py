@@ -120,6 +120,8 @@ CASES = [
     ([17, 33, 65, 9], 6, 7, 30),      # ragged tiles in every kernel
     ([5, 6, 7, 6, 5], 19, 17, 23),    # bond ranks 17..20: 4 x 4 x 4 remainder blocks, ragged chunks
     ([4, 8, 8, 8, 4], 20, 18, 40),    # same, r != s on both sandwich sides
+    ([7, 9, 8, 7], 7, 7, 44),         # a 44-wide frame: a full third column block in the thin GEMM
+    ([6, 9, 7, 5], 7, 6, 35),         # a 35-wide frame: one 4-wide strip in the thin GEMM
 ]
 
 
