@@ -567,6 +567,33 @@ def test_many_pairs_fused_gram_cholesky_wide_frames(ell):
         assert tt.rel_err(got, ref) <= TOL, b
 
 
+def test_many_pairs_fused_gram_cholesky_long_frames():
+    """34 pairs whose frames have up to 640 rows (many row batches per
+    fused Gram + Cholesky block): every pair matches the oracle, also the two
+    with zero columns in their second factor, whose rank-deficient frames go
+    to the Householder fallback."""
+    B = 34
+    n = [16] * 5
+    pairs = [wk.spectral_pair(6000 + b, d=5, n=16, rx=7, ry=8) for b in range(B)]
+    for b in (5, 20):
+        y, z = pairs[b]
+        z = [c.copy() for c in z]
+        for c in z[:-1]:
+            c[:, :, 1:] = 0.0
+        pairs[b] = (y, z)
+    ys = [p[0] for p in pairs]
+    zs = [p[1] for p in pairs]
+    l = _ell(ys[0], zs[0], 40)
+    R = wk.gaussian_sketch(np.random.default_rng(40), n, l)
+    _say(f"hatt_recompress batch={B} ell={l} max_rank=20 (long frames, two rank-deficient pairs)")
+    res = _gpu_hatt(ys, zs, 40, sketch=H.TT.from_cores(R), max_rank=20)
+    for b in range(B):
+        ref = rounding.tt_round(ohatt.hatt(ys[b], zs[b], R), max_rank=20)
+        got = res.train(b)
+        assert tt.ranks(got) == tt.ranks(ref), b
+        assert tt.rel_err(got, ref) <= TOL, b
+
+
 def test_many_pairs_fused_gram_cholesky():
     """40 pairs in one batch (the CholeskyQR2 Gram matrices are then formed
     inside the factorisation kernel): every pair matches the oracle, also
