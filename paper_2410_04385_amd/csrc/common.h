@@ -153,8 +153,8 @@ hipError_t launch_splitk_reduce(const GemmArgs &g, hipStream_t s);
 // Output tile (BM x BN) and wave layout (0: 2 x 2, 1: waves along M, 2: along
 // N) the launcher uses for an M x N product.
 void gemm_tile(int64_t M, int64_t N, int *bm, int *bn, int *wl);
-// Name of the FP64 kernel launch_gemm runs for g, as a kernel trace lists it.
-void gemm_f64_name(const GemmArgs &g, char *buf, size_t n);
+// Name of the kernel launch_gemm runs for g, as a kernel trace lists it.
+void gemm_kernel_name(const GemmArgs &g, char *buf, size_t n);
 // Layout of the split-K partials: pair p, chunk t at part + (p * ksplit + t) * M * N.
 
 // ---- TSQR (k_qr.hip) -------------------------------------------------------

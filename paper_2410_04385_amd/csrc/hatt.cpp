@@ -238,19 +238,10 @@ hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_
   g.part = gc.part;
   if (ks_out != nullptr) *ks_out = g.ksplit;
   if (g_prof.on) {
-    char b[160];
-    int bm = 0, bn = 0, wl = 0;
-    gemm_tile(M, N, &bm, &bn, &wl);
-    if (ty.prec)
-      snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=1 [gemm_f32_kernel<%d, %d, %s, %s, %s, %d>]", (long long)M,
-               (long long)N, (long long)K, bm, bn, ty.a32 ? "float" : "double", ty.b32 ? "float" : "double",
-               ty.c32 ? "float" : "double", wl);
-    else {
-      char kn[64];
-      gemm_f64_name(g, kn, sizeof kn);
-      snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=%d%s [%s]", (long long)M, (long long)N, (long long)K,
-               g.ksplit, run_flag ? " flagged" : "", kn);
-    }
+    char b[200], kn[96];
+    gemm_kernel_name(g, kn, sizeof kn);
+    snprintf(b, sizeof b, "gemm %lldx%lldx%lld ks=%d%s [%s]", (long long)M, (long long)N, (long long)K,
+             g.ksplit, run_flag ? " flagged" : "", kn);
     g_site = b;
   }
   LAUNCH(launch_gemm(g, st));

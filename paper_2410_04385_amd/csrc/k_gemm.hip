@@ -331,10 +331,15 @@ constexpr int kThinCh = 16, kThinLdb = 49;
 constexpr int thin_mi(bool ak) { return ak ? 2 : 1; }
 }
 
-template <int MI, bool AK, bool FULL2>
-__global__ __launch_bounds__(256) void gemm_thin_f64_kernel(GemmArgs g) {
+// CT is the compute type (FP64, or FP32 matrix cores accumulating in FP32,
+// always with a full third column block); TA, TB, TC are the storage types.
+template <int MI, bool AK, bool FULL2, typename CT, typename TA, typename TB, typename TC>
+__device__ __forceinline__ void thin_body(const GemmArgs &g) {
+  constexpr bool F64 = std::is_same<CT, double>::value;
+  static_assert(F64 || FULL2, "the 4 x 4 x 4 strips are FP64 only");
+  using acc_t = typename std::conditional<F64, d4_t, f4_t>::type;
   constexpr int CH = kThinCh, LDB = kThinLdb, NB = FULL2 ? 3 : 2;
-  __shared__ double Bs[2][CH * LDB];
+  __shared__ CT Bs[2][CH * LDB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = lane & 15, kq = lane >> 4;
   const int ks = g.ksplit;
@@ -356,7 +361,7 @@ __global__ __launch_bounds__(256) void gemm_thin_f64_kernel(GemmArgs g) {
 
   // A: per-lane offsets of the row part (rows past M read row M-1; their
   // results are never stored) and of the permuted k index at step t.
-  const double *Ab = g.A.ptr + p * g.A.bs + kbeg * g.A.cs;
+  const TA *Ab = reinterpret_cast<const TA *>(static_cast<const void *>(g.A.ptr)) + p * g.A.bs + kbeg * g.A.cs;
   const int ars = (int)g.A.rs, acs = (int)g.A.cs;
   int a_row[MI];
 #pragma unroll
@@ -367,7 +372,7 @@ __global__ __launch_bounds__(256) void gemm_thin_f64_kernel(GemmArgs g) {
   auto kidx = [&](int t) { return AK ? 4 * kq + t : 4 * t + kq; };
 
   // B: three elements per thread per chunk; k-fast B is walked along k.
-  const double *Bb = g.B.ptr + p * g.B.bs + kbeg * g.B.rs;
+  const TB *Bb = reinterpret_cast<const TB *>(static_cast<const void *>(g.B.ptr)) + p * g.B.bs + kbeg * g.B.rs;
   const bool b_kfast = g.B.rs == 1 && g.B.cs != 1;
   const int brs = (int)g.B.rs;
   int b_k[3], b_noff[3], b_loff[3];  // b_k: the k index, or CH for a column past N
@@ -385,65 +390,65 @@ __global__ __launch_bounds__(256) void gemm_thin_f64_kernel(GemmArgs g) {
   // the values they bring are zeroed where they are used (B when parked, A
   // before its MFMAs), so no load waits on a branch.
   auto chunk_rem = [&](int c) { return (int)std::min<int64_t>(kend - kbeg - (int64_t)CH * c, CH); };
-  typedef double Frag[MI][4];
+  typedef CT Frag[MI][4];
   auto fetchA = [&](int c, Frag &dst) {
-    const double *base = Ab + (int64_t)(CH * c) * acs;
+    const TA *base = Ab + (int64_t)(CH * c) * acs;
     const int last = chunk_rem(c) - 1;
 #pragma unroll
     for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int kk = std::min(kidx(t), last);
-        dst[i][t] = base[a_row[i] + (AK ? kk : kk * acs)];
+        dst[i][t] = (CT)base[a_row[i] + (AK ? kk : kk * acs)];
       }
   };
-  double rb[3];
+  TB rb[3];
   auto fetchB = [&](int c) {
-    const double *base = Bb + (int64_t)(CH * c) * g.B.rs;
+    const TB *base = Bb + (int64_t)(CH * c) * g.B.rs;
     const int last = chunk_rem(c) - 1;
 #pragma unroll
     for (int u = 0; u < 3; ++u) rb[u] = base[std::min(b_k[u], last) * brs + b_noff[u]];
   };
   auto parkB = [&](int c, int buf) {
-    double *dst = Bs[buf];
+    CT *dst = Bs[buf];
     const int rem = chunk_rem(c);
 #pragma unroll
-    for (int u = 0; u < 3; ++u) dst[b_loff[u]] = b_k[u] < rem ? rb[u] : 0.0;
+    for (int u = 0; u < 3; ++u) dst[b_loff[u]] = b_k[u] < rem ? (CT)rb[u] : (CT)0;
   };
 
-  d4_t acc[MI][NB];
+  acc_t acc[MI][NB];
   double racc[MI][2];
 #pragma unroll
   for (int i = 0; i < MI; ++i) {
 #pragma unroll
-    for (int j = 0; j < NB; ++j) acc[i][j] = d4_t{0, 0, 0, 0};
+    for (int j = 0; j < NB; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
     racc[i][0] = racc[i][1] = 0.0;
   }
   auto mult = [&](int s, const Frag &a) {
-    const double *bs = Bs[s & 1];
+    const CT *bs = Bs[s & 1];
     const int rem = chunk_rem(s);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const double *bp = bs + kidx(t) * LDB;
-      double bv[NB];
+      const CT *bp = bs + kidx(t) * LDB;
+      CT bv[NB];
 #pragma unroll
       for (int j = 0; j < NB; ++j) bv[j] = bp[16 * j + r];
-      double x[2];
+      double x[2] = {0.0, 0.0};
       if constexpr (!FULL2) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) x[q] = bp[32 + 4 * q + (lane & 3)];
+        for (int q = 0; q < 2; ++q) x[q] = (double)bp[32 + 4 * q + (lane & 3)];
       }
       const bool kin = kidx(t) < rem;
 #pragma unroll
       for (int i = 0; i < MI; ++i) {
         if (!live[i]) continue;  // wave-uniform
-        const double av = kin ? a[i][t] : 0.0;
+        const CT av = kin ? a[i][t] : (CT)0;
 #pragma unroll
         for (int j = 0; j < NB; ++j) acc[i][j] = mfma16(av, bv[j], acc[i][j]);
         if constexpr (!FULL2) {
 #pragma unroll
           for (int q = 0; q < 2; ++q)
-            if (q < rem_cnt) racc[i][q] = mfma4(av, x[q], racc[i][q]);
+            if (q < rem_cnt) racc[i][q] = mfma4((double)av, x[q], racc[i][q]);
         }
       }
     }
@@ -481,7 +486,7 @@ __global__ __launch_bounds__(256) void gemm_thin_f64_kernel(GemmArgs g) {
     *gn = 32 + 4 * q + (lane & 3);
   };
   if (ks == 1) {
-    double *Cb = g.C.ptr + p * g.C.bs;
+    TC *Cb = reinterpret_cast<TC *>(static_cast<void *>(g.C.ptr)) + p * g.C.bs;
 #pragma unroll
     for (int i = 0; i < MI; ++i) {
       if (!live[i]) continue;
@@ -489,13 +494,13 @@ __global__ __launch_bounds__(256) void gemm_thin_f64_kernel(GemmArgs g) {
       for (int j = 0; j < NB; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int64_t gm = m0 + 16 * i + kq + 4 * v;
+          const int64_t gm = m0 + 16 * i + mfma_row<CT>(kq, v);
           const int gn = 16 * j + r;
           if (gm < M && gn < N) {
-            double *cp = Cb + gm * g.C.rs + gn * g.C.cs;
-            double y = g.alpha * acc[i][j][v];
-            if (g.beta != 0.0) y += g.beta * (*cp);
-            *cp = y;
+            TC *cp = Cb + gm * g.C.rs + gn * g.C.cs;
+            double y = g.alpha * (double)acc[i][j][v];
+            if (g.beta != 0.0) y += g.beta * (double)(*cp);
+            *cp = (TC)y;
           }
         }
       if constexpr (!FULL2) {
@@ -505,15 +510,15 @@ __global__ __launch_bounds__(256) void gemm_thin_f64_kernel(GemmArgs g) {
           int gn;
           strip_at(q, i, &gm, &gn);
           if (q < rem_cnt && gm < M && gn < N) {
-            double *cp = Cb + gm * g.C.rs + gn * g.C.cs;
+            TC *cp = Cb + gm * g.C.rs + gn * g.C.cs;
             double y = g.alpha * racc[i][q];
-            if (g.beta != 0.0) y += g.beta * (*cp);
-            *cp = y;
+            if (g.beta != 0.0) y += g.beta * (double)(*cp);
+            *cp = (TC)y;
           }
         }
       }
     }
-  } else {
+  } else if constexpr (F64) {  // split-K partials (the FP32 form runs unsplit)
     double *Pb = g.part + ((int64_t)p * ks + kc) * g.M * g.N;
 #pragma unroll
     for (int i = 0; i < MI; ++i) {
@@ -522,7 +527,7 @@ __global__ __launch_bounds__(256) void gemm_thin_f64_kernel(GemmArgs g) {
       for (int j = 0; j < NB; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int64_t gm = m0 + 16 * i + kq + 4 * v;
+          const int64_t gm = m0 + 16 * i + mfma_row<CT>(kq, v);
           const int gn = 16 * j + r;
           if (gm < M && gn < N) Pb[g.part_t ? gn * g.M + gm : gm * N + gn] = g.alpha * acc[i][j][v];
         }
@@ -539,12 +544,28 @@ __global__ __launch_bounds__(256) void gemm_thin_f64_kernel(GemmArgs g) {
   }
 }
 
+template <int MI, bool AK, bool FULL2>
+__global__ __launch_bounds__(256) void gemm_thin_f64_kernel(GemmArgs g) {
+  thin_body<MI, AK, FULL2, double, double, double, double>(g);
+}
+
+template <int MI, bool AK, typename TA, typename TB, typename TC>
+__global__ __launch_bounds__(256) void gemm_thin_f32_kernel(GemmArgs g) {
+  thin_body<MI, AK, true, float, TA, TB, TC>(g);
+}
+
 // The thin kernel's variant for g (bit 1: A k-fast, bit 0: a full third
-// column block), or -1 when it does not apply: FP64 operands, 32 < N <= 48
-// with more than 32 rows, A with a unit stride, and every per-pair offset
-// within 32 bits.
+// column block, always set for the FP32 form), or -1 when it does not apply:
+// 32 < N <= 48 with more than 32 rows, A with a unit stride, every per-pair
+// offset within 32 bits, and FP64 operands or one of the FP32 path's
+// storage combinations (unsplit).
 static int thin_variant(const GemmArgs &g) {
-  if (g.prec || g.a_f32 || g.b_f32 || g.c_f32) return -1;
+  if (g.prec) {
+    const int combo = g.a_f32 * 4 + g.b_f32 * 2 + g.c_f32;
+    if ((combo != 5 && combo != 2 && combo != 7) || g.ksplit > 1) return -1;
+  } else if (g.a_f32 || g.b_f32 || g.c_f32) {
+    return -1;
+  }
   if (!(g.N > 32 && g.N <= 48 && g.M > 32)) return -1;
   const bool ak = g.A.cs == 1;
   if (!ak && g.A.rs != 1) return -1;
@@ -553,13 +574,13 @@ static int thin_variant(const GemmArgs &g) {
   const int64_t kpad = g.K + kThinCh;
   if (g.M >= lim || (g.M - 1) * g.A.rs + kpad * g.A.cs >= lim) return -1;
   if (kpad * g.B.rs + 48 * g.B.cs >= lim) return -1;
-  return (ak ? 2 : 0) | (g.N > 40 ? 1 : 0);
+  return (ak ? 2 : 0) | ((g.prec || g.N > 40) ? 1 : 0);
 }
 
 // Arguments and variant of the thin kernel for g: g itself when it is thin
 // in N; for 32 < M <= 48 and N > 48 the transposed product C^T = B^T A^T
-// (operands and C with their strides swapped, split-K partials still written
-// in g's M x N layout); -1 when neither applies.
+// (operands, their storage types and C with their strides swapped, split-K
+// partials still written in g's M x N layout); -1 when neither applies.
 static int thin_args(const GemmArgs &g, GemmArgs *t) {
   *t = g;
   int v = thin_variant(g);
@@ -567,6 +588,8 @@ static int thin_args(const GemmArgs &g, GemmArgs *t) {
   t->A = CMat{g.B.ptr, g.B.cs, g.B.rs, g.B.bs};
   t->B = CMat{g.A.ptr, g.A.cs, g.A.rs, g.A.bs};
   t->C = Mat{g.C.ptr, g.C.cs, g.C.rs, g.C.bs};
+  t->a_f32 = g.b_f32;
+  t->b_f32 = g.a_f32;
   t->M = g.N;
   t->N = g.M;
   t->part_t = 1;
@@ -575,17 +598,28 @@ static int thin_args(const GemmArgs &g, GemmArgs *t) {
   return v;
 }
 
-void gemm_f64_name(const GemmArgs &g, char *buf, size_t n) {
+static const char *tname(int f32) { return f32 ? "float" : "double"; }
+
+void gemm_kernel_name(const GemmArgs &g, char *buf, size_t n) {
   GemmArgs t;
   const int v = thin_args(g, &t);
+  const char *ak = (v & 2) ? "true" : "false";
+  if (v >= 0 && !g.prec) {
+    snprintf(buf, n, "gemm_thin_f64_kernel<%d, %s, %s>", thin_mi(v & 2), ak, (v & 1) ? "true" : "false");
+    return;
+  }
   if (v >= 0) {
-    snprintf(buf, n, "gemm_thin_f64_kernel<%d, %s, %s>", thin_mi(v & 2), (v & 2) ? "true" : "false",
-             (v & 1) ? "true" : "false");
+    snprintf(buf, n, "gemm_thin_f32_kernel<%d, %s, %s, %s, %s>", thin_mi(v & 2), ak, tname(t.a_f32),
+             tname(t.b_f32), tname(t.c_f32));
     return;
   }
   int bm, bn, wl;
   gemm_tile(g.M, g.N, &bm, &bn, &wl);
-  snprintf(buf, n, "gemm_f64_kernel<%d, %d, %d>", bm, bn, wl);
+  if (g.prec)
+    snprintf(buf, n, "gemm_f32_kernel<%d, %d, %s, %s, %s, %d>", bm, bn, tname(g.a_f32), tname(g.b_f32),
+             tname(g.c_f32), wl);
+  else
+    snprintf(buf, n, "gemm_f64_kernel<%d, %d, %d>", bm, bn, wl);
 }
 
 // Tile shape: 32 rows or columns when that side of C is at most 32 wide
@@ -625,7 +659,18 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
   if (thin >= 0) {
     const int rows = 64 * thin_mi(thin & 2);
     dim3 tg((unsigned)((t.M + rows - 1) / rows), 1, (unsigned)(t.batch * t.ksplit));
-    if (thin == 3) gemm_thin_f64_kernel<thin_mi(true), true, true><<<tg, 256, 0, s>>>(t);
+    if (t.prec) {
+      const int combo = t.a_f32 * 4 + t.b_f32 * 2 + t.c_f32;
+#define HATT_THIN32(TA, TB, TC)                                                               \
+  do {                                                                                        \
+    if (thin & 2) gemm_thin_f32_kernel<thin_mi(true), true, TA, TB, TC><<<tg, 256, 0, s>>>(t); \
+    else gemm_thin_f32_kernel<thin_mi(false), false, TA, TB, TC><<<tg, 256, 0, s>>>(t);        \
+  } while (0)
+      if (combo == 5) HATT_THIN32(float, double, float);
+      else if (combo == 2) HATT_THIN32(double, float, double);
+      else HATT_THIN32(float, float, float);
+#undef HATT_THIN32
+    } else if (thin == 3) gemm_thin_f64_kernel<thin_mi(true), true, true><<<tg, 256, 0, s>>>(t);
     else if (thin == 2) gemm_thin_f64_kernel<thin_mi(true), true, false><<<tg, 256, 0, s>>>(t);
     else if (thin == 1) gemm_thin_f64_kernel<thin_mi(false), false, true><<<tg, 256, 0, s>>>(t);
     else gemm_thin_f64_kernel<thin_mi(false), false, false><<<tg, 256, 0, s>>>(t);
