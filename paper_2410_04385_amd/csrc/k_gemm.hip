@@ -309,10 +309,12 @@ __global__ void splitk_reduce_kernel(GemmArgs g) {
   }
 }
 
-// Thin-N FP64 GEMM (32 < N <= 48, C = alpha A B + beta C; the launcher also
-// runs products thin in M here, transposed): a workgroup forms 64 MI rows of
-// C, each wave 16 MI of them (MI 16-row MFMA blocks) across all N columns.  A goes from global memory straight into the MFMA operand
-// registers with no LDS round trip.  Inside each 16-wide K chunk the K order
+// Thin-N GEMM (32 < N <= 48, C = alpha A B + beta C; FP64, or FP32 matrix
+// cores for the FP32 range finding; the launcher also runs products thin in
+// M here, transposed): a workgroup forms 64 MI rows of C, each wave 16 MI of
+// them (MI 16-row MFMA blocks) across all N columns.  A goes from global
+// memory straight into the MFMA operand registers with no LDS round trip.
+// Inside each 16-wide K chunk the K order
 // is permuted so that loads stay coalesced: with A k-fast a lane's four
 // values are consecutive in memory (k = 4 (lane / 16) + t at MFMA step t),
 // with A m-fast 16 lanes read 16 consecutive rows (k = 4 t + lane / 16).  B's
