@@ -109,24 +109,36 @@ def _roofline(report, batch, steps, perfmodel, precision="f64"):
         acc["bytes"] += nb * calls
     if not groups:
         return None
-    dom = max(groups, key=lambda k: groups[k]["ms"])
-    gr = groups[dom]
-    avg_s = gr["ms"] / gr["calls"] / 1000.0
-    per_launch = gr["flops"] / gr["calls"]
-    bytes_launch = gr["bytes"] / gr["calls"]
-    tflops = per_launch / avg_s / 1e12
-    gbs = bytes_launch / avg_s / 1e9
-    bound = gr["bound"]
-    if bound == "mfma" and bytes_launch > 0:
-        # roofline: below the ridge (peak flops / peak bandwidth, ~9.8 flop/B
-        # in FP64) the compulsory bytes, not the matrix cores, set the bound
-        ridge = perfmodel.PEAK_FP64_TFLOPS * 1e12 / (perfmodel.PEAK_HBM_GBS * 1e9)
-        if per_launch / bytes_launch < ridge:
-            bound = "hbm"
-    if bound == "hbm":
-        achieved, peak, unit = gbs, perfmodel.PEAK_HBM_GBS, "GB/s"
-    else:
-        achieved, peak, unit = tflops, perfmodel.PEAK_FP64_TFLOPS, "TFLOP/s"
+
+    def figures(kernel):
+        gr = groups[kernel]
+        avg_s = gr["ms"] / gr["calls"] / 1000.0
+        per_launch = gr["flops"] / gr["calls"]
+        bytes_launch = gr["bytes"] / gr["calls"]
+        tflops = per_launch / avg_s / 1e12
+        gbs = bytes_launch / avg_s / 1e9
+        bound = gr["bound"]
+        if bound == "mfma" and bytes_launch > 0:
+            # roofline: below the ridge (peak flops / peak bandwidth, ~9.8
+            # flop/B in FP64) the compulsory bytes, not the matrix cores, set
+            # the bound
+            ridge = perfmodel.PEAK_FP64_TFLOPS * 1e12 / (perfmodel.PEAK_HBM_GBS * 1e9)
+            if per_launch / bytes_launch < ridge:
+                bound = "hbm"
+        if bound == "hbm":
+            achieved, peak, unit = gbs, perfmodel.PEAK_HBM_GBS, "GB/s"
+        else:
+            achieved, peak, unit = tflops, perfmodel.PEAK_FP64_TFLOPS, "TFLOP/s"
+        return gr, avg_s, per_launch, bytes_launch, tflops, gbs, bound, achieved, peak, unit
+
+    order = sorted(groups, key=lambda k: -groups[k]["ms"])
+    dom = order[0]
+    gr, avg_s, per_launch, bytes_launch, tflops, gbs, bound, achieved, peak, unit = figures(dom)
+    nxt = []
+    for k in order[1:4]:
+        g2, _, _, _, _, _, b2, a2, p2, u2 = figures(k)
+        nxt.append({"kernel": k, "bound": b2, "achieved": a2, "peak": p2, "unit": u2, "frac": a2 / p2,
+                    "ms_per_step": g2["ms"] / steps})
     return {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak, "traffic": _traffic(dom, batch, precision),
             "avg_launch_us": 1e6 * avg_s, "launches_per_step": gr["calls"] / steps,
@@ -134,7 +146,8 @@ def _roofline(report, batch, steps, perfmodel, precision="f64"):
             "algorithmic_bytes_per_launch": bytes_launch,
             "algorithmic_intensity_flop_per_byte": per_launch / bytes_launch if bytes_launch else None,
             "algorithmic_TFLOPs": tflops,
-            "algorithmic_GBs": gbs}
+            "algorithmic_GBs": gbs,
+            "next_kernels": nxt}
 
 
 def _traffic(kernel, batch, precision):

@@ -42,6 +42,12 @@ def test_roofline_groups_sites_by_compiled_kernel():
     assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
     assert roof["achieved"] == pytest.approx(nbytes / 0.110 / 1e9)
     assert roof["frac"] == pytest.approx(roof["achieved"] / 8000.0)
+    # the runner-up kernels, by time: the VALU sandwich (10 ms per step)
+    nxt = roof["next_kernels"]
+    assert [k["kernel"] for k in nxt] == ["sandwich_reg_kernel<24, 2, false>"]
+    assert nxt[0]["ms_per_step"] == pytest.approx(10.0)
+    sw_flops = 2.0 * 32 * 40 * (20 * 20 * 20 + 20 * 20 * 20) * 128 * 20
+    assert nxt[0]["unit"] == "TFLOP/s" and nxt[0]["achieved"] == pytest.approx(sw_flops / 0.100 / 1e12)
 
 
 def test_roofline_above_the_ridge_is_matrix_core_bound():
