@@ -43,8 +43,9 @@ def _parse():
     ap.add_argument("--rp-train", type=int, default=128, help="rankpred: training recompressions")
     ap.add_argument("--rp-eval", type=int, default=24, help="rankpred: fresh pairs evaluated")
     ap.add_argument("--rp-margin", type=float, default=0.15, help="rankpred: width safety margin")
-    ap.add_argument("--workload", choices=["spectral", "batched", "rankpred"], default="spectral",
-                    help="spectral: the metric's workload; batched: the 512-pair uneven workload (own JSON line)")
+    ap.add_argument("--workload", choices=["trig", "spectral", "batched", "rankpred"], default="trig",
+                    help="trig: the metric's tol-1e-8 workload (u2, u3 on the 256^3 grid); spectral: 512 "
+                         "order-20 pairs truncated to rank 30; batched: 512 uneven pairs (own JSON lines)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (reference dispatch for "
                          "hardware byte counters)")
@@ -216,6 +217,154 @@ def _bench_batched(args, torch, wk, H) -> int:
     return 0
 
 
+def _full_np(cores):
+    """Full tensor of a TT (host numpy cores), for the pointwise error check
+    against the closed-form product."""
+    acc = cores[0].reshape(-1, cores[0].shape[2])
+    for c in cores[1:]:
+        acc = (acc @ c.reshape(c.shape[0], -1)).reshape(-1, c.shape[2])
+    return acc.reshape(-1)
+
+
+def _bench_trig(args, torch, wk, H, perfmodel) -> int:
+    """The Allen-Cahn-shaped nonlinearity on the 256^3 periodic grid: u has
+    ranks 40 (40 separable sin/cos products); one step recompresses
+    u2 = u (.) u, then u3 = u2 (.) u, each with a seeded Gaussian sketch and
+    TT-Rounding at tol 1e-8.  The kept ranks of u2 are read back (one host
+    synchronisation) so that u3 runs on the compact rank-81 factor."""
+    cfg = wk.WORKLOADS["trig"]
+    tol, l2, l3 = cfg["tol"], cfg["ell2"], cfg["ell3"]
+    s2, s3 = 21, 22
+    say = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)  # noqa: E731
+    u = wk.trig_u(11, n=cfg["n"], terms=2 * cfg["nfreq"], nfreq=cfg["nfreq"])
+    U = H.TT.from_cores(u)
+    p2 = H.plan(U, U, l2, tol=tol, seed=s2, precision=args.precision)
+    ws2 = torch.empty(p2["ws_bytes"], dtype=torch.uint8, device="cuda")
+    out2 = H.TT.empty(U.n, p2["ell"], 1)
+    rk2 = torch.empty((1, U.d + 1), dtype=torch.int64, device="cuda")
+    state = {}
+
+    def u2_step():
+        return H.recompress(U, U, l2, tol=tol, seed=s2, workspace=ws2, out=out2, ranks=rk2,
+                            precision=args.precision)
+
+    def u3_step(U2):
+        if "ws3" not in state or state["ranks3"] != U2.ranks:
+            p3 = H.plan(U2, U, l3, tol=tol, seed=s3, precision=args.precision)
+            state.update(ws3=torch.empty(p3["ws_bytes"], dtype=torch.uint8, device="cuda"),
+                         out3=H.TT.empty(U.n, p3["ell"], 1), ranks3=list(U2.ranks), ell3=p3["ell"],
+                         rk3=torch.empty((1, U.d + 1), dtype=torch.int64, device="cuda"))
+        return H.recompress(U2, U, l3, tol=tol, seed=s3, workspace=state["ws3"], out=state["out3"],
+                            ranks=state["rk3"], precision=args.precision)
+
+    def step():
+        r2 = u2_step()
+        U2 = H.TT.from_device_cores(H.kept_cores(r2))  # reads the kept ranks (host sync)
+        r3 = u3_step(U2)
+        return r2, U2, r3
+
+    say(f"trig 256^3: u2 at width {l2}, u3 at width {l3}, tol {tol:g}, precision {args.precision}")
+    for _ in range(max(args.warmup, 1)):
+        r2, U2, r3 = step()
+    torch.cuda.synchronize()
+    gpu_s, wall_s = _time_steps(step, args.steps, torch)
+    ms_per_step = 1000.0 * wall_s / args.steps
+    say(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
+    # per-product wall time (each synchronised on its own)
+    t2 = t3 = 0.0
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r2 = u2_step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        U2 = H.TT.from_device_cores(H.kept_cores(r2))
+        torch.cuda.synchronize()
+        t1b = time.perf_counter()
+        r3 = u3_step(U2)
+        torch.cuda.synchronize()
+        t2 += t1 - t0
+        t3 += time.perf_counter() - t1b
+    t2, t3 = 1000 * t2 / args.steps, 1000 * t3 / args.steps
+    H.profile_start()
+    for _ in range(args.steps):
+        step()
+    H.profile_stop()
+    torch.cuda.synchronize()
+    report = H.profile_report()
+    say("per launch site over the profiled steps:\n" + report)
+    roof = _roofline(report, 1, args.steps, perfmodel, args.precision)
+    kept2 = rk2[0].cpu().tolist()
+    kept3 = state["rk3"][0].cpu().tolist()
+    # error against the closed-form products, pointwise on all 256^3 points
+    fu = _full_np(u)
+    g2 = r2.train(0)
+    g3 = r3.train(0)
+    e2 = float(np.linalg.norm(_full_np(g2) - fu ** 2) / np.linalg.norm(fu ** 2))
+    e3 = float(np.linalg.norm(_full_np(g3) - fu ** 3) / np.linalg.norm(fu ** 3))
+    say(f"u2 ranks {kept2} err {e2:.3e}; u3 ranks {kept3} err {e3:.3e}")
+    ell2, ell3 = p2["ell"], state["ell3"]
+    chatt2 = perfmodel.chatt_paper(3, cfg["n"], 40, 40, ell2[1])
+    chatt3 = perfmodel.chatt_paper(3, cfg["n"], U2.ranks[1], 40, ell3[1])
+    f2 = perfmodel.hatt_round_flops(U.n, U.ranks, U.ranks, ell2, max(ell2))["total"]
+    f3 = perfmodel.hatt_round_flops(U.n, U2.ranks, U.ranks, ell3, max(ell3))["total"]
+    value = 2 * args.steps / wall_s
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_info
+
+        from oracle import hatt as ohatt
+        from oracle import philox, rounding, tt
+
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        t0 = time.perf_counter()
+        ref2 = rounding.tt_round(ohatt.hatt(u, u, philox.sketch(s2, U.n, ell2)), tol=tol)
+        ta = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ref3 = rounding.tt_round(ohatt.hatt(g2, u, philox.sketch(s3, U.n, ell3)), tol=tol)
+        tb = time.perf_counter() - t0
+        cpu = {"value": 2.0 / (ta + tb), "unit": "recompressions/s", "cores": threads, "kind": "oracle",
+               "sample": "one step: u2 and u3 by the FP64 numpy oracle (HaTT-1 with the same Philox sketches, "
+                         "then TT-Rounding at tol 1e-8), u3 from the GPU's u2 factor",
+               "u2_s": ta, "u3_s": tb}
+        parity = {"u2_rel_err_vs_oracle": tt.rel_err(g2, ref2), "u3_rel_err_vs_oracle": tt.rel_err(g3, ref3),
+                  "u2_oracle_ranks": tt.ranks(ref2), "u3_oracle_ranks": tt.ranks(ref3)}
+
+    line = {
+        "metric": "HaTT recompressions/s + GB/s/MFMA% vs explicit-PKP rounding, 1 GPU @ rel err 1e-8",
+        "value": value,
+        "unit": "recompressions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "f64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"trig 256^3: u2 = u*u then u3 = u2*u, u of ranks 40 (40 separable sin/cos "
+                               f"products), sketch widths {ell2[1]} / {ell3[1]}, TT-Rounding at tol {tol:g}",
+                   "recompressions_per_step": 2, "variant": "HaTT-1", "launch": "eager",
+                   "precision": args.precision},
+        "rel_err_vs_closed_form": {"u2": e2, "u3": e3},
+        "kept_ranks": {"u2": kept2, "u3": kept3},
+        "ms_per_product": {"u2": t2, "u3": t3},
+        "chatt_gflop": {"u2": chatt2 / 1e9, "u3": chatt3 / 1e9},
+        "chatt_tflops": {"u2": chatt2 / t2 / 1e9, "u3": chatt3 / t3 / 1e9,
+                         "step": (chatt2 + chatt3) / (ms_per_step / 1000.0) / 1e12},
+        "chatt_frac_of_fp64_peak": (chatt2 + chatt3) / (ms_per_step / 1000.0) / 1e12 / perfmodel.PEAK_FP64_TFLOPS,
+        "algorithmic_gflop_incl_qr_and_rounding": {"u2": f2 / 1e9, "u3": f3 / 1e9},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def _rp_pairs(wk, H, seed, count, max_rs=1024):
     """Pairs of the uneven 512-pair distribution (spectral cores), leaving
     out those whose exact rank r_x r_y exceeds the 1024-column SVD limit."""
@@ -348,6 +497,8 @@ def main() -> int:
         return _bench_batched(args, torch, wk, H)
     if args.workload == "rankpred":
         return _bench_rankpred(args, torch, wk, H)
+    if args.workload == "trig":
+        return _bench_trig(args, torch, wk, H, perfmodel)
     cfg = wk.WORKLOADS["spectral"]
     d, n, r, ell, cap = cfg["d"], cfg["n"], cfg["r"], cfg["ell"], cfg["max_rank"]
     B = args.batch

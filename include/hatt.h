@@ -50,7 +50,7 @@ typedef enum {
   HATT_ESHAPE = -2,      /* inconsistent mode sizes or ranks (rank[0] or rank[d] != 1, ...) */
   HATT_EWORKSPACE = -3,  /* workspace smaller than the plan call reported */
   HATT_EDEVICE = -4,     /* a HIP call or kernel launch failed */
-  HATT_ENOTCONV = -5,    /* reserved: adaptive sketch growth did not converge */
+  HATT_ENOTCONV = -5,    /* the tolerance-driven width growth did not converge (hatt_recompress_adaptive) */
   HATT_ENONFINITE = -6,  /* reserved: non-finite input detected */
   HATT_EUNSUPPORTED = -7 /* a shape the library does not handle (see message) */
 } hatt_status;
@@ -133,7 +133,11 @@ HATT_API hatt_status hatt_recompress(const hatt_tt *x, const hatt_tt *y, const h
  * separate workspace slots.  How many streams run concurrently is bounded by
  * the process's hardware queues (HIP's GPU_MAX_HW_QUEUES).  No host
  * synchronisation.  Errors of any pair are reported before anything is
- * enqueued.
+ * enqueued.  While `stream` is being captured into a HIP graph at most 12
+ * pairs are accepted (HATT_EUNSUPPORTED above that: a capture of 512 pairs,
+ * some 10^5 kernel nodes, ended the host process).  Concurrent calls from
+ * several host threads are serialised inside the library (the forked
+ * streams are shared per device).
  */
 HATT_API hatt_status hatt_batched_plan(int32_t npairs, const hatt_tt *x, const hatt_tt *y,
                                        const hatt_opts *opts, int64_t *out_offset,

@@ -68,6 +68,15 @@ class TT:
         host = torch.from_numpy(np.concatenate(flat))
         return TT(host.to(device), n, ranks, len(trains))
 
+    @staticmethod
+    def from_device_cores(cores: Sequence[torch.Tensor]) -> "TT":
+        """One train from device cores (r_k, n_k, r_{k+1}), packed into a flat
+        buffer (a device copy)."""
+        n = [int(c.shape[1]) for c in cores]
+        ranks = [int(cores[0].shape[0])] + [int(c.shape[2]) for c in cores]
+        data = torch.cat([c.reshape(-1) for c in cores]).to(torch.float64).contiguous()
+        return TT(data, n, ranks, 1)
+
     def view(self):
         n_arr, r_arr = i64_array(self.n), i64_array(self.ranks)
         v = HattTT(self.d, self.batch, n_arr, r_arr, ctypes.c_void_p(self.data.data_ptr()), self.stride)

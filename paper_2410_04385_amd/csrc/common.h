@@ -73,6 +73,9 @@ struct SandwichArgs {
   int prec;            // 1: C and out are FP32 and the products run on the FP32 matrix cores
 };
 hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s);
+// Whether launch_sandwich has a kernel for these shapes (checked on the host
+// before anything is enqueued).
+bool sandwich_supported(const SandwichArgs &a);
 // Matrix-core variant (k_sandwich.hip): block and LDS plan for a chunk of GC
 // sketch columns per workgroup; false when even one column does not fit.
 // Division by a launch constant d as a multiply-high: q = (x * m) >> 32 with

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <map>
 #include <vector>
@@ -959,6 +960,10 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
       if (!sandwich_mfma_plan(a, kSandwichLdsDoubles, &swp))
         return fail(HATT_EUNSUPPORTED, "FP32 range finding: ranks above 64 are not built (use FP64)");
     }
+    if (!sandwich_supported(a))
+      return fail(HATT_EUNSUPPORTED, "HaTT: no sandwich kernel for the W_L build at core " + std::to_string(c) +
+                                         " (ranks " + std::to_string(a.RA) + ", " + std::to_string(a.RI) + " of x, " +
+                                         std::to_string(a.SO) + ", " + std::to_string(a.SI) + " of y)");
     site("sandwich W_L n=%lld G=%lld RA=%d RI=%d SI=%d SO=%d [%s]", (long long)n[c], (long long)l1, a.RA, a.RI,
          a.SI, a.SO, sandwich_kernel_name(a));
     LAUNCH(launch_sandwich(a, st));
@@ -1045,6 +1050,10 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     a.n = n[cn];
     a.G = l[cn];
     a.batch = P;
+    if (!sandwich_supported(a))
+      return fail(HATT_EUNSUPPORTED, "HaTT: no sandwich kernel for the core update at core " + std::to_string(cn) +
+                                         " (ranks " + std::to_string(a.RI) + ", " + std::to_string(a.RA) + " of x, " +
+                                         std::to_string(a.SI) + ", " + std::to_string(a.SO) + " of y)");
     site("sandwich update n=%lld G=%lld RA=%d RI=%d SI=%d SO=%d [%s]", (long long)n[cn], (long long)l[cn], a.RA,
          a.RI, a.SI, a.SO, sandwich_kernel_name(a));
     LAUNCH(launch_sandwich(a, st));
@@ -1244,6 +1253,14 @@ hatt_status hatt_recompress(const hatt_tt *x, const hatt_tt *y, const hatt_tt *s
 // pairs never share scratch memory.  How many streams run at once is set by
 // the process's hardware queues (HIP's GPU_MAX_HW_QUEUES, 4 by default).
 constexpr int kBatchStreams = 32;
+// Largest uneven batch accepted while the caller's stream is being captured
+// into a HIP graph: the capture of a 512-pair batch (of the order of 10^5
+// kernel nodes on 32 forked streams) ended the process on the host, and the
+// largest captured batch known to replay correctly has 12 pairs.
+constexpr int kBatchCaptureMaxPairs = 12;
+// Serialises the library streams' fork / join sequence (and their creation)
+// between host threads: the fork event and the streams are shared per device.
+std::mutex g_batch_mu;
 
 struct BatchStreams {
   int device = -1;
@@ -1395,10 +1412,16 @@ hatt_status hatt_recompress_batched(int32_t npairs, const hatt_tt *x, const hatt
   const size_t need = bp.slot * (size_t)bp.streams;
   if (ws == nullptr || ws_bytes < need)
     return fail(HATT_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  hipStream_t caller = (hipStream_t)stream;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(caller, &cap) != hipSuccess) return fail(HATT_EDEVICE, "hipStreamIsCapturing failed");
+  if (cap != hipStreamCaptureStatusNone && npairs > kBatchCaptureMaxPairs)
+    return fail(HATT_EUNSUPPORTED, "uneven batches of more than " + std::to_string(kBatchCaptureMaxPairs) +
+                                       " pairs are not supported under HIP graph capture");
+  std::lock_guard<std::mutex> lock(g_batch_mu);
   BatchStreams *bs = nullptr;
   st = batch_streams(&bs);
   if (st != HATT_OK) return st;
-  hipStream_t caller = (hipStream_t)stream;
   if (hipEventRecord(bs->fork, caller) != hipSuccess) return fail(HATT_EDEVICE, "event record failed");
   for (int k = 0; k < bp.streams; ++k)
     if (hipStreamWaitEvent(bs->s[k], bs->fork, 0) != hipSuccess) return fail(HATT_EDEVICE, "stream wait failed");

@@ -393,6 +393,20 @@ const char *sandwich_kernel_name(const SandwichArgs &a) {
   return lg ? "sandwich_kernel<true>" : "sandwich_kernel<false>";
 }
 
+bool sandwich_supported(const SandwichArgs &a) {
+  if (a.n <= 0 || a.G <= 0 || a.batch <= 0) return true;
+  const int64_t budget = 19456;
+  SwPlan pl;
+  if ((g_sandwich_mfma || a.prec) && sandwich_mfma_plan(a, kSandwichLdsDoubles, &pl)) return true;
+  if (a.prec) return false;
+  // the scalar kernel is the last resort: one YL and ZR slice and at least one
+  // sketch column of intermediates must fit in LDS
+  const int64_t fixed = (int64_t)a.RA * a.RI + (int64_t)a.SI * a.SO;
+  const int64_t perg = (int64_t)a.RI * a.SI + (int64_t)a.RI * a.SO;
+  const int64_t gc = std::min<int64_t>(8, (budget - fixed) / perg);
+  return gc >= 1 && a.n < (1LL << 31) && (a.G + gc - 1) / gc <= 65535 && a.batch <= 65535;
+}
+
 hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s) {
   if (a.n <= 0 || a.G <= 0 || a.batch <= 0) return hipSuccess;
   const int64_t budget = 19456;  // doubles of dynamic LDS

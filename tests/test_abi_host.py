@@ -292,3 +292,16 @@ def test_adaptive_start_widths_are_validated():
     x = _cpu_tt([4, 4, 4], [1, 3, 3, 1])
     with pytest.raises(ValueError):
         api.recompress_adaptive(x, x, 1e-6, ell_init=[1, 5, 1])
+
+
+def test_plan_rejects_sandwich_shapes_without_a_kernel():
+    """Factor ranks 81 on both sides (u2 * u2 on the 256^3 grid) need a
+    sandwich no kernel covers: the plan call reports it before any launch."""
+    n = [256, 256, 256]
+    r = [1, 81, 81, 1]
+    with pytest.raises(HattError) as ei:
+        api.plan(_cpu_tt(n, r), _cpu_tt(n, r), 96, tol=1e-8)
+    assert ei.value.status == -7 and "sandwich" in str(ei.value)
+    # u2 * u (ranks 81 and 40) is covered
+    p = api.plan(_cpu_tt(n, r), _cpu_tt(n, [1, 40, 40, 1]), 136, tol=1e-8)
+    assert p["ell"] == [1, 136, 136, 1]
