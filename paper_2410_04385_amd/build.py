@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhatt.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["k_basic.hip", "k_sandwich.hip", "k_gemm.hip", "k_qr.hip", "k_svd.hip", "k_rankpred.hip", "hatt.cpp"]
+SOURCES = ["k_basic.hip", "k_sandwich.hip", "k_gemm.hip", "k_qr.hip", "k_svd.hip", "k_rankpred.hip", "k_hh.hip", "hatt.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

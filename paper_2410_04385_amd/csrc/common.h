@@ -105,6 +105,7 @@ struct SwPlan {
                               // register-blocked instantiation covers them, else 0
   int rem;                    // 1: FP64, b' and a' ranges of 17 to 20 (one full 16-block and a
                               // remainder of at most 4, formed by the 4 x 4 x 4 MFMA)
+  int nbuf;                   // YL / ZR slice buffers: 2 (next slice staged during this one) or 1
 };
 bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl);
 hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStream_t s);
@@ -193,6 +194,43 @@ hipError_t launch_chol(const double *g, int64_t gbs, int ks, int64_t kstride, do
 // A (m x n per pair, any strides; one block per pair streams all of A).
 hipError_t launch_gram_chol(CMat A, int64_t m, int n, double *r, double *rinv, int64_t rbs, int *flag,
                             int64_t fstride, int first, double thr_rel, int batch, hipStream_t s);
+
+// ---- Householder QR of short matrices, triangular inverse, Cholesky of
+// larger Gram matrices, row sketch (k_hh.hip) --------------------------------
+// Householder QR of A (m x n per pair, n <= 128, n <= m <= 512 for n <= 64,
+// else <= 256), one workgroup per pair: Q (m x n, explicit, when Q.ptr) and
+// R (n x n upper, when R.ptr), diag(R) >= 0.  A may be the same buffer as Q.
+// Pairs with skip_flag[p * skip_stride] == 1 are left untouched.
+struct HhArgs {
+  CMat A;
+  Mat Q, R;
+  int64_t m, n;
+  const int *skip_flag;
+  int64_t skip_stride;
+};
+bool hh_qr_supported(int64_t m, int64_t n);
+hipError_t launch_hh_qr(const HhArgs &a, int batch, hipStream_t s);
+const char *hh_qr_kernel_name(int64_t m, int64_t n);
+// X = R^{-1} of upper triangular R (n x n row-major, n <= 128); flag as in
+// launch_chol (cleared by a zero or non-finite diagonal entry; may be null).
+// With mask (int [n] per pair, stride mbs): columns whose diagonal entry is
+// at most 1e-13 of the largest are replaced by a unit column (scaled to the
+// largest diagonal entry) before inversion and marked 1.
+hipError_t launch_trinv(const double *r, int64_t rbs, double *x, int64_t xbs, int n, int *flag, int64_t fstride,
+                        int first, int *mask, int64_t mbs, int batch, hipStream_t s);
+// Replace the masked columns of A (m x n row-major, pair stride abs) by
+// unit-norm random sign vectors.
+hipError_t launch_complete_cols(double *a, int64_t m, int n, int64_t abs_, const int *mask, int64_t mbs,
+                                uint32_t key, int batch, hipStream_t s);
+// Cholesky factor and its inverse of G (n x n row-major, n <= 128, pair
+// stride gbs), R and R^{-1} with pair stride rbs; flag as in launch_chol.
+hipError_t launch_chol1k(const double *g, int64_t gbs, double *r, double *rinv, int64_t rbs, int n, int *flag,
+                         int64_t fstride, int first, double thr_rel, int batch, hipStream_t s);
+// B = Omega A (k x n row-major per pair, pair stride bbs): row r of B is the
+// signed sum of the rows r, r + k, r + 2k, ... of A (m rows), signs hashed
+// from the row index and key.
+hipError_t launch_sketch_rows(CMat A, int64_t m, int n, int k, double *b, int64_t bbs, uint32_t key, int batch,
+                              hipStream_t s);
 
 // ---- Jacobi SVD + rank choice (k_svd.hip) ----------------------------------
 // For each pair: R (kr x nc, row-major, kr <= nc <= kSvdMaxN) = U S V^T by

@@ -264,10 +264,24 @@ hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_
 // The second pass is what keeps Q orthonormal when a panel is (numerically)
 // rank deficient: the first TSQR then completes the panel with normalised
 // rounding noise that still has O(1) components along Q_prev.
-constexpr int64_t kPanel = 64;  // <= 64 columns: a TSQR tree with >= 2n-row blocks always exists
+constexpr int64_t kPanel = 128;  // <= 128 columns: one preconditioned CholeskyQR2 or TSQR per panel
+
+// Sketch-preconditioned CholeskyQR2 (tall frames up to kPcholMaxN columns):
+// B = Omega A (k = 256 signed row sums), [~, R0] = Householder QR of B,
+// A' = A R0^{-1}, then CholeskyQR2 of A' and R = R2 R1 R0.  R0 equalises the
+// column space so that A' is well conditioned even when A is numerically
+// rank deficient (a sketched frame wider than the rank it sees); a pair whose
+// Cholesky factors still fail the pivot tests is recomputed by Householder
+// TSQR, as for plain CholeskyQR2.
+constexpr int64_t kPcholMaxN = 128;
+constexpr int64_t kPcholSketchRows = 256;  // rows of B (>= 2n for every n <= kPcholMaxN)
 
 struct QrOp {
   int64_t m = 0, n = 0, k = 0;
+  bool hh = false;                   // one-workgroup Householder QR (short frames)
+  bool pchol = false;                // sketch-preconditioned CholeskyQR2 with TSQR fallback
+  int64_t sk_rows = 0;               // pchol: rows of the sketch B
+  bool has_direct = false;           // `direct` holds a TSQR plan (the fallback)
   bool chol = false;                 // CholeskyQR2 with per-pair TSQR fallback
   bool big = false;
   bool wide = false;                 // m < n, n > kQrMaxCols: QR of the first m columns, then R2 = Q^T A2
@@ -289,23 +303,51 @@ constexpr double kCholThr1 = 1e-12;
 constexpr double kCholThr2 = 0.5;
 
 int64_t chol_ws_doubles(int64_t m, int64_t n) { return m * n + 5 * n * n + 1; }
+// pchol scratch after the CholeskyQR2 block: A' (m n), B (k n), R0, R0^{-1},
+// T (n n each), the dependent-column mask (n ints)
+int64_t pchol_ws_doubles(int64_t m, int64_t n, int64_t k) { return m * n + k * n + 3 * n * n + n; }
 
 bool qr_prepare(int64_t m, int64_t n, QrOp *op) {
   op->m = m;
   op->n = n;
   op->k = std::min(m, n);
-  op->big = op->wide = op->chol = false;
-  // tall frames wider than one Cholesky panel go to BCGS2 over CholeskyQR2
-  // panels: the one-shot tree for them has blocks of barely n rows, so it
-  // needs many levels and forms Q a few columns at a time
-  const bool panelled = g_use_chol && m >= n && n > kCholMaxN;
-  if (n <= kQrMaxCols && !panelled && qr_make_plan(m, n, &op->direct)) {
-    op->ws_doubles = op->direct.ws_doubles;
-    if (g_use_chol && m >= n && n <= kCholMaxN) {
-      op->chol = true;
-      op->ws_tree = op->direct.ws_doubles;
-      op->ws_doubles = op->ws_tree + chol_ws_doubles(m, n);
+  op->big = op->wide = op->chol = op->hh = op->pchol = false;
+  op->ws_doubles = 0;
+  op->ws_tree = 0;
+  // short frames: one workgroup runs the Householder QR in registers
+  if (g_use_chol && m >= n && hh_qr_supported(m, n)) {
+    op->hh = true;
+    return true;
+  }
+  // wide frames: QR of the first m columns, then R2 = Q^T A2 (qr_exec)
+  if (g_use_chol && m < n && hh_qr_supported(m, m)) {
+    op->wide = true;
+    op->sub = std::make_shared<QrOp>();
+    if (!qr_prepare(m, m, op->sub.get())) return false;
+    op->ws_doubles = op->sub->ws_doubles;
+    return true;
+  }
+  // tall frames up to kPcholMaxN columns: CholeskyQR2 (many pairs of at
+  // most 64 columns) or its sketch-preconditioned form, with the Householder
+  // TSQR fallback where a TSQR plan exists
+  if (g_use_chol && m >= n && n <= kPcholMaxN) {
+    op->has_direct = qr_make_plan(m, n, &op->direct);
+    op->chol = op->has_direct && n <= kCholMaxN;
+    op->sk_rows = kPcholSketchRows;
+    op->pchol = m >= kPcholSketchRows && hh_qr_supported(kPcholSketchRows, n);
+    if (op->chol || op->pchol) {
+      op->ws_tree = op->has_direct ? op->direct.ws_doubles : 0;
+      op->ws_doubles = op->ws_tree + chol_ws_doubles(m, n) + (op->pchol ? pchol_ws_doubles(m, n, op->sk_rows) : 0);
+      return true;
     }
+  }
+  // tall frames wider than one panel go to BCGS2 over panels: the one-shot
+  // tree for them has blocks of barely n rows, so it needs many levels and
+  // forms Q a few columns at a time
+  const bool panelled = g_use_chol && m >= n && n > kPcholMaxN;
+  if (n <= kQrMaxCols && !panelled && qr_make_plan(m, n, &op->direct)) {
+    op->has_direct = true;
+    op->ws_doubles = op->direct.ws_doubles;
     return true;
   }
   if (m < n) {
@@ -348,6 +390,81 @@ struct QrDeferred {
   int64_t wsp = 0, fst = 0;
   bool used = false;
 };
+
+hatt_status pchol_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double *ws, int64_t wsp, int P,
+                       GemmCtx &gc, hipStream_t st, QrDeferred *def) {
+  const int64_t m = op.m, n = op.n, k = op.sk_rows;
+  double *q1 = ws + op.ws_tree;  // m x n row-major
+  double *g = q1 + m * n;
+  double *r1 = g + n * n, *r1i = r1 + n * n, *r2 = r1i + n * n, *r2i = r2 + n * n;
+  int *flag = reinterpret_cast<int *>(r2i + n * n);
+  double *ap = r2i + n * n + 1;
+  double *B = ap + m * n, *R0 = B + k * n, *R0i = R0 + n * n, *T = R0i + n * n;
+  int *mask = reinterpret_cast<int *>(T + n * n);
+  const int64_t fst = 2 * wsp, mbs = 2 * wsp;
+  const bool inq = def != nullptr && def->q1_in_q;
+  const Mat q1m = inq ? Q : Mat{q1, n, 1, wsp};
+  CMat q1c{q1m.ptr, q1m.rs, q1m.cs, q1m.bs}, q1t{q1m.ptr, q1m.cs, q1m.rs, q1m.bs};
+  CMat apc{ap, n, 1, wsp}, apt{ap, 1, n, wsp};
+  hatt_status sg;
+  // preconditioner: R0 of the Householder QR of the row sketch B = Omega A
+  site("pchol sketch %lldx%lld k=%lld", (long long)m, (long long)n, (long long)k);
+  LAUNCH(launch_sketch_rows(A, m, (int)n, (int)k, B, wsp, 0x9E3779B9u, P, st));
+  {
+    HhArgs h{};
+    h.A = CMat{B, n, 1, wsp};
+    h.Q = Mat{nullptr, 0, 0, 0};
+    h.R = Mat{R0, n, 1, wsp};
+    h.m = k;
+    h.n = n;
+    site("pchol hh %lldx%lld [%s]", (long long)k, (long long)n, hh_qr_kernel_name(k, n));
+    LAUNCH(launch_hh_qr(h, P, st));
+  }
+  // R0^{-1}; sketch columns that depend on the ones before them (pivot at
+  // most 1e-13 of the largest) are marked and their columns of A' replaced
+  // by random unit vectors: Q then spans range(A) plus those directions
+  site("pchol trinv %lld", (long long)n);
+  LAUNCH(launch_trinv(R0, wsp, R0i, wsp, (int)n, flag, fst, 1, mask, mbs, P, st));
+  sg = gemm(run, gc, A, CMat{R0i, n, 1, wsp}, Mat{ap, n, 1, wsp}, m, n, n, 1.0, 0.0, P, st, false);
+  if (sg != HATT_OK) return sg;
+  site("pchol complete %lldx%lld", (long long)m, (long long)n);
+  LAUNCH(launch_complete_cols(ap, m, (int)n, wsp, mask, mbs, 0x7F4A7C15u, P, st));
+  // CholeskyQR2 of A'
+  sg = gemm(run, gc, apt, apc, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true);
+  if (sg != HATT_OK) return sg;
+  site("pchol chol1k %lld", (long long)n);
+  LAUNCH(launch_chol1k(g, wsp, r1, r1i, wsp, (int)n, flag, fst, 0, kCholThr1, P, st));
+  sg = gemm(run, gc, apc, CMat{r1i, n, 1, wsp}, q1m, m, n, n, 1.0, 0.0, P, st, false);
+  if (sg != HATT_OK) return sg;
+  sg = gemm(run, gc, q1t, q1c, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true);
+  if (sg != HATT_OK) return sg;
+  site("pchol chol1k %lld", (long long)n);
+  LAUNCH(launch_chol1k(g, wsp, r2, r2i, wsp, (int)n, flag, fst, 0, kCholThr2, P, st));
+  if (R.ptr) {
+    // R = Q^T A = R2^{-T} (Q1^T A), exact because range(Q) contains range(A);
+    // formed before Q is written (Q may share A's buffer)
+    sg = gemm(run, gc, q1t, A, Mat{T, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true);
+    if (sg != HATT_OK) return sg;
+    sg = gemm(run, gc, CMat{r2i, 1, n, wsp}, CMat{T, n, 1, wsp}, R, n, n, n, 1.0, 0.0, P, st, false, flag, fst);
+    if (sg != HATT_OK) return sg;
+  }
+  if (def != nullptr) {
+    def->q1 = q1m.ptr;
+    def->r2i = r2i;
+    def->flag = flag;
+    def->wsp = wsp;
+    def->fst = fst;
+    def->used = true;
+  } else {
+    sg = gemm(run, gc, q1c, CMat{r2i, n, 1, wsp}, Q, m, n, n, 1.0, 0.0, P, st, false, flag, fst);
+    if (sg != HATT_OK) return sg;
+  }
+  if (op.has_direct) {
+    site("tsqr fallback %lldx%lld", (long long)m, (long long)n);
+    LAUNCH(launch_tsqr(op.direct, A, Q, R, ws, wsp, P, st, flag, fst));
+  }
+  return HATT_OK;
+}
 
 hatt_status cholqr2_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double *ws, int64_t wsp, int P,
                          GemmCtx &gc, hipStream_t st, QrDeferred *def = nullptr) {
@@ -420,6 +537,19 @@ hatt_status qr_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, int64_t rbuf
     }
     return HATT_OK;
   }
+  if (op.hh) {
+    HhArgs h{};
+    h.A = A;
+    h.Q = Q;
+    h.R = R.ptr ? R : Mat{nullptr, 0, 0, 0};
+    h.m = op.m;
+    h.n = op.n;
+    site("hh %lldx%lld [%s]", (long long)op.m, (long long)op.n, hh_qr_kernel_name(op.m, op.n));
+    LAUNCH(launch_hh_qr(h, P, st));
+    return HATT_OK;
+  }
+  // many pairs of at most 64 columns: the fused Gram + Cholesky blocks
+  if (op.pchol && !(op.chol && P >= kCholFuseMinPairs)) return pchol_exec(run, op, A, Q, R, ws, wsp, P, gc, st, def);
   if (op.chol) return cholqr2_exec(run, op, A, Q, R, ws, wsp, P, gc, st, def);
   if (!op.big) {
     site("tsqr %lldx%lld", (long long)op.m, (long long)op.n);

@@ -1,0 +1,567 @@
+// Dense kernels for the QR of tall frames that may be rank deficient:
+//
+//  * hh_qr_kernel: economy Householder QR of one short matrix (m <= 512
+//    rows for n <= 64 columns, m <= 256 for n <= 128) per workgroup, the matrix resident in registers.
+//    This is the QR Alg. 4 asks for (the paper's econ-QR), exact for rank
+//    deficient input: whatever the rank, Q has orthonormal columns and
+//    Q R = A to rounding.
+//  * trinv_kernel: inverse of an upper triangular n x n matrix (n <= 128).
+//  * chol1k_kernel: Cholesky factor R and R^{-1} of an n x n Gram matrix
+//    (n <= 128), the symmetric elimination of [G | I] with 1024 threads.
+//  * sketch_rows_kernel: B = Omega A for a sparse sign matrix Omega with k
+//    rows (row r of B sums the rows r, r + k, r + 2k, ... of A with hashed
+//    signs); B R0^{-1} well conditioned makes A R0^{-1} well conditioned
+//    enough for CholeskyQR2 (randomised preconditioning of CholeskyQR).
+//
+// Register layout of hh_qr_kernel (1024 threads = 16 waves): wave w owns the
+// columns w, w + 16, w + 32, ... (CPW of them); lane l holds the rows l,
+// l + 64, ... (RPL of them).  Column dot products are wave reductions, so a
+// Householder step needs one barrier: the owner of column j publishes its
+// reflector through LDS and every wave updates its own columns.
+#include "common.h"
+
+namespace hatt {
+
+namespace {
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the 64 lanes, the same bits in every lane (each butterfly step
+// adds the pair in both orders, and x + y == y + x exactly).
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);  // row_half_mirror: quads of an 8-lane half
+  v += dpp_d<0x140>(v);  // row_mirror: halves of a 16-lane row
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
+// Sum over aligned groups of 8 lanes (every lane of the group gets it).
+__device__ __forceinline__ double group8_sum(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+  // integer finaliser of MurmurHash3 (Appleby)
+  x ^= x >> 16;
+  x *= 0x85ebca6bu;
+  x ^= x >> 13;
+  x *= 0xc2b2ae35u;
+  x ^= x >> 16;
+  return x;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Householder QR.  Reflector j (LAPACK's dlarfg convention): for the column
+// x = A(j:m, j), beta = -sign(alpha) ||x||, tau = (beta - alpha) / beta,
+// v = [1; x(2:) / (alpha - beta)], H_j = I - tau v v^T, H_j x = beta e_1;
+// x(2:) = 0 gives tau = 0.  Q = H_0 H_1 ... H_{n-1} [I_n; 0] is formed by
+// backward accumulation.  Finally rows of R and columns of Q are flipped so
+// that diag(R) >= 0.
+template <int CPW, int RPL>
+__global__ __launch_bounds__(1024) void hh_qr_kernel(HhArgs a) {
+  constexpr int MR = 64 * RPL;
+  __shared__ double vbuf[2][MR];
+  __shared__ double tau_s[16 * CPW];
+  __shared__ double sgn_s[16 * CPW];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int p = blockIdx.x;
+  if (a.skip_flag != nullptr && a.skip_flag[p * a.skip_stride] == 1) return;
+  const int m = a.m, n = a.n;
+  const double *A = a.A.ptr + p * a.A.bs;
+  double x[CPW][RPL];
+#pragma unroll
+  for (int t = 0; t < CPW; ++t) {
+    const int c = w + 16 * t;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int r = lane + 64 * q;
+      x[t][q] = (c < n && r < m) ? A[r * a.A.rs + c * a.A.cs] : 0.0;
+    }
+  }
+  // A may alias Q: every load above is done before any store below
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const int ow = j & 15, tj = j >> 4;
+    double *vb = vbuf[j & 1];
+    if (w == ow) {
+      double col[RPL];
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        col[q] = 0.0;
+#pragma unroll
+        for (int t = 0; t < CPW; ++t)
+          if (t == tj) col[q] = x[t][q];
+      }
+      double s = 0.0, al = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int r = lane + 64 * q;
+        if (r > j) s += col[q] * col[q];
+        if (r == j) al = col[q];
+      }
+      const double sigma = wave_sum(s);
+      const double alpha = wave_sum(al);  // one lane holds it
+      double tau = 0.0, beta = alpha, scale = 0.0;
+      if (sigma > 0.0) {
+        const double nrm = sqrt(alpha * alpha + sigma);
+        beta = (alpha >= 0.0) ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int r = lane + 64 * q;
+        const double v = (r > j) ? col[q] * scale : (r == j ? 1.0 : 0.0);
+        vb[r] = v;
+        // the owner keeps beta on the diagonal and v below it
+        const double nv = (r > j) ? v : (r == j ? beta : col[q]);
+#pragma unroll
+        for (int t = 0; t < CPW; ++t)
+          if (t == tj) x[t][q] = nv;
+      }
+      if (lane == 0) {
+        tau_s[j] = tau;
+        sgn_s[j] = (beta < 0.0) ? -1.0 : 1.0;
+      }
+    }
+    __syncthreads();
+    const double tau = tau_s[j];
+    double v[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) v[q] = vb[lane + 64 * q];
+#pragma unroll
+    for (int t = 0; t < CPW; ++t) {
+      const int c = w + 16 * t;
+      if (c > j && c < n) {  // uniform per wave
+        double dot = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) dot += v[q] * x[t][q];
+        const double f = tau * wave_sum(dot);
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) x[t][q] -= f * v[q];
+      }
+    }
+  }
+  __syncthreads();
+  // R: rows i <= c of column c, sign-flipped per row
+  if (a.R.ptr != nullptr) {
+    double *R = a.R.ptr + p * a.R.bs;
+#pragma unroll
+    for (int t = 0; t < CPW; ++t) {
+      const int c = w + 16 * t;
+      if (c < n) {
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+          const int r = lane + 64 * q;
+          if (r < n) R[r * a.R.rs + c * a.R.cs] = (r <= c) ? sgn_s[r] * x[t][q] : 0.0;
+        }
+      }
+    }
+  }
+  if (a.Q.ptr == nullptr) return;
+  // reflectors to the Q buffer (below the diagonal; read back by every wave)
+  double *Q = a.Q.ptr + p * a.Q.bs;
+#pragma unroll
+  for (int t = 0; t < CPW; ++t) {
+    const int c = w + 16 * t;
+    if (c < n) {
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int r = lane + 64 * q;
+        if (r > c && r < m) Q[r * a.Q.rs + c * a.Q.cs] = x[t][q];
+      }
+    }
+  }
+  __syncthreads();
+  // Q = H_0 ... H_{n-1} [I; 0], starting from the identity columns
+#pragma unroll
+  for (int t = 0; t < CPW; ++t) {
+    const int c = w + 16 * t;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) x[t][q] = (lane + 64 * q == c) ? 1.0 : 0.0;
+  }
+  for (int j = n - 1; j >= 0; --j) {
+    const double tau = tau_s[j];
+    if (tau == 0.0) continue;  // uniform
+    double v[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int r = lane + 64 * q;
+      v[q] = (r > j && r < m) ? Q[r * a.Q.rs + j * a.Q.cs] : (r == j ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int t = 0; t < CPW; ++t) {
+      const int c = w + 16 * t;
+      if (c >= j && c < n) {
+        double dot = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) dot += v[q] * x[t][q];
+        const double f = tau * wave_sum(dot);
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) x[t][q] -= f * v[q];
+      }
+    }
+  }
+  __syncthreads();  // every reflector has been read
+#pragma unroll
+  for (int t = 0; t < CPW; ++t) {
+    const int c = w + 16 * t;
+    if (c < n) {
+      const double sg = sgn_s[c];
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int r = lane + 64 * q;
+        if (r < m) Q[r * a.Q.rs + c * a.Q.cs] = sg * x[t][q];
+      }
+    }
+  }
+}
+
+bool hh_qr_supported(int64_t m, int64_t n) { return n >= 1 && n <= 128 && m >= n && m <= (n <= 64 ? 512 : 256); }
+
+hipError_t launch_hh_qr(const HhArgs &a, int batch, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  if (!hh_qr_supported(a.m, a.n)) return hipErrorInvalidValue;
+  const int m = (int)a.m;
+  if (a.n <= 64) {
+    if (m <= 128) hh_qr_kernel<4, 2><<<batch, 1024, 0, s>>>(a);
+    else if (m <= 256) hh_qr_kernel<4, 4><<<batch, 1024, 0, s>>>(a);
+    else hh_qr_kernel<4, 8><<<batch, 1024, 0, s>>>(a);
+  } else {
+    if (m <= 128) hh_qr_kernel<8, 2><<<batch, 1024, 0, s>>>(a);
+    else hh_qr_kernel<8, 4><<<batch, 1024, 0, s>>>(a);
+  }
+  return hipGetLastError();
+}
+
+const char *hh_qr_kernel_name(int64_t m, int64_t n) {
+  if (n <= 64) {
+    if (m <= 128) return "hh_qr_kernel<4, 2>";
+    if (m <= 256) return "hh_qr_kernel<4, 4>";
+    return "hh_qr_kernel<4, 8>";
+  }
+  if (m <= 128) return "hh_qr_kernel<8, 2>";
+  return "hh_qr_kernel<8, 4>";
+}
+
+// ---------------------------------------------------------------------------
+// X = R^{-1} for upper triangular R (n x n, n <= 128): eight lanes per
+// column c run the back substitution X(i, c) = -(sum_{i<k<=c} R(i,k) X(k,c))
+// / R(i,i), lane t of the group holding X(k, c) for k = t (mod 8).  R sits in
+// LDS.  With mask != nullptr, a column whose diagonal entry is at most
+// 1e-13 of the largest (a column of the factored matrix that depends on the
+// ones before it) is replaced by dmax e_j before the inversion and marked
+// mask[j] = 1 (else 0); otherwise a zero or non-finite diagonal entry clears
+// the pair's flag (may be null).
+constexpr double kDepRel = 1e-13;
+
+__global__ __launch_bounds__(1024) void trinv_kernel(const double *r, int64_t rbs, double *xo, int64_t xbs, int n,
+                                                     int *flag, int64_t fstride, int first, int *mask,
+                                                     int64_t mbs) {
+  extern __shared__ double Rs[];  // n x n, then the reciprocal diagonal
+  double *dinv = Rs + n * n;
+  __shared__ int ok_s;
+  __shared__ double dmax_s;
+  const int tid = threadIdx.x;
+  const int p = blockIdx.x;
+  const double *R = r + p * rbs;
+  if (tid == 0) ok_s = 1;
+  for (int e = tid; e < n * n; e += 1024) Rs[e] = R[e];
+  __syncthreads();
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(Rs[i * n + i]));
+    dmax_s = mx;
+  }
+  __syncthreads();
+  const double dmax = dmax_s;
+  if (mask != nullptr) {
+    // one thread per column: its entries above the diagonal are cleared
+    for (int j = tid; j < n; j += 1024) {
+      const double d = Rs[j * n + j];
+      const int dep = !(fabs(d) > kDepRel * dmax) ? 1 : 0;  // also NaN
+      mask[p * mbs + j] = dep;
+      if (dep) {
+        for (int i = 0; i < j; ++i) Rs[i * n + j] = 0.0;
+        Rs[j * n + j] = (dmax > 0.0 && isfinite(dmax)) ? dmax : 1.0;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += 1024) {
+    const double d = Rs[i * n + i];
+    if (!(d != 0.0) || !isfinite(d)) ok_s = 0;
+    dinv[i] = 1.0 / d;
+  }
+  __syncthreads();
+  const int c = tid >> 3, t = tid & 7;
+  double xk[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) xk[s] = 0.0;
+  // the column's first entry; groups beyond n idle but take part in the
+  // group sums with zeros
+  const int cc = (c < n) ? c : -1;
+  if (cc >= 0 && (cc & 7) == t) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+      if (s == (cc >> 3)) xk[s] = dinv[cc];
+  }
+  // the wave runs to the largest column it holds (columns 8 w' .. 8 w' + 7)
+  const int cmax = ((tid >> 6) << 3) + 7;
+  for (int i = cmax - 1; i >= 0; --i) {
+    double acc = 0.0;
+    if (cc > i) {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const int k = t + 8 * s;
+        if (k > i && k <= cc) acc += Rs[i * n + k] * xk[s];
+      }
+    }
+    const double sum = group8_sum(acc);
+    if (cc > i && (i & 7) == t) {
+      const double v = -sum * dinv[i];
+#pragma unroll
+      for (int s = 0; s < 16; ++s)
+        if (s == (i >> 3)) xk[s] = v;
+    }
+  }
+  if (cc >= 0) {
+    double *X = xo + p * xbs;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k = t + 8 * s;
+      if (k < n) X[k * n + cc] = (k <= cc) ? xk[s] : 0.0;
+    }
+  }
+  if (flag != nullptr && tid == 0) {
+    int *f = flag + p * fstride;
+    *f = first ? ok_s : (*f & ok_s);
+  }
+}
+
+hipError_t launch_trinv(const double *r, int64_t rbs, double *x, int64_t xbs, int n, int *flag, int64_t fstride,
+                        int first, int *mask, int64_t mbs, int batch, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  if (n < 1 || n > 128) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(n * n + n) * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute((const void *)trinv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)((128 * 128 + 128) * sizeof(double)));
+    attr = true;
+  }
+  trinv_kernel<<<batch, 1024, lds, s>>>(r, rbs, x, xbs, n, flag, fstride, first, mask, mbs);
+  return hipGetLastError();
+}
+
+// Columns j of A (m x n row-major per pair, pair stride abs) with
+// mask[p * mbs + j] set are replaced by a hashed random sign vector of unit
+// norm (entries +-1/sqrt(m)).
+__global__ void complete_cols_kernel(double *a, int64_t m, int n, int64_t abs_, const int *mask, int64_t mbs,
+                                     uint32_t key) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (e >= m * n) return;
+  const int c = (int)(e % n);
+  if (!mask[p * mbs + c]) return;
+  const int64_t r = e / n;
+  const double v = 1.0 / sqrt((double)m);
+  const uint32_t h = hash32((uint32_t)r * 0x9E3779B1u ^ hash32((uint32_t)c + key));
+  a[p * abs_ + e] = (h & 1u) ? -v : v;
+}
+
+hipError_t launch_complete_cols(double *a, int64_t m, int n, int64_t abs_, const int *mask, int64_t mbs,
+                                uint32_t key, int batch, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  dim3 grid((unsigned)((m * n + 255) / 256), (unsigned)batch);
+  complete_cols_kernel<<<grid, 256, 0, s>>>(a, m, n, abs_, mask, mbs, key);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky factor of G (n x n, n <= 128) with R^{-1}, by the symmetric
+// Gaussian elimination of [G | I] (G = L D L^T; R = D^{1/2} L^T,
+// R^{-1} = L^{-T} D^{-1/2}), held in registers: thread (ty, tx) of 16 x 64
+// holds rows ty + 16 k of the columns tx + 64 s.  The multipliers of pivot j
+// are its own row (symmetry), published through a double-buffered LDS row by
+// its owner.  Pivots <= thr_rel * max diag(G) (and NaN) clear the flag.
+__global__ __launch_bounds__(1024) void chol1k_kernel(const double *g, int64_t gbs, double *ro, double *rio,
+                                                      int64_t rbs, int n, int *flag, int64_t fstride, int first,
+                                                      double thr_rel) {
+  constexpr int KR = 8, NS = 4;  // rows per thread, column slots (2n <= 256)
+  __shared__ double prow[2][256];
+  __shared__ double piv[128];
+  __shared__ double dmax_s;
+  const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+  const int p = blockIdx.x;
+  const double *G = g + p * gbs;
+  const int n2 = 2 * n;
+  double w[KR][NS];
+#pragma unroll
+  for (int k = 0; k < KR; ++k) {
+    const int i = ty + 16 * k;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int c = tx + 64 * s;
+      double v = 0.0;
+      if (i < n && c < n2) v = (c < n) ? G[i * n + c] : ((c - n == i) ? 1.0 : 0.0);
+      w[k][s] = v;
+    }
+  }
+  if (ty == 0) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int c = tx + 64 * s;
+      if (c < n2) prow[0][c] = w[0][s];
+    }
+  }
+  if (tid == 0) {
+    double m = 0.0;
+    for (int j = 0; j < n; ++j) m = fmax(m, G[j * n + j]);
+    dmax_s = m;
+  }
+  __syncthreads();
+  const double dmax = dmax_s;
+  const bool dmax_ok = (dmax > 0.0) && (dmax < 1e300);
+  const double thr = thr_rel * dmax;
+  int bad = dmax_ok ? 0 : 1;
+  for (int j = 0; j < n; ++j) {
+    const double *pr = prow[j & 1];
+    double d = pr[j];
+    if (!(d > thr)) {
+      bad = 1;
+      d = (thr > 0.0 && thr < 1e300) ? thr : 1.0;
+    }
+    if (tid == 0) piv[j] = d;
+    const double inv = 1.0 / d;
+    double pc[NS];
+    bool act[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int c = tx + 64 * s;
+      // left half: columns > j (upper triangle only, rows i <= c); right half: up to n + j
+      act[s] = (c < n) ? (c > j) : (c < n2 && c <= n + j);
+      pc[s] = act[s] ? pr[c] * inv : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int i = ty + 16 * k;
+      if (i > j && i < n) {
+        const double mul = pr[i];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int c = tx + 64 * s;
+          if (act[s] && (c >= n || i <= c)) w[k][s] -= mul * pc[s];
+        }
+      }
+    }
+    if (j + 1 < n && ty == ((j + 1) & 15)) {
+      const int kk = (j + 1) >> 4;
+      double *nr = prow[(j + 1) & 1];
+#pragma unroll
+      for (int k = 0; k < KR; ++k)
+        if (k == kk) {
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            const int c = tx + 64 * s;
+            if (c < n2) nr[c] = w[k][s];
+          }
+        }
+    }
+    __syncthreads();
+  }
+  double *R = ro + p * rbs, *Ri = rio + p * rbs;
+  // R(i, c) = U(i, c) / sqrt(d_i) (c > i), sqrt(d_i) on the diagonal;
+  // R^{-1}(c, i) = L^{-1}(i, c) / sqrt(d_i) for c <= i, i.e. from the right half
+#pragma unroll
+  for (int k = 0; k < KR; ++k) {
+    const int i = ty + 16 * k;
+    if (i < n) {
+      const double si = sqrt(piv[i]);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int c = tx + 64 * s;
+        if (c < n) {
+          R[i * n + c] = (c > i) ? w[k][s] / si : ((c == i) ? si : 0.0);
+        } else if (c < n2) {
+          const int cc = c - n;  // L^{-1}(i, cc), nonzero for cc <= i
+          Ri[cc * n + i] = (cc <= i) ? w[k][s] / si : 0.0;
+        }
+      }
+    }
+  }
+  if (tid == 0) {
+    int *f = flag + p * fstride;
+    const int ok = bad ? 0 : 1;
+    *f = first ? ok : (*f & ok);
+  }
+}
+
+hipError_t launch_chol1k(const double *g, int64_t gbs, double *r, double *rinv, int64_t rbs, int n, int *flag,
+                         int64_t fstride, int first, double thr_rel, int batch, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  if (n < 1 || n > 128) return hipErrorInvalidValue;
+  chol1k_kernel<<<batch, 1024, 0, s>>>(g, gbs, r, rinv, rbs, n, flag, fstride, first, thr_rel);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// B(r, c) = sum_t sign(r + t k) A(r + t k, c), r < k, c < n, per pair.
+// Threads run along whichever of r, c is contiguous in A.
+__global__ void sketch_rows_kernel(CMat A, int64_t m, int n, int k, double *b, int64_t bbs, uint32_t key,
+                                   int rows_fast) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (e >= (int64_t)k * n) return;
+  int r, c;
+  if (rows_fast) {
+    c = (int)(e / k);
+    r = (int)(e - (int64_t)c * k);
+  } else {
+    r = (int)(e / n);
+    c = (int)(e - (int64_t)r * n);
+  }
+  const double *a = A.ptr + p * A.bs + c * A.cs;
+  // eight independent partial sums keep eight loads in flight
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t i = r;
+  for (; i + 7 * (int64_t)k < m; i += 8 * (int64_t)k) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t ii = i + u * (int64_t)k;
+      const double v = a[ii * A.rs];
+      acc[u] += (hash32((uint32_t)ii ^ key) & 1u) ? -v : v;
+    }
+  }
+  for (int u = 0; i < m; i += k, ++u) {
+    const double v = a[i * A.rs];
+    acc[u] += (hash32((uint32_t)i ^ key) & 1u) ? -v : v;
+  }
+  b[p * bbs + (int64_t)r * n + c] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
+hipError_t launch_sketch_rows(CMat A, int64_t m, int n, int k, double *b, int64_t bbs, uint32_t key, int batch,
+                              hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  const int64_t tot = (int64_t)k * n;
+  dim3 grid((unsigned)((tot + 255) / 256), (unsigned)batch);
+  sketch_rows_kernel<<<grid, 256, 0, s>>>(A, m, n, k, b, bbs, key, A.rs == 1 ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace hatt

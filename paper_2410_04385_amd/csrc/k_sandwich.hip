@@ -21,6 +21,10 @@ namespace {
 __host__ __device__ inline int rup(int x, int m) { return (x + m - 1) / m * m; }
 }  // namespace
 
+// K steps of the generic kernel's MFMA chains: up to 32 (K <= 128), run in
+// unrolled chunks of 16.
+constexpr int kSwMaxKSteps = 32;
+
 // Largest K-step count with a register-blocked instantiation, and its fetch
 // slots per thread for the next slice's YL / ZR entries.
 constexpr int kSwKsMax = 8;
@@ -34,14 +38,18 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
   // the register prefetch of the next slice needs every YL / ZR slot to fit
   // kSwPrefetch slots per thread (else each slice is staged directly)
   bool pf = (int64_t)RA16 * RI4 + (int64_t)SI4 * SO16 <= kSwPrefetch * 256;
+  int nbuf = 2;
   auto lds_for = [&](int gc, int *ldt, int *m1) {
     *m1 = rup(gc * a.RI, 16);
     *ldt = rup(gc * a.SO, 16) + 1;
-    return (int64_t)(*m1) * ldc + 2 * yz + (int64_t)RI4 * (*ldt);
+    return (int64_t)(*m1) * ldc + nbuf * yz + (int64_t)RI4 * (*ldt);
   };
-  // largest chunk (<= 16 columns) that keeps two blocks per CU, else one
+  // largest chunk (<= 16 columns) that keeps two blocks per CU, else one;
+  // failing that, one YL / ZR buffer (the next slice is staged after this
+  // one's products, large factor ranks)
   int best = 0;
-  for (int pass = 0; pass < 2 && best == 0; ++pass) {
+  for (int pass = 0; pass < 3 && best == 0; ++pass) {
+    if (pass == 2) nbuf = 1;
     const int64_t lim = pass == 0 ? std::min<int64_t>(budget, 9728) : budget;
     for (int gc = (int)std::min<int64_t>(16, a.G); gc >= 1; --gc) {
       int ldt, m1;
@@ -52,6 +60,8 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
     }
   }
   if (best == 0) return false;
+  pl->nbuf = nbuf;
+  if (nbuf == 1) pf = false;
   const int64_t chunks = (a.G + best - 1) / best;
   const int GC = (int)((a.G + chunks - 1) / chunks);  // balanced chunks
   int ldt, m1;
@@ -72,7 +82,7 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
   pl->fd_gc = make_fastdiv(GC);
   // the multiply-high decodes need row / column indices below 2^16 and divisors <= 4096
   if (m1 >= (1 << 16) || ldt >= (1 << 16) || a.RI > 4096 || a.SO > 4096) return false;
-  if (RI4 > 64 || SI4 > 64) return false;  // K steps of the unrolled MFMA loop
+  if (RI4 > 4 * kSwMaxKSteps || SI4 > 4 * kSwMaxKSteps) return false;  // K steps of the MFMA loops
   // slices per block: about 2048 blocks in the grid; C is staged once per block
   const int64_t others = chunks * (int64_t)a.batch;
   int64_t ipb = std::max<int64_t>(1, (a.n * others) / 2048);
@@ -93,6 +103,7 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
   if (off32 && omax < (1LL << 31) && RI4 == SI4 && RI4 / 4 <= kSwKsMax && 4 % (SO16 / 16) == 0 &&
       4 % (RA16 / 16) == 0 && (int64_t)a.RA * a.RI + (int64_t)a.SI * a.SO <= 256LL * sw_ks_slots(RI4 / 4))
     pl->ks = RI4 / 4;
+  if (pl->nbuf != 2) pl->ks = 0;
   pl->rem = (pl->ks > 0 && a.prec == 0 && a.og != 1 && a.SO >= 17 && a.SO <= 20 && a.RA >= 17 && a.RA <= 20) ? 1 : 0;
   return true;
 }
@@ -101,18 +112,19 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
 // c0 += A0 B0, c1 += A1 B1 over K steps of 4 (A rows advance by lda_k per
 // step, B rows by ldb_k).  Both chains always run; a caller without a second
 // block passes the first block's operands twice and drops c1.
-constexpr int kSwMaxKSteps = 16;  // K <= 64 on both stages
-
 template <typename CT, typename ACC>
 __device__ __forceinline__ void mfma_pair(const CT *a0, const CT *b0, const CT *a1, const CT *b1, int lda_k,
                                           int ldb_k, int ksteps, ACC &c0, ACC &c1) {
+  for (int k0 = 0; k0 < ksteps; k0 += 16) {
 #pragma unroll
-  for (int k = 0; k < kSwMaxKSteps; ++k) {
-    if (k < ksteps) {
-      const CT x0 = a0[k * lda_k], y0 = b0[k * ldb_k];
-      const CT x1 = a1[k * lda_k], y1 = b1[k * ldb_k];
-      c0 = mfma16(x0, y0, c0);
-      c1 = mfma16(x1, y1, c1);
+    for (int k = 0; k < 16; ++k) {
+      if (k0 + k < ksteps) {
+        const int kk = k0 + k;
+        const CT x0 = a0[kk * lda_k], y0 = b0[kk * ldb_k];
+        const CT x1 = a1[kk * lda_k], y1 = b1[kk * ldb_k];
+        c0 = mfma16(x0, y0, c0);
+        c1 = mfma16(x1, y1, c1);
+      }
     }
   }
 }
@@ -120,9 +132,11 @@ __device__ __forceinline__ void mfma_pair(const CT *a0, const CT *b0, const CT *
 // One chain, for a wave whose last tile has no partner.
 template <typename CT, typename ACC>
 __device__ __forceinline__ void mfma_one(const CT *a0, const CT *b0, int lda_k, int ldb_k, int ksteps, ACC &c0) {
+  for (int k0 = 0; k0 < ksteps; k0 += 16) {
 #pragma unroll
-  for (int k = 0; k < kSwMaxKSteps; ++k) {
-    if (k < ksteps) c0 = mfma16(a0[k * lda_k], b0[k * ldb_k], c0);
+    for (int k = 0; k < 16; ++k) {
+      if (k0 + k < ksteps) c0 = mfma16(a0[(k0 + k) * lda_k], b0[(k0 + k) * ldb_k], c0);
+    }
   }
 }
 
@@ -147,7 +161,7 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
   const int yzs = pl.SI4 * pl.ldz + pl.RA16 * pl.ldy;
   CT *Cs = sm;                               // pl.M1 rows (g, a) x ldc, K = b
   CT *YZ0 = Cs + pl.M1 * pl.ldc;             // [ZR: SI4 x ldz | YL: RA16 x ldy], two buffers
-  CT *Ts = YZ0 + 2 * yzs;                    // RI4 rows (a) x ldt, N = stage-2 columns
+  CT *Ts = YZ0 + pl.nbuf * yzs;              // RI4 rows (a) x ldt, N = stage-2 columns
   const int M1 = gc * RI;                    // valid stage-1 rows
   const int M1p = rup(M1, 16);
 
@@ -317,11 +331,17 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
       }
     }
     if (more) {
-      if (pfr) park(YZ0 + (buf ^ 1) * yzs);
-      else stage_direct(i + 1, YZ0 + (buf ^ 1) * yzs);
+      if (pl.nbuf == 1) {
+        __syncthreads();  // every wave is done with this slice's YL / ZR
+        stage_direct(i + 1, YZ0);
+      } else if (pfr) {
+        park(YZ0 + (buf ^ 1) * yzs);
+      } else {
+        stage_direct(i + 1, YZ0 + (buf ^ 1) * yzs);
+      }
     }
     __syncthreads();  // Ts and the YL / ZR buffer are reused by the next slice
-    buf ^= 1;
+    if (pl.nbuf == 2) buf ^= 1;
   }
 }
 

@@ -223,11 +223,15 @@ def test_precision_option_validation():
 
 
 def test_fp32_unsupported_ranks_fail_at_plan():
-    x = _cpu_tt([4, 80, 80, 4], [1, 4, 70, 4, 1])
+    """The FP32 sandwich runs only on the matrix cores (K <= 128 per
+    product): a factor rank of 130 is refused at plan time; FP64 takes it on
+    its vector kernel."""
+    x = _cpu_tt([4, 160, 160, 4], [1, 4, 130, 4, 1])
+    y = _cpu_tt([4, 160, 160, 4], [1, 4, 4, 4, 1])
     with pytest.raises(HattError) as e:
-        api.plan(x, x, 90, precision="f32")
+        api.plan(x, y, 90, precision="f32")
     assert e.value.status == -7
-    api.plan(x, x, 90)  # FP64 takes it
+    api.plan(x, y, 90)  # FP64 takes it
 
 
 def _uneven_pairs(seed, count):

@@ -23,7 +23,7 @@ TT = List[np.ndarray]
 WORKLOADS = {
     "tiny": dict(d=6, n=4, r=3, ell_exact=9, ell_trunc=4),
     "spectral": dict(d=20, n=32, r=20, ell=40, max_rank=30),
-    "trig": dict(d=3, n=256, r=40, nfreq=20, tol=1e-8, ell2=96, ell3=136),
+    "trig": dict(d=3, n=256, r=40, nfreq=20, tol=1e-8, ell2=96, ell3=128),
     "batched": dict(pairs=512, d=(8, 32), n=(16, 32, 64), r=(8, 48), tol=1e-6),
 }
 
