@@ -195,15 +195,23 @@ __global__ __launch_bounds__(1024) void hh_qr_kernel(HhArgs a) {
 #pragma unroll
     for (int q = 0; q < RPL; ++q) x[t][q] = (lane + 64 * q == c) ? 1.0 : 0.0;
   }
-  for (int j = n - 1; j >= 0; --j) {
-    const double tau = tau_s[j];
-    if (tau == 0.0) continue;  // uniform
-    double v[RPL];
+  // reflector j is read one step ahead of its use
+  double vn[RPL];
+  auto vload = [&](int j, double(&v)[RPL]) {
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       const int r = lane + 64 * q;
-      v[q] = (r > j && r < m) ? Q[r * a.Q.rs + j * a.Q.cs] : (r == j ? 1.0 : 0.0);
+      v[q] = (j >= 0 && r > j && r < m) ? Q[r * a.Q.rs + j * a.Q.cs] : (r == j ? 1.0 : 0.0);
     }
+  };
+  vload(n - 1, vn);
+  for (int j = n - 1; j >= 0; --j) {
+    const double tau = tau_s[j];
+    double v[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) v[q] = vn[q];
+    vload(j - 1, vn);
+    if (tau == 0.0) continue;  // uniform
 #pragma unroll
     for (int t = 0; t < CPW; ++t) {
       const int c = w + 16 * t;
@@ -458,10 +466,12 @@ __global__ __launch_bounds__(1024) void chol1k_kernel(const double *g, int64_t g
       act[s] = (c < n) ? (c > j) : (c < n2 && c <= n + j);
       pc[s] = act[s] ? pr[c] * inv : 0.0;
     }
+    // rows ty + 16 k <= j are final: k below kmin is skipped (wave-uniform)
+    const int kmin = (j + 16 - ty) >> 4;  // first k with ty + 16 k > j
 #pragma unroll
     for (int k = 0; k < KR; ++k) {
       const int i = ty + 16 * k;
-      if (i > j && i < n) {
+      if (k >= kmin && i < n) {
         const double mul = pr[i];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {

@@ -297,6 +297,241 @@ __global__ __launch_bounds__(kBlockThreads) void svd_block_kernel(SvdArgs a, int
   }
 }
 
+// ---------------------------------------------------------------------------
+// Block one-sided Jacobi in registers (64 < nc <= 128, kr <= 128), one
+// workgroup per matrix.  Columns are grouped in blocks of 8 (nb blocks,
+// padded with zero columns to an even count); wave w holds the block pair
+// (top[w], bot[w]): lane group g (lanes 8g .. 8g + 7) holds column g of each
+// block, lane t of the group the rows t + 8 s.  A sweep is
+//   * the pairs inside every block: seven rounds pairing columns g and g ^ x
+//     of the same block (both lane groups form the same dot products from
+//     the same products in the same order, hence the same rotation);
+//   * the pairs across blocks: nb' - 1 block rounds of the circle order
+//     (top[0] fixed, the others move one position), in each of which the
+//     bot block's columns pass the top block's eight lane groups in eight
+//     steps (a shift by one lane group), so every top column meets every
+//     bot column once; the blocks move between waves through LDS.
+// A pair is rotated under the same test as the other Jacobi kernels.  The
+// sums over the 8 lanes of a group use DPP (quad permutes, row half mirror).
+namespace {
+template <int CTRL>
+__device__ __forceinline__ double svd_dpp(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ double g8sum(double v) {
+  v += svd_dpp<0xB1>(v);
+  v += svd_dpp<0x4E>(v);
+  v += svd_dpp<0x141>(v);
+  return v;
+}
+// 1/x and 1/sqrt(x) from the hardware estimates with Newton steps (the
+// estimates are accurate to about 2^-26 relative; each step squares the
+// relative error): x > 0, finite.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
+}
+// Rotation of the pair (x, y) (x plays "p"); returns whether it rotated.
+// The rotation is c = 1/sqrt(1+t^2), s = c t, so c^2 + s^2 = 1 to rounding
+// whatever the accuracy of t (t only steers convergence).
+template <int RPT>
+__device__ __forceinline__ bool jrot(double (&x)[RPT], double (&y)[RPT], double al, double be, double ga, double thr) {
+  if (ga == 0.0 || !(ga * ga > (thr * thr) * (al * be))) return false;
+  const double zeta = (be - al) * (0.5 * rcp_nr(ga));
+  double tt;
+  if (fabs(zeta) < 1e150) {
+    const double q = fma(zeta, zeta, 1.0);
+    const double den = fabs(zeta) + q * rsq_nr(q);  // |zeta| + sqrt(1 + zeta^2)
+    tt = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(den);
+  } else {
+    // t = 1 / (2 zeta) to rounding; none at all for an overflowed zeta
+    tt = isfinite(zeta) ? 0.5 * rcp_nr(zeta) : 0.0;
+  }
+  const double cs = rsq_nr(fma(tt, tt, 1.0)), sn = cs * tt;
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const double u = x[s], v = y[s];
+    x[s] = cs * u - sn * v;
+    y[s] = sn * u + cs * v;
+  }
+  return true;
+}
+}  // namespace
+
+template <int RPT>
+__global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
+  extern __shared__ double slots[];  // 2 h blocks of 8 columns x kr rows: [top 0..h-1 | bot 0..h-1]
+  __shared__ double sig[kSvdMaxN];
+  __shared__ double sigs[kSvdMaxN];
+  __shared__ int perm[kSvdMaxN];
+  __shared__ int s_rot;
+  __shared__ int s_rho;
+  const int kr = a.kr, nc = a.nc;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 3, t = lane & 7;
+  const int p = blockIdx.x;
+  const double *R = a.r + p * a.rbs;
+  int nb = (nc + 7) / 8;
+  nb += nb & 1;
+  const int h = nb / 2;
+  const bool act = w < h;
+  const double thr = jacobi_tau(kr);
+  const int bsz = 8 * kr;  // doubles per block slot
+  double tv[RPT], bv[RPT];
+  // initial blocks: top[w] = block w, bot[w] = block nb - 1 - w
+  {
+    const int ct = 8 * w + g, cb = 8 * (nb - 1 - w) + g;
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      const int r = t + 8 * s;
+      tv[s] = (act && r < kr && ct < nc) ? R[r * nc + ct] : 0.0;
+      bv[s] = (act && r < kr && cb < nc) ? R[r * nc + cb] : 0.0;
+    }
+  }
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) s_rot = 0;
+    int rot = 0;
+    if (act) {
+      // pairs inside each block
+      for (int x = 1; x < 8; ++x) {
+        const bool isp = g < (g ^ x);
+        double pt[RPT], pb[RPT];
+#pragma unroll
+        for (int s = 0; s < RPT; ++s) {
+          pt[s] = __shfl_xor(tv[s], 8 * x);
+          pb[s] = __shfl_xor(bv[s], 8 * x);
+        }
+        double a1 = 0.0, b1 = 0.0, g1 = 0.0, a2 = 0.0, b2 = 0.0, g2 = 0.0;
+#pragma unroll
+        for (int s = 0; s < RPT; ++s) {
+          const double lo1 = isp ? tv[s] : pt[s], hi1 = isp ? pt[s] : tv[s];
+          const double lo2 = isp ? bv[s] : pb[s], hi2 = isp ? pb[s] : bv[s];
+          a1 += lo1 * lo1;
+          b1 += hi1 * hi1;
+          g1 += lo1 * hi1;
+          a2 += lo2 * lo2;
+          b2 += hi2 * hi2;
+          g2 += lo2 * hi2;
+        }
+        a1 = g8sum(a1);
+        b1 = g8sum(b1);
+        g1 = g8sum(g1);
+        a2 = g8sum(a2);
+        b2 = g8sum(b2);
+        g2 = g8sum(g2);
+        // each lane group updates only its own column of the pair
+        if (isp) {
+          rot |= jrot<RPT>(tv, pt, a1, b1, g1, thr);
+          rot |= jrot<RPT>(bv, pb, a2, b2, g2, thr);
+        } else {
+          rot |= jrot<RPT>(pt, tv, a1, b1, g1, thr);
+          rot |= jrot<RPT>(pb, bv, a2, b2, g2, thr);
+        }
+      }
+    }
+    for (int br = 0; br < nb - 1; ++br) {
+      if (act) {
+        for (int st = 0; st < 8; ++st) {
+          double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+          for (int s = 0; s < RPT; ++s) {
+            al += tv[s] * tv[s];
+            be += bv[s] * bv[s];
+            ga += tv[s] * bv[s];
+          }
+          al = g8sum(al);
+          be = g8sum(be);
+          ga = g8sum(ga);
+          rot |= jrot<RPT>(tv, bv, al, be, ga, thr);
+          // the bot columns move on to the next lane group
+#pragma unroll
+          for (int s = 0; s < RPT; ++s) bv[s] = __shfl(bv[s], (lane + 8) & 63);
+        }
+        // circle order: publish both blocks
+#pragma unroll
+        for (int s = 0; s < RPT; ++s) {
+          const int r = t + 8 * s;
+          if (r < kr) {
+            slots[w * bsz + g * kr + r] = tv[s];
+            slots[(h + w) * bsz + g * kr + r] = bv[s];
+          }
+        }
+      }
+      __syncthreads();
+      if (act) {
+        const int st = (w == 0) ? 0 : (w == 1 ? h : w - 1);   // new top: top[0] stays, top[1] <- bot[0]
+        const int sb = (w == h - 1) ? (h - 1) : (h + w + 1);  // new bot: bot[h-1] <- top[h-1]
+#pragma unroll
+        for (int s = 0; s < RPT; ++s) {
+          const int r = t + 8 * s;
+          tv[s] = (r < kr) ? slots[st * bsz + g * kr + r] : 0.0;
+          bv[s] = (r < kr) ? slots[sb * bsz + g * kr + r] : 0.0;
+        }
+      }
+      __syncthreads();
+    }
+    if (rot) s_rot = 1;
+    __syncthreads();
+    if (s_rot == 0) break;
+    __syncthreads();
+  }
+  // final columns into the slots (column index 8 * slot + g), norms, order
+  double *A = slots;  // column c at A + c * kr
+  if (act) {
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      const int r = t + 8 * s;
+      if (r < kr) {
+        A[(8 * w + g) * kr + r] = tv[s];
+        A[(8 * (h + w) + g) * kr + r] = bv[s];
+      }
+    }
+  }
+  __syncthreads();
+  const int ncp = 8 * nb;
+  for (int c = tid; c < ncp; c += 512) {
+    double s2 = 0.0;
+    for (int r = 0; r < kr; ++r) s2 += A[c * kr + r] * A[c * kr + r];
+    sig[c] = sqrt(s2);
+  }
+  __syncthreads();
+  for (int c = tid; c < ncp; c += 512) {
+    int rk = 0;
+    const double sc = sig[c];
+    for (int j = 0; j < ncp; ++j) rk += (sig[j] > sc) || (sig[j] == sc && j < c);
+    perm[rk] = c;
+    sigs[rk] = sc;
+  }
+  __syncthreads();
+  if (tid == 0) s_rho = choose_rank(sigs, kr, nc, a, p);
+  __syncthreads();
+  const int rho = s_rho;
+  double *U = a.u + p * a.ubs;
+  for (int e = tid; e < kr * a.ucap; e += 512) {
+    const int r = e / a.ucap, j = e - r * a.ucap;
+    double v = 0.0;
+    if (j < rho) {
+      const int c = perm[j];
+      const double sc = sigs[j];
+      v = (sc > 0.0) ? A[c * kr + r] / sc : 0.0;
+    }
+    U[e] = v;
+  }
+}
+
 hipError_t launch_svd_trunc(const SvdArgs &a, hipStream_t s) {
   if (a.batch <= 0) return hipSuccess;
   if (a.kr > a.nc || a.kr < 1) return hipErrorInvalidValue;
@@ -306,6 +541,23 @@ hipError_t launch_svd_trunc(const SvdArgs &a, hipStream_t s) {
     if (a.kr <= 40) return svd_wave_launch<40>(a, s);
     if (a.kr <= 48) return svd_wave_launch<48>(a, s);
     return svd_wave_launch<64>(a, s);
+  }
+  if (a.nc <= 128 && a.kr <= 128) {
+    // register block Jacobi: the slots hold the whole (padded) matrix
+    int nb = (a.nc + 7) / 8;
+    nb += nb & 1;
+    const size_t lds = (size_t)nb * 8 * a.kr * sizeof(double);
+    static bool attr_bj = false;
+    if (!attr_bj) {
+      hipFuncSetAttribute((const void *)svd_bj_kernel<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(16 * 8 * 128 * sizeof(double)));
+      hipFuncSetAttribute((const void *)svd_bj_kernel<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(16 * 8 * 128 * sizeof(double)));
+      attr_bj = true;
+    }
+    if (a.kr <= 64) svd_bj_kernel<8><<<a.batch, 512, lds, s>>>(a);
+    else svd_bj_kernel<16><<<a.batch, 512, lds, s>>>(a);
+    return hipGetLastError();
   }
   if (a.nc > kSvdMaxN || (int64_t)a.nc * a.kr > kQrLdsDoubles) return hipErrorInvalidValue;
   const int np = a.nc + (a.nc & 1);
