@@ -115,6 +115,22 @@ HATT_API hatt_status hatt_recompress(const hatt_tt *x, const hatt_tt *y, const h
                             int64_t *out_rank, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * hatt_recompress_noalloc -- hatt_recompress for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same computation and
+ * arguments without the workspace, which is a library-owned static device
+ * array of 128 MiB (one per device, held until the process ends; nothing is
+ * allocated by the call).  A problem whose hatt_plan workspace exceeds
+ * 128 MiB returns HATT_EWORKSPACE before anything is enqueued.  Every call on
+ * a device uses that device's one array: calls that overlap on one device
+ * (other streams, other host threads) race and must be serialised by the
+ * caller; the array keeps the last call's contents, which no call relies on.
+ */
+HATT_API hatt_status hatt_recompress_noalloc(const hatt_tt *x, const hatt_tt *y, const hatt_tt *sketch,
+                                             const hatt_opts *opts, double *out, int64_t out_stride,
+                                             int64_t *out_rank, void *stream);
+
+/*
  * Uneven batches: npairs independent recompressions x[p] (.) y[p] whose
  * shapes (order, mode sizes, ranks, batch) differ from pair to pair; each
  * pair is the hatt_recompress problem above.  opts applies to every pair

@@ -31,6 +31,7 @@ from .api import (  # noqa: F401
     recompress,
     recompress_adaptive,
     recompress_batched,
+    recompress_noalloc,
     round,
     round_plan,
     set_qr_method,

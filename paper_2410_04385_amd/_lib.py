@@ -17,7 +17,7 @@ STATUS_NAMES = {
 }
 
 EXPORTED = [
-    "hatt_plan", "hatt_recompress", "hatt_adaptive_plan", "hatt_recompress_adaptive", "tt_hadamard_explicit", "tt_round_plan", "tt_round",
+    "hatt_plan", "hatt_recompress", "hatt_recompress_noalloc", "hatt_adaptive_plan", "hatt_recompress_adaptive", "tt_hadamard_explicit", "tt_round_plan", "tt_round",
     "tt_norm_plan", "tt_norm", "hatt_sketch_fill", "hatt_profile_start", "hatt_profile_stop",
     "hatt_profile_class_name", "hatt_last_error", "hatt_version", "hatt_set_qr_method",
     "hatt_profile_report", "hatt_batched_plan", "hatt_recompress_batched",
@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
     szp = ctypes.POINTER(ctypes.c_size_t)
     L.hatt_plan.argtypes = [ttp, ttp, optp, i64p, szp, i64p]
     L.hatt_recompress.argtypes = [ttp, ttp, ttp, optp, vp, ctypes.c_int64, vp, vp, ctypes.c_size_t, vp]
+    L.hatt_recompress_noalloc.argtypes = [ttp, ttp, ttp, optp, vp, ctypes.c_int64, vp, vp]
     aop = ctypes.POINTER(HattAdaptOpts)
     L.hatt_adaptive_plan.argtypes = [ttp, ttp, aop, i64p, szp, i64p]
     L.hatt_recompress_adaptive.argtypes = [ttp, ttp, aop, vp, ctypes.c_int64, vp, i64p,

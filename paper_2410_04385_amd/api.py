@@ -171,6 +171,32 @@ def recompress(x: TT, y: TT, ell, *, max_rank: int = 0, tol: float = 0.0, seed: 
     return Result(out, ranks)
 
 
+def recompress_noalloc(x: TT, y: TT, ell, *, max_rank: int = 0, tol: float = 0.0, seed: int = 0,
+                       sketch: Optional[TT] = None, variant: int = 1, ep: float = 0.0, precision: str = "f64",
+                       out: Optional[TT] = None, ranks: Optional[torch.Tensor] = None, stream=None) -> Result:
+    """recompress() on the library's static scratch array (no workspace):
+    for problems whose workspace fits in 128 MiB."""
+    p = plan(x, y, ell, max_rank, tol, seed, variant, ep, precision)
+    dev = x.data.device
+    if out is None:
+        out = TT.empty(x.n, p["ell"], x.batch, device=dev)
+    if ranks is None:
+        ranks = torch.empty((x.batch, x.d + 1), dtype=torch.int64, device=dev)
+    xv, kx = x.view()
+    yv, ky = y.view()
+    o, ka = _opts(ell, max_rank, tol, seed, variant, ep, x.d, precision)
+    sk_ptr = None
+    keep = None
+    if sketch is not None:
+        sv, keep = sketch.view()
+        sk_ptr = ctypes.byref(sv)
+    st = lib().hatt_recompress_noalloc(ctypes.byref(xv), ctypes.byref(yv), sk_ptr, ctypes.byref(o),
+                                       ctypes.c_void_p(out.data.data_ptr()), out.stride,
+                                       ctypes.c_void_p(ranks.data_ptr()), _stream_ptr(stream))
+    check("hatt_recompress_noalloc", st)
+    return Result(out, ranks)
+
+
 def batched_plan(pairs, ell: int = 0, *, max_rank: int = 0, tol: float = 0.0, seed: int = 0, variant: int = 1,
                  ep: float = 0.0):
     """Plan of recompress_batched: per-pair output and rank offsets, widths,

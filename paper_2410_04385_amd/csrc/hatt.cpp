@@ -21,6 +21,15 @@
 
 using namespace hatt;
 
+// Scratch of hatt_recompress_noalloc: a library-owned device array used in
+// place of a caller workspace, for callers that cannot allocate device
+// memory.  In host code `hatt_scratch` names a host-side stand-in; its
+// device address comes from hipGetSymbolAddress, resolved once per device
+// (each device holds its own copy, kept until the process ends) and used
+// wherever host code needs the array.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) char hatt_scratch[kScratchBytes];
+
 namespace {
 
 thread_local std::string g_err;
@@ -73,6 +82,27 @@ hatt_status read_tt(const hatt_tt *t, const char *name, Shape *s, bool need_data
   s->stride = t->batch_stride ? t->batch_stride : s->total;
   s->data = t->data;
   if (need_data && s->data == nullptr) return fail(HATT_EINVAL, std::string(name) + ": NULL data");
+  return HATT_OK;
+}
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;
+
+hatt_status scratch_address(void **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(HATT_EDEVICE, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return HATT_OK;
+  }
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(hatt_scratch));
+  if (e != hipSuccess || p == nullptr)
+    return fail(HATT_EDEVICE, std::string("hipGetSymbolAddress of the scratch array failed: ") + hipGetErrorString(e));
+  g_scratch_ptr[dev] = p;
+  *out = p;
   return HATT_OK;
 }
 
@@ -1373,6 +1403,22 @@ hatt_status hatt_recompress(const hatt_tt *x, const hatt_tt *y, const hatt_tt *s
   st = hatt_run(true, sp, w, (hipStream_t)stream);
   if (st == HATT_OK) g_err.clear();
   return st;
+}
+
+hatt_status hatt_recompress_noalloc(const hatt_tt *x, const hatt_tt *y, const hatt_tt *sketch, const hatt_opts *opts,
+                                    double *out, int64_t out_stride, int64_t *out_rank, void *stream) {
+  // the size check is host-only and comes before any device call
+  size_t need = 0;
+  hatt_status st = hatt_plan(x, y, opts, nullptr, &need, nullptr);
+  if (st != HATT_OK) return st;
+  if (need > kScratchBytes)
+    return fail(HATT_EWORKSPACE, "hatt_recompress_noalloc: the problem needs " + std::to_string(need) +
+                                     " bytes of scratch; the library's static scratch holds " +
+                                     std::to_string(kScratchBytes) + " (use hatt_recompress with a workspace)");
+  void *ws = nullptr;
+  st = scratch_address(&ws);
+  if (st != HATT_OK) return st;
+  return hatt_recompress(x, y, sketch, opts, out, out_stride, out_rank, ws, kScratchBytes, stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -309,3 +309,18 @@ def test_plan_rejects_sandwich_shapes_without_a_kernel():
     # u2 * u (ranks 81 and 40) is covered
     p = api.plan(_cpu_tt(n, r), _cpu_tt(n, [1, 40, 40, 1]), 136, tol=1e-8)
     assert p["ell"] == [1, 136, 136, 1]
+
+
+def test_noalloc_rejects_problems_beyond_its_scratch_before_any_device_call():
+    """The static-scratch entry point checks the workspace need on the host:
+    the 256^3 trig product needs about 1 GB, beyond the 128 MiB array, and
+    is refused with HATT_EWORKSPACE (no GPU is touched, so this runs here)."""
+    n = [256, 256, 256]
+    u = _cpu_tt(n, [1, 40, 40, 1])
+    class _NullStream:
+        cuda_stream = 0
+
+    with pytest.raises(HattError) as ei:
+        api.recompress_noalloc(u, u, 96, tol=1e-8, out=_cpu_tt(n, [1, 96, 96, 1]),
+                               ranks=torch.zeros((1, 4), dtype=torch.int64), stream=_NullStream())
+    assert ei.value.status == -3 and "scratch" in str(ei.value)
