@@ -217,6 +217,21 @@ def _bench_batched(args, torch, wk, H) -> int:
     return 0
 
 
+def _calib_copy(args, torch):
+    """One plain device copy of --calib-copy-mib MiB: the reference dispatch
+    that scales the hardware byte counters of a profiled run."""
+    if args.calib_copy_mib <= 0:
+        return
+    nbytes = args.calib_copy_mib << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"[bench] calibration copy of {nbytes} bytes done", file=sys.stderr, flush=True)
+    del src, dst
+
+
 def _full_np(cores):
     """Full tensor of a TT (host numpy cores), for the pointwise error check
     against the closed-form product."""
@@ -263,6 +278,7 @@ def _bench_trig(args, torch, wk, H, perfmodel) -> int:
         r3 = u3_step(U2)
         return r2, U2, r3
 
+    _calib_copy(args, torch)
     say(f"trig 256^3: u2 at width {l2}, u3 at width {l3}, tol {tol:g}, precision {args.precision}")
     for _ in range(max(args.warmup, 1)):
         r2, U2, r3 = step()
@@ -512,15 +528,7 @@ def main() -> int:
     ranks = torch.empty((B, d + 1), dtype=torch.int64, device="cuda")
     ws = torch.empty(p["ws_bytes"], dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
-    if args.calib_copy_mib > 0:
-        nbytes = args.calib_copy_mib << 20
-        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(f"[bench] calibration copy of {nbytes} bytes done", file=sys.stderr, flush=True)
-        del src, dst
+    _calib_copy(args, torch)
 
     def step():
         H.recompress(x, y, ell, max_rank=cap, seed=seed, workspace=ws, out=out, ranks=ranks,

@@ -197,7 +197,7 @@ hipError_t launch_gram_chol(CMat A, int64_t m, int n, double *r, double *rinv, i
 
 // ---- Householder QR of short matrices, triangular inverse, Cholesky of
 // larger Gram matrices, row sketch (k_hh.hip) --------------------------------
-// Householder QR of A (m x n per pair, n <= 128, n <= m <= 512 for n <= 64,
+// Householder QR of A (m x n per pair, n <= 128, n <= m <= 384 for n <= 64,
 // else <= 256), one workgroup per pair: Q (m x n, explicit, when Q.ptr) and
 // R (n x n upper, when R.ptr), diag(R) >= 0.  A may be the same buffer as Q.
 // Pairs with skip_flag[p * skip_stride] == 1 are left untouched.

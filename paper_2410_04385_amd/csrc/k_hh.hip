@@ -1,6 +1,6 @@
 // Dense kernels for the QR of tall frames that may be rank deficient:
 //
-//  * hh_qr_kernel: economy Householder QR of one short matrix (m <= 512
+//  * hh_qr_kernel: economy Householder QR of one short matrix (m <= 384
 //    rows for n <= 64 columns, m <= 256 for n <= 128) per workgroup, the matrix resident in registers.
 //    This is the QR Alg. 4 asks for (the paper's econ-QR), exact for rank
 //    deficient input: whatever the rank, Q has orthonormal columns and
@@ -52,6 +52,42 @@ __device__ __forceinline__ double group8_sum(double v) {
   return v;
 }
 
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, src);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Wave sums of 8 values per lane at once (a reduce-scatter): halving
+// exchanges across lanes 32, 16 and 8 apart leave lanes 8t .. 8t+7 with
+// partial sums of value t, an 8-lane sum completes them, and lane 8t
+// broadcasts.  out[t] = sum over the 64 lanes of d[t], the same in every
+// lane.
+__device__ __forceinline__ void wave_sum8(const double (&d)[8], double (&out)[8]) {
+  const int lane = threadIdx.x & 63;
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+  double e[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double keep = b5 ? d[k + 4] : d[k], give = b5 ? d[k] : d[k + 4];
+    e[k] = keep + __shfl_xor(give, 32);
+  }
+  double f[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double keep = b4 ? e[k + 2] : e[k], give = b4 ? e[k] : e[k + 2];
+    f[k] = keep + __shfl_xor(give, 16);
+  }
+  double g = (b3 ? f[1] : f[0]) + __shfl_xor(b3 ? f[0] : f[1], 8);
+  g += dpp_d<0xB1>(g);
+  g += dpp_d<0x4E>(g);
+  g += dpp_d<0x141>(g);
+  // lanes 8t..8t+7 hold value t' with t' = (lane>>3 & 1) + 2 (lane>>4 & 1) + 4 (lane>>5 & 1)
+#pragma unroll
+  for (int t = 0; t < 8; ++t) out[t] = lane_bcast(g, 8 * t);
+}
+
 __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   // integer finaliser of MurmurHash3 (Appleby)
   x ^= x >> 16;
@@ -71,6 +107,33 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
 // x(2:) = 0 gives tau = 0.  Q = H_0 H_1 ... H_{n-1} [I_n; 0] is formed by
 // backward accumulation.  Finally rows of R and columns of Q are flipped so
 // that diag(R) >= 0.
+// x(:, c) -= tau v (v^T x(:, c)) for the wave's columns c with c0 <= c < n.
+template <int CPW, int RPL>
+__device__ __forceinline__ void hh_apply(double (&x)[CPW][RPL], const double (&v)[RPL], double tau, int w, int c0,
+                                         int n) {
+  static_assert(CPW % 4 == 0 && CPW <= 8, "column slots");
+  if (w + 16 * (CPW - 1) < c0) return;  // no live column (wave-uniform)
+  double d[8], sum[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    d[t] = 0.0;
+    if (t < CPW) {
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) d[t] += v[q] * x[t < CPW ? t : 0][q];
+    }
+  }
+  wave_sum8(d, sum);
+#pragma unroll
+  for (int t = 0; t < CPW; ++t) {
+    const int c = w + 16 * t;
+    if (c >= c0 && c < n) {  // uniform per wave
+      const double f = tau * sum[t];
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) x[t][q] -= f * v[q];
+    }
+  }
+}
+
 template <int CPW, int RPL>
 __global__ __launch_bounds__(1024) void hh_qr_kernel(HhArgs a) {
   constexpr int MR = 64 * RPL;
@@ -144,18 +207,7 @@ __global__ __launch_bounds__(1024) void hh_qr_kernel(HhArgs a) {
     double v[RPL];
 #pragma unroll
     for (int q = 0; q < RPL; ++q) v[q] = vb[lane + 64 * q];
-#pragma unroll
-    for (int t = 0; t < CPW; ++t) {
-      const int c = w + 16 * t;
-      if (c > j && c < n) {  // uniform per wave
-        double dot = 0.0;
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) dot += v[q] * x[t][q];
-        const double f = tau * wave_sum(dot);
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) x[t][q] -= f * v[q];
-      }
-    }
+    hh_apply<CPW, RPL>(x, v, tau, w, j + 1, n);
   }
   __syncthreads();
   // R: rows i <= c of column c, sign-flipped per row
@@ -212,18 +264,7 @@ __global__ __launch_bounds__(1024) void hh_qr_kernel(HhArgs a) {
     for (int q = 0; q < RPL; ++q) v[q] = vn[q];
     vload(j - 1, vn);
     if (tau == 0.0) continue;  // uniform
-#pragma unroll
-    for (int t = 0; t < CPW; ++t) {
-      const int c = w + 16 * t;
-      if (c >= j && c < n) {
-        double dot = 0.0;
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) dot += v[q] * x[t][q];
-        const double f = tau * wave_sum(dot);
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) x[t][q] -= f * v[q];
-      }
-    }
+    hh_apply<CPW, RPL>(x, v, tau, w, j, n);
   }
   __syncthreads();  // every reflector has been read
 #pragma unroll
@@ -240,7 +281,7 @@ __global__ __launch_bounds__(1024) void hh_qr_kernel(HhArgs a) {
   }
 }
 
-bool hh_qr_supported(int64_t m, int64_t n) { return n >= 1 && n <= 128 && m >= n && m <= (n <= 64 ? 512 : 256); }
+bool hh_qr_supported(int64_t m, int64_t n) { return n >= 1 && n <= 128 && m >= n && m <= (n <= 64 ? 384 : 256); }
 
 hipError_t launch_hh_qr(const HhArgs &a, int batch, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
@@ -249,7 +290,7 @@ hipError_t launch_hh_qr(const HhArgs &a, int batch, hipStream_t s) {
   if (a.n <= 64) {
     if (m <= 128) hh_qr_kernel<4, 2><<<batch, 1024, 0, s>>>(a);
     else if (m <= 256) hh_qr_kernel<4, 4><<<batch, 1024, 0, s>>>(a);
-    else hh_qr_kernel<4, 8><<<batch, 1024, 0, s>>>(a);
+    else hh_qr_kernel<4, 6><<<batch, 1024, 0, s>>>(a);
   } else {
     if (m <= 128) hh_qr_kernel<8, 2><<<batch, 1024, 0, s>>>(a);
     else hh_qr_kernel<8, 4><<<batch, 1024, 0, s>>>(a);
@@ -261,7 +302,7 @@ const char *hh_qr_kernel_name(int64_t m, int64_t n) {
   if (n <= 64) {
     if (m <= 128) return "hh_qr_kernel<4, 2>";
     if (m <= 256) return "hh_qr_kernel<4, 4>";
-    return "hh_qr_kernel<4, 8>";
+    return "hh_qr_kernel<4, 6>";
   }
   if (m <= 128) return "hh_qr_kernel<8, 2>";
   return "hh_qr_kernel<8, 4>";
