@@ -37,6 +37,8 @@ def _parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-explicit", action="store_true")
+    ap.add_argument("--no-cpu-explicit", action="store_true",
+                    help="trig: skip the host oracle's explicit PKP + TT-Rounding of u2 (5.2 GB core)")
     ap.add_argument("--eager", action="store_true", help="launch kernels directly instead of replaying a HIP graph")
     ap.add_argument("--precision", choices=["f64", "f32"], default="f64",
                     help="f32: range finding on the FP32 matrix cores, projection and truncation in FP64")
@@ -326,6 +328,39 @@ def _bench_trig(args, torch, wk, H, perfmodel) -> int:
     f3 = perfmodel.hatt_round_flops(U.n, U2.ranks, U.ranks, ell3, max(ell3))["total"]
     value = 2 * args.steps / wall_s
 
+    # the comparator of the metric: explicit PKP cores (ranks 1600 and 3240)
+    # then TT-Rounding at the same tolerance, on the same GPU
+    explicit = None
+    if not args.no_explicit:
+        explicit = {}
+        for name, (a_tt, b_tt) in (("u2", (U, U)), ("u3", (U2, U))):
+            try:
+                H.round(H.hadamard_explicit(a_tt, b_tt), tol=tol)  # warm-up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                z = H.hadamard_explicit(a_tt, b_tt)
+                torch.cuda.synchronize()
+                t_pkp = time.perf_counter() - t0
+                t0 = time.perf_counter()
+                zr = H.round(z, tol=tol)
+                torch.cuda.synchronize()
+                t_round = time.perf_counter() - t0
+                ge = zr.train(0)
+                ref = fu ** 2 if name == "u2" else fu ** 3
+                err = float(np.linalg.norm(_full_np(ge) - ref) / np.linalg.norm(ref))
+                explicit[name] = {"pkp_ms": 1000 * t_pkp, "pkp_GBs": z.total * 8 / t_pkp / 1e9,
+                                  "round_ms": 1000 * t_round, "ranks": zr.ranks[0].tolist(),
+                                  "rel_err_vs_closed_form": err,
+                                  "hatt_speedup": (t_pkp + t_round) / ((t2 if name == "u2" else t3) / 1000.0)}
+                del z, zr
+                torch.cuda.empty_cache()
+            except HattError as e:
+                explicit[name] = {"status": f"unsupported: {e}"}
+        ok = [explicit[k] for k in ("u2", "u3") if "round_ms" in explicit[k]]
+        if len(ok) == 2:
+            explicit["recompressions_per_s"] = 2.0 / sum((e["pkp_ms"] + e["round_ms"]) / 1000.0 for e in ok)
+            explicit["hatt_speedup"] = value / explicit["recompressions_per_s"]
+
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
@@ -347,6 +382,14 @@ def _bench_trig(args, torch, wk, H, perfmodel) -> int:
                "u2_s": ta, "u3_s": tb}
         parity = {"u2_rel_err_vs_oracle": tt.rel_err(g2, ref2), "u3_rel_err_vs_oracle": tt.rel_err(g3, ref3),
                   "u2_oracle_ranks": tt.ranks(ref2), "u3_oracle_ranks": tt.ranks(ref3)}
+        if not args.no_cpu_explicit:
+            # the comparator on the host: the oracle's explicit PKP cores of u2
+            # (a 5.2 GB middle core) and its TT-Rounding at the same tolerance
+            t0 = time.perf_counter()
+            re2 = rounding.tt_round(tt.pkp(u, u), tol=tol)
+            cpu["explicit_pkp_round_u2_s"] = time.perf_counter() - t0
+            cpu["explicit_pkp_round_u2_ranks"] = tt.ranks(re2)
+            del re2
 
     line = {
         "metric": "HaTT recompressions/s + GB/s/MFMA% vs explicit-PKP rounding, 1 GPU @ rel err 1e-8",
@@ -376,6 +419,7 @@ def _bench_trig(args, torch, wk, H, perfmodel) -> int:
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity": parity,
+        "explicit_pkp_rounding_gpu": explicit,
     }
     print(json.dumps(line), flush=True)
     return 0
@@ -505,6 +549,7 @@ def main() -> int:
     import paper_2410_04385_amd as H
     from paper_2410_04385_amd import perfmodel
     from paper_2410_04385_amd._lib import HattError
+    globals()["HattError"] = HattError
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)

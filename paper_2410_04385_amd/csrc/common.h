@@ -214,8 +214,8 @@ const char *hh_qr_kernel_name(int64_t m, int64_t n);
 // X = R^{-1} of upper triangular R (n x n row-major, n <= 128); flag as in
 // launch_chol (cleared by a zero or non-finite diagonal entry; may be null).
 // With mask (int [n] per pair, stride mbs): columns whose diagonal entry is
-// at most 1e-13 of the largest are replaced by a unit column (scaled to the
-// largest diagonal entry) before inversion and marked 1.
+// at most 1e-12 of the column's norm are replaced by a unit column (scaled
+// to the largest diagonal entry) before inversion and marked 1.
 hipError_t launch_trinv(const double *r, int64_t rbs, double *x, int64_t xbs, int n, int *flag, int64_t fstride,
                         int first, int *mask, int64_t mbs, int batch, hipStream_t s);
 // Replace the masked columns of A (m x n row-major, pair stride abs) by
@@ -227,10 +227,19 @@ hipError_t launch_complete_cols(double *a, int64_t m, int n, int64_t abs_, const
 hipError_t launch_chol1k(const double *g, int64_t gbs, double *r, double *rinv, int64_t rbs, int n, int *flag,
                          int64_t fstride, int first, double thr_rel, int batch, hipStream_t s);
 // B = Omega A (k x n row-major per pair, pair stride bbs): row r of B is the
-// signed sum of the rows r, r + k, r + 2k, ... of A (m rows), signs hashed
-// from the row index and key.
+// signed sum of the rows pi(r), pi(r + k), pi(r + 2k), ... of A (m < 2^31
+// rows), pi a pseudo-random permutation and the signs hashed from the row
+// index, both keyed by key.
 hipError_t launch_sketch_rows(CMat A, int64_t m, int n, int k, double *b, int64_t bbs, uint32_t key, int batch,
                               hipStream_t s);
+
+// Block Gram-Schmidt: mark the columns of a projected panel W (m x cw, cw <=
+// 128) whose residual is at most rel of the column's norm before projection
+// (||S1_j||^2 + ||W_j||^2), and replace them by random unit vectors.
+hipError_t launch_panel_dep(Mat W, CMat S1, int64_t m, int64_t c0, int cw, int *mask, int64_t mbs, double rel,
+                            uint32_t key, int batch, hipStream_t s);
+// Zero the masked columns of R (rows x cw).
+hipError_t launch_zero_masked_cols(Mat R, int rows, int cw, const int *mask, int64_t mbs, int batch, hipStream_t s);
 
 // ---- Jacobi SVD + rank choice (k_svd.hip) ----------------------------------
 // For each pair: R (kr x nc, row-major, kr <= nc <= kSvdMaxN) = U S V^T by

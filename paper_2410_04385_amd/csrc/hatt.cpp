@@ -318,6 +318,7 @@ struct QrOp {
   std::shared_ptr<QrOp> sub;
   QrPlan direct{};
   std::vector<QrOp> panels;          // big: one QR per panel (CholeskyQR2 or TSQR)
+  int64_t panel = 0;                 // big: panel width
   int64_t ws_doubles = 0;  // per pair
   int64_t ws_tree = 0;     // big: TSQR tree part at the front; chol: fallback TSQR tree
 };
@@ -391,17 +392,22 @@ bool qr_prepare(int64_t m, int64_t n, QrOp *op) {
   }
   op->big = true;
   op->panels.clear();
+  // panels: preconditioned CholeskyQR2 takes 128 columns; a Householder TSQR
+  // panel (method 1) at most 64, where a tree of >= 2n-row blocks exists
+  const int64_t panel = g_use_chol ? kPanel : 64;
+  if (n <= panel) return false;  // a single panel would recurse into this same shape
   int64_t w = 0;
-  for (int64_t c0 = 0; c0 < n; c0 += kPanel) {
-    const int64_t cw = std::min(kPanel, n - c0);
+  for (int64_t c0 = 0; c0 < n; c0 += panel) {
+    const int64_t cw = std::min(panel, n - c0);
     QrOp pl;
     if (!qr_prepare(m, cw, &pl) || pl.big || pl.wide) return false;
     op->panels.push_back(pl);
     w = std::max(w, pl.ws_doubles);
   }
   op->ws_tree = w;
-  // panel QR scratch + S1, S2 (n x kPanel each) + R1, R2 (kPanel x kPanel each)
-  op->ws_doubles = w + 2 * n * kPanel + 2 * kPanel * kPanel;
+  op->panel = panel;
+  // panel QR scratch + S1, S2 (n x panel each) + R1, R2 (panel x panel each) + dependence mask
+  op->ws_doubles = w + 2 * n * panel + 2 * panel * panel + panel;
   return true;
 }
 
@@ -422,7 +428,7 @@ struct QrDeferred {
 };
 
 hatt_status pchol_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double *ws, int64_t wsp, int P,
-                       GemmCtx &gc, hipStream_t st, QrDeferred *def) {
+                       GemmCtx &gc, hipStream_t st, QrDeferred *def, uint32_t salt) {
   const int64_t m = op.m, n = op.n, k = op.sk_rows;
   double *q1 = ws + op.ws_tree;  // m x n row-major
   double *g = q1 + m * n;
@@ -458,7 +464,7 @@ hatt_status pchol_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double *w
   sg = gemm(run, gc, A, CMat{R0i, n, 1, wsp}, Mat{ap, n, 1, wsp}, m, n, n, 1.0, 0.0, P, st, false);
   if (sg != HATT_OK) return sg;
   site("pchol complete %lldx%lld", (long long)m, (long long)n);
-  LAUNCH(launch_complete_cols(ap, m, (int)n, wsp, mask, mbs, 0x7F4A7C15u, P, st));
+  LAUNCH(launch_complete_cols(ap, m, (int)n, wsp, mask, mbs, 0x7F4A7C15u ^ (salt * 0x9E3779B9u), P, st));
   // CholeskyQR2 of A'
   sg = gemm(run, gc, apt, apc, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true);
   if (sg != HATT_OK) return sg;
@@ -554,8 +560,10 @@ hatt_status cholqr2_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double 
 
 // A (m x n), Q (m x k), R (k x n row-major with row stride r.rs, or null).
 // R, when given, must be a contiguous per-pair block of rbuf doubles.
+// salt: distinguishes the random completion vectors of the QRs of one block
+// Gram-Schmidt (its panels and passes share one column space).
 hatt_status qr_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, int64_t rbuf, double *ws, int64_t wsp,
-                    int P, GemmCtx &gc, hipStream_t st, QrDeferred *def = nullptr) {
+                    int P, GemmCtx &gc, hipStream_t st, QrDeferred *def = nullptr, uint32_t salt = 0) {
   ClassScope cls(P_QR);
   if (op.wide) {
     hatt_status s0 = qr_exec(run, *op.sub, A, Q, R, rbuf, ws, wsp, P, gc, st);
@@ -579,7 +587,8 @@ hatt_status qr_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, int64_t rbuf
     return HATT_OK;
   }
   // many pairs of at most 64 columns: the fused Gram + Cholesky blocks
-  if (op.pchol && !(op.chol && P >= kCholFuseMinPairs)) return pchol_exec(run, op, A, Q, R, ws, wsp, P, gc, st, def);
+  if (op.pchol && !(op.chol && P >= kCholFuseMinPairs))
+    return pchol_exec(run, op, A, Q, R, ws, wsp, P, gc, st, def, salt);
   if (op.chol) return cholqr2_exec(run, op, A, Q, R, ws, wsp, P, gc, st, def);
   if (!op.big) {
     site("tsqr %lldx%lld", (long long)op.m, (long long)op.n);
@@ -588,21 +597,22 @@ hatt_status qr_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, int64_t rbuf
   }
   const int64_t m = op.m, n = op.n;
   double *s1buf = ws + op.ws_tree;
-  double *s2buf = s1buf + n * kPanel;
-  double *r1buf = s2buf + n * kPanel;
-  double *r2buf = r1buf + kPanel * kPanel;
+  double *s2buf = s1buf + n * op.panel;
+  double *r1buf = s2buf + n * op.panel;
+  double *r2buf = r1buf + op.panel * op.panel;
+  int *pmask = reinterpret_cast<int *>(r2buf + op.panel * op.panel);
   LAUNCH(launch_copy(A, Q, m, n, P, st));
   if (R.ptr) LAUNCH(launch_fill(R.ptr, (int64_t)P * rbuf, 0.0, st));
   int pi = 0;
-  for (int64_t c0 = 0; c0 < n; c0 += kPanel, ++pi) {
-    const int64_t cw = std::min(kPanel, n - c0);
+  for (int64_t c0 = 0; c0 < n; c0 += op.panel, ++pi) {
+    const int64_t cw = std::min(op.panel, n - c0);
     CMat Qprev{Q.ptr, Q.rs, Q.cs, Q.bs};
     CMat QprevT{Q.ptr, Q.cs, Q.rs, Q.bs};
     Mat Qpan{Q.ptr + c0 * Q.cs, Q.rs, Q.cs, Q.bs};
     CMat Qpanc{Qpan.ptr, Qpan.rs, Qpan.cs, Qpan.bs};
     Mat rdiag = R.ptr ? Mat{R.ptr + c0 * R.rs + c0 * R.cs, R.rs, R.cs, R.bs} : Mat{nullptr, 0, 0, 0};
     if (c0 == 0) {
-      hatt_status sp0 = qr_exec(run, op.panels[pi], Qpanc, Qpan, rdiag, rbuf, ws, wsp, P, gc, st);
+      hatt_status sp0 = qr_exec(run, op.panels[pi], Qpanc, Qpan, rdiag, rbuf, ws, wsp, P, gc, st, nullptr, 1u);
       if (sp0 != HATT_OK) return sp0;
       continue;
     }
@@ -613,16 +623,23 @@ hatt_status qr_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, int64_t rbuf
     if (sg != HATT_OK) return sg;
     sg = gemm(run, gc, Qprev, s1c, Qpan, m, cw, c0, -1.0, 1.0, P, st, false);
     if (sg != HATT_OK) return sg;
+    // columns already in the span of the previous panels (residual at most
+    // 1e-12 of the column) become random vectors for the panel QR, and their
+    // R1 columns zero: A_p = Q_prev S1 + Q1 R1 then still holds to that level,
+    // and both passes work on a well-conditioned panel
+    site("panel dependence %lldx%lld", (long long)m, (long long)cw);
+    LAUNCH(launch_panel_dep(Qpan, s1c, m, c0, (int)cw, pmask, 2 * wsp, 1e-12, 0x51ED270Bu ^ (uint32_t)pi, P, st));
     Mat r1 = R.ptr ? Mat{r1buf, cw, 1, wsp} : Mat{nullptr, 0, 0, 0};
-    sg = qr_exec(run, op.panels[pi], Qpanc, Qpan, r1, rbuf, ws, wsp, P, gc, st);
+    sg = qr_exec(run, op.panels[pi], Qpanc, Qpan, r1, rbuf, ws, wsp, P, gc, st, nullptr, 2u * (uint32_t)pi + 2u);
     if (sg != HATT_OK) return sg;
+    if (R.ptr) LAUNCH(launch_zero_masked_cols(r1, (int)cw, (int)cw, pmask, 2 * wsp, P, st));
     // second pass on the orthonormalised panel
     sg = gemm(run, gc, QprevT, Qpanc, Mat{s2buf, cw, 1, wsp}, c0, cw, m, 1.0, 0.0, P, st, true);
     if (sg != HATT_OK) return sg;
     sg = gemm(run, gc, Qprev, CMat{s2buf, cw, 1, wsp}, Qpan, m, cw, c0, -1.0, 1.0, P, st, false);
     if (sg != HATT_OK) return sg;
     Mat r2 = R.ptr ? Mat{r2buf, cw, 1, wsp} : Mat{nullptr, 0, 0, 0};
-    sg = qr_exec(run, op.panels[pi], Qpanc, Qpan, r2, rbuf, ws, wsp, P, gc, st);
+    sg = qr_exec(run, op.panels[pi], Qpanc, Qpan, r2, rbuf, ws, wsp, P, gc, st, nullptr, 2u * (uint32_t)pi + 3u);
     if (sg != HATT_OK) return sg;
     if (R.ptr) {
       // R(prev, p) += S2 R1;  R(p, p) = R2 R1
@@ -720,7 +737,8 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
   const auto &cap = sp.cap;
   // --- sizes
   int64_t qr_ws = 1, qbuf = 1, rbuf = 1, ubuf = 1, sbuf = 1, tbuf = 1, tmp = 1, svd_ws = 1;
-  std::vector<QrOp> op_rl(d), op_lr(d);
+  int64_t lq_q = 1, lq_r = 1, lq_s = 1;
+  std::vector<QrOp> op_rl(d), op_lr(d), op_lq(d);
   for (int c = d - 1; c >= 1; --c) {
     const int64_t m = n[c] * rb[c + 1], nc = sp.rin[c];
     if (!qr_prepare(m, nc, &op_rl[c]))
@@ -736,10 +754,20 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
       if (!qr_prepare(m, nc, &op_lr[c]))
         return fail(HATT_EUNSUPPORTED, "TT-Rounding: a left-to-right QR of " + std::to_string(m) + " x " +
                                            std::to_string(nc) + " exceeds the library's QR limits");
-      if (nc > kSvdBigMaxN)
+      const int64_t k = op_lr[c].k;
+      if (k < nc) {
+        // wide R (k x nc): its SVD through R^T = Q' R', the k x k factor R'^T
+        if (!qr_prepare(nc, k, &op_lq[c]))
+          return fail(HATT_EUNSUPPORTED, "TT-Rounding: the QR of a " + std::to_string(nc) + " x " +
+                                             std::to_string(k) + " transposed R factor is not supported");
+        qr_ws = std::max(qr_ws, op_lq[c].ws_doubles);
+        lq_q = std::max(lq_q, nc * k);
+        lq_r = std::max(lq_r, k * k);
+        lq_s = std::max(lq_s, cap[c + 1] * k);
+      }
+      if (std::min(k, nc) > kSvdBigMaxN)
         return fail(HATT_EUNSUPPORTED, "TT-Rounding: bond rank " + std::to_string(nc) +
                                            " exceeds the library's SVD limit (" + std::to_string(kSvdBigMaxN) + ")");
-      const int64_t k = op_lr[c].k;
       qr_ws = std::max(qr_ws, op_lr[c].ws_doubles);
       qbuf = std::max(qbuf, m * k);
       rbuf = std::max(rbuf, k * nc);
@@ -748,7 +776,7 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
       tbuf = std::max(tbuf, cap[c + 1] * n[c + 1] * rb[c + 2]);
       tmp = std::max(tmp, k * cap[c + 1]);  // R2^{-1} U of a deferred CholeskyQR2
       tmp = std::max(tmp, cap[c + 1] * nc);  // S V^T R2^{-T} of a deferred right-to-left QR
-      svd_ws = std::max(svd_ws, svd_ws_doubles((int)k, (int)nc));
+      svd_ws = std::max(svd_ws, svd_ws_doubles((int)k, (int)std::min(k, nc)));
     }
   }
   double *work = sp.in_place ? sp.src : ws.d((int64_t)P * stot);
@@ -770,6 +798,10 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
     keep_tot += sp.rin[c] * sp.rin[c] + 1;
   }
   double *keep = ws.d((int64_t)P * keep_tot);
+  double *LqQ = ws.d((int64_t)P * lq_q);
+  double *LqR = ws.d((int64_t)P * lq_r);
+  double *LqL = ws.d((int64_t)P * lq_r);
+  double *LqS = ws.d((int64_t)P * lq_s);
   std::vector<char> deferred(d + 1, 0);
   double *dl2 = ws.d(P);
   double *svdbig = ws.d((int64_t)P * svd_ws);
@@ -857,7 +889,26 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
     sa.rank_out = sp.orank + c + 1;
     sa.rank_bs = d + 1;
     if (k > nc) return fail(HATT_EUNSUPPORTED, "internal: QR rank exceeds columns");
-    s = svd_exec(run, sa, svdbig, svd_ws, flags, gc, st);
+    if (k < nc) {
+      // R^T = Q' R' (nc x k); the singular values and left vectors of R are
+      // those of L = R'^T (k x k); S V^T = U^T R
+      s = qr_exec(run, op_lq[c], CMat{Rb, 1, nc, rbuf}, Mat{LqQ, k, 1, lq_q}, Mat{LqR, k, 1, lq_r}, lq_r, wqr, qr_ws,
+                  P, gc, st);
+      if (s != HATT_OK) return s;
+      LAUNCH(launch_copy(CMat{LqR, 1, k, lq_r}, Mat{LqL, k, 1, lq_r}, k, k, P, st));
+      SvdArgs sl = sa;
+      sl.r = LqL;
+      sl.rbs = lq_r;
+      sl.nc = (int)k;
+      sl.svt = LqS;
+      sl.sbs = lq_s;
+      s = svd_exec(run, sl, svdbig, svd_ws, flags, gc, st);
+      if (s != HATT_OK) return s;
+      s = gemm(run, gc, CMat{Ub, 1, cap[c + 1], ubuf}, CMat{Rb, nc, 1, rbuf}, Mat{Sb, nc, 1, sbuf}, cap[c + 1], nc, k,
+               1.0, 0.0, P, st, true);
+    } else {
+      s = svd_exec(run, sa, svdbig, svd_ws, flags, gc, st);
+    }
     if (s != HATT_OK) return s;
     // out core c = Q U  (m x cap_{c+1})
     const Mat oc{sp.out + ooff[c], cap[c + 1], 1, sp.ostride};

@@ -9,9 +9,11 @@
 //  * chol1k_kernel: Cholesky factor R and R^{-1} of an n x n Gram matrix
 //    (n <= 128), the symmetric elimination of [G | I] with 1024 threads.
 //  * sketch_rows_kernel: B = Omega A for a sparse sign matrix Omega with k
-//    rows (row r of B sums the rows r, r + k, r + 2k, ... of A with hashed
-//    signs); B R0^{-1} well conditioned makes A R0^{-1} well conditioned
-//    enough for CholeskyQR2 (randomised preconditioning of CholeskyQR).
+//    rows (row r of B sums the rows pi(r), pi(r + k), pi(r + 2k), ... of A
+//    with hashed signs, pi a pseudo-random permutation of the rows, so that
+//    every row of B mixes unrelated rows of A); B R0^{-1} well conditioned
+//    makes A R0^{-1} well conditioned enough for CholeskyQR2 (randomised
+//    preconditioning of CholeskyQR).
 //
 // Register layout of hh_qr_kernel (1024 threads = 16 waves): wave w owns the
 // columns w, w + 16, w + 32, ... (CPW of them); lane l holds the rows l,
@@ -96,6 +98,13 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   x *= 0xc2b2ae35u;
   x ^= x >> 16;
   return x;
+}
+
+// Random bit stream for completion vectors: entry r of vector c under a
+// key; nested hashes, so that different (key, c) give unrelated vectors.
+__device__ __forceinline__ uint32_t rand_sign(uint32_t key, int c, int64_t r) {
+  const uint32_t col = hash32(hash32(key) ^ ((uint32_t)c * 0x85EBCA77u + 0x27D4EB2Fu));
+  return hash32(col ^ ((uint32_t)r * 0x9E3779B1u)) >> 7;
 }
 
 }  // namespace
@@ -313,11 +322,11 @@ const char *hh_qr_kernel_name(int64_t m, int64_t n) {
 // column c run the back substitution X(i, c) = -(sum_{i<k<=c} R(i,k) X(k,c))
 // / R(i,i), lane t of the group holding X(k, c) for k = t (mod 8).  R sits in
 // LDS.  With mask != nullptr, a column whose diagonal entry is at most
-// 1e-13 of the largest (a column of the factored matrix that depends on the
-// ones before it) is replaced by dmax e_j before the inversion and marked
-// mask[j] = 1 (else 0); otherwise a zero or non-finite diagonal entry clears
-// the pair's flag (may be null).
-constexpr double kDepRel = 1e-13;
+// 1e-12 of the column's norm (a column of the factored matrix that depends
+// on the ones before it) is replaced by dmax e_j before the inversion and
+// marked mask[j] = 1 (else 0); otherwise a zero or non-finite diagonal entry
+// clears the pair's flag (may be null).
+constexpr double kDepRel = 1e-12;
 
 __global__ __launch_bounds__(1024) void trinv_kernel(const double *r, int64_t rbs, double *xo, int64_t xbs, int n,
                                                      int *flag, int64_t fstride, int first, int *mask,
@@ -340,10 +349,14 @@ __global__ __launch_bounds__(1024) void trinv_kernel(const double *r, int64_t rb
   __syncthreads();
   const double dmax = dmax_s;
   if (mask != nullptr) {
-    // one thread per column: its entries above the diagonal are cleared
+    // one thread per column: a column whose pivot is at most kDepRel of its
+    // own norm (the norm of the factored column) depends on the ones before
+    // it; its entries above the diagonal are cleared
     for (int j = tid; j < n; j += 1024) {
       const double d = Rs[j * n + j];
-      const int dep = !(fabs(d) > kDepRel * dmax) ? 1 : 0;  // also NaN
+      double cn = 0.0;
+      for (int i = 0; i <= j; ++i) cn += Rs[i * n + j] * Rs[i * n + j];
+      const int dep = !(fabs(d) > kDepRel * sqrt(cn)) || !(fabs(d) > 1e-300) ? 1 : 0;  // also NaN
       mask[p * mbs + j] = dep;
       if (dep) {
         for (int i = 0; i < j; ++i) Rs[i * n + j] = 0.0;
@@ -430,8 +443,7 @@ __global__ void complete_cols_kernel(double *a, int64_t m, int n, int64_t abs_, 
   if (!mask[p * mbs + c]) return;
   const int64_t r = e / n;
   const double v = 1.0 / sqrt((double)m);
-  const uint32_t h = hash32((uint32_t)r * 0x9E3779B1u ^ hash32((uint32_t)c + key));
-  a[p * abs_ + e] = (h & 1u) ? -v : v;
+  a[p * abs_ + e] = (rand_sign(key, c, r) & 1u) ? -v : v;
 }
 
 hipError_t launch_complete_cols(double *a, int64_t m, int n, int64_t abs_, const int *mask, int64_t mbs,
@@ -572,8 +584,96 @@ hipError_t launch_chol1k(const double *g, int64_t gbs, double *r, double *rinv, 
 }
 
 // ---------------------------------------------------------------------------
+// Block Gram-Schmidt panel test: W = A_p - Q S1 is a panel's residual after
+// its first projection (m x cw), S1 the projection coefficients (c0 x cw).
+// A column with ||W_j||^2 <= rel^2 (||S1_j||^2 + ||W_j||^2) lies in the span
+// of the previous panels up to rounding: it is marked (mask[j] = 1) and W_j
+// is replaced by a random unit vector, so that the panel QR and the second
+// projection see a well-conditioned panel.  One 1024-thread block per pair:
+// thread (row group tr of 8, column tc of 128).
+__global__ __launch_bounds__(1024) void panel_dep_kernel(Mat W, CMat S1, int64_t m, int64_t c0, int cw, int *mask,
+                                                         int64_t mbs, double rel, uint32_t key) {
+  __shared__ double pw[8][128], ps[8][128];
+  __shared__ int dep[128];
+  const int tid = threadIdx.x, tc = tid & 127, tr = tid >> 7;
+  const int p = blockIdx.x;
+  double sw = 0.0, ss = 0.0;
+  if (tc < cw) {
+    const double *w = W.ptr + p * W.bs + tc * W.cs;
+    for (int64_t r = tr; r < m; r += 8) {
+      const double v = w[r * W.rs];
+      sw += v * v;
+    }
+    const double *s = S1.ptr + p * S1.bs + tc * S1.cs;
+    for (int64_t r = tr; r < c0; r += 8) {
+      const double v = s[r * S1.rs];
+      ss += v * v;
+    }
+  }
+  pw[tr][tc] = sw;
+  ps[tr][tc] = ss;
+  __syncthreads();
+  if (tr == 0) {
+    double a = 0.0, b = 0.0;
+    for (int g = 0; g < 8; ++g) {
+      a += pw[g][tc];
+      b += ps[g][tc];
+    }
+    const int d = (tc < cw) && !(a > rel * rel * (a + b)) ? 1 : 0;
+    dep[tc] = d;
+    if (tc < cw) mask[p * mbs + tc] = d;
+  }
+  __syncthreads();
+  if (tc < cw && dep[tc]) {
+    double *w = W.ptr + p * W.bs + tc * W.cs;
+    const double v = 1.0 / sqrt((double)m);
+    for (int64_t r = tr; r < m; r += 8) w[r * W.rs] = (rand_sign(key, tc, r) & 1u) ? -v : v;
+  }
+}
+
+hipError_t launch_panel_dep(Mat W, CMat S1, int64_t m, int64_t c0, int cw, int *mask, int64_t mbs, double rel,
+                            uint32_t key, int batch, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  if (cw < 1 || cw > 128) return hipErrorInvalidValue;
+  panel_dep_kernel<<<batch, 1024, 0, s>>>(W, S1, m, c0, cw, mask, mbs, rel, key);
+  return hipGetLastError();
+}
+
+// Columns j of R (rows x cw, strided) with mask[p * mbs + j] set become zero.
+__global__ void zero_masked_cols_kernel(Mat R, int rows, int cw, const int *mask, int64_t mbs) {
+  const int p = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cw) return;
+  const int r = e / cw, c = e - r * cw;
+  if (mask[p * mbs + c]) R.ptr[p * R.bs + r * R.rs + c * R.cs] = 0.0;
+}
+
+hipError_t launch_zero_masked_cols(Mat R, int rows, int cw, const int *mask, int64_t mbs, int batch, hipStream_t s) {
+  if (batch <= 0 || rows <= 0 || cw <= 0) return hipSuccess;
+  dim3 grid((unsigned)((rows * cw + 255) / 256), (unsigned)batch);
+  zero_masked_cols_kernel<<<grid, 256, 0, s>>>(R, rows, cw, mask, mbs);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // B(r, c) = sum_t sign(r + t k) A(r + t k, c), r < k, c < n, per pair.
 // Threads run along whichever of r, c is contiguous in A.
+// A pseudo-random permutation of [0, m) (m < 2^31): a bijection of
+// [0, 2^bits) built from invertible steps (odd multiplications, xor with a
+// right shift, key addition), walked along its cycle until it lands below m.
+__device__ __forceinline__ uint32_t perm_row(uint32_t x, uint32_t m, int bits, uint32_t key) {
+  const uint32_t mask = (bits >= 32) ? 0xFFFFFFFFu : ((1u << bits) - 1u);
+  const int sh = (bits + 1) / 2;
+  do {
+    x = (x * 0x9E3779B1u + key) & mask;
+    x ^= x >> sh;
+    x = (x * 0x85EBCA77u + (key >> 7)) & mask;
+    x ^= x >> sh;
+    x = (x * 0xC2B2AE3Du) & mask;
+  } while (x >= m);
+  return x;
+}
+
 __global__ void sketch_rows_kernel(CMat A, int64_t m, int n, int k, double *b, int64_t bbs, uint32_t key,
                                    int rows_fast) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -588,20 +688,24 @@ __global__ void sketch_rows_kernel(CMat A, int64_t m, int n, int k, double *b, i
     c = (int)(e - (int64_t)r * n);
   }
   const double *a = A.ptr + p * A.bs + c * A.cs;
-  // eight independent partial sums keep eight loads in flight
+  int bits = 1;
+  while (bits < 31 && ((int64_t)1 << bits) < m) ++bits;
+  // row t of the sum is row perm(r + t k) of A; eight independent partial
+  // sums keep eight loads in flight
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int64_t i = r;
   for (; i + 7 * (int64_t)k < m; i += 8 * (int64_t)k) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int64_t ii = i + u * (int64_t)k;
-      const double v = a[ii * A.rs];
-      acc[u] += (hash32((uint32_t)ii ^ key) & 1u) ? -v : v;
+      const uint32_t ii = perm_row((uint32_t)(i + u * (int64_t)k), (uint32_t)m, bits, key);
+      const double v = a[(int64_t)ii * A.rs];
+      acc[u] += (hash32(ii ^ key) & 1u) ? -v : v;
     }
   }
   for (int u = 0; i < m; i += k, ++u) {
-    const double v = a[i * A.rs];
-    acc[u] += (hash32((uint32_t)i ^ key) & 1u) ? -v : v;
+    const uint32_t ii = perm_row((uint32_t)i, (uint32_t)m, bits, key);
+    const double v = a[(int64_t)ii * A.rs];
+    acc[u] += (hash32(ii ^ key) & 1u) ? -v : v;
   }
   b[p * bbs + (int64_t)r * n + c] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
 }

@@ -620,3 +620,52 @@ def test_many_pairs_fused_gram_cholesky():
         got = res.train(b)
         assert tt.ranks(got) == tt.ranks(ref), b
         assert tt.rel_err(got, ref) <= TOL, b
+
+
+@pytest.mark.parametrize("n,terms,rank", [(48, 12, 25), (64, 20, 41)])
+def test_round_explicit_trig_product_wide_r(n, terms, rank):
+    """Explicit PKP cores of u (.) u (ranks terms^2: 144, or 400 = four
+    Gram-Schmidt panels) rounded at tol 1e-8: the frames hold exactly
+    duplicated columns (the (a, b) and (b, a) products), and the first
+    left-to-right QR leaves a wide R, whose SVD goes through the QR of R^T.
+    Ranks and tensor against the oracle's TT-Rounding of its own PKP cores,
+    and the norm of the PKP train against the full tensor."""
+    u = wk.trig_u(7, n=n, terms=terms, nfreq=terms // 2)
+    U = H.TT.from_cores(u)
+    _say(f"tt_hadamard_explicit + tt_norm + tt_round trig {n}^3, {terms} terms")
+    A = H.hadamard_explicit(U, U)
+    full = tt.full(u) ** 2
+    assert abs(float(H.norm(A)[0].item()) - np.linalg.norm(full)) <= 1e-12 * np.linalg.norm(full)
+    res = H.round(A, tol=1e-8)
+    torch.cuda.synchronize()
+    ref = rounding.tt_round(tt.pkp(u, u), tol=1e-8)
+    got = res.train(0)
+    assert tt.ranks(got) == tt.ranks(ref) == [1, rank, rank, 1]
+    assert tt.rel_err(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("mode", ["dup", "zero"])
+def test_norm_and_round_exactly_dependent_wide_frames(mode):
+    """Bond rank 400 (four Gram-Schmidt panels of 128 columns) with 150 left
+    slices of the middle core duplicated or zero: the right-to-left frames
+    have exactly dependent columns.  The norm (right-to-left sweep alone) and
+    a TT-Rounding at tol 1e-6 against the oracle's."""
+    g = np.random.default_rng(2)
+    n, r = 64, 400
+    c0 = g.standard_normal((1, n, r))
+    c1 = g.standard_normal((r, n, r)) / np.sqrt(r)
+    c2 = g.standard_normal((r, n, 1))
+    for k in range(150):
+        c1[2 * k + 1] = c1[2 * k] if mode == "dup" else 0.0
+    cores = [c0, c1, c2]
+    A = H.TT.from_cores(cores)
+    _say(f"tt_norm / tt_round rank 400 with {mode} slices")
+    nrm = float(H.norm(A)[0].item())
+    ex = np.linalg.norm(tt.full(cores))
+    assert abs(nrm - ex) <= 1e-12 * ex
+    res = H.round(A, tol=1e-6)
+    torch.cuda.synchronize()
+    ref = rounding.tt_round(cores, tol=1e-6)
+    got = res.train(0)
+    assert tt.ranks(got) == tt.ranks(ref)
+    assert tt.rel_err(got, ref) <= TOL
