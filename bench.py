@@ -348,11 +348,23 @@ def _bench_trig(args, torch, wk, H, perfmodel) -> int:
                 ge = zr.train(0)
                 ref = fu ** 2 if name == "u2" else fu ** 3
                 err = float(np.linalg.norm(_full_np(ge) - ref) / np.linalg.norm(ref))
+                # RandOrth (Alg. 2) on the same PKP cores, same widths and seed
+                lw, sd = (l2, s2) if name == "u2" else (l3, s3)
+                H.randorth(z, lw, seed=sd, tol=tol)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                zo = H.randorth(z, lw, seed=sd, tol=tol)
+                torch.cuda.synchronize()
+                t_ro = time.perf_counter() - t0
+                err_ro = float(np.linalg.norm(_full_np(zo.train(0)) - ref) / np.linalg.norm(ref))
                 explicit[name] = {"pkp_ms": 1000 * t_pkp, "pkp_GBs": z.total * 8 / t_pkp / 1e9,
                                   "round_ms": 1000 * t_round, "ranks": zr.ranks[0].tolist(),
                                   "rel_err_vs_closed_form": err,
-                                  "hatt_speedup": (t_pkp + t_round) / ((t2 if name == "u2" else t3) / 1000.0)}
-                del z, zr
+                                  "hatt_speedup": (t_pkp + t_round) / ((t2 if name == "u2" else t3) / 1000.0),
+                                  "randorth_ms": 1000 * t_ro, "randorth_ranks": zo.ranks[0].tolist(),
+                                  "randorth_rel_err_vs_closed_form": err_ro,
+                                  "hatt_speedup_vs_randorth": (t_pkp + t_ro) / ((t2 if name == "u2" else t3) / 1000.0)}
+                del z, zr, zo
                 torch.cuda.empty_cache()
             except HattError as e:
                 explicit[name] = {"status": f"unsupported: {e}"}
@@ -360,6 +372,9 @@ def _bench_trig(args, torch, wk, H, perfmodel) -> int:
         if len(ok) == 2:
             explicit["recompressions_per_s"] = 2.0 / sum((e["pkp_ms"] + e["round_ms"]) / 1000.0 for e in ok)
             explicit["hatt_speedup"] = value / explicit["recompressions_per_s"]
+            explicit["randorth_recompressions_per_s"] = 2.0 / sum((e["pkp_ms"] + e["randorth_ms"]) / 1000.0
+                                                                  for e in ok)
+            explicit["hatt_speedup_vs_randorth"] = value / explicit["randorth_recompressions_per_s"]
 
     cpu = None
     parity = None

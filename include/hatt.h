@@ -210,6 +210,28 @@ HATT_API hatt_status tt_hadamard_explicit(const hatt_tt *x, const hatt_tt *y, do
                                  int64_t out_stride, void *stream);
 
 /*
+ * tt_randorth_plan / tt_randorth -- RandOrth (Alg. 2) of an explicit TT a:
+ * the sketch W^{(k)} = (A_{k+1..d} contracted with R_{k+1..d}) right to
+ * left (eq. rtlpc), then for k = 1..d-1: Q = QR(V(B_k) W^{(k)}) becomes
+ * V(B_k), M = Q^T V(B_k) (the core before the QR), H(B_{k+1}) = M H(A_{k+1}); optionally
+ * TT-Rounding (Alg. 1) of the rank-l result to max_rank and/or tol.  On the
+ * PKP cores of x (.) y (tt_hadamard_explicit) it is the paper's RandOrth
+ * comparator, and with the same sketch it represents the same tensor as
+ * hatt_recompress (HaTT reorganises exactly these products).  Widths are
+ * clamped as in hatt_plan with the ranks of a in place of r_k s_k; the
+ * sketch is `sketch` (ranks ell_out, batch 1 or a->batch) or, if NULL, the
+ * Philox sketch keyed by seed (the same one hatt_recompress draws for that
+ * seed and those widths).  Output at
+ * capacity shape ell_out, kept ranks in out_rank (device [batch][d+1]).
+ * tt_randorth_plan reports the workspace for a call with truncation.
+ */
+HATT_API hatt_status tt_randorth_plan(const hatt_tt *a, int64_t ell, const int64_t *ell_bond, int64_t *ell_out,
+                                      size_t *ws_bytes, int64_t *out_elems);
+HATT_API hatt_status tt_randorth(const hatt_tt *a, const hatt_tt *sketch, int64_t ell, const int64_t *ell_bond,
+                                 uint64_t seed, int64_t max_rank, double tol, double *out, int64_t out_stride,
+                                 int64_t *out_rank, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * tt_round_plan / tt_round -- TT-Rounding (Alg. 1): right-to-left QR
  * orthogonalisation, then left-to-right economy QR + SVD truncation.
  * Bond rule: delta = tol ||a||_F / sqrt(d-1); keep the smallest rho >= 1

@@ -32,6 +32,7 @@ from .api import (  # noqa: F401
     recompress_adaptive,
     recompress_batched,
     recompress_noalloc,
+    randorth,
     round,
     round_plan,
     set_qr_method,

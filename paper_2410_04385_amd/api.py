@@ -308,6 +308,35 @@ def hadamard_explicit(x: TT, y: TT, out: Optional[TT] = None, stream=None) -> TT
     return out
 
 
+def randorth(a: TT, ell, *, max_rank: int = 0, tol: float = 0.0, seed: int = 0, sketch: Optional[TT] = None,
+             workspace: Optional[torch.Tensor] = None, stream=None) -> Result:
+    """RandOrth (Alg. 2) of an explicit TT, e.g. the PKP cores of
+    hadamard_explicit(x, y), optionally truncated by TT-Rounding."""
+    ell_arr = None if np.isscalar(ell) else i64_array(ell)
+    ell_u = int(ell) if np.isscalar(ell) else 0
+    av, ka = a.view()
+    eo = (ctypes.c_int64 * (a.d + 1))()
+    ws = ctypes.c_size_t(0)
+    oe = ctypes.c_int64(0)
+    check("tt_randorth_plan", lib().tt_randorth_plan(ctypes.byref(av), ell_u, ell_arr, eo, ctypes.byref(ws),
+                                                     ctypes.byref(oe)))
+    dev = a.data.device
+    out = TT.empty(a.n, list(eo), a.batch, device=dev)
+    ranks = torch.empty((a.batch, a.d + 1), dtype=torch.int64, device=dev)
+    if workspace is None or workspace.numel() < ws.value:
+        workspace = torch.empty(max(ws.value, 1), dtype=torch.uint8, device=dev)
+    sk_ptr = None
+    keep = None
+    if sketch is not None:
+        sv, keep = sketch.view()
+        sk_ptr = ctypes.byref(sv)
+    check("tt_randorth", lib().tt_randorth(ctypes.byref(av), sk_ptr, ell_u, ell_arr, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                           int(max_rank), float(tol), ctypes.c_void_p(out.data.data_ptr()), out.stride,
+                                           ctypes.c_void_p(ranks.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+                                           workspace.numel(), _stream_ptr(stream)))
+    return Result(out, ranks)
+
+
 def round_plan(a: TT):
     av, ka = a.view()
     cap = (ctypes.c_int64 * (a.d + 1))()

@@ -1306,10 +1306,231 @@ hatt_status hatt_run(bool run, const HattSpec &sp, Ws &ws, hipStream_t st) {
   return hatt_body(run, sp, ws, g1, st);
 }
 
+// ---------------------------------------------------------------------------
+// RandOrth (Alg. 2) on an explicit TT a (for a Hadamard product: its PKP
+// cores), with the sketch right to left (eq. rtlpc) and the orthogonalising
+// sweep, then optionally TT-Rounding of the rank-l result.  The paper's
+// second comparator (Table 4.1): the same products and QRs as HaTT, but on
+// cores of rank R_k = r_k s_k.
+struct RoSpec {
+  Shape A;
+  std::vector<int64_t> ell;
+  const double *sketch;
+  int64_t sketch_stride;
+  uint64_t seed;
+  int64_t max_rank;
+  double tol;
+  double *out;
+  int64_t ostride;
+  int64_t *orank;
+};
+
+hatt_status randorth_body(bool run, const RoSpec &sp, Ws &ws, GemmCtx &gc, hipStream_t st) {
+  const int d = sp.A.d, P = sp.A.batch;
+  const auto &n = sp.A.n, &R = sp.A.r, &l = sp.ell;
+  std::vector<int64_t> ooff, skoff;
+  int64_t otot, sktot;
+  make_offsets(n, l, &ooff, &otot);
+  make_offsets(n, l, &skoff, &sktot);
+  const double *ad = sp.A.data;
+  const int64_t as = sp.A.stride;
+  std::vector<int64_t> woff(d + 1, 0);
+  int64_t wtot = 1, tsz = 1, bsz = 1, ysz = 1, msz = 1, qrws = 1;
+  for (int b = 1; b < d; ++b) {
+    woff[b] = wtot;
+    wtot += R[b] * l[b];
+  }
+  for (int c = 1; c <= d - 2; ++c) tsz = std::max(tsz, R[c] * n[c] * l[c + 1]);
+  std::vector<QrOp> qp(d);
+  for (int c = 0; c < d - 1; ++c) {
+    bsz = std::max(bsz, l[c] * n[c] * R[c + 1]);
+    ysz = std::max(ysz, l[c] * n[c] * l[c + 1]);
+    msz = std::max(msz, l[c + 1] * R[c + 1]);
+    if (!qr_prepare(l[c] * n[c], l[c + 1], &qp[c]))
+      return fail(HATT_EUNSUPPORTED, "RandOrth: the QR of a " + std::to_string(l[c] * n[c]) + " x " +
+                                         std::to_string(l[c + 1]) + " sketched frame is not supported");
+    qrws = std::max(qrws, qp[c].ws_doubles);
+  }
+  bsz = std::max(bsz, l[d - 1] * n[d - 1]);
+  double *sk = sp.sketch ? (double *)sp.sketch : ws.d(sktot);
+  const int64_t sks = sp.sketch ? sp.sketch_stride : 0;
+  double *W = ws.d((int64_t)P * wtot);
+  double *T = ws.d((int64_t)P * tsz);
+  double *B0 = ws.d((int64_t)P * bsz);
+  double *B1 = ws.d((int64_t)P * bsz);
+  double *Yb = ws.d((int64_t)P * ysz);
+  double *Mb = ws.d((int64_t)P * msz);
+  double *wqr = ws.d((int64_t)P * qrws);
+  if (d == 1) {
+    LAUNCH(launch_fill_i64(sp.orank, (int64_t)P * 2, 1, st));
+    LAUNCH(launch_copy(CMat{ad, n[0], 1, as}, Mat{sp.out, n[0], 1, sp.ostride}, 1, n[0], P, st));
+    return HATT_OK;
+  }
+  if (!sp.sketch) {
+    for (int k = 0; k < d; ++k) {
+      const int64_t cnt = l[k] * n[k] * l[k + 1];
+      LAUNCH(launch_sketch_fill(sp.seed, k, cnt, 1.0 / sqrt((double)cnt), sk + skoff[k], st));
+    }
+  }
+  // W^{(d-1)} = H(A_d) H(R_d)^T
+  hatt_status s = gemm(run, gc, CMat{ad + sp.A.off[d - 1], n[d - 1], 1, as}, CMat{sk + skoff[d - 1], 1, n[d - 1], sks},
+                       Mat{W + woff[d - 1], l[d - 1], 1, wtot}, R[d - 1], l[d - 1], n[d - 1], 1.0, 0.0, P, st, true);
+  if (s != HATT_OK) return s;
+  for (int c = d - 2; c >= 1; --c) {
+    // V(T) = V(A_c) W^{(c+1)}; W^{(c)} = H(T) H(R_c)^T
+    s = gemm(run, gc, CMat{ad + sp.A.off[c], R[c + 1], 1, as}, CMat{W + woff[c + 1], l[c + 1], 1, wtot},
+             Mat{T, l[c + 1], 1, tsz}, R[c] * n[c], l[c + 1], R[c + 1], 1.0, 0.0, P, st, true);
+    if (s != HATT_OK) return s;
+    s = gemm(run, gc, CMat{T, n[c] * l[c + 1], 1, tsz}, CMat{sk + skoff[c], 1, n[c] * l[c + 1], sks},
+             Mat{W + woff[c], l[c], 1, wtot}, R[c], l[c], n[c] * l[c + 1], 1.0, 0.0, P, st, true);
+    if (s != HATT_OK) return s;
+  }
+  // sweep: B_1 = A_1; Y = V(B_k) W^{(k)}, Q = qr(Y), M = Q^T V(B_k), H(B_{k+1}) = M H(A_{k+1})
+  double *Bc = B0, *Bn = B1;
+  LAUNCH(launch_copy(CMat{ad, R[1], 1, as}, Mat{Bc, R[1], 1, bsz}, n[0], R[1], P, st));
+  for (int c = 0; c < d - 1; ++c) {
+    const int64_t m = l[c] * n[c];
+    s = gemm(run, gc, CMat{Bc, R[c + 1], 1, bsz}, CMat{W + woff[c + 1], l[c + 1], 1, wtot}, Mat{Yb, l[c + 1], 1, ysz},
+             m, l[c + 1], R[c + 1], 1.0, 0.0, P, st, true);
+    if (s != HATT_OK) return s;
+    double *qcore = sp.out + ooff[c];
+    s = qr_exec(run, qp[c], CMat{Yb, l[c + 1], 1, ysz}, Mat{qcore, l[c + 1], 1, sp.ostride}, Mat{nullptr, 0, 0, 0}, 0,
+                wqr, qrws, P, gc, st);
+    if (s != HATT_OK) return s;
+    s = gemm(run, gc, CMat{qcore, 1, l[c + 1], sp.ostride}, CMat{Bc, R[c + 1], 1, bsz}, Mat{Mb, R[c + 1], 1, msz},
+             l[c + 1], R[c + 1], m, 1.0, 0.0, P, st, true);
+    if (s != HATT_OK) return s;
+    const int cn = c + 1;
+    const int64_t ncol = n[cn] * R[cn + 1];
+    if (cn < d - 1) {
+      s = gemm(run, gc, CMat{Mb, R[cn], 1, msz}, CMat{ad + sp.A.off[cn], ncol, 1, as}, Mat{Bn, ncol, 1, bsz}, l[cn],
+               ncol, R[cn], 1.0, 0.0, P, st, true);
+    } else {
+      s = gemm(run, gc, CMat{Mb, R[cn], 1, msz}, CMat{ad + sp.A.off[cn], ncol, 1, as},
+               Mat{sp.out + ooff[cn], ncol, 1, sp.ostride}, l[cn], ncol, R[cn], 1.0, 0.0, P, st, true);
+    }
+    if (s != HATT_OK) return s;
+    std::swap(Bc, Bn);
+  }
+  if ((int)l.size() > kMaxRankPattern) return fail(HATT_EUNSUPPORTED, "order too large for the library (rank pattern buffer)");
+  LAUNCH(launch_rank_pattern(sp.orank, P, d + 1, l.data(), st));
+  if (sp.max_rank > 0 || sp.tol > 0.0) {
+    RoundSpec rs{};
+    rs.n = n;
+    rs.rin = l;
+    rs.cap = l;
+    rs.src = sp.out;
+    rs.sstride = sp.ostride;
+    rs.in_place = true;
+    rs.out = sp.out;
+    rs.ostride = sp.ostride;
+    rs.orank = sp.orank;
+    rs.max_rank = sp.max_rank;
+    rs.tol = sp.tol;
+    rs.batch = P;
+    GemmCtx gr{nullptr, 0, 0};
+    s = round_run(run, rs, ws, gr, st);
+    if (s != HATT_OK) return s;
+  }
+  return HATT_OK;
+}
+
+hatt_status randorth_run(bool run, const RoSpec &sp, Ws &ws, hipStream_t st) {
+  Ws probe(nullptr);
+  GemmCtx g0{nullptr, 0, 0};
+  hatt_status s = randorth_body(false, sp, probe, g0, st);
+  if (s != HATT_OK) return s;
+  GemmCtx g1{nullptr, 0, 0};
+  g1.part = ws.d(std::max<int64_t>(g0.part_need, 1));
+  g1.part_cap = g0.part_need;
+  return randorth_body(run, sp, ws, g1, st);
+}
+
+hatt_status randorth_prepare(const hatt_tt *a, int64_t ell, const int64_t *ell_bond, int64_t max_rank, double tol,
+                             RoSpec *sp, bool need_data) {
+  hatt_status st = read_tt(a, "a", &sp->A, need_data);
+  if (st != HATT_OK) return st;
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(HATT_EINVAL, "tol must be finite and >= 0");
+  const int d = sp->A.d;
+  std::vector<int64_t> req(d + 1, 1), ones(d + 1, 1);
+  for (int k = 1; k < d; ++k) {
+    req[k] = ell_bond ? ell_bond[k] : ell;
+    if (req[k] < 1) return fail(HATT_EINVAL, "sketch width must be >= 1");
+  }
+  sp->ell = clamp_ell(sp->A.n, sp->A.r, ones, req);
+  sp->max_rank = max_rank;
+  sp->tol = tol;
+  sp->sketch = nullptr;
+  sp->sketch_stride = 0;
+  sp->out = nullptr;
+  sp->orank = nullptr;
+  return HATT_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
 extern "C" {
+
+hatt_status tt_randorth_plan(const hatt_tt *a, int64_t ell, const int64_t *ell_bond, int64_t *ell_out,
+                             size_t *ws_bytes, int64_t *out_elems) {
+  RoSpec sp{};
+  hatt_status st = randorth_prepare(a, ell, ell_bond, 0, 0.0, &sp, false);
+  if (st != HATT_OK) return st;
+  // the truncation's workspace is the larger one: plan with it
+  sp.tol = 1.0;
+  Ws ws(nullptr);
+  st = randorth_run(false, sp, ws, nullptr);
+  if (st != HATT_OK) return st;
+  if (ell_out)
+    for (int k = 0; k <= sp.A.d; ++k) ell_out[k] = sp.ell[k];
+  if (ws_bytes) *ws_bytes = ws.off;
+  if (out_elems) {
+    std::vector<int64_t> off;
+    int64_t tot;
+    make_offsets(sp.A.n, sp.ell, &off, &tot);
+    *out_elems = tot;
+  }
+  g_err.clear();
+  return HATT_OK;
+}
+
+hatt_status tt_randorth(const hatt_tt *a, const hatt_tt *sketch, int64_t ell, const int64_t *ell_bond, uint64_t seed,
+                        int64_t max_rank, double tol, double *out, int64_t out_stride, int64_t *out_rank, void *ws,
+                        size_t ws_bytes, void *stream) {
+  RoSpec sp{};
+  hatt_status st = randorth_prepare(a, ell, ell_bond, max_rank, tol, &sp, true);
+  if (st != HATT_OK) return st;
+  if (out == nullptr || out_rank == nullptr) return fail(HATT_EINVAL, "out or out_rank is NULL");
+  std::vector<int64_t> off;
+  int64_t otot;
+  make_offsets(sp.A.n, sp.ell, &off, &otot);
+  if (out_stride != 0 && out_stride < otot) return fail(HATT_EINVAL, "out_stride smaller than one output train");
+  sp.out = out;
+  sp.ostride = out_stride ? out_stride : otot;
+  sp.orank = out_rank;
+  sp.seed = seed;
+  if (sketch != nullptr) {
+    Shape sk;
+    st = read_tt(sketch, "sketch", &sk, true);
+    if (st != HATT_OK) return st;
+    if (sk.d != sp.A.d || sk.n != sp.A.n || sk.r != sp.ell)
+      return fail(HATT_ESHAPE, "sketch shape differs from the planned sketch widths");
+    if (sk.batch != 1 && sk.batch != sp.A.batch)
+      return fail(HATT_ESHAPE, "sketch batch must be 1 or equal to the input batch");
+    sp.sketch = sk.data;
+    sp.sketch_stride = (sk.batch == 1) ? 0 : sk.stride;
+  }
+  Ws meas(nullptr);
+  st = randorth_run(false, sp, meas, nullptr);
+  if (st != HATT_OK) return st;
+  if (ws == nullptr || ws_bytes < meas.off)
+    return fail(HATT_EWORKSPACE, "workspace too small: need " + std::to_string(meas.off) + " bytes");
+  Ws w(ws);
+  st = randorth_run(true, sp, w, (hipStream_t)stream);
+  if (st == HATT_OK) g_err.clear();
+  return st;
+}
 
 const char *hatt_last_error(void) { return g_err.c_str(); }
 

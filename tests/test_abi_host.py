@@ -324,3 +324,22 @@ def test_noalloc_rejects_problems_beyond_its_scratch_before_any_device_call():
         api.recompress_noalloc(u, u, 96, tol=1e-8, out=_cpu_tt(n, [1, 96, 96, 1]),
                                ranks=torch.zeros((1, 4), dtype=torch.int64), stream=_NullStream())
     assert ei.value.status == -3 and "scratch" in str(ei.value)
+
+
+def test_randorth_plan_matches_oracle_clamps():
+    """RandOrth's widths follow the same clamps as HaTT's with the ranks of
+    the explicit train (r_k s_k for PKP cores)."""
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        d = int(rng.integers(2, 7))
+        n = [int(v) for v in rng.integers(2, 6, size=d)]
+        ra = wk.feasible_ranks(n, int(rng.integers(2, 20)))
+        ell = int(rng.integers(1, 30))
+        av, keep = _cpu_tt(n, ra).view()
+        eo = (ctypes.c_int64 * (d + 1))()
+        ws = ctypes.c_size_t(0)
+        oe = ctypes.c_int64(0)
+        st = _lib.lib().tt_randorth_plan(ctypes.byref(av), ell, None, eo, ctypes.byref(ws), ctypes.byref(oe))
+        assert st == 0
+        assert list(eo) == oplan.clamp_ell(n, ra, [1] * (d + 1), ell)
+        assert ws.value > 0

@@ -669,3 +669,33 @@ def test_norm_and_round_exactly_dependent_wide_frames(mode):
     got = res.train(0)
     assert tt.ranks(got) == tt.ranks(ref)
     assert tt.rel_err(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("shape", [(6, 4, 3, 3, 9), (8, 8, 6, 5, 20), (3, 48, 12, 12, 40)])
+def test_randorth_explicit_matches_oracle_and_hatt(shape):
+    """GPU RandOrth (Alg. 2) on the GPU's PKP cores against the oracle's
+    RandOrth of its own PKP cores with the same explicit sketch, and against
+    GPU HaTT with the same seeded sketch (HaTT reorganises exactly these
+    products, so the tensors agree)."""
+    d, n, r, s, ell = shape
+    if d == 3:
+        y = wk.trig_u(3, n=n, terms=r, nfreq=r // 2)
+        z = wk.trig_u(4, n=n, terms=s, nfreq=s // 2)
+    else:
+        y, z = wk.spectral_pair(31 + d, d, n, r, s)
+    X, Y = H.TT.from_cores(y), H.TT.from_cores(z)
+    A = H.hadamard_explicit(X, Y)
+    ell_c = plan.clamp_ell(tt.modes(y), tt.ranks(y), tt.ranks(z), ell)
+    R = wk.gaussian_sketch(np.random.default_rng(9), tt.modes(y), ell_c)
+    _say(f"tt_randorth d={d} n={n} r={r} s={s} ell={ell}")
+    got = H.randorth(A, ell, sketch=H.TT.from_cores(R))
+    torch.cuda.synchronize()
+    ref = randorth.randorth(tt.pkp(y, z), R)
+    assert got.ranks[0].tolist() == ell_c
+    assert tt.rel_err(got.train(0), ref) <= TOL
+    # seeded: the same Philox sketch as hatt_recompress draws
+    g2 = H.randorth(A, ell, seed=77, tol=1e-10)
+    h2 = H.recompress(X, Y, ell, seed=77, tol=1e-10)
+    torch.cuda.synchronize()
+    assert g2.ranks[0].tolist() == h2.ranks[0].tolist()
+    assert tt.rel_err(g2.train(0), h2.train(0)) <= TOL
