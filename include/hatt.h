@@ -255,6 +255,15 @@ HATT_API hatt_status tt_norm_plan(const hatt_tt *a, size_t *ws_bytes);
 HATT_API hatt_status tt_norm(const hatt_tt *a, double *out, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * tt_scale -- multiply (invert = 0) or divide (invert = 1) train b of `a` by
+ * alpha[b] (device double [batch], e.g. the output of tt_norm), through its
+ * first core, in place; enqueue only.  Lets an iteration that repeats
+ * Hadamard products (the power iteration of Sec. 5, Example 3) keep its
+ * iterate normalised without a host round trip.
+ */
+HATT_API hatt_status tt_scale(const hatt_tt *a, const double *alpha, int32_t invert, void *stream);
+
+/*
  * hatt_sketch_fill -- materialise the seeded random Gaussian TT (Def. 2.1)
  * with ranks ell[0..d] (ell[0] = ell[d] = 1) and mode sizes n[0..d-1]:
  * entries N(0, 1/(ell_{k-1} n_k ell_k)) from Philox4x32-10 (key = seed,

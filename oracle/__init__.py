@@ -21,6 +21,8 @@ Everything here is plain, slow and written to be read against the paper
                 slack; Sec. 5.1.1 and Sec. 6 leave the rule open).
 * ``rankpred``  the per-bond width predictor: core statistics, a small tanh
                 MLP, its gradient and the Adam update.
+* ``power``     the power iteration for a TT's largest entry with HaTT
+                recompressions (Sec. 5, Example 3).
 
 All arithmetic is numpy float64; QR and SVD are LAPACK calls (Householder QR
 and divide-and-conquer SVD), used only as library steps.
@@ -30,4 +32,4 @@ Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 inequalities); none is "parity unpinned".
 """
 
-from . import tt, rounding, randorth, hatt, plan, philox, flops, adapt, rankpred  # noqa: F401
+from . import tt, rounding, randorth, hatt, plan, philox, flops, adapt, rankpred, power  # noqa: F401

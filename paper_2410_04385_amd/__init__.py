@@ -35,6 +35,7 @@ from .api import (  # noqa: F401
     randorth,
     round,
     round_plan,
+    scale,
     set_qr_method,
     sketch_fill,
     version,

@@ -17,7 +17,7 @@ STATUS_NAMES = {
 }
 
 EXPORTED = [
-    "hatt_plan", "hatt_recompress", "hatt_recompress_noalloc", "hatt_adaptive_plan", "hatt_recompress_adaptive", "tt_hadamard_explicit", "tt_randorth_plan", "tt_randorth", "tt_round_plan", "tt_round",
+    "hatt_plan", "hatt_recompress", "hatt_recompress_noalloc", "hatt_adaptive_plan", "hatt_recompress_adaptive", "tt_hadamard_explicit", "tt_scale", "tt_randorth_plan", "tt_randorth", "tt_round_plan", "tt_round",
     "tt_norm_plan", "tt_norm", "hatt_sketch_fill", "hatt_profile_start", "hatt_profile_stop",
     "hatt_profile_class_name", "hatt_last_error", "hatt_version", "hatt_set_qr_method",
     "hatt_profile_report", "hatt_batched_plan", "hatt_recompress_batched",
@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
     L.tt_randorth_plan.argtypes = [ttp, ctypes.c_int64, i64p, i64p, szp, i64p]
     L.tt_randorth.argtypes = [ttp, ttp, ctypes.c_int64, i64p, ctypes.c_uint64, ctypes.c_int64, ctypes.c_double, vp,
                               ctypes.c_int64, vp, vp, ctypes.c_size_t, vp]
+    L.tt_scale.argtypes = [ttp, vp, ctypes.c_int32, vp]
     L.tt_round_plan.argtypes = [ttp, i64p, szp, i64p]
     L.tt_round.argtypes = [ttp, ctypes.c_int64, ctypes.c_double, vp, ctypes.c_int64, vp, vp, ctypes.c_size_t, vp]
     L.tt_norm_plan.argtypes = [ttp, szp]

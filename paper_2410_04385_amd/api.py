@@ -337,6 +337,17 @@ def randorth(a: TT, ell, *, max_rank: int = 0, tol: float = 0.0, seed: int = 0, 
     return Result(out, ranks)
 
 
+def scale(a: TT, alpha: torch.Tensor, invert: bool = False, stream=None) -> TT:
+    """In place: train b of ``a`` times alpha[b] (divided by it with
+    invert); alpha is a float64 device tensor of length batch."""
+    if alpha.dtype != torch.float64 or alpha.numel() < a.batch:
+        raise ValueError("alpha must be float64 with batch entries")
+    av, ka = a.view()
+    check("tt_scale", lib().tt_scale(ctypes.byref(av), ctypes.c_void_p(alpha.data_ptr()), int(bool(invert)),
+                                     _stream_ptr(stream)))
+    return a
+
+
 def round_plan(a: TT):
     av, ka = a.view()
     cap = (ctypes.c_int64 * (a.d + 1))()

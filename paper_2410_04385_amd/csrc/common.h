@@ -120,6 +120,9 @@ hipError_t launch_cast_f32(const double *src, int64_t sbs, float *dst, int64_t d
 // Per pair, scale w[p * bs .. + count) by the power of two that puts its
 // largest magnitude in [1, 2).
 hipError_t launch_rescale_pow2(float *w, int64_t count, int64_t bs, int batch, hipStream_t s);
+// x[p * bs + k] *= alpha[p] (or /= with invert), k < count; alpha on the device.
+hipError_t launch_scale_by(double *x, int64_t count, int64_t bs, const double *alpha, int invert, int batch,
+                           hipStream_t s);
 // Batched strided copy: dst(r, c) = src(r, c) for an M x N block.
 hipError_t launch_copy(CMat src, Mat dst, int64_t M, int64_t N, int batch, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t s);

@@ -2131,6 +2131,19 @@ hatt_status tt_norm(const hatt_tt *a, double *out, void *ws, size_t ws_bytes, vo
   return st;
 }
 
+hatt_status tt_scale(const hatt_tt *a, const double *alpha, int32_t invert, void *stream) {
+  Shape A;
+  hatt_status rc = read_tt(a, "a", &A, true);
+  if (rc != HATT_OK) return rc;
+  if (alpha == nullptr) return fail(HATT_EINVAL, "alpha is NULL");
+  if (invert != 0 && invert != 1) return fail(HATT_EINVAL, "invert must be 0 or 1");
+  const bool run = true;
+  hipStream_t st = (hipStream_t)stream;
+  LAUNCH(launch_scale_by(A.data, A.r[0] * A.n[0] * A.r[1], A.stride, alpha, invert, A.batch, st));
+  g_err.clear();
+  return HATT_OK;
+}
+
 hatt_status hatt_sketch_fill(uint64_t seed, int32_t d, const int64_t *n, const int64_t *ell, double *out,
                              void *stream) {
   if (d < 1 || n == nullptr || ell == nullptr || out == nullptr)

@@ -446,6 +446,23 @@ hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// x[p * bs + k] *= alpha[p] (invert = 0) or /= alpha[p] (invert = 1), k < count.
+__global__ void scale_by_kernel(double *x, int64_t count, int64_t bs, const double *alpha, int invert) {
+  const int p = blockIdx.y;
+  const double a = invert ? 1.0 / alpha[p] : alpha[p];
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x)
+    x[p * bs + k] *= a;
+}
+
+hipError_t launch_scale_by(double *x, int64_t count, int64_t bs, const double *alpha, int invert, int batch,
+                           hipStream_t s) {
+  if (count <= 0 || batch <= 0) return hipSuccess;
+  dim3 grid((unsigned)std::min<int64_t>((count + 255) / 256, 4096), (unsigned)batch);
+  scale_by_kernel<<<grid, 256, 0, s>>>(x, count, bs, alpha, invert);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 __global__ void copy_kernel(CMat src, Mat dst, int64_t M, int64_t N, int batch) {
   const int64_t per = M * N, total = per * batch;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;

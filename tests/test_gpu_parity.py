@@ -699,3 +699,73 @@ def test_randorth_explicit_matches_oracle_and_hatt(shape):
     torch.cuda.synchronize()
     assert g2.ranks[0].tolist() == h2.ranks[0].tolist()
     assert tt.rel_err(g2.train(0), h2.train(0)) <= TOL
+
+
+def _gpu_power(Y, ell, iters, seed):
+    """Power iteration on the GPU (Sec. 5, Example 3): HaTT with the Philox
+    sketch keyed by seed + t, the norm, and the normalisation by tt_scale."""
+    X = H.TT.from_cores([np.ones((1, k, 1)) for k in Y.n])
+    H.scale(X, H.norm(X), invert=True)
+    lams = []
+    for t in range(iters):
+        Z = H.recompress(X, Y, ell, seed=seed + t).out
+        nz = H.norm(Z)
+        lams.append(nz)
+        H.scale(Z, nz, invert=True)
+        X = Z
+    torch.cuda.synchronize()
+    return [float(v.item()) for v in lams], X
+
+
+@pytest.mark.parametrize("fn", ["qing", "alpine"])
+def test_power_iteration_matches_oracle(fn):
+    """Twelve power-iteration steps at the paper's width l = 5 on a d = 8
+    Qing / Alpine tensor (10 points per mode, rank 8): the estimate sequence
+    and the final iterate against the oracle's with the same sketches."""
+    from oracle import power
+    vals = (wk.qing_values if fn == "qing" else wk.alpine_values)(8)
+    y = wk.separable_sum_tt(vals)
+    _say(f"power iteration {fn} d=8 l=5, 12 steps")
+    lam, X = _gpu_power(H.TT.from_cores(y), 5, 12, 40)
+    lam_ref, x_ref = power.power_iteration(y, 5, 12, 40)
+    assert np.allclose(lam, lam_ref, rtol=1e-10, atol=0)
+    assert tt.rel_err(X.to_numpy(0), x_ref) <= 1e-9
+
+
+def test_qtt_trig_product_adaptive_matches_oracle():
+    """QTT shape of the Allen-Cahn solutions (mode size 2, order 12): phi (.)
+    phi at tol 1e-8 by the tolerance mode, same widths, attempts, ranks and
+    tensor as the oracle's, and pointwise within tol of the closed form."""
+    from oracle import adapt
+    phi, a, ks = wk.qtt_trig_field(5, 4, terms=4)
+    _say("hatt_recompress_adaptive QTT 16^3 (d=12, n=2) phi*phi tol=1e-8")
+    P = H.TT.from_cores(phi)
+    res, ell, att = H.recompress_adaptive(P, P, 1e-8, seed=8)
+    torch.cuda.synchronize()
+    outs, l_ref, att_ref, ok = adapt.hatt_adaptive([(phi, phi)], tol=1e-8, seed=8)
+    assert ok and ell == l_ref and att == att_ref
+    got = res.train(0)
+    assert tt.ranks(got) == tt.ranks(outs[0])
+    assert tt.rel_err(got, outs[0]) <= TOL
+    f = tt.full(phi).reshape(-1) ** 2
+    assert np.linalg.norm(tt.full(got).reshape(-1) - f) <= 1e-8 * np.linalg.norm(f)
+
+
+def test_qtt_allen_cahn_cubic_order_21():
+    """phi^3 = (phi (.) phi) (.) phi on the 128^3 grid in QTT format (order
+    21, phi of rank 30): both products by the tolerance mode at 1e-8,
+    against the closed-form field on all 2^21 points."""
+    phi, a, ks = wk.qtt_trig_field(9, 7, terms=15)
+    P = H.TT.from_cores(phi)
+    _say("QTT order 21: phi*phi, then *phi, tol 1e-8")
+    r2, ell2, att2 = H.recompress_adaptive(P, P, 1e-8, seed=1)
+    torch.cuda.synchronize()
+    u2 = H.TT.from_device_cores(H.kept_cores(r2))
+    r3, ell3, att3 = H.recompress_adaptive(u2, P, 1e-8, seed=2)
+    torch.cuda.synchronize()
+    f = tt.full(phi).reshape(-1)
+    g2 = tt.full(r2.train(0)).reshape(-1)
+    g3 = tt.full(r3.train(0)).reshape(-1)
+    assert np.linalg.norm(g2 - f ** 2) <= 1e-8 * np.linalg.norm(f ** 2)
+    assert np.linalg.norm(g3 - f ** 3) <= 3e-8 * np.linalg.norm(f ** 3)
+    assert max(r3.ranks[0].tolist()) <= 2 * max(ell3)

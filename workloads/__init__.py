@@ -24,4 +24,9 @@ from .gen import (  # noqa: F401
     modes_of,
     feasible_ranks,
     mlp_init,
+    separable_sum_tt,
+    qing_values,
+    alpine_values,
+    qtt_sine,
+    qtt_trig_field,
 )

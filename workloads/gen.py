@@ -9,6 +9,10 @@ Workloads (sizes and value laws):
                 of sin/cos with random amplitudes (ranks [1,40,40,1]).
 * ``batched``   512 pairs with d in [8,32], n in {16,32,64}, ranks in [8,48],
                 cores as in ``spectral``.
+* ``power``     Qing and Alpine functions on 10^d grids (d = 10..50) as rank-d
+                TTs, for the power iteration that finds their largest entry.
+* ``qtt``       QTT (mode size 2, order 3D) trig fields on (2^D)^3 grids, the
+                shape of the Allen-Cahn solutions (ranks up to 30).
 """
 
 from __future__ import annotations
@@ -25,6 +29,8 @@ WORKLOADS = {
     "spectral": dict(d=20, n=32, r=20, ell=40, max_rank=30),
     "trig": dict(d=3, n=256, r=40, nfreq=20, tol=1e-8, ell2=96, ell3=128),
     "batched": dict(pairs=512, d=(8, 32), n=(16, 32, 64), r=(8, 48), tol=1e-6),
+    "power": dict(d=(10, 20, 30, 40, 50), n=10, ell=5, iters=100),
+    "qtt": dict(D=(7, 9, 12, 15), terms=15, tol=1e-8),
 }
 
 
@@ -127,6 +133,109 @@ def trig_u(seed: int, n: int = 256, terms: int = 40, nfreq: int = 20) -> TT:
         c2[t, :, t] = f[1][t]
     c3 = f[2][:, :, None]                                     # (T, n, 1)
     return [c1, c2, c3]
+
+
+def separable_sum_tt(values: Sequence[np.ndarray]) -> TT:
+    """f(x_1..x_d) = sum_k g_k(x_k) on a product grid, from the per-mode
+    values g_k (arrays of length n_k), as the rank-d TT of its d separable
+    terms (term t is g_t in mode t and 1 elsewhere): ranks [1, d, .., d, 1]."""
+    d = len(values)
+    cores = []
+    for k, g in enumerate(values):
+        n = len(g)
+        if d == 1:
+            cores.append(np.asarray(g, dtype=np.float64).reshape(1, n, 1))
+            continue
+        lr = 1 if k == 0 else d
+        rr = 1 if k == d - 1 else d
+        c = np.zeros((lr, n, rr))
+        for t in range(d):
+            v = g if t == k else np.ones(n)
+            if k == 0:
+                c[0, :, t] = v
+            elif k == d - 1:
+                c[t, :, 0] = v
+            else:
+                c[t, :, t] = v
+        cores.append(c)
+    return cores
+
+
+def qing_values(d: int, n: int = 10) -> List[np.ndarray]:
+    """Per-mode values of the Qing function sum_i (x_i - i)^2 on n uniform
+    points of [-500, 500] (endpoints included), i = 1..d."""
+    x = np.linspace(-500.0, 500.0, n)
+    return [(x - (i + 1)) ** 2 for i in range(d)]
+
+
+def alpine_values(d: int, n: int = 10) -> List[np.ndarray]:
+    """Per-mode values of the Alpine function sum_i |x_i sin x_i + 0.1 x_i|
+    on n uniform points of [-2.5 pi, 2.5 pi] (endpoints included)."""
+    x = np.linspace(-2.5 * math.pi, 2.5 * math.pi, n)
+    g = np.abs(x * np.sin(x) + 0.1 * x)
+    return [g.copy() for _ in range(d)]
+
+
+def qtt_sine(k: float, D: int) -> TT:
+    """sin(k x_j) on the periodic grid x_j = h (j - 1/2), h = 2 pi / 2^D,
+    j = 1..2^D, as a QTT of order D (mode sizes 2, ranks 2): with
+    j - 1 = sum_b i_b 2^(D-b) (i_1 the most significant bit), the angle is
+    k h / 2 + sum_b theta_b i_b, theta_b = k h 2^(D-b), carried as
+    [cos, sin] through the rotations of the cores."""
+    h = 2.0 * math.pi / (1 << D)
+    cores = []
+    for b in range(1, D + 1):
+        th = k * h * (1 << (D - b))
+        c = np.zeros((2, 2, 2))
+        for i in (0, 1):
+            a = th * i
+            c[:, i, :] = [[math.cos(a), math.sin(a)], [-math.sin(a), math.cos(a)]]
+        cores.append(c)
+    a0 = k * h / 2.0
+    first = np.einsum("p,pir->ir", np.array([math.cos(a0), math.sin(a0)]), cores[0])[None, :, :]
+    last = np.einsum("pir,r->pi", cores[-1], np.array([0.0, 1.0]))[:, :, None]
+    if D == 1:
+        return [np.einsum("ir,r->i", first[0], np.array([0.0, 1.0])).reshape(1, 2, 1)]
+    return [first] + cores[1:-1] + [last]
+
+
+def qtt_trig_field(seed: int, D: int, terms: int = 15, kmax: int = 6):
+    """phi(x1, x2, x3) = sum_t a_t sin(k_t1 x1) sin(k_t2 x2) sin(k_t3 x3) on
+    the (2^D)^3 periodic grid as a QTT of order 3D (mode sizes 2; the D bits
+    of x1, then of x2, then of x3), a_t ~ U[0.1, 1.1], k ~ U{1..kmax}; the
+    shape of the Allen-Cahn solutions of Sec. 5 (ranks up to 2 terms).
+    Returns (cores, amplitudes, frequencies [terms][3])."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.1, 1.1, size=terms)
+    ks = rng.integers(1, kmax + 1, size=(terms, 3))
+    d = 3 * D
+    parts = []
+    for t in range(terms):
+        cs = []
+        for m in range(3):
+            cs += qtt_sine(float(ks[t, m]), D)
+        cs[0] = cs[0] * a[t]
+        parts.append(cs)
+    # sum of the terms: first cores side by side, last cores stacked,
+    # interior cores block-diagonal
+    cores = []
+    for k in range(d):
+        blocks = [p[k] for p in parts]
+        if k == 0:
+            cores.append(np.concatenate(blocks, axis=2))
+        elif k == d - 1:
+            cores.append(np.concatenate(blocks, axis=0))
+        else:
+            rl = sum(b.shape[0] for b in blocks)
+            rr = sum(b.shape[2] for b in blocks)
+            c = np.zeros((rl, 2, rr))
+            i0 = j0 = 0
+            for b in blocks:
+                c[i0:i0 + b.shape[0], :, j0:j0 + b.shape[2]] = b
+                i0 += b.shape[0]
+                j0 += b.shape[2]
+            cores.append(c)
+    return cores, a, ks
 
 
 def batched_pair_shapes(seed: int, pairs: int = 512):
