@@ -45,7 +45,7 @@ def _parse():
     ap.add_argument("--rp-train", type=int, default=128, help="rankpred: training recompressions")
     ap.add_argument("--rp-eval", type=int, default=24, help="rankpred: fresh pairs evaluated")
     ap.add_argument("--rp-margin", type=float, default=0.15, help="rankpred: width safety margin")
-    ap.add_argument("--workload", choices=["trig", "spectral", "batched", "rankpred"], default="trig",
+    ap.add_argument("--workload", choices=["trig", "spectral", "batched", "rankpred", "power", "qtt"], default="trig",
                     help="trig: the metric's tol-1e-8 workload (u2, u3 on the 256^3 grid); spectral: 512 "
                          "order-20 pairs truncated to rank 30; batched: 512 uneven pairs (own JSON lines)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -440,6 +440,151 @@ def _bench_trig(args, torch, wk, H, perfmodel) -> int:
     return 0
 
 
+def _bench_power(args, torch, wk, H) -> int:
+    """Power iteration for the largest entry (Sec. 5, Example 3): Qing and
+    Alpine functions on 10^d grids as rank-d TTs, 100 steps of
+    X <- HaTT(X (.) Y) / ||.|| at sketch width 5, for d = 10..50."""
+    cfg = wk.WORKLOADS["power"]
+    ell, iters = cfg["ell"], cfg["iters"]
+    say = lambda m: print(f"[power] {m}", file=sys.stderr, flush=True)  # noqa: E731
+    rows = []
+    for fn in ("qing", "alpine"):
+        for d in cfg["d"]:
+            vals = (wk.qing_values if fn == "qing" else wk.alpine_values)(d, cfg["n"])
+            Y = H.TT.from_cores(wk.separable_sum_tt(vals))
+            top = float(sum(v.max() for v in vals))
+
+            def run():
+                X = H.TT.from_cores([np.ones((1, k, 1)) for k in Y.n])
+                H.scale(X, H.norm(X), invert=True)
+                lam = None
+                for t in range(iters):
+                    Z = H.recompress(X, Y, ell, seed=500 + t).out
+                    lam = H.norm(Z)
+                    H.scale(Z, lam, invert=True)
+                    X = Z
+                return lam
+
+            run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lam = run()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            est = float(lam.item())
+            rows.append({"function": fn, "d": d, "steps": iters, "s": dt, "ms_per_step": 1000 * dt / iters,
+                         "largest_entry": top, "estimate": est, "rel_err": abs(est - top) / top})
+            say(f"{fn} d={d}: {1000 * dt / iters:.2f} ms/step, estimate rel err {abs(est - top) / top:.2e}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_info
+
+        from oracle import power
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        vals = wk.qing_values(10, cfg["n"])
+        t0 = time.perf_counter()
+        power.power_iteration(wk.separable_sum_tt(vals), ell, 20, 500)
+        dt = time.perf_counter() - t0
+        cpu = {"value": 20 / dt, "unit": "power-iteration steps/s", "cores": threads, "kind": "oracle",
+               "sample": "20 steps of the oracle's power iteration on the d=10 Qing tensor"}
+    tot = sum(r["s"] for r in rows)
+    steps = sum(r["steps"] for r in rows)
+    line = {"metric": "power-iteration steps/s (HaTT at width 5, largest entry of Qing / Alpine TTs)",
+            "value": steps / tot, "unit": "steps/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+            "data": "synthetic", "vs_baseline": None,
+            "config": {"workload": f"power iteration, Qing and Alpine, n={cfg['n']}, d={list(cfg['d'])}, "
+                                   f"l={ell}, {iters} steps", "launch": "eager"},
+            "runs": rows, "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def _tt_entries(cores, idx):
+    """Entries of a TT (host cores) at the multi-indices idx [samples][d]."""
+    out = np.empty(len(idx))
+    for s, ii in enumerate(idx):
+        v = cores[0][:, ii[0], :]
+        for k in range(1, len(cores)):
+            v = v @ cores[k][:, ii[k], :]
+        out[s] = v[0, 0]
+    return out
+
+
+def _bench_qtt(args, torch, wk, H) -> int:
+    """The Allen-Cahn nonlinearity in QTT format (Sec. 5, Example 4, eq.
+    QTTlinear): phi of rank 30 on (2^D)^3 grids as an order-3D train of
+    mode size 2; phi2 = phi (.) phi and phi3 = phi2 (.) phi by the tolerance
+    mode at 1e-8, for D = 7, 9, 12, 15."""
+    cfg = wk.WORKLOADS["qtt"]
+    tol = cfg["tol"]
+    say = lambda m: print(f"[qtt] {m}", file=sys.stderr, flush=True)  # noqa: E731
+    rows = []
+    for D in cfg["D"]:
+        phi, amp, ks = wk.qtt_trig_field(9, D, terms=cfg["terms"])
+        P = H.TT.from_cores(phi)
+
+        def run():
+            r2, ell2, a2 = H.recompress_adaptive(P, P, tol, seed=1)
+            u2 = H.TT.from_device_cores(H.kept_cores(r2))
+            r3, ell3, a3 = H.recompress_adaptive(u2, P, tol, seed=2)
+            return r2, ell2, a2, r3, ell3, a3
+
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r2, ell2, a2 = H.recompress_adaptive(P, P, tol, seed=1)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter() - t0
+        u2 = H.TT.from_device_cores(H.kept_cores(r2))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r3, ell3, a3 = H.recompress_adaptive(u2, P, tol, seed=2)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter() - t0
+        # pointwise error at 4096 sampled grid points against the closed form
+        g = np.random.default_rng(D)
+        idx = g.integers(0, 2, size=(4096, 3 * D))
+        n = 1 << D
+        h = 2 * np.pi / n
+        f = np.zeros(len(idx))
+        jj = [(idx[:, m * D:(m + 1) * D] * (1 << np.arange(D - 1, -1, -1))).sum(1) for m in range(3)]
+        xx = [h * (j + 0.5) for j in jj]
+        for t in range(len(amp)):
+            f += amp[t] * np.sin(ks[t, 0] * xx[0]) * np.sin(ks[t, 1] * xx[1]) * np.sin(ks[t, 2] * xx[2])
+        e2 = _tt_entries(r2.train(0), idx)
+        e3 = _tt_entries(r3.train(0), idx)
+        rows.append({"D": D, "order": 3 * D, "phi_rank": max(wk.ranks_of(phi)),
+                     "phi2": {"ms": 1000 * t2, "attempts": a2, "max_width": max(ell2),
+                              "max_rank": max(r2.ranks[0].tolist()),
+                              "sampled_rel_err": float(np.linalg.norm(e2 - f ** 2) / np.linalg.norm(f ** 2))},
+                     "phi3": {"ms": 1000 * t3, "attempts": a3, "max_width": max(ell3),
+                              "max_rank": max(r3.ranks[0].tolist()),
+                              "sampled_rel_err": float(np.linalg.norm(e3 - f ** 3) / np.linalg.norm(f ** 3))}})
+        say(f"D={D}: phi2 {1000 * t2:.1f} ms ({a2} attempts, rank {max(r2.ranks[0].tolist())}), "
+            f"phi3 {1000 * t3:.1f} ms ({a3} attempts, rank {max(r3.ranks[0].tolist())})")
+    cpu = None
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_info
+
+        from oracle import adapt
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        phi, _, _ = wk.qtt_trig_field(9, 7, terms=cfg["terms"])
+        t0 = time.perf_counter()
+        adapt.hatt_adaptive([(phi, phi)], tol=tol, seed=1)
+        dt = time.perf_counter() - t0
+        cpu = {"value": 1.0 / dt, "unit": "recompressions/s", "cores": threads, "kind": "oracle",
+               "sample": "phi (.) phi at D=7 (order 21) by the oracle's tolerance mode"}
+    tot = sum(r["phi2"]["ms"] + r["phi3"]["ms"] for r in rows) / 1000.0
+    line = {"metric": "QTT Allen-Cahn nonlinearity: tolerance-mode recompressions/s (phi^2, phi^3)",
+            "value": 2 * len(rows) / tot, "unit": "recompressions/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "f64", "data": "synthetic", "vs_baseline": None,
+            "config": {"workload": f"QTT trig field rank {2 * cfg['terms']}, D={list(cfg['D'])} (order 3D, mode "
+                                   f"size 2), tol {tol:g}", "launch": "eager"},
+            "runs": rows, "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def _rp_pairs(wk, H, seed, count, max_rs=1024):
     """Pairs of the uneven 512-pair distribution (spectral cores), leaving
     out those whose exact rank r_x r_y exceeds the 1024-column SVD limit."""
@@ -575,6 +720,10 @@ def main() -> int:
         return _bench_rankpred(args, torch, wk, H)
     if args.workload == "trig":
         return _bench_trig(args, torch, wk, H, perfmodel)
+    if args.workload == "power":
+        return _bench_power(args, torch, wk, H)
+    if args.workload == "qtt":
+        return _bench_qtt(args, torch, wk, H)
     cfg = wk.WORKLOADS["spectral"]
     d, n, r, ell, cap = cfg["d"], cfg["n"], cfg["r"], cfg["ell"], cfg["max_rank"]
     B = args.batch

@@ -171,9 +171,12 @@ HATT_API hatt_status hatt_recompress_batched(int32_t npairs, const hatt_tt *x, c
  *   accept when every bond keeps rho_k <= l_k - p or l_k is at its largest
  *   feasible value; else on each failing bond (failing for any train of the
  *   batch) l_k = min(cap_k, ceil(1.5 l_k) + p) and retry.
- * hatt_adaptive_plan: cap_out (host [d+1]) = largest feasible widths,
- * ws_bytes = workspace for any attempt, out_elems = elements of one output
- * train at the cap widths (the per-train slot size).
+ * Widths never grow beyond 1024 (the truncation's SVD limit): a bond that
+ * would need more returns HATT_ENOTCONV.
+ * hatt_adaptive_plan: cap_out (host [d+1]) = largest widths the growth may
+ * reach (the feasible widths, clamped to 1024), ws_bytes = workspace for any
+ * attempt, out_elems = elements of one output train at those widths (the
+ * per-train slot size).
  * hatt_recompress_adaptive: synchronises `stream` once per attempt (the
  * decision needs the kept ranks on the host).  The result of the last
  * attempt is written per train at the widths returned in ell_out (host

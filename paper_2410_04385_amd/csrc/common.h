@@ -217,10 +217,11 @@ const char *hh_qr_kernel_name(int64_t m, int64_t n);
 // X = R^{-1} of upper triangular R (n x n row-major, n <= 128); flag as in
 // launch_chol (cleared by a zero or non-finite diagonal entry; may be null).
 // With mask (int [n] per pair, stride mbs): columns whose diagonal entry is
-// at most 1e-12 of the column's norm are replaced by a unit column (scaled
-// to the largest diagonal entry) before inversion and marked 1.
+// at most 1e-12 of the column's norm (dep_abs <= 0), or at most dep_abs
+// (dep_abs > 0), are replaced by a unit column (scaled to the largest
+// diagonal entry) before inversion and marked 1.
 hipError_t launch_trinv(const double *r, int64_t rbs, double *x, int64_t xbs, int n, int *flag, int64_t fstride,
-                        int first, int *mask, int64_t mbs, int batch, hipStream_t s);
+                        int first, int *mask, int64_t mbs, double dep_abs, int batch, hipStream_t s);
 // Replace the masked columns of A (m x n row-major, pair stride abs) by
 // unit-norm random sign vectors.
 hipError_t launch_complete_cols(double *a, int64_t m, int n, int64_t abs_, const int *mask, int64_t mbs,

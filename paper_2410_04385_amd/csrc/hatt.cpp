@@ -318,6 +318,7 @@ struct QrOp {
   std::shared_ptr<QrOp> sub;
   QrPlan direct{};
   std::vector<QrOp> panels;          // big: one QR per panel (CholeskyQR2 or TSQR)
+  std::vector<QrOp> panels2;         // big: second-pass QR per panel (projected preconditioned CholeskyQR2)
   int64_t panel = 0;                 // big: panel width
   int64_t ws_doubles = 0;  // per pair
   int64_t ws_tree = 0;     // big: TSQR tree part at the front; chol: fallback TSQR tree
@@ -337,6 +338,24 @@ int64_t chol_ws_doubles(int64_t m, int64_t n) { return m * n + 5 * n * n + 1; }
 // pchol scratch after the CholeskyQR2 block: A' (m n), B (k n), R0, R0^{-1},
 // T (n n each), the dependent-column mask (n ints)
 int64_t pchol_ws_doubles(int64_t m, int64_t n, int64_t k) { return m * n + k * n + 3 * n * n + n; }
+
+// Sketch-preconditioned CholeskyQR2 for the second pass of a panel (any
+// m >= n, n <= kPcholMaxN): the sketch keeps min(m, kPcholSketchRows) rows
+// (for m at most that, a signed row permutation), the TSQR plan, where one
+// exists, is the fallback.
+bool qr_prepare_pass2(int64_t m, int64_t n, QrOp *op) {
+  *op = QrOp{};
+  op->m = m;
+  op->n = n;
+  op->k = std::min(m, n);
+  op->sk_rows = std::min<int64_t>(m, kPcholSketchRows);
+  if (m < n || n > kPcholMaxN || !hh_qr_supported(op->sk_rows, n)) return false;
+  op->pchol = true;
+  op->has_direct = qr_make_plan(m, n, &op->direct);
+  op->ws_tree = op->has_direct ? op->direct.ws_doubles : 0;
+  op->ws_doubles = op->ws_tree + chol_ws_doubles(m, n) + pchol_ws_doubles(m, n, op->sk_rows);
+  return true;
+}
 
 bool qr_prepare(int64_t m, int64_t n, QrOp *op) {
   op->m = m;
@@ -392,6 +411,7 @@ bool qr_prepare(int64_t m, int64_t n, QrOp *op) {
   }
   op->big = true;
   op->panels.clear();
+  op->panels2.clear();
   // panels: preconditioned CholeskyQR2 takes 128 columns; a Householder TSQR
   // panel (method 1) at most 64, where a tree of >= 2n-row blocks exists
   const int64_t panel = g_use_chol ? kPanel : 64;
@@ -399,10 +419,15 @@ bool qr_prepare(int64_t m, int64_t n, QrOp *op) {
   int64_t w = 0;
   for (int64_t c0 = 0; c0 < n; c0 += panel) {
     const int64_t cw = std::min(panel, n - c0);
-    QrOp pl;
+    QrOp pl, pl2;
     if (!qr_prepare(m, cw, &pl) || pl.big || pl.wide) return false;
     op->panels.push_back(pl);
     w = std::max(w, pl.ws_doubles);
+    if (c0 > 0) {
+      if (!qr_prepare_pass2(m, cw, &pl2)) return false;
+      w = std::max(w, pl2.ws_doubles);
+    }
+    op->panels2.push_back(pl2);
   }
   op->ws_tree = w;
   op->panel = panel;
@@ -412,6 +437,10 @@ bool qr_prepare(int64_t m, int64_t n, QrOp *op) {
 }
 
 constexpr int kCholFuseMinPairs = 32;
+// Second-pass dependence threshold of a panel (its columns are projections
+// of orthonormal vectors): a direction within 1e-7 of the earlier panels
+// carries at most ~1e-14 of the input (the projection's rounding noise).
+constexpr double kPass2DepAbs = 1e-7;
 
 // CholeskyQR2 that leaves Q = Q1 R2^{-1} unformed for the pairs it keeps:
 // the caller applies Q1 and R2^{-1} itself (Q holds the fallback's Q for the
@@ -427,8 +456,24 @@ struct QrDeferred {
   bool used = false;
 };
 
+// Optional projection (second pass of a panel): prev holds the c0
+// orthonormal columns of the earlier panels and A is already projected
+// against them.  Then a sketch pivot at most dep_abs marks its column as
+// dependent (A's columns are projections of orthonormal vectors, so such a
+// direction lies within that angle of the earlier panels and carries
+// nothing of the input), and A' (completion vectors included) is projected
+// twice against prev before its CholeskyQR2, so that Q is orthogonal to the
+// earlier panels to working precision.  pscr: c0 x n doubles per pair.
+struct PcholProj {
+  CMat prev{};
+  int64_t c0 = 0;
+  double *pscr = nullptr;
+  double dep_abs = 0.0;
+};
+
 hatt_status pchol_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double *ws, int64_t wsp, int P,
-                       GemmCtx &gc, hipStream_t st, QrDeferred *def, uint32_t salt) {
+                       GemmCtx &gc, hipStream_t st, QrDeferred *def, uint32_t salt,
+                       const PcholProj *proj = nullptr) {
   const int64_t m = op.m, n = op.n, k = op.sk_rows;
   double *q1 = ws + op.ws_tree;  // m x n row-major
   double *g = q1 + m * n;
@@ -460,11 +505,21 @@ hatt_status pchol_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, double *w
   // most 1e-13 of the largest) are marked and their columns of A' replaced
   // by random unit vectors: Q then spans range(A) plus those directions
   site("pchol trinv %lld", (long long)n);
-  LAUNCH(launch_trinv(R0, wsp, R0i, wsp, (int)n, flag, fst, 1, mask, mbs, P, st));
+  LAUNCH(launch_trinv(R0, wsp, R0i, wsp, (int)n, flag, fst, 1, mask, mbs, proj ? proj->dep_abs : 0.0, P, st));
   sg = gemm(run, gc, A, CMat{R0i, n, 1, wsp}, Mat{ap, n, 1, wsp}, m, n, n, 1.0, 0.0, P, st, false);
   if (sg != HATT_OK) return sg;
   site("pchol complete %lldx%lld", (long long)m, (long long)n);
   LAUNCH(launch_complete_cols(ap, m, (int)n, wsp, mask, mbs, 0x7F4A7C15u ^ (salt * 0x9E3779B9u), P, st));
+  if (proj != nullptr && proj->c0 > 0) {
+    const CMat pv = proj->prev, pvt{pv.ptr, pv.cs, pv.rs, pv.bs};
+    for (int pass = 0; pass < 2; ++pass) {
+      sg = gemm(run, gc, pvt, apc, Mat{proj->pscr, n, 1, wsp}, proj->c0, n, m, 1.0, 0.0, P, st, true);
+      if (sg != HATT_OK) return sg;
+      sg = gemm(run, gc, pv, CMat{proj->pscr, n, 1, wsp}, Mat{ap, n, 1, wsp}, m, n, proj->c0, -1.0, 1.0, P, st,
+                false);
+      if (sg != HATT_OK) return sg;
+    }
+  }
   // CholeskyQR2 of A'
   sg = gemm(run, gc, apt, apc, Mat{g, n, 1, wsp}, n, n, m, 1.0, 0.0, P, st, true);
   if (sg != HATT_OK) return sg;
@@ -638,8 +693,18 @@ hatt_status qr_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, int64_t rbuf
     if (sg != HATT_OK) return sg;
     sg = gemm(run, gc, Qprev, CMat{s2buf, cw, 1, wsp}, Qpan, m, cw, c0, -1.0, 1.0, P, st, false);
     if (sg != HATT_OK) return sg;
+    // the panel now spans what the input adds to the earlier panels, plus
+    // directions that the first pass took from rounding noise; those lie
+    // within a small angle of the earlier panels, so this pass replaces
+    // them (sketch pivots below 1e-7) by random directions orthogonal to
+    // the earlier panels
     Mat r2 = R.ptr ? Mat{r2buf, cw, 1, wsp} : Mat{nullptr, 0, 0, 0};
-    sg = qr_exec(run, op.panels[pi], Qpanc, Qpan, r2, rbuf, ws, wsp, P, gc, st, nullptr, 2u * (uint32_t)pi + 3u);
+    PcholProj pj;
+    pj.prev = Qprev;
+    pj.c0 = c0;
+    pj.pscr = s1buf;
+    pj.dep_abs = kPass2DepAbs;
+    sg = pchol_exec(run, op.panels2[pi], Qpanc, Qpan, r2, ws, wsp, P, gc, st, nullptr, 2u * (uint32_t)pi + 3u, &pj);
     if (sg != HATT_OK) return sg;
     if (R.ptr) {
       // R(prev, p) += S2 R1;  R(p, p) = R2 R1
@@ -1896,9 +1961,15 @@ hatt_status hatt_recompress_batched(int32_t npairs, const hatt_tt *x, const hatt
 }
 
 // ---------------------------------------------------------------------------
+// Largest width the tolerance mode grows a bond to: the truncation's SVD
+// takes at most kSvdBigMaxN columns.
+constexpr int64_t kAdaptMaxWidth = kSvdBigMaxN;
+
+// cap: the largest feasible widths (a bond at its cap is exact); lim: the
+// widths the growth may reach (cap clamped to kAdaptMaxWidth).
 static hatt_status adapt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_adapt_opts *ao, HattSpec *sp,
-                                 std::vector<int64_t> *cap, std::vector<int64_t> *ell0, int *p, int *maxa,
-                                 bool need_data) {
+                                 std::vector<int64_t> *cap, std::vector<int64_t> *lim, std::vector<int64_t> *ell0,
+                                 int *p, int *maxa, bool need_data) {
   if (ao == nullptr) return fail(HATT_EINVAL, "adapt opts is NULL");
   if (!(ao->tol > 0.0) || !std::isfinite(ao->tol)) return fail(HATT_EINVAL, "tol must be finite and > 0");
   hatt_opts o{};
@@ -1914,9 +1985,11 @@ static hatt_status adapt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_
   *maxa = ao->max_attempts > 0 ? ao->max_attempts : 8;
   std::vector<int64_t> big(d + 1, (int64_t)1 << 40), req(d + 1, 1);
   *cap = clamp_ell(sp->X.n, sp->X.r, sp->Y.r, big);
-  for (int k = 1; k < d; ++k) req[k] = std::max(sp->X.r[k], sp->Y.r[k]) + *p;
+  std::vector<int64_t> lreq(d + 1, kAdaptMaxWidth);
+  *lim = clamp_ell(sp->X.n, sp->X.r, sp->Y.r, lreq);
+  for (int k = 1; k < d; ++k) req[k] = std::min(std::max(sp->X.r[k], sp->Y.r[k]) + *p, kAdaptMaxWidth);
   if (ao->ell_init != nullptr)
-    for (int k = 1; k < d; ++k) req[k] = ao->ell_init[k];
+    for (int k = 1; k < d; ++k) req[k] = std::min(ao->ell_init[k], kAdaptMaxWidth);
   *ell0 = clamp_ell(sp->X.n, sp->X.r, sp->Y.r, req);
   return HATT_OK;
 }
@@ -1924,9 +1997,9 @@ static hatt_status adapt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_
 hatt_status hatt_adaptive_plan(const hatt_tt *x, const hatt_tt *y, const hatt_adapt_opts *opts, int64_t *cap_out,
                                size_t *ws_bytes, int64_t *out_elems) {
   HattSpec sp{};
-  std::vector<int64_t> cap, ell0;
+  std::vector<int64_t> cap_true, cap, ell0;
   int p, maxa;
-  hatt_status st = adapt_prepare(x, y, opts, &sp, &cap, &ell0, &p, &maxa, false);
+  hatt_status st = adapt_prepare(x, y, opts, &sp, &cap_true, &cap, &ell0, &p, &maxa, false);
   if (st != HATT_OK) return st;
   sp.ell = cap;
   sp.sketch = nullptr;
@@ -1952,16 +2025,16 @@ hatt_status hatt_recompress_adaptive(const hatt_tt *x, const hatt_tt *y, const h
                                      int64_t out_stride, int64_t *out_rank, int64_t *ell_out, int32_t *attempts_out,
                                      void *ws, size_t ws_bytes, void *stream) {
   HattSpec sp{};
-  std::vector<int64_t> cap, ell;
+  std::vector<int64_t> cap, lim, ell;
   int p, maxa;
-  hatt_status st = adapt_prepare(x, y, opts, &sp, &cap, &ell, &p, &maxa, true);
+  hatt_status st = adapt_prepare(x, y, opts, &sp, &cap, &lim, &ell, &p, &maxa, true);
   if (st != HATT_OK) return st;
   if (out == nullptr || out_rank == nullptr || ell_out == nullptr || attempts_out == nullptr)
     return fail(HATT_EINVAL, "NULL output argument");
   const int d = sp.X.d, P = sp.X.batch;
   std::vector<int64_t> coff;
   int64_t ctot;
-  make_offsets(sp.X.n, cap, &coff, &ctot);
+  make_offsets(sp.X.n, lim, &coff, &ctot);
   if (out_stride != 0 && out_stride < ctot) return fail(HATT_EINVAL, "out_stride smaller than the planned slot");
   sp.out = out;
   sp.ostride = out_stride ? out_stride : ctot;
@@ -1998,7 +2071,12 @@ hatt_status hatt_recompress_adaptive(const hatt_tt *x, const hatt_tt *y, const h
       return HATT_OK;
     }
     ell = sp.ell;
-    for (int k : bad) ell[k] = std::min<int64_t>(cap[k], (int64_t)std::ceil(1.5 * (double)sp.ell[k]) + p);
+    for (int k : bad) {
+      if (sp.ell[k] >= lim[k])
+        return fail(HATT_ENOTCONV, "bond " + std::to_string(k) + " needs a sketch wider than " +
+                                       std::to_string(lim[k]) + " (the truncation's SVD limit)");
+      ell[k] = std::min<int64_t>(lim[k], (int64_t)std::ceil(1.5 * (double)sp.ell[k]) + p);
+    }
   }
   return fail(HATT_ENOTCONV, "sketch widths did not converge within max_attempts");
 }

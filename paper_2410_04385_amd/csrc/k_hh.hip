@@ -330,7 +330,7 @@ constexpr double kDepRel = 1e-12;
 
 __global__ __launch_bounds__(1024) void trinv_kernel(const double *r, int64_t rbs, double *xo, int64_t xbs, int n,
                                                      int *flag, int64_t fstride, int first, int *mask,
-                                                     int64_t mbs) {
+                                                     int64_t mbs, double dep_abs) {
   extern __shared__ double Rs[];  // n x n, then the reciprocal diagonal
   double *dinv = Rs + n * n;
   __shared__ int ok_s;
@@ -350,13 +350,15 @@ __global__ __launch_bounds__(1024) void trinv_kernel(const double *r, int64_t rb
   const double dmax = dmax_s;
   if (mask != nullptr) {
     // one thread per column: a column whose pivot is at most kDepRel of its
-    // own norm (the norm of the factored column) depends on the ones before
-    // it; its entries above the diagonal are cleared
+    // own norm (the norm of the factored column), or at most dep_abs when
+    // that is set, depends on the ones before it; its entries above the
+    // diagonal are cleared
     for (int j = tid; j < n; j += 1024) {
       const double d = Rs[j * n + j];
       double cn = 0.0;
       for (int i = 0; i <= j; ++i) cn += Rs[i * n + j] * Rs[i * n + j];
-      const int dep = !(fabs(d) > kDepRel * sqrt(cn)) || !(fabs(d) > 1e-300) ? 1 : 0;  // also NaN
+      const double thr = dep_abs > 0.0 ? dep_abs : kDepRel * sqrt(cn);
+      const int dep = !(fabs(d) > thr) || !(fabs(d) > 1e-300) ? 1 : 0;  // also NaN
       mask[p * mbs + j] = dep;
       if (dep) {
         for (int i = 0; i < j; ++i) Rs[i * n + j] = 0.0;
@@ -417,7 +419,7 @@ __global__ __launch_bounds__(1024) void trinv_kernel(const double *r, int64_t rb
 }
 
 hipError_t launch_trinv(const double *r, int64_t rbs, double *x, int64_t xbs, int n, int *flag, int64_t fstride,
-                        int first, int *mask, int64_t mbs, int batch, hipStream_t s) {
+                        int first, int *mask, int64_t mbs, double dep_abs, int batch, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
   if (n < 1 || n > 128) return hipErrorInvalidValue;
   const size_t lds = (size_t)(n * n + n) * sizeof(double);
@@ -427,7 +429,7 @@ hipError_t launch_trinv(const double *r, int64_t rbs, double *x, int64_t xbs, in
                         (int)((128 * 128 + 128) * sizeof(double)));
     attr = true;
   }
-  trinv_kernel<<<batch, 1024, lds, s>>>(r, rbs, x, xbs, n, flag, fstride, first, mask, mbs);
+  trinv_kernel<<<batch, 1024, lds, s>>>(r, rbs, x, xbs, n, flag, fstride, first, mask, mbs, dep_abs);
   return hipGetLastError();
 }
 

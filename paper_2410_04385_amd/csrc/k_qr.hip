@@ -26,21 +26,25 @@
 namespace hatt {
 
 // Column chunk width the Q-forming kernel keeps in LDS next to the
-// reflectors, for a panel of n columns (largest that still lets a block hold
-// at least n rows).
-static int qr_chunk(int64_t n, int64_t k) {
+// reflectors, for an m x n matrix: the largest that lets a block hold 2n
+// rows (the tree then shrinks), else n rows.  A matrix of fewer than 2n rows
+// cannot be cut into blocks of n rows, so there one block must hold all m.
+static int qr_chunk(int64_t m, int64_t n, int64_t k) {
   const int cand[6] = {(int)std::min<int64_t>(k, 64), 32, 16, 8, 4, 1};
-  for (int need = 2; need >= 1; --need) {   // prefer blocks of >= 2n rows: the tree then shrinks
+  const int64_t need[2] = {m < 2 * n ? m : 2 * n, m < 2 * n ? m : n};
+  for (int t = 0; t < 2; ++t) {
     for (int i = 0; i < 6; ++i) {
       const int ch = std::max(1, std::min<int>(cand[i], (int)k));
       const int64_t mb = kQrLdsDoubles / (n + ch) - 1;
-      if (mb >= need * n) return ch;
+      if (mb >= need[t]) return ch;
     }
   }
   return 1;
 }
 
-static int64_t qr_block_rows_max(int64_t n, int64_t k) { return kQrLdsDoubles / (n + qr_chunk(n, k)) - 1; }
+static int64_t qr_block_rows_max(int64_t m, int64_t n, int64_t k) {
+  return kQrLdsDoubles / (n + qr_chunk(m, n, k)) - 1;
+}
 
 bool qr_make_plan(int64_t m, int64_t n, QrPlan *p) {
   if (m < 1 || n < 1 || n > kQrMaxCols) return false;
@@ -48,7 +52,7 @@ bool qr_make_plan(int64_t m, int64_t n, QrPlan *p) {
   q.m = m;
   q.n = n;
   q.k = std::min(m, n);
-  const int64_t mb = qr_block_rows_max(n, q.k);
+  const int64_t mb = qr_block_rows_max(m, n, q.k);
   if (mb < std::min(m, n)) return false;
   int64_t rows = m;
   int64_t off = 0;
@@ -58,7 +62,7 @@ bool qr_make_plan(int64_t m, int64_t n, QrPlan *p) {
     int64_t blocks;
     if (rows <= mb) blocks = 1;
     else blocks = std::max<int64_t>(1, std::min((rows + mb - 1) / mb, rows / n));
-    if (blocks > 1 && (rows + blocks - 1) / blocks > mb) return false;
+    if ((rows + blocks - 1) / blocks > mb) return false;  // a block must fit in LDS
     q.rows[L] = rows;
     q.blocks[L] = blocks;
     if (L > 0) {
@@ -318,7 +322,7 @@ hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_
                        hipStream_t s, const int *skip_flag, int64_t skip_stride) {
   if (batch <= 0) return hipSuccess;
   const int64_t n = p.n;
-  const int ch = qr_chunk(n, p.k);
+  const int ch = qr_chunk(p.m, n, p.k);
   const size_t lds_max = (size_t)kQrLdsDoubles * sizeof(double);
   static bool attr_done = false;  // set once: the maximum a launch may ask for
   if (!attr_done) {

@@ -298,6 +298,23 @@ def test_adaptive_start_widths_are_validated():
         api.recompress_adaptive(x, x, 1e-6, ell_init=[1, 5, 1])
 
 
+def test_adaptive_plan_limits_widths_to_the_svd_limit():
+    """A QTT pair (order 24, mode size 2) with ranks 33 and 40 has feasible
+    widths up to 1320; the tolerance mode plans its workspace for widths clamped to
+    the 1024-column truncation, and every width stays feasible."""
+    from oracle import plan as oplan
+    d = 24
+    rx = [1] + [min(2 ** k, 2 ** (d - k), 33) for k in range(1, d)] + [1]
+    ry = [1] + [min(2 ** k, 2 ** (d - k), 40) for k in range(1, d)] + [1]
+    n = [2] * d
+    x, y = _cpu_tt(n, rx), _cpu_tt(n, ry)
+    caps = api.adaptive_caps(x, y)
+    full = oplan.clamp_ell(n, rx, ry, [1] + [1 << 40] * (d - 1) + [1])
+    assert max(full) == 1320
+    assert caps == oplan.clamp_ell(n, rx, ry, [min(c, 1024) for c in full])
+    assert max(caps) == 1024
+
+
 def test_plan_rejects_sandwich_shapes_without_a_kernel():
     """Factor ranks 81 on both sides (u2 * u2 on the 256^3 grid) need a
     sandwich no kernel covers: the plan call reports it before any launch."""

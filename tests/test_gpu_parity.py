@@ -769,3 +769,62 @@ def test_qtt_allen_cahn_cubic_order_21():
     assert np.linalg.norm(g2 - f ** 2) <= 1e-8 * np.linalg.norm(f ** 2)
     assert np.linalg.norm(g3 - f ** 3) <= 3e-8 * np.linalg.norm(f ** 3)
     assert max(r3.ranks[0].tolist()) <= 2 * max(ell3)
+
+
+# Widths of the third tolerance-mode attempt for (phi (.) phi) (.) phi on the
+# 512^3 grid (order 27): bond 13 is 262 wide against an exact rank of 166,
+# so the sketched frame there is square (262 x 262) and rank deficient, and
+# its QR runs as panels whose later columns add nothing to the earlier ones.
+_QTT9_WIDTHS = [1, 2, 4, 8, 16, 32, 64, 65, 65, 43, 38, 76, 131, 262, 149, 124, 86, 65, 43, 38, 38, 38, 32, 16,
+                8, 4, 2, 1]
+
+
+@pytest.mark.parametrize("method", ["cholqr2", "householder"])
+def test_hatt_panelled_rank_deficient_square_frames(method):
+    """HaTT of a QTT pair whose wide bond needs a panelled QR of a square,
+    rank-deficient frame: the untruncated result equals the oracle's
+    (same sketch), and its TT-Rounding keeps the oracle's ranks."""
+    from oracle import adapt
+    phi, _, _ = wk.qtt_trig_field(9, 9, terms=15)
+    outs, _, _, ok = adapt.hatt_adaptive([(phi, phi)], tol=1e-8, seed=1)
+    assert ok
+    u2 = outs[0]
+    n = tt.modes(u2)
+    l = list(_QTT9_WIDTHS)
+    raw = ohatt.hatt(u2, phi, philox.sketch(4, n, l), 1, 0.0)
+    ref = rounding.tt_round(raw, tol=1e-8)
+    X, P = H.TT.from_cores(u2), H.TT.from_cores(phi)
+    _say(f"HaTT QTT order 27 widths up to 262, QR method {method}")
+    H.set_qr_method(method)
+    try:
+        got = H.recompress(X, P, l, seed=4)
+        rnd = H.recompress(X, P, l, tol=1e-8, seed=4)
+        torch.cuda.synchronize()
+    finally:
+        H.set_qr_method("cholqr2")
+    assert tt.ranks(got.train(0)) == tt.ranks(raw)
+    assert tt.rel_err(got.train(0), raw) <= TOL
+    assert tt.ranks(rnd.train(0)) == tt.ranks(ref)
+    assert tt.rel_err(rnd.train(0), ref) <= TOL
+
+
+def test_adaptive_widths_stop_at_svd_limit():
+    """The tolerance mode plans and grows widths only up to the 1024-column
+    truncation limit: (phi (.) phi) (.) phi on the 512^3 grid (order 27) has
+    feasible widths up to 2048 at the middle bonds; it plans, and its
+    attempts, widths, ranks and tensor equal the oracle's."""
+    from oracle import adapt
+    phi, _, _ = wk.qtt_trig_field(9, 9, terms=15)
+    outs, _, _, ok = adapt.hatt_adaptive([(phi, phi)], tol=1e-8, seed=1)
+    assert ok
+    u2 = outs[0]
+    X, P = H.TT.from_cores(u2), H.TT.from_cores(phi)
+    caps = H.adaptive_caps(X, P)
+    assert max(caps) == 1024
+    _say("adaptive plan with widths limited to 1024 (QTT order 27)")
+    r3, ell3, att3 = H.recompress_adaptive(X, P, 1e-8, seed=2)
+    torch.cuda.synchronize()
+    ref, l_ref, att_ref, ok = adapt.hatt_adaptive([(u2, phi)], tol=1e-8, seed=2)
+    assert ok and ell3 == l_ref and att3 == att_ref
+    assert tt.ranks(r3.train(0)) == tt.ranks(ref[0])
+    assert tt.rel_err(r3.train(0), ref[0]) <= TOL
