@@ -74,10 +74,12 @@ typedef struct {
   double tol;             /* relative Frobenius tolerance of that truncation; <= 0: none */
   uint64_t seed;          /* key of the Philox4x32-10 sketch (used when no sketch is passed) */
   int32_t precision;      /* 0: FP64 throughout; 1: FP32 range finding -- the HPCRL sketches
-                             W^{(k)} (W_L build and W_L W_R^T) and the sketched frames
-                             X^{(k)} W^{(k)} run on the FP32 matrix cores with FP32
-                             accumulation and storage, then QR, the projection Q^T X, the
-                             core update and the truncation run in FP64 (HaTT-1 only) */
+                             W^{(k)} (W_L build and W_L W_R^T, Alg. 3) run on the FP32
+                             matrix cores with FP32 accumulation and storage; the sweep
+                             (Alg. 4: the frame X^{(k)} W^{(k)} with W^{(k)} widened to
+                             FP64, its QR, the projection Q^T X, the core update) and the
+                             truncation run in FP64, so every frame spans a subspace of
+                             range(X^{(k)}) to FP64 accuracy (HaTT-1 only) */
 } hatt_opts;
 
 /*
@@ -194,6 +196,7 @@ typedef struct {
   double ep;              /* HaTT-2 threshold */
   const int64_t *ell_init;/* optional host [d+1]: start widths instead of max(r_k, s_k) + p
                              (e.g. hatt_rankpred_widths); clamped like any request */
+  int32_t precision;      /* as in hatt_opts: 0 FP64, 1 FP32 range finding */
 } hatt_adapt_opts;
 
 HATT_API hatt_status hatt_adaptive_plan(const hatt_tt *x, const hatt_tt *y, const hatt_adapt_opts *opts,

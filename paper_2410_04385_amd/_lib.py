@@ -63,6 +63,7 @@ class HattAdaptOpts(ctypes.Structure):
         ("variant", ctypes.c_int32),
         ("ep", ctypes.c_double),
         ("ell_init", i64p),
+        ("precision", ctypes.c_int32),
     ]
 
 

@@ -259,11 +259,12 @@ def recompress_batched(pairs, ell: int = 0, *, max_rank: int = 0, tol: float = 0
 
 def recompress_adaptive(x: TT, y: TT, tol: float, *, seed: int = 0, oversample: int = 8,
                         max_attempts: int = 8, variant: int = 1, ep: float = 0.0,
-                        ell_init: Optional[Sequence[int]] = None,
+                        ell_init: Optional[Sequence[int]] = None, precision: str = "f64",
                         workspace: Optional[torch.Tensor] = None, stream=None):
     """Tolerance-driven HaTT: grows the sketch widths until the truncation
     at ``tol`` leaves slack on every bond, starting from ``ell_init`` (d+1
     widths, e.g. predicted ones) or from max(r_k, s_k) + oversample.
+    ``precision`` "f32": HPCRL sketches on the FP32 matrix cores.
     Returns (Result, widths used, attempts)."""
     xv, kx = x.view()
     yv, ky = y.view()
@@ -272,8 +273,10 @@ def recompress_adaptive(x: TT, y: TT, tol: float, *, seed: int = 0, oversample: 
         if len(ell_init) != x.d + 1:
             raise ValueError("ell_init needs d+1 entries")
         init = i64_array(ell_init)
+    if precision not in ("f64", "f32"):
+        raise ValueError(f"unknown precision {precision!r}")
     o = HattAdaptOpts(float(tol), int(seed) & 0xFFFFFFFFFFFFFFFF, int(oversample), int(max_attempts),
-                      int(variant), float(ep), init)
+                      int(variant), float(ep), init, 1 if precision == "f32" else 0)
     cap = (ctypes.c_int64 * (x.d + 1))()
     ws = ctypes.c_size_t(0)
     oe = ctypes.c_int64(0)
@@ -554,7 +557,7 @@ def adaptive_caps(x: TT, y: TT) -> List[int]:
     widths (the clamp of r_k s_k) limited to the 1024-column truncation."""
     xv, kx = x.view()
     yv, ky = y.view()
-    o = HattAdaptOpts(1.0, 0, 8, 1, 1, 0.0, None)
+    o = HattAdaptOpts(1.0, 0, 8, 1, 1, 0.0, None, 0)
     cap = (ctypes.c_int64 * (x.d + 1))()
     ws = ctypes.c_size_t(0)
     oe = ctypes.c_int64(0)

@@ -117,6 +117,9 @@ const char *sandwich_kernel_name(const SandwichArgs &a);
 // dst[p * dbs + k] = (float) src[p * sbs + k] for k < count, p < batch.
 hipError_t launch_cast_f32(const double *src, int64_t sbs, float *dst, int64_t dbs, int64_t count, int batch,
                            hipStream_t s);
+// dst = (double)src, count elements per pair (pair strides sbs, dbs).
+hipError_t launch_cast_f64(const float *src, int64_t sbs, double *dst, int64_t dbs, int64_t count, int batch,
+                           hipStream_t s);
 // Per pair, scale w[p * bs .. + count) by the power of two that puts its
 // largest magnitude in [1, 2).
 hipError_t launch_rescale_pow2(float *w, int64_t count, int64_t bs, int batch, hipStream_t s);

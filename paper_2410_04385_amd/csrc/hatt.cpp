@@ -1109,6 +1109,11 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
   auto as_d = [](float *p) { return reinterpret_cast<double *>(static_cast<void *>(p)); };
   const int64_t lastsz = (d >= 2) ? std::max<int64_t>(r[d - 1] * s[d - 1] * l[d - 1], 1) : 1;
   double *Wlast = (f32 && d >= 2) ? ws.d((int64_t)P * lastsz) : nullptr;
+  // FP32 range finding: each W^{(k)} is widened to FP64 for the sketched
+  // frame X^{(k)} W^{(k)}, which then lies in range(X^{(k)}) to FP64 accuracy
+  int64_t wdsz = 1;
+  for (int b = 1; b < d; ++b) wdsz = std::max(wdsz, r[b] * s[b] * l[b]);
+  double *Wd = f32 ? ws.d((int64_t)P * wdsz) : nullptr;
   double *Xc = ws.d((int64_t)P * xsz);
   double *Yb = ws.d((int64_t)P * ysz);
   double *Mb = ws.d((int64_t)P * msz);
@@ -1269,12 +1274,11 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     const int64_t m = l[c] * n[c], rs1 = r[c + 1] * s[c + 1];
     hatt_status stt;
     if (f32) {
-      // sketched frame on the FP32 matrix cores (X converted on load), stored as FP64 for the QR
-      GemmTypes ty;
-      ty.prec = 1;
-      ty.b32 = 1;
-      stt = gemm(run, gc, CMat{Xc, rs1, 1, xsz}, CMat{as_d(Wf + woff[c + 1]), l[c + 1], 1, wtot},
-                 Mat{Yb, l[c + 1], 1, ysz}, m, l[c + 1], rs1, 1.0, 0.0, P, st, false, nullptr, 0, nullptr, ty);
+      // the sketch found in FP32 is just another sketch: the frame product
+      // itself runs in FP64, so the frame's range stays inside range(X^{(k)})
+      LAUNCH(launch_cast_f64(Wf + woff[c + 1], wtot, Wd, wdsz, rs1 * l[c + 1], P, st));
+      stt = gemm(run, gc, CMat{Xc, rs1, 1, xsz}, CMat{Wd, l[c + 1], 1, wdsz}, Mat{Yb, l[c + 1], 1, ysz}, m,
+                 l[c + 1], rs1, 1.0, 0.0, P, st, true);
     } else {
       stt = gemm(run, gc, CMat{Xc, rs1, 1, xsz}, CMat{W + woff[c + 1], l[c + 1], 1, wtot},
                  Mat{Yb, l[c + 1], 1, ysz}, m, l[c + 1], rs1, 1.0, 0.0, P, st, true);
@@ -1978,6 +1982,7 @@ static hatt_status adapt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_
   o.ell = 1;
   o.tol = ao->tol;
   o.seed = ao->seed;
+  o.precision = ao->precision;
   hatt_status st = hatt_prepare(x, y, &o, sp, need_data);
   if (st != HATT_OK) return st;
   const int d = sp->X.d;

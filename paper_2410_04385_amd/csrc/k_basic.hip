@@ -491,6 +491,24 @@ hipError_t launch_cast_f32(const double *src, int64_t sbs, float *dst, int64_t d
   return hipGetLastError();
 }
 
+__global__ void cast_f64_kernel(const float *src, int64_t sbs, double *dst, int64_t dbs, int64_t count, int batch) {
+  const int64_t total = count * batch;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / count, k = e - p * count;
+    dst[p * dbs + k] = (double)src[p * sbs + k];
+  }
+}
+
+hipError_t launch_cast_f64(const float *src, int64_t sbs, double *dst, int64_t dbs, int64_t count, int batch,
+                           hipStream_t s) {
+  const int64_t total = count * batch;
+  if (total <= 0) return hipSuccess;
+  int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  cast_f64_kernel<<<grid, 256, 0, s>>>(src, sbs, dst, dbs, count, batch);
+  return hipGetLastError();
+}
+
 // Per pair, multiply w[p * bs .. + count) by the power of two that brings its
 // largest magnitude into [1, 2) (exact: only the exponents change).  One
 // block per pair.

@@ -460,7 +460,8 @@ def test_batched_uneven_pairs_match_oracle():
 def test_batched_workload_sample():
     """The 512-pair uneven workload's distribution (d in 8..32, n in
     {16, 32, 64}, ranks 8..48, spectral cores), first 24 pairs at full size,
-    tol 1e-6: the three cheapest pairs match the oracle; every pair's kept
+    tol 1e-6: the three cheapest pairs and the three of largest r_x r_y
+    (panelled frames, the largest SVDs) match the oracle; every pair's kept
     ranks respect the planned capacities."""
     shapes = wk.batched_pair_shapes(3, 24)
     pairs, cores = [], []
@@ -472,7 +473,8 @@ def test_batched_workload_sample():
     res = H.recompress_batched(pairs, 0, tol=1e-6, seed=900)
     torch.cuda.synchronize()
     cost = [d * n * rx * ry for (d, n, rx, ry) in shapes]
-    for p in np.argsort(cost)[:3]:
+    wide = [rx * ry for (_, _, rx, ry) in shapes]
+    for p in sorted(set(np.argsort(cost)[:3].tolist() + np.argsort(wide)[-3:].tolist())):
         y, z = cores[p]
         ell = _rule_ell(y, z)
         ref = rounding.tt_round(ohatt.hatt(y, z, philox.sketch(900 + int(p), tt.modes(y), ell)), tol=1e-6)
@@ -542,6 +544,73 @@ def test_fp32_range_finding_full_order():
     e32, e64 = tt.rel_err(a.train(0), zz), tt.rel_err(b.train(0), zz)
     _say(f"  error vs z: f32 {e32:.6f}, f64 {e64:.6f}")
     assert abs(e32 - e64) <= 1e-3 * e64
+
+
+def test_fp32_range_finding_matches_oracle_spectral_order_20():
+    """FP32 range finding (HPCRL on the FP32 matrix cores, the sweep in
+    FP64) against the oracle's FP64 HaTT with the same Philox sketch, element
+    by element through the difference TT, on the spectral workload's shape
+    (d = 20, width 40), untruncated and truncated to rank 30.  The FP32
+    sketches differ from the FP64 ones by ~1e-6 relative; the frames found
+    with them differ by that times the sketched frame's conditioning, so the
+    bound is 1e-3 (the rank-30 truncation itself is ~0.5 away from z)."""
+    cfg = wk.WORKLOADS["spectral"]
+    y, z = wk.spectral_pair(1001, cfg["d"], cfg["n"], cfg["r"], cfg["r"])
+    X, Z = H.TT.from_cores([y]), H.TT.from_cores([z])
+    l = _ell(y, z, cfg["ell"])
+    raw = ohatt.hatt(y, z, philox.sketch(5, tt.modes(y), l))
+    ref = rounding.tt_round(raw, max_rank=cfg["max_rank"])
+    _say("hatt_recompress f32 vs oracle spectral d=20")
+    a = H.recompress(X, Z, cfg["ell"], seed=5, precision="f32")
+    b = H.recompress(X, Z, cfg["ell"], max_rank=cfg["max_rank"], seed=5, precision="f32")
+    torch.cuda.synchronize()
+    e_raw, e_tr = tt.rel_err(a.train(0), raw), tt.rel_err(b.train(0), ref)
+    _say(f"  f32 vs oracle: untruncated {e_raw:.2e}, rank 30 {e_tr:.2e}")
+    assert tt.ranks(b.train(0)) == tt.ranks(ref)
+    assert e_raw <= 1e-3 and e_tr <= 1e-3
+
+
+def test_fp32_range_finding_accuracy_on_trig_u2():
+    """u (.) u on the 256^3 trig grid at width 96, tol 1e-8, FP32 range
+    finding: u (.) u has exact rank 81 < 96 and the FP64 path reaches it to
+    ~1e-13.  With FP32 sketches W^{(k)} the frame X^{(k)} W^{(k)} (formed in
+    FP64) picks up X^{(k)} times the sketch's rounding noise, and X^{(k)}
+    has directions outside the product's column space, so the captured
+    range is off by a few FP32 roundings: same ranks as the oracle, and
+    within 1e-6 of both the oracle's FP64 result (same Philox sketch) and
+    the closed form (measured ~4e-8): an FP32-class result, not the 1e-8
+    configuration."""
+    cfg = wk.WORKLOADS["trig"]
+    u = wk.trig_u(11, n=cfg["n"], terms=2 * cfg["nfreq"], nfreq=cfg["nfreq"])
+    U = H.TT.from_cores(u)
+    l = _ell(u, u, cfg["ell2"])
+    ref = rounding.tt_round(ohatt.hatt(u, u, philox.sketch(1, tt.modes(u), l)), tol=cfg["tol"])
+    _say("hatt_recompress f32 trig 256^3 u*u width 96 tol 1e-8")
+    got = H.recompress(U, U, cfg["ell2"], tol=cfg["tol"], seed=1, precision="f32")
+    torch.cuda.synchronize()
+    g = got.train(0)
+    assert tt.ranks(g) == tt.ranks(ref) == [1, 81, 81, 1]
+    e_or = tt.rel_err(g, ref)
+    fu = tt.full(u)
+    e_cf = np.linalg.norm(tt.full(g) - fu ** 2) / np.linalg.norm(fu ** 2)
+    _say(f"  f32 vs oracle {e_or:.2e}, vs closed form {e_cf:.2e}")
+    assert e_or <= 1e-6 and e_cf <= 1e-6
+
+
+def test_fp32_adaptive_matches_oracle_small_trig():
+    """Tolerance mode with FP32 range finding on a small trig product: the
+    same widths, attempts and ranks as the oracle's FP64 tolerance mode, and
+    the same tensor to FP32 range-finding accuracy (1e-6)."""
+    from oracle import adapt
+    u = wk.trig_u(3, n=24, terms=8, nfreq=4)
+    U = H.TT.from_cores(u)
+    _say("hatt_recompress_adaptive f32 small trig tol 1e-8")
+    res, ell, att = H.recompress_adaptive(U, U, 1e-8, seed=6, precision="f32")
+    torch.cuda.synchronize()
+    outs, l_ref, att_ref, ok = adapt.hatt_adaptive([(u, u)], tol=1e-8, seed=6)
+    assert ok and ell == l_ref and att == att_ref
+    assert tt.ranks(res.train(0)) == tt.ranks(outs[0])
+    assert tt.rel_err(res.train(0), outs[0]) <= 1e-6
 
 
 @pytest.mark.parametrize("ell", [40, 56])
