@@ -51,7 +51,7 @@ typedef enum {
   HATT_EWORKSPACE = -3,  /* workspace smaller than the plan call reported */
   HATT_EDEVICE = -4,     /* a HIP call or kernel launch failed */
   HATT_ENOTCONV = -5,    /* the tolerance-driven width growth did not converge (hatt_recompress_adaptive) */
-  HATT_ENONFINITE = -6,  /* reserved: non-finite input detected */
+  HATT_ENONFINITE = -6,  /* non-finite input (hatt_recompress_adaptive, hatt_rankpred_widths) */
   HATT_EUNSUPPORTED = -7 /* a shape the library does not handle (see message) */
 } hatt_status;
 
@@ -80,6 +80,8 @@ typedef struct {
                              FP64, its QR, the projection Q^T X, the core update) and the
                              truncation run in FP64, so every frame spans a subspace of
                              range(X^{(k)}) to FP64 accuracy (HaTT-1 only) */
+  const int64_t *max_rank_bond; /* optional host [d+1]: entry k caps the kept rank of bond k
+                             (entries <= 0: max_rank applies there); not for the uneven batch */
 } hatt_opts;
 
 /*
@@ -179,8 +181,10 @@ HATT_API hatt_status hatt_recompress_batched(int32_t npairs, const hatt_tt *x, c
  * reach (the feasible widths, clamped to 1024), ws_bytes = workspace for any
  * attempt, out_elems = elements of one output train at those widths (the
  * per-train slot size).
- * hatt_recompress_adaptive: synchronises `stream` once per attempt (the
- * decision needs the kept ranks on the host).  The result of the last
+ * hatt_recompress_adaptive: first checks that x and y hold only finite
+ * values (HATT_ENONFINITE otherwise, nothing written but out_rank), then
+ * synchronises `stream` once per attempt (the decision needs the kept ranks
+ * on the host).  The result of the last
  * attempt is written per train at the widths returned in ell_out (host
  * [d+1]; packed inside each train's slot of out_stride elements, 0 = the
  * planned slot size), kept ranks in out_rank (device [batch][d+1]), the
@@ -259,6 +263,15 @@ HATT_API hatt_status tt_round(const hatt_tt *a, int64_t max_rank, double tol, do
  */
 HATT_API hatt_status tt_norm_plan(const hatt_tt *a, size_t *ws_bytes);
 HATT_API hatt_status tt_norm(const hatt_tt *a, double *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * tt_check_finite -- flag[b] (device int32 [batch]) = 1 when every entry of
+ * train b's cores is finite, else 0; enqueue only.  The other enqueue-only
+ * entry points do not inspect their inputs: a non-finite input yields
+ * non-finite output and meaningless kept ranks, so a caller that cannot
+ * trust its data runs this first (the tolerance mode does).
+ */
+HATT_API hatt_status tt_check_finite(const hatt_tt *a, int32_t *flag, void *stream);
 
 /*
  * tt_scale -- multiply (invert = 0) or divide (invert = 1) train b of `a` by
@@ -374,6 +387,13 @@ HATT_API hatt_status hatt_rankpred_train_step(float *theta, float *adam_m, float
                                              const hatt_adam_opts *opts, const float *stats, const float *feat,
                                              const float *label, const int32_t *idx, int64_t batch, float *loss,
                                              void *ws, size_t ws_bytes, void *stream);
+/* Host only: training targets of one accepted tolerance-mode
+ * recompression of order d: for bond k = 1..d-1, row k-1 of out (host float
+ * [d-1][2]) is (ln rho_k, ln min(cap_k, rho_k + p)), from the kept ranks
+ * (host [d+1], each >= 1) and the widths the growth may reach (host [d+1],
+ * e.g. cap_out of hatt_adaptive_plan); p = oversample (<= 0 means 8). */
+HATT_API hatt_status hatt_rankpred_labels(int32_t d, const int64_t *kept, const int64_t *cap, int32_t oversample,
+                                         float *out);
 /* Host only: widths and predicted kept ranks from predictions (host float
  * [rows][2], e.g. copied back from hatt_rankpred_forward).  Per bond
  * l_k = ceil((1 + margin) max(e^{pred_1}, e^{pred_0} + p)) and

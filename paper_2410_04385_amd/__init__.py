@@ -36,7 +36,9 @@ from .api import (  # noqa: F401
     round,
     round_plan,
     scale,
+    check_finite,
     set_qr_method,
     sketch_fill,
     version,
 )
+from ._lib import HattError  # noqa: F401,E402

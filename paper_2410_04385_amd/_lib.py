@@ -17,12 +17,12 @@ STATUS_NAMES = {
 }
 
 EXPORTED = [
-    "hatt_plan", "hatt_recompress", "hatt_recompress_noalloc", "hatt_adaptive_plan", "hatt_recompress_adaptive", "tt_hadamard_explicit", "tt_scale", "tt_randorth_plan", "tt_randorth", "tt_round_plan", "tt_round",
+    "hatt_plan", "hatt_recompress", "hatt_recompress_noalloc", "hatt_adaptive_plan", "hatt_recompress_adaptive", "tt_hadamard_explicit", "tt_scale", "tt_check_finite", "tt_randorth_plan", "tt_randorth", "tt_round_plan", "tt_round",
     "tt_norm_plan", "tt_norm", "hatt_sketch_fill", "hatt_profile_start", "hatt_profile_stop",
     "hatt_profile_class_name", "hatt_last_error", "hatt_version", "hatt_set_qr_method",
     "hatt_profile_report", "hatt_batched_plan", "hatt_recompress_batched",
     "hatt_rankpred_features", "hatt_rankpred_fit_stats", "hatt_rankpred_forward", "hatt_rankpred_ws_bytes",
-    "hatt_rankpred_grad", "hatt_rankpred_train_step", "hatt_rankpred_widths",
+    "hatt_rankpred_grad", "hatt_rankpred_train_step", "hatt_rankpred_widths", "hatt_rankpred_labels",
 ]
 RANKPRED_NIN, RANKPRED_NTHETA, RANKPRED_NSTATS = 21, 19586, 46
 PROFILE_CLASSES = 8
@@ -51,6 +51,7 @@ class HattOpts(ctypes.Structure):
         ("tol", ctypes.c_double),
         ("seed", ctypes.c_uint64),
         ("precision", ctypes.c_int32),
+        ("max_rank_bond", i64p),
     ]
 
 
@@ -104,6 +105,8 @@ def lib() -> ctypes.CDLL:
     L.tt_randorth.argtypes = [ttp, ttp, ctypes.c_int64, i64p, ctypes.c_uint64, ctypes.c_int64, ctypes.c_double, vp,
                               ctypes.c_int64, vp, vp, ctypes.c_size_t, vp]
     L.tt_scale.argtypes = [ttp, vp, ctypes.c_int32, vp]
+    L.hatt_rankpred_labels.argtypes = [ctypes.c_int32, i64p, i64p, ctypes.c_int32, vp]
+    L.tt_check_finite.argtypes = [ttp, vp, vp]
     L.tt_round_plan.argtypes = [ttp, i64p, szp, i64p]
     L.tt_round.argtypes = [ttp, ctypes.c_int64, ctypes.c_double, vp, ctypes.c_int64, vp, vp, ctypes.c_size_t, vp]
     L.tt_norm_plan.argtypes = [ttp, szp]

@@ -121,9 +121,18 @@ def _opts(ell, max_rank, tol, seed, variant, ep, d, precision="f64"):
         ell_u = int(ell)
     if precision not in _PRECISION:
         raise ValueError(f"precision must be one of {sorted(_PRECISION)}")
-    o = HattOpts(int(variant), float(ep), ell_u, ell_arr if ell_arr is not None else None,
-                 int(max_rank), float(tol), int(seed) & 0xFFFFFFFFFFFFFFFF, _PRECISION[precision])
-    return o, ell_arr
+    mr_arr = None
+    if np.isscalar(max_rank):
+        mr_u = int(max_rank)
+    else:
+        # per-bond caps: entry k caps bond k (<= 0: no cap there)
+        if len(max_rank) != d + 1:
+            raise ValueError("per-bond max_rank needs d+1 entries")
+        mr_arr = i64_array(max_rank)
+        mr_u = 0
+    o = HattOpts(int(variant), float(ep), ell_u, ell_arr, mr_u, float(tol), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                 _PRECISION[precision], mr_arr)
+    return o, (ell_arr, mr_arr)
 
 
 def plan(x: TT, y: TT, ell, max_rank: int = 0, tol: float = 0.0, seed: int = 0, variant: int = 1,
@@ -338,6 +347,15 @@ def randorth(a: TT, ell, *, max_rank: int = 0, tol: float = 0.0, seed: int = 0, 
                                            ctypes.c_void_p(ranks.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
                                            workspace.numel(), _stream_ptr(stream)))
     return Result(out, ranks)
+
+
+def check_finite(a: TT, stream=None) -> torch.Tensor:
+    """Device int32 [batch]: 1 where every entry of the train is finite."""
+    flag = torch.empty(a.batch, dtype=torch.int32, device=a.data.device)
+    av, ka = a.view()
+    check("tt_check_finite", lib().tt_check_finite(ctypes.byref(av), ctypes.c_void_p(flag.data_ptr()),
+                                                   _stream_ptr(stream)))
+    return flag
 
 
 def scale(a: TT, alpha: torch.Tensor, invert: bool = False, stream=None) -> TT:
@@ -570,8 +588,10 @@ def rankpred_labels(kept: Sequence[int], cap: Sequence[int], oversample: int = 8
     """Targets of the width predictor for one accepted recompression: per
     bond (ln rho_k, ln min(cap_k, rho_k + p))."""
     d = len(kept) - 1
-    return np.array([[np.log(kept[k]), np.log(min(int(cap[k]), int(kept[k]) + oversample))] for k in range(1, d)],
-                    dtype=np.float32).reshape(d - 1, 2)
+    out = np.zeros((max(d - 1, 0), 2), dtype=np.float32)
+    check("hatt_rankpred_labels", lib().hatt_rankpred_labels(d, i64_array(kept), i64_array(cap), int(oversample),
+                                                             out.ctypes.data_as(ctypes.c_void_p)))
+    return out
 
 
 def kept_cores(res: Result, b: int = 0) -> List[torch.Tensor]:

@@ -117,6 +117,10 @@ const char *sandwich_kernel_name(const SandwichArgs &a);
 // dst[p * dbs + k] = (float) src[p * sbs + k] for k < count, p < batch.
 hipError_t launch_cast_f32(const double *src, int64_t sbs, float *dst, int64_t dbs, int64_t count, int batch,
                            hipStream_t s);
+// flag[p] (int, device) = 1 when the first `count` doubles of train p
+// (pair stride `stride`) are all finite, else 0.
+hipError_t launch_finite_check(const double *data, int64_t count, int64_t stride, int batch, int *flag,
+                               hipStream_t s);
 // dst = (double)src, count elements per pair (pair strides sbs, dbs).
 hipError_t launch_cast_f64(const float *src, int64_t sbs, double *dst, int64_t dbs, int64_t count, int batch,
                            hipStream_t s);

@@ -772,6 +772,7 @@ struct RoundSpec {
   int64_t ostride;
   int64_t *orank;
   int64_t max_rank;
+  std::vector<int64_t> bond_cap;  // optional [d+1]: per-bond cap (replaces max_rank)
   double tol;
   int batch;
   bool norm_only;     // stop after the right-to-left sweep and write ||B_1||
@@ -948,7 +949,7 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
     sa.delta2 = dl2;
     sa.first_bond = (c == 0);
     sa.tol2_over_dm1 = tol2;
-    sa.cap = sp.max_rank;
+    sa.cap = sp.bond_cap.empty() ? sp.max_rank : sp.bond_cap[c + 1];
     sa.prev_rank = (c == 0) ? nullptr : sp.orank + c;
     sa.n_mode = n[c];
     sa.rank_out = sp.orank + c + 1;
@@ -1039,6 +1040,7 @@ hatt_status round_run(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &, hipStrea
 struct HattSpec {
   Shape X, Y;
   std::vector<int64_t> ell;
+  std::vector<int64_t> bond_cap;  // [d+1] truncation cap per bond (0: none)
   const double *sketch;  // explicit sketch data or nullptr
   int64_t sketch_stride;
   hatt_opts o;
@@ -1342,12 +1344,15 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
   if ((int)l.size() > kMaxRankPattern) return fail(HATT_EUNSUPPORTED, "order too large for the library (rank pattern buffer)");
   LAUNCH(launch_rank_pattern(sp.orank, P, d + 1, l.data(), st));
   // ---- truncation (Alg. 1 on the rank-l result)
-  const bool trunc = (sp.o.max_rank > 0) || (sp.o.tol > 0.0);
+  bool capped = false;
+  for (int64_t c : sp.bond_cap) capped = capped || c > 0;
+  const bool trunc = capped || (sp.o.tol > 0.0);
   if (trunc) {
     RoundSpec rs{};
     rs.n = n;
     rs.rin = l;
     rs.cap = l;
+    rs.bond_cap = sp.bond_cap;
     rs.src = sp.out;
     rs.sstride = sp.ostride;
     rs.in_place = true;
@@ -1681,6 +1686,11 @@ static hatt_status hatt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_o
   }
   sp->ell = clamp_ell(sp->X.n, sp->X.r, sp->Y.r, req);
   sp->o = *o;
+  sp->o.max_rank_bond = nullptr;  // read here only; the caller's array need not outlive the call
+  sp->bond_cap.assign(d + 1, std::max<int64_t>(o->max_rank, 0));
+  if (o->max_rank_bond != nullptr)
+    for (int k = 1; k < d; ++k)
+      if (o->max_rank_bond[k] > 0) sp->bond_cap[k] = o->max_rank_bond[k];
   return HATT_OK;
 }
 
@@ -1858,6 +1868,7 @@ static hatt_status batch_prepare(int32_t npairs, const hatt_tt *x, const hatt_tt
   if (npairs < 1) return fail(HATT_EINVAL, "npairs must be >= 1");
   if (x == nullptr || y == nullptr || o == nullptr) return fail(HATT_EINVAL, "NULL argument");
   if (o->ell_bond != nullptr) return fail(HATT_EINVAL, "per-bond widths are not taken by the uneven batch");
+  if (o->max_rank_bond != nullptr) return fail(HATT_EINVAL, "per-bond rank caps are not taken by the uneven batch");
   bp->sp.assign(npairs, HattSpec{});
   bp->req.assign(npairs, {});
   bp->out_off.assign(npairs + 1, 0);
@@ -2047,6 +2058,23 @@ hatt_status hatt_recompress_adaptive(const hatt_tt *x, const hatt_tt *y, const h
   sp.sketch = nullptr;
   hipStream_t strm = (hipStream_t)stream;
   std::vector<int64_t> host_rank((size_t)P * (d + 1));
+  {
+    // non-finite inputs: the rank decisions below would be meaningless.
+    // The flags of x and y borrow out_rank (>= 2 P ints) until the first attempt.
+    int *fl = reinterpret_cast<int *>(out_rank);
+    const bool run = true;
+    hipStream_t st = strm;
+    LAUNCH(launch_finite_check(sp.X.data, sp.X.total, sp.X.stride, P, fl, st));
+    LAUNCH(launch_finite_check(sp.Y.data, sp.Y.total, sp.Y.stride, P, fl + P, st));
+    std::vector<int> hf(2 * (size_t)P);
+    if (hipMemcpyAsync(hf.data(), fl, hf.size() * sizeof(int), hipMemcpyDeviceToHost, strm) != hipSuccess ||
+        hipStreamSynchronize(strm) != hipSuccess)
+      return fail(HATT_EDEVICE, "reading the finiteness flags failed");
+    for (int q = 0; q < 2 * P; ++q)
+      if (hf[q] != 1)
+        return fail(HATT_ENONFINITE, std::string(q < P ? "x" : "y") + " train " + std::to_string(q % P) +
+                                         " has a non-finite entry");
+  }
   for (int attempt = 0; attempt < maxa; ++attempt) {
     sp.ell = clamp_ell(sp.X.n, sp.X.r, sp.Y.r, ell);
     sp.o.seed = opts->seed + (uint64_t)attempt;
@@ -2227,6 +2255,18 @@ hatt_status tt_scale(const hatt_tt *a, const double *alpha, int32_t invert, void
   return HATT_OK;
 }
 
+hatt_status tt_check_finite(const hatt_tt *a, int32_t *flag, void *stream) {
+  Shape A;
+  hatt_status rc = read_tt(a, "a", &A, true);
+  if (rc != HATT_OK) return rc;
+  if (flag == nullptr) return fail(HATT_EINVAL, "flag is NULL");
+  const bool run = true;
+  hipStream_t st = (hipStream_t)stream;
+  LAUNCH(launch_finite_check(A.data, A.total, A.stride, A.batch, flag, st));
+  g_err.clear();
+  return HATT_OK;
+}
+
 hatt_status hatt_sketch_fill(uint64_t seed, int32_t d, const int64_t *n, const int64_t *ell, double *out,
                              void *stream) {
   if (d < 1 || n == nullptr || ell == nullptr || out == nullptr)
@@ -2390,6 +2430,20 @@ hatt_status hatt_rankpred_train_step(float *theta, float *adam_m, float *adam_v,
   return rp_grad_common(theta, stats, feat, label, idx, batch, nullptr, loss, ad, ws, ws_bytes, stream);
 }
 
+hatt_status hatt_rankpred_labels(int32_t d, const int64_t *kept, const int64_t *cap, int32_t oversample,
+                                 float *out) {
+  if (d < 1 || kept == nullptr || cap == nullptr || (out == nullptr && d > 1))
+    return fail(HATT_EINVAL, "rankpred_labels: bad arguments");
+  const int64_t p = oversample > 0 ? oversample : 8;
+  for (int k = 1; k < d; ++k) {
+    if (kept[k] < 1 || cap[k] < 1) return fail(HATT_EINVAL, "rankpred_labels: ranks and caps must be >= 1");
+    out[2 * (k - 1)] = (float)std::log((double)kept[k]);
+    out[2 * (k - 1) + 1] = (float)std::log((double)std::min(cap[k], kept[k] + p));
+  }
+  g_err.clear();
+  return HATT_OK;
+}
+
 hatt_status hatt_rankpred_widths(int32_t npairs, const hatt_tt *x, const hatt_tt *y, const float *pred,
                                  double margin, int32_t oversample, int64_t *ell_out, int64_t *rho_out) {
   std::vector<Shape> X, Y;
@@ -2407,7 +2461,7 @@ hatt_status hatt_rankpred_widths(int32_t npairs, const hatt_tt *x, const hatt_tt
     for (int k = 1; k < d; ++k, ++row) {
       const double la = (double)pred[2 * row], lb = (double)pred[2 * row + 1];
       if (!std::isfinite(la) || !std::isfinite(lb))
-        return fail(HATT_EINVAL, "non-finite prediction in row " + std::to_string(row));
+        return fail(HATT_ENONFINITE, "non-finite prediction in row " + std::to_string(row));
       const double w = std::max(std::exp(lb), std::exp(la) + (double)p);
       const double lw = std::ceil((1.0 + margin) * w), lr = std::ceil(std::exp(la));
       req[k] = (int64_t)std::max(1.0, std::min(lw, 9.0e15));

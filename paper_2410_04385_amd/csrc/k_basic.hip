@@ -491,6 +491,34 @@ hipError_t launch_cast_f32(const double *src, int64_t sbs, float *dst, int64_t d
   return hipGetLastError();
 }
 
+// flag[p] = 1, then 0 for every train p with a non-finite entry among its
+// first `count` doubles (pair stride `stride`).  Every block scans a slice
+// of one train and only ever stores 0, so the blocks need no ordering.
+__global__ void finite_init_kernel(int *flag, int batch) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < batch) flag[p] = 1;
+}
+
+__global__ void finite_check_kernel(const double *data, int64_t count, int64_t stride, int *flag) {
+  const int p = blockIdx.y;
+  const double *a = data + p * stride;
+  int bad = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(a[e]);
+  if (__syncthreads_or(bad) && threadIdx.x == 0) flag[p] = 0;
+}
+
+hipError_t launch_finite_check(const double *data, int64_t count, int64_t stride, int batch, int *flag,
+                               hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  finite_init_kernel<<<(batch + 255) / 256, 256, 0, s>>>(flag, batch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || count <= 0) return e;
+  const int64_t blocks = std::min<int64_t>((count + 4095) / 4096, 1024);
+  finite_check_kernel<<<dim3((unsigned)blocks, (unsigned)batch), 256, 0, s>>>(data, count, stride, flag);
+  return hipGetLastError();
+}
+
 __global__ void cast_f64_kernel(const float *src, int64_t sbs, double *dst, int64_t dbs, int64_t count, int batch) {
   const int64_t total = count * batch;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;

@@ -273,8 +273,13 @@ def test_rankpred_host_errors_and_workspace():
     assert e.value.status == -1
     bad = pred.copy()
     bad[0, 0] = np.nan
-    with pytest.raises(HattError):
+    with pytest.raises(HattError) as e:
         api.rankpred_widths(pairs, bad)
+    assert e.value.status == -6
+    bad[0, 0] = np.inf
+    with pytest.raises(HattError) as e:
+        api.rankpred_widths(pairs, bad)
+    assert e.value.status == -6
     with pytest.raises(ValueError):
         api.rankpred_widths(pairs, pred[:-1])
     x = _cpu_tt([2, 4, 2], [1, 2, 2, 1])
@@ -360,3 +365,42 @@ def test_randorth_plan_matches_oracle_clamps():
         assert st == 0
         assert list(eo) == oplan.clamp_ell(n, ra, [1] * (d + 1), ell)
         assert ws.value > 0
+
+
+def test_rankpred_labels_match_oracle():
+    """The predictor's targets are computed behind the C ABI: (ln rho_k,
+    ln min(cap_k, rho_k + p)) per interior bond, as the oracle defines them;
+    ranks below 1 are rejected."""
+    from oracle import rankpred as orp
+    rng = np.random.default_rng(4)
+    for d in (2, 5, 17):
+        kept = [1] + rng.integers(1, 300, size=d - 1).tolist() + [1]
+        cap = [1] + [k + int(rng.integers(0, 20)) for k in kept[1:-1]] + [1]
+        for p in (8, 3):
+            got = api.rankpred_labels(kept, cap, oversample=p)
+            assert got.dtype == np.float32 and got.shape == (d - 1, 2)
+            assert np.allclose(got, orp.labels(kept, cap, p).astype(np.float32))
+    with pytest.raises(HattError) as e:
+        api.rankpred_labels([1, 0, 1], [1, 4, 1])
+    assert e.value.status == -1
+
+
+def test_per_bond_rank_caps_are_options():
+    """max_rank may be given per bond (d+1 entries): the plan takes it; the
+    uneven batch, whose pairs differ in order, refuses it."""
+    n = [8] * 5
+    x = _cpu_tt(n, [1, 4, 6, 6, 4, 1])
+    p = api.plan(x, x, 16, max_rank=[0, 3, 0, 9, 2, 0])
+    assert p["ell"] == oplan.clamp_ell(n, [1, 4, 6, 6, 4, 1], [1, 4, 6, 6, 4, 1], [1, 16, 16, 16, 16, 1])
+    with pytest.raises(ValueError):
+        api.plan(x, x, 16, max_rank=[0, 3, 0])
+    xv, kx = x.view()
+    xs = (_lib.HattTT * 1)(xv)
+    caps = _lib.i64_array([0, 3, 0, 9, 2, 0])
+    o = _lib.HattOpts(1, 0.0, 16, None, 0, 0.0, 0, 0, caps)
+    oo = (ctypes.c_int64 * 2)()
+    ro = (ctypes.c_int64 * 2)()
+    eo = (ctypes.c_int64 * 6)()
+    ws = ctypes.c_size_t(0)
+    st = _lib.lib().hatt_batched_plan(1, xs, xs, ctypes.byref(o), oo, ro, eo, ctypes.byref(ws))
+    assert st == -1 and "per-bond rank caps" in _lib.lib().hatt_last_error().decode()

@@ -897,3 +897,41 @@ def test_adaptive_widths_stop_at_svd_limit():
     assert ok and ell3 == l_ref and att3 == att_ref
     assert tt.ranks(r3.train(0)) == tt.ranks(ref[0])
     assert tt.rel_err(r3.train(0), ref[0]) <= TOL
+
+
+def test_per_bond_max_rank_matches_oracle():
+    """Per-bond truncation caps (entries <= 0 leave a bond to tol alone):
+    spectral pair of order 8, width 40, caps on some bonds plus tol 1e-3,
+    against the oracle's TT-Rounding with the same caps."""
+    y, z = wk.spectral_pair(77, 8, 16, 12, 10)
+    X, Z = H.TT.from_cores([y]), H.TT.from_cores([z])
+    caps = [0, 5, 0, 17, 3, 0, 11, 0, 0]
+    l = _ell(y, z, 40)
+    raw = ohatt.hatt(y, z, philox.sketch(21, tt.modes(y), l))
+    ref = rounding.tt_round(raw, max_rank=[c if c > 0 else None for c in caps], tol=1e-3)
+    _say("hatt_recompress per-bond max_rank, spectral d=8")
+    got = H.recompress(X, Z, 40, max_rank=caps, tol=1e-3, seed=21)
+    torch.cuda.synchronize()
+    g = got.train(0)
+    assert tt.ranks(g) == tt.ranks(ref)
+    assert all(tt.ranks(g)[k] <= caps[k] for k in range(1, 8) if caps[k] > 0)
+    assert tt.rel_err(g, ref) <= TOL
+
+
+def test_check_finite_and_adaptive_rejects_non_finite():
+    """tt_check_finite flags exactly the trains with a NaN or an infinity;
+    the tolerance mode refuses such inputs with HATT_ENONFINITE."""
+    u = [wk.trig_u(s, n=16, terms=4, nfreq=2) for s in (1, 2, 3)]
+    bad1 = [c.copy() for c in u[1]]
+    bad1[1][0, 3, 1] = np.nan
+    bad2 = [c.copy() for c in u[2]]
+    bad2[2][2, 0, 0] = np.inf
+    A = H.TT.from_cores([u[0], bad1, bad2])
+    flags = H.check_finite(A)
+    torch.cuda.synchronize()
+    assert flags.cpu().tolist() == [1, 0, 0]
+    B = H.TT.from_cores(bad1)
+    G = H.TT.from_cores(u[0])
+    with pytest.raises(H.HattError) as e:
+        H.recompress_adaptive(G, B, 1e-8, seed=1)
+    assert e.value.status == -6 and "y train 0" in str(e.value)
