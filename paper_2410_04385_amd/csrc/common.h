@@ -106,6 +106,9 @@ struct SwPlan {
   int rem;                    // 1: FP64, b' and a' ranges of 17 to 20 (one full 16-block and a
                               // remainder of at most 4, formed by the 4 x 4 x 4 MFMA)
   int nbuf;                   // YL / ZR slice buffers: 2 (next slice staged during this one) or 1
+  int slice;                  // 1: slice-major kernel (one mode index per block, YL / ZR staged
+                              // once, the sketch columns streamed in chunks of GC)
+  int gpb, gblocks;           // slice-major: sketch columns per block, blocks along g
 };
 bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl);
 hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStream_t s);

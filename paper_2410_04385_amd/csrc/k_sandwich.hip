@@ -25,6 +25,72 @@ __host__ __device__ inline int rup(int x, int m) { return (x + m - 1) / m * m; }
 // unrolled chunks of 16.
 constexpr int kSwMaxKSteps = 32;
 
+// Register slots per thread for the next chunk of sketch columns in the
+// slice-major kernel (its chunk holds at most 256 * kSlicePf C entries).
+constexpr int kSlicePf = 24;
+
+bool g_sandwich_slice = true;
+
+// Slice-major plan (FP64, output not contiguous in g): LDS holds YL and ZR of
+// one slice, a chunk of GC sketch columns C_g (rows (g, a), K = b) and the
+// stage-1 result T; the block walks its gpb sketch columns chunk by chunk.
+static bool sandwich_slice_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
+  if (a.prec != 0 || a.og == 1) return false;
+  const int RI4 = rup(a.RI, 4), SI4 = rup(a.SI, 4);
+  const int SO16 = rup(a.SO, 16), RA16 = rup(a.RA, 16);
+  if (RI4 > 4 * kSwMaxKSteps || SI4 > 4 * kSwMaxKSteps) return false;
+  const int ldc = SI4 + 1, ldz = SO16 + 1, ldy = RI4 + 1;
+  const int64_t fixed = (int64_t)RA16 * ldy + (int64_t)SI4 * ldz;
+  int best = 0, bm1 = 0, bldt = 0;
+  for (int gc = (int)std::min<int64_t>(8, a.G); gc >= 1; --gc) {
+    const int m1 = rup(gc * a.RI, 16), ldt = rup(gc * a.SO, 16) + 1;
+    if ((int64_t)m1 * SI4 > 256LL * kSlicePf) continue;
+    if (fixed + (int64_t)m1 * ldc + (int64_t)RI4 * ldt <= budget) {
+      best = gc;
+      bm1 = m1;
+      bldt = ldt;
+      break;
+    }
+  }
+  if (best == 0) return false;
+  // output and C offsets within a block are 32-bit
+  const int64_t omax = (int64_t)(best - 1) * std::llabs(a.og) + (int64_t)(a.SO - 1) * std::llabs(a.obb) +
+                       (int64_t)(a.RA - 1) * std::llabs(a.oa);
+  const int64_t cmax = (int64_t)(best - 1) * std::llabs(a.cg) + (int64_t)(a.RI - 1) * std::llabs(a.ca) +
+                       (int64_t)(a.SI - 1) * std::llabs(a.cbb);
+  if (omax >= (1LL << 31) || cmax >= (1LL << 31) || bm1 >= (1 << 16) || bldt >= (1 << 16)) return false;
+  pl->slice = 1;
+  pl->ks = 0;
+  pl->rem = 0;
+  pl->nbuf = 1;
+  pl->pf = 0;
+  pl->GC = best;
+  pl->RI4 = RI4;
+  pl->SI4 = SI4;
+  pl->SO16 = SO16;
+  pl->RA16 = RA16;
+  pl->ldc = ldc;
+  pl->ldz = ldz;
+  pl->ldy = ldy;
+  pl->ldt = bldt;
+  pl->M1 = bm1;
+  pl->fd_ri = make_fastdiv(a.RI);
+  pl->fd_so = make_fastdiv(a.SO);
+  pl->fd_gc = make_fastdiv(best);
+  pl->lds_doubles = fixed + (int64_t)bm1 * ldc + (int64_t)RI4 * bldt;
+  // one slice per block; split g only when the slices alone leave the CUs idle
+  const int64_t slices = a.n * (int64_t)a.batch;
+  const int64_t chunks = (a.G + best - 1) / best;
+  int64_t gbl = std::max<int64_t>(1, std::min<int64_t>(chunks, (512 + slices - 1) / slices));
+  const int64_t cpb = (chunks + gbl - 1) / gbl;
+  pl->gpb = (int)(cpb * best);
+  pl->gblocks = (int)((a.G + pl->gpb - 1) / pl->gpb);
+  pl->ipb = 1;
+  pl->iblocks = (int)a.n;
+  pl->chunks = pl->gblocks;
+  return pl->iblocks >= 1 && a.n < (1LL << 31) && pl->gblocks <= 65535;
+}
+
 // Largest K-step count with a register-blocked instantiation, and its fetch
 // slots per thread for the next slice's YL / ZR entries.
 constexpr int kSwKsMax = 8;
@@ -105,6 +171,14 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
     pl->ks = RI4 / 4;
   if (pl->nbuf != 2) pl->ks = 0;
   pl->rem = (pl->ks > 0 && a.prec == 0 && a.og != 1 && a.SO >= 17 && a.SO <= 20 && a.RA >= 17 && a.RA <= 20) ? 1 : 0;
+  pl->slice = 0;
+  // large factor ranks leave room for only one or two sketch columns per
+  // block next to a YL / ZR slice: there the slice-major kernel stages each
+  // slice once and streams the sketch columns instead
+  if (g_sandwich_slice && pl->ks == 0 && (pl->nbuf == 1 || pl->GC <= 2)) {
+    SwPlan sp = *pl;
+    if (sandwich_slice_plan(a, budget, &sp)) *pl = sp;
+  }
   return true;
 }
 
@@ -342,6 +416,166 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
     }
     __syncthreads();  // Ts and the YL / ZR buffer are reused by the next slice
     if (pl.nbuf == 2) buf ^= 1;
+  }
+}
+
+// Slice-major form of sandwich_mfma_kernel (FP64, the (g, b') column order)
+// for large factor ranks: the block owns one mode index i, stages YL_i and
+// ZR_i once, and walks its sketch columns GC at a time.  Each chunk's C
+// entries are fetched into registers while the previous chunk's stage 1
+// runs and parked in LDS once that stage is done, so the loads overlap the
+// matrix-core work.  Stage 1 stacks the chunk's g blocks along M (rows
+// (g, a), K = b), stage 2 places their results side by side along N
+// (columns (g, b'), K = a), as in sandwich_mfma_kernel.
+__global__ __launch_bounds__(256) void sandwich_slice_kernel(SandwichArgs a, SwPlan pl) {
+  extern __shared__ double sm[];
+  const int RA = a.RA, RI = a.RI, SI = a.SI, SO = a.SO;
+  const int GC = pl.GC;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int r16 = lane & 15, q4 = lane >> 4;
+  const int64_t i = blockIdx.x;
+  const int64_t gb0 = (int64_t)blockIdx.y * pl.gpb;
+  const int64_t gb1 = std::min<int64_t>(a.G, gb0 + pl.gpb);
+  const int p = blockIdx.z;
+  if (i >= a.n || gb0 >= gb1) return;
+  double *YLs = sm;                              // RA16 rows (a') x ldy, K = a
+  double *ZRs = YLs + pl.RA16 * pl.ldy;          // SI4 rows (b) x ldz
+  double *Cs = ZRs + pl.SI4 * pl.ldz;            // M1 rows (g, a) x ldc, K = b
+  double *Ts = Cs + pl.M1 * pl.ldc;              // RI4 rows (a) x ldt, columns (g, b')
+  {
+    const double *zr = a.zr + p * a.zrb + i * a.zri, *yl = a.yl + p * a.ylb + i * a.yli;
+    stage_lds<4>(pl.SI4 * pl.SO16, Rad3(tid, 256, pl.SO16, pl.SI4), ZRs,  // digits (b', b)
+                 [&](const Rad3 &d) {
+                   return (d.i1 < SI && d.i0 < SO) ? zr[(int64_t)d.i1 * a.zrr + (int64_t)d.i0 * a.zrc] : 0.0;
+                 },
+                 [&](const Rad3 &d) { return d.i1 * pl.ldz + d.i0; });
+    stage_lds<4>(pl.RA16 * pl.RI4, Rad3(tid, 256, pl.RI4, pl.RA16), YLs,  // digits (a, a')
+                 [&](const Rad3 &d) {
+                   return (d.i1 < RA && d.i0 < RI) ? yl[(int64_t)d.i1 * a.ylr + (int64_t)d.i0 * a.ylc] : 0.0;
+                 },
+                 [&](const Rad3 &d) { return d.i1 * pl.ldy + d.i0; });
+  }
+  // rows a >= RI of T are K padding of stage 2
+  for (int e = tid; e < (pl.RI4 - RI) * pl.ldt; e += 256) Ts[RI * pl.ldt + e] = 0.0;
+
+  // C slots of this thread: slot u is entry tid + 256 u of the chunk's
+  // (row, b) grid, row = g RI + a; stored at Cs[row * ldc + b], read from
+  // C_{g0+g}(a, b) (zero for b >= SI or a row beyond the chunk)
+  const int nce = pl.M1 * pl.SI4;
+  // (a row beyond a short last chunk is one whose LDS index reaches gc RI ldc)
+  int c_lds[kSlicePf], c_off[kSlicePf];
+  unsigned c_ok = 0;
+#pragma unroll
+  for (int u = 0; u < kSlicePf; ++u) {
+    const int e = tid + 256 * u;
+    c_lds[u] = -1;
+    c_off[u] = 0;
+    if (e < nce) {
+      const int row = e / pl.SI4, b = e - row * pl.SI4;
+      c_lds[u] = row * pl.ldc + b;
+      const int g = fdiv(row, pl.fd_ri), aa = row - g * RI;
+      if (b < SI && g < GC) {
+        c_ok |= 1u << u;
+        c_off[u] = (int)(g * a.cg + aa * a.ca + b * a.cbb);
+      }
+    }
+  }
+  const double *cbase = a.c + p * a.cb;
+  double cf[kSlicePf];
+  auto cfetch = [&](int64_t g0, int gc) {
+    const double *cp = cbase + g0 * a.cg;
+    const int lim = gc * RI * pl.ldc;
+#pragma unroll
+    for (int u = 0; u < kSlicePf; ++u) cf[u] = (((c_ok >> u) & 1u) && c_lds[u] < lim) ? cp[c_off[u]] : 0.0;
+  };
+  auto cpark = [&]() {
+#pragma unroll
+    for (int u = 0; u < kSlicePf; ++u)
+      if (c_lds[u] >= 0) Cs[c_lds[u]] = cf[u];
+  };
+  int gcur = (int)std::min<int64_t>(GC, gb1 - gb0);
+  cfetch(gb0, gcur);
+  cpark();
+  __syncthreads();
+
+  const int nt1 = pl.SO16 / 16;
+  double *obase0 = a.o + p * a.ob + i * a.oi;
+  for (int64_t g0 = gb0; g0 < gb1; g0 += GC) {
+    const int gc = gcur;
+    const int64_t gn = g0 + GC;
+    const bool more = gn < gb1;
+    int gnext = 0;
+    if (more) {
+      gnext = (int)std::min<int64_t>(GC, gb1 - gn);
+      cfetch(gn, gnext);  // in flight during stage 1
+    }
+    const int M1 = gc * RI, M1p = rup(M1, 16);
+    const int tiles1 = (M1p / 16) * nt1;
+    // ---- stage 1: T(a; g, b') = sum_b C_g(a, b) ZR(b, b')
+    for (int t = wave; t < tiles1; t += 8) {
+      const int t2 = t + 4;
+      const bool two = t2 < tiles1;
+      const int tm0 = (t / nt1) * 16, tn0 = (t - (t / nt1) * nt1) * 16;
+      const int tm1 = two ? (t2 / nt1) * 16 : tm0, tn1 = two ? (t2 - (t2 / nt1) * nt1) * 16 : tn0;
+      d4_t c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+      if (two)
+        mfma_pair(Cs + (tm0 + r16) * pl.ldc + q4, ZRs + q4 * pl.ldz + tn0 + r16, Cs + (tm1 + r16) * pl.ldc + q4,
+                  ZRs + q4 * pl.ldz + tn1 + r16, 4, 4 * pl.ldz, pl.SI4 / 4, c0, c1);
+      else
+        mfma_one(Cs + (tm0 + r16) * pl.ldc + q4, ZRs + q4 * pl.ldz + tn0 + r16, 4, 4 * pl.ldz, pl.SI4 / 4, c0);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (u == 1 && !two) break;
+        const d4_t &c = u ? c1 : c0;
+        const int tm = u ? tm1 : tm0, bq = (u ? tn1 : tn0) + r16;
+        if (bq < SO) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = tm + mfma_row<double>(q4, v);
+            if (row < M1) {
+              const int g = fdiv(row, pl.fd_ri), aa = row - g * RI;
+              Ts[aa * pl.ldt + g * SO + bq] = c[v];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();  // T complete; C of this chunk no longer read
+    if (more) cpark();
+    // ---- stage 2: out(a'; g, b') = sum_a YL(a', a) T(a; g, b')
+    const int ncols = gc * SO;
+    const int nt2 = rup(ncols, 16) / 16, tiles2 = (pl.RA16 / 16) * nt2;
+    double *obase = obase0 + g0 * a.og;
+    for (int t = wave; t < tiles2; t += 8) {
+      const int t2 = t + 4;
+      const bool two = t2 < tiles2;
+      const int tm0 = (t / nt2) * 16, tn0 = (t - (t / nt2) * nt2) * 16;
+      const int tm1 = two ? (t2 / nt2) * 16 : tm0, tn1 = two ? (t2 - (t2 / nt2) * nt2) * 16 : tn0;
+      d4_t c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+      if (two)
+        mfma_pair(YLs + (tm0 + r16) * pl.ldy + q4, Ts + q4 * pl.ldt + tn0 + r16, YLs + (tm1 + r16) * pl.ldy + q4,
+                  Ts + q4 * pl.ldt + tn1 + r16, 4, 4 * pl.ldt, pl.RI4 / 4, c0, c1);
+      else
+        mfma_one(YLs + (tm0 + r16) * pl.ldy + q4, Ts + q4 * pl.ldt + tn0 + r16, 4, 4 * pl.ldt, pl.RI4 / 4, c0);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (u == 1 && !two) break;
+        const d4_t &c = u ? c1 : c0;
+        const int tm = u ? tm1 : tm0, col = (u ? tn1 : tn0) + r16;
+        const int g = fdiv(col, pl.fd_so), bq = col - g * SO;
+        if (col < ncols) {
+          double *o = obase + g * a.og + bq * a.obb + (int64_t)tm * a.oa;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int rr = mfma_row<double>(q4, v);
+            if (tm + rr < RA) o[(int64_t)rr * a.oa] = c[v];
+          }
+        }
+      }
+    }
+    __syncthreads();  // T and the parked C chunk: next chunk
+    gcur = gnext;
   }
 }
 
@@ -729,6 +963,7 @@ const char *sandwich_mfma_name(const SandwichArgs &a, const SwPlan &pl) {
        {{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr},
         {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr}}}};
   const int lg = a.og == 1 ? 1 : 0, f = a.prec ? 1 : 0;
+  if (pl.slice) return "sandwich_slice_kernel";
   if (g_sandwich_ks && pl.ks >= 1 && pl.ks <= kSwKsMax) {
     const int r = (pl.rem && !f && !lg) ? 1 : 0;
     return ks_names[r][f][lg][pl.ks - 1];
@@ -759,7 +994,12 @@ hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStre
     ks_attrs<6>(mx);
     ks_attrs<7>(mx);
     ks_attrs<8>(mx);
+    (void)hipFuncSetAttribute((const void *)sandwich_slice_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     attr_done = true;
+  }
+  if (pl.slice) {
+    sandwich_slice_kernel<<<dim3((unsigned)pl.iblocks, (unsigned)pl.gblocks, (unsigned)a.batch), 256, lds, s>>>(a, pl);
+    return hipGetLastError();
   }
   dim3 grid((unsigned)pl.iblocks, (unsigned)pl.chunks, (unsigned)a.batch);
   const bool ks = g_sandwich_ks && pl.ks >= 1 && pl.ks <= kSwKsMax;

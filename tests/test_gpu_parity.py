@@ -935,3 +935,24 @@ def test_check_finite_and_adaptive_rejects_non_finite():
     with pytest.raises(H.HattError) as e:
         H.recompress_adaptive(G, B, 1e-8, seed=1)
     assert e.value.status == -6 and "y train 0" in str(e.value)
+
+
+@pytest.mark.parametrize("shape", [(70, 50, 37), (81, 40, 29), (60, 44, 131)])
+def test_sandwich_large_ranks_slice_major_matches_oracle(shape):
+    """Factor ranks of 60 to 81 against 40 to 50 (the u^2 (.) u shape of the
+    trig workload and ragged neighbours): the W_L build and the core update
+    take the slice-major sandwich (one mode index per block, sketch columns
+    streamed), with a ragged last chunk of sketch columns; HaTT against the
+    oracle with the same sketch, untruncated."""
+    r, s, ell = shape
+    rng = np.random.default_rng(r * 1000 + s)
+    n = [150, 5, 150]
+    y = [rng.standard_normal((1, 150, r)), rng.standard_normal((r, 5, r)) / r, rng.standard_normal((r, 150, 1))]
+    z = [rng.standard_normal((1, 150, s)), rng.standard_normal((s, 5, s)) / s, rng.standard_normal((s, 150, 1))]
+    l = _ell(y, z, ell)
+    assert l == [1, ell, ell, 1]
+    ref = ohatt.hatt(y, z, philox.sketch(40 + r, n, l))
+    _say(f"hatt_recompress slice-major sandwich r={r} s={s} ell={l}")
+    got = _gpu_hatt([y], [z], ell, seed=40 + r)
+    assert tt.ranks(got.train(0)) == tt.ranks(ref)
+    assert tt.rel_err(got.train(0), ref) <= TOL
