@@ -172,10 +172,10 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
   if (pl->nbuf != 2) pl->ks = 0;
   pl->rem = (pl->ks > 0 && a.prec == 0 && a.og != 1 && a.SO >= 17 && a.SO <= 20 && a.RA >= 17 && a.RA <= 20) ? 1 : 0;
   pl->slice = 0;
-  // large factor ranks leave room for only one or two sketch columns per
-  // block next to a YL / ZR slice: there the slice-major kernel stages each
-  // slice once and streams the sketch columns instead
-  if (g_sandwich_slice && pl->ks == 0 && (pl->nbuf == 1 || pl->GC <= 2)) {
+  // large factor ranks leave room for a single YL / ZR slice buffer next to
+  // the sketch columns: there the slice-major kernel stages each slice once
+  // and streams the sketch columns instead
+  if (g_sandwich_slice && pl->ks == 0 && pl->nbuf == 1) {
     SwPlan sp = *pl;
     if (sandwich_slice_plan(a, budget, &sp)) *pl = sp;
   }

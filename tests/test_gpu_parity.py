@@ -937,13 +937,13 @@ def test_check_finite_and_adaptive_rejects_non_finite():
     assert e.value.status == -6 and "y train 0" in str(e.value)
 
 
-@pytest.mark.parametrize("shape", [(70, 50, 37), (81, 40, 29), (60, 44, 131)])
+@pytest.mark.parametrize("shape", [(70, 50, 37), (81, 40, 29), (96, 8, 131)])
 def test_sandwich_large_ranks_slice_major_matches_oracle(shape):
-    """Factor ranks of 60 to 81 against 40 to 50 (the u^2 (.) u shape of the
-    trig workload and ragged neighbours): the W_L build and the core update
-    take the slice-major sandwich (one mode index per block, sketch columns
-    streamed), with a ragged last chunk of sketch columns; HaTT against the
-    oracle with the same sketch, untruncated."""
+    """Factor ranks of 70 to 96 (the u^2 (.) u shape of the trig workload and
+    neighbours): the W_L build and the core update take the slice-major
+    sandwich (one mode index per block, sketch columns streamed one at a
+    time, or six at a time with a ragged last chunk for the rank-8 partner);
+    HaTT against the oracle with the same sketch, untruncated."""
     r, s, ell = shape
     rng = np.random.default_rng(r * 1000 + s)
     n = [150, 5, 150]
