@@ -407,10 +407,10 @@ def _bench_trig(args, torch, wk, H, perfmodel) -> int:
 
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
         t0 = time.perf_counter()
-        ref2 = rounding.tt_round(ohatt.hatt(u, u, philox.sketch(s2, U.n, ell2)), tol=tol)
+        ref2 = rounding.tt_round_left_orth(ohatt.hatt(u, u, philox.sketch(s2, U.n, ell2)), tol=tol)
         ta = time.perf_counter() - t0
         t0 = time.perf_counter()
-        ref3 = rounding.tt_round(ohatt.hatt(g2, u, philox.sketch(s3, U.n, ell3)), tol=tol)
+        ref3 = rounding.tt_round_left_orth(ohatt.hatt(g2, u, philox.sketch(s3, U.n, ell3)), tol=tol)
         tb = time.perf_counter() - t0
         cpu = {"value": 2.0 / (ta + tb), "unit": "recompressions/s", "cores": threads, "kind": "oracle",
                "sample": "one step: u2 and u3 by the FP64 numpy oracle (HaTT-1 with the same Philox sketches, "
@@ -877,7 +877,7 @@ def main() -> int:
         refs = []
         while done < B and (time.perf_counter() - t0) < args.cpu_seconds:
             yb, zb = pairs[done]
-            refs.append(rounding.tt_round(ohatt.hatt(yb, zb, R), max_rank=cap))
+            refs.append(rounding.tt_round_left_orth(ohatt.hatt(yb, zb, R), max_rank=cap))
             done += 1
         t_hatt = time.perf_counter() - t0
         cpu = {"value": done / t_hatt, "unit": "recompressions/s", "cores": threads, "kind": "oracle",

@@ -99,7 +99,10 @@ HATT_API hatt_status hatt_plan(const hatt_tt *x, const hatt_tt *y, const hatt_op
 /*
  * hatt_recompress -- Alg. 4 (HaTT): recompress x (.) y (elementwise product,
  * Sec. 2.2) for every train of the batch, then optionally truncate the
- * result with TT-Rounding (Alg. 1) to max_rank and/or tol.
+ * result to max_rank and/or tol with Alg. 1's truncation loop run from the
+ * right: every output core but the last is the Q of a QR, so the result is
+ * already left-orthogonal and Alg. 1's orthogonalisation pass is skipped
+ * (the bond rule is tt_round's, with ||z|| read off the last core).
  *   - Sketch: `sketch` may hold an explicit Gaussian TT with ranks
  *     ell_out of hatt_plan (batch 1: shared by all trains, or batch equal to
  *     x->batch: one per train); if NULL the library draws the random
@@ -224,7 +227,8 @@ HATT_API hatt_status tt_hadamard_explicit(const hatt_tt *x, const hatt_tt *y, do
  * the sketch W^{(k)} = (A_{k+1..d} contracted with R_{k+1..d}) right to
  * left (eq. rtlpc), then for k = 1..d-1: Q = QR(V(B_k) W^{(k)}) becomes
  * V(B_k), M = Q^T V(B_k) (the core before the QR), H(B_{k+1}) = M H(A_{k+1}); optionally
- * TT-Rounding (Alg. 1) of the rank-l result to max_rank and/or tol.  On the
+ * the rank-l result (left-orthogonal) is truncated to max_rank and/or tol as
+ * in hatt_recompress.  On the
  * PKP cores of x (.) y (tt_hadamard_explicit) it is the paper's RandOrth
  * comparator, and with the same sketch it represents the same tensor as
  * hatt_recompress (HaTT reorganises exactly these products).  Widths are

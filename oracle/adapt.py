@@ -7,7 +7,9 @@ small enough, l should be increased (Sec. 5.1.1).  The rule implemented here
 (the same on both sides):
 
 * start: l_k = max(r_k, s_k) + p (p = oversampling, default 8), clamped;
-* run HaTT with the sketch keyed by seed + attempt, then TT-Rounding at tol;
+* run HaTT with the sketch keyed by seed + attempt, then truncate at tol
+  (Alg. 1's truncation loop from the right on HaTT's left-orthogonal
+  output, rounding.tt_round_left_orth);
 * accept when every bond keeps rho_k <= l_k - p, or l_k already equals its
   largest feasible value (then the sketch captured the bond exactly);
 * otherwise on each failing bond set l_k = min(cap_k, ceil(1.5 l_k) + p) and
@@ -67,7 +69,7 @@ def hatt_adaptive(pairs, tol: float, seed: int, p: int = 8, max_attempts: int = 
     for attempt in range(max_attempts):
         l = plan.clamp_ell(n, rx, ry, ell)
         R = philox.sketch(seed + attempt * seed_step, n, l)
-        outs = [rounding.tt_round(hatt(y, z, R, variant, ep), tol=tol) for (y, z) in pairs]
+        outs = [rounding.tt_round_left_orth(hatt(y, z, R, variant, ep), tol=tol) for (y, z) in pairs]
         bad = failing_bonds([tt.ranks(o) for o in outs], l, cap, p)
         if not bad:
             return outs, l, attempt + 1, True

@@ -1,4 +1,6 @@
-"""TT-Rounding, Alg. 1 (Sec. 2.3), FP64 numpy.
+"""TT-Rounding, Alg. 1 (Sec. 2.3), FP64 numpy; its truncation loop run from
+the right on a left-orthogonal train (tt_round_left_orth, used after Alg. 4
+and Alg. 2, whose outputs are left-orthogonal).
 
 Readings (the printed listing is garbled in two places; the meaning taken):
 
@@ -69,6 +71,41 @@ def tt_round(tt: Sequence[np.ndarray], max_rank=None, tol: float = 0.0, return_s
         b[k] = (q @ u[:, :rho]).reshape(r0, n, rho)
         _, pn, p1 = b[k + 1].shape
         b[k + 1] = ((s[:rho, None] * vt[:rho, :]) @ H(b[k + 1])).reshape(rho, pn, p1)
+    if return_sigmas:
+        return b, sigmas
+    return b
+
+
+def tt_round_left_orth(tt: Sequence[np.ndarray], max_rank=None, tol: float = 0.0, return_sigmas: bool = False):
+    """Alg. 1's truncation loop run from the right on a left-orthogonal train
+    (cores 1..d-1 have orthonormal columns in V(.), as every core of Alg. 4's
+    and Alg. 2's output but the last).  Alg. 1 first orthogonalises one way
+    and then truncates the other; such an input is already orthogonalised
+    from the left, so the truncation runs right to left with no
+    orthogonalisation pass.  Bond k: QR of H(B_k)^T = Q R, so H(B_k) = R^T Q^T;
+    SVD R^T = U S W^T; keep rho columns (same rule and delta = tol ||A||_F /
+    sqrt(d-1) as tt_round, ||A||_F = ||B_d||_F); B_k <- (Q W_rho)^T folded,
+    B_{k-1} <- B_{k-1} x_3 (U_rho S_rho).  ``max_rank`` as in tt_round."""
+    d = len(tt)
+    if max_rank is None:
+        caps = [None] * (d + 1)
+    elif np.isscalar(max_rank):
+        caps = [int(max_rank)] * (d + 1)
+    else:
+        caps = list(max_rank)
+    b = [np.array(c, dtype=np.float64, copy=True) for c in tt]
+    nrm = float(np.linalg.norm(b[d - 1]))
+    delta = tol * nrm / math.sqrt(d - 1) if (tol > 0 and d > 1) else 0.0
+    sigmas = [None] * (d - 1)
+    for k in range(d - 1, 0, -1):
+        r0, n, r1 = b[k].shape
+        q, r = _qr_pos(H(b[k]).T)              # (n r1) x r0 = Q R
+        u, sg, wt = np.linalg.svd(r.T, full_matrices=False)
+        rho = choose_rank(sg, delta, caps[k])
+        sigmas[k - 1] = sg
+        b[k] = (q @ wt[:rho, :].T).T.reshape(rho, n, r1)
+        p0, pn, _ = b[k - 1].shape
+        b[k - 1] = (V(b[k - 1]) @ (u[:, :rho] * sg[None, :rho])).reshape(p0, pn, rho)
     if return_sigmas:
         return b, sigmas
     return b

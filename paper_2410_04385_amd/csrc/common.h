@@ -120,6 +120,21 @@ const char *sandwich_kernel_name(const SandwichArgs &a);
 // dst[p * dbs + k] = (float) src[p * sbs + k] for k < count, p < batch.
 hipError_t launch_cast_f32(const double *src, int64_t sbs, float *dst, int64_t dbs, int64_t count, int batch,
                            hipStream_t s);
+// Reversal of a train of at most kRevMaxCores cores (per core: element
+// offsets and r0, n, r1 of the source core; the destination core d-1-k sits
+// at doff[k]); dst(b, i, a) = src(a, i, b).
+constexpr int kRevMaxCores = 96;
+struct RevArgs {
+  const double *src;
+  double *dst;
+  int64_t sstride, dstride;
+  int d;
+  int64_t soff[kRevMaxCores], doff[kRevMaxCores];
+  int r0[kRevMaxCores], n[kRevMaxCores], r1[kRevMaxCores];
+};
+hipError_t launch_tt_reverse(const RevArgs &a, int64_t max_core, int batch, hipStream_t s);
+// dst[p][k] = src[p][d - k] for the kept-rank arrays ([batch][d+1], int64).
+hipError_t launch_rank_reverse(const int64_t *src, int64_t *dst, int d, int batch, hipStream_t s);
 // flag[p] (int, device) = 1 when the first `count` doubles of train p
 // (pair stride `stride`) are all finite, else 0.
 hipError_t launch_finite_check(const double *data, int64_t count, int64_t stride, int batch, int *flag,

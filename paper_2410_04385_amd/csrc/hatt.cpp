@@ -775,6 +775,7 @@ struct RoundSpec {
   std::vector<int64_t> bond_cap;  // optional [d+1]: per-bond cap (replaces max_rank)
   double tol;
   int batch;
+  bool right_orth = false;  // cores 1..d-1 already have orthonormal rows: no right-to-left pass
   bool norm_only;     // stop after the right-to-left sweep and write ||B_1||
   double *norm_out;   // [batch] (norm_only)
 };
@@ -799,13 +800,15 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
   make_offsets(n, sp.rin, &soff, &stot);
   // right-to-left ranks
   std::vector<int64_t> rb(sp.rin);
-  for (int c = d - 1; c >= 1; --c) rb[c] = std::min(sp.rin[c], n[c] * rb[c + 1]);
+  if (!sp.right_orth)
+    for (int c = d - 1; c >= 1; --c) rb[c] = std::min(sp.rin[c], n[c] * rb[c + 1]);
   const auto &cap = sp.cap;
   // --- sizes
   int64_t qr_ws = 1, qbuf = 1, rbuf = 1, ubuf = 1, sbuf = 1, tbuf = 1, tmp = 1, svd_ws = 1;
   int64_t lq_q = 1, lq_r = 1, lq_s = 1;
   std::vector<QrOp> op_rl(d), op_lr(d), op_lq(d);
-  for (int c = d - 1; c >= 1; --c) {
+  if (sp.right_orth) tmp = std::max(tmp, n[0] * rb[1]);  // the first core, copied for the left-to-right pass
+  for (int c = d - 1; c >= 1 && !sp.right_orth; --c) {
     const int64_t m = n[c] * rb[c + 1], nc = sp.rin[c];
     if (!qr_prepare(m, nc, &op_rl[c]))
       return fail(HATT_EUNSUPPORTED, "TT-Rounding: a right-to-left QR of " + std::to_string(m) + " x " +
@@ -884,10 +887,13 @@ hatt_status round_body(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &gc, hipSt
     }
     return HATT_OK;
   }
+  if (sp.right_orth)  // the left-to-right pass reads the first core from Tm
+    LAUNCH(launch_copy(CMat{work + soff[0], n[0] * rb[1], 1, wstride}, Mat{Tm, n[0] * rb[1], 1, tmp}, 1,
+                       n[0] * rb[1], P, st));
   // --- right-to-left orthogonalisation; core c layout: [*][n_c][rb_{c+1}] compact.
   // V(B_{c-1}) R^T lands in Tm in that same compact layout, and the next QR
   // reads it there (writing its Q into the core's slot), so no copy-back.
-  for (int c = d - 1; c >= 1; --c) {
+  for (int c = d - 1; c >= 1 && !sp.right_orth; --c) {
     const QrOp &op = op_rl[c];
     const int64_t m = n[c] * rb[c + 1], nc = sp.rin[c], k = op.k;
     double *core = work + soff[c];
@@ -1034,6 +1040,78 @@ hatt_status round_run(bool run, const RoundSpec &sp, Ws &ws, GemmCtx &, hipStrea
   g1.part = ws.d(std::max<int64_t>(g0.part_need, 1));
   g1.part_cap = g0.part_need;
   return round_body(run, sp, ws, g1, st);
+}
+
+// Truncation of a left-orthogonal train (cores 0..d-2 with orthonormal
+// columns in V(.), as Alg. 4 and Alg. 2 leave them) in place at capacity
+// ranks l: Alg. 1's truncation loop run from the right.  The train is
+// reversed into scratch (a reversed left-orthogonal train is right-orthogonal,
+// which is what Alg. 1's first pass would produce), truncated left to right
+// there without that pass, and reversed back with its kept ranks.
+hatt_status truncate_left_orth(bool run, const std::vector<int64_t> &n, const std::vector<int64_t> &l,
+                               double *out, int64_t ostride, int64_t *orank, const std::vector<int64_t> &bond_cap,
+                               double tol, int P, Ws &ws, hipStream_t st) {
+  const int d = (int)n.size();
+  if (d > kRevMaxCores)
+    return fail(HATT_EUNSUPPORTED, "truncation: order above " + std::to_string(kRevMaxCores) + " is not built");
+  std::vector<int64_t> ooff, roff, nr(d), lr(d + 1), cr(d + 1, 0);
+  int64_t otot, rtot;
+  make_offsets(n, l, &ooff, &otot);
+  for (int k = 0; k < d; ++k) nr[k] = n[d - 1 - k];
+  for (int k = 0; k <= d; ++k) {
+    lr[k] = l[d - k];
+    if (!bond_cap.empty()) cr[k] = bond_cap[d - k];
+  }
+  make_offsets(nr, lr, &roff, &rtot);
+  double *rev = ws.d((int64_t)P * rtot);
+  int64_t *rrank = ws.i64((int64_t)P * (d + 1));
+  RevArgs fwd{}, bwd{};
+  fwd.src = out;
+  fwd.dst = rev;
+  fwd.sstride = ostride;
+  fwd.dstride = rtot;
+  fwd.d = d;
+  bwd.src = rev;
+  bwd.dst = out;
+  bwd.sstride = rtot;
+  bwd.dstride = ostride;
+  bwd.d = d;
+  int64_t mx = 1;
+  for (int k = 0; k < d; ++k) {
+    fwd.soff[k] = ooff[k];
+    fwd.doff[k] = roff[d - 1 - k];
+    fwd.r0[k] = (int)l[k];
+    fwd.n[k] = (int)n[k];
+    fwd.r1[k] = (int)l[k + 1];
+    bwd.soff[k] = roff[k];
+    bwd.doff[k] = ooff[d - 1 - k];
+    bwd.r0[k] = (int)lr[k];
+    bwd.n[k] = (int)nr[k];
+    bwd.r1[k] = (int)lr[k + 1];
+    mx = std::max(mx, l[k] * n[k] * l[k + 1]);
+  }
+  LAUNCH(launch_tt_reverse(fwd, mx, P, st));
+  RoundSpec rs{};
+  rs.n = nr;
+  rs.rin = lr;
+  rs.cap = lr;
+  rs.src = rev;
+  rs.sstride = rtot;
+  rs.in_place = true;
+  rs.out = rev;
+  rs.ostride = rtot;
+  rs.orank = rrank;
+  rs.max_rank = 0;
+  rs.bond_cap = cr;
+  rs.tol = tol;
+  rs.batch = P;
+  rs.right_orth = true;
+  GemmCtx gr{nullptr, 0, 0};
+  hatt_status s = round_run(run, rs, ws, gr, st);
+  if (s != HATT_OK) return s;
+  LAUNCH(launch_tt_reverse(bwd, mx, P, st));
+  LAUNCH(launch_rank_reverse(rrank, orank, d, P, st));
+  return HATT_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1347,23 +1425,9 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
   bool capped = false;
   for (int64_t c : sp.bond_cap) capped = capped || c > 0;
   const bool trunc = capped || (sp.o.tol > 0.0);
-  if (trunc) {
-    RoundSpec rs{};
-    rs.n = n;
-    rs.rin = l;
-    rs.cap = l;
-    rs.bond_cap = sp.bond_cap;
-    rs.src = sp.out;
-    rs.sstride = sp.ostride;
-    rs.in_place = true;
-    rs.out = sp.out;
-    rs.ostride = sp.ostride;
-    rs.orank = sp.orank;
-    rs.max_rank = sp.o.max_rank;
-    rs.tol = sp.o.tol;
-    rs.batch = P;
-    GemmCtx gr{nullptr, 0, 0};
-    hatt_status s1 = round_run(run, rs, ws, gr, st);
+  if (trunc && d >= 2) {
+    // every output core but the last is the Q of a QR: left-orthogonal
+    hatt_status s1 = truncate_left_orth(run, n, l, sp.out, sp.ostride, sp.orank, sp.bond_cap, sp.o.tol, P, ws, st);
     if (s1 != HATT_OK) return s1;
   }
   return HATT_OK;
@@ -1488,22 +1552,10 @@ hatt_status randorth_body(bool run, const RoSpec &sp, Ws &ws, GemmCtx &gc, hipSt
   }
   if ((int)l.size() > kMaxRankPattern) return fail(HATT_EUNSUPPORTED, "order too large for the library (rank pattern buffer)");
   LAUNCH(launch_rank_pattern(sp.orank, P, d + 1, l.data(), st));
-  if (sp.max_rank > 0 || sp.tol > 0.0) {
-    RoundSpec rs{};
-    rs.n = n;
-    rs.rin = l;
-    rs.cap = l;
-    rs.src = sp.out;
-    rs.sstride = sp.ostride;
-    rs.in_place = true;
-    rs.out = sp.out;
-    rs.ostride = sp.ostride;
-    rs.orank = sp.orank;
-    rs.max_rank = sp.max_rank;
-    rs.tol = sp.tol;
-    rs.batch = P;
-    GemmCtx gr{nullptr, 0, 0};
-    s = round_run(run, rs, ws, gr, st);
+  if ((sp.max_rank > 0 || sp.tol > 0.0) && d >= 2) {
+    // RandOrth's cores but the last are the Q factors of its QRs: left-orthogonal
+    std::vector<int64_t> caps(d + 1, std::max<int64_t>(sp.max_rank, 0));
+    s = truncate_left_orth(run, n, l, sp.out, sp.ostride, sp.orank, caps, sp.tol, P, ws, st);
     if (s != HATT_OK) return s;
   }
   return HATT_OK;

@@ -519,6 +519,48 @@ hipError_t launch_finite_check(const double *data, int64_t count, int64_t stride
   return hipGetLastError();
 }
 
+// Reversal of a train: core k (r0 x n x r1, row-major) becomes core d-1-k
+// (r1 x n x r0) of the destination, dst(b, i, a) = src(a, i, b).  One block
+// row per core (blockIdx.y), pairs along blockIdx.z; reads are coalesced.
+__global__ void tt_reverse_kernel(RevArgs a) {
+  const int k = blockIdx.y, p = blockIdx.z;
+  const int r0 = a.r0[k], n = a.n[k], r1 = a.r1[k];
+  const int64_t cnt = (int64_t)r0 * n * r1;
+  const double *src = a.src + p * a.sstride + a.soff[k];
+  double *dst = a.dst + p * a.dstride + a.doff[k];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ai = e / r1;
+    const int b = (int)(e - ai * r1);
+    const int64_t aa = ai / n;
+    const int i = (int)(ai - aa * n);
+    dst[((int64_t)b * n + i) * r0 + aa] = src[e];
+  }
+}
+
+hipError_t launch_tt_reverse(const RevArgs &a, int64_t max_core, int batch, hipStream_t s) {
+  if (batch <= 0 || a.d <= 0) return hipSuccess;
+  if (a.d > kRevMaxCores) return hipErrorInvalidValue;
+  const unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_core + 255) / 256, 1024));
+  tt_reverse_kernel<<<dim3(bx, (unsigned)a.d, (unsigned)batch), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+// dst[p][k] = src[p][d - k], k = 0..d (the kept ranks of a reversed train).
+__global__ void rank_reverse_kernel(const int64_t *src, int64_t *dst, int d, int batch) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)batch * (d + 1)) return;
+  const int64_t p = e / (d + 1);
+  const int k = (int)(e - p * (d + 1));
+  dst[e] = src[p * (d + 1) + (d - k)];
+}
+
+hipError_t launch_rank_reverse(const int64_t *src, int64_t *dst, int d, int batch, hipStream_t s) {
+  const int64_t tot = (int64_t)batch * (d + 1);
+  if (tot <= 0) return hipSuccess;
+  rank_reverse_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(src, dst, d, batch);
+  return hipGetLastError();
+}
+
 __global__ void cast_f64_kernel(const float *src, int64_t sbs, double *dst, int64_t dbs, int64_t count, int batch) {
   const int64_t total = count * batch;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;

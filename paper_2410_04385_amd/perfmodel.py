@@ -42,17 +42,16 @@ def hatt_round_flops(n: Sequence[int], r: Sequence[int], s: Sequence[int], ell: 
         cn = c + 1
         out["sandwich"] += 2.0 * n[cn] * ell[cn] * (r[cn] * s[cn] * s[cn + 1] + r[cn + 1] * r[cn] * s[cn + 1])
     if cap is not None and d > 1:
-        # TT-Rounding of the rank-l result: right-to-left QR + absorb,
-        # left-to-right QR + (Q U) + (S V^T) H(B_{k+1})
-        for c in range(d - 1, 0, -1):
-            out["qr"] += _qr_flops(n[c] * ell[c + 1], ell[c])
-            out["gemm_f64"] += 2.0 * ell[c - 1] * n[c - 1] * ell[c] * ell[c]
+        # truncation of the left-orthogonal rank-l result from the right (no
+        # orthogonalisation pass): per bond the QR of the transposed
+        # unfolding, the kept core (Q W) and the absorb of (U S) into the
+        # core to its left
         caps = [1] + [min(cap, ell[k]) for k in range(1, d)] + [1]
-        for c in range(d - 1):
-            m = caps[c] * n[c]
-            out["qr"] += _qr_flops(m, ell[c + 1])
-            out["gemm_f64"] += 2.0 * m * ell[c + 1] * caps[c + 1]
-            out["gemm_f64"] += 2.0 * caps[c + 1] * ell[c + 1] * n[c + 1] * ell[c + 2]
+        for c in range(d - 1, 0, -1):
+            m = n[c] * caps[c + 1]
+            out["qr"] += _qr_flops(m, ell[c])
+            out["gemm_f64"] += 2.0 * m * ell[c] * caps[c]
+            out["gemm_f64"] += 2.0 * ell[c - 1] * n[c - 1] * ell[c] * caps[c]
     out["total"] = sum(out.values())
     return out
 

@@ -200,7 +200,7 @@ def test_hatt_truncated_matches_oracle(kw):
     R = wk.gaussian_sketch(np.random.default_rng(1), tt.modes(y), l)
     _say(f"hatt_recompress truncated {kw}")
     res = _gpu_hatt(y, z, 9, sketch=H.TT.from_cores(R), **kw)
-    ref = rounding.tt_round(ohatt.hatt(y, z, R), max_rank=kw.get("max_rank"), tol=kw.get("tol", 0.0))
+    ref = rounding.tt_round_left_orth(ohatt.hatt(y, z, R), max_rank=kw.get("max_rank"), tol=kw.get("tol", 0.0))
     got = res.train(0)
     assert tt.ranks(got) == tt.ranks(ref)
     assert tt.rel_err(got, ref) <= TOL
@@ -216,7 +216,7 @@ def test_hatt_batched_pairs_match_per_pair_oracle():
     _say("hatt_recompress batch=5 shared sketch max_rank=5")
     res = _gpu_hatt(ys, zs, 7, sketch=H.TT.from_cores(R), max_rank=5)
     for b in range(B):
-        ref = rounding.tt_round(ohatt.hatt(ys[b], zs[b], R), max_rank=5)
+        ref = rounding.tt_round_left_orth(ohatt.hatt(ys[b], zs[b], R), max_rank=5)
         assert tt.rel_err(res.train(b), ref) <= TOL
 
 
@@ -238,7 +238,7 @@ def test_spectral_workload_full_size():
     seed = 7
     _say("hatt_recompress spectral full size, 1 pair")
     res = _gpu_hatt(y, z, cfg["ell"], seed=seed, max_rank=cfg["max_rank"])
-    ref = rounding.tt_round(ohatt.hatt(y, z, philox.sketch(seed, tt.modes(y), l)), max_rank=cfg["max_rank"])
+    ref = rounding.tt_round_left_orth(ohatt.hatt(y, z, philox.sketch(seed, tt.modes(y), l)), max_rank=cfg["max_rank"])
     got = res.train(0)
     assert tt.ranks(got) == tt.ranks(ref)
     assert tt.rel_err(got, ref) <= TOL
@@ -269,7 +269,7 @@ def test_hatt_sketch_wider_than_one_panel():
     R = wk.gaussian_sketch(np.random.default_rng(3), tt.modes(y), l)
     _say(f"hatt_recompress ell={l} tol=1e-6")
     res = _gpu_hatt(y, z, 150, sketch=H.TT.from_cores(R), tol=1e-6)
-    ref = rounding.tt_round(ohatt.hatt(y, z, R), tol=1e-6)
+    ref = rounding.tt_round_left_orth(ohatt.hatt(y, z, R), tol=1e-6)
     got = res.train(0)
     assert tt.ranks(got) == tt.ranks(ref)
     assert tt.rel_err(got, ref) <= TOL
@@ -416,7 +416,7 @@ def test_qr_methods_agree_with_oracle(method):
     finally:
         H.set_qr_method("cholqr2")
     R = philox.sketch(8, tt.modes(y), plan.clamp_ell(tt.modes(y), tt.ranks(y), tt.ranks(z), 40))
-    ref = rounding.tt_round(ohatt.hatt(y, z, R), max_rank=30)
+    ref = rounding.tt_round_left_orth(ohatt.hatt(y, z, R), max_rank=30)
     got = res.train(0)
     assert tt.ranks(got) == tt.ranks(ref)
     assert tt.rel_err(got, ref) <= 1e-10
@@ -451,7 +451,7 @@ def test_batched_uneven_pairs_match_oracle():
         ell = _rule_ell(ys[0], zs[0])
         R = philox.sketch(500 + p, tt.modes(ys[0]), ell)
         for b in range(len(ys)):
-            ref = rounding.tt_round(ohatt.hatt(ys[b], zs[b], R), max_rank=6)
+            ref = rounding.tt_round_left_orth(ohatt.hatt(ys[b], zs[b], R), max_rank=6)
             got = res[p].train(b)
             assert tt.ranks(got) == tt.ranks(ref), p
             assert tt.rel_err(got, ref) <= 1e-10, p
@@ -477,7 +477,7 @@ def test_batched_workload_sample():
     for p in sorted(set(np.argsort(cost)[:3].tolist() + np.argsort(wide)[-3:].tolist())):
         y, z = cores[p]
         ell = _rule_ell(y, z)
-        ref = rounding.tt_round(ohatt.hatt(y, z, philox.sketch(900 + int(p), tt.modes(y), ell)), tol=1e-6)
+        ref = rounding.tt_round_left_orth(ohatt.hatt(y, z, philox.sketch(900 + int(p), tt.modes(y), ell)), tol=1e-6)
         got = res[p].train(0)
         assert tt.ranks(got) == tt.ranks(ref)
         assert tt.rel_err(got, ref) <= 1e-9
@@ -559,7 +559,7 @@ def test_fp32_range_finding_matches_oracle_spectral_order_20():
     X, Z = H.TT.from_cores([y]), H.TT.from_cores([z])
     l = _ell(y, z, cfg["ell"])
     raw = ohatt.hatt(y, z, philox.sketch(5, tt.modes(y), l))
-    ref = rounding.tt_round(raw, max_rank=cfg["max_rank"])
+    ref = rounding.tt_round_left_orth(raw, max_rank=cfg["max_rank"])
     _say("hatt_recompress f32 vs oracle spectral d=20")
     a = H.recompress(X, Z, cfg["ell"], seed=5, precision="f32")
     b = H.recompress(X, Z, cfg["ell"], max_rank=cfg["max_rank"], seed=5, precision="f32")
@@ -584,7 +584,7 @@ def test_fp32_range_finding_accuracy_on_trig_u2():
     u = wk.trig_u(11, n=cfg["n"], terms=2 * cfg["nfreq"], nfreq=cfg["nfreq"])
     U = H.TT.from_cores(u)
     l = _ell(u, u, cfg["ell2"])
-    ref = rounding.tt_round(ohatt.hatt(u, u, philox.sketch(1, tt.modes(u), l)), tol=cfg["tol"])
+    ref = rounding.tt_round_left_orth(ohatt.hatt(u, u, philox.sketch(1, tt.modes(u), l)), tol=cfg["tol"])
     _say("hatt_recompress f32 trig 256^3 u*u width 96 tol 1e-8")
     got = H.recompress(U, U, cfg["ell2"], tol=cfg["tol"], seed=1, precision="f32")
     torch.cuda.synchronize()
@@ -630,7 +630,7 @@ def test_many_pairs_fused_gram_cholesky_wide_frames(ell):
     _say(f"hatt_recompress batch={B} ell={l} max_rank=20 (fused Gram + Cholesky, wide frames)")
     res = _gpu_hatt(ys, zs, ell, sketch=H.TT.from_cores(R), max_rank=20)
     for b in range(B):
-        ref = rounding.tt_round(ohatt.hatt(ys[b], zs[b], R), max_rank=20)
+        ref = rounding.tt_round_left_orth(ohatt.hatt(ys[b], zs[b], R), max_rank=20)
         got = res.train(b)
         assert tt.ranks(got) == tt.ranks(ref), b
         assert tt.rel_err(got, ref) <= TOL, b
@@ -657,7 +657,7 @@ def test_many_pairs_fused_gram_cholesky_long_frames():
     _say(f"hatt_recompress batch={B} ell={l} max_rank=20 (long frames, two rank-deficient pairs)")
     res = _gpu_hatt(ys, zs, 40, sketch=H.TT.from_cores(R), max_rank=20)
     for b in range(B):
-        ref = rounding.tt_round(ohatt.hatt(ys[b], zs[b], R), max_rank=20)
+        ref = rounding.tt_round_left_orth(ohatt.hatt(ys[b], zs[b], R), max_rank=20)
         got = res.train(b)
         assert tt.ranks(got) == tt.ranks(ref), b
         assert tt.rel_err(got, ref) <= TOL, b
@@ -685,7 +685,7 @@ def test_many_pairs_fused_gram_cholesky():
     _say("hatt_recompress batch=40 ell=24 max_rank=10 (fused Gram + Cholesky, two rank-deficient pairs)")
     res = _gpu_hatt(ys, zs, 24, sketch=H.TT.from_cores(R), max_rank=10)
     for b in range(B):
-        ref = rounding.tt_round(ohatt.hatt(ys[b], zs[b], R), max_rank=10)
+        ref = rounding.tt_round_left_orth(ohatt.hatt(ys[b], zs[b], R), max_rank=10)
         got = res.train(b)
         assert tt.ranks(got) == tt.ranks(ref), b
         assert tt.rel_err(got, ref) <= TOL, b
@@ -861,7 +861,7 @@ def test_hatt_panelled_rank_deficient_square_frames(method):
     n = tt.modes(u2)
     l = list(_QTT9_WIDTHS)
     raw = ohatt.hatt(u2, phi, philox.sketch(4, n, l), 1, 0.0)
-    ref = rounding.tt_round(raw, tol=1e-8)
+    ref = rounding.tt_round_left_orth(raw, tol=1e-8)
     X, P = H.TT.from_cores(u2), H.TT.from_cores(phi)
     _say(f"HaTT QTT order 27 widths up to 262, QR method {method}")
     H.set_qr_method(method)
@@ -908,7 +908,7 @@ def test_per_bond_max_rank_matches_oracle():
     caps = [0, 5, 0, 17, 3, 0, 11, 0, 0]
     l = _ell(y, z, 40)
     raw = ohatt.hatt(y, z, philox.sketch(21, tt.modes(y), l))
-    ref = rounding.tt_round(raw, max_rank=[c if c > 0 else None for c in caps], tol=1e-3)
+    ref = rounding.tt_round_left_orth(raw, max_rank=[c if c > 0 else None for c in caps], tol=1e-3)
     _say("hatt_recompress per-bond max_rank, spectral d=8")
     got = H.recompress(X, Z, 40, max_rank=caps, tol=1e-3, seed=21)
     torch.cuda.synchronize()

@@ -210,3 +210,54 @@ def test_order_one_and_two():
     x = hatt.hatt(y, z, R)
     fz = tt.full(y) * tt.full(z)
     assert np.linalg.norm(tt.full(x) - fz) < 1e-13 * np.linalg.norm(fz)
+
+
+def _reversed_full(a):
+    """Full tensor with its modes in reverse order."""
+    f = tt.full(a)
+    return np.transpose(f, tuple(range(f.ndim - 1, -1, -1)))
+
+
+def _reverse_train(cores):
+    return [np.transpose(c, (2, 1, 0)) for c in reversed(cores)]
+
+
+@pytest.mark.parametrize("cap,tol", [(None, 1e-12), (3, 0.0), ([None, 2, 5, 4, 3, None], 0.0), (None, 0.2)])
+def test_round_left_orth_equals_reverse_tt_svd(cap, tol):
+    """The right-to-left truncation of a left-orthogonal train equals TT-SVD
+    of the full tensor run from the last mode (the TT-SVD of the
+    mode-reversed tensor, reversed back): same ranks, same tensor.  The
+    train is a random one made left-orthogonal, so only the tensor, not
+    the gauge, is shared with the reference."""
+    rng = np.random.default_rng(11)
+    n = [3, 4, 3, 5, 2]
+    a = [rng.standard_normal((r0, m, r1)) for r0, m, r1 in zip([1, 3, 6, 6, 4], n, [3, 6, 6, 4, 1])]
+    a = tt.orthogonalize_lr(a)
+    got = rounding.tt_round_left_orth(a, max_rank=cap, tol=tol)
+    rcap = None if cap is None or np.isscalar(cap) else list(reversed(cap))
+    ref = _reverse_train(rounding.tt_svd(_reversed_full(a), tol=tol, max_rank=cap if np.isscalar(cap) else rcap))
+    assert tt.ranks(got) == tt.ranks(ref)
+    assert tt.rel_err(got, ref) <= 1e-12
+    if cap is None:
+        full = tt.full(a)
+        assert np.linalg.norm(tt.full(got) - full) <= max(tol, 1e-13) * np.linalg.norm(full) * (1 + 1e-12)
+
+
+def test_round_left_orth_on_hatt_output():
+    """Alg. 4's output is left-orthogonal: the right-to-left truncation
+    without an orthogonalisation pass keeps the Alg. 1 error guarantee
+    (within tol of the untruncated result) and, in the exact-rank regime,
+    gives the same tensor and ranks as Alg. 1."""
+    y, z = wk.spectral_pair(6, 6, 8, 6, 5)
+    l = plan.clamp_ell(tt.modes(y), tt.ranks(y), tt.ranks(z), [1] + [24] * 5 + [1])
+    raw = hatt.hatt(y, z, philox.sketch(9, tt.modes(y), l))
+    for k in range(len(raw) - 1):
+        q = tt.V(raw[k])
+        assert np.allclose(q.T @ q, np.eye(q.shape[1]), atol=1e-12)
+    for tol in (1e-2, 1e-5):
+        got = rounding.tt_round_left_orth(raw, tol=tol)
+        assert tt.rel_err(got, raw) <= tol
+    exact = rounding.tt_round_left_orth(raw, tol=1e-13)
+    alg1 = rounding.tt_round(raw, tol=1e-13)
+    assert tt.ranks(exact) == tt.ranks(alg1)
+    assert tt.rel_err(exact, alg1) <= 1e-12
