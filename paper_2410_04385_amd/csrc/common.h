@@ -43,18 +43,6 @@ struct PkpArgs {
 };
 hipError_t launch_pkp(const PkpArgs &a, hipStream_t s);
 
-// W(a s + b, g) = sum_i X(a, i) Y(b, i) R(g, i) (last cores, right rank 1).
-struct LastArgs {
-  const double *x;
-  const double *y;
-  const double *r;
-  double *w;
-  int64_t rx, sy, l, n;
-  int64_t xs, ys, rsb, ws;  // batch strides
-  int batch;
-};
-hipError_t launch_hpcrl_last(const LastArgs &a, hipStream_t s);
-
 // Sandwich: out_{i,g}(a', b') = sum_{a,b} YL_i(a', a) C_g(a, b) ZR_i(b, b')
 // for i < n, g < G.  All operands strided; see hatt.cpp for the two uses
 // (W_L columns of HPCRL and the PKP-free core update).
@@ -132,7 +120,8 @@ struct RevArgs {
   int64_t soff[kRevMaxCores], doff[kRevMaxCores];
   int r0[kRevMaxCores], n[kRevMaxCores], r1[kRevMaxCores];
 };
-hipError_t launch_tt_reverse(const RevArgs &a, int64_t max_core, int batch, hipStream_t s);
+// max_tiles: the largest ceil(r0/32) ceil(r1/32) n over the cores.
+hipError_t launch_tt_reverse(const RevArgs &a, int64_t max_tiles, int batch, hipStream_t s);
 // dst[p][k] = src[p][d - k] for the kept-rank arrays ([batch][d+1], int64).
 hipError_t launch_rank_reverse(const int64_t *src, int64_t *dst, int d, int batch, hipStream_t s);
 // flag[p] (int, device) = 1 when the first `count` doubles of train p

@@ -169,7 +169,6 @@ int class_of(const char *expr) {
   if (strstr(expr, "launch_sandwich")) return P_SANDWICH;
   if (strstr(expr, "launch_svd")) return P_SVD;
   if (strstr(expr, "launch_pkp")) return P_PKP;
-  if (strstr(expr, "launch_hpcrl_last")) return P_LAST;
   if (strstr(expr, "launch_sketch")) return P_SKETCH;
   return P_OTHER;
 }
@@ -1088,7 +1087,7 @@ hatt_status truncate_left_orth(bool run, const std::vector<int64_t> &n, const st
     bwd.r0[k] = (int)lr[k];
     bwd.n[k] = (int)nr[k];
     bwd.r1[k] = (int)lr[k + 1];
-    mx = std::max(mx, l[k] * n[k] * l[k + 1]);
+    mx = std::max(mx, ((l[k] + 31) / 32) * ((l[k + 1] + 31) / 32) * n[k]);
   }
   LAUNCH(launch_tt_reverse(fwd, mx, P, st));
   RoundSpec rs{};
@@ -1194,6 +1193,7 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
   int64_t wdsz = 1;
   for (int b = 1; b < d; ++b) wdsz = std::max(wdsz, r[b] * s[b] * l[b]);
   double *Wd = f32 ? ws.d((int64_t)P * wdsz) : nullptr;
+  double *Hlast = (d >= 2) ? ws.d((int64_t)P * r[d - 1] * s[d - 1] * n[d - 1]) : nullptr;
   double *Xc = ws.d((int64_t)P * xsz);
   double *Yb = ws.d((int64_t)P * ysz);
   double *Mb = ws.d((int64_t)P * msz);
@@ -1220,21 +1220,18 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
   }
   // ---- HPCRL (Alg. 3), HaTT-1 split
   {
-    LastArgs la{};
-    la.x = xd + sp.X.off[d - 1];
-    la.y = yd + sp.Y.off[d - 1];
-    la.r = sk + skoff[d - 1];
-    la.w = f32 ? Wlast : W + woff[d - 1];
-    la.rx = r[d - 1];
-    la.sy = s[d - 1];
-    la.l = l[d - 1];
-    la.n = n[d - 1];
-    la.xs = xs;
-    la.ys = ys;
-    la.rsb = sks;
-    la.ws = f32 ? lastsz : wtot;
-    la.batch = P;
-    LAUNCH(launch_hpcrl_last(la, st));
+    // W^{(d-1)} = H(Y_d (x)^1 Z_d) H(R_d)^T: the product's last-core rows
+    // (rank r s, one mode index each: the PKP of two rank-1-on-the-right
+    // cores, r s n entries) times the sketch's last core on the matrix cores
+    ClassScope cs(P_LAST);
+    const int64_t rs = r[d - 1] * s[d - 1];
+    PkpArgs pl{xd + sp.X.off[d - 1], yd + sp.Y.off[d - 1], Hlast, r[d - 1], 1, s[d - 1], 1, n[d - 1], xs, ys,
+               rs * n[d - 1], P};
+    LAUNCH(launch_pkp(pl, st));
+    hatt_status sl = gemm(run, gc, CMat{Hlast, n[d - 1], 1, rs * n[d - 1]}, CMat{sk + skoff[d - 1], 1, n[d - 1], sks},
+                          Mat{f32 ? Wlast : W + woff[d - 1], l[d - 1], 1, f32 ? lastsz : wtot}, rs, l[d - 1],
+                          n[d - 1], 1.0, 0.0, P, st, true);
+    if (sl != HATT_OK) return sl;
     if (f32) {
       // FP32 keeps 8 exponent bits: each W^{(k)} is brought back to unit scale
       // by a power of two (range(X W) is unchanged by any rescaling of W)
@@ -1372,6 +1369,14 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
                l[c + 1], rs1, m, 1.0, 0.0, P, st, true);
     if (stt != HATT_OK) return stt;
     const int cn = c + 1;
+    if (cn == d - 1) {
+      // last core (right ranks 1): X_d(g, i) = sum_{a,b} M(g, a s + b) Y_d(a, i) Z_d(b, i)
+      // = (M H)(g, i) with H the last-core PKP rows HPCRL formed
+      hatt_status sg = gemm(run, gc, CMat{Mb, rs1, 1, msz}, CMat{Hlast, n[cn], 1, rs1 * n[cn]},
+                            Mat{sp.out + ooff[cn], n[cn], 1, sp.ostride}, l[cn], n[cn], rs1, 1.0, 0.0, P, st, true);
+      if (sg != HATT_OK) return sg;
+      continue;
+    }
     SandwichArgs a{};
     a.yl = xd + sp.X.off[cn];
     a.ylb = xs;

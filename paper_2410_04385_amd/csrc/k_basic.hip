@@ -91,36 +91,6 @@ hipError_t launch_pkp(const PkpArgs &a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// W^{(d-1)}(a s + b, g) = sum_i X_d(a, i) Y_d(b, i) R_d(g, i)  (Alg. 3, first
-// line).  One thread per output entry; the sum over i is short.
-__global__ void hpcrl_last_kernel(LastArgs a) {
-  const int64_t rows = a.rx * a.sy;
-  const int64_t per = rows * a.l;
-  const int64_t total = per * a.batch;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t p = e / per;
-    const int64_t rem = e - p * per;
-    const int64_t row = rem / a.l, g = rem - row * a.l;
-    const int64_t ia = row / a.sy, ib = row - ia * a.sy;
-    const double *xp = a.x + p * a.xs + ia * a.n;
-    const double *yp = a.y + p * a.ys + ib * a.n;
-    const double *rp = a.r + p * a.rsb + g * a.n;
-    double acc = 0.0;
-    for (int64_t i = 0; i < a.n; ++i) acc += xp[i] * yp[i] * rp[i];
-    a.w[p * a.ws + rem] = acc;
-  }
-}
-
-hipError_t launch_hpcrl_last(const LastArgs &a, hipStream_t s) {
-  const int64_t total = a.rx * a.sy * a.l * a.batch;
-  if (total <= 0) return hipSuccess;
-  int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
-  hpcrl_last_kernel<<<grid, 256, 0, s>>>(a);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
 // Sandwich contraction out_{i,g} = YL_i C_g ZR_i for a chunk of GC values of
 // g per workgroup, slice i = blockIdx.x.  YL_i and ZR_i are staged once in
 // LDS, the GC matrices C_g next to them; the product is formed as
@@ -520,28 +490,41 @@ hipError_t launch_finite_check(const double *data, int64_t count, int64_t stride
 }
 
 // Reversal of a train: core k (r0 x n x r1, row-major) becomes core d-1-k
-// (r1 x n x r0) of the destination, dst(b, i, a) = src(a, i, b).  One block
-// row per core (blockIdx.y), pairs along blockIdx.z; reads are coalesced.
-__global__ void tt_reverse_kernel(RevArgs a) {
+// (r1 x n x r0) of the destination, dst(b, i, a) = src(a, i, b).  For each
+// mode index i that is a transpose of an r0 x r1 matrix: a block moves one
+// 32 x 32 tile through LDS, reading along b and writing along a, so both
+// sides are coalesced.  blockIdx.x = tile (a-tile, b-tile, i), y = core,
+// z = pair; blocks past a core's tile count return.
+__global__ __launch_bounds__(256) void tt_reverse_kernel(RevArgs a) {
+  __shared__ double tile[32][33];
   const int k = blockIdx.y, p = blockIdx.z;
   const int r0 = a.r0[k], n = a.n[k], r1 = a.r1[k];
-  const int64_t cnt = (int64_t)r0 * n * r1;
+  const int ta = (r0 + 31) / 32, tb = (r1 + 31) / 32;
+  const int64_t t = blockIdx.x;
+  if (t >= (int64_t)ta * tb * n) return;
+  const int i = (int)(t / (ta * tb));
+  const int rem = (int)(t - (int64_t)i * ta * tb);
+  const int a0 = (rem / tb) * 32, b0 = (rem - (rem / tb) * tb) * 32;
   const double *src = a.src + p * a.sstride + a.soff[k];
   double *dst = a.dst + p * a.dstride + a.doff[k];
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t ai = e / r1;
-    const int b = (int)(e - ai * r1);
-    const int64_t aa = ai / n;
-    const int i = (int)(ai - aa * n);
-    dst[((int64_t)b * n + i) * r0 + aa] = src[e];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int aa = a0 + ty + 8 * u, bb = b0 + tx;
+    if (aa < r0 && bb < r1) tile[ty + 8 * u][tx] = src[((int64_t)aa * n + i) * r1 + bb];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int bb = b0 + ty + 8 * u, aa = a0 + tx;
+    if (aa < r0 && bb < r1) dst[((int64_t)bb * n + i) * r0 + aa] = tile[tx][ty + 8 * u];
   }
 }
 
-hipError_t launch_tt_reverse(const RevArgs &a, int64_t max_core, int batch, hipStream_t s) {
+hipError_t launch_tt_reverse(const RevArgs &a, int64_t max_tiles, int batch, hipStream_t s) {
   if (batch <= 0 || a.d <= 0) return hipSuccess;
-  if (a.d > kRevMaxCores) return hipErrorInvalidValue;
-  const unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_core + 255) / 256, 1024));
-  tt_reverse_kernel<<<dim3(bx, (unsigned)a.d, (unsigned)batch), 256, 0, s>>>(a);
+  if (a.d > kRevMaxCores || max_tiles <= 0 || max_tiles > 0x7FFFFFFF) return hipErrorInvalidValue;
+  tt_reverse_kernel<<<dim3((unsigned)max_tiles, (unsigned)a.d, (unsigned)batch), 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -110,20 +110,26 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
     *ldt = rup(gc * a.SO, 16) + 1;
     return (int64_t)(*m1) * ldc + nbuf * yz + (int64_t)RI4 * (*ldt);
   };
-  // largest chunk (<= 16 columns) that keeps two blocks per CU, else one;
-  // failing that, one YL / ZR buffer (the next slice is staged after this
-  // one's products, large factor ranks)
-  int best = 0;
-  for (int pass = 0; pass < 3 && best == 0; ++pass) {
-    if (pass == 2) nbuf = 1;
-    const int64_t lim = pass == 0 ? std::min<int64_t>(budget, 9728) : budget;
+  // largest chunk (<= 16 columns) that keeps two blocks per CU, unless one
+  // block per CU takes at least twice as many columns of a chunk below four
+  // (the slices are then staged for too little work); failing both, one
+  // YL / ZR buffer (the next slice is staged after this one's products,
+  // large factor ranks)
+  auto largest = [&](int64_t lim) {
     for (int gc = (int)std::min<int64_t>(16, a.G); gc >= 1; --gc) {
       int ldt, m1;
-      if (lds_for(gc, &ldt, &m1) <= lim) {
-        best = gc;
-        break;
-      }
+      if (lds_for(gc, &ldt, &m1) <= lim) return gc;
     }
+    return 0;
+  };
+  int best = largest(std::min<int64_t>(budget, 9728));
+  if (best < 4) {
+    const int one = largest(budget);
+    if (one > 0 && (best == 0 || one >= 2 * best)) best = one;
+  }
+  if (best == 0) {
+    nbuf = 1;
+    best = largest(budget);
   }
   if (best == 0) return false;
   pl->nbuf = nbuf;

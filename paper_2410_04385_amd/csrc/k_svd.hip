@@ -346,6 +346,10 @@ __device__ __forceinline__ double rsq_nr(double x) {
 // Rotation of the pair (x, y) (x plays "p"); returns whether it rotated.
 // The rotation is c = 1/sqrt(1+t^2), s = c t, so c^2 + s^2 = 1 to rounding
 // whatever the accuracy of t (t only steers convergence).
+// Early stop of the block Jacobi: a sweep whose largest squared cosine
+// between two columns is at most this leaves them orthogonal to rounding.
+constexpr double kJacobiStop2 = 1e-16;
+
 template <int RPT>
 __device__ __forceinline__ bool jrot(double (&x)[RPT], double (&y)[RPT], double al, double be, double ga, double thr) {
   if (ga == 0.0 || !(ga * ga > (thr * thr) * (al * be))) return false;
@@ -376,7 +380,7 @@ __global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
   __shared__ double sig[kSvdMaxN];
   __shared__ double sigs[kSvdMaxN];
   __shared__ int perm[kSvdMaxN];
-  __shared__ int s_rot;
+  __shared__ int s_rot, s_big;
   __shared__ int s_rho;
   const int kr = a.kr, nc = a.nc;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -401,9 +405,15 @@ __global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
       bv[s] = (act && r < kr && cb < nc) ? R[r * nc + cb] : 0.0;
     }
   }
+  // A sweep in which no pair had cos^2 above kJacobiStop2 rotated by
+  // angles whose squares are below rounding: by the quadratic convergence of
+  // cyclic Jacobi the next sweep would find nothing, so it is not run.
   for (int sweep = 0; sweep < 60; ++sweep) {
-    if (tid == 0) s_rot = 0;
-    int rot = 0;
+    if (tid == 0) {
+      s_rot = 0;
+      s_big = 0;
+    }
+    int rot = 0, big = 0;
     if (act) {
       // pairs inside each block
       for (int x = 1; x < 8; ++x) {
@@ -432,6 +442,7 @@ __global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
         a2 = g8sum(a2);
         b2 = g8sum(b2);
         g2 = g8sum(g2);
+        big |= (g1 * g1 > kJacobiStop2 * (a1 * b1)) | (g2 * g2 > kJacobiStop2 * (a2 * b2));
         // each lane group updates only its own column of the pair
         if (isp) {
           rot |= jrot<RPT>(tv, pt, a1, b1, g1, thr);
@@ -455,6 +466,7 @@ __global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
           al = g8sum(al);
           be = g8sum(be);
           ga = g8sum(ga);
+          big |= (ga * ga > kJacobiStop2 * (al * be));
           rot |= jrot<RPT>(tv, bv, al, be, ga, thr);
           // the bot columns move on to the next lane group
 #pragma unroll
@@ -484,8 +496,9 @@ __global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
       __syncthreads();
     }
     if (rot) s_rot = 1;
+    if (big) s_big = 1;
     __syncthreads();
-    if (s_rot == 0) break;
+    if (s_rot == 0 || s_big == 0) break;
     __syncthreads();
   }
   // final columns into the slots (column index 8 * slot + g), norms, order
