@@ -84,8 +84,8 @@ def _site_group(label, batch):
         flops = 2.0 * n * G * (RI * SI * SO + RA * RI * SO) * batch
         nbytes = 8.0 * (G * RI * SI + n * RA * RI + n * SI * SO + n * G * RA * SO) * batch
         kern = m.group(8)
-        # the sandwich_ks / sandwich_mfma kernels run on the matrix cores
-        unit = "mfma" if ("_ks_" in kern or "_mfma_" in kern) else "alu"
+        # the sandwich_ks / sandwich_mfma / sandwich_slice kernels run on the matrix cores
+        unit = "mfma" if ("_ks_" in kern or "_mfma_" in kern or "_slice_" in kern) else "alu"
         return kern, unit, flops, nbytes
     m = _GEMM.match(label)
     if m:
