@@ -26,6 +26,26 @@ namespace hatt {
 // Rotation threshold on |cos| of a column pair's angle (see above).
 __device__ __forceinline__ double jacobi_tau(int kr) { return fmax(1e-15, (double)kr * 2.220446049250313e-16); }
 
+// Early stop of every Jacobi kernel: a sweep whose largest squared cosine
+// between two columns is at most this rotated by angles whose squares are
+// below rounding, so by the quadratic convergence of cyclic Jacobi the
+// columns are orthogonal to rounding after it.  Without it, columns that are
+// pure rounding noise (rank-deficient R) kept passing the rotation test on
+// the noise of their own dot products and ran to the sweep limit.
+constexpr double kJacobiStop2 = 1e-16;
+
+// A column whose squared norm is at most this is zero to every Jacobi kernel:
+// it is neither rotated nor counted for the early stop, and its singular
+// value is reported as 0 (zero U column, zero S V^T row).  Such columns are
+// what rotation leaves of the null space of a rank-deficient R; their
+// entries square into the subnormal range, where the dot products lose all
+// relative accuracy and the pair would rotate on its own rounding until the
+// sweep limit.  Entries of a column at the threshold are still around 1e-141,
+// so products with them stay well clear of underflow.
+constexpr double kJacobiTiny2 = 1e-280;
+__device__ __forceinline__ bool jacobi_live(double al, double be) { return al > kJacobiTiny2 && be > kJacobiTiny2; }
+__device__ __forceinline__ double jacobi_sigma(double s2) { return s2 > kJacobiTiny2 ? sqrt(s2) : 0.0; }
+
 __device__ __forceinline__ int rr_partner(int c, int t, int np) {
   // round t: position 0 holds index 0, position j >= 1 holds 1 + (j - 1 + t) mod (np - 1);
   // positions k and np - 1 - k are paired
@@ -97,7 +117,7 @@ __global__ __launch_bounds__(64) void svd_wave_kernel(SvdArgs a) {
   const int np = nc + (nc & 1);
   int buf = 0;
   for (int sweep = 0; sweep < 60; ++sweep) {
-    int rot = 0;
+    int rot = 0, big = 0;
     for (int t = 0; t < np - 1; ++t) {
       double *xb = buf ? xb1 : xb0;
       buf ^= 1;
@@ -118,7 +138,9 @@ __global__ __launch_bounds__(64) void svd_wave_kernel(SvdArgs a) {
         // roles: the lower index is "p"
         const bool isp = lane < q;
         const double ap = isp ? al : be, aq = isp ? be : al;
-        if (ga != 0.0 && fabs(ga) > jacobi_tau(kr) * sqrt(ap * aq)) {
+        const bool live = jacobi_live(ap, aq);
+        big |= live && (ga * ga > kJacobiStop2 * (ap * aq));
+        if (live && ga != 0.0 && fabs(ga) > jacobi_tau(kr) * sqrt(ap * aq)) {
           const double zeta = (aq - ap) / (2.0 * ga);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -133,7 +155,8 @@ __global__ __launch_bounds__(64) void svd_wave_kernel(SvdArgs a) {
         }
       }
     }
-    if (!__syncthreads_or(rot)) break;
+    const int any_big = __syncthreads_or(big);
+    if (!__syncthreads_or(rot) || !any_big) break;
   }
   // final columns to xb0, R to xb1, column norms
   double s2 = 0.0;
@@ -143,7 +166,7 @@ __global__ __launch_bounds__(64) void svd_wave_kernel(SvdArgs a) {
     xb0[i * 64 + lane] = col[i];
   }
   for (int e = lane; e < kr * nc; e += 64) xb1[e] = R[e];
-  sig[lane] = (lane < nc) ? sqrt(s2) : -1.0;
+  sig[lane] = (lane < nc) ? jacobi_sigma(s2) : -1.0;
   __syncthreads();
   if (lane < nc) {
     int rk = 0;
@@ -208,7 +231,7 @@ __global__ __launch_bounds__(kBlockThreads) void svd_block_kernel(SvdArgs a, int
   __shared__ double sig[kSvdMaxN];
   __shared__ double sigs[kSvdMaxN];
   __shared__ int perm[kSvdMaxN];
-  __shared__ int s_rot;
+  __shared__ int s_rot, s_big;
   __shared__ int s_rho;
   const int kr = a.kr, nc = a.nc;
   const int tid = threadIdx.x;
@@ -224,9 +247,12 @@ __global__ __launch_bounds__(kBlockThreads) void svd_block_kernel(SvdArgs a, int
   const double thr = jacobi_tau(kr);
   __syncthreads();
   for (int sweep = 0; sweep < 60; ++sweep) {
-    if (tid == 0) s_rot = 0;
+    if (tid == 0) {
+      s_rot = 0;
+      s_big = 0;
+    }
     __syncthreads();
-    int myrot = 0;
+    int myrot = 0, mybig = 0;
     for (int t = 0; t < np - 1; ++t) {
       if (grp < npairs) {
         const int pa = grp, pb = np - 1 - grp;
@@ -247,7 +273,9 @@ __global__ __launch_bounds__(kBlockThreads) void svd_block_kernel(SvdArgs a, int
             be += __shfl_xor(be, off, tpg);
             ga += __shfl_xor(ga, off, tpg);
           }
-          if (ga != 0.0 && fabs(ga) > thr * sqrt(al * be)) {
+          const bool live = jacobi_live(al, be);
+          mybig |= live && (ga * ga > kJacobiStop2 * (al * be));
+          if (live && ga != 0.0 && fabs(ga) > thr * sqrt(al * be)) {
             const double zeta = (be - al) / (2.0 * ga);
             const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -263,14 +291,15 @@ __global__ __launch_bounds__(kBlockThreads) void svd_block_kernel(SvdArgs a, int
       __syncthreads();
     }
     if (myrot) s_rot = 1;
+    if (mybig) s_big = 1;
     __syncthreads();
-    if (s_rot == 0) break;
+    if (s_rot == 0 || s_big == 0) break;
     __syncthreads();
   }
   for (int c = tid; c < nc; c += kBlockThreads) {
     double s2 = 0.0;
     for (int r = 0; r < kr; ++r) s2 += A[c * kr + r] * A[c * kr + r];
-    sig[c] = sqrt(s2);
+    sig[c] = jacobi_sigma(s2);
   }
   __syncthreads();
   for (int c = tid; c < nc; c += kBlockThreads) {
@@ -346,13 +375,9 @@ __device__ __forceinline__ double rsq_nr(double x) {
 // Rotation of the pair (x, y) (x plays "p"); returns whether it rotated.
 // The rotation is c = 1/sqrt(1+t^2), s = c t, so c^2 + s^2 = 1 to rounding
 // whatever the accuracy of t (t only steers convergence).
-// Early stop of the block Jacobi: a sweep whose largest squared cosine
-// between two columns is at most this leaves them orthogonal to rounding.
-constexpr double kJacobiStop2 = 1e-16;
-
 template <int RPT>
 __device__ __forceinline__ bool jrot(double (&x)[RPT], double (&y)[RPT], double al, double be, double ga, double thr) {
-  if (ga == 0.0 || !(ga * ga > (thr * thr) * (al * be))) return false;
+  if (ga == 0.0 || !jacobi_live(al, be) || !(ga * ga > (thr * thr) * (al * be))) return false;
   const double zeta = (be - al) * (0.5 * rcp_nr(ga));
   double tt;
   if (fabs(zeta) < 1e150) {
@@ -442,7 +467,8 @@ __global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
         a2 = g8sum(a2);
         b2 = g8sum(b2);
         g2 = g8sum(g2);
-        big |= (g1 * g1 > kJacobiStop2 * (a1 * b1)) | (g2 * g2 > kJacobiStop2 * (a2 * b2));
+        big |= (jacobi_live(a1, b1) && g1 * g1 > kJacobiStop2 * (a1 * b1)) |
+               (jacobi_live(a2, b2) && g2 * g2 > kJacobiStop2 * (a2 * b2));
         // each lane group updates only its own column of the pair
         if (isp) {
           rot |= jrot<RPT>(tv, pt, a1, b1, g1, thr);
@@ -466,7 +492,7 @@ __global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
           al = g8sum(al);
           be = g8sum(be);
           ga = g8sum(ga);
-          big |= (ga * ga > kJacobiStop2 * (al * be));
+          big |= jacobi_live(al, be) && (ga * ga > kJacobiStop2 * (al * be));
           rot |= jrot<RPT>(tv, bv, al, be, ga, thr);
           // the bot columns move on to the next lane group
 #pragma unroll
@@ -518,7 +544,7 @@ __global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
   for (int c = tid; c < ncp; c += 512) {
     double s2 = 0.0;
     for (int r = 0; r < kr; ++r) s2 += A[c * kr + r] * A[c * kr + r];
-    sig[c] = sqrt(s2);
+    sig[c] = jacobi_sigma(s2);
   }
   __syncthreads();
   for (int c = tid; c < ncp; c += 512) {
@@ -657,6 +683,7 @@ __global__ __launch_bounds__(kBigRoundThreads) void svd_big_round_kernel(double 
   while (tpg > 1 && tpg * npairs > kBigRoundThreads) tpg >>= 1;
   const double thr = jacobi_tau(kr);
   const int grp = tid / tpg, gl = tid % tpg;
+  int mybig = 0;
   __syncthreads();
   // one cyclic sweep over the pairs of the two blocks per round: every
   // outer sweep is then at least one full cyclic Jacobi sweep over all
@@ -685,7 +712,9 @@ __global__ __launch_bounds__(kBigRoundThreads) void svd_big_round_kernel(double 
             be += __shfl_xor(be, off, tpg);
             ga += __shfl_xor(ga, off, tpg);
           }
-          if (ga != 0.0 && fabs(ga) > thr * sqrt(al * be)) {
+          const bool live = jacobi_live(al, be);
+          if (live && ga * ga > kJacobiStop2 * (al * be)) mybig = 1;
+          if (live && ga != 0.0 && fabs(ga) > thr * sqrt(al * be)) {
             const double zeta = (be - al) / (2.0 * ga);
             const double t2 = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             const double cs = 1.0 / sqrt(1.0 + t2 * t2), sn = cs * t2;
@@ -711,7 +740,10 @@ __global__ __launch_bounds__(kBigRoundThreads) void svd_big_round_kernel(double 
     const int gc = (c < wa) ? a0 + c : b0 + (c - wa);
     base[(int64_t)gc * kr + r] = A[e];
   }
+  // bit 0: this round rotated; bit 1: some pair had a squared cosine above
+  // the early-stop level
   if (tid == 0 && s_any) atomicOr(flags + 2 * p, 1);
+  if (mybig) atomicOr(flags + 2 * p, 2);
 }
 
 hipError_t launch_svd_big_round(double *acol, int64_t acs, int kr, int nc, int bw, int nb, int t, int *flags,
@@ -731,7 +763,7 @@ hipError_t launch_svd_big_round(double *acol, int64_t acs, int kr, int nc, int b
 __global__ void svd_big_sweep_end_kernel(int *flags, int batch) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < batch) {
-    if (flags[2 * p] == 0) flags[2 * p + 1] = 1;
+    if (flags[2 * p] == 0 || (flags[2 * p] & 2) == 0) flags[2 * p + 1] = 1;
     flags[2 * p] = 0;
   }
 }
@@ -758,7 +790,7 @@ __global__ __launch_bounds__(256) void svd_big_finish_kernel(SvdArgs a, const do
     double s2 = 0.0;
     for (int r = lane; r < kr; r += 64) s2 += col[r] * col[r];
     for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
-    if (lane == 0) sig[c] = sqrt(s2);
+    if (lane == 0) sig[c] = jacobi_sigma(s2);
   }
   __syncthreads();
   for (int c = tid; c < nc; c += 256) {
