@@ -14,6 +14,9 @@ Everything here is plain, slow and written to be read against the paper
 * ``randorth``  PartialContractionRL (eq. rtlpc) and RandOrth (Alg. 2).
 * ``hatt``      HPCRL (Alg. 3; HaTT-1 and HaTT-2 splits, eqs. HPCRL--1/--2)
                 and HaTT (Alg. 4) without forming PKP cores.
+* ``hatt3``     the same for three factors, x (.) y (.) w, by three-mode
+                products (the Kronecker-times-vector identity taken over three
+                factors; an extension the paper does not spell out).
 * ``plan``      the sketch-width clamps applied before a recompression.
 * ``philox``    the counter-based generator of the seeded Gaussian sketch.
 * ``flops``     the paper's operation counts (Sec. 4, Table 4.1).
@@ -32,4 +35,4 @@ Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 inequalities); none is "parity unpinned".
 """
 
-from . import tt, rounding, randorth, hatt, plan, philox, flops, adapt, rankpred, power  # noqa: F401
+from . import tt, rounding, randorth, hatt, hatt3, plan, philox, flops, adapt, rankpred, power  # noqa: F401

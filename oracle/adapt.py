@@ -16,7 +16,9 @@ small enough, l should be increased (Sec. 5.1.1).  The rule implemented here
   retry; give up after ``max_attempts``.
 
 For a batch of pairs the widths are common to all pairs and a bond fails if
-it fails for any pair.
+it fails for any pair.  A triple (x, y, w) in place of a pair runs the
+three-factor HaTT (hatt3) under the same rule, with r_k s_k t_k as the
+product rank in the clamps and max(r_k, s_k, t_k) + p as the start.
 """
 
 from __future__ import annotations
@@ -28,6 +30,7 @@ import numpy as np
 
 from . import philox, plan, rounding, tt
 from .hatt import hatt
+from .hatt3 import hatt3
 
 BIG = 1 << 40
 
@@ -61,15 +64,23 @@ def hatt_adaptive(pairs, tol: float, seed: int, p: int = 8, max_attempts: int = 
     keyed by seed + a * seed_step; ``ell0`` replaces the starting widths
     (a predicted start).  Returns (outputs, widths used, attempts,
     converged)."""
-    y0, z0 = pairs[0]
-    n, rx, ry = tt.modes(y0), tt.ranks(y0), tt.ranks(z0)
+    ops0 = pairs[0]
+    n = tt.modes(ops0[0])
+    rk = [tt.ranks(o) for o in ops0]
+    rx = rk[0]
+    ry = [int(np.prod([r[k] for r in rk[1:]])) for k in range(len(rx))]
     cap = plan.clamp_ell(n, rx, ry, BIG)
-    ell = initial_widths(n, rx, ry, p) if ell0 is None else list(ell0)
+    if ell0 is None:
+        req = [1] + [max(r[k] for r in rk) + p for k in range(1, len(n))] + [1]
+        ell = plan.clamp_ell(n, rx, ry, req)
+    else:
+        ell = list(ell0)
     outs = None
     for attempt in range(max_attempts):
         l = plan.clamp_ell(n, rx, ry, ell)
         R = philox.sketch(seed + attempt * seed_step, n, l)
-        outs = [rounding.tt_round_left_orth(hatt(y, z, R, variant, ep), tol=tol) for (y, z) in pairs]
+        outs = [rounding.tt_round_left_orth(hatt(ops[0], ops[1], R, variant, ep) if len(ops) == 2
+                                            else hatt3(ops[0], ops[1], ops[2], R), tol=tol) for ops in pairs]
         bad = failing_bonds([tt.ranks(o) for o in outs], l, cap, p)
         if not bad:
             return outs, l, attempt + 1, True
