@@ -214,6 +214,39 @@ HATT_API hatt_status hatt_recompress_adaptive(const hatt_tt *x, const hatt_tt *y
                                               size_t ws_bytes, void *stream);
 
 /*
+ * Three factors: recompress x (.) y (.) w in one pass, without forming the
+ * three-way PKP cores (rank r_k s_k t_k).  The identity that turns the PKP
+ * products into two-sided products (eq. kronecker_product_times_vec, used by
+ * eqs. WLWR and M*core0) is taken over three factors, so HPCRL (Alg. 3,
+ * HaTT-1 split) and the sweep (Alg. 4) apply X_k(i), Y_k(i) and W_k(i) as a
+ * three-mode product; the result equals RandOrth (Alg. 2) on the explicit
+ * three-way PKP train with the same sketch.  The paper forms its cubic
+ * nonlinearity as successive products (Sec. 5, Example 4); this form skips
+ * the intermediate recompression.  Output, ranks and truncation are those of
+ * hatt_recompress (three-way PKP index order: x's index slowest, w's fastest).
+ * Limits: one triple per call (every batch 1), opts->variant 1,
+ * opts->precision 0 (HATT_EUNSUPPORTED otherwise).  Widths are clamped with
+ * r_k s_k t_k in place of r_k s_k.  x, y and w must have the same d and mode
+ * sizes.
+ * hatt_plan3 / hatt_recompress3: as hatt_plan / hatt_recompress.
+ * hatt_adaptive_plan3 / hatt_recompress3_adaptive: the tolerance-driven rule
+ * above with start widths max(r_k, s_k, t_k) + p; the finiteness check covers
+ * all three factors.
+ */
+HATT_API hatt_status hatt_plan3(const hatt_tt *x, const hatt_tt *y, const hatt_tt *w, const hatt_opts *opts,
+                                int64_t *ell_out, size_t *ws_bytes, int64_t *out_elems);
+HATT_API hatt_status hatt_recompress3(const hatt_tt *x, const hatt_tt *y, const hatt_tt *w, const hatt_tt *sketch,
+                                      const hatt_opts *opts, double *out, int64_t out_stride, int64_t *out_rank,
+                                      void *ws, size_t ws_bytes, void *stream);
+HATT_API hatt_status hatt_adaptive_plan3(const hatt_tt *x, const hatt_tt *y, const hatt_tt *w,
+                                         const hatt_adapt_opts *opts, int64_t *cap_out, size_t *ws_bytes,
+                                         int64_t *out_elems);
+HATT_API hatt_status hatt_recompress3_adaptive(const hatt_tt *x, const hatt_tt *y, const hatt_tt *w,
+                                               const hatt_adapt_opts *opts, double *out, int64_t out_stride,
+                                               int64_t *out_rank, int64_t *ell_out, int32_t *attempts_out,
+                                               void *ws, size_t ws_bytes, void *stream);
+
+/*
  * tt_hadamard_explicit -- the PKP cores of x (.) y (Sec. 2.2):
  * A_k(a s + b, i, a' s' + b') = X_k(a, i, a') Y_k(b, i, b'), ranks r_k s_k.
  * out: device, batch trains with ranks r_k s_k, stride out_stride

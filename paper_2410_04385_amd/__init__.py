@@ -30,6 +30,9 @@ from .api import (  # noqa: F401
     rankpred_widths,
     recompress,
     recompress_adaptive,
+    plan3,
+    recompress3,
+    recompress3_adaptive,
     recompress_batched,
     recompress_noalloc,
     randorth,

@@ -23,6 +23,7 @@ EXPORTED = [
     "hatt_profile_report", "hatt_batched_plan", "hatt_recompress_batched",
     "hatt_rankpred_features", "hatt_rankpred_fit_stats", "hatt_rankpred_forward", "hatt_rankpred_ws_bytes",
     "hatt_rankpred_grad", "hatt_rankpred_train_step", "hatt_rankpred_widths", "hatt_rankpred_labels",
+    "hatt_plan3", "hatt_recompress3", "hatt_adaptive_plan3", "hatt_recompress3_adaptive",
 ]
 RANKPRED_NIN, RANKPRED_NTHETA, RANKPRED_NSTATS = 21, 19586, 46
 PROFILE_CLASSES = 8
@@ -100,6 +101,11 @@ def lib() -> ctypes.CDLL:
     L.hatt_adaptive_plan.argtypes = [ttp, ttp, aop, i64p, szp, i64p]
     L.hatt_recompress_adaptive.argtypes = [ttp, ttp, aop, vp, ctypes.c_int64, vp, i64p,
                                            ctypes.POINTER(ctypes.c_int32), vp, ctypes.c_size_t, vp]
+    L.hatt_plan3.argtypes = [ttp, ttp, ttp, optp, i64p, szp, i64p]
+    L.hatt_recompress3.argtypes = [ttp, ttp, ttp, ttp, optp, vp, ctypes.c_int64, vp, vp, ctypes.c_size_t, vp]
+    L.hatt_adaptive_plan3.argtypes = [ttp, ttp, ttp, aop, i64p, szp, i64p]
+    L.hatt_recompress3_adaptive.argtypes = [ttp, ttp, ttp, aop, vp, ctypes.c_int64, vp, i64p,
+                                            ctypes.POINTER(ctypes.c_int32), vp, ctypes.c_size_t, vp]
     L.tt_hadamard_explicit.argtypes = [ttp, ttp, vp, ctypes.c_int64, vp]
     L.tt_randorth_plan.argtypes = [ttp, ctypes.c_int64, i64p, i64p, szp, i64p]
     L.tt_randorth.argtypes = [ttp, ttp, ctypes.c_int64, i64p, ctypes.c_uint64, ctypes.c_int64, ctypes.c_double, vp,

@@ -307,6 +307,85 @@ def recompress_adaptive(x: TT, y: TT, tol: float, *, seed: int = 0, oversample: 
     return Result(out, ranks), list(ell), int(att.value)
 
 
+def plan3(x: TT, y: TT, w: TT, ell, max_rank: int = 0, tol: float = 0.0, seed: int = 0):
+    """Widths, workspace and output size of recompress3."""
+    xv, kx = x.view()
+    yv, ky = y.view()
+    wv, kw = w.view()
+    o, ka = _opts(ell, max_rank, tol, seed, 1, 0.0, x.d)
+    ell_out = (ctypes.c_int64 * (x.d + 1))()
+    ws = ctypes.c_size_t(0)
+    oe = ctypes.c_int64(0)
+    check("hatt_plan3", lib().hatt_plan3(ctypes.byref(xv), ctypes.byref(yv), ctypes.byref(wv), ctypes.byref(o),
+                                         ell_out, ctypes.byref(ws), ctypes.byref(oe)))
+    return {"ell": list(ell_out), "ws_bytes": int(ws.value), "out_elems": int(oe.value)}
+
+
+def recompress3(x: TT, y: TT, w: TT, ell, *, max_rank: int = 0, tol: float = 0.0, seed: int = 0,
+                sketch: Optional[TT] = None, workspace: Optional[torch.Tensor] = None, stream=None) -> Result:
+    """HaTT of the three-factor product x (.) y (.) w in one pass (three-mode
+    products in place of the three-way PKP cores), optionally truncated to
+    ``max_rank`` / ``tol``; one triple (batch 1), FP64, HaTT-1."""
+    p = plan3(x, y, w, ell, max_rank, tol, seed)
+    dev = x.data.device
+    out = TT.empty(x.n, p["ell"], 1, device=dev)
+    ranks = torch.empty((1, x.d + 1), dtype=torch.int64, device=dev)
+    if workspace is None or workspace.numel() < p["ws_bytes"]:
+        workspace = torch.empty(max(p["ws_bytes"], 1), dtype=torch.uint8, device=dev)
+    xv, kx = x.view()
+    yv, ky = y.view()
+    wv, kw = w.view()
+    o, ka = _opts(ell, max_rank, tol, seed, 1, 0.0, x.d)
+    sk_ptr = None
+    keep = None
+    if sketch is not None:
+        sv, keep = sketch.view()
+        sk_ptr = ctypes.byref(sv)
+    check("hatt_recompress3", lib().hatt_recompress3(
+        ctypes.byref(xv), ctypes.byref(yv), ctypes.byref(wv), sk_ptr, ctypes.byref(o),
+        ctypes.c_void_p(out.data.data_ptr()), out.stride, ctypes.c_void_p(ranks.data_ptr()),
+        ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr(stream)))
+    return Result(out, ranks)
+
+
+def recompress3_adaptive(x: TT, y: TT, w: TT, tol: float, *, seed: int = 0, oversample: int = 8,
+                         max_attempts: int = 8, ell_init: Optional[Sequence[int]] = None,
+                         workspace: Optional[torch.Tensor] = None, stream=None):
+    """Tolerance-driven three-factor HaTT (the rule of recompress_adaptive,
+    starting from max(r_k, s_k, t_k) + oversample).  Returns (Result, widths
+    used, attempts)."""
+    xv, kx = x.view()
+    yv, ky = y.view()
+    wv, kw = w.view()
+    init = None
+    if ell_init is not None:
+        if len(ell_init) != x.d + 1:
+            raise ValueError("ell_init needs d+1 entries")
+        init = i64_array(ell_init)
+    o = HattAdaptOpts(float(tol), int(seed) & 0xFFFFFFFFFFFFFFFF, int(oversample), int(max_attempts), 1, 0.0,
+                      init, 0)
+    cap = (ctypes.c_int64 * (x.d + 1))()
+    ws = ctypes.c_size_t(0)
+    oe = ctypes.c_int64(0)
+    check("hatt_adaptive_plan3", lib().hatt_adaptive_plan3(ctypes.byref(xv), ctypes.byref(yv), ctypes.byref(wv),
+                                                           ctypes.byref(o), cap, ctypes.byref(ws),
+                                                           ctypes.byref(oe)))
+    dev = x.data.device
+    slot = int(oe.value)
+    data = torch.zeros(slot, dtype=torch.float64, device=dev)
+    ranks = torch.empty((1, x.d + 1), dtype=torch.int64, device=dev)
+    if workspace is None or workspace.numel() < ws.value:
+        workspace = torch.empty(max(ws.value, 1), dtype=torch.uint8, device=dev)
+    ell = (ctypes.c_int64 * (x.d + 1))()
+    att = ctypes.c_int32(0)
+    check("hatt_recompress3_adaptive", lib().hatt_recompress3_adaptive(
+        ctypes.byref(xv), ctypes.byref(yv), ctypes.byref(wv), ctypes.byref(o), ctypes.c_void_p(data.data_ptr()),
+        slot, ctypes.c_void_p(ranks.data_ptr()), ell, ctypes.byref(att), ctypes.c_void_p(workspace.data_ptr()),
+        workspace.numel(), _stream_ptr(stream)))
+    out = TT(data, x.n, list(ell), 1, stride=slot)
+    return Result(out, ranks), list(ell), int(att.value)
+
+
 def hadamard_explicit(x: TT, y: TT, out: Optional[TT] = None, stream=None) -> TT:
     """Explicit PKP cores of x (.) y (ranks r_k s_k)."""
     rr = [a * b for a, b in zip(x.ranks, y.ranks)]

@@ -1116,6 +1116,9 @@ hatt_status truncate_left_orth(bool run, const std::vector<int64_t> &n, const st
 // ---------------------------------------------------------------------------
 struct HattSpec {
   Shape X, Y;
+  Shape W;                        // third factor (three = true)
+  bool three = false;
+  std::vector<int64_t> ryw;       // rank of the trailing factors per bond: s_k, or s_k t_k
   std::vector<int64_t> ell;
   std::vector<int64_t> bond_cap;  // [d+1] truncation cap per bond (0: none)
   const double *sketch;  // explicit sketch data or nullptr
@@ -1126,7 +1129,10 @@ struct HattSpec {
   int64_t *orank;
 };
 
+hatt_status hatt3_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStream_t st);
+
 hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStream_t st) {
+  if (sp.three) return hatt3_body(run, sp, ws, gc, st);
   const int d = sp.X.d, P = sp.X.batch;
   const auto &n = sp.X.n, &r = sp.X.r, &s = sp.Y.r, &l = sp.ell;
   std::vector<int64_t> ooff, skoff;
@@ -1438,6 +1444,195 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
   return HATT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Three factors, z = x (.) y (.) w: one triple per call, FP64, HaTT-1.  The
+// Kronecker-times-vector identity behind eq. WLWR and eq. M*core0, taken
+// over three factors, turns HPCRL's recursion and the sweep's core update
+// into three-mode products.  Each mode product is one GEMM batched over the
+// mode index i that contracts the tensor's leading rank index and appends
+// the new index last (a cyclic rotation of the index order), so the
+// products chain without a permutation pass:
+//   HPCRL, bond k+1 -> k:  V_i = W^{(k+1)} R_k(i)^T, then
+//     V[i][a'][b'][c'][g] -> T1[i][b'][c'][g][a] -> T2[i][c'][g][a][b]
+//     -> W^{(k)}[g][a][b][c]  (the last product also sums over i: K = (i, c'))
+//   core update, M = Q^T X^{(k)} stored as [a][b][c][g]:
+//     M -> U1[i][b][c][g][a'] -> U2[i][c][g][a'][b'] -> X^{(k+1)}[i][g][a'][b'][c']
+// W^{(k)} is column-major (rows (a, b, c), a slowest).  The sketched frame
+// X^{(k)} W^{(k)} is a GEMM per i whose rows g land on rows (g, i) of the
+// frame (the output core's order), and M = sum_i Q_i^T X_i reduces per-i
+// products in a fixed order.
+hatt_status hatt3_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStream_t st) {
+  const int d = sp.X.d;
+  const auto &n = sp.X.n, &r = sp.X.r, &s = sp.Y.r, &t = sp.W.r, &l = sp.ell;
+  std::vector<int64_t> ooff, skoff;
+  int64_t otot, sktot;
+  make_offsets(n, l, &ooff, &otot);
+  make_offsets(n, l, &skoff, &sktot);
+  const double *xd = sp.X.data, *yd = sp.Y.data, *wd = sp.W.data;
+  std::vector<int64_t> rst(d + 1);
+  for (int b = 0; b <= d; ++b) rst[b] = r[b] * s[b] * t[b];
+  std::vector<int64_t> woff(d + 1, 0);
+  int64_t wtot = 0;
+  for (int b = 1; b < d; ++b) {
+    woff[b] = wtot;
+    wtot += rst[b] * l[b];
+  }
+  int64_t vsz = 1, t1sz = 1, t2sz = 1, u1sz = 1, u2sz = 1;
+  for (int c = 1; c <= d - 2; ++c) {
+    vsz = std::max(vsz, n[c] * rst[c + 1] * l[c]);
+    t1sz = std::max(t1sz, n[c] * s[c + 1] * t[c + 1] * l[c] * r[c]);
+    t2sz = std::max(t2sz, n[c] * t[c + 1] * l[c] * r[c] * s[c]);
+    u1sz = std::max(u1sz, n[c] * s[c] * t[c] * l[c] * r[c + 1]);
+    u2sz = std::max(u2sz, n[c] * t[c] * l[c] * r[c + 1] * s[c + 1]);
+  }
+  int64_t xsz = 1, ysz = 1, msz = 1, mpsz = 1, qrws = 1;
+  std::vector<QrOp> qp(d);
+  for (int c = 0; c < d - 1; ++c) {
+    xsz = std::max(xsz, n[c] * l[c] * rst[c + 1]);
+    ysz = std::max(ysz, l[c] * n[c] * l[c + 1]);
+    msz = std::max(msz, l[c + 1] * rst[c + 1]);
+    if (n[c] > 1) mpsz = std::max(mpsz, n[c] * l[c + 1] * rst[c + 1]);
+    if (!qr_prepare(l[c] * n[c], l[c + 1], &qp[c]))
+      return fail(HATT_EUNSUPPORTED, "HaTT (three factors): the QR of a " + std::to_string(l[c] * n[c]) + " x " +
+                                         std::to_string(l[c + 1]) + " sketched frame is not supported");
+    qrws = std::max(qrws, qp[c].ws_doubles);
+  }
+  const int64_t ptsz = std::max<int64_t>(r[d - 1] * s[d - 1] * n[d - 1], r[1] * s[1] * n[0]);
+  double *sk = nullptr;
+  if (sp.sketch) {
+    sk = (double *)sp.sketch;
+  } else {
+    sk = ws.d(sktot);
+  }
+  double *W = ws.d(std::max<int64_t>(wtot, 1));
+  double *Vb = ws.d(vsz), *T1b = ws.d(t1sz), *T2b = ws.d(t2sz);
+  double *U1 = ws.d(u1sz), *U2 = ws.d(u2sz);
+  double *Hlast = ws.d(rst[d - 1] * n[d - 1]);
+  double *ptmp = ws.d(ptsz);
+  double *Xc = ws.d(xsz), *Yb = ws.d(ysz), *Mb = ws.d(msz), *Mp = ws.d(mpsz);
+  double *wqr = ws.d(qrws);
+  if (d == 1) {
+    LAUNCH(launch_fill_i64(sp.orank, 2, 1, st));
+    PkpArgs p1{xd, yd, ptmp, 1, 1, 1, 1, n[0], 0, 0, 0, 1};
+    LAUNCH(launch_pkp(p1, st));
+    PkpArgs p2{ptmp, wd, sp.out, 1, 1, 1, 1, n[0], 0, 0, 0, 1};
+    LAUNCH(launch_pkp(p2, st));
+    return HATT_OK;
+  }
+  if (!sp.sketch) {
+    for (int k = 0; k < d; ++k) {
+      const int64_t cnt = l[k] * n[k] * l[k + 1];
+      LAUNCH(launch_sketch_fill(sp.o.seed, k, cnt, 1.0 / sqrt((double)cnt), sk + skoff[k], st));
+    }
+  }
+  hatt_status stt;
+  // ---- HPCRL (Alg. 3), HaTT-1 split
+  {
+    // W^{(d-1)}: rows (a, b, c) of the right-rank-1 last cores times the
+    // sketch's last core
+    ClassScope cs(P_LAST);
+    const int c = d - 1;
+    PkpArgs p1{xd + sp.X.off[c], yd + sp.Y.off[c], ptmp, r[c], 1, s[c], 1, n[c], 0, 0, 0, 1};
+    LAUNCH(launch_pkp(p1, st));
+    PkpArgs p2{ptmp, wd + sp.W.off[c], Hlast, r[c] * s[c], 1, t[c], 1, n[c], 0, 0, 0, 1};
+    LAUNCH(launch_pkp(p2, st));
+    stt = gemm(run, gc, CMat{Hlast, n[c], 1, 0}, CMat{sk + skoff[c], 1, n[c], 0}, Mat{W + woff[c], 1, rst[c], 0},
+               rst[c], l[c], n[c], 1.0, 0.0, 1, st, true);
+    if (stt != HATT_OK) return stt;
+  }
+  for (int c = d - 2; c >= 1; --c) {
+    const int64_t nn = n[c], l0 = l[c], l1 = l[c + 1];
+    const int64_t r0 = r[c], s0 = s[c], t0 = t[c], r1 = r[c + 1], s1 = s[c + 1], t1 = t[c + 1];
+    const int64_t K1 = rst[c + 1];
+    // V_i = W^{(k+1)} R_k(i)^T
+    stt = gemm(run, gc, CMat{W + woff[c + 1], 1, K1, 0}, CMat{sk + skoff[c], 1, nn * l1, l1},
+               Mat{Vb, l0, 1, K1 * l0}, K1, l0, l1, 1.0, 0.0, (int)nn, st, true);
+    if (stt != HATT_OK) return stt;
+    // T1_i[(b' c' g), a] = sum_a' V_i[a', (b' c' g)] X_k(a, i, a')
+    stt = gemm(run, gc, CMat{Vb, 1, s1 * t1 * l0, K1 * l0}, CMat{xd + sp.X.off[c], 1, nn * r1, r1},
+               Mat{T1b, r0, 1, s1 * t1 * l0 * r0}, s1 * t1 * l0, r0, r1, 1.0, 0.0, (int)nn, st, true);
+    if (stt != HATT_OK) return stt;
+    // T2_i[(c' g a), b] = sum_b' T1_i[b', (c' g a)] Y_k(b, i, b')
+    stt = gemm(run, gc, CMat{T1b, 1, t1 * l0 * r0, s1 * t1 * l0 * r0}, CMat{yd + sp.Y.off[c], 1, nn * s1, s1},
+               Mat{T2b, s0, 1, t1 * l0 * r0 * s0}, t1 * l0 * r0, s0, s1, 1.0, 0.0, (int)nn, st, true);
+    if (stt != HATT_OK) return stt;
+    // W^{(k)}[(g a b), c] = sum_{(i, c')} T2[(i, c'), (g a b)] W_k(c, i, c')
+    stt = gemm(run, gc, CMat{T2b, 1, l0 * r0 * s0, 0}, CMat{wd + sp.W.off[c], 1, nn * t1, 0},
+               Mat{W + woff[c], t0, 1, 0}, l0 * r0 * s0, t0, nn * t1, 1.0, 0.0, 1, st, true);
+    if (stt != HATT_OK) return stt;
+  }
+  // ---- sweep (Alg. 4)
+  {
+    // X^{(1)}: row i, columns (a, b, c) of the first cores
+    PkpArgs p1{xd, yd, ptmp, 1, r[1], 1, s[1], n[0], 0, 0, 0, 1};
+    LAUNCH(launch_pkp(p1, st));
+    PkpArgs p2{ptmp, wd, Xc, 1, r[1] * s[1], 1, t[1], n[0], 0, 0, 0, 1};
+    LAUNCH(launch_pkp(p2, st));
+  }
+  for (int c = 0; c < d - 1; ++c) {
+    const int64_t nn = n[c], lc = l[c], l1 = l[c + 1], K1 = rst[c + 1];
+    // sketched frame: slice i of X^{(k)} (rows g) times W^{(k)} -> frame rows (g, i)
+    stt = gemm(run, gc, CMat{Xc, K1, 1, lc * K1}, CMat{W + woff[c + 1], 1, K1, 0}, Mat{Yb, nn * l1, 1, l1}, lc, l1,
+               K1, 1.0, 0.0, (int)nn, st, true);
+    if (stt != HATT_OK) return stt;
+    double *qcore = sp.out + ooff[c];
+    stt = qr_exec(run, qp[c], CMat{Yb, l1, 1, ysz}, Mat{qcore, l1, 1, sp.ostride}, Mat{nullptr, 0, 0, 0}, 0, wqr,
+                  qrws, 1, gc, st);
+    if (stt != HATT_OK) return stt;
+    // M = Q^T X^{(k)} = sum_i Q_i^T X_i, stored column-major (rows g')
+    if (nn == 1) {
+      stt = gemm(run, gc, CMat{qcore, 1, l1, 0}, CMat{Xc, K1, 1, 0}, Mat{Mb, 1, l1, 0}, l1, K1, lc, 1.0, 0.0, 1, st,
+                 true);
+      if (stt != HATT_OK) return stt;
+    } else {
+      stt = gemm(run, gc, CMat{qcore, 1, nn * l1, l1}, CMat{Xc, K1, 1, lc * K1}, Mat{Mp, K1, 1, l1 * K1}, l1, K1,
+                 lc, 1.0, 0.0, (int)nn, st, false);
+      if (stt != HATT_OK) return stt;
+      GemmArgs ra{};
+      ra.M = l1;
+      ra.N = K1;
+      ra.batch = 1;
+      ra.ksplit = (int)nn;
+      ra.part = Mp;
+      ra.C = Mat{Mb, 1, l1, 0};
+      ra.alpha = 1.0;
+      ra.beta = 0.0;
+      site("reduce M over %lld slices", (long long)nn);
+      LAUNCH(launch_splitk_reduce(ra, st));
+    }
+    const int cn = c + 1;
+    if (cn == d - 1) {
+      // last core: X_d(g, i) = sum_{(a, b, c)} M(g, (a, b, c)) X_d(a, i) Y_d(b, i) W_d(c, i)
+      stt = gemm(run, gc, CMat{Mb, 1, l1, 0}, CMat{Hlast, n[cn], 1, 0}, Mat{sp.out + ooff[cn], n[cn], 1, 0}, l1,
+                 n[cn], K1, 1.0, 0.0, 1, st, true);
+      if (stt != HATT_OK) return stt;
+      continue;
+    }
+    const int64_t n1 = n[cn], ra_ = r[cn], sa = s[cn], ta = t[cn], r2 = r[cn + 1], s2 = s[cn + 1], t2 = t[cn + 1];
+    // U1_i[(b c g), a'] = sum_a M[a, (b c g)] X(a, i, a')
+    stt = gemm(run, gc, CMat{Mb, 1, sa * ta * l1, 0}, CMat{xd + sp.X.off[cn], n1 * r2, 1, r2},
+               Mat{U1, r2, 1, sa * ta * l1 * r2}, sa * ta * l1, r2, ra_, 1.0, 0.0, (int)n1, st, true);
+    if (stt != HATT_OK) return stt;
+    // U2_i[(c g a'), b'] = sum_b U1_i[b, (c g a')] Y(b, i, b')
+    stt = gemm(run, gc, CMat{U1, 1, ta * l1 * r2, sa * ta * l1 * r2}, CMat{yd + sp.Y.off[cn], n1 * s2, 1, s2},
+               Mat{U2, s2, 1, ta * l1 * r2 * s2}, ta * l1 * r2, s2, sa, 1.0, 0.0, (int)n1, st, true);
+    if (stt != HATT_OK) return stt;
+    // X^{(k+1)}_i[(g a' b'), c'] = sum_c U2_i[c, (g a' b')] W(c, i, c')
+    stt = gemm(run, gc, CMat{U2, 1, l1 * r2 * s2, ta * l1 * r2 * s2}, CMat{wd + sp.W.off[cn], n1 * t2, 1, t2},
+               Mat{Xc, t2, 1, l1 * rst[cn + 1]}, l1 * r2 * s2, t2, ta, 1.0, 0.0, (int)n1, st, true);
+    if (stt != HATT_OK) return stt;
+  }
+  if ((int)l.size() > kMaxRankPattern) return fail(HATT_EUNSUPPORTED, "order too large for the library (rank pattern buffer)");
+  LAUNCH(launch_rank_pattern(sp.orank, 1, d + 1, l.data(), st));
+  bool capped = false;
+  for (int64_t cp : sp.bond_cap) capped = capped || cp > 0;
+  if ((capped || sp.o.tol > 0.0) && d >= 2) {
+    stt = truncate_left_orth(run, n, l, sp.out, sp.ostride, sp.orank, sp.bond_cap, sp.o.tol, 1, ws, st);
+    if (stt != HATT_OK) return stt;
+  }
+  return HATT_OK;
+}
+
 hatt_status hatt_run(bool run, const HattSpec &sp, Ws &ws, hipStream_t st) {
   Ws probe(nullptr);
   GemmCtx g0{nullptr, 0, 0};
@@ -1719,8 +1914,8 @@ const char *hatt_profile_class_name(int32_t cls) {
 }
 const char *hatt_version(void) { return "hatt-mi355x 0.1 (gfx950, fp64)"; }
 
-static hatt_status hatt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_opts *o, HattSpec *sp,
-                                bool need_data) {
+static hatt_status hatt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_tt *w, const hatt_opts *o,
+                                HattSpec *sp, bool need_data) {
   if (o == nullptr) return fail(HATT_EINVAL, "opts is NULL");
   hatt_status st = read_tt(x, "x", &sp->X, need_data);
   if (st != HATT_OK) return st;
@@ -1729,6 +1924,19 @@ static hatt_status hatt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_o
   if (sp->X.d != sp->Y.d) return fail(HATT_ESHAPE, "x and y have different orders");
   if (sp->X.batch != sp->Y.batch) return fail(HATT_ESHAPE, "x and y have different batch counts");
   if (sp->X.n != sp->Y.n) return fail(HATT_ESHAPE, "x and y have different mode sizes");
+  sp->ryw = sp->Y.r;
+  sp->three = (w != nullptr);
+  if (sp->three) {
+    st = read_tt(w, "w", &sp->W, need_data);
+    if (st != HATT_OK) return st;
+    if (sp->W.d != sp->X.d) return fail(HATT_ESHAPE, "x and w have different orders");
+    if (sp->W.n != sp->X.n) return fail(HATT_ESHAPE, "x and w have different mode sizes");
+    if (sp->X.batch != 1 || sp->W.batch != 1)
+      return fail(HATT_EUNSUPPORTED, "three factors: one triple per call (batch 1)");
+    if (o->variant != 1) return fail(HATT_EUNSUPPORTED, "three factors: HaTT-1 only");
+    if (o->precision != 0) return fail(HATT_EUNSUPPORTED, "three factors: FP64 only");
+    for (int k = 0; k <= sp->X.d; ++k) sp->ryw[k] = sp->Y.r[k] * sp->W.r[k];
+  }
   if (o->variant != 1 && o->variant != 2) return fail(HATT_EINVAL, "variant must be 1 or 2");
   if (o->variant == 2 && !(o->ep >= 0.0 && o->ep < 1.0)) return fail(HATT_EINVAL, "ep must be in [0, 1)");
   if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(HATT_EINVAL, "tol must be finite and >= 0");
@@ -1741,7 +1949,7 @@ static hatt_status hatt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_o
     req[k] = o->ell_bond ? o->ell_bond[k] : o->ell;
     if (req[k] < 1) return fail(HATT_EINVAL, "sketch width must be >= 1");
   }
-  sp->ell = clamp_ell(sp->X.n, sp->X.r, sp->Y.r, req);
+  sp->ell = clamp_ell(sp->X.n, sp->X.r, sp->ryw, req);
   sp->o = *o;
   sp->o.max_rank_bond = nullptr;  // read here only; the caller's array need not outlive the call
   sp->bond_cap.assign(d + 1, std::max<int64_t>(o->max_rank, 0));
@@ -1751,10 +1959,10 @@ static hatt_status hatt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_o
   return HATT_OK;
 }
 
-hatt_status hatt_plan(const hatt_tt *x, const hatt_tt *y, const hatt_opts *opts, int64_t *ell_out,
-                      size_t *ws_bytes, int64_t *out_elems) {
+static hatt_status plan_common(const hatt_tt *x, const hatt_tt *y, const hatt_tt *w, const hatt_opts *opts,
+                               int64_t *ell_out, size_t *ws_bytes, int64_t *out_elems) {
   HattSpec sp{};
-  hatt_status st = hatt_prepare(x, y, opts, &sp, false);
+  hatt_status st = hatt_prepare(x, y, w, opts, &sp, false);
   if (st != HATT_OK) return st;
   sp.sketch = nullptr;
   sp.out = nullptr;
@@ -1775,11 +1983,11 @@ hatt_status hatt_plan(const hatt_tt *x, const hatt_tt *y, const hatt_opts *opts,
   return HATT_OK;
 }
 
-hatt_status hatt_recompress(const hatt_tt *x, const hatt_tt *y, const hatt_tt *sketch, const hatt_opts *opts,
-                            double *out, int64_t out_stride, int64_t *out_rank, void *ws, size_t ws_bytes,
-                            void *stream) {
+static hatt_status recompress_common(const hatt_tt *x, const hatt_tt *y, const hatt_tt *w, const hatt_tt *sketch,
+                                     const hatt_opts *opts, double *out, int64_t out_stride, int64_t *out_rank,
+                                     void *ws, size_t ws_bytes, void *stream) {
   HattSpec sp{};
-  hatt_status st = hatt_prepare(x, y, opts, &sp, true);
+  hatt_status st = hatt_prepare(x, y, w, opts, &sp, true);
   if (st != HATT_OK) return st;
   if (out == nullptr || out_rank == nullptr) return fail(HATT_EINVAL, "out or out_rank is NULL");
   std::vector<int64_t> off;
@@ -1807,10 +2015,34 @@ hatt_status hatt_recompress(const hatt_tt *x, const hatt_tt *y, const hatt_tt *s
   if (st != HATT_OK) return st;
   if (ws == nullptr || ws_bytes < meas.off)
     return fail(HATT_EWORKSPACE, "workspace too small: need " + std::to_string(meas.off) + " bytes");
-  Ws w(ws);
-  st = hatt_run(true, sp, w, (hipStream_t)stream);
+  Ws wk(ws);
+  st = hatt_run(true, sp, wk, (hipStream_t)stream);
   if (st == HATT_OK) g_err.clear();
   return st;
+}
+
+hatt_status hatt_plan(const hatt_tt *x, const hatt_tt *y, const hatt_opts *opts, int64_t *ell_out,
+                      size_t *ws_bytes, int64_t *out_elems) {
+  return plan_common(x, y, nullptr, opts, ell_out, ws_bytes, out_elems);
+}
+
+hatt_status hatt_recompress(const hatt_tt *x, const hatt_tt *y, const hatt_tt *sketch, const hatt_opts *opts,
+                            double *out, int64_t out_stride, int64_t *out_rank, void *ws, size_t ws_bytes,
+                            void *stream) {
+  return recompress_common(x, y, nullptr, sketch, opts, out, out_stride, out_rank, ws, ws_bytes, stream);
+}
+
+hatt_status hatt_plan3(const hatt_tt *x, const hatt_tt *y, const hatt_tt *w, const hatt_opts *opts,
+                       int64_t *ell_out, size_t *ws_bytes, int64_t *out_elems) {
+  if (w == nullptr) return fail(HATT_EINVAL, "w: NULL tensor view");
+  return plan_common(x, y, w, opts, ell_out, ws_bytes, out_elems);
+}
+
+hatt_status hatt_recompress3(const hatt_tt *x, const hatt_tt *y, const hatt_tt *w, const hatt_tt *sketch,
+                             const hatt_opts *opts, double *out, int64_t out_stride, int64_t *out_rank, void *ws,
+                             size_t ws_bytes, void *stream) {
+  if (w == nullptr) return fail(HATT_EINVAL, "w: NULL tensor view");
+  return recompress_common(x, y, w, sketch, opts, out, out_stride, out_rank, ws, ws_bytes, stream);
 }
 
 hatt_status hatt_recompress_noalloc(const hatt_tt *x, const hatt_tt *y, const hatt_tt *sketch, const hatt_opts *opts,
@@ -1945,7 +2177,7 @@ static hatt_status batch_prepare(int32_t npairs, const hatt_tt *x, const hatt_tt
       op.ell_bond = rq.data();
     }
     HattSpec &sp = bp->sp[p];
-    hatt_status st = hatt_prepare(&x[p], &y[p], &op, &sp, need_data);
+    hatt_status st = hatt_prepare(&x[p], &y[p], nullptr, &op, &sp, need_data);
     if (st != HATT_OK) return fail(st, "pair " + std::to_string(p) + ": " + g_err);
     sp.o.ell_bond = nullptr;
     sp.sketch = nullptr;
@@ -2039,7 +2271,8 @@ constexpr int64_t kAdaptMaxWidth = kSvdBigMaxN;
 
 // cap: the largest feasible widths (a bond at its cap is exact); lim: the
 // widths the growth may reach (cap clamped to kAdaptMaxWidth).
-static hatt_status adapt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_adapt_opts *ao, HattSpec *sp,
+static hatt_status adapt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_tt *w, const hatt_adapt_opts *ao,
+                                 HattSpec *sp,
                                  std::vector<int64_t> *cap, std::vector<int64_t> *lim, std::vector<int64_t> *ell0,
                                  int *p, int *maxa, bool need_data) {
   if (ao == nullptr) return fail(HATT_EINVAL, "adapt opts is NULL");
@@ -2051,28 +2284,33 @@ static hatt_status adapt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_
   o.tol = ao->tol;
   o.seed = ao->seed;
   o.precision = ao->precision;
-  hatt_status st = hatt_prepare(x, y, &o, sp, need_data);
+  hatt_status st = hatt_prepare(x, y, w, &o, sp, need_data);
   if (st != HATT_OK) return st;
   const int d = sp->X.d;
   *p = ao->oversample > 0 ? ao->oversample : 8;
   *maxa = ao->max_attempts > 0 ? ao->max_attempts : 8;
   std::vector<int64_t> big(d + 1, (int64_t)1 << 40), req(d + 1, 1);
-  *cap = clamp_ell(sp->X.n, sp->X.r, sp->Y.r, big);
+  *cap = clamp_ell(sp->X.n, sp->X.r, sp->ryw, big);
   std::vector<int64_t> lreq(d + 1, kAdaptMaxWidth);
-  *lim = clamp_ell(sp->X.n, sp->X.r, sp->Y.r, lreq);
-  for (int k = 1; k < d; ++k) req[k] = std::min(std::max(sp->X.r[k], sp->Y.r[k]) + *p, kAdaptMaxWidth);
+  *lim = clamp_ell(sp->X.n, sp->X.r, sp->ryw, lreq);
+  for (int k = 1; k < d; ++k) {
+    int64_t rmax = std::max(sp->X.r[k], sp->Y.r[k]);
+    if (sp->three) rmax = std::max(rmax, sp->W.r[k]);
+    req[k] = std::min(rmax + *p, kAdaptMaxWidth);
+  }
   if (ao->ell_init != nullptr)
     for (int k = 1; k < d; ++k) req[k] = std::min(ao->ell_init[k], kAdaptMaxWidth);
-  *ell0 = clamp_ell(sp->X.n, sp->X.r, sp->Y.r, req);
+  *ell0 = clamp_ell(sp->X.n, sp->X.r, sp->ryw, req);
   return HATT_OK;
 }
 
-hatt_status hatt_adaptive_plan(const hatt_tt *x, const hatt_tt *y, const hatt_adapt_opts *opts, int64_t *cap_out,
-                               size_t *ws_bytes, int64_t *out_elems) {
+static hatt_status adaptive_plan_common(const hatt_tt *x, const hatt_tt *y, const hatt_tt *w,
+                                        const hatt_adapt_opts *opts, int64_t *cap_out, size_t *ws_bytes,
+                                        int64_t *out_elems) {
   HattSpec sp{};
   std::vector<int64_t> cap_true, cap, ell0;
   int p, maxa;
-  hatt_status st = adapt_prepare(x, y, opts, &sp, &cap_true, &cap, &ell0, &p, &maxa, false);
+  hatt_status st = adapt_prepare(x, y, w, opts, &sp, &cap_true, &cap, &ell0, &p, &maxa, false);
   if (st != HATT_OK) return st;
   sp.ell = cap;
   sp.sketch = nullptr;
@@ -2094,13 +2332,13 @@ hatt_status hatt_adaptive_plan(const hatt_tt *x, const hatt_tt *y, const hatt_ad
   return HATT_OK;
 }
 
-hatt_status hatt_recompress_adaptive(const hatt_tt *x, const hatt_tt *y, const hatt_adapt_opts *opts, double *out,
-                                     int64_t out_stride, int64_t *out_rank, int64_t *ell_out, int32_t *attempts_out,
-                                     void *ws, size_t ws_bytes, void *stream) {
+static hatt_status adaptive_common(const hatt_tt *x, const hatt_tt *y, const hatt_tt *w3,
+                                   const hatt_adapt_opts *opts, double *out, int64_t out_stride, int64_t *out_rank,
+                                   int64_t *ell_out, int32_t *attempts_out, void *ws, size_t ws_bytes, void *stream) {
   HattSpec sp{};
   std::vector<int64_t> cap, lim, ell;
   int p, maxa;
-  hatt_status st = adapt_prepare(x, y, opts, &sp, &cap, &lim, &ell, &p, &maxa, true);
+  hatt_status st = adapt_prepare(x, y, w3, opts, &sp, &cap, &lim, &ell, &p, &maxa, true);
   if (st != HATT_OK) return st;
   if (out == nullptr || out_rank == nullptr || ell_out == nullptr || attempts_out == nullptr)
     return fail(HATT_EINVAL, "NULL output argument");
@@ -2117,23 +2355,27 @@ hatt_status hatt_recompress_adaptive(const hatt_tt *x, const hatt_tt *y, const h
   std::vector<int64_t> host_rank((size_t)P * (d + 1));
   {
     // non-finite inputs: the rank decisions below would be meaningless.
-    // The flags of x and y borrow out_rank (>= 2 P ints) until the first attempt.
+    // The flags of the factors borrow out_rank (>= 2 P int64 slots, so room
+    // for 3 P ints) until the first attempt.
     int *fl = reinterpret_cast<int *>(out_rank);
     const bool run = true;
     hipStream_t st = strm;
+    const int nf = sp.three ? 3 : 2;
     LAUNCH(launch_finite_check(sp.X.data, sp.X.total, sp.X.stride, P, fl, st));
     LAUNCH(launch_finite_check(sp.Y.data, sp.Y.total, sp.Y.stride, P, fl + P, st));
-    std::vector<int> hf(2 * (size_t)P);
+    if (sp.three) LAUNCH(launch_finite_check(sp.W.data, sp.W.total, sp.W.stride, P, fl + 2 * P, st));
+    std::vector<int> hf((size_t)nf * P);
     if (hipMemcpyAsync(hf.data(), fl, hf.size() * sizeof(int), hipMemcpyDeviceToHost, strm) != hipSuccess ||
         hipStreamSynchronize(strm) != hipSuccess)
       return fail(HATT_EDEVICE, "reading the finiteness flags failed");
-    for (int q = 0; q < 2 * P; ++q)
+    static const char *kNames[3] = {"x", "y", "w"};
+    for (int q = 0; q < nf * P; ++q)
       if (hf[q] != 1)
-        return fail(HATT_ENONFINITE, std::string(q < P ? "x" : "y") + " train " + std::to_string(q % P) +
+        return fail(HATT_ENONFINITE, std::string(kNames[q / P]) + " train " + std::to_string(q % P) +
                                          " has a non-finite entry");
   }
   for (int attempt = 0; attempt < maxa; ++attempt) {
-    sp.ell = clamp_ell(sp.X.n, sp.X.r, sp.Y.r, ell);
+    sp.ell = clamp_ell(sp.X.n, sp.X.r, sp.ryw, ell);
     sp.o.seed = opts->seed + (uint64_t)attempt;
     Ws meas(nullptr);
     st = hatt_run(false, sp, meas, nullptr);
@@ -2169,6 +2411,31 @@ hatt_status hatt_recompress_adaptive(const hatt_tt *x, const hatt_tt *y, const h
     }
   }
   return fail(HATT_ENOTCONV, "sketch widths did not converge within max_attempts");
+}
+
+hatt_status hatt_adaptive_plan(const hatt_tt *x, const hatt_tt *y, const hatt_adapt_opts *opts, int64_t *cap_out,
+                               size_t *ws_bytes, int64_t *out_elems) {
+  return adaptive_plan_common(x, y, nullptr, opts, cap_out, ws_bytes, out_elems);
+}
+
+hatt_status hatt_recompress_adaptive(const hatt_tt *x, const hatt_tt *y, const hatt_adapt_opts *opts, double *out,
+                                     int64_t out_stride, int64_t *out_rank, int64_t *ell_out, int32_t *attempts_out,
+                                     void *ws, size_t ws_bytes, void *stream) {
+  return adaptive_common(x, y, nullptr, opts, out, out_stride, out_rank, ell_out, attempts_out, ws, ws_bytes, stream);
+}
+
+hatt_status hatt_adaptive_plan3(const hatt_tt *x, const hatt_tt *y, const hatt_tt *w, const hatt_adapt_opts *opts,
+                                int64_t *cap_out, size_t *ws_bytes, int64_t *out_elems) {
+  if (w == nullptr) return fail(HATT_EINVAL, "w: NULL tensor view");
+  return adaptive_plan_common(x, y, w, opts, cap_out, ws_bytes, out_elems);
+}
+
+hatt_status hatt_recompress3_adaptive(const hatt_tt *x, const hatt_tt *y, const hatt_tt *w,
+                                      const hatt_adapt_opts *opts, double *out, int64_t out_stride,
+                                      int64_t *out_rank, int64_t *ell_out, int32_t *attempts_out, void *ws,
+                                      size_t ws_bytes, void *stream) {
+  if (w == nullptr) return fail(HATT_EINVAL, "w: NULL tensor view");
+  return adaptive_common(x, y, w, opts, out, out_stride, out_rank, ell_out, attempts_out, ws, ws_bytes, stream);
 }
 
 hatt_status tt_hadamard_explicit(const hatt_tt *x, const hatt_tt *y, double *out, int64_t out_stride,

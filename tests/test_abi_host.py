@@ -404,3 +404,31 @@ def test_per_bond_rank_caps_are_options():
     ws = ctypes.c_size_t(0)
     st = _lib.lib().hatt_batched_plan(1, xs, xs, ctypes.byref(o), oo, ro, eo, ctypes.byref(ws))
     assert st == -1 and "per-bond rank caps" in _lib.lib().hatt_last_error().decode()
+
+
+def test_plan3_clamps_with_three_factor_ranks_and_rejects_unsupported():
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        d = int(rng.integers(1, 8))
+        n = [int(v) for v in rng.integers(1, 6, size=d)]
+        rx, ry, rw = (wk.feasible_ranks(n, int(rng.integers(1, 5))) for _ in range(3))
+        ell = int(rng.integers(1, 60))
+        p = api.plan3(_cpu_tt(n, rx), _cpu_tt(n, ry), _cpu_tt(n, rw), ell)
+        assert p["ell"] == oplan.clamp_ell(n, rx, [a * b for a, b in zip(ry, rw)], ell)
+        assert p["ws_bytes"] > 0
+    n = [4] * 4
+    x = _cpu_tt(n, [1, 3, 3, 3, 1])
+    with pytest.raises(HattError) as e:
+        api.plan3(x, x, _cpu_tt([4, 4, 4, 3], [1, 3, 3, 3, 1]), 5)
+    assert e.value.status == -2
+    xb = _cpu_tt(n, [1, 3, 3, 3, 1], batch=2)
+    with pytest.raises(HattError) as e:
+        api.plan3(xb, xb, xb, 5)
+    assert e.value.status == -7
+    L = _lib.lib()
+    xv, kx = x.view()
+    for variant, prec in ((2, 0), (1, 1)):
+        o = _lib.HattOpts(variant, 0.1, 5, None, 0, 0.0, 0, prec, None)
+        st = L.hatt_plan3(ctypes.byref(xv), ctypes.byref(xv), ctypes.byref(xv), ctypes.byref(o), None, None, None)
+        assert st == -7
+    assert L.hatt_plan3(ctypes.byref(xv), ctypes.byref(xv), None, ctypes.byref(o), None, None, None) == -1
