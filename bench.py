@@ -40,8 +40,9 @@ def _parse():
     ap.add_argument("--no-cpu-explicit", action="store_true",
                     help="trig: skip the host oracle's explicit PKP + TT-Rounding of u2 (5.2 GB core)")
     ap.add_argument("--eager", action="store_true", help="launch kernels directly instead of replaying a HIP graph")
-    ap.add_argument("--precision", choices=["f64", "f32"], default="f64",
-                    help="f32: range finding on the FP32 matrix cores, projection and truncation in FP64")
+    ap.add_argument("--precision", choices=["f64", "f32", "bf16"], default="f64",
+                    help="f32 / bf16: range finding on the FP32 / BF16 matrix cores, projection and "
+                         "truncation in FP64")
     ap.add_argument("--rp-train", type=int, default=128, help="rankpred: training recompressions")
     ap.add_argument("--rp-eval", type=int, default=24, help="rankpred: fresh pairs evaluated")
     ap.add_argument("--rp-margin", type=float, default=0.15, help="rankpred: width safety margin")
@@ -131,7 +132,7 @@ def _roofline(report, batch, steps, perfmodel, precision="f64"):
         if bound == "hbm":
             achieved, peak, unit = gbs, perfmodel.PEAK_HBM_GBS, "GB/s"
         else:
-            achieved, peak, unit = tflops, perfmodel.PEAK_FP64_TFLOPS, "TFLOP/s"
+            achieved, peak, unit = tflops, perfmodel.mfma_peak_tflops(kernel), "TFLOP/s"
         return gr, avg_s, per_launch, bytes_launch, tflops, gbs, bound, achieved, peak, unit
 
     order = sorted(groups, key=lambda k: -groups[k]["ms"])
@@ -438,7 +439,7 @@ def _bench_trig(args, torch, wk, H, perfmodel) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "f64" else "f32+f64",
+        "dtype": "f64" if args.precision == "f64" else args.precision + "+f64",
         "data": "synthetic",
         "config": {"workload": f"trig 256^3: u2 = u*u then u3 = u2*u, u of ranks 40 (40 separable sin/cos "
                                f"products), sketch widths {ell2[1]} / {ell3[1]}, TT-Rounding at tol {tol:g}",
@@ -920,7 +921,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "f64" else "f32+f64",
+        "dtype": "f64" if args.precision == "f64" else args.precision + "+f64",
         "data": "synthetic",
         "config": {"workload": f"spectral d={d} n={n} r_x=r_y={r} sketch={ell} max_rank={cap}",
                    "pairs_per_step": B, "variant": "HaTT-1", "seed": seed, "launch": mode,

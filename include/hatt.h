@@ -75,11 +75,15 @@ typedef struct {
   uint64_t seed;          /* key of the Philox4x32-10 sketch (used when no sketch is passed) */
   int32_t precision;      /* 0: FP64 throughout; 1: FP32 range finding -- the HPCRL sketches
                              W^{(k)} (W_L build and W_L W_R^T, Alg. 3) run on the FP32
-                             matrix cores with FP32 accumulation and storage; the sweep
-                             (Alg. 4: the frame X^{(k)} W^{(k)} with W^{(k)} widened to
-                             FP64, its QR, the projection Q^T X, the core update) and the
-                             truncation run in FP64, so every frame spans a subspace of
-                             range(X^{(k)}) to FP64 accuracy (HaTT-1 only) */
+                             matrix cores with FP32 accumulation and storage; 2: BF16
+                             range finding -- the same products with their operands
+                             rounded to BF16 on the BF16 matrix cores (FP32 accumulation,
+                             FP32 storage).  In both the sweep (Alg. 4: the frame
+                             X^{(k)} W^{(k)} with W^{(k)} widened to FP64, its QR, the
+                             projection Q^T X, the core update) and the truncation run in
+                             FP64, so every frame spans a subspace of range(X^{(k)}) to
+                             FP64 accuracy; what the sketch's rounding costs is range
+                             capture (HaTT-1 only) */
   const int64_t *max_rank_bond; /* optional host [d+1]: entry k caps the kept rank of bond k
                              (entries <= 0: max_rank applies there); not for the uneven batch */
 } hatt_opts;
@@ -203,7 +207,7 @@ typedef struct {
   double ep;              /* HaTT-2 threshold */
   const int64_t *ell_init;/* optional host [d+1]: start widths instead of max(r_k, s_k) + p
                              (e.g. hatt_rankpred_widths); clamped like any request */
-  int32_t precision;      /* as in hatt_opts: 0 FP64, 1 FP32 range finding */
+  int32_t precision;      /* as in hatt_opts: 0 FP64, 1 FP32, 2 BF16 range finding */
 } hatt_adapt_opts;
 
 HATT_API hatt_status hatt_adaptive_plan(const hatt_tt *x, const hatt_tt *y, const hatt_adapt_opts *opts,

@@ -107,7 +107,7 @@ class Result:
         return self.out.to_numpy(b, kept)
 
 
-_PRECISION = {"f64": 0, "f32": 1}
+_PRECISION = {"f64": 0, "f32": 1, "bf16": 2}
 
 
 def _opts(ell, max_rank, tol, seed, variant, ep, d, precision="f64"):
@@ -153,9 +153,9 @@ def recompress(x: TT, y: TT, ell, *, max_rank: int = 0, tol: float = 0.0, seed: 
                workspace: Optional[torch.Tensor] = None, out: Optional[TT] = None,
                ranks: Optional[torch.Tensor] = None, stream=None) -> Result:
     """HaTT (Alg. 4) of x (.) y for every train of the batch, optionally
-    truncated by TT-Rounding to ``max_rank`` / ``tol``.  precision "f32":
-    range finding on the FP32 matrix cores, projection and truncation in
-    FP64."""
+    truncated by TT-Rounding to ``max_rank`` / ``tol``.  precision "f32" /
+    "bf16": range finding on the FP32 / BF16 matrix cores, projection and
+    truncation in FP64."""
     p = plan(x, y, ell, max_rank, tol, seed, variant, ep, precision)
     dev = x.data.device
     if out is None:
@@ -273,7 +273,8 @@ def recompress_adaptive(x: TT, y: TT, tol: float, *, seed: int = 0, oversample: 
     """Tolerance-driven HaTT: grows the sketch widths until the truncation
     at ``tol`` leaves slack on every bond, starting from ``ell_init`` (d+1
     widths, e.g. predicted ones) or from max(r_k, s_k) + oversample.
-    ``precision`` "f32": HPCRL sketches on the FP32 matrix cores.
+    ``precision`` "f32" / "bf16": HPCRL sketches on the FP32 / BF16 matrix
+    cores.
     Returns (Result, widths used, attempts)."""
     xv, kx = x.view()
     yv, ky = y.view()
@@ -282,10 +283,10 @@ def recompress_adaptive(x: TT, y: TT, tol: float, *, seed: int = 0, oversample: 
         if len(ell_init) != x.d + 1:
             raise ValueError("ell_init needs d+1 entries")
         init = i64_array(ell_init)
-    if precision not in ("f64", "f32"):
+    if precision not in _PRECISION:
         raise ValueError(f"unknown precision {precision!r}")
     o = HattAdaptOpts(float(tol), int(seed) & 0xFFFFFFFFFFFFFFFF, int(oversample), int(max_attempts),
-                      int(variant), float(ep), init, 1 if precision == "f32" else 0)
+                      int(variant), float(ep), init, _PRECISION[precision])
     cap = (ctypes.c_int64 * (x.d + 1))()
     ws = ctypes.c_size_t(0)
     oe = ctypes.c_int64(0)

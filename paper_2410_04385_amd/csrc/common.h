@@ -58,7 +58,8 @@ struct SandwichArgs {
   int RA, RI, SI, SO;  // YL is RA x RI, C is RI x SI, ZR is SI x SO
   int64_t n, G;
   int batch;
-  int prec;            // 1: C and out are FP32 and the products run on the FP32 matrix cores
+  int prec;            // 1: C and out are FP32 and the products run on the FP32 matrix cores;
+                       // 2: C and out are FP32, the products run on the BF16 matrix cores
 };
 hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s);
 // Whether launch_sandwich has a kernel for these shapes (checked on the host
@@ -160,7 +161,8 @@ struct GemmArgs {
   int ksplit;
   double *part;
   int no_reduce;        // split-K: leave the partial products in `part` (the caller reduces them)
-  int prec;             // 0: FP64 matrix cores; 1: FP32 matrix cores (no split-K)
+  int prec;             // 0: FP64 matrix cores; 1: FP32 matrix cores; 2: BF16 matrix cores with
+                        // FP32 accumulation (split-K partials are FP64 in every case)
   int a_f32, b_f32, c_f32;  // storage of A, B, C is FP32 (pointers reinterpreted), else FP64
   const int *run_flag;  // optional: pair p is computed only when run_flag[p * run_flag_stride] == run_when
   int64_t run_flag_stride;

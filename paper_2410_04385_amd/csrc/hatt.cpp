@@ -232,7 +232,7 @@ struct GemmCtx {
   int64_t part_need;  // max requested (measuring)
 };
 
-// Storage / compute types of one product: prec = 1 runs it on the FP32 matrix
+// Storage / compute types of one product: prec = 1 (2) runs it on the FP32 (BF16) matrix
 // cores (no K split); a32 / b32 / c32 mark FP32 storage of A / B / C.
 struct GemmTypes {
   int prec = 0, a32 = 0, b32 = 0, c32 = 0;
@@ -247,7 +247,6 @@ hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_
   g.a_f32 = ty.a32;
   g.b_f32 = ty.b32;
   g.c_f32 = ty.c32;
-  if (ty.prec) allow_split = false;
   g.no_reduce = 1;  // the reduction, when needed, is its own launch below
   g.run_flag = run_flag;
   g.run_flag_stride = run_flag_stride;
@@ -1187,7 +1186,9 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     sks = 0;
   }
   // FP32 range finding keeps W^{(k)} and W_L as FP32 inside the same buffers
-  const bool f32 = (sp.o.precision == 1);
+  // (BF16 range finding keeps the same FP32 storage; only the sandwich and
+  // W_L W_R^T products round their operands to BF16 on the matrix cores)
+  const bool f32 = (sp.o.precision != 0);
   double *W = ws.d((int64_t)P * std::max<int64_t>(wtot, 1));
   double *WL = ws.d((int64_t)P * wlsz);
   float *Wf = reinterpret_cast<float *>(W), *WLf = reinterpret_cast<float *>(WL);
@@ -1288,7 +1289,7 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
       ucb = h2_q;
     }
     SandwichArgs a{};
-    a.prec = f32 ? 1 : 0;
+    a.prec = sp.o.precision;
     a.yl = xd + sp.X.off[c];
     a.ylb = xs;
     a.yli = r[c + 1];
@@ -1322,7 +1323,8 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     if (f32) {
       SwPlan swp;
       if (!sandwich_mfma_plan(a, kSandwichLdsDoubles, &swp))
-        return fail(HATT_EUNSUPPORTED, "FP32 range finding: ranks above 64 are not built (use FP64)");
+        return fail(HATT_EUNSUPPORTED, "low-precision range finding: no matrix-core sandwich plan for these ranks "
+                                       "(use FP64)");
     }
     if (!sandwich_supported(a))
       return fail(HATT_EUNSUPPORTED, "HaTT: no sandwich kernel for the W_L build at core " + std::to_string(c) +
@@ -1336,11 +1338,11 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
     hatt_status stt;
     if (f32) {
       GemmTypes ty;
-      ty.prec = 1;
+      ty.prec = sp.o.precision;
       ty.a32 = 1;
       ty.c32 = 1;
       stt = gemm(run, gc, CMat{as_d(WLf), 1, r[c] * s[c], wlsz}, wr, Mat{as_d(Wf + woff[c]), l[c], 1, wtot}, r[c] * s[c],
-                 l[c], K, 1.0, 0.0, P, st, false, nullptr, 0, nullptr, ty);
+                 l[c], K, 1.0, 0.0, P, st, true, nullptr, 0, nullptr, ty);
       if (stt == HATT_OK) LAUNCH(launch_rescale_pow2(Wf + woff[c], r[c] * s[c] * l[c], wtot, P, st));
     } else {
       stt = gemm(run, gc, CMat{WL, 1, r[c] * s[c], wlsz}, wr, Mat{W + woff[c], l[c], 1, wtot}, r[c] * s[c], l[c], K, 1.0,
@@ -1940,9 +1942,10 @@ static hatt_status hatt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_t
   if (o->variant != 1 && o->variant != 2) return fail(HATT_EINVAL, "variant must be 1 or 2");
   if (o->variant == 2 && !(o->ep >= 0.0 && o->ep < 1.0)) return fail(HATT_EINVAL, "ep must be in [0, 1)");
   if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(HATT_EINVAL, "tol must be finite and >= 0");
-  if (o->precision != 0 && o->precision != 1) return fail(HATT_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
-  if (o->precision == 1 && o->variant != 1)
-    return fail(HATT_EUNSUPPORTED, "FP32 range finding is built for HaTT-1 only");
+  if (o->precision < 0 || o->precision > 2)
+    return fail(HATT_EINVAL, "precision must be 0 (FP64), 1 (FP32) or 2 (BF16)");
+  if (o->precision != 0 && o->variant != 1)
+    return fail(HATT_EUNSUPPORTED, "low-precision range finding is built for HaTT-1 only");
   const int d = sp->X.d;
   std::vector<int64_t> req(d + 1, 1);
   for (int k = 1; k < d; ++k) {

@@ -349,7 +349,7 @@ const char *sandwich_kernel_name(const SandwichArgs &a) {
   const int64_t budget = 19456;
   SwPlan pl;
   if ((a.prec || g_sandwich_mfma) && sandwich_mfma_plan(a, kSandwichLdsDoubles, &pl)) return sandwich_mfma_name(a, pl);
-  if (a.prec) return "none (FP32 sandwich needs the matrix-core plan)";
+  if (a.prec) return "none (the low-precision sandwich needs the matrix-core plan)";
   const int RIp = (a.RI + 1) & ~1, SIp = (a.SI + 1) & ~1;
   const int64_t fixed = (int64_t)a.RA * RIp + (((int64_t)a.SI * a.SO + 1) & ~1);
   const int m = std::max(std::max(a.RI, a.SI), 1);
@@ -383,7 +383,7 @@ hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s) {
   if (g_sandwich_mfma || a.prec) {
     SwPlan pl;
     if (sandwich_mfma_plan(a, kSandwichLdsDoubles, &pl)) return launch_sandwich_mfma(a, pl, s);
-    if (a.prec) return hipErrorInvalidValue;  // the FP32 variant exists only on the matrix cores
+    if (a.prec) return hipErrorInvalidValue;  // the FP32 / BF16 variants exist only on the matrix cores
   }
   if (g_sandwich_reg) {
     const int RIp = (a.RI + 1) & ~1, SIp = (a.SI + 1) & ~1;

@@ -117,13 +117,13 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g) {
     for (int t = 0; t < A_PER; ++t) {
       const int v = a_var0 + t * a_vard;
       const bool ok = a_kfast ? (a_fix < rem && v < a_lim) : (a_fix < 0 && v < rem);
-      ra[t] = ok ? (CT)pa[t * astep] : (CT)0;
+      ra[t] = to_ct<CT>(ok ? (double)pa[t * astep] : 0.0);
     }
 #pragma unroll
     for (int t = 0; t < B_PER; ++t) {
       const int v = b_var0 + t * b_vard;
       const bool ok = b_nfast ? (b_fix < 0 && v < rem) : (b_fix < rem && v < b_lim);
-      rb[t] = ok ? (CT)pb[t * bstep] : (CT)0;
+      rb[t] = to_ct<CT>(ok ? (double)pb[t * bstep] : 0.0);
     }
   };
   auto park = [&]() {
@@ -182,6 +182,29 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g) {
     const bool more = k0 + BK < kend;
     if (more) fetch(k0 + BK, slab + 1);
     const int kval = (int)std::min<int64_t>(BK, kend - k0);
+    if constexpr (is_bf16<CT>::value) {
+      // BF16: one K-16 MFMA per block and 16 K values of the slab (the slab
+      // is zero beyond the valid K)
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 16) {
+        if (kk >= kval) break;
+        const int q = lane >> 4, c16 = lane & 15;
+        CT av[MI][4], bv[NJ][4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int kr = kk + 4 * e + q;
+#pragma unroll
+          for (int i = 0; i < MI; ++i) av[i][e] = As[kr * LDA_S + wm + i * 16 + c16];
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) bv[j][e] = Bs[kr * LDB_S + wn + j * 16 + c16];
+        }
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j)
+            if (live_m[i] && live_n[j]) acc[i][j] = mfma16_bf16(av[i], bv[j], acc[i][j]);
+      }
+    } else {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       if (kk >= kval) break;
@@ -210,6 +233,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g) {
           }
         }
       }
+    }
     }
     __syncthreads();
     if (more) {
@@ -259,7 +283,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs &g) {
         }
       }
     }
-  } else if (std::is_same<CT, double>::value) {  // split-K partials (FP64 path only)
+  } else {  // split-K partials, FP64 whatever the compute type
     double *Pb = g.part + ((int64_t)p * ks + kc) * g.M * g.N;
 #pragma unroll
     for (int i = 0; i < MI; ++i)
@@ -292,6 +316,13 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
   gemm_body<BM, BN, float, TA, TB, TC, WL>(g);
 }
 
+// BF16 matrix cores, FP32 accumulation; operands stored as FP32 or FP64 and
+// rounded to BF16 when staged.
+template <int BM, int BN, typename TA, typename TB, typename TC, int WL>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
+  gemm_body<BM, BN, __bf16, TA, TB, TC, WL>(g);
+}
+
 // Sum of the ksplit partial products in chunk order (bitwise reproducible).
 __global__ void splitk_reduce_kernel(GemmArgs g) {
   const int64_t per = g.M * g.N, total = per * g.batch;
@@ -303,9 +334,16 @@ __global__ void splitk_reduce_kernel(GemmArgs g) {
     const double *src = g.part + p * g.ksplit * per + rem;
     double acc = 0.0;
     for (int t = 0; t < g.ksplit; ++t) acc += src[t * per];
-    double *cp = g.C.ptr + p * g.C.bs + r * g.C.rs + c * g.C.cs;
-    if (g.beta != 0.0) acc += g.beta * (*cp);
-    *cp = acc;
+    const int64_t off = p * g.C.bs + r * g.C.rs + c * g.C.cs;
+    if (g.c_f32) {  // FP32 storage of C (the low-precision range finding)
+      float *cp = reinterpret_cast<float *>(static_cast<void *>(g.C.ptr)) + off;
+      if (g.beta != 0.0) acc += g.beta * (double)(*cp);
+      *cp = (float)acc;
+    } else {
+      double *cp = g.C.ptr + off;
+      if (g.beta != 0.0) acc += g.beta * (*cp);
+      *cp = acc;
+    }
   }
 }
 
@@ -604,7 +642,7 @@ static const char *tname(int f32) { return f32 ? "float" : "double"; }
 
 void gemm_kernel_name(const GemmArgs &g, char *buf, size_t n) {
   GemmArgs t;
-  const int v = thin_args(g, &t);
+  const int v = (g.prec == 2) ? -1 : thin_args(g, &t);
   const char *ak = (v & 2) ? "true" : "false";
   if (v >= 0 && !g.prec) {
     snprintf(buf, n, "gemm_thin_f64_kernel<%d, %s, %s>", thin_mi(v & 2), ak, (v & 1) ? "true" : "false");
@@ -618,8 +656,8 @@ void gemm_kernel_name(const GemmArgs &g, char *buf, size_t n) {
   int bm, bn, wl;
   gemm_tile(g.M, g.N, &bm, &bn, &wl);
   if (g.prec)
-    snprintf(buf, n, "gemm_f32_kernel<%d, %d, %s, %s, %s, %d>", bm, bn, tname(g.a_f32), tname(g.b_f32),
-             tname(g.c_f32), wl);
+    snprintf(buf, n, "%s<%d, %d, %s, %s, %s, %d>", g.prec == 2 ? "gemm_bf16_kernel" : "gemm_f32_kernel", bm, bn,
+             tname(g.a_f32), tname(g.b_f32), tname(g.c_f32), wl);
   else
     snprintf(buf, n, "gemm_f64_kernel<%d, %d, %d>", bm, bn, wl);
 }
@@ -654,10 +692,10 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
   if (a.ksplit > 1 && a.part == nullptr) a.ksplit = 1;
   int bm, bn, wl;
   gemm_tile(a.M, a.N, &bm, &bn, &wl);
-  if (a.prec) a.ksplit = 1;  // the FP32 path writes its result directly
+
   dim3 grid((unsigned)((a.M + bm - 1) / bm), (unsigned)((a.N + bn - 1) / bn), (unsigned)(a.batch * a.ksplit));
   GemmArgs t;
-  const int thin = thin_args(a, &t);
+  const int thin = (a.prec == 2) ? -1 : thin_args(a, &t);  // no thin BF16 kernel
   if (thin >= 0) {
     const int rows = 64 * thin_mi(thin & 2);
     dim3 tg((unsigned)((t.M + rows - 1) / rows), 1, (unsigned)(t.batch * t.ksplit));
@@ -685,6 +723,16 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
     } else if (bm == 64) gemm_f64_kernel<64, 32, 0><<<grid, 256, 0, s>>>(a);
     else if (bn == 64) gemm_f64_kernel<32, 64, 0><<<grid, 256, 0, s>>>(a);
     else gemm_f64_kernel<32, 32, 0><<<grid, 256, 0, s>>>(a);
+  } else if (a.prec == 2) {
+    // BF16 range finding: W_L (FP32) x sketch (FP64) -> W (FP32)
+    if (a.a_f32 != 1 || a.b_f32 != 0 || a.c_f32 != 1) return hipErrorInvalidValue;
+    if (bm == 64 && bn == 64) {
+      if (wl == 1) gemm_bf16_kernel<64, 64, float, double, float, 1><<<grid, 256, 0, s>>>(a);
+      else if (wl == 2) gemm_bf16_kernel<64, 64, float, double, float, 2><<<grid, 256, 0, s>>>(a);
+      else gemm_bf16_kernel<64, 64, float, double, float, 0><<<grid, 256, 0, s>>>(a);
+    } else if (bm == 64) gemm_bf16_kernel<64, 32, float, double, float, 0><<<grid, 256, 0, s>>>(a);
+    else if (bn == 64) gemm_bf16_kernel<32, 64, float, double, float, 0><<<grid, 256, 0, s>>>(a);
+    else gemm_bf16_kernel<32, 32, float, double, float, 0><<<grid, 256, 0, s>>>(a);
   } else {
     const int combo = a.a_f32 * 4 + a.b_f32 * 2 + a.c_f32;
 #define HATT_GEMM32(TA, TB, TC)                                                              \

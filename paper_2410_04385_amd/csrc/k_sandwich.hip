@@ -97,7 +97,13 @@ constexpr int kSwKsMax = 8;
 __host__ __device__ constexpr int sw_ks_slots(int ks) { return ks <= 2 ? 2 : (ks <= 4 ? 4 : 8); }
 
 bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
-  const int RI4 = rup(a.RI, 4), SI4 = rup(a.SI, 4);
+  // K edges: whole K steps of 4, or whole K-16 BF16 MFMAs.  The budget is
+  // given in doubles; BF16 plans count 2-byte elements, so they get four per
+  // double (FP32 plans keep the FP64 element count)
+  const int kq = (a.prec == 2) ? 16 : 4;
+  const int64_t per_double = (a.prec == 2) ? 4 : 1;
+  budget *= per_double;
+  const int RI4 = rup(a.RI, kq), SI4 = rup(a.SI, kq);
   const int SO16 = rup(a.SO, 16), RA16 = rup(a.RA, 16);
   const int ldc = SI4 + 1, ldz = SO16 + 1, ldy = RI4 + 1;
   const int64_t yz = (int64_t)SI4 * ldz + (int64_t)RA16 * ldy;  // one YL + ZR buffer
@@ -122,7 +128,7 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
     }
     return 0;
   };
-  int best = largest(std::min<int64_t>(budget, 9728));
+  int best = largest(std::min<int64_t>(budget, 9728 * per_double));
   if (best < 4) {
     const int one = largest(budget);
     if (one > 0 && (best == 0 || one >= 2 * best)) best = one;
@@ -175,7 +181,7 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
   if (off32 && omax < (1LL << 31) && RI4 == SI4 && RI4 / 4 <= kSwKsMax && 4 % (SO16 / 16) == 0 &&
       4 % (RA16 / 16) == 0 && (int64_t)a.RA * a.RI + (int64_t)a.SI * a.SO <= 256LL * sw_ks_slots(RI4 / 4))
     pl->ks = RI4 / 4;
-  if (pl->nbuf != 2) pl->ks = 0;
+  if (pl->nbuf != 2 || a.prec == 2) pl->ks = 0;  // the register-blocked kernel has no BF16 form
   pl->rem = (pl->ks > 0 && a.prec == 0 && a.og != 1 && a.SO >= 17 && a.SO <= 20 && a.RA >= 17 && a.RA <= 20) ? 1 : 0;
   pl->slice = 0;
   // large factor ranks leave room for a single YL / ZR slice buffer next to
@@ -209,6 +215,25 @@ __device__ __forceinline__ void mfma_pair(const CT *a0, const CT *b0, const CT *
   }
 }
 
+// BF16: the same chains with one K-16 MFMA per four K steps (ksteps is a
+// multiple of 4: the BF16 plans pad K to 16 with zeros).
+template <typename ACC>
+__device__ __forceinline__ void mfma_pair(const __bf16 *a0, const __bf16 *b0, const __bf16 *a1, const __bf16 *b1,
+                                          int lda_k, int ldb_k, int ksteps, ACC &c0, ACC &c1) {
+  for (int k0 = 0; k0 < ksteps; k0 += 4) {
+    __bf16 x0[4], y0[4], x1[4], y1[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      x0[e] = a0[(k0 + e) * lda_k];
+      y0[e] = b0[(k0 + e) * ldb_k];
+      x1[e] = a1[(k0 + e) * lda_k];
+      y1[e] = b1[(k0 + e) * ldb_k];
+    }
+    c0 = mfma16_bf16(x0, y0, c0);
+    c1 = mfma16_bf16(x1, y1, c1);
+  }
+}
+
 // One chain, for a wave whose last tile has no partner.
 template <typename CT, typename ACC>
 __device__ __forceinline__ void mfma_one(const CT *a0, const CT *b0, int lda_k, int ldb_k, int ksteps, ACC &c0) {
@@ -219,12 +244,27 @@ __device__ __forceinline__ void mfma_one(const CT *a0, const CT *b0, int lda_k, 
     }
   }
 }
+template <typename ACC>
+__device__ __forceinline__ void mfma_one(const __bf16 *a0, const __bf16 *b0, int lda_k, int ldb_k, int ksteps,
+                                         ACC &c0) {
+  for (int k0 = 0; k0 < ksteps; k0 += 4) {
+    __bf16 x0[4], y0[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      x0[e] = a0[(k0 + e) * lda_k];
+      y0[e] = b0[(k0 + e) * ldb_k];
+    }
+    c0 = mfma16_bf16(x0, y0, c0);
+  }
+}
 
-// CT: compute and LDS type (FP64, or FP32 for the FP32 range finding); C
-// and the output are stored in CT, YL and ZR (cores of x and y) in FP64.
+// CT: compute and LDS type (FP64, or FP32 / BF16 for the low-precision
+// range finding); C and the output are stored in ST (CT, FP32 for BF16), YL
+// and ZR (cores of x and y) in FP64.
 template <bool LG, typename CT>
 __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPlan pl) {
   using acc_t = typename std::conditional<std::is_same<CT, double>::value, d4_t, f4_t>::type;
+  using ST = typename std::conditional<is_bf16<CT>::value, float, CT>::type;
   extern __shared__ double smraw[];
   CT *sm = reinterpret_cast<CT *>(smraw);
   const int RA = a.RA, RI = a.RI, SI = a.SI, SO = a.SO;
@@ -246,7 +286,7 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
   const int M1p = rup(M1, 16);
 
   // ---- C chunk (fixed for all slices of this block), zero K padding
-  const CT *cbase = reinterpret_cast<const CT *>(static_cast<const void *>(a.c)) + p * a.cb + g0 * a.cg;
+  const ST *cbase = reinterpret_cast<const ST *>(static_cast<const void *>(a.c)) + p * a.cb + g0 * a.cg;
   if (a.cg == 1) {  // g fastest in memory: consecutive threads take consecutive g
     stage_lds<8>(gc * RI * pl.SI4, Rad3(tid, 256, gc, pl.SI4), Cs,  // digits (g, b, a)
                  [&](const Rad3 &d) {
@@ -262,10 +302,10 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
   }
   for (int e = tid; e < (M1p - M1) * pl.SI4; e += 256) {
     const int r = M1 + e / pl.SI4, k = e - (e / pl.SI4) * pl.SI4;
-    Cs[r * pl.ldc + k] = (CT)0;
+    Cs[r * pl.ldc + k] = to_ct<CT>(0.0);
   }
   // rows a >= RI of T are K padding of stage 2: zero once
-  for (int e = tid; e < (pl.RI4 - RI) * pl.ldt; e += 256) Ts[RI * pl.ldt + e] = (CT)0;
+  for (int e = tid; e < (pl.RI4 - RI) * pl.ldt; e += 256) Ts[RI * pl.ldt + e] = to_ct<CT>(0.0);
 
   // ---- YL / ZR slots of this thread: slot u is element tid + 256 u of the
   // padded [ZR | YL] grid; kind 0 = zero padding, 1 = ZR entry, 2 = YL entry
@@ -307,7 +347,7 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
   auto park = [&](CT *buf) {
 #pragma unroll
     for (int u = 0; u < kSwPrefetch; ++u)
-      if (pf_lds[u] >= 0) buf[pf_lds[u]] = (CT)pf[u];
+      if (pf_lds[u] >= 0) buf[pf_lds[u]] = to_ct<CT>(pf[u]);
   };
   // without the register prefetch: stage slice i straight into buf
   auto stage_direct = [&](int64_t i, CT *buf) {
@@ -366,7 +406,7 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
             if (row < M1) {
               const int g = fdiv(row, pl.fd_ri), aa = row - g * RI;
               const int col = LG ? bq * GC + g : g * SO + bq;
-              Ts[aa * pl.ldt + col] = c[v];
+              Ts[aa * pl.ldt + col] = to_ct<CT>(c[v]);
             }
           }
         }
@@ -375,7 +415,7 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
     __syncthreads();
 
     // ---- stage 2: out(a', col) = sum_a YL(a', a) T(a, col)
-    CT *obase = reinterpret_cast<CT *>(static_cast<void *>(a.o)) + p * a.ob + i * a.oi + g0 * a.og;
+    ST *obase = reinterpret_cast<ST *>(static_cast<void *>(a.o)) + p * a.ob + i * a.oi + g0 * a.og;
     for (int t = wave; t < tiles2; t += 8) {
       const int t2 = t + 4;
       const bool two = t2 < tiles2;
@@ -401,11 +441,11 @@ __global__ __launch_bounds__(256) void sandwich_mfma_kernel(SandwichArgs a, SwPl
           bq = col - g * SO;
         }
         if (col < ncols && g < gc) {
-          CT *o = obase + g * a.og + bq * a.obb + (int64_t)tm * a.oa;
+          ST *o = obase + g * a.og + bq * a.obb + (int64_t)tm * a.oa;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int rr = mfma_row<CT>(q4, v);
-            if (tm + rr < RA) o[(int64_t)rr * a.oa] = c[v];
+            if (tm + rr < RA) o[(int64_t)rr * a.oa] = (ST)c[v];
           }
         }
       }
@@ -974,12 +1014,13 @@ const char *sandwich_mfma_name(const SandwichArgs &a, const SwPlan &pl) {
     const int r = (pl.rem && !f && !lg) ? 1 : 0;
     return ks_names[r][f][lg][pl.ks - 1];
   }
+  if (a.prec == 2) return lg ? "sandwich_mfma_kernel<true, __bf16>" : "sandwich_mfma_kernel<false, __bf16>";
   if (a.prec) return lg ? "sandwich_mfma_kernel<true, float>" : "sandwich_mfma_kernel<false, float>";
   return lg ? "sandwich_mfma_kernel<true, double>" : "sandwich_mfma_kernel<false, double>";
 }
 
 hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStream_t s) {
-  const size_t esz = a.prec ? sizeof(float) : sizeof(double);
+  const size_t esz = a.prec == 2 ? sizeof(__bf16) : (a.prec ? sizeof(float) : sizeof(double));
   const size_t lds = (size_t)pl.lds_doubles * esz;
   static bool attr_done = false;  // set once: the maximum a launch may ask for
   if (!attr_done) {
@@ -991,6 +1032,10 @@ hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStre
     (void)hipFuncSetAttribute((const void *)sandwich_mfma_kernel<true, float>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     (void)hipFuncSetAttribute((const void *)sandwich_mfma_kernel<false, float>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    (void)hipFuncSetAttribute((const void *)sandwich_mfma_kernel<true, __bf16>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    (void)hipFuncSetAttribute((const void *)sandwich_mfma_kernel<false, __bf16>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     ks_attrs<1>(mx);
     ks_attrs<2>(mx);
@@ -1009,7 +1054,10 @@ hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStre
   }
   dim3 grid((unsigned)pl.iblocks, (unsigned)pl.chunks, (unsigned)a.batch);
   const bool ks = g_sandwich_ks && pl.ks >= 1 && pl.ks <= kSwKsMax;
-  if (a.prec) {
+  if (a.prec == 2) {
+    if (a.og == 1) sandwich_mfma_kernel<true, __bf16><<<grid, 256, lds, s>>>(a, pl);
+    else sandwich_mfma_kernel<false, __bf16><<<grid, 256, lds, s>>>(a, pl);
+  } else if (a.prec) {
     if (ks) {
       if (a.og == 1) ks_launch<true, float, false>(a, pl, grid, lds, s);
       else ks_launch<false, float, false>(a, pl, grid, lds, s);

@@ -328,20 +328,23 @@ __global__ __launch_bounds__(kBlockThreads) void svd_block_kernel(SvdArgs a, int
 
 // ---------------------------------------------------------------------------
 // Block one-sided Jacobi in registers (64 < nc <= 128, kr <= 128), one
-// workgroup per matrix.  Columns are grouped in blocks of 8 (nb blocks,
-// padded with zero columns to an even count); wave w holds the block pair
-// (top[w], bot[w]): lane group g (lanes 8g .. 8g + 7) holds column g of each
-// block, lane t of the group the rows t + 8 s.  A sweep is
-//   * the pairs inside every block: seven rounds pairing columns g and g ^ x
+// workgroup per matrix.  A column is held by a group of LPC lanes (8 or 16),
+// so a wave holds CB = 64 / LPC columns of each of two blocks.  Columns are
+// grouped in blocks of CB (nb blocks, padded with zero columns to an even
+// count); wave w holds the block pair (top[w], bot[w]): lane group g (lanes
+// LPC g .. LPC g + LPC - 1) holds column g of each block, lane t of the group
+// the rows t + LPC s.  A sweep is
+//   * the pairs inside every block: CB - 1 rounds pairing columns g and g ^ x
 //     of the same block (both lane groups form the same dot products from
 //     the same products in the same order, hence the same rotation);
 //   * the pairs across blocks: nb' - 1 block rounds of the circle order
 //     (top[0] fixed, the others move one position), in each of which the
-//     bot block's columns pass the top block's eight lane groups in eight
-//     steps (a shift by one lane group), so every top column meets every
-//     bot column once; the blocks move between waves through LDS.
+//     bot block's columns pass the top block's CB lane groups in CB steps (a
+//     shift by one lane group), so every top column meets every bot column
+//     once; the blocks move between waves through LDS.
 // A pair is rotated under the same test as the other Jacobi kernels.  The
-// sums over the 8 lanes of a group use DPP (quad permutes, row half mirror).
+// sums over the lanes of a group use DPP (quad permutes, row half mirror,
+// and for 16 lanes the row mirror).
 namespace {
 template <int CTRL>
 __device__ __forceinline__ double svd_dpp(double v) {
@@ -350,10 +353,12 @@ __device__ __forceinline__ double svd_dpp(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
   return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
-__device__ __forceinline__ double g8sum(double v) {
-  v += svd_dpp<0xB1>(v);
-  v += svd_dpp<0x4E>(v);
-  v += svd_dpp<0x141>(v);
+template <int LPC>
+__device__ __forceinline__ double gsum(double v) {
+  v += svd_dpp<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += svd_dpp<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += svd_dpp<0x141>(v);  // row_half_mirror: quads 0 <-> 1 of each 8 lanes
+  if (LPC == 16) v += svd_dpp<0x140>(v);  // row_mirror: halves of each 16 lanes
   return v;
 }
 // 1/x and 1/sqrt(x) from the hardware estimates with Newton steps (the
@@ -399,9 +404,10 @@ __device__ __forceinline__ bool jrot(double (&x)[RPT], double (&y)[RPT], double 
 }
 }  // namespace
 
-template <int RPT>
-__global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
-  extern __shared__ double slots[];  // 2 h blocks of 8 columns x kr rows: [top 0..h-1 | bot 0..h-1]
+template <int LPC, int RPT>
+__global__ __launch_bounds__(LPC * 64) void svd_bj_kernel(SvdArgs a) {
+  constexpr int CB = 64 / LPC;  // columns per block
+  extern __shared__ double slots[];  // 2 h blocks of CB columns x kr rows: [top 0..h-1 | bot 0..h-1]
   __shared__ double sig[kSvdMaxN];
   __shared__ double sigs[kSvdMaxN];
   __shared__ int perm[kSvdMaxN];
@@ -410,22 +416,23 @@ __global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
   const int kr = a.kr, nc = a.nc;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int g = lane >> 3, t = lane & 7;
+  const int g = lane / LPC, t = lane % LPC;
+  const int nt = blockDim.x;
   const int p = blockIdx.x;
   const double *R = a.r + p * a.rbs;
-  int nb = (nc + 7) / 8;
+  int nb = (nc + CB - 1) / CB;
   nb += nb & 1;
   const int h = nb / 2;
   const bool act = w < h;
   const double thr = jacobi_tau(kr);
-  const int bsz = 8 * kr;  // doubles per block slot
+  const int bsz = CB * kr;  // doubles per block slot
   double tv[RPT], bv[RPT];
   // initial blocks: top[w] = block w, bot[w] = block nb - 1 - w
   {
-    const int ct = 8 * w + g, cb = 8 * (nb - 1 - w) + g;
+    const int ct = CB * w + g, cb = CB * (nb - 1 - w) + g;
 #pragma unroll
     for (int s = 0; s < RPT; ++s) {
-      const int r = t + 8 * s;
+      const int r = t + LPC * s;
       tv[s] = (act && r < kr && ct < nc) ? R[r * nc + ct] : 0.0;
       bv[s] = (act && r < kr && cb < nc) ? R[r * nc + cb] : 0.0;
     }
@@ -441,13 +448,13 @@ __global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
     int rot = 0, big = 0;
     if (act) {
       // pairs inside each block
-      for (int x = 1; x < 8; ++x) {
+      for (int x = 1; x < CB; ++x) {
         const bool isp = g < (g ^ x);
         double pt[RPT], pb[RPT];
 #pragma unroll
         for (int s = 0; s < RPT; ++s) {
-          pt[s] = __shfl_xor(tv[s], 8 * x);
-          pb[s] = __shfl_xor(bv[s], 8 * x);
+          pt[s] = __shfl_xor(tv[s], LPC * x);
+          pb[s] = __shfl_xor(bv[s], LPC * x);
         }
         double a1 = 0.0, b1 = 0.0, g1 = 0.0, a2 = 0.0, b2 = 0.0, g2 = 0.0;
 #pragma unroll
@@ -461,12 +468,12 @@ __global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
           b2 += hi2 * hi2;
           g2 += lo2 * hi2;
         }
-        a1 = g8sum(a1);
-        b1 = g8sum(b1);
-        g1 = g8sum(g1);
-        a2 = g8sum(a2);
-        b2 = g8sum(b2);
-        g2 = g8sum(g2);
+        a1 = gsum<LPC>(a1);
+        b1 = gsum<LPC>(b1);
+        g1 = gsum<LPC>(g1);
+        a2 = gsum<LPC>(a2);
+        b2 = gsum<LPC>(b2);
+        g2 = gsum<LPC>(g2);
         big |= (jacobi_live(a1, b1) && g1 * g1 > kJacobiStop2 * (a1 * b1)) |
                (jacobi_live(a2, b2) && g2 * g2 > kJacobiStop2 * (a2 * b2));
         // each lane group updates only its own column of the pair
@@ -481,7 +488,7 @@ __global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
     }
     for (int br = 0; br < nb - 1; ++br) {
       if (act) {
-        for (int st = 0; st < 8; ++st) {
+        for (int st = 0; st < CB; ++st) {
           double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
           for (int s = 0; s < RPT; ++s) {
@@ -489,19 +496,19 @@ __global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
             be += bv[s] * bv[s];
             ga += tv[s] * bv[s];
           }
-          al = g8sum(al);
-          be = g8sum(be);
-          ga = g8sum(ga);
+          al = gsum<LPC>(al);
+          be = gsum<LPC>(be);
+          ga = gsum<LPC>(ga);
           big |= jacobi_live(al, be) && (ga * ga > kJacobiStop2 * (al * be));
           rot |= jrot<RPT>(tv, bv, al, be, ga, thr);
           // the bot columns move on to the next lane group
 #pragma unroll
-          for (int s = 0; s < RPT; ++s) bv[s] = __shfl(bv[s], (lane + 8) & 63);
+          for (int s = 0; s < RPT; ++s) bv[s] = __shfl(bv[s], (lane + LPC) & 63);
         }
         // circle order: publish both blocks
 #pragma unroll
         for (int s = 0; s < RPT; ++s) {
-          const int r = t + 8 * s;
+          const int r = t + LPC * s;
           if (r < kr) {
             slots[w * bsz + g * kr + r] = tv[s];
             slots[(h + w) * bsz + g * kr + r] = bv[s];
@@ -514,7 +521,7 @@ __global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
         const int sb = (w == h - 1) ? (h - 1) : (h + w + 1);  // new bot: bot[h-1] <- top[h-1]
 #pragma unroll
         for (int s = 0; s < RPT; ++s) {
-          const int r = t + 8 * s;
+          const int r = t + LPC * s;
           tv[s] = (r < kr) ? slots[st * bsz + g * kr + r] : 0.0;
           bv[s] = (r < kr) ? slots[sb * bsz + g * kr + r] : 0.0;
         }
@@ -527,27 +534,27 @@ __global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
     if (s_rot == 0 || s_big == 0) break;
     __syncthreads();
   }
-  // final columns into the slots (column index 8 * slot + g), norms, order
+  // final columns into the slots (column index CB * slot + g), norms, order
   double *A = slots;  // column c at A + c * kr
   if (act) {
 #pragma unroll
     for (int s = 0; s < RPT; ++s) {
-      const int r = t + 8 * s;
+      const int r = t + LPC * s;
       if (r < kr) {
-        A[(8 * w + g) * kr + r] = tv[s];
-        A[(8 * (h + w) + g) * kr + r] = bv[s];
+        A[(CB * w + g) * kr + r] = tv[s];
+        A[(CB * (h + w) + g) * kr + r] = bv[s];
       }
     }
   }
   __syncthreads();
-  const int ncp = 8 * nb;
-  for (int c = tid; c < ncp; c += 512) {
+  const int ncp = CB * nb;
+  for (int c = tid; c < ncp; c += nt) {
     double s2 = 0.0;
     for (int r = 0; r < kr; ++r) s2 += A[c * kr + r] * A[c * kr + r];
     sig[c] = jacobi_sigma(s2);
   }
   __syncthreads();
-  for (int c = tid; c < ncp; c += 512) {
+  for (int c = tid; c < ncp; c += nt) {
     int rk = 0;
     const double sc = sig[c];
     for (int j = 0; j < ncp; ++j) rk += (sig[j] > sc) || (sig[j] == sc && j < c);
@@ -559,7 +566,7 @@ __global__ __launch_bounds__(512) void svd_bj_kernel(SvdArgs a) {
   __syncthreads();
   const int rho = s_rho;
   double *U = a.u + p * a.ubs;
-  for (int e = tid; e < kr * a.ucap; e += 512) {
+  for (int e = tid; e < kr * a.ucap; e += nt) {
     const int r = e / a.ucap, j = e - r * a.ucap;
     double v = 0.0;
     if (j < rho) {
@@ -582,20 +589,25 @@ hipError_t launch_svd_trunc(const SvdArgs &a, hipStream_t s) {
     return svd_wave_launch<64>(a, s);
   }
   if (a.nc <= 128 && a.kr <= 128) {
-    // register block Jacobi: the slots hold the whole (padded) matrix
+    // register block Jacobi: the slots hold the whole (padded) matrix; 8
+    // lanes per column (blocks of 8 columns, 512 threads), 8, 12 or 16 rows
+    // per lane.  (16 lanes per column, with blocks of 4 and twice the waves,
+    // measured slower at 128 rows: twice the block rounds and barriers for
+    // the same shuffle traffic.)
+    static bool attr_bj = false;
+    if (!attr_bj) {
+      const int mx = (int)(128 * 128 * sizeof(double));
+      hipFuncSetAttribute((const void *)svd_bj_kernel<8, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+      hipFuncSetAttribute((const void *)svd_bj_kernel<8, 12>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+      hipFuncSetAttribute((const void *)svd_bj_kernel<8, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+      attr_bj = true;
+    }
     int nb = (a.nc + 7) / 8;
     nb += nb & 1;
     const size_t lds = (size_t)nb * 8 * a.kr * sizeof(double);
-    static bool attr_bj = false;
-    if (!attr_bj) {
-      hipFuncSetAttribute((const void *)svd_bj_kernel<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)(16 * 8 * 128 * sizeof(double)));
-      hipFuncSetAttribute((const void *)svd_bj_kernel<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)(16 * 8 * 128 * sizeof(double)));
-      attr_bj = true;
-    }
-    if (a.kr <= 64) svd_bj_kernel<8><<<a.batch, 512, lds, s>>>(a);
-    else svd_bj_kernel<16><<<a.batch, 512, lds, s>>>(a);
+    if (a.kr <= 64) svd_bj_kernel<8, 8><<<a.batch, 512, lds, s>>>(a);
+    else if (a.kr <= 96) svd_bj_kernel<8, 12><<<a.batch, 512, lds, s>>>(a);
+    else svd_bj_kernel<8, 16><<<a.batch, 512, lds, s>>>(a);
     return hipGetLastError();
   }
   if (a.nc > kSvdMaxN || (int64_t)a.nc * a.kr > kQrLdsDoubles) return hipErrorInvalidValue;

@@ -34,6 +34,32 @@ __device__ __forceinline__ int mfma_row(int rq, int v) {
   return std::is_same<CT, double>::value ? rq + 4 * v : 4 * rq + v;
 }
 
+// BF16 operands (BF16 range finding): kept as __bf16 in LDS, accumulated in
+// FP32.  The 16 x 16 x 16 BF16 MFMA takes four K values per lane; lane l,
+// element e is given the operand that the 16 x 16 x 4 layout puts at K step
+// 4 e + l / 16.  The instruction sums over all (l / 16, e), and A and B use
+// the same assignment, so the product is that of the four K steps (a
+// permutation of K).  The result rows held by lane l are the FP32 ones,
+// 4 (l / 16) + v.  K must be padded with zeros to a multiple of 16.
+typedef short s4_t __attribute__((ext_vector_type(4)));
+template <typename CT>
+struct is_bf16 : std::is_same<CT, __bf16> {};
+template <typename CT>
+__device__ __forceinline__ CT to_ct(double x) {
+  return (CT)x;
+}
+template <>
+__device__ __forceinline__ __bf16 to_ct<__bf16>(double x) {
+  return (__bf16)(float)x;  // round to nearest even (through FP32)
+}
+__device__ __forceinline__ short bf16_bits(__bf16 x) { return __builtin_bit_cast(short, x); }
+// One K-16 step: a[e] = A(l % 16, step 4 e + l / 16), b[e] likewise for B.
+__device__ __forceinline__ f4_t mfma16_bf16(const __bf16 (&a)[4], const __bf16 (&b)[4], f4_t c) {
+  const s4_t av = {bf16_bits(a[0]), bf16_bits(a[1]), bf16_bits(a[2]), bf16_bits(a[3])};
+  const s4_t bv = {bf16_bits(b[0]), bf16_bits(b[1]), bf16_bits(b[2]), bf16_bits(b[3])};
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
+}
+
 
 // Three-digit counter (i0 fastest, radices n0, n1) stepped by a fixed stride
 // with carries instead of a division per element.
@@ -74,7 +100,7 @@ __device__ __forceinline__ void stage_lds(int total, Rad3 d, T *dst, Src src, Id
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (e0 + 256 * u < total) dst[di[u]] = (T)v[u];
+      if (e0 + 256 * u < total) dst[di[u]] = to_ct<T>(v[u]);
   }
 }
 

@@ -13,6 +13,18 @@ from typing import Dict, Sequence
 
 # MI355X published peaks used as roofline denominators
 PEAK_FP64_TFLOPS = 78.6      # FP64 vector and FP64 matrix cores alike
+PEAK_FP32_TFLOPS = 157.3     # FP32 (dense, matrix cores)
+PEAK_BF16_TFLOPS = 2500.0    # BF16 (dense, matrix cores)
+
+
+def mfma_peak_tflops(kernel: str) -> float:
+    """Dense matrix-core peak of the type a kernel computes in, read off its
+    name (the FP32 and BF16 range-finding instantiations name their type)."""
+    if "bf16" in kernel:
+        return PEAK_BF16_TFLOPS
+    if "f32" in kernel or "float" in kernel:
+        return PEAK_FP32_TFLOPS
+    return PEAK_FP64_TFLOPS
 PEAK_HBM_GBS = 8000.0
 
 

@@ -216,21 +216,22 @@ def test_precision_option_validation():
     p64 = api.plan(x, x, 6)
     assert p32["ell"] == p64["ell"]
     with pytest.raises(ValueError):
-        api.plan(x, x, 6, precision="bf16")
+        api.plan(x, x, 6, precision="f16")
     with pytest.raises(HattError) as e:
         api.plan(x, x, 6, precision="f32", variant=2)
     assert e.value.status == -7
 
 
 def test_fp32_unsupported_ranks_fail_at_plan():
-    """The FP32 sandwich runs only on the matrix cores (K <= 128 per
-    product): a factor rank of 130 is refused at plan time; FP64 takes it on
-    its vector kernel."""
+    """The FP32 and BF16 sandwiches run only on the matrix cores (K <= 128
+    per product): a factor rank of 130 is refused at plan time; FP64 takes it
+    on its vector kernel."""
     x = _cpu_tt([4, 160, 160, 4], [1, 4, 130, 4, 1])
     y = _cpu_tt([4, 160, 160, 4], [1, 4, 4, 4, 1])
-    with pytest.raises(HattError) as e:
-        api.plan(x, y, 90, precision="f32")
-    assert e.value.status == -7
+    for prec in ("f32", "bf16"):
+        with pytest.raises(HattError) as e:
+            api.plan(x, y, 90, precision=prec)
+        assert e.value.status == -7
     api.plan(x, y, 90)  # FP64 takes it
 
 
@@ -432,3 +433,18 @@ def test_plan3_clamps_with_three_factor_ranks_and_rejects_unsupported():
         st = L.hatt_plan3(ctypes.byref(xv), ctypes.byref(xv), ctypes.byref(xv), ctypes.byref(o), None, None, None)
         assert st == -7
     assert L.hatt_plan3(ctypes.byref(xv), ctypes.byref(xv), None, ctypes.byref(o), None, None, None) == -1
+
+
+def test_precision_option_values():
+    n = [4] * 5
+    x = _cpu_tt(n, [1, 3, 3, 3, 3, 1])
+    p64 = api.plan(x, x, 7)
+    for prec in ("f32", "bf16"):
+        assert api.plan(x, x, 7, precision=prec)["ell"] == p64["ell"]
+    with pytest.raises(HattError) as e:
+        api.plan(x, x, 7, variant=2, ep=0.1, precision="bf16")
+    assert e.value.status == -7
+    L = _lib.lib()
+    xv, kx = x.view()
+    o = _lib.HattOpts(1, 0.0, 7, None, 0, 0.0, 0, 3, None)
+    assert L.hatt_plan(ctypes.byref(xv), ctypes.byref(xv), ctypes.byref(o), None, None, None) == -1
