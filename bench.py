@@ -46,6 +46,8 @@ def _parse():
     ap.add_argument("--rp-train", type=int, default=128, help="rankpred: training recompressions")
     ap.add_argument("--rp-eval", type=int, default=24, help="rankpred: fresh pairs evaluated")
     ap.add_argument("--rp-margin", type=float, default=0.15, help="rankpred: width safety margin")
+    ap.add_argument("--rp-max-rs", type=int, default=1024,
+                    help="rankpred: leave out pairs whose product rank r_x r_y exceeds this (2304 keeps all)")
     ap.add_argument("--workload", choices=["trig", "spectral", "batched", "rankpred", "power", "qtt"], default="trig",
                     help="trig: the metric's tol-1e-8 workload (u2, u3 on the 256^3 grid); spectral: 512 "
                          "order-20 pairs truncated to rank 30; batched: 512 uneven pairs (own JSON lines)")
@@ -642,7 +644,9 @@ def _bench_qtt(args, torch, wk, H) -> int:
 
 def _rp_pairs(wk, H, seed, count, max_rs=1024):
     """Pairs of the uneven 512-pair distribution (spectral cores), leaving
-    out those whose exact rank r_x r_y exceeds the 1024-column SVD limit."""
+    out those whose exact rank r_x r_y exceeds max_rs (--rp-max-rs; the
+    library truncates up to 3072 columns, so 2304 keeps every pair, at the
+    cost of tolerance-mode widths in the thousands on the widest ones)."""
     out = []
     for p, (d, n, rx, ry) in enumerate(wk.batched_pair_shapes(seed, 8 * count)):
         if rx * ry > max_rs:
@@ -662,7 +666,7 @@ def _bench_rankpred(args, torch, wk, H) -> int:
     import numpy as np
     tol = wk.WORKLOADS["batched"]["tol"]
     say = lambda m: print(f"[rankpred] {m}", file=sys.stderr, flush=True)  # noqa: E731
-    train = _rp_pairs(wk, H, 101, args.rp_train)
+    train = _rp_pairs(wk, H, 101, args.rp_train, args.rp_max_rs)
     say(f"{len(train)} training pairs")
     labels, t_label = [], 0.0
     for i, (shape, x, y) in enumerate(train):
@@ -694,7 +698,7 @@ def _bench_rankpred(args, torch, wk, H) -> int:
     lh = loss.cpu().numpy()
     say(f"trained {steps} Adam steps on {rows} bond rows in {t_train:.2f} s; loss {lh[:20].mean():.3g} -> "
         f"{lh[-100:].mean():.3g}")
-    fresh = _rp_pairs(wk, H, 202, args.rp_eval)
+    fresh = _rp_pairs(wk, H, 202, args.rp_eval, args.rp_max_rs)
     rec = []
     for i, (shape, x, y) in enumerate(fresh):
         torch.cuda.synchronize()
@@ -722,7 +726,7 @@ def _bench_rankpred(args, torch, wk, H) -> int:
     line = {"metric": "learned start widths: adaptive recompression time without / with the predictor",
             "value": tp / tq, "unit": "x", "n_gpus": 1, "higher_is_better": True, "dtype": "f64 (network f32)",
             "data": "synthetic",
-            "config": {"workload": f"uneven pairs d 8..32, n {{16,32,64}}, r 8..48 with r_x r_y <= 1024, spectral "
+            "config": {"workload": f"uneven pairs d 8..32, n {{16,32,64}}, r 8..48 with r_x r_y <= {args.rp_max_rs}, spectral "
                                    f"cores, tol {tol:g}, margin {args.rp_margin}",
                        "train_pairs": len(train), "train_rows": int(rows), "eval_pairs": len(fresh)},
             "train": {"label_s": t_label, "train_s": t_train, "steps": steps, "minibatch": bsz,

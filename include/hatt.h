@@ -182,10 +182,10 @@ HATT_API hatt_status hatt_recompress_batched(int32_t npairs, const hatt_tt *x, c
  *   accept when every bond keeps rho_k <= l_k - p or l_k is at its largest
  *   feasible value; else on each failing bond (failing for any train of the
  *   batch) l_k = min(cap_k, ceil(1.5 l_k) + p) and retry.
- * Widths never grow beyond 1024 (the truncation's SVD limit): a bond that
+ * Widths never grow beyond 3072 (the truncation's SVD limit): a bond that
  * would need more returns HATT_ENOTCONV.
  * hatt_adaptive_plan: cap_out (host [d+1]) = largest widths the growth may
- * reach (the feasible widths, clamped to 1024), ws_bytes = workspace for any
+ * reach (the feasible widths, clamped to 3072), ws_bytes = workspace for any
  * attempt, out_elems = elements of one output train at those widths (the
  * per-train slot size).
  * hatt_recompress_adaptive: first checks that x and y hold only finite

@@ -652,7 +652,7 @@ def rankpred_widths(pairs, pred, margin: float = 0.0, oversample: int = 8):
 
 def adaptive_caps(x: TT, y: TT) -> List[int]:
     """Largest widths the tolerance mode may use for a pair: the feasible
-    widths (the clamp of r_k s_k) limited to the 1024-column truncation."""
+    widths (the clamp of r_k s_k) limited to the 3072-column truncation."""
     xv, kx = x.view()
     yv, ky = y.view()
     o = HattAdaptOpts(1.0, 0, 8, 1, 1, 0.0, None, 0)

@@ -12,7 +12,11 @@ namespace hatt {
 // Largest column count of one TSQR panel and of the in-LDS Jacobi SVD.
 constexpr int kQrMaxCols = 128;
 constexpr int kSvdMaxN = 139;
-constexpr int kSvdBigMaxN = 1024;
+// Largest column count of the block Jacobi SVD over global memory: its
+// finishing kernel sorts the singular values in static LDS (20 bytes per
+// column, within the 64 KiB of static LDS a kernel may declare).  3072
+// columns hold every bond product r_k s_k of the uneven batches (<= 48 x 48).
+constexpr int kSvdBigMaxN = 3072;
 // Doubles of dynamic LDS a TSQR block may use (of the 160 KiB per CU).
 constexpr int kQrLdsDoubles = 19456;
 

@@ -720,7 +720,10 @@ hatt_status qr_exec(bool run, const QrOp &op, CMat A, Mat Q, Mat R, int64_t rbuf
 // SVD + rank choice dispatch: one-workgroup Jacobi when the matrix fits in
 // LDS, else block Jacobi over global memory (scratch `big` of kr*nc doubles
 // per pair plus 2 ints).
-constexpr int kBigSweeps = 14;
+// Sweeps enqueued for the block Jacobi (a sweep after convergence returns at
+// once on the device flags, so spare sweeps cost only their launches): 24
+// covers dense random 1296-column matrices, which 14 did not.
+constexpr int kBigSweeps = 24;
 
 int64_t svd_ws_doubles(int kr, int nc) {
   if (nc <= kSvdMaxN && (int64_t)kr * nc <= kQrLdsDoubles) return 0;
@@ -737,7 +740,8 @@ hatt_status svd_exec(bool run, const SvdArgs &sa, double *big, int64_t bigp, int
     return gemm(run, gc, CMat{sa.u, 1, sa.ucap, sa.ubs}, CMat{sa.r, sa.nc, 1, sa.rbs}, Mat{sa.svt, sa.nc, 1, sa.sbs},
                 sa.ucap, sa.nc, sa.kr, 1.0, 0.0, sa.batch, st, true);
   }
-  if (sa.nc > kSvdBigMaxN) return fail(HATT_EUNSUPPORTED, "SVD of more than 1024 columns is not built");
+  if (sa.nc > kSvdBigMaxN)
+    return fail(HATT_EUNSUPPORTED, "SVD of more than " + std::to_string(kSvdBigMaxN) + " columns is not built");
   const int bw = svd_big_block_width(sa.kr);
   if (bw < 1) return fail(HATT_EUNSUPPORTED, "SVD column too long for the block Jacobi");
   int nb = (sa.nc + bw - 1) / bw;

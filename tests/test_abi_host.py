@@ -136,13 +136,15 @@ def test_null_arguments_are_rejected():
 
 
 def test_unsupported_widths_are_reported():
-    # truncating a sketch wider than the library's largest SVD is refused
-    n = [2048, 2048, 2048]
-    x = _cpu_tt(n, [1, 40, 40, 1])
-    p = api.plan(x, x, 1100)            # no truncation: any width is fine
-    assert p["ell"] == [1, 1100, 1100, 1][:1] + [1100, 1100] + [1]
+    # truncating a sketch wider than the library's largest SVD (3072
+    # columns) is refused; 1100 columns are truncated
+    n = [4096, 4096, 4096]
+    x = _cpu_tt(n, [1, 60, 60, 1])
+    api.plan(x, x, 1100, tol=1e-6)
+    p = api.plan(x, x, 3100)            # no truncation: any width is fine
+    assert p["ell"] == [1, 3100, 3100, 1]
     with pytest.raises(HattError) as e:
-        api.plan(x, x, 1100, tol=1e-6)
+        api.plan(x, x, 3100, tol=1e-6)
     assert e.value.status == -7
     assert b"SVD" in _lib.lib().hatt_last_error()
 
@@ -305,20 +307,20 @@ def test_adaptive_start_widths_are_validated():
 
 
 def test_adaptive_plan_limits_widths_to_the_svd_limit():
-    """A QTT pair (order 24, mode size 2) with ranks 33 and 40 has feasible
-    widths up to 1320; the tolerance mode plans its workspace for widths clamped to
-    the 1024-column truncation, and every width stays feasible."""
+    """A QTT pair (order 28, mode size 2) with ranks 60 and 64 has feasible
+    widths up to 3840; the tolerance mode plans its workspace for widths clamped to
+    the 3072-column truncation, and every width stays feasible."""
     from oracle import plan as oplan
-    d = 24
-    rx = [1] + [min(2 ** k, 2 ** (d - k), 33) for k in range(1, d)] + [1]
-    ry = [1] + [min(2 ** k, 2 ** (d - k), 40) for k in range(1, d)] + [1]
+    d = 28
+    rx = [1] + [min(2 ** k, 2 ** (d - k), 60) for k in range(1, d)] + [1]
+    ry = [1] + [min(2 ** k, 2 ** (d - k), 64) for k in range(1, d)] + [1]
     n = [2] * d
     x, y = _cpu_tt(n, rx), _cpu_tt(n, ry)
     caps = api.adaptive_caps(x, y)
     full = oplan.clamp_ell(n, rx, ry, [1] + [1 << 40] * (d - 1) + [1])
-    assert max(full) == 1320
-    assert caps == oplan.clamp_ell(n, rx, ry, [min(c, 1024) for c in full])
-    assert max(caps) == 1024
+    assert max(full) == 3840
+    assert caps == oplan.clamp_ell(n, rx, ry, [min(c, 3072) for c in full])
+    assert max(caps) == 3072
 
 
 def test_plan_rejects_sandwich_shapes_without_a_kernel():

@@ -877,11 +877,11 @@ def test_hatt_panelled_rank_deficient_square_frames(method):
     assert tt.rel_err(rnd.train(0), ref) <= TOL
 
 
-def test_adaptive_widths_stop_at_svd_limit():
-    """The tolerance mode plans and grows widths only up to the 1024-column
-    truncation limit: (phi (.) phi) (.) phi on the 512^3 grid (order 27) has
-    feasible widths up to 2048 at the middle bonds; it plans, and its
-    attempts, widths, ranks and tensor equal the oracle's."""
+def test_adaptive_widths_below_svd_limit():
+    """(phi (.) phi) (.) phi on the 512^3 grid (order 27) has feasible widths
+    up to 2640 (88 x 30) at the middle bonds, all below the 3072-column
+    truncation limit: the tolerance mode plans for them, and its attempts,
+    widths, ranks and tensor equal the oracle's."""
     from oracle import adapt
     phi, _, _ = wk.qtt_trig_field(9, 9, terms=15)
     outs, _, _, ok = adapt.hatt_adaptive([(phi, phi)], tol=1e-8, seed=1)
@@ -889,8 +889,8 @@ def test_adaptive_widths_stop_at_svd_limit():
     u2 = outs[0]
     X, P = H.TT.from_cores(u2), H.TT.from_cores(phi)
     caps = H.adaptive_caps(X, P)
-    assert max(caps) == 1024
-    _say("adaptive plan with widths limited to 1024 (QTT order 27)")
+    assert max(caps) == 2640
+    _say("adaptive plan with feasible widths up to 2640 (QTT order 27)")
     r3, ell3, att3 = H.recompress_adaptive(X, P, 1e-8, seed=2)
     torch.cuda.synchronize()
     ref, l_ref, att_ref, ok = adapt.hatt_adaptive([(u2, phi)], tol=1e-8, seed=2)
@@ -956,3 +956,29 @@ def test_sandwich_large_ranks_slice_major_matches_oracle(shape):
     got = _gpu_hatt([y], [z], ell, seed=40 + r)
     assert tt.ranks(got.train(0)) == tt.ranks(ref)
     assert tt.rel_err(got.train(0), ref) <= TOL
+
+
+@pytest.mark.parametrize("kind", ["gaussian_cap_1100", "spectral_tol"])
+def test_round_svd_above_1024_columns(kind):
+    """A bond of rank 1296 (n = 36, order 4): the truncation's SVD of a
+    1296-column R runs the block Jacobi over global memory (7-column blocks,
+    185 rounds per sweep) past the former 1024-column limit; capped at 1100
+    (random cores, all singular values of order one) and by tol 1e-8
+    (spectral cores), against the oracle's TT-Rounding."""
+    n = [36] * 4
+    ranks = [1, 36, 1296, 36, 1]
+    rng = np.random.default_rng(1296)
+    if kind == "gaussian_cap_1100":
+        a = wk.gaussian_tt(rng, n, ranks)
+        kw = {"max_rank": 1100}
+    else:
+        a = wk.spectral_tt(rng, n, ranks)
+        kw = {"tol": 1e-8}
+    _say(f"tt_round {kind}: bond rank 1296 -> SVD of 1296 columns")
+    res = H.round(H.TT.from_cores([a]), **kw)
+    torch.cuda.synchronize()
+    ref = rounding.tt_round(a, max_rank=kw.get("max_rank"), tol=kw.get("tol", 0.0))
+    got = res.train(0)
+    _say(f"  ranks {tt.ranks(got)} vs {tt.ranks(ref)}")
+    assert tt.ranks(got) == tt.ranks(ref)
+    assert tt.rel_err(got, ref) <= TOL
