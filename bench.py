@@ -43,6 +43,9 @@ def _parse():
     ap.add_argument("--precision", choices=["f64", "f32", "bf16"], default="f64",
                     help="f32 / bf16: range finding on the FP32 / BF16 matrix cores, projection and "
                          "truncation in FP64")
+    ap.add_argument("--tune", action="store_true",
+                    help="trig / spectral / batched: one untimed step in the autotuner's record mode, then the "
+                         "timed steps with the recorded kernel choices (use mode)")
     ap.add_argument("--rp-train", type=int, default=128, help="rankpred: training recompressions")
     ap.add_argument("--rp-eval", type=int, default=24, help="rankpred: fresh pairs evaluated")
     ap.add_argument("--rp-margin", type=float, default=0.15, help="rankpred: width safety margin")
@@ -187,7 +190,8 @@ def _bench_batched(args, torch, wk, H) -> int:
     for p, (d, n, rx, ry) in enumerate(shapes):
         y, z = wk.spectral_pair(20000 + p, d, n, rx, ry)
         pairs.append((H.TT.from_cores([y]), H.TT.from_cores([z])))
-    plan = H.batched_plan(pairs, 0, tol=cfg["tol"], seed=77)
+    _tune_begin(args, H)
+    plan = H.batched_plan(pairs, 0, tol=cfg["tol"], seed=77, precision=args.precision)
     ws = torch.empty(plan["ws_bytes"], dtype=torch.uint8, device="cuda")
     out = torch.zeros(plan["out_offset"][-1], dtype=torch.float64, device="cuda")
     ranks = torch.zeros(plan["rank_offset"][-1], dtype=torch.int64, device="cuda")
@@ -195,11 +199,13 @@ def _bench_batched(args, torch, wk, H) -> int:
           file=sys.stderr, flush=True)
 
     def eager_step():
-        return H.recompress_batched(pairs, 0, tol=cfg["tol"], seed=77, workspace=ws, out=out, ranks=ranks)
+        return H.recompress_batched(pairs, 0, tol=cfg["tol"], seed=77, precision=args.precision, workspace=ws,
+                                    out=out, ranks=ranks)
 
     # eager launches: a capture of all 512 pairs (some 10^5 kernel nodes in
     # four long chains) ended the process on the host; graph capture of the
     # uneven path is exercised at a dozen pairs by the tests
+    tune = _tune_step(args, H, eager_step, torch)
     res = eager_step()
     torch.cuda.synchronize()
     step = eager_step
@@ -231,16 +237,46 @@ def _bench_batched(args, torch, wk, H) -> int:
     line = {"metric": "HaTT recompressions/s, uneven batch of 512 pairs", "value": value,
             "unit": "recompressions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": 1000.0 * wall_s / args.steps, "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "vs_baseline": None, "dtype": "f64" if args.precision == "f64" else args.precision + "+f64",
+            "data": "synthetic",
             "config": {"workload": "batched: 512 pairs, d 8..32, n {16,32,64}, r 8..48, l = max(r,s)+8, tol 1e-6",
+                       "precision": args.precision,
                        "launch": "eager, 32 library streams, GPU_MAX_HW_QUEUES="
                                  + os.environ.get("GPU_MAX_HW_QUEUES", "default")},
+            "autotuner": tune,
             "mean_kept_rank": float(np.mean([max(k) for k in kept])),
             "tolerance_check": {"bonds": nbond, "bonds_without_slack": int(sum(tight)),
                                 "pairs_with_slack_on_every_bond": int(sum(1 for t in tight if t == 0)),
                                 "sample": errs}}
     print(json.dumps(line), flush=True)
     return 0
+
+
+def _tune_begin(args, H):
+    """--tune: the autotuner's record mode from here on.  It comes before the
+    workload's plans, whose workspaces then cover the split-K partials of
+    every candidate the recording step times."""
+    if args.tune:
+        H.tune_clear()
+        H.tune("record")
+
+
+def _tune_step(args, H, step, torch):
+    """--tune: one untimed step in record mode (every shape bucket's
+    candidates timed once), then use mode for everything after.  Returns the
+    line's "autotuner" field (None without --tune)."""
+    if not args.tune:
+        return None
+    t0 = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    rec_s = time.perf_counter() - t0
+    H.tune("use")
+    table = H.tune_table()
+    print("[bench] autotuner table:\n" + table, file=sys.stderr, flush=True)
+    rows = [ln for ln in table.splitlines() if ln.strip()]
+    return {"mode": "use", "buckets": len(rows), "record_step_s": rec_s,
+            "table": rows[:64], "table_truncated": len(rows) > 64}
 
 
 def _calib_copy(args, torch):
@@ -279,6 +315,7 @@ def _bench_trig(args, torch, wk, H, perfmodel) -> int:
     say = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)  # noqa: E731
     u = wk.trig_u(11, n=cfg["n"], terms=2 * cfg["nfreq"], nfreq=cfg["nfreq"])
     U = H.TT.from_cores(u)
+    _tune_begin(args, H)
     p2 = H.plan(U, U, l2, tol=tol, seed=s2, precision=args.precision)
     ws2 = torch.empty(p2["ws_bytes"], dtype=torch.uint8, device="cuda")
     out2 = H.TT.empty(U.n, p2["ell"], 1)
@@ -306,6 +343,7 @@ def _bench_trig(args, torch, wk, H, perfmodel) -> int:
 
     _calib_copy(args, torch)
     say(f"trig 256^3: u2 at width {l2}, u3 at width {l3}, tol {tol:g}, precision {args.precision}")
+    tune = _tune_step(args, H, step, torch)
     for _ in range(max(args.warmup, 1)):
         r2, U2, r3 = step()
     torch.cuda.synchronize()
@@ -447,6 +485,7 @@ def _bench_trig(args, torch, wk, H, perfmodel) -> int:
                                f"products), sketch widths {ell2[1]} / {ell3[1]}, TT-Rounding at tol {tol:g}",
                    "recompressions_per_step": 2, "variant": "HaTT-1", "launch": "eager",
                    "precision": args.precision},
+        "autotuner": tune,
         "rel_err_vs_closed_form": {"u2": e2, "u3": e3},
         "kept_ranks": {"u2": kept2, "u3": kept3},
         "ms_per_product": {"u2": t2, "u3": t3},
@@ -791,6 +830,7 @@ def main() -> int:
     pairs = [wk.spectral_pair(1000 + b, d, n, r, r) for b in range(B)]
     x = H.TT.from_cores([p[0] for p in pairs])
     y = H.TT.from_cores([p[1] for p in pairs])
+    _tune_begin(args, H)
     p = H.plan(x, y, ell, max_rank=cap, seed=seed, precision=args.precision)
     out = H.TT.empty(x.n, p["ell"], B)
     ranks = torch.empty((B, d + 1), dtype=torch.int64, device="cuda")
@@ -804,6 +844,7 @@ def main() -> int:
 
     print(f"[bench] warmup {args.warmup} steps, batch {B}, workspace {p['ws_bytes'] / 2**20:.1f} MiB",
           file=sys.stderr, flush=True)
+    tune = _tune_step(args, H, step, torch)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -930,6 +971,7 @@ def main() -> int:
         "config": {"workload": f"spectral d={d} n={n} r_x=r_y={r} sketch={ell} max_rank={cap}",
                    "pairs_per_step": B, "variant": "HaTT-1", "seed": seed, "launch": mode,
                    "precision": args.precision},
+        "autotuner": tune,
         "roofline": roof,
         "cpu_baseline": cpu,
         "step_tflops_algorithmic": step_tflops,

@@ -350,6 +350,33 @@ HATT_API hatt_status hatt_sketch_fill(uint64_t seed, int32_t d, const int64_t *n
 HATT_API hatt_status hatt_set_qr_method(int32_t method);
 
 /*
+ * Autotuner (shape buckets to kernel choices; not in the paper).  Mode 0
+ * (default): the fixed tile and kernel rules.  Mode 1 (record): the first
+ * launch of each shape bucket times its candidates on the caller's stream
+ * (a host wait per candidate, so a recording call is slow and synchronises)
+ * and keeps the fastest for that bucket; later launches reuse it.  Mode 2
+ * (use): recorded choices only, no timing; unseen buckets take the fixed
+ * rules.  Buckets: a GEMM by (M, N, K, batch, compute type, operand
+ * layouts), its candidate K splits 1, 2, 4 .. 64; a sandwich contraction by
+ * its shapes, output layout and type, its candidates the matrix-core plan
+ * with and without the register-blocked and slice-major kernels, smaller
+ * sketch-column chunks, and (FP64) the vector-ALU kernels.  Choices change
+ * only the summation order of split-K products (results agree to rounding).
+ * Nothing is timed while the stream is captured into a graph, nor a GEMM
+ * that accumulates into its output.  The table is per process, shared by all
+ * devices and threads (it is guarded by a mutex).
+ * hatt_tune_mode: sets the mode (HATT_EINVAL outside 0..2).
+ * hatt_tune_clear: empties the table.
+ * hatt_tune_table: writes the table as text, one bucket per line
+ * ("<bucket> -> <choice>  <us> us (fixed rules <us> us)"), NUL-terminated and
+ * cut to cap bytes, into buf (may be NULL); returns the bytes the whole table
+ * needs, terminator included.
+ */
+HATT_API hatt_status hatt_tune_mode(int32_t mode);
+HATT_API hatt_status hatt_tune_clear(void);
+HATT_API int64_t hatt_tune_table(char *buf, int64_t cap);
+
+/*
  * Instrumentation (not thread-safe; for benchmarks).  Between
  * hatt_profile_start() and hatt_profile_stop() every kernel launch the
  * library enqueues is bracketed by two HIP events on the launching stream

@@ -42,6 +42,9 @@ from .api import (  # noqa: F401
     check_finite,
     set_qr_method,
     sketch_fill,
+    tune,
+    tune_clear,
+    tune_table,
     version,
 )
 from ._lib import HattError  # noqa: F401,E402

@@ -24,6 +24,7 @@ EXPORTED = [
     "hatt_rankpred_features", "hatt_rankpred_fit_stats", "hatt_rankpred_forward", "hatt_rankpred_ws_bytes",
     "hatt_rankpred_grad", "hatt_rankpred_train_step", "hatt_rankpred_widths", "hatt_rankpred_labels",
     "hatt_plan3", "hatt_recompress3", "hatt_adaptive_plan3", "hatt_recompress3_adaptive",
+    "hatt_tune_mode", "hatt_tune_clear", "hatt_tune_table",
 ]
 RANKPRED_NIN, RANKPRED_NTHETA, RANKPRED_NSTATS = 21, 19586, 46
 PROFILE_CLASSES = 8
@@ -133,12 +134,15 @@ def lib() -> ctypes.CDLL:
     L.hatt_profile_class_name.restype = ctypes.c_char_p
     for fn in EXPORTED:
         if fn not in ("hatt_profile_class_name", "hatt_last_error", "hatt_version", "hatt_profile_report",
-                      "hatt_rankpred_ws_bytes"):
+                      "hatt_rankpred_ws_bytes", "hatt_tune_table"):
             getattr(L, fn).restype = ctypes.c_int
     L.hatt_last_error.restype = ctypes.c_char_p
     L.hatt_version.restype = ctypes.c_char_p
     L.hatt_profile_report.restype = ctypes.c_char_p
     L.hatt_rankpred_ws_bytes.restype = ctypes.c_size_t
+    L.hatt_tune_table.restype = ctypes.c_int64
+    L.hatt_tune_table.argtypes = [ctypes.c_char_p, ctypes.c_int64]
+    L.hatt_tune_mode.argtypes = [ctypes.c_int32]
     _lib = L
     return L
 

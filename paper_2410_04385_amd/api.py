@@ -207,14 +207,14 @@ def recompress_noalloc(x: TT, y: TT, ell, *, max_rank: int = 0, tol: float = 0.0
 
 
 def batched_plan(pairs, ell: int = 0, *, max_rank: int = 0, tol: float = 0.0, seed: int = 0, variant: int = 1,
-                 ep: float = 0.0):
+                 ep: float = 0.0, precision: str = "f64"):
     """Plan of recompress_batched: per-pair output and rank offsets, widths,
     workspace bytes."""
     npairs = len(pairs)
     views = [(x.view(), y.view()) for x, y in pairs]
     xs = (HattTT * npairs)(*[v[0][0] for v in views])
     ys = (HattTT * npairs)(*[v[1][0] for v in views])
-    o, _ = _opts(int(ell), max_rank, tol, seed, variant, ep, 0)
+    o, _ = _opts(int(ell), max_rank, tol, seed, variant, ep, 0, precision)
     oo = (ctypes.c_int64 * (npairs + 1))()
     ro = (ctypes.c_int64 * (npairs + 1))()
     ne = sum(x.d + 1 for x, _ in pairs)
@@ -231,16 +231,19 @@ def batched_plan(pairs, ell: int = 0, *, max_rank: int = 0, tol: float = 0.0, se
 
 
 def recompress_batched(pairs, ell: int = 0, *, max_rank: int = 0, tol: float = 0.0, seed: int = 0,
-                       variant: int = 1, ep: float = 0.0, workspace: Optional[torch.Tensor] = None,
-                       out: Optional[torch.Tensor] = None, ranks: Optional[torch.Tensor] = None,
-                       stream=None) -> List[Result]:
+                       variant: int = 1, ep: float = 0.0, precision: str = "f64",
+                       workspace: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                       ranks: Optional[torch.Tensor] = None, stream=None) -> List[Result]:
     """Uneven batch: ``pairs`` is a list of (x, y) TT pairs of any shapes;
     pair p uses the sketch keyed by seed + p; ell <= 0 asks for
     l_k = max(r_k, s_k) + 8.  ``out`` / ``ranks`` (flat float64 / int64
     device tensors of at least out_offset[-1] / rank_offset[-1] elements of
-    batched_plan) may be passed in, e.g. for graph capture.  Returns one
-    Result per pair (views into one output buffer)."""
-    p = batched_plan(pairs, ell, max_rank=max_rank, tol=tol, seed=seed, variant=variant, ep=ep)
+    batched_plan) may be passed in, e.g. for graph capture.  ``precision``
+    "f32" / "bf16": every pair's HPCRL on the FP32 / BF16 matrix cores, the
+    sweep and truncation in FP64.  Returns one Result per pair (views into one
+    output buffer)."""
+    p = batched_plan(pairs, ell, max_rank=max_rank, tol=tol, seed=seed, variant=variant, ep=ep,
+                     precision=precision)
     views, xs, ys = p["_keep"]
     dev = pairs[0][0].data.device
     if out is None:
@@ -253,7 +256,7 @@ def recompress_batched(pairs, ell: int = 0, *, max_rank: int = 0, tol: float = 0
         raise ValueError("ranks must be int64 with rank_offset[-1] elements")
     if workspace is None or workspace.numel() < p["ws_bytes"]:
         workspace = torch.empty(max(p["ws_bytes"], 1), dtype=torch.uint8, device=dev)
-    o, _ = _opts(int(ell), max_rank, tol, seed, variant, ep, 0)
+    o, _ = _opts(int(ell), max_rank, tol, seed, variant, ep, 0, precision)
     check("hatt_recompress_batched", lib().hatt_recompress_batched(
         len(pairs), xs, ys, ctypes.byref(o), ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ranks.data_ptr()),
         ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr(stream)))
@@ -524,6 +527,30 @@ def set_qr_method(method: str) -> None:
     if method not in codes:
         raise ValueError(f"unknown QR method {method!r}")
     check("hatt_set_qr_method", lib().hatt_set_qr_method(codes[method]))
+
+
+_TUNE = {"off": 0, "record": 1, "use": 2}
+
+
+def tune(mode: str) -> None:
+    """Autotuner mode: "off" (fixed rules), "record" (time the candidates of
+    each new shape bucket on first use, keep the fastest) or "use" (recorded
+    choices only)."""
+    if mode not in _TUNE:
+        raise ValueError(f"tune mode must be one of {sorted(_TUNE)}")
+    check("hatt_tune_mode", lib().hatt_tune_mode(_TUNE[mode]))
+
+
+def tune_clear() -> None:
+    check("hatt_tune_clear", lib().hatt_tune_clear())
+
+
+def tune_table() -> str:
+    """The recorded choices, one shape bucket per line."""
+    need = int(lib().hatt_tune_table(None, 0))
+    buf = ctypes.create_string_buffer(need)
+    lib().hatt_tune_table(buf, need)
+    return buf.value.decode()
 
 
 def version() -> str:

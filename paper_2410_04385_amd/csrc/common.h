@@ -65,7 +65,14 @@ struct SandwichArgs {
   int prec;            // 1: C and out are FP32 and the products run on the FP32 matrix cores;
                        // 2: C and out are FP32, the products run on the BF16 matrix cores
 };
-hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s);
+// Overrides of the sandwich kernel choice (the autotuner's candidates):
+// no_ks / no_slice rule out the register-blocked / slice-major kernels,
+// gc_div divides the chunk of sketch columns per block, valu takes the
+// vector-ALU kernels instead of the matrix-core plan (FP64 only).
+struct SwForce {
+  int no_ks = 0, no_slice = 0, gc_div = 1, valu = 0;
+};
+hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s, const SwForce *force = nullptr);
 // Whether launch_sandwich has a kernel for these shapes (checked on the host
 // before anything is enqueued).
 bool sandwich_supported(const SandwichArgs &a);
@@ -103,12 +110,12 @@ struct SwPlan {
                               // once, the sketch columns streamed in chunks of GC)
   int gpb, gblocks;           // slice-major: sketch columns per block, blocks along g
 };
-bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl);
+bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl, const SwForce *force = nullptr);
 hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStream_t s);
 // Name of the compiled kernel launch_sandwich_mfma runs for this plan.
 const char *sandwich_mfma_name(const SandwichArgs &a, const SwPlan &pl);
 // Name of the compiled kernel launch_sandwich picks for these arguments.
-const char *sandwich_kernel_name(const SandwichArgs &a);
+const char *sandwich_kernel_name(const SandwichArgs &a, const SwForce *force = nullptr);
 
 // dst[p * dbs + k] = (float) src[p * sbs + k] for k < count, p < batch.
 hipError_t launch_cast_f32(const double *src, int64_t sbs, float *dst, int64_t dbs, int64_t count, int batch,

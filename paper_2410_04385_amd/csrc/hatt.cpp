@@ -238,6 +238,136 @@ struct GemmTypes {
   int prec = 0, a32 = 0, b32 = 0, c32 = 0;
 };
 
+// ---------------------------------------------------------------------------
+// Autotuner.  In record mode the first launch of a shape bucket times its
+// candidate configurations on the caller's stream (one untimed and three
+// timed launches each, HIP events, a host wait) and keeps the fastest; use
+// mode takes the recorded choices and leaves unseen buckets to the fixed
+// rules.  Buckets: a GEMM by (M, N, K, batch, compute type, operand layouts),
+// its candidates the K splits 1..64; a sandwich by (its shapes, output
+// layout, type), its candidates the kernel and chunk choices of SwForce.
+// Tuning is skipped while the stream is being captured into a graph and for
+// a GEMM that accumulates into C (its repeated launches would not be
+// idempotent).
+struct TuneEntry {
+  int ks = 1;
+  SwForce f{};
+  double us = 0.0, us_default = 0.0;
+  std::string choice;
+};
+std::mutex g_tune_mu;
+int g_tune_mode = 0;
+std::map<std::string, TuneEntry> g_tune;
+
+bool stream_capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+bool tune_get(const std::string &key, TuneEntry *e) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  *e = it->second;
+  return true;
+}
+
+void tune_put(const std::string &key, const TuneEntry &e) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune[key] = e;
+}
+
+// Microseconds per launch of fn on st (one untimed launch first); < 0 when a
+// launch fails.
+template <class F>
+double time_launches(hipStream_t st, F fn) {
+  constexpr int reps = 3;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
+  double us = -1.0;
+  bool ok = fn() == hipSuccess && hipEventRecord(e0, st) == hipSuccess;
+  for (int r = 0; ok && r < reps; ++r) ok = fn() == hipSuccess;
+  float ms = 0.0f;
+  if (ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+      hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+    us = 1000.0 * ms / reps;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return us;
+}
+
+std::string sandwich_tune_key(const SandwichArgs &a) {
+  char b[160];
+  // the unit-stride flags tell the W_L build from the core update of equal shapes
+  snprintf(b, sizeof b, "sandwich RA=%d RI=%d SI=%d SO=%d n=%lld G=%lld batch=%d og1=%d cg1=%d ylr1=%d prec=%d", a.RA,
+           a.RI, a.SI, a.SO, (long long)a.n, (long long)a.G, a.batch, a.og == 1 ? 1 : 0, a.cg == 1 ? 1 : 0,
+           a.ylr == 1 ? 1 : 0, a.prec);
+  return b;
+}
+
+// The sandwich override for this launch (false: the fixed rules); in record
+// mode an unseen bucket is tuned here first.
+bool sandwich_tune(bool run, const SandwichArgs &a, hipStream_t st, SwForce *out) {
+  if (g_tune_mode == 0) return false;
+  const std::string key = sandwich_tune_key(a);
+  TuneEntry e;
+  if (tune_get(key, &e)) {
+    *out = e.f;
+    return true;
+  }
+  if (g_tune_mode != 1 || !run || stream_capturing(st)) return false;
+  std::vector<SwForce> cands(1);  // the fixed rules first
+  SwForce f;
+  f.no_ks = 1;
+  cands.push_back(f);
+  f = SwForce{};
+  f.no_slice = 1;
+  cands.push_back(f);
+  for (int div : {2, 4}) {
+    f = SwForce{};
+    f.gc_div = div;
+    cands.push_back(f);
+  }
+  if (a.prec == 0) {
+    f = SwForce{};
+    f.valu = 1;
+    cands.push_back(f);
+  }
+  // distinct launches only: candidates that resolve to the same kernel and plan are timed once
+  std::vector<std::string> seen;
+  double best = -1.0, def = -1.0;
+  SwForce bf{};
+  std::string bname;
+  for (size_t c = 0; c < cands.size(); ++c) {
+    const SwForce &fc = cands[c];
+    SwPlan pl{};
+    std::string sig = sandwich_kernel_name(a, &fc);
+    if (!fc.valu && sandwich_mfma_plan(a, kSandwichLdsDoubles, &pl, &fc))
+      sig += " GC=" + std::to_string(pl.GC) + " ks=" + std::to_string(pl.ks) + " slice=" + std::to_string(pl.slice);
+    if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
+    seen.push_back(sig);
+    const double us = time_launches(st, [&]() { return launch_sandwich(a, st, &fc); });
+    if (us < 0.0) {
+      (void)hipGetLastError();
+      continue;
+    }
+    if (c == 0) def = us;
+    if (best < 0.0 || us < best) {
+      best = us;
+      bf = fc;
+      bname = sig;
+    }
+  }
+  if (best < 0.0) return false;
+  e.f = bf;
+  e.us = best;
+  e.us_default = def;
+  e.choice = bname;
+  tune_put(key, e);
+  *out = bf;
+  return true;
+}
+
 hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_t N, int64_t K,
                  double alpha, double beta, int batch, hipStream_t st, bool allow_split,
                  const int *run_flag = nullptr, int64_t run_flag_stride = 0, int *ks_out = nullptr,
@@ -261,10 +391,63 @@ hatt_status gemm(bool run, GemmCtx &gc, CMat A, CMat B, Mat C, int64_t M, int64_
   g.beta = beta;
   g.batch = batch;
   g.ksplit = allow_split ? gemm_pick_ksplit(M, N, K, batch) : 1;
-  const int64_t need = g.ksplit > 1 ? (int64_t)batch * g.ksplit * M * N : 0;
+  // autotuner: the K split of this product's bucket
+  std::vector<int> cands;
+  std::string tkey;
+  if (g_tune_mode != 0 && allow_split && beta == 0.0 && ks_out == nullptr && run_flag == nullptr &&
+      !(run && (C.ptr == A.ptr || C.ptr == B.ptr))) {
+    char kb[200];
+    snprintf(kb, sizeof kb, "gemm %lldx%lldx%lld batch=%d prec=%d a32=%d b32=%d c32=%d A=%d%d B=%d%d C=%d%d",
+             (long long)M, (long long)N, (long long)K, batch, ty.prec, ty.a32, ty.b32, ty.c32, A.rs == 1, A.cs == 1,
+             B.rs == 1, B.cs == 1, C.rs == 1, C.cs == 1);
+    tkey = kb;
+    TuneEntry te;
+    if (tune_get(tkey, &te)) {
+      g.ksplit = te.ks;
+    } else if (g_tune_mode == 1) {
+      for (int ks = 1; ks <= 64; ks *= 2)
+        if (ks == 1 || K >= (int64_t)ks * 64) cands.push_back(ks);
+    }
+  }
+  auto need_of = [&](int ks) { return ks > 1 ? (int64_t)batch * ks * M * N : (int64_t)0; };
+  int64_t need = need_of(g.ksplit);
+  for (int ks : cands) need = std::max(need, need_of(ks));
   gc.part_need = std::max(gc.part_need, need);
-  if (g.ksplit > 1 && need > gc.part_cap) g.ksplit = 1;
+  if (g.ksplit > 1 && need_of(g.ksplit) > gc.part_cap) g.ksplit = 1;
   g.part = gc.part;
+  if (run && !cands.empty() && !stream_capturing(st)) {
+    const int ks_default = g.ksplit;
+    double best = -1.0, def = -1.0;
+    int bks = ks_default;
+    for (int ks : cands) {
+      if (need_of(ks) > gc.part_cap) continue;
+      GemmArgs t = g;
+      t.ksplit = ks;
+      const double us = time_launches(st, [&]() {
+        hipError_t e = launch_gemm(t, st);
+        if (e == hipSuccess && ks > 1) e = launch_splitk_reduce(t, st);
+        return e;
+      });
+      if (us < 0.0) {
+        (void)hipGetLastError();
+        continue;
+      }
+      if (ks == ks_default) def = us;
+      if (best < 0.0 || us < best) {
+        best = us;
+        bks = ks;
+      }
+    }
+    if (best >= 0.0) {
+      TuneEntry te;
+      te.ks = bks;
+      te.us = best;
+      te.us_default = def;
+      te.choice = "ks=" + std::to_string(bks);
+      tune_put(tkey, te);
+      g.ksplit = bks;
+    }
+  }
   if (ks_out != nullptr) *ks_out = g.ksplit;
   if (g_prof.on) {
     char b[200], kn[96];
@@ -1334,9 +1517,11 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
       return fail(HATT_EUNSUPPORTED, "HaTT: no sandwich kernel for the W_L build at core " + std::to_string(c) +
                                          " (ranks " + std::to_string(a.RA) + ", " + std::to_string(a.RI) + " of x, " +
                                          std::to_string(a.SO) + ", " + std::to_string(a.SI) + " of y)");
+    SwForce sf;
+    const bool tuned = sandwich_tune(run, a, st, &sf);
     site("sandwich W_L n=%lld G=%lld RA=%d RI=%d SI=%d SO=%d [%s]", (long long)n[c], (long long)l1, a.RA, a.RI,
-         a.SI, a.SO, sandwich_kernel_name(a));
-    LAUNCH(launch_sandwich(a, st));
+         a.SI, a.SO, sandwich_kernel_name(a, tuned ? &sf : nullptr));
+    LAUNCH(launch_sandwich(a, st, tuned ? &sf : nullptr));
     const int64_t K = n[c] * l1;
     const CMat wr = v2 ? CMat{h2WR, 1, K, h2_wr} : CMat{sk + skoff[c], 1, K, sks};
     hatt_status stt;
@@ -1431,9 +1616,11 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
       return fail(HATT_EUNSUPPORTED, "HaTT: no sandwich kernel for the core update at core " + std::to_string(cn) +
                                          " (ranks " + std::to_string(a.RI) + ", " + std::to_string(a.RA) + " of x, " +
                                          std::to_string(a.SI) + ", " + std::to_string(a.SO) + " of y)");
+    SwForce sf;
+    const bool tuned = sandwich_tune(run, a, st, &sf);
     site("sandwich update n=%lld G=%lld RA=%d RI=%d SI=%d SO=%d [%s]", (long long)n[cn], (long long)l[cn], a.RA,
-         a.RI, a.SI, a.SO, sandwich_kernel_name(a));
-    LAUNCH(launch_sandwich(a, st));
+         a.RI, a.SI, a.SO, sandwich_kernel_name(a, tuned ? &sf : nullptr));
+    LAUNCH(launch_sandwich(a, st, tuned ? &sf : nullptr));
   }
   // ranks before truncation: the sketch widths
   if ((int)l.size() > kMaxRankPattern) return fail(HATT_EUNSUPPORTED, "order too large for the library (rank pattern buffer)");
@@ -1912,6 +2099,41 @@ hatt_status hatt_set_qr_method(int32_t method) {
   if (method != 0 && method != 1) return fail(HATT_EINVAL, "QR method must be 0 (CholeskyQR2 + fallback) or 1");
   g_use_chol = (method == 0);
   return HATT_OK;
+}
+
+hatt_status hatt_tune_mode(int32_t mode) {
+  if (mode < 0 || mode > 2) return fail(HATT_EINVAL, "tune mode must be 0 (off), 1 (record) or 2 (use)");
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune_mode = mode;
+  g_err.clear();
+  return HATT_OK;
+}
+
+hatt_status hatt_tune_clear(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune.clear();
+  g_err.clear();
+  return HATT_OK;
+}
+
+int64_t hatt_tune_table(char *buf, int64_t cap) {
+  std::string txt;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    char line[160];
+    for (const auto &kv : g_tune) {
+      snprintf(line, sizeof line, " -> %s  %.1f us (fixed rules %.1f us)\n", kv.second.choice.c_str(), kv.second.us,
+               kv.second.us_default);
+      txt += kv.first + line;
+    }
+  }
+  const int64_t len = (int64_t)txt.size();
+  if (buf != nullptr && cap > 0) {
+    const int64_t n = std::min(len, cap - 1);
+    memcpy(buf, txt.data(), (size_t)n);
+    buf[n] = '\0';
+  }
+  return len + 1;
 }
 
 const char *hatt_profile_class_name(int32_t cls) {

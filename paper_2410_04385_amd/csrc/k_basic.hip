@@ -345,10 +345,12 @@ hipError_t sandwich_reg_dispatch(const SandwichArgs &a, hipStream_t s, int64_t b
 bool g_sandwich_reg = true;
 bool g_sandwich_mfma = true;
 
-const char *sandwich_kernel_name(const SandwichArgs &a) {
+const char *sandwich_kernel_name(const SandwichArgs &a, const SwForce *force) {
   const int64_t budget = 19456;
   SwPlan pl;
-  if ((a.prec || g_sandwich_mfma) && sandwich_mfma_plan(a, kSandwichLdsDoubles, &pl)) return sandwich_mfma_name(a, pl);
+  const bool valu = force != nullptr && force->valu && !a.prec;
+  if ((a.prec || g_sandwich_mfma) && !valu && sandwich_mfma_plan(a, kSandwichLdsDoubles, &pl, force))
+    return sandwich_mfma_name(a, pl);
   if (a.prec) return "none (the low-precision sandwich needs the matrix-core plan)";
   const int RIp = (a.RI + 1) & ~1, SIp = (a.SI + 1) & ~1;
   const int64_t fixed = (int64_t)a.RA * RIp + (((int64_t)a.SI * a.SO + 1) & ~1);
@@ -377,12 +379,13 @@ bool sandwich_supported(const SandwichArgs &a) {
   return gc >= 1 && a.n < (1LL << 31) && (a.G + gc - 1) / gc <= 65535 && a.batch <= 65535;
 }
 
-hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s) {
+hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s, const SwForce *force) {
   if (a.n <= 0 || a.G <= 0 || a.batch <= 0) return hipSuccess;
   const int64_t budget = 19456;  // doubles of dynamic LDS
-  if (g_sandwich_mfma || a.prec) {
+  const bool valu = force != nullptr && force->valu && !a.prec;
+  if ((g_sandwich_mfma && !valu) || a.prec) {
     SwPlan pl;
-    if (sandwich_mfma_plan(a, kSandwichLdsDoubles, &pl)) return launch_sandwich_mfma(a, pl, s);
+    if (sandwich_mfma_plan(a, kSandwichLdsDoubles, &pl, force)) return launch_sandwich_mfma(a, pl, s);
     if (a.prec) return hipErrorInvalidValue;  // the FP32 / BF16 variants exist only on the matrix cores
   }
   if (g_sandwich_reg) {

@@ -96,7 +96,7 @@ static bool sandwich_slice_plan(const SandwichArgs &a, int64_t budget, SwPlan *p
 constexpr int kSwKsMax = 8;
 __host__ __device__ constexpr int sw_ks_slots(int ks) { return ks <= 2 ? 2 : (ks <= 4 ? 4 : 8); }
 
-bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
+bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl, const SwForce *force) {
   // K edges: whole K steps of 4, or whole K-16 BF16 MFMAs.  The budget is
   // given in doubles; BF16 plans count 2-byte elements, so they get four per
   // double (FP32 plans keep the FP64 element count)
@@ -138,6 +138,7 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
     best = largest(budget);
   }
   if (best == 0) return false;
+  if (force != nullptr && force->gc_div > 1) best = std::max(1, best / force->gc_div);
   pl->nbuf = nbuf;
   if (nbuf == 1) pf = false;
   const int64_t chunks = (a.G + best - 1) / best;
@@ -182,12 +183,13 @@ bool sandwich_mfma_plan(const SandwichArgs &a, int64_t budget, SwPlan *pl) {
       4 % (RA16 / 16) == 0 && (int64_t)a.RA * a.RI + (int64_t)a.SI * a.SO <= 256LL * sw_ks_slots(RI4 / 4))
     pl->ks = RI4 / 4;
   if (pl->nbuf != 2 || a.prec == 2) pl->ks = 0;  // the register-blocked kernel has no BF16 form
+  if (force != nullptr && force->no_ks) pl->ks = 0;
   pl->rem = (pl->ks > 0 && a.prec == 0 && a.og != 1 && a.SO >= 17 && a.SO <= 20 && a.RA >= 17 && a.RA <= 20) ? 1 : 0;
   pl->slice = 0;
   // large factor ranks leave room for a single YL / ZR slice buffer next to
   // the sketch columns: there the slice-major kernel stages each slice once
   // and streams the sketch columns instead
-  if (g_sandwich_slice && pl->ks == 0 && pl->nbuf == 1) {
+  if (g_sandwich_slice && pl->ks == 0 && pl->nbuf == 1 && !(force != nullptr && force->no_slice)) {
     SwPlan sp = *pl;
     if (sandwich_slice_plan(a, budget, &sp)) *pl = sp;
   }

@@ -450,3 +450,14 @@ def test_precision_option_values():
     xv, kx = x.view()
     o = _lib.HattOpts(1, 0.0, 7, None, 0, 0.0, 0, 3, None)
     assert L.hatt_plan(ctypes.byref(xv), ctypes.byref(xv), ctypes.byref(o), None, None, None) == -1
+
+
+def test_tune_mode_and_table_on_the_host():
+    api.tune_clear()
+    assert api.tune_table() == ""
+    for m in ("record", "use", "off"):
+        api.tune(m)
+    with pytest.raises(ValueError):
+        api.tune("fast")
+    assert _lib.lib().hatt_tune_mode(3) == -1
+    assert _lib.lib().hatt_tune_table(None, 0) == 1

@@ -147,3 +147,59 @@ def test_bf16_adaptive_runs_and_keeps_projection():
     assert ok and ell == l_ref and att == att_ref
     assert e <= 1e-3  # measured 5e-9: the tolerance, not the sketch, sets it
     assert tt.rel_err(res.train(0), outs[0]) <= 1e-3
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_low_precision_uneven_batch_against_per_pair_runs(prec):
+    """Uneven batch with FP32 / BF16 range finding: every pair equals the
+    single-pair call with the same precision and the sketch keyed by seed +
+    p (bit for bit: the same launches in the same order on another stream),
+    and the FP64 projection identity holds per pair."""
+    shapes = [(6, 16, 8, 12), (9, 32, 12, 10), (7, 16, 20, 16), (8, 64, 10, 9)]
+    pairs, raw = [], []
+    for p, (d, n, rx, ry) in enumerate(shapes):
+        y, z = wk.spectral_pair(7000 + p, d, n, rx, ry)
+        raw.append((y, z))
+        pairs.append((H.TT.from_cores([y]), H.TT.from_cores([z])))
+    _say(f"hatt_recompress_batched {prec}: {len(pairs)} uneven pairs")
+    res = H.recompress_batched(pairs, 0, max_rank=7, seed=600, precision=prec)
+    torch.cuda.synchronize()
+    ells = H.batched_plan(pairs, 0, max_rank=7, seed=600, precision=prec)["ell"]
+    for p, (X, Z) in enumerate(pairs):
+        one = H.recompress(X, Z, ells[p], max_rank=7, seed=600 + p, precision=prec)
+        torch.cuda.synchronize()
+        a, b = res[p].train(0), one.train(0)
+        assert tt.ranks(a) == tt.ranks(b)
+        assert tt.rel_err(a, b) <= 1e-13
+
+
+def test_autotuner_records_uses_and_matches_oracle():
+    """Record mode times the candidates of every GEMM and sandwich bucket of
+    a spectral recompression (order 8, width 40, rank 30) and keeps the
+    fastest; use mode then runs the recorded choices without timing and
+    reproduces the recording run bit for bit; both agree with the oracle to
+    the parity tolerance (split-K choices change only the summation order)."""
+    y, z = wk.spectral_pair(41, 8, 32, 20, 20)
+    X, Z = H.TT.from_cores([y]), H.TT.from_cores([z])
+    l = _ell(y, z, 40)
+    ref = rounding.tt_round_left_orth(ohatt.hatt(y, z, philox.sketch(12, tt.modes(y), l)), max_rank=30)
+    H.tune_clear()
+    try:
+        H.tune("record")
+        _say("autotuner: record on a spectral pair d=8")
+        a = H.recompress(X, Z, 40, max_rank=30, seed=12)
+        torch.cuda.synchronize()
+        table = H.tune_table()
+        _say("  table:\n" + table)
+        assert "gemm" in table and "sandwich" in table
+        H.tune("use")
+        b = H.recompress(X, Z, 40, max_rank=30, seed=12)
+        torch.cuda.synchronize()
+        assert H.tune_table() == table
+    finally:
+        H.tune("off")
+        H.tune_clear()
+    ga, gb = a.train(0), b.train(0)
+    assert tt.ranks(ga) == tt.ranks(gb) == tt.ranks(ref)
+    assert all(np.array_equal(p, q) for p, q in zip(ga, gb))
+    assert tt.rel_err(ga, ref) <= 1e-10
