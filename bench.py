@@ -234,6 +234,49 @@ def _bench_batched(args, torch, wk, H) -> int:
                      "rel_err_vs_z": _err_vs_product(res[q].train(0), y, z)})
     print(f"[bench] error vs z on {len(errs)} sampled pairs: max {max(e['rel_err_vs_z'] for e in errs):.2e}",
           file=sys.stderr, flush=True)
+    # the tolerance met per pair: the tolerance mode (widths grown per pair
+    # until the truncation at tol leaves slack) on the three smallest, three
+    # median and three widest products r_x r_y of the batch; the error against
+    # z is the norm of the difference TT [out | -z] (z's explicit PKP cores,
+    # ranks up to r_x r_y + kept) over ||z||, both by the library's tt_norm on
+    # the GPU (an orthogonalisation sweep: no cancellation), with the error at
+    # 4096 sampled entries beside it (uniform samples of these spectral
+    # tensors overweight their small entries, so it reads higher)
+    mid = len(order) // 2
+    picks = order[:3] + order[mid - 1:mid + 2] + order[-3:]
+    tol_rows = []
+    for q in picks:
+        d, n, rx, ry = shapes[q]
+        y, z = wk.spectral_pair(20000 + q, d, n, rx, ry)
+        X, Z = pairs[q]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ra, ell_a, att_a = H.recompress_adaptive(X, Z, cfg["tol"], seed=77 + q, max_attempts=12,
+                                                 precision=args.precision)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        got = ra.train(0)
+        idx = np.random.default_rng(q).integers(0, n, size=(4096, d))
+        ref = _tt_entries(y, idx) * _tt_entries(z, idx)
+        samp = float(np.linalg.norm(_tt_entries(got, idx) - ref) / np.linalg.norm(ref))
+        # the difference TT (and z's explicit cores) must fit comfortably in HBM
+        kept_r = ra.ranks[0].tolist()
+        zr = [a * b for a, b in zip(X.ranks, Z.ranks)]
+        diff_bytes = 8 * sum((kept_r[k] + zr[k]) * n * (kept_r[k + 1] + zr[k + 1]) for k in range(d))
+        exact = None
+        if diff_bytes <= 48 << 30:
+            zt = H.hadamard_explicit(X, Z)
+            exact = H.rel_err(H.kept_cores(ra), [zt.core(k, 0) for k in range(d)])
+            del zt
+        row = {"pair": q, "d": d, "n": n, "r_x": rx, "r_y": ry, "attempts": att_a, "max_width": max(ell_a),
+               "max_rank": max(ra.ranks[0].tolist()), "s": dt, "rel_err_vs_z": exact,
+               "sampled_rel_err_vs_z": samp}
+        tol_rows.append(row)
+        ex_s = f"{exact:.2e}" if exact is not None else "not formed (difference TT too large)"
+        print(f"[bench] tolerance mode pair {q} (d {d}, n {n}, r {rx}x{ry}): {dt:.2f} s, {att_a} attempts, "
+              f"width {max(ell_a)}, error vs z {ex_s} (sampled entries {samp:.1e})", file=sys.stderr, flush=True)
+        del ra
+        torch.cuda.empty_cache()
     line = {"metric": "HaTT recompressions/s, uneven batch of 512 pairs", "value": value,
             "unit": "recompressions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": 1000.0 * wall_s / args.steps, "higher_is_better": True, "scaling": "weak",
@@ -247,7 +290,10 @@ def _bench_batched(args, torch, wk, H) -> int:
             "mean_kept_rank": float(np.mean([max(k) for k in kept])),
             "tolerance_check": {"bonds": nbond, "bonds_without_slack": int(sum(tight)),
                                 "pairs_with_slack_on_every_bond": int(sum(1 for t in tight if t == 0)),
-                                "sample": errs}}
+                                "sample": errs},
+            "tolerance_mode_sample": {"tol": cfg["tol"], "pairs": tol_rows,
+                                      "note": "per pair, widths grown until the truncation leaves slack "
+                                              "(not part of the value)"}}
     print(json.dumps(line), flush=True)
     return 0
 
@@ -457,6 +503,14 @@ def _bench_trig(args, torch, wk, H, perfmodel) -> int:
                "sample": "one step: u2 and u3 by the FP64 numpy oracle (HaTT-1 with the same Philox sketches, "
                          "then TT-Rounding at tol 1e-8), u3 from the GPU's u2 factor",
                "u2_s": ta, "u3_s": tb}
+        # the same oracle on one host thread (u2 only, a bounded sample)
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            rounding.tt_round_left_orth(ohatt.hatt(u, u, philox.sketch(s2, U.n, ell2)), tol=tol)
+            t1 = time.perf_counter() - t0
+        cpu["one_core"] = {"value": 1.0 / t1, "unit": "recompressions/s", "cores": 1,
+                           "sample": "u2 by the oracle on one BLAS thread"}
         parity = {"u2_rel_err_vs_oracle": tt.rel_err(g2, ref2), "u3_rel_err_vs_oracle": tt.rel_err(g3, ref3),
                   "u2_oracle_ranks": tt.ranks(ref2), "u3_oracle_ranks": tt.ranks(ref3)}
         if not args.no_cpu_explicit:

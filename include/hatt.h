@@ -178,10 +178,17 @@ HATT_API hatt_status hatt_recompress_batched(int32_t npairs, const hatt_tt *x, c
  * tolerance control open (Sec. 6); it suggests enlarging l when a sketch's
  * smallest singular value is not small enough (Sec. 5.1.1).  Rule:
  *   start l_k = max(r_k, s_k) + p (clamped as in hatt_plan); run HaTT with
- *   the Philox sketch keyed by seed + attempt, then TT-Rounding at tol;
- *   accept when every bond keeps rho_k <= l_k - p or l_k is at its largest
- *   feasible value; else on each failing bond (failing for any train of the
- *   batch) l_k = min(cap_k, ceil(1.5 l_k) + p) and retry.
+ *   the Philox sketch keyed by seed + attempt, then TT-Rounding at
+ *   tol sqrt(3) / 2; accept when every bond keeps rho_k <= l_k - p or l_k is
+ *   at its largest feasible value, and the sketch captured the product's
+ *   range to within tol / 2: the untruncated HaTT result X is an orthogonal
+ *   projection of z = x (.) y, so ||z - X||^2 = ||z||^2 - ||X||^2 (||z|| by
+ *   hatt_hadamard_norm2, once per call), and the truncation error is
+ *   orthogonal to z - X, so the result is within tol of z (the check cannot
+ *   resolve ||z - X||^2 below 256 eps ||z||^2).  Else l_k = min(cap_k,
+ *   ceil(1.5 l_k) + p) on each bond failing the slack test (for any train of
+ *   the batch), or on every bond below its cap when only the capture test
+ *   failed, and retry.
  * Widths never grow beyond 3072 (the truncation's SVD limit): a bond that
  * would need more returns HATT_ENOTCONV.
  * hatt_adaptive_plan: cap_out (host [d+1]) = largest widths the growth may
@@ -234,8 +241,9 @@ HATT_API hatt_status hatt_recompress_adaptive(const hatt_tt *x, const hatt_tt *y
  * sizes.
  * hatt_plan3 / hatt_recompress3: as hatt_plan / hatt_recompress.
  * hatt_adaptive_plan3 / hatt_recompress3_adaptive: the tolerance-driven rule
- * above with start widths max(r_k, s_k, t_k) + p; the finiteness check covers
- * all three factors.
+ * above with start widths max(r_k, s_k, t_k) + p but the slack test alone
+ * (truncation at tol, no capture test); the finiteness check covers all three
+ * factors.
  */
 HATT_API hatt_status hatt_plan3(const hatt_tt *x, const hatt_tt *y, const hatt_tt *w, const hatt_opts *opts,
                                 int64_t *ell_out, size_t *ws_bytes, int64_t *out_elems);
@@ -313,6 +321,20 @@ HATT_API hatt_status tt_norm(const hatt_tt *a, double *out, void *ws, size_t ws_
  * trust its data runs this first (the tolerance mode does).
  */
 HATT_API hatt_status tt_check_finite(const hatt_tt *a, int32_t *flag, void *stream);
+
+/*
+ * hatt_hadamard_norm2 -- ||x (.) y||_F^2 of every train (device out [batch]),
+ * without the PKP cores: the Gram recursion of the TT inner product (Sec.
+ * 2.1), G_0 = 1, G_k = sum_i Z_k(i)^T G_{k-1} Z_k(i) with Z_k(i) =
+ * X_k(i) kron Y_k(i) (Sec. 2.2), each step as two sandwich contractions and
+ * a fixed-order sum over i, ||z||^2 = G_d.  x and y must have the same d,
+ * mode sizes and batch.  Work on the stream, no synchronisation;
+ * hatt_hadamard_norm2_plan gives the workspace (r_k s_k r_{k+1} s_{k+1} n_k
+ * doubles twice, plus one Gram matrix).
+ */
+HATT_API hatt_status hatt_hadamard_norm2_plan(const hatt_tt *x, const hatt_tt *y, size_t *ws_bytes);
+HATT_API hatt_status hatt_hadamard_norm2(const hatt_tt *x, const hatt_tt *y, double *out, void *ws,
+                                         size_t ws_bytes, void *stream);
 
 /*
  * tt_scale -- multiply (invert = 0) or divide (invert = 1) train b of `a` by

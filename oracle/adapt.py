@@ -7,18 +7,25 @@ small enough, l should be increased (Sec. 5.1.1).  The rule implemented here
 (the same on both sides):
 
 * start: l_k = max(r_k, s_k) + p (p = oversampling, default 8), clamped;
-* run HaTT with the sketch keyed by seed + attempt, then truncate at tol
-  (Alg. 1's truncation loop from the right on HaTT's left-orthogonal
-  output, rounding.tt_round_left_orth);
+* run HaTT with the sketch keyed by seed + attempt, then truncate at
+  tol sqrt(3) / 2 (Alg. 1's truncation loop from the right on HaTT's
+  left-orthogonal output, rounding.tt_round_left_orth);
 * accept when every bond keeps rho_k <= l_k - p, or l_k already equals its
-  largest feasible value (then the sketch captured the bond exactly);
-* otherwise on each failing bond set l_k = min(cap_k, ceil(1.5 l_k) + p) and
-  retry; give up after ``max_attempts``.
+  largest feasible value (then the sketch captured the bond exactly), and
+  the sketch captured z's range to within tol / 2: the untruncated HaTT
+  result X is an orthogonal projection of z, so ||z - X||^2 =
+  ||z||^2 - ||X||^2, and the truncation's error is orthogonal to it, so the
+  two shares add up to at most tol (the capture test cannot resolve
+  ||z - X||^2 below 256 eps ||z||^2, its floor);
+* otherwise grow l_k = min(cap_k, ceil(1.5 l_k) + p) on each bond failing
+  the slack test, or on every bond below its cap when only the capture test
+  failed, and retry; give up after ``max_attempts``.
 
 For a batch of pairs the widths are common to all pairs and a bond fails if
 it fails for any pair.  A triple (x, y, w) in place of a pair runs the
-three-factor HaTT (hatt3) under the same rule, with r_k s_k t_k as the
-product rank in the clamps and max(r_k, s_k, t_k) + p as the start.
+three-factor HaTT (hatt3) under the slack rule alone (truncation at tol, no
+capture test), with r_k s_k t_k as the product rank in the clamps and
+max(r_k, s_k, t_k) + p as the start.
 """
 
 from __future__ import annotations
@@ -33,6 +40,9 @@ from .hatt import hatt
 from .hatt3 import hatt3
 
 BIG = 1 << 40
+TRUNC_SHARE = math.sqrt(3.0) / 2.0
+CAPTURE_SHARE2 = 0.25
+CAPTURE_FLOOR = 256.0 * np.finfo(np.float64).eps
 
 
 def initial_widths(n, rx, ry, p: int = 8) -> List[int]:
@@ -75,13 +85,22 @@ def hatt_adaptive(pairs, tol: float, seed: int, p: int = 8, max_attempts: int = 
         ell = plan.clamp_ell(n, rx, ry, req)
     else:
         ell = list(ell0)
+    two = len(ops0) == 2 and len(n) >= 2
+    z2 = [tt.norm(tt.pkp(ops[0], ops[1])) ** 2 for ops in pairs] if two else None
     outs = None
     for attempt in range(max_attempts):
         l = plan.clamp_ell(n, rx, ry, ell)
         R = philox.sketch(seed + attempt * seed_step, n, l)
-        outs = [rounding.tt_round_left_orth(hatt(ops[0], ops[1], R, variant, ep) if len(ops) == 2
-                                            else hatt3(ops[0], ops[1], ops[2], R), tol=tol) for ops in pairs]
+        raws = [hatt(ops[0], ops[1], R, variant, ep) if len(ops) == 2 else hatt3(ops[0], ops[1], ops[2], R)
+                for ops in pairs]
+        outs = [rounding.tt_round_left_orth(x, tol=tol * TRUNC_SHARE if two else tol) for x in raws]
         bad = failing_bonds([tt.ranks(o) for o in outs], l, cap, p)
+        if two and not bad:
+            for x, zz in zip(raws, z2):
+                c2 = max(0.0, zz - tt.norm(x) ** 2)
+                if c2 > max(CAPTURE_SHARE2 * tol * tol, CAPTURE_FLOOR) * zz:
+                    bad = [k for k in range(1, len(n)) if l[k] < cap[k]]
+                    break
         if not bad:
             return outs, l, attempt + 1, True
         ell = grow(l, bad, cap, p)

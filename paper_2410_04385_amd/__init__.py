@@ -16,6 +16,7 @@ from .api import (  # noqa: F401
     rel_err,
     batched_plan,
     hadamard_explicit,
+    hadamard_norm2,
     norm,
     plan,
     profile_report,

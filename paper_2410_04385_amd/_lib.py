@@ -24,7 +24,7 @@ EXPORTED = [
     "hatt_rankpred_features", "hatt_rankpred_fit_stats", "hatt_rankpred_forward", "hatt_rankpred_ws_bytes",
     "hatt_rankpred_grad", "hatt_rankpred_train_step", "hatt_rankpred_widths", "hatt_rankpred_labels",
     "hatt_plan3", "hatt_recompress3", "hatt_adaptive_plan3", "hatt_recompress3_adaptive",
-    "hatt_tune_mode", "hatt_tune_clear", "hatt_tune_table",
+    "hatt_tune_mode", "hatt_tune_clear", "hatt_tune_table", "hatt_hadamard_norm2_plan", "hatt_hadamard_norm2",
 ]
 RANKPRED_NIN, RANKPRED_NTHETA, RANKPRED_NSTATS = 21, 19586, 46
 PROFILE_CLASSES = 8
@@ -108,6 +108,8 @@ def lib() -> ctypes.CDLL:
     L.hatt_recompress3_adaptive.argtypes = [ttp, ttp, ttp, aop, vp, ctypes.c_int64, vp, i64p,
                                             ctypes.POINTER(ctypes.c_int32), vp, ctypes.c_size_t, vp]
     L.tt_hadamard_explicit.argtypes = [ttp, ttp, vp, ctypes.c_int64, vp]
+    L.hatt_hadamard_norm2_plan.argtypes = [ttp, ttp, szp]
+    L.hatt_hadamard_norm2.argtypes = [ttp, ttp, vp, vp, ctypes.c_size_t, vp]
     L.tt_randorth_plan.argtypes = [ttp, ctypes.c_int64, i64p, i64p, szp, i64p]
     L.tt_randorth.argtypes = [ttp, ttp, ctypes.c_int64, i64p, ctypes.c_uint64, ctypes.c_int64, ctypes.c_double, vp,
                               ctypes.c_int64, vp, vp, ctypes.c_size_t, vp]

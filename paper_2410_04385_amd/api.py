@@ -390,6 +390,24 @@ def recompress3_adaptive(x: TT, y: TT, w: TT, tol: float, *, seed: int = 0, over
     return Result(out, ranks), list(ell), int(att.value)
 
 
+def hadamard_norm2(x: TT, y: TT, workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """||x (.) y||_F^2 per train (device float64 [batch]) by the PKP-free Gram
+    recursion."""
+    xv, kx = x.view()
+    yv, ky = y.view()
+    ws = ctypes.c_size_t(0)
+    check("hatt_hadamard_norm2_plan", lib().hatt_hadamard_norm2_plan(ctypes.byref(xv), ctypes.byref(yv),
+                                                                     ctypes.byref(ws)))
+    dev = x.data.device
+    if workspace is None or workspace.numel() < ws.value:
+        workspace = torch.empty(max(ws.value, 1), dtype=torch.uint8, device=dev)
+    out = torch.empty(x.batch, dtype=torch.float64, device=dev)
+    check("hatt_hadamard_norm2", lib().hatt_hadamard_norm2(
+        ctypes.byref(xv), ctypes.byref(yv), ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+        workspace.numel(), _stream_ptr(stream)))
+    return out
+
+
 def hadamard_explicit(x: TT, y: TT, out: Optional[TT] = None, stream=None) -> TT:
     """Explicit PKP cores of x (.) y (ranks r_k s_k)."""
     rr = [a * b for a, b in zip(x.ranks, y.ranks)]

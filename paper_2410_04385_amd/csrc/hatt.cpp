@@ -1313,6 +1313,7 @@ struct HattSpec {
   double *out;
   int64_t ostride;
   int64_t *orank;
+  double *xnorm = nullptr;  // optional device [batch]: ||X|| of the untruncated HaTT output
 };
 
 hatt_status hatt3_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStream_t st);
@@ -1625,6 +1626,9 @@ hatt_status hatt_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStre
   // ranks before truncation: the sketch widths
   if ((int)l.size() > kMaxRankPattern) return fail(HATT_EUNSUPPORTED, "order too large for the library (rank pattern buffer)");
   LAUNCH(launch_rank_pattern(sp.orank, P, d + 1, l.data(), st));
+  // ||X|| of the untruncated result: every core but the last is orthonormal
+  if (sp.xnorm != nullptr && d >= 2)
+    LAUNCH(launch_block_norm(sp.out + ooff[d - 1], l[d - 1] * n[d - 1], sp.ostride, sp.xnorm, P, st));
   // ---- truncation (Alg. 1 on the rank-l result)
   bool capped = false;
   for (int64_t c : sp.bond_cap) capped = capped || c > 0;
@@ -1823,6 +1827,121 @@ hatt_status hatt3_body(bool run, const HattSpec &sp, Ws &ws, GemmCtx &gc, hipStr
     stt = truncate_left_orth(run, n, l, sp.out, sp.ostride, sp.orank, sp.bond_cap, sp.o.tol, 1, ws, st);
     if (stt != HATT_OK) return stt;
   }
+  return HATT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// ||x (.) y||_F^2 per train without the PKP cores (Sec. 2.2: the product's
+// cores are Z_k(i) = X_k(i) kron Y_k(i)).  The Gram recursion of the TT inner
+// product, G_0 = 1, G_k = sum_i Z_k(i)^T G_{k-1} Z_k(i), ||z||^2 = G_d, with
+// each step as two sandwich contractions (the identity of eq.
+// kronecker_product_times_vec applied to the rows of G, then to the columns
+// of the result) and a fixed-order sum over i:
+//   K_i[(a b), (c' d')] = sum_{c, d} G[(a b), (c d)] X(c, i, c') Y(d, i, d')
+//   G'[(a' b'), (c' d')] = sum_i sum_{a, b} X(a, i, a') Y(b, i, b') K_i[(a b), (c' d')]
+// The second contraction runs one mode index per batch entry (the
+// sandwich's batch dimension carries i), so trains are taken one at a time.
+hatt_status hadamard_norm2_body(bool run, const Shape &X, const Shape &Y, double *out, Ws &ws, GemmCtx &gc,
+                                hipStream_t st) {
+  const int d = X.d;
+  const auto &n = X.n, &r = X.r, &s = Y.r;
+  int64_t gsz = 1, ksz = 1;
+  for (int k = 0; k < d; ++k) {
+    gsz = std::max(gsz, (r[k + 1] * s[k + 1]) * (r[k + 1] * s[k + 1]));
+    ksz = std::max(ksz, n[k] * (r[k] * s[k]) * (r[k + 1] * s[k + 1]));
+    ksz = std::max(ksz, n[k] * (r[k + 1] * s[k + 1]) * (r[k + 1] * s[k + 1]));
+  }
+  double *G = ws.d(gsz), *Kb = ws.d(ksz), *Ob = ws.d(ksz);
+  for (int p = 0; p < X.batch; ++p) {
+    LAUNCH(launch_fill(G, 1, 1.0, st));
+    for (int k = 0; k < d; ++k) {
+      const int64_t r0 = r[k], s0 = s[k], r1 = r[k + 1], s1 = s[k + 1], nn = n[k];
+      const int64_t q0 = r0 * s0, q1 = r1 * s1;
+      const double *xk = X.data + p * X.stride + X.off[k], *yk = Y.data + p * Y.stride + Y.off[k];
+      SandwichArgs a{};
+      // K_i = G Z_i: row g of G folded to (c, d), X_i^T (.) Y_i
+      a.yl = xk;
+      a.ylb = 0;
+      a.yli = r1;
+      a.ylr = 1;
+      a.ylc = nn * r1;
+      a.zr = yk;
+      a.zrb = 0;
+      a.zri = s1;
+      a.zrr = nn * s1;
+      a.zrc = 1;
+      a.c = G;
+      a.cb = 0;
+      a.cg = q0;
+      a.ca = s0;
+      a.cbb = 1;
+      a.o = Kb;
+      a.ob = 0;
+      a.oi = q0 * q1;
+      a.og = q1;
+      a.oa = s1;
+      a.obb = 1;
+      a.RA = (int)r1;
+      a.RI = (int)r0;
+      a.SI = (int)s0;
+      a.SO = (int)s1;
+      a.n = nn;
+      a.G = q0;
+      a.batch = 1;
+      if (!sandwich_supported(a)) return fail(HATT_EUNSUPPORTED, "||x (.) y||: no sandwich kernel for these ranks");
+      site("norm2 rows n=%lld G=%lld RA=%d RI=%d SI=%d SO=%d", (long long)nn, (long long)q0, a.RA, a.RI, a.SI, a.SO);
+      LAUNCH(launch_sandwich(a, st));
+      // O_i = Z_i^T K_i: column g of K_i folded to (a, b); the batch entry is i
+      SandwichArgs b{};
+      b.yl = xk;
+      b.ylb = r1;
+      b.yli = 0;
+      b.ylr = 1;
+      b.ylc = nn * r1;
+      b.zr = yk;
+      b.zrb = s1;
+      b.zri = 0;
+      b.zrr = nn * s1;
+      b.zrc = 1;
+      b.c = Kb;
+      b.cb = q0 * q1;
+      b.cg = 1;
+      b.ca = s0 * q1;
+      b.cbb = q1;
+      b.o = (nn == 1) ? G : Ob;
+      b.ob = q1 * q1;
+      b.oi = 0;
+      b.og = 1;
+      b.oa = s1 * q1;
+      b.obb = q1;
+      b.RA = (int)r1;
+      b.RI = (int)r0;
+      b.SI = (int)s0;
+      b.SO = (int)s1;
+      b.n = 1;
+      b.G = q1;
+      b.batch = (int)nn;
+      if (!sandwich_supported(b)) return fail(HATT_EUNSUPPORTED, "||x (.) y||: no sandwich kernel for these ranks");
+      site("norm2 columns n=%lld G=%lld RA=%d RI=%d SI=%d SO=%d", (long long)nn, (long long)q1, b.RA, b.RI, b.SI,
+           b.SO);
+      LAUNCH(launch_sandwich(b, st));
+      if (nn > 1) {
+        // G = sum_i O_i in the order of i
+        GemmArgs ra{};
+        ra.M = q1;
+        ra.N = q1;
+        ra.batch = 1;
+        ra.ksplit = (int)nn;
+        ra.part = Ob;
+        ra.C = Mat{G, q1, 1, 0};
+        ra.alpha = 1.0;
+        ra.beta = 0.0;
+        LAUNCH(launch_splitk_reduce(ra, st));
+      }
+    }
+    LAUNCH(launch_copy(CMat{G, 1, 1, 0}, Mat{out + p, 1, 1, 0}, 1, 1, 1, st));
+  }
+  (void)gc;
   return HATT_OK;
 }
 
@@ -2498,6 +2617,19 @@ hatt_status hatt_recompress_batched(int32_t npairs, const hatt_tt *x, const hatt
 // takes at most kSvdBigMaxN columns.
 constexpr int64_t kAdaptMaxWidth = kSvdBigMaxN;
 
+// Bytes kept at the end of the tolerance mode's workspace for ||X|| of each
+// train's untruncated result.
+static size_t xnorm_slot_bytes(int batch) { return ((size_t)batch * sizeof(double) + 255) & ~(size_t)255; }
+
+// Tolerance-mode truncation at tol sqrt(3) / 2, with the captured range's
+// error (||z||^2 - ||X||^2 of the untruncated projection X) held below tol / 2:
+// the two are orthogonal, so together they stay within tol.  The capture
+// check can only resolve errors whose square exceeds the rounding of the two
+// squared norms, so its threshold is never below kCaptureFloor ||z||^2.
+constexpr double kTruncShare = 0.8660254037844386;  // sqrt(3) / 2
+constexpr double kCaptureShare2 = 0.25;             // (1 / 2)^2
+constexpr double kCaptureFloor = 256.0 * 2.220446049250313e-16;
+
 // cap: the largest feasible widths (a bond at its cap is exact); lim: the
 // widths the growth may reach (cap clamped to kAdaptMaxWidth).
 static hatt_status adapt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_tt *w, const hatt_adapt_opts *ao,
@@ -2549,8 +2681,18 @@ static hatt_status adaptive_plan_common(const hatt_tt *x, const hatt_tt *y, cons
   if (cap_out)
     for (int k = 0; k <= sp.X.d; ++k) cap_out[k] = cap[k];
   // widths below the caps need no more than the caps' buffers up to the
-  // integer effects of the QR tree shapes; keep a margin and re-check per attempt
-  if (ws_bytes) *ws_bytes = ws.off + ws.off / 8 + ((size_t)4 << 20);
+  // integer effects of the QR tree shapes; keep a margin and re-check per
+  // attempt.  Two factors also need ||x (.) y||^2 (run before the attempts,
+  // in the same memory) and a slot for ||X|| at the end of the workspace.
+  size_t need = ws.off + ws.off / 8 + ((size_t)4 << 20);
+  if (!sp.three) {
+    Ws wn(nullptr);
+    GemmCtx gm{nullptr, 0, 0};
+    st = hadamard_norm2_body(false, sp.X, sp.Y, nullptr, wn, gm, nullptr);
+    if (st != HATT_OK) return st;
+    need = std::max(need, wn.off) + xnorm_slot_bytes(sp.X.batch);
+  }
+  if (ws_bytes) *ws_bytes = need;
   if (out_elems) {
     std::vector<int64_t> off;
     int64_t tot;
@@ -2603,19 +2745,46 @@ static hatt_status adaptive_common(const hatt_tt *x, const hatt_tt *y, const hat
         return fail(HATT_ENONFINITE, std::string(kNames[q / P]) + " train " + std::to_string(q % P) +
                                          " has a non-finite entry");
   }
+  // two factors: ||x (.) y||^2 of every train for the capture check, the
+  // truncation at tol sqrt(3) / 2, and ||X|| in a slot at the workspace's end
+  const bool capture = !sp.three && d >= 2;
+  const double tol = opts->tol;
+  std::vector<double> z2((size_t)P, 0.0), xn((size_t)P, 0.0);
+  size_t ws_att = ws_bytes;
+  if (capture) {
+    const size_t slot = xnorm_slot_bytes(P);
+    if (ws == nullptr || ws_bytes < slot) return fail(HATT_EWORKSPACE, "workspace too small");
+    ws_att = ws_bytes - slot;
+    sp.xnorm = reinterpret_cast<double *>(static_cast<char *>(ws) + ws_att);
+    sp.o.tol = tol * kTruncShare;
+    Ws meas(nullptr);
+    GemmCtx gm{nullptr, 0, 0};
+    st = hadamard_norm2_body(false, sp.X, sp.Y, nullptr, meas, gm, nullptr);
+    if (st != HATT_OK) return st;
+    if (ws_att < meas.off)
+      return fail(HATT_EWORKSPACE, "workspace too small: need " + std::to_string(meas.off + slot) + " bytes");
+    Ws wn(ws);
+    st = hadamard_norm2_body(true, sp.X, sp.Y, sp.xnorm, wn, gm, strm);
+    if (st != HATT_OK) return st;
+    if (hipMemcpyAsync(z2.data(), sp.xnorm, z2.size() * sizeof(double), hipMemcpyDeviceToHost, strm) != hipSuccess ||
+        hipStreamSynchronize(strm) != hipSuccess)
+      return fail(HATT_EDEVICE, "reading ||x (.) y|| failed");
+  }
   for (int attempt = 0; attempt < maxa; ++attempt) {
     sp.ell = clamp_ell(sp.X.n, sp.X.r, sp.ryw, ell);
     sp.o.seed = opts->seed + (uint64_t)attempt;
     Ws meas(nullptr);
     st = hatt_run(false, sp, meas, nullptr);
     if (st != HATT_OK) return st;
-    if (ws == nullptr || ws_bytes < meas.off)
+    if (ws == nullptr || ws_att < meas.off)
       return fail(HATT_EWORKSPACE, "workspace too small: need " + std::to_string(meas.off) + " bytes");
     Ws w(ws);
     st = hatt_run(true, sp, w, strm);
     if (st != HATT_OK) return st;
     if (hipMemcpyAsync(host_rank.data(), out_rank, host_rank.size() * sizeof(int64_t), hipMemcpyDeviceToHost,
                        strm) != hipSuccess ||
+        (capture &&
+         hipMemcpyAsync(xn.data(), sp.xnorm, xn.size() * sizeof(double), hipMemcpyDeviceToHost, strm) != hipSuccess) ||
         hipStreamSynchronize(strm) != hipSuccess)
       return fail(HATT_EDEVICE, "reading the kept ranks failed");
     std::vector<int> bad;
@@ -2625,6 +2794,18 @@ static hatt_status adaptive_common(const hatt_tt *x, const hatt_tt *y, const hat
         if (host_rank[(size_t)q * (d + 1) + k] > sp.ell[k] - p && sp.ell[k] < cap[k]) b = true;
       if (b) bad.push_back(k);
     }
+    // the captured range: ||z - X||^2 = ||z||^2 - ||X||^2 (X is an orthogonal
+    // projection of z); when it exceeds (tol / 2)^2 ||z||^2 every bond below
+    // its cap grows
+    bool capture_bad = false;
+    if (capture)
+      for (int q = 0; q < P; ++q) {
+        const double c2 = std::max(0.0, z2[q] - xn[q] * xn[q]);
+        if (c2 > std::max(kCaptureShare2 * tol * tol, kCaptureFloor) * z2[q]) capture_bad = true;
+      }
+    if (bad.empty() && capture_bad)
+      for (int k = 1; k < d; ++k)
+        if (sp.ell[k] < cap[k]) bad.push_back(k);
     for (int k = 0; k <= d; ++k) ell_out[k] = sp.ell[k];
     *attempts_out = attempt + 1;
     if (bad.empty()) {
@@ -2791,6 +2972,47 @@ hatt_status tt_norm(const hatt_tt *a, double *out, void *ws, size_t ws_bytes, vo
   Ws w(ws);
   GemmCtx g2{nullptr, 0, 0};
   st = round_run(true, rs, w, g2, (hipStream_t)stream);
+  if (st == HATT_OK) g_err.clear();
+  return st;
+}
+
+static hatt_status norm2_prepare(const hatt_tt *x, const hatt_tt *y, Shape *X, Shape *Y, bool need_data) {
+  hatt_status st = read_tt(x, "x", X, need_data);
+  if (st != HATT_OK) return st;
+  st = read_tt(y, "y", Y, need_data);
+  if (st != HATT_OK) return st;
+  if (X->d != Y->d || X->n != Y->n || X->batch != Y->batch)
+    return fail(HATT_ESHAPE, "x and y differ in order, mode sizes or batch");
+  return HATT_OK;
+}
+
+hatt_status hatt_hadamard_norm2_plan(const hatt_tt *x, const hatt_tt *y, size_t *ws_bytes) {
+  Shape X, Y;
+  hatt_status st = norm2_prepare(x, y, &X, &Y, false);
+  if (st != HATT_OK) return st;
+  Ws meas(nullptr);
+  GemmCtx gm{nullptr, 0, 0};
+  st = hadamard_norm2_body(false, X, Y, nullptr, meas, gm, nullptr);
+  if (st != HATT_OK) return st;
+  if (ws_bytes) *ws_bytes = meas.off;
+  g_err.clear();
+  return HATT_OK;
+}
+
+hatt_status hatt_hadamard_norm2(const hatt_tt *x, const hatt_tt *y, double *out, void *ws, size_t ws_bytes,
+                                void *stream) {
+  Shape X, Y;
+  hatt_status st = norm2_prepare(x, y, &X, &Y, true);
+  if (st != HATT_OK) return st;
+  if (out == nullptr) return fail(HATT_EINVAL, "out is NULL");
+  Ws meas(nullptr);
+  GemmCtx gm{nullptr, 0, 0};
+  st = hadamard_norm2_body(false, X, Y, nullptr, meas, gm, nullptr);
+  if (st != HATT_OK) return st;
+  if (ws == nullptr || ws_bytes < meas.off)
+    return fail(HATT_EWORKSPACE, "workspace too small: need " + std::to_string(meas.off) + " bytes");
+  Ws w(ws);
+  st = hadamard_norm2_body(true, X, Y, out, w, gm, (hipStream_t)stream);
   if (st == HATT_OK) g_err.clear();
   return st;
 }

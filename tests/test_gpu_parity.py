@@ -982,3 +982,40 @@ def test_round_svd_above_1024_columns(kind):
     _say(f"  ranks {tt.ranks(got)} vs {tt.ranks(ref)}")
     assert tt.ranks(got) == tt.ranks(ref)
     assert tt.rel_err(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("n,r,s,batch", [([7], 1, 1, 2), ([4, 5, 6, 3], 3, 4, 3), ([2] * 9, 3, 2, 1),
+                                         ([1, 6, 1, 5], 2, 3, 2), ([9, 17, 8], 20, 24, 1)])
+def test_hadamard_norm2_matches_explicit(n, r, s, batch):
+    """||x (.) y||^2 by the PKP-free Gram recursion against the norm of the
+    oracle's explicit PKP train, per train of a batch."""
+    xs, ys = [], []
+    for b in range(batch):
+        x, y = _pair(sum(n) * 3 + r + b, n, r, s)
+        xs.append(x)
+        ys.append(y)
+    _say(f"hatt_hadamard_norm2 n={n} r={r} s={s} batch={batch}")
+    got = H.hadamard_norm2(H.TT.from_cores(xs), H.TT.from_cores(ys)).cpu().numpy()
+    for b in range(batch):
+        ref = tt.norm(tt.pkp(xs[b], ys[b])) ** 2
+        assert abs(got[b] - ref) <= 1e-12 * ref
+
+
+def test_tolerance_mode_meets_tol_on_a_wide_uneven_pair():
+    """A pair of the uneven distribution (d 13, n 16, ranks 17 x 42, product
+    rank 714) on which the slack test alone accepted a result 4.8e-6 away
+    from z at tol 1e-6: with the capture test the result is within tol,
+    checked through the difference TT against the explicit product on the
+    GPU."""
+    shapes = wk.batched_pair_shapes(1, 512)
+    d, n, rx, ry = shapes[398]
+    assert (d, n, rx, ry) == (13, 16, 17, 42)
+    y, z = wk.spectral_pair(20000 + 398, d, n, rx, ry)
+    X, Z = H.TT.from_cores([y]), H.TT.from_cores([z])
+    _say("hatt_recompress_adaptive tol 1e-6 on uneven pair 398 (13, 16, 17 x 42)")
+    res, ell, att = H.recompress_adaptive(X, Z, 1e-6, seed=77 + 398, max_attempts=12)
+    torch.cuda.synchronize()
+    zt = H.hadamard_explicit(X, Z)
+    err = H.rel_err(H.kept_cores(res), [zt.core(k, 0) for k in range(d)])
+    _say(f"  {att} attempts, max width {max(ell)}, error vs z {err:.2e}")
+    assert err <= 1e-6

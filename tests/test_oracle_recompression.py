@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import workloads as wk
-from oracle import hatt, philox, plan, randorth, rounding, tt
+from oracle import adapt, hatt, philox, plan, randorth, rounding, tt
 
 
 def _setup(y, z, ell, seed=11):
@@ -261,3 +261,21 @@ def test_round_left_orth_on_hatt_output():
     alg1 = rounding.tt_round(raw, tol=1e-13)
     assert tt.ranks(exact) == tt.ranks(alg1)
     assert tt.rel_err(exact, alg1) <= 1e-12
+
+
+@pytest.mark.parametrize("shape", [(6, 10, 12, 12), (7, 8, 10, 12)])
+def test_tolerance_rule_meets_tol_against_explicit_product(shape):
+    """The tolerance rule truncates at tol sqrt(3)/2 and accepts only when
+    the captured range leaves ||z||^2 - ||X||^2 <= (tol/2)^2 ||z||^2, so the
+    result is within tol of z; checked through the difference TT against the
+    explicit PKP cores (no cancellation)."""
+    d, n, r, s = shape
+    y, z = wk.spectral_pair(504 + d, d, n, r, s)
+    outs, l, att, ok = adapt.hatt_adaptive([(y, z)], tol=1e-6, seed=3)
+    assert ok
+    zz = tt.pkp(y, z)
+    assert tt.rel_err(outs[0], zz) <= 1e-6
+    # the truncation share alone: tol sqrt(3)/2 of ||z|| on the projection
+    raw = hatt.hatt(y, z, philox.sketch(3 + att - 1, tt.modes(y), l))
+    cap2 = tt.norm(zz) ** 2 - tt.norm(raw) ** 2
+    assert cap2 <= max(0.25e-12, 256 * np.finfo(float).eps) * tt.norm(zz) ** 2
