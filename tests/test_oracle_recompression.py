@@ -279,3 +279,29 @@ def test_tolerance_rule_meets_tol_against_explicit_product(shape):
     raw = hatt.hatt(y, z, philox.sketch(3 + att - 1, tt.modes(y), l))
     cap2 = tt.norm(zz) ** 2 - tt.norm(raw) ** 2
     assert cap2 <= max(0.25e-12, 256 * np.finfo(float).eps) * tt.norm(zz) ** 2
+
+
+def test_hatt2_sketches_equal_explicit_truncated_recursion():
+    """eq. HPCRL--2 written out on the explicit PKP train: W^{(d-1)} by the
+    definition, then at each bond its SVD truncated to sigma > ep sigma_1 and
+    W^{(k-1)} = H(A_k x_3 trunc(W^{(k)})) H(R_k)^T; the oracle's HaTT-2
+    (sandwich form, never forming A) keeps the same number of terms and gives
+    the same sketches (the truncated product U S V^T has no gauge freedom)."""
+    y, z = _rand_pair(9, [4, 5, 4, 5, 4], 3, 3)
+    l, R = _setup(y, z, 6)
+    ep = 0.3
+    w2, used = hatt.hpcrl(y, z, R, variant=2, ep=ep, return_split_ranks=True)
+    a = tt.pkp(y, z)
+    d = len(a)
+    wb = tt.H(a[d - 1]) @ tt.H(R[d - 1]).T
+    assert np.allclose(w2[d - 1], wb, rtol=0, atol=1e-13 * np.abs(wb).max())
+    for b in range(d - 1, 1, -1):
+        u, sg, vt = np.linalg.svd(wb, full_matrices=False)
+        keep = max(1, int(np.sum(sg > ep * sg[0])))
+        assert used[b] == keep
+        assert keep < len(sg)          # really truncated
+        wt = (u[:, :keep] * sg[:keep]) @ vt[:keep]
+        c = b - 1
+        r0, n, _ = a[c].shape
+        wb = (tt.V(a[c]) @ wt).reshape(r0, n * wt.shape[1]) @ tt.H(R[c]).T
+        assert np.allclose(w2[b - 1], wb, rtol=0, atol=1e-12 * np.abs(wb).max())
