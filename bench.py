@@ -234,47 +234,68 @@ def _bench_batched(args, torch, wk, H) -> int:
                      "rel_err_vs_z": _err_vs_product(res[q].train(0), y, z)})
     print(f"[bench] error vs z on {len(errs)} sampled pairs: max {max(e['rel_err_vs_z'] for e in errs):.2e}",
           file=sys.stderr, flush=True)
-    # the tolerance met per pair: the tolerance mode (widths grown per pair
-    # until the truncation at tol leaves slack) on the three smallest, three
-    # median and three widest products r_x r_y of the batch; the error against
-    # z is the norm of the difference TT [out | -z] (z's explicit PKP cores,
-    # ranks up to r_x r_y + kept) over ||z||, both by the library's tt_norm on
-    # the GPU (an orthogonalisation sweep: no cancellation), with the error at
-    # 4096 sampled entries beside it (uniform samples of these spectral
-    # tensors overweight their small entries, so it reads higher)
+    # the tolerance met per pair: the batched tolerance mode (each pair's
+    # widths grown until the truncation at tol leaves slack and the sketch
+    # captured the product, attempt rounds of all pairs side by side) on the
+    # three smallest, three median and three widest products r_x r_y of the
+    # batch, pair i of the sample with seed 77 + i; the error against z is the
+    # norm of the difference TT [out | -z] (z's explicit PKP cores, ranks up
+    # to r_x r_y + kept) over ||z||, both by the library's tt_norm on the GPU
+    # (an orthogonalisation sweep: no cancellation), with the error at 4096
+    # sampled entries beside it (uniform samples of these spectral tensors
+    # overweight their small entries, so it reads higher).  The same pairs
+    # then run one by one through the single-pair tolerance mode with the
+    # same seeds, for the time and to confirm the same widths.
     mid = len(order) // 2
     picks = order[:3] + order[mid - 1:mid + 2] + order[-3:]
+    sub = [pairs[q] for q in picks]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rb, ell_b, att_b = H.recompress_batched_adaptive(sub, cfg["tol"], seed=77, max_attempts=12,
+                                                     precision=args.precision)
+    torch.cuda.synchronize()
+    batch_s = time.perf_counter() - t0
+    print(f"[bench] batched tolerance mode on {len(sub)} pairs: {batch_s:.2f} s", file=sys.stderr, flush=True)
     tol_rows = []
-    for q in picks:
+    for i, q in enumerate(picks):
         d, n, rx, ry = shapes[q]
         y, z = wk.spectral_pair(20000 + q, d, n, rx, ry)
         X, Z = pairs[q]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ra, ell_a, att_a = H.recompress_adaptive(X, Z, cfg["tol"], seed=77 + q, max_attempts=12,
-                                                 precision=args.precision)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        got = ra.train(0)
+        got = rb[i].train(0)
         idx = np.random.default_rng(q).integers(0, n, size=(4096, d))
         ref = _tt_entries(y, idx) * _tt_entries(z, idx)
         samp = float(np.linalg.norm(_tt_entries(got, idx) - ref) / np.linalg.norm(ref))
         # the difference TT (and z's explicit cores) must fit comfortably in HBM
-        kept_r = ra.ranks[0].tolist()
+        kept_r = rb[i].ranks[0].tolist()
         zr = [a * b for a, b in zip(X.ranks, Z.ranks)]
         diff_bytes = 8 * sum((kept_r[k] + zr[k]) * n * (kept_r[k + 1] + zr[k + 1]) for k in range(d))
         exact = None
         if diff_bytes <= 48 << 30:
             zt = H.hadamard_explicit(X, Z)
-            exact = H.rel_err(H.kept_cores(ra), [zt.core(k, 0) for k in range(d)])
+            exact = H.rel_err(H.kept_cores(rb[i]), [zt.core(k, 0) for k in range(d)])
             del zt
-        row = {"pair": q, "d": d, "n": n, "r_x": rx, "r_y": ry, "attempts": att_a, "max_width": max(ell_a),
-               "max_rank": max(ra.ranks[0].tolist()), "s": dt, "rel_err_vs_z": exact,
-               "sampled_rel_err_vs_z": samp}
+            torch.cuda.empty_cache()
+        row = {"pair": q, "d": d, "n": n, "r_x": rx, "r_y": ry, "attempts": att_b[i], "max_width": max(ell_b[i]),
+               "max_rank": max(kept_r), "rel_err_vs_z": exact, "sampled_rel_err_vs_z": samp}
         tol_rows.append(row)
         ex_s = f"{exact:.2e}" if exact is not None else "not formed (difference TT too large)"
-        print(f"[bench] tolerance mode pair {q} (d {d}, n {n}, r {rx}x{ry}): {dt:.2f} s, {att_a} attempts, "
-              f"width {max(ell_a)}, error vs z {ex_s} (sampled entries {samp:.1e})", file=sys.stderr, flush=True)
+        print(f"[bench] tolerance mode pair {q} (d {d}, n {n}, r {rx}x{ry}): {att_b[i]} attempts, "
+              f"width {max(ell_b[i])}, error vs z {ex_s} (sampled entries {samp:.1e})", file=sys.stderr, flush=True)
+    del rb
+    torch.cuda.empty_cache()
+    single_s, same = 0.0, True
+    for i, q in enumerate(picks):
+        X, Z = pairs[q]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ra, ell_a, att_a = H.recompress_adaptive(X, Z, cfg["tol"], seed=77 + i, max_attempts=12,
+                                                 precision=args.precision)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        single_s += dt
+        tol_rows[i]["single_pair_s"] = dt
+        same = same and ell_a == ell_b[i] and att_a == att_b[i]
+        print(f"[bench] single-pair tolerance mode pair {q}: {dt:.2f} s", file=sys.stderr, flush=True)
         del ra
         torch.cuda.empty_cache()
     line = {"metric": "HaTT recompressions/s, uneven batch of 512 pairs", "value": value,
@@ -291,9 +312,11 @@ def _bench_batched(args, torch, wk, H) -> int:
             "tolerance_check": {"bonds": nbond, "bonds_without_slack": int(sum(tight)),
                                 "pairs_with_slack_on_every_bond": int(sum(1 for t in tight if t == 0)),
                                 "sample": errs},
-            "tolerance_mode_sample": {"tol": cfg["tol"], "pairs": tol_rows,
-                                      "note": "per pair, widths grown until the truncation leaves slack "
-                                              "(not part of the value)"}}
+            "tolerance_mode_sample": {"tol": cfg["tol"], "pairs": tol_rows, "batched_s": batch_s,
+                                      "single_pair_total_s": single_s, "same_widths_as_single_pair": same,
+                                      "note": "batched tolerance mode: per pair, widths grown until the "
+                                              "truncation leaves slack and the sketch captured the product; "
+                                              "attempt rounds of all pairs side by side (not part of the value)"}}
     print(json.dumps(line), flush=True)
     return 0
 

@@ -188,7 +188,10 @@ HATT_API hatt_status hatt_recompress_batched(int32_t npairs, const hatt_tt *x, c
  *   resolve ||z - X||^2 below 256 eps ||z||^2).  Else l_k = min(cap_k,
  *   ceil(1.5 l_k) + p) on each bond failing the slack test (for any train of
  *   the batch), or on every bond below its cap when only the capture test
- *   failed, and retry.
+ *   failed, and retry.  With FP32 or BF16 range finding (opts->precision),
+ *   a capture failure with every bond at its cap (where the sketch spans the
+ *   product's range up to its own rounding) switches the following attempts
+ *   to FP64 range finding instead; the plan's workspace covers both.
  * Widths never grow beyond 3072 (the truncation's SVD limit): a bond that
  * would need more returns HATT_ENOTCONV.
  * hatt_adaptive_plan: cap_out (host [d+1]) = largest widths the growth may
@@ -223,6 +226,46 @@ HATT_API hatt_status hatt_recompress_adaptive(const hatt_tt *x, const hatt_tt *y
                                               double *out, int64_t out_stride, int64_t *out_rank,
                                               int64_t *ell_out, int32_t *attempts_out, void *ws,
                                               size_t ws_bytes, void *stream);
+
+/*
+ * Tolerance mode over an uneven batch (npairs pairs of any shapes, two
+ * factors each): pair p follows the rule of hatt_recompress_adaptive with
+ * seed opts->seed + p and its own widths, so its widths, attempts and result
+ * are those of the single-pair call with that seed.  Attempts run in rounds:
+ * round a runs attempt a of every pair not yet accepted, concurrently on the
+ * library streams (forked from `stream` and joined back), then synchronises
+ * `stream` once and takes every pair's decision from its kept ranks and
+ * ||X||.  Before the first round the same streams check x and y for
+ * non-finite values (HATT_ENONFINITE, naming the pair) and form ||x (.) y||
+ * of every train.  opts->ell_init, if not NULL, holds the start widths of
+ * every pair (d_p + 1 entries per pair, concatenated in pair order).
+ * hatt_batched_adaptive_plan: out_offset / rank_offset (host [npairs + 1]):
+ * pair p's trains at element offset out_offset[p] of `out`, one slot per
+ * train at the widths in cap_out (host, may be NULL; d_p + 1 entries per
+ * pair, concatenated: the widths the growth may reach), its kept ranks
+ * ([batch_p][d_p + 1]) at rank_offset[p] of out_rank.  ws_min: the smallest
+ * workspace that runs every round (one pair at a time when a round's pairs
+ * do not fit side by side); ws_full: enough for the largest pairs to run on
+ * all streams at once.  Between the two, each round runs as many pairs side
+ * by side as the workspace holds.
+ * hatt_recompress_batched_adaptive: writes pair p's result packed inside its
+ * slots at the widths of its last attempt, those widths in ell_out (host,
+ * d_p + 1 per pair, concatenated) and its attempt count in attempts_out
+ * (host [npairs]).  A pair that cannot converge (a failing bond at its
+ * limit, or max_attempts used) keeps its last result; the other pairs
+ * finish, and the call returns HATT_ENOTCONV naming the first such pair.
+ * Not capturable (HATT_EUNSUPPORTED under HIP graph capture); concurrent
+ * calls are serialised with hatt_recompress_batched.
+ */
+HATT_API hatt_status hatt_batched_adaptive_plan(int32_t npairs, const hatt_tt *x, const hatt_tt *y,
+                                                const hatt_adapt_opts *opts, int64_t *out_offset,
+                                                int64_t *rank_offset, int64_t *cap_out, size_t *ws_min,
+                                                size_t *ws_full);
+HATT_API hatt_status hatt_recompress_batched_adaptive(int32_t npairs, const hatt_tt *x, const hatt_tt *y,
+                                                      const hatt_adapt_opts *opts, double *out,
+                                                      int64_t *out_rank, int64_t *ell_out,
+                                                      int32_t *attempts_out, void *ws, size_t ws_bytes,
+                                                      void *stream);
 
 /*
  * Three factors: recompress x (.) y (.) w in one pass, without forming the

@@ -15,6 +15,7 @@ from .api import (  # noqa: F401
     rankpred_labels,
     rel_err,
     batched_plan,
+    batched_adaptive_plan,
     hadamard_explicit,
     hadamard_norm2,
     norm,
@@ -35,6 +36,7 @@ from .api import (  # noqa: F401
     recompress3,
     recompress3_adaptive,
     recompress_batched,
+    recompress_batched_adaptive,
     recompress_noalloc,
     randorth,
     round,

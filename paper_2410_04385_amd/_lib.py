@@ -25,6 +25,7 @@ EXPORTED = [
     "hatt_rankpred_grad", "hatt_rankpred_train_step", "hatt_rankpred_widths", "hatt_rankpred_labels",
     "hatt_plan3", "hatt_recompress3", "hatt_adaptive_plan3", "hatt_recompress3_adaptive",
     "hatt_tune_mode", "hatt_tune_clear", "hatt_tune_table", "hatt_hadamard_norm2_plan", "hatt_hadamard_norm2",
+    "hatt_batched_adaptive_plan", "hatt_recompress_batched_adaptive",
 ]
 RANKPRED_NIN, RANKPRED_NTHETA, RANKPRED_NSTATS = 21, 19586, 46
 PROFILE_CLASSES = 8
@@ -102,6 +103,9 @@ def lib() -> ctypes.CDLL:
     L.hatt_adaptive_plan.argtypes = [ttp, ttp, aop, i64p, szp, i64p]
     L.hatt_recompress_adaptive.argtypes = [ttp, ttp, aop, vp, ctypes.c_int64, vp, i64p,
                                            ctypes.POINTER(ctypes.c_int32), vp, ctypes.c_size_t, vp]
+    L.hatt_batched_adaptive_plan.argtypes = [ctypes.c_int32, ttp, ttp, aop, i64p, i64p, i64p, szp, szp]
+    L.hatt_recompress_batched_adaptive.argtypes = [ctypes.c_int32, ttp, ttp, aop, vp, vp, i64p,
+                                                   ctypes.POINTER(ctypes.c_int32), vp, ctypes.c_size_t, vp]
     L.hatt_plan3.argtypes = [ttp, ttp, ttp, optp, i64p, szp, i64p]
     L.hatt_recompress3.argtypes = [ttp, ttp, ttp, ttp, optp, vp, ctypes.c_int64, vp, vp, ctypes.c_size_t, vp]
     L.hatt_adaptive_plan3.argtypes = [ttp, ttp, ttp, aop, i64p, szp, i64p]

@@ -311,6 +311,79 @@ def recompress_adaptive(x: TT, y: TT, tol: float, *, seed: int = 0, oversample: 
     return Result(out, ranks), list(ell), int(att.value)
 
 
+def _batched_adapt_opts(pairs, tol, seed, oversample, max_attempts, variant, ep, ell_init, precision):
+    init = None
+    if ell_init is not None:
+        if len(ell_init) != len(pairs) or any(len(e) != x.d + 1 for e, (x, _) in zip(ell_init, pairs)):
+            raise ValueError("ell_init needs d_p+1 widths for every pair")
+        init = i64_array([v for e in ell_init for v in e])
+    if precision not in _PRECISION:
+        raise ValueError(f"unknown precision {precision!r}")
+    o = HattAdaptOpts(float(tol), int(seed) & 0xFFFFFFFFFFFFFFFF, int(oversample), int(max_attempts),
+                      int(variant), float(ep), init, _PRECISION[precision])
+    return o, init
+
+
+def batched_adaptive_plan(pairs, tol: float, *, seed: int = 0, oversample: int = 8, max_attempts: int = 8,
+                          variant: int = 1, ep: float = 0.0, ell_init=None, precision: str = "f64"):
+    """Plan of recompress_batched_adaptive: per-pair output and rank offsets,
+    the widths each pair may grow to, and the smallest / full-concurrency
+    workspace sizes."""
+    npairs = len(pairs)
+    views = [(x.view(), y.view()) for x, y in pairs]
+    xs = (HattTT * npairs)(*[v[0][0] for v in views])
+    ys = (HattTT * npairs)(*[v[1][0] for v in views])
+    o, init = _batched_adapt_opts(pairs, tol, seed, oversample, max_attempts, variant, ep, ell_init, precision)
+    oo = (ctypes.c_int64 * (npairs + 1))()
+    ro = (ctypes.c_int64 * (npairs + 1))()
+    co = (ctypes.c_int64 * sum(x.d + 1 for x, _ in pairs))()
+    wmin, wfull = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    check("hatt_batched_adaptive_plan", lib().hatt_batched_adaptive_plan(
+        npairs, xs, ys, ctypes.byref(o), oo, ro, co, ctypes.byref(wmin), ctypes.byref(wfull)))
+    caps, e = [], 0
+    for x, _ in pairs:
+        caps.append(list(co[e:e + x.d + 1]))
+        e += x.d + 1
+    return {"out_offset": list(oo), "rank_offset": list(ro), "cap": caps, "ws_min": int(wmin.value),
+            "ws_full": int(wfull.value), "_keep": (views, xs, ys, o, init)}
+
+
+def recompress_batched_adaptive(pairs, tol: float, *, seed: int = 0, oversample: int = 8, max_attempts: int = 8,
+                                variant: int = 1, ep: float = 0.0, ell_init=None, precision: str = "f64",
+                                max_workspace: int = 64 << 30, workspace: Optional[torch.Tensor] = None,
+                                stream=None):
+    """Tolerance mode over an uneven batch: pair p follows recompress_adaptive
+    with seed + p and its own widths; every attempt round runs the pairs not
+    yet accepted side by side and synchronises once.  The workspace (given,
+    or allocated at the full-concurrency size capped by ``max_workspace`` but
+    never below the minimum) decides how many pairs run side by side.
+    Returns (one Result per pair, widths per pair, attempts per pair)."""
+    p = batched_adaptive_plan(pairs, tol, seed=seed, oversample=oversample, max_attempts=max_attempts,
+                              variant=variant, ep=ep, ell_init=ell_init, precision=precision)
+    views, xs, ys, o, _ = p["_keep"]
+    dev = pairs[0][0].data.device
+    out = torch.zeros(max(p["out_offset"][-1], 1), dtype=torch.float64, device=dev)
+    ranks = torch.empty(max(p["rank_offset"][-1], 1), dtype=torch.int64, device=dev)
+    if workspace is None:
+        workspace = torch.empty(max(p["ws_min"], min(p["ws_full"], int(max_workspace))), dtype=torch.uint8,
+                                device=dev)
+    npairs = len(pairs)
+    ell = (ctypes.c_int64 * sum(x.d + 1 for x, _ in pairs))()
+    att = (ctypes.c_int32 * npairs)()
+    check("hatt_recompress_batched_adaptive", lib().hatt_recompress_batched_adaptive(
+        npairs, xs, ys, ctypes.byref(o), ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ranks.data_ptr()), ell,
+        att, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr(stream)))
+    res, ells, e = [], [], 0
+    for k, (x, _) in enumerate(pairs):
+        a, b = p["out_offset"][k], p["out_offset"][k + 1]
+        ells.append(list(ell[e:e + x.d + 1]))
+        e += x.d + 1
+        tt = TT(out[a:b], x.n, ells[-1], x.batch, stride=(b - a) // x.batch)
+        ra, rb = p["rank_offset"][k], p["rank_offset"][k + 1]
+        res.append(Result(tt, ranks[ra:rb].view(x.batch, x.d + 1)))
+    return res, ells, list(att)
+
+
 def plan3(x: TT, y: TT, w: TT, ell, max_rank: int = 0, tol: float = 0.0, seed: int = 0):
     """Widths, workspace and output size of recompress3."""
     xv, kx = x.view()

@@ -2665,6 +2665,63 @@ static hatt_status adapt_prepare(const hatt_tt *x, const hatt_tt *y, const hatt_
   return HATT_OK;
 }
 
+// One decision of the tolerance rule for the P trains of one recompression
+// at widths sp.ell: the bonds to grow, or a switch of the range finding to
+// FP64 (neither: accept).  kept holds the kept ranks [P][d+1]; z2 and xn hold
+// ||z||^2 and ||X|| per train (read only with `capture`).  Slack test: a bond
+// below its cap keeps at most l_k - p.  A capture failure grows every bond
+// below its cap; with every bond at its cap the sketch spans the product's
+// range exactly up to the rounding of the sketches, so a failure there under
+// FP32 or BF16 range finding is that rounding, and the next attempt runs in
+// FP64.
+struct AdaptStep {
+  std::vector<int> grow;
+  bool to_fp64 = false;
+  bool accept() const { return grow.empty() && !to_fp64; }
+};
+
+static AdaptStep adapt_decide(const HattSpec &sp, const std::vector<int64_t> &cap, int p, const int64_t *kept,
+                              bool capture, const double *z2, const double *xn, double tol) {
+  const int d = sp.X.d, P = sp.X.batch;
+  AdaptStep step;
+  std::vector<int> &bad = step.grow;
+  for (int k = 1; k < d; ++k) {
+    bool b = false;
+    for (int q = 0; q < P; ++q)
+      if (kept[(size_t)q * (d + 1) + k] > sp.ell[k] - p && sp.ell[k] < cap[k]) b = true;
+    if (b) bad.push_back(k);
+  }
+  // the captured range: ||z - X||^2 = ||z||^2 - ||X||^2 (X is an orthogonal
+  // projection of z); when it exceeds (tol / 2)^2 ||z||^2 every bond below
+  // its cap grows
+  bool capture_bad = false;
+  if (capture)
+    for (int q = 0; q < P; ++q) {
+      const double c2 = std::max(0.0, z2[q] - xn[q] * xn[q]);
+      if (c2 > std::max(kCaptureShare2 * tol * tol, kCaptureFloor) * z2[q]) capture_bad = true;
+    }
+  if (bad.empty() && capture_bad) {
+    for (int k = 1; k < d; ++k)
+      if (sp.ell[k] < cap[k]) bad.push_back(k);
+    if (bad.empty() && sp.o.precision != 0) step.to_fp64 = true;
+  }
+  return step;
+}
+
+// Growth of the failing bonds: l_k = min(lim_k, ceil(1.5 l_k) + p); a bond
+// already at lim_k cannot grow (HATT_ENOTCONV).
+static hatt_status adapt_grow(const std::vector<int64_t> &cur, const std::vector<int> &bad,
+                              const std::vector<int64_t> &lim, int p, std::vector<int64_t> *ell) {
+  *ell = cur;
+  for (int k : bad) {
+    if (cur[k] >= lim[k])
+      return fail(HATT_ENOTCONV, "bond " + std::to_string(k) + " needs a sketch wider than " +
+                                     std::to_string(lim[k]) + " (the truncation's SVD limit)");
+    (*ell)[k] = std::min<int64_t>(lim[k], (int64_t)std::ceil(1.5 * (double)cur[k]) + p);
+  }
+  return HATT_OK;
+}
+
 static hatt_status adaptive_plan_common(const hatt_tt *x, const hatt_tt *y, const hatt_tt *w,
                                         const hatt_adapt_opts *opts, int64_t *cap_out, size_t *ws_bytes,
                                         int64_t *out_elems) {
@@ -2678,6 +2735,15 @@ static hatt_status adaptive_plan_common(const hatt_tt *x, const hatt_tt *y, cons
   Ws ws(nullptr);
   st = hatt_run(false, sp, ws, nullptr);
   if (st != HATT_OK) return st;
+  if (sp.o.precision != 0) {
+    // a capture failure at the caps switches the attempts to FP64
+    HattSpec s64 = sp;
+    s64.o.precision = 0;
+    Ws w64(nullptr);
+    st = hatt_run(false, s64, w64, nullptr);
+    if (st != HATT_OK) return st;
+    ws.off = std::max(ws.off, w64.off);
+  }
   if (cap_out)
     for (int k = 0; k <= sp.X.d; ++k) cap_out[k] = cap[k];
   // widths below the caps need no more than the caps' buffers up to the
@@ -2787,38 +2853,16 @@ static hatt_status adaptive_common(const hatt_tt *x, const hatt_tt *y, const hat
          hipMemcpyAsync(xn.data(), sp.xnorm, xn.size() * sizeof(double), hipMemcpyDeviceToHost, strm) != hipSuccess) ||
         hipStreamSynchronize(strm) != hipSuccess)
       return fail(HATT_EDEVICE, "reading the kept ranks failed");
-    std::vector<int> bad;
-    for (int k = 1; k < d; ++k) {
-      bool b = false;
-      for (int q = 0; q < P; ++q)
-        if (host_rank[(size_t)q * (d + 1) + k] > sp.ell[k] - p && sp.ell[k] < cap[k]) b = true;
-      if (b) bad.push_back(k);
-    }
-    // the captured range: ||z - X||^2 = ||z||^2 - ||X||^2 (X is an orthogonal
-    // projection of z); when it exceeds (tol / 2)^2 ||z||^2 every bond below
-    // its cap grows
-    bool capture_bad = false;
-    if (capture)
-      for (int q = 0; q < P; ++q) {
-        const double c2 = std::max(0.0, z2[q] - xn[q] * xn[q]);
-        if (c2 > std::max(kCaptureShare2 * tol * tol, kCaptureFloor) * z2[q]) capture_bad = true;
-      }
-    if (bad.empty() && capture_bad)
-      for (int k = 1; k < d; ++k)
-        if (sp.ell[k] < cap[k]) bad.push_back(k);
+    const AdaptStep step = adapt_decide(sp, cap, p, host_rank.data(), capture, z2.data(), xn.data(), tol);
     for (int k = 0; k <= d; ++k) ell_out[k] = sp.ell[k];
     *attempts_out = attempt + 1;
-    if (bad.empty()) {
+    if (step.accept()) {
       g_err.clear();
       return HATT_OK;
     }
-    ell = sp.ell;
-    for (int k : bad) {
-      if (sp.ell[k] >= lim[k])
-        return fail(HATT_ENOTCONV, "bond " + std::to_string(k) + " needs a sketch wider than " +
-                                       std::to_string(lim[k]) + " (the truncation's SVD limit)");
-      ell[k] = std::min<int64_t>(lim[k], (int64_t)std::ceil(1.5 * (double)sp.ell[k]) + p);
-    }
+    if (step.to_fp64) sp.o.precision = 0;
+    st = adapt_grow(sp.ell, step.grow, lim, p, &ell);
+    if (st != HATT_OK) return st;
   }
   return fail(HATT_ENOTCONV, "sketch widths did not converge within max_attempts");
 }
@@ -2846,6 +2890,333 @@ hatt_status hatt_recompress3_adaptive(const hatt_tt *x, const hatt_tt *y, const 
                                       size_t ws_bytes, void *stream) {
   if (w == nullptr) return fail(HATT_EINVAL, "w: NULL tensor view");
   return adaptive_common(x, y, w, opts, out, out_stride, out_rank, ell_out, attempts_out, ws, ws_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Tolerance mode over an uneven batch.  Every pair follows the rule of
+// hatt_recompress_adaptive with its own widths; an attempt round runs the
+// attempts of all pairs not yet accepted at once on the library streams and
+// ends with one host synchronisation, after which the decision of each pair
+// is taken from its kept ranks and ||X|| (copied back together for the whole
+// batch).  The workspace begins with a header (||z||^2, ||X|| and finiteness
+// flags of every train); the rest is carved per round into one region per
+// stream, as large as the largest pair that stream runs in that round, with
+// fewer streams when the regions would not fit.
+struct BatchAdapt {
+  std::vector<HattSpec> sp;
+  std::vector<std::vector<int64_t>> cap, lim, ell;
+  std::vector<int64_t> out_off, rank_off, train_off;
+  std::vector<bool> capture;
+  int p = 8, maxa = 8;
+  size_t header = 0;
+  size_t need_min = 0;   // one region that fits any pair's attempt and its ||z|| pass
+  size_t need_full = 0;  // regions for the min(npairs, streams) largest pairs
+};
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static hatt_status batch_adapt_prepare(int32_t npairs, const hatt_tt *x, const hatt_tt *y, const hatt_adapt_opts *ao,
+                                       bool need_data, BatchAdapt *ba) {
+  if (npairs < 1) return fail(HATT_EINVAL, "npairs must be >= 1");
+  if (x == nullptr || y == nullptr || ao == nullptr) return fail(HATT_EINVAL, "NULL argument");
+  ba->sp.assign(npairs, HattSpec{});
+  ba->cap.assign(npairs, {});
+  ba->lim.assign(npairs, {});
+  ba->ell.assign(npairs, {});
+  ba->capture.assign(npairs, false);
+  ba->out_off.assign(npairs + 1, 0);
+  ba->rank_off.assign(npairs + 1, 0);
+  ba->train_off.assign(npairs + 1, 0);
+  std::vector<size_t> need(npairs, 0);
+  int64_t eoff = 0;
+  for (int32_t q = 0; q < npairs; ++q) {
+    hatt_adapt_opts o = *ao;
+    o.seed = ao->seed + (uint64_t)q;
+    if (ao->ell_init != nullptr) {
+      if (x[q].d < 1) return fail(HATT_ESHAPE, "pair " + std::to_string(q) + ": bad order");
+      o.ell_init = ao->ell_init + eoff;
+      eoff += x[q].d + 1;
+    }
+    HattSpec &sp = ba->sp[q];
+    hatt_status st = adapt_prepare(&x[q], &y[q], nullptr, &o, &sp, &ba->cap[q], &ba->lim[q], &ba->ell[q], &ba->p,
+                                   &ba->maxa, need_data);
+    if (st != HATT_OK) return fail(st, "pair " + std::to_string(q) + ": " + g_err);
+    sp.o.seed = o.seed;
+    sp.sketch = nullptr;
+    ba->capture[q] = sp.X.d >= 2;
+    // any attempt: the buffers at the growth limit, with the single-pair
+    // margin; the ||x (.) y|| pass runs in the same region before the attempts
+    HattSpec at = sp;
+    at.ell = ba->lim[q];
+    Ws meas(nullptr);
+    st = hatt_run(false, at, meas, nullptr);
+    if (st != HATT_OK) return fail(st, "pair " + std::to_string(q) + ": " + g_err);
+    if (at.o.precision != 0) {
+      // a capture failure at the caps switches the attempts to FP64
+      at.o.precision = 0;
+      Ws w64(nullptr);
+      st = hatt_run(false, at, w64, nullptr);
+      if (st != HATT_OK) return fail(st, "pair " + std::to_string(q) + ": " + g_err);
+      meas.off = std::max(meas.off, w64.off);
+    }
+    size_t nd = meas.off + meas.off / 8 + ((size_t)4 << 20);
+    if (ba->capture[q]) {
+      Ws wn(nullptr);
+      GemmCtx gm{nullptr, 0, 0};
+      st = hadamard_norm2_body(false, sp.X, sp.Y, nullptr, wn, gm, nullptr);
+      if (st != HATT_OK) return fail(st, "pair " + std::to_string(q) + ": " + g_err);
+      nd = std::max(nd, wn.off);
+    }
+    need[q] = align256(nd);
+    std::vector<int64_t> off;
+    int64_t tot;
+    make_offsets(sp.X.n, ba->lim[q], &off, &tot);
+    sp.ostride = tot;
+    ba->out_off[q + 1] = ba->out_off[q] + tot * sp.X.batch;
+    ba->rank_off[q + 1] = ba->rank_off[q] + (int64_t)sp.X.batch * (sp.X.d + 1);
+    ba->train_off[q + 1] = ba->train_off[q] + sp.X.batch;
+  }
+  const int64_t T = ba->train_off[npairs];
+  ba->header = 2 * align256((size_t)T * sizeof(double)) + align256((size_t)T * 2 * sizeof(int));
+  std::vector<size_t> sorted = need;
+  std::sort(sorted.begin(), sorted.end(), std::greater<size_t>());
+  ba->need_min = ba->header + sorted[0];
+  size_t full = ba->header;
+  for (int k = 0; k < std::min<int>(npairs, kBatchStreams); ++k) full += sorted[k];
+  ba->need_full = full;
+  return HATT_OK;
+}
+
+// Streams and regions of one round: pairs `todo` with workspace needs `need`
+// onto at most kBatchStreams streams, longest first onto the least loaded;
+// regions as large as the largest pair of their stream, the stream count
+// lowered until the regions fit in `avail` bytes.
+static hatt_status batch_adapt_carve(const std::vector<int> &todo, const std::vector<double> &cost,
+                                     const std::vector<size_t> &need, size_t avail, std::vector<int> *stream_of,
+                                     std::vector<size_t> *region_off, int *streams) {
+  std::vector<int> order(todo);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  for (int S = std::min<int>((int)todo.size(), kBatchStreams); S >= 1; --S) {
+    std::vector<double> load(S, 0.0);
+    std::vector<size_t> reg(S, 0);
+    for (int q : order) {
+      int k = 0;
+      for (int t = 1; t < S; ++t)
+        if (load[t] < load[k]) k = t;
+      (*stream_of)[q] = k;
+      load[k] += cost[q];
+      reg[k] = std::max(reg[k], need[q]);
+    }
+    size_t tot = 0;
+    region_off->assign(S + 1, 0);
+    for (int k = 0; k < S; ++k) {
+      (*region_off)[k] = tot;
+      tot += reg[k];
+    }
+    (*region_off)[S] = tot;
+    if (tot <= avail) {
+      *streams = S;
+      return HATT_OK;
+    }
+  }
+  size_t big = 0;
+  for (int q : todo) big = std::max(big, need[q]);
+  return fail(HATT_EWORKSPACE, "workspace too small: a round needs " + std::to_string(big) +
+                                   " bytes after the header, " + std::to_string(avail) + " available");
+}
+
+hatt_status hatt_batched_adaptive_plan(int32_t npairs, const hatt_tt *x, const hatt_tt *y,
+                                       const hatt_adapt_opts *opts, int64_t *out_offset, int64_t *rank_offset,
+                                       int64_t *cap_out, size_t *ws_min, size_t *ws_full) {
+  BatchAdapt ba;
+  hatt_status st = batch_adapt_prepare(npairs, x, y, opts, false, &ba);
+  if (st != HATT_OK) return st;
+  if (out_offset)
+    for (int32_t q = 0; q <= npairs; ++q) out_offset[q] = ba.out_off[q];
+  if (rank_offset)
+    for (int32_t q = 0; q <= npairs; ++q) rank_offset[q] = ba.rank_off[q];
+  if (cap_out) {
+    int64_t e = 0;
+    for (int32_t q = 0; q < npairs; ++q)
+      for (int64_t v : ba.lim[q]) cap_out[e++] = v;
+  }
+  if (ws_min) *ws_min = ba.need_min;
+  if (ws_full) *ws_full = ba.need_full;
+  g_err.clear();
+  return HATT_OK;
+}
+
+hatt_status hatt_recompress_batched_adaptive(int32_t npairs, const hatt_tt *x, const hatt_tt *y,
+                                             const hatt_adapt_opts *opts, double *out, int64_t *out_rank,
+                                             int64_t *ell_out, int32_t *attempts_out, void *ws, size_t ws_bytes,
+                                             void *stream) {
+  BatchAdapt ba;
+  hatt_status st = batch_adapt_prepare(npairs, x, y, opts, true, &ba);
+  if (st != HATT_OK) return st;
+  if (out == nullptr || out_rank == nullptr || ell_out == nullptr || attempts_out == nullptr)
+    return fail(HATT_EINVAL, "NULL output argument");
+  if (ws == nullptr || ws_bytes < ba.need_min)
+    return fail(HATT_EWORKSPACE, "workspace too small: need at least " + std::to_string(ba.need_min) + " bytes");
+  hipStream_t caller = (hipStream_t)stream;
+  hipStreamCaptureStatus capst = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(caller, &capst) != hipSuccess) return fail(HATT_EDEVICE, "hipStreamIsCapturing failed");
+  if (capst != hipStreamCaptureStatusNone)
+    return fail(HATT_EUNSUPPORTED, "the tolerance mode synchronises per round and cannot be captured");
+  std::lock_guard<std::mutex> lock(g_batch_mu);
+  BatchStreams *bs = nullptr;
+  st = batch_streams(&bs);
+  if (st != HATT_OK) return st;
+  const int64_t T = ba.train_off[npairs];
+  char *base = static_cast<char *>(ws);
+  double *z2d = reinterpret_cast<double *>(base);
+  double *xnd = reinterpret_cast<double *>(base + align256((size_t)T * sizeof(double)));
+  int *fld = reinterpret_cast<int *>(base + 2 * align256((size_t)T * sizeof(double)));
+  char *arena = base + ba.header;
+  const size_t avail = ws_bytes - ba.header;
+  std::vector<int> stream_of(npairs, 0);
+  std::vector<size_t> region;
+  std::vector<double> cost(npairs, 0.0);
+  std::vector<size_t> need(npairs, 0);
+  int S = 1;
+  auto fork = [&](int nstreams) -> hatt_status {
+    if (hipEventRecord(bs->fork, caller) != hipSuccess) return fail(HATT_EDEVICE, "event record failed");
+    for (int k = 0; k < nstreams; ++k)
+      if (hipStreamWaitEvent(bs->s[k], bs->fork, 0) != hipSuccess) return fail(HATT_EDEVICE, "stream wait failed");
+    return HATT_OK;
+  };
+  auto join = [&](int nstreams) -> hatt_status {
+    for (int k = 0; k < nstreams; ++k) {
+      if (hipEventRecord(bs->join[k], bs->s[k]) != hipSuccess) return fail(HATT_EDEVICE, "event record failed");
+      if (hipStreamWaitEvent(caller, bs->join[k], 0) != hipSuccess) return fail(HATT_EDEVICE, "stream wait failed");
+    }
+    return HATT_OK;
+  };
+  std::vector<int> todo(npairs);
+  for (int32_t q = 0; q < npairs; ++q) todo[q] = q;
+
+  // set-up round: finiteness of x and y, then ||x (.) y||^2 per train
+  std::vector<double> z2((size_t)T, 0.0), xn((size_t)T, 0.0);
+  {
+    for (int q : todo) {
+      Ws wn(nullptr);
+      GemmCtx gm{nullptr, 0, 0};
+      if (ba.capture[q]) {
+        st = hadamard_norm2_body(false, ba.sp[q].X, ba.sp[q].Y, nullptr, wn, gm, nullptr);
+        if (st != HATT_OK) return fail(st, "pair " + std::to_string(q) + ": " + g_err);
+      }
+      need[q] = align256(std::max<size_t>(wn.off, 256));
+      cost[q] = batch_pair_cost(ba.sp[q]);
+    }
+    st = batch_adapt_carve(todo, cost, need, avail, &stream_of, &region, &S);
+    if (st != HATT_OK) return st;
+    st = fork(S);
+    if (st != HATT_OK) return st;
+    for (int q : todo) {
+      const HattSpec &sp = ba.sp[q];
+      const bool run = true;
+      hipStream_t s_ = bs->s[stream_of[q]];
+      int *fl = fld + 2 * ba.train_off[q];
+      const int P = sp.X.batch;
+      {
+        hipStream_t st = s_;
+        LAUNCH(launch_finite_check(sp.X.data, sp.X.total, sp.X.stride, P, fl, st));
+        LAUNCH(launch_finite_check(sp.Y.data, sp.Y.total, sp.Y.stride, P, fl + P, st));
+      }
+      if (ba.capture[q]) {
+        Ws wn(arena + region[stream_of[q]]);
+        GemmCtx gm{nullptr, 0, 0};
+        st = hadamard_norm2_body(true, sp.X, sp.Y, z2d + ba.train_off[q], wn, gm, s_);
+        if (st != HATT_OK) return fail(st, "pair " + std::to_string(q) + ": " + g_err);
+      }
+    }
+    st = join(S);
+    if (st != HATT_OK) return st;
+    std::vector<int> hf((size_t)2 * T);
+    if (hipMemcpyAsync(hf.data(), fld, hf.size() * sizeof(int), hipMemcpyDeviceToHost, caller) != hipSuccess ||
+        hipMemcpyAsync(z2.data(), z2d, z2.size() * sizeof(double), hipMemcpyDeviceToHost, caller) != hipSuccess ||
+        hipStreamSynchronize(caller) != hipSuccess)
+      return fail(HATT_EDEVICE, "reading the finiteness flags and ||x (.) y|| failed");
+    for (int q : todo) {
+      const int P = ba.sp[q].X.batch;
+      for (int t = 0; t < 2 * P; ++t)
+        if (hf[2 * ba.train_off[q] + t] != 1)
+          return fail(HATT_ENONFINITE, "pair " + std::to_string(q) + ": " + (t < P ? "x" : "y") + " train " +
+                                           std::to_string(t % P) + " has a non-finite entry");
+    }
+  }
+
+  // attempt rounds
+  const double tol = opts->tol;
+  std::vector<int64_t> host_rank((size_t)ba.rank_off[npairs]);
+  std::vector<std::vector<int64_t>> used(npairs);
+  std::string stuck;
+  int nstuck = 0;
+  for (int attempt = 0; attempt < ba.maxa && !todo.empty(); ++attempt) {
+    for (int q : todo) {
+      HattSpec &sp = ba.sp[q];
+      sp.ell = clamp_ell(sp.X.n, sp.X.r, sp.ryw, ba.ell[q]);
+      sp.o.seed = opts->seed + (uint64_t)q + (uint64_t)attempt;
+      sp.o.tol = ba.capture[q] ? tol * kTruncShare : tol;
+      sp.out = out + ba.out_off[q];
+      sp.orank = out_rank + ba.rank_off[q];
+      sp.xnorm = ba.capture[q] ? xnd + ba.train_off[q] : nullptr;
+      Ws meas(nullptr);
+      st = hatt_run(false, sp, meas, nullptr);
+      if (st != HATT_OK) return fail(st, "pair " + std::to_string(q) + ": " + g_err);
+      need[q] = align256(std::max<size_t>(meas.off, 256));
+      cost[q] = batch_pair_cost(sp);
+    }
+    st = batch_adapt_carve(todo, cost, need, avail, &stream_of, &region, &S);
+    if (st != HATT_OK) return st;
+    st = fork(S);
+    if (st != HATT_OK) return st;
+    // largest first, so each stream starts with its costliest pair
+    std::vector<int> order(todo);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    for (int q : order) {
+      Ws w(arena + region[stream_of[q]]);
+      st = hatt_run(true, ba.sp[q], w, bs->s[stream_of[q]]);
+      if (st != HATT_OK) return fail(st, "pair " + std::to_string(q) + ": " + g_err);
+    }
+    st = join(S);
+    if (st != HATT_OK) return st;
+    if (hipMemcpyAsync(host_rank.data(), out_rank, host_rank.size() * sizeof(int64_t), hipMemcpyDeviceToHost,
+                       caller) != hipSuccess ||
+        hipMemcpyAsync(xn.data(), xnd, xn.size() * sizeof(double), hipMemcpyDeviceToHost, caller) != hipSuccess ||
+        hipStreamSynchronize(caller) != hipSuccess)
+      return fail(HATT_EDEVICE, "reading the kept ranks failed");
+    // a pair whose failing bond cannot grow stops there (its last result in
+    // place); the others go on
+    std::vector<int> next;
+    for (int q : todo) {
+      const HattSpec &sp = ba.sp[q];
+      const AdaptStep step =
+          adapt_decide(sp, ba.cap[q], ba.p, host_rank.data() + ba.rank_off[q], ba.capture[q],
+                       z2.data() + ba.train_off[q], xn.data() + ba.train_off[q], tol);
+      used[q] = sp.ell;
+      attempts_out[q] = attempt + 1;
+      if (step.accept()) continue;
+      if (step.to_fp64) ba.sp[q].o.precision = 0;
+      if (adapt_grow(sp.ell, step.grow, ba.lim[q], ba.p, &ba.ell[q]) != HATT_OK) {
+        if (stuck.empty()) stuck = "pair " + std::to_string(q) + ": " + g_err;
+        ++nstuck;
+        continue;
+      }
+      next.push_back(q);
+    }
+    todo.swap(next);
+  }
+  int64_t e = 0;
+  for (int32_t q = 0; q < npairs; ++q)
+    for (int64_t v : used[q]) ell_out[e++] = v;
+  if (!stuck.empty())
+    return fail(HATT_ENOTCONV, stuck + " (" + std::to_string(nstuck) + " pairs at the width limit, " +
+                                   std::to_string(todo.size()) + " out of attempts)");
+  if (!todo.empty())
+    return fail(HATT_ENOTCONV, "pair " + std::to_string(todo[0]) + ": sketch widths did not converge within " +
+                                   "max_attempts (" + std::to_string(todo.size()) + " pairs unconverged)");
+  g_err.clear();
+  return HATT_OK;
 }
 
 hatt_status tt_hadamard_explicit(const hatt_tt *x, const hatt_tt *y, double *out, int64_t out_stride,

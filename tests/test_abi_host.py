@@ -461,3 +461,44 @@ def test_tune_mode_and_table_on_the_host():
         api.tune("fast")
     assert _lib.lib().hatt_tune_mode(3) == -1
     assert _lib.lib().hatt_tune_table(None, 0) == 1
+
+
+def test_batched_adaptive_plan_matches_single_pair_plans():
+    """The batched tolerance mode's plan: per pair, the widths the growth may
+    reach are the single-pair plan's, and the output slots are laid out at
+    those widths one after the other; the minimum workspace runs any one pair
+    and the full one covers the largest pairs side by side."""
+    shapes = [(6, 8, 4, 6), (7, 12, 8, 5), (5, 16, 10, 10), (3, 4, 2, 3)]
+    pairs = []
+    for d, n, rx, ry in shapes:
+        nn = [n] * d
+        pairs.append((_cpu_tt(nn, wk.feasible_ranks(nn, rx)), _cpu_tt(nn, wk.feasible_ranks(nn, ry))))
+    p = api.batched_adaptive_plan(pairs, 1e-6, seed=3)
+    off = 0
+    for k, (x, y) in enumerate(pairs):
+        caps = api.adaptive_caps(x, y)
+        assert p["cap"][k] == caps
+        assert p["out_offset"][k] == off
+        off += api._offsets(x.n, caps)[1] * x.batch
+        assert p["rank_offset"][k + 1] - p["rank_offset"][k] == x.batch * (x.d + 1)
+    assert p["out_offset"][-1] == off
+    assert 0 < p["ws_min"] <= p["ws_full"]
+    one = api.batched_adaptive_plan(pairs[2:3], 1e-6, seed=3)
+    assert one["ws_min"] <= p["ws_min"] and one["ws_full"] == one["ws_min"]
+
+
+def test_batched_adaptive_argument_errors():
+    nn = [4] * 5
+    x = _cpu_tt(nn, wk.feasible_ranks(nn, 3))
+    with pytest.raises(ValueError):
+        api.batched_adaptive_plan([(x, x), (x, x)], 1e-6, ell_init=[[1, 5, 5, 5, 5, 1]])
+    with pytest.raises(ValueError):
+        api.batched_adaptive_plan([(x, x)], 1e-6, ell_init=[[1, 5, 1]])
+    with pytest.raises(HattError) as e:
+        api.batched_adaptive_plan([(x, x)], 0.0)
+    assert e.value.status == -1
+    y = _cpu_tt([4] * 4, wk.feasible_ranks([4] * 4, 3))
+    with pytest.raises(HattError) as e:
+        api.batched_adaptive_plan([(x, x), (x, y)], 1e-6)
+    assert "pair 1" in str(e.value)
+    assert _lib.lib().hatt_batched_adaptive_plan(0, None, None, None, None, None, None, None, None) == -1
