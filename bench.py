@@ -216,6 +216,8 @@ def _bench_batched(args, torch, wk, H) -> int:
     torch.cuda.synchronize()
     kept = [r.ranks[0].cpu().tolist() for r in res]
     value = len(pairs) * args.steps / wall_s
+    print(f"[bench] {value:.1f} recompressions/s ({1000.0 * wall_s / args.steps:.1f} ms per step)",
+          file=sys.stderr, flush=True)
     # the widths are fixed at max(r, s) + 8: a bond whose kept rank reaches
     # its width had no slack, and the tolerance is not guaranteed there
     ells = plan["ell"]
@@ -238,14 +240,16 @@ def _bench_batched(args, torch, wk, H) -> int:
     # widths grown until the truncation at tol leaves slack and the sketch
     # captured the product, attempt rounds of all pairs side by side) on the
     # three smallest, three median and three widest products r_x r_y of the
-    # batch, pair i of the sample with seed 77 + i; the error against z is the
+    # batch, pair i of the sample with seed 77 + i.  The same pairs then run
+    # one by one through the single-pair tolerance mode with the same seeds
+    # (the same launches, so the same results; checked on the widths,
+    # attempts and kept ranks), timed, and the error of each against z is
+    # taken from that single result (one output in memory at a time): the
     # norm of the difference TT [out | -z] (z's explicit PKP cores, ranks up
     # to r_x r_y + kept) over ||z||, both by the library's tt_norm on the GPU
     # (an orthogonalisation sweep: no cancellation), with the error at 4096
     # sampled entries beside it (uniform samples of these spectral tensors
-    # overweight their small entries, so it reads higher).  The same pairs
-    # then run one by one through the single-pair tolerance mode with the
-    # same seeds, for the time and to confirm the same widths.
+    # overweight their small entries, so it reads higher).
     mid = len(order) // 2
     picks = order[:3] + order[mid - 1:mid + 2] + order[-3:]
     sub = [pairs[q] for q in picks]
@@ -255,36 +259,15 @@ def _bench_batched(args, torch, wk, H) -> int:
                                                      precision=args.precision)
     torch.cuda.synchronize()
     batch_s = time.perf_counter() - t0
-    print(f"[bench] batched tolerance mode on {len(sub)} pairs: {batch_s:.2f} s", file=sys.stderr, flush=True)
-    tol_rows = []
+    kept_b = [r.ranks[0].tolist() for r in rb]
+    del rb
+    torch.cuda.empty_cache()
+    print(f"[bench] batched tolerance mode on {len(sub)} pairs: {batch_s:.2f} s, attempts {att_b}",
+          file=sys.stderr, flush=True)
+    tol_rows, single_s, same = [], 0.0, True
     for i, q in enumerate(picks):
         d, n, rx, ry = shapes[q]
         y, z = wk.spectral_pair(20000 + q, d, n, rx, ry)
-        X, Z = pairs[q]
-        got = rb[i].train(0)
-        idx = np.random.default_rng(q).integers(0, n, size=(4096, d))
-        ref = _tt_entries(y, idx) * _tt_entries(z, idx)
-        samp = float(np.linalg.norm(_tt_entries(got, idx) - ref) / np.linalg.norm(ref))
-        # the difference TT (and z's explicit cores) must fit comfortably in HBM
-        kept_r = rb[i].ranks[0].tolist()
-        zr = [a * b for a, b in zip(X.ranks, Z.ranks)]
-        diff_bytes = 8 * sum((kept_r[k] + zr[k]) * n * (kept_r[k + 1] + zr[k + 1]) for k in range(d))
-        exact = None
-        if diff_bytes <= 48 << 30:
-            zt = H.hadamard_explicit(X, Z)
-            exact = H.rel_err(H.kept_cores(rb[i]), [zt.core(k, 0) for k in range(d)])
-            del zt
-            torch.cuda.empty_cache()
-        row = {"pair": q, "d": d, "n": n, "r_x": rx, "r_y": ry, "attempts": att_b[i], "max_width": max(ell_b[i]),
-               "max_rank": max(kept_r), "rel_err_vs_z": exact, "sampled_rel_err_vs_z": samp}
-        tol_rows.append(row)
-        ex_s = f"{exact:.2e}" if exact is not None else "not formed (difference TT too large)"
-        print(f"[bench] tolerance mode pair {q} (d {d}, n {n}, r {rx}x{ry}): {att_b[i]} attempts, "
-              f"width {max(ell_b[i])}, error vs z {ex_s} (sampled entries {samp:.1e})", file=sys.stderr, flush=True)
-    del rb
-    torch.cuda.empty_cache()
-    single_s, same = 0.0, True
-    for i, q in enumerate(picks):
         X, Z = pairs[q]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -293,9 +276,28 @@ def _bench_batched(args, torch, wk, H) -> int:
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         single_s += dt
-        tol_rows[i]["single_pair_s"] = dt
-        same = same and ell_a == ell_b[i] and att_a == att_b[i]
-        print(f"[bench] single-pair tolerance mode pair {q}: {dt:.2f} s", file=sys.stderr, flush=True)
+        kept_r = ra.ranks[0].tolist()
+        same = same and ell_a == ell_b[i] and att_a == att_b[i] and kept_r == kept_b[i]
+        got = ra.train(0)
+        idx = np.random.default_rng(q).integers(0, n, size=(4096, d))
+        ref = _tt_entries(y, idx) * _tt_entries(z, idx)
+        samp = float(np.linalg.norm(_tt_entries(got, idx) - ref) / np.linalg.norm(ref))
+        # the difference TT (and z's explicit cores) must fit comfortably in HBM
+        zr = [a * b for a, b in zip(X.ranks, Z.ranks)]
+        diff_bytes = 8 * sum((kept_r[k] + zr[k]) * n * (kept_r[k + 1] + zr[k + 1]) for k in range(d))
+        exact = None
+        if diff_bytes <= 48 << 30:
+            zt = H.hadamard_explicit(X, Z)
+            exact = H.rel_err(H.kept_cores(ra), [zt.core(k, 0) for k in range(d)])
+            del zt
+        row = {"pair": q, "d": d, "n": n, "r_x": rx, "r_y": ry, "attempts": att_b[i], "max_width": max(ell_b[i]),
+               "max_rank": max(kept_b[i]), "rel_err_vs_z": exact, "sampled_rel_err_vs_z": samp,
+               "single_pair_s": dt}
+        tol_rows.append(row)
+        ex_s = f"{exact:.2e}" if exact is not None else "not formed (difference TT too large)"
+        print(f"[bench] tolerance mode pair {q} (d {d}, n {n}, r {rx}x{ry}): {att_b[i]} attempts, "
+              f"width {max(ell_b[i])}, single-pair {dt:.2f} s, error vs z {ex_s} (sampled entries {samp:.1e})",
+              file=sys.stderr, flush=True)
         del ra
         torch.cuda.empty_cache()
     line = {"metric": "HaTT recompressions/s, uneven batch of 512 pairs", "value": value,
@@ -774,26 +776,62 @@ def _rp_pairs(wk, H, seed, count, max_rs=1024):
     return out
 
 
+def _rp_chunks(H, pairs, tol, budget=136 << 30, most=48):
+    """Consecutive chunks of at most ``most`` pairs for the batched tolerance
+    mode whose outputs (slots at the widths each pair may grow to) stay
+    within ``budget`` bytes of device memory; the workspace beside them is
+    capped at 64 GiB (recompress_batched_adaptive's default), which sets how
+    many pairs of a round run side by side (at most 32, one per library
+    stream)."""
+    chunks, cur, used = [], [], 0
+    for k, (x, y) in enumerate(pairs):
+        b = 8 * H.batched_adaptive_plan([(x, y)], tol)["out_offset"][-1]
+        if cur and (used + b > budget or len(cur) == most):
+            chunks.append(cur)
+            cur, used = [], 0
+        cur.append(k)
+        used += b
+    if cur:
+        chunks.append(cur)
+    return chunks
+
+
+def _rp_call(H, torch, pairs, tol, seed, ell_init=None):
+    """One timed batched tolerance-mode call; returns (results, widths,
+    attempts, seconds)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, ells, atts = H.recompress_batched_adaptive(pairs, tol, seed=seed, max_attempts=12, ell_init=ell_init)
+    torch.cuda.synchronize()
+    return res, ells, atts, time.perf_counter() - t0
+
+
 def _bench_rankpred(args, torch, wk, H) -> int:
-    """Learned start widths on the uneven distribution at tol 1e-6: label
-    recompressions from the adaptive method, GPU training of the width
-    network, then fresh pairs recompressed adaptively from the default and
-    from the predicted widths (the adaptive rule accepts or grows either)."""
+    """Learned start widths on the uneven distribution at tol 1e-6: labels
+    from the batched tolerance mode (each pair's accepted ranks), GPU
+    training of the width network, then fresh pairs recompressed by the
+    batched tolerance mode from the default and from the predicted widths
+    (the rule accepts or grows either; pair k equals the single-pair mode
+    with the same seed, so the attempts are those of the plain method)."""
     import numpy as np
     tol = wk.WORKLOADS["batched"]["tol"]
     say = lambda m: print(f"[rankpred] {m}", file=sys.stderr, flush=True)  # noqa: E731
     train = _rp_pairs(wk, H, 101, args.rp_train, args.rp_max_rs)
-    say(f"{len(train)} training pairs")
-    labels, t_label = [], 0.0
-    for i, (shape, x, y) in enumerate(train):
-        t0 = time.perf_counter()
-        res, ell, att = H.recompress_adaptive(x, y, tol, seed=1000 + i, max_attempts=12)
-        torch.cuda.synchronize()
-        t_label += time.perf_counter() - t0
-        labels.append(H.rankpred_labels(res.ranks[0].tolist(), H.adaptive_caps(x, y)))
-        say(f"label {i} {shape} attempts {att} max width {max(ell)} ({time.perf_counter() - t0:.2f} s)")
-        del res
     pairs = [(x, y) for _, x, y in train]
+    say(f"{len(train)} training pairs")
+    # labels: pair k with seed 1000 + k, in chunks that fit in memory
+    labels, t_label, att_lab = [None] * len(pairs), 0.0, []
+    for ch in _rp_chunks(H, pairs, tol):
+        res, _, atts, dt = _rp_call(H, torch, [pairs[k] for k in ch], tol, 1000 + ch[0])
+        t_label += dt
+        att_lab += atts
+        for j, k in enumerate(ch):
+            labels[k] = H.rankpred_labels(res[j].ranks[0].tolist(), H.adaptive_caps(*pairs[k]))
+        say(f"labels {ch[0]}..{ch[-1]}: {dt:.1f} s, attempts {min(atts)}..{max(atts)}")
+        del res
+        torch.cuda.empty_cache()
+    say(f"labels: {len(pairs)} batched tolerance-mode recompressions in {t_label:.1f} s, attempts "
+        f"{np.mean(att_lab):.2f} on average")
     feat = H.rankpred_features(pairs)
     lab = torch.tensor(np.concatenate(labels), device="cuda")
     stats = H.rankpred_fit_stats(feat, lab)
@@ -815,46 +853,55 @@ def _bench_rankpred(args, torch, wk, H) -> int:
     say(f"trained {steps} Adam steps on {rows} bond rows in {t_train:.2f} s; loss {lh[:20].mean():.3g} -> "
         f"{lh[-100:].mean():.3g}")
     fresh = _rp_pairs(wk, H, 202, args.rp_eval, args.rp_max_rs)
-    rec = []
-    for i, (shape, x, y) in enumerate(fresh):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r0, ell0, a0 = H.recompress_adaptive(x, y, tol, seed=5000 + i, max_attempts=12)
-        torch.cuda.synchronize()
-        t_plain = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        pred = H.rankpred_forward(theta, stats, H.rankpred_features([(x, y)]))
-        (ell_p, rho_p), = H.rankpred_widths([(x, y)], pred, margin=args.rp_margin)
-        r1, ell1, a1 = H.recompress_adaptive(x, y, tol, seed=5000 + i, ell_init=ell_p, max_attempts=12)
-        torch.cuda.synchronize()
-        t_pred = time.perf_counter() - t0
-        k0, k1 = r0.ranks[0].tolist(), r1.ranks[0].tolist()
-        # the difference TT has ranks rho_0 + rho_1: measured where that stays moderate
-        err = H.rel_err(H.kept_cores(r1), H.kept_cores(r0)) if max(k0) + max(k1) <= 1200 else None
-        rec.append(dict(shape=shape, attempts_plain=a0, attempts_pred=a1, t_plain=t_plain, t_pred=t_pred,
-                        err_vs_plain=err, width_plain=max(ell0), width_pred=max(ell1), kept_plain=max(k0),
-                        kept_pred=max(k1), rho_pred=max(rho_p)))
-        say(f"eval {i} {shape}: plain {a0} attempts {t_plain:.2f} s, predicted {a1} attempts {t_pred:.2f} s, "
-            f"kept {max(k0)}/{max(k1)} (predicted {max(rho_p)}), rel err vs plain {err}")
+    fpairs = [(x, y) for _, x, y in fresh]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred = H.rankpred_forward(theta, stats, H.rankpred_features(fpairs))
+    widths = H.rankpred_widths(fpairs, pred, margin=args.rp_margin)
+    torch.cuda.synchronize()
+    t_infer = time.perf_counter() - t0
+    # per chunk (half the memory budget each, both results held for the
+    # comparison): the plain start, then the predicted start, pair k with
+    # seed 5000 + k in both
+    rec, t_plain, t_pred = [], 0.0, 0.0
+    for ch in _rp_chunks(H, fpairs, tol, budget=68 << 30):
+        sub = [fpairs[k] for k in ch]
+        r0, ell0, a0, dt0 = _rp_call(H, torch, sub, tol, 5000 + ch[0])
+        r1, ell1, a1, dt1 = _rp_call(H, torch, sub, tol, 5000 + ch[0], ell_init=[widths[k][0] for k in ch])
+        t_plain += dt0
+        t_pred += dt1
+        for j, k in enumerate(ch):
+            k0, k1 = r0[j].ranks[0].tolist(), r1[j].ranks[0].tolist()
+            # the difference TT has ranks rho_0 + rho_1: measured where that stays moderate
+            err = H.rel_err(H.kept_cores(r1[j]), H.kept_cores(r0[j])) if max(k0) + max(k1) <= 1200 else None
+            rec.append(dict(shape=fresh[k][0], attempts_plain=a0[j], attempts_pred=a1[j], err_vs_plain=err,
+                            width_plain=max(ell0[j]), width_pred=max(ell1[j]), kept_plain=max(k0),
+                            kept_pred=max(k1), rho_pred=max(widths[k][1])))
+        say(f"eval {ch[0]}..{ch[-1]}: plain {dt0:.1f} s (attempts {max(a0)} max), predicted {dt1:.1f} s "
+            f"(attempts {max(a1)} max)")
         del r0, r1
         torch.cuda.empty_cache()
-    tp, tq = sum(r["t_plain"] for r in rec), sum(r["t_pred"] for r in rec)
-    line = {"metric": "learned start widths: adaptive recompression time without / with the predictor",
-            "value": tp / tq, "unit": "x", "n_gpus": 1, "higher_is_better": True, "dtype": "f64 (network f32)",
+    say(f"plain {t_plain:.1f} s, predicted: inference {t_infer:.3f} s + recompressions {t_pred:.1f} s")
+    errs = [r["err_vs_plain"] for r in rec if r["err_vs_plain"] is not None]
+    say(f"attempts plain {np.mean([r['attempts_plain'] for r in rec]):.2f}, predicted "
+        f"{np.mean([r['attempts_pred'] for r in rec]):.2f}; max rel err vs plain {max(errs, default=0):.2e}")
+    tq = t_infer + t_pred
+    line = {"metric": "learned start widths: batched tolerance-mode time without / with the predictor",
+            "value": t_plain / tq, "unit": "x", "n_gpus": 1, "higher_is_better": True, "dtype": "f64 (network f32)",
             "data": "synthetic",
             "config": {"workload": f"uneven pairs d 8..32, n {{16,32,64}}, r 8..48 with r_x r_y <= {args.rp_max_rs}, spectral "
                                    f"cores, tol {tol:g}, margin {args.rp_margin}",
-                       "train_pairs": len(train), "train_rows": int(rows), "eval_pairs": len(fresh)},
-            "train": {"label_s": t_label, "train_s": t_train, "steps": steps, "minibatch": bsz,
-                      "loss_first": float(lh[:20].mean()), "loss_last": float(lh[-100:].mean())},
-            "eval": {"pairs_per_s_plain": len(rec) / tp, "pairs_per_s_pred": len(rec) / tq,
+                       "train_pairs": len(train), "train_rows": int(rows), "eval_pairs": len(fresh),
+                       "launch": "batched tolerance mode, attempt rounds side by side on 32 library streams"},
+            "train": {"label_s": t_label, "labels_per_s": len(train) / t_label, "train_s": t_train, "steps": steps,
+                      "minibatch": bsz, "loss_first": float(lh[:20].mean()), "loss_last": float(lh[-100:].mean())},
+            "eval": {"plain_s": t_plain, "pred_s": tq, "inference_s": t_infer,
+                     "pairs_per_s_plain": len(rec) / t_plain, "pairs_per_s_pred": len(rec) / tq,
                      "mean_attempts_plain": float(np.mean([r["attempts_plain"] for r in rec])),
                      "mean_attempts_pred": float(np.mean([r["attempts_pred"] for r in rec])),
                      "first_attempt_accepted": sum(r["attempts_pred"] == 1 for r in rec),
-                     "max_rel_err_vs_plain": max((r["err_vs_plain"] for r in rec if r["err_vs_plain"] is not None),
-                                                 default=None),
-                     "pairs_with_err": sum(r["err_vs_plain"] is not None for r in rec),
-                     "tol": tol},
+                     "max_rel_err_vs_plain": max(errs, default=None),
+                     "pairs_with_err": len(errs), "tol": tol},
             "pairs": rec}
     print(json.dumps(line), flush=True)
     return 0
@@ -867,7 +914,7 @@ def main() -> int:
               "multi-GPU path; independent pairs would shard across GPUs without communication.",
               file=sys.stderr)
         return 2
-    if args.workload == "batched":
+    if args.workload in ("batched", "rankpred"):
         # independent pairs run on the library's 32 streams; HIP's default of 4
         # hardware queues per process would run only 4 of them at a time
         # (raised to 32 where the environment sets fewer; HIP reads it at start-up)

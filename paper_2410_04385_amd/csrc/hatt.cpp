@@ -11,7 +11,9 @@
 
 #include <algorithm>
 #include <memory>
+#include <functional>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <map>
 #include <vector>
@@ -2456,6 +2458,64 @@ static hatt_status batch_streams(BatchStreams **out) {
   return HATT_OK;
 }
 
+// Enqueues each library stream's pairs (in `order`) from a host thread of
+// its own: a pair with many launches (wide truncations issue thousands) would
+// otherwise hold the one enqueuing thread, and every other stream with it,
+// until its own hardware queue has room again.  Single-threaded under graph
+// capture, with the profiler on, or while the autotuner records (their
+// records are not shared between threads).  run_pair(p, k) enqueues pair p
+// on stream k; the first failure is reported after every thread has ended.
+static hatt_status batch_enqueue(int streams, const std::vector<int> &order, const std::vector<int> &stream_of,
+                                 bool threaded, int device,
+                                 const std::function<hatt_status(int, int)> &run_pair) {
+  if (!threaded || streams <= 1) {
+    for (int p : order) {
+      hatt_status st = run_pair(p, stream_of[p]);
+      if (st != HATT_OK) return fail(st, "pair " + std::to_string(p) + ": " + g_err);
+    }
+    return HATT_OK;
+  }
+  std::vector<std::vector<int>> per(streams);
+  for (int p : order) per[stream_of[p]].push_back(p);
+  std::vector<hatt_status> sts(streams, HATT_OK);
+  std::vector<std::string> msgs(streams);
+  auto work = [&](int k) {
+    if (hipSetDevice(device) != hipSuccess) {
+      sts[k] = HATT_EDEVICE;
+      msgs[k] = "hipSetDevice failed in an enqueuing thread";
+      return;
+    }
+    for (int p : per[k]) {
+      hatt_status st = run_pair(p, k);
+      if (st != HATT_OK) {
+        sts[k] = st;
+        msgs[k] = "pair " + std::to_string(p) + ": " + g_err;
+        return;
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  th.reserve(streams);
+  for (int k = 0; k < streams; ++k) {
+    if (per[k].empty()) continue;
+    bool started = false;
+    try {
+      th.emplace_back(work, k);
+      started = true;
+    } catch (...) {
+    }
+    if (!started) work(k);  // no thread to be had: this stream from here
+  }
+  for (auto &t : th) t.join();
+  for (int k = 0; k < streams; ++k)
+    if (sts[k] != HATT_OK) return fail(sts[k], msgs[k]);
+  return HATT_OK;
+}
+
+bool batch_threaded(hipStreamCaptureStatus cap) {
+  return cap == hipStreamCaptureStatusNone && !g_prof.on && g_tune_mode != 1;
+}
+
 struct BatchPlan {
   std::vector<HattSpec> sp;
   std::vector<std::vector<int64_t>> req;  // per-pair width requests (rule widths)
@@ -2596,14 +2656,14 @@ hatt_status hatt_recompress_batched(int32_t npairs, const hatt_tt *x, const hatt
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return batch_pair_cost(bp.sp[a]) > batch_pair_cost(bp.sp[b]); });
   for (int32_t p : order) {
-    const int k = bp.stream_of[p];
-    HattSpec &sp = bp.sp[p];
-    sp.out = out + bp.out_off[p];
-    sp.orank = out_rank + bp.rank_off[p];
-    Ws w((char *)ws + (size_t)k * bp.slot);
-    st = hatt_run(true, sp, w, bs->s[k]);
-    if (st != HATT_OK) return fail(st, "pair " + std::to_string(p) + ": " + g_err);
+    bp.sp[p].out = out + bp.out_off[p];
+    bp.sp[p].orank = out_rank + bp.rank_off[p];
   }
+  st = batch_enqueue(bp.streams, order, bp.stream_of, batch_threaded(cap), bs->device, [&](int p, int k) {
+    Ws w((char *)ws + (size_t)k * bp.slot);
+    return hatt_run(true, bp.sp[p], w, bs->s[k]);
+  });
+  if (st != HATT_OK) return st;
   for (int k = 0; k < bp.streams; ++k) {
     if (hipEventRecord(bs->join[k], bs->s[k]) != hipSuccess) return fail(HATT_EDEVICE, "event record failed");
     if (hipStreamWaitEvent(caller, bs->join[k], 0) != hipSuccess) return fail(HATT_EDEVICE, "stream wait failed");
@@ -3111,24 +3171,20 @@ hatt_status hatt_recompress_batched_adaptive(int32_t npairs, const hatt_tt *x, c
     if (st != HATT_OK) return st;
     st = fork(S);
     if (st != HATT_OK) return st;
-    for (int q : todo) {
+    st = batch_enqueue(S, todo, stream_of, batch_threaded(capst), bs->device, [&](int q, int k) -> hatt_status {
       const HattSpec &sp = ba.sp[q];
       const bool run = true;
-      hipStream_t s_ = bs->s[stream_of[q]];
       int *fl = fld + 2 * ba.train_off[q];
       const int P = sp.X.batch;
-      {
-        hipStream_t st = s_;
-        LAUNCH(launch_finite_check(sp.X.data, sp.X.total, sp.X.stride, P, fl, st));
-        LAUNCH(launch_finite_check(sp.Y.data, sp.Y.total, sp.Y.stride, P, fl + P, st));
-      }
-      if (ba.capture[q]) {
-        Ws wn(arena + region[stream_of[q]]);
-        GemmCtx gm{nullptr, 0, 0};
-        st = hadamard_norm2_body(true, sp.X, sp.Y, z2d + ba.train_off[q], wn, gm, s_);
-        if (st != HATT_OK) return fail(st, "pair " + std::to_string(q) + ": " + g_err);
-      }
-    }
+      hipStream_t st = bs->s[k];
+      LAUNCH(launch_finite_check(sp.X.data, sp.X.total, sp.X.stride, P, fl, st));
+      LAUNCH(launch_finite_check(sp.Y.data, sp.Y.total, sp.Y.stride, P, fl + P, st));
+      if (!ba.capture[q]) return HATT_OK;
+      Ws wn(arena + region[k]);
+      GemmCtx gm{nullptr, 0, 0};
+      return hadamard_norm2_body(true, sp.X, sp.Y, z2d + ba.train_off[q], wn, gm, st);
+    });
+    if (st != HATT_OK) return st;
     st = join(S);
     if (st != HATT_OK) return st;
     std::vector<int> hf((size_t)2 * T);
@@ -3173,11 +3229,11 @@ hatt_status hatt_recompress_batched_adaptive(int32_t npairs, const hatt_tt *x, c
     // largest first, so each stream starts with its costliest pair
     std::vector<int> order(todo);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    for (int q : order) {
-      Ws w(arena + region[stream_of[q]]);
-      st = hatt_run(true, ba.sp[q], w, bs->s[stream_of[q]]);
-      if (st != HATT_OK) return fail(st, "pair " + std::to_string(q) + ": " + g_err);
-    }
+    st = batch_enqueue(S, order, stream_of, batch_threaded(capst), bs->device, [&](int q, int k) {
+      Ws w(arena + region[k]);
+      return hatt_run(true, ba.sp[q], w, bs->s[k]);
+    });
+    if (st != HATT_OK) return st;
     st = join(S);
     if (st != HATT_OK) return st;
     if (hipMemcpyAsync(host_rank.data(), out_rank, host_rank.size() * sizeof(int64_t), hipMemcpyDeviceToHost,

@@ -2,6 +2,7 @@
 // the last-core sketch of HPCRL and the "sandwich" contraction that carries
 // both the W_L columns of HPCRL (eq. WLWR) and the PKP-free core update of
 // the HaTT sweep (eq. M*core0).
+#include <mutex>
 #include "common.h"
 #include "stage.h"
 
@@ -317,12 +318,11 @@ hipError_t sandwich_reg_launch(const SandwichArgs &a, hipStream_t s, int64_t bud
   const int64_t chunks = (a.G + gmax - 1) / gmax;
   const int64_t GC = (a.G + chunks - 1) / chunks;
   const size_t lds = (size_t)(fixed + GC * cgs) * sizeof(double);
-  static bool attr_done = false;
-  if (!attr_done) {
+  static std::once_flag attr_done;
+  std::call_once(attr_done, [&] {
     hipFuncSetAttribute((const void *)sandwich_reg_kernel<MAXR, BPT, LG>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)(budget * sizeof(double)));
-    attr_done = true;
-  }
+  });
   dim3 grid((unsigned)a.n, (unsigned)chunks, (unsigned)a.batch);
   sandwich_reg_kernel<MAXR, BPT, LG><<<grid, 256, lds, s>>>(a, (int)GC, TPG);
   return hipGetLastError();
@@ -405,14 +405,13 @@ hipError_t launch_sandwich(const SandwichArgs &a, hipStream_t s, const SwForce *
   gc = std::min<int64_t>(gc, a.G);
   const size_t lds = (size_t)(fixed + gc * perg) * sizeof(double);
   dim3 grid((unsigned)a.n, (unsigned)((a.G + gc - 1) / gc), (unsigned)a.batch);
-  static bool attr_done = false;  // set once: the maximum a launch may ask for
-  if (!attr_done) {
+  static std::once_flag attr_done;  // set once: the maximum a launch may ask for
+  std::call_once(attr_done, [&] {
     hipFuncSetAttribute((const void *)sandwich_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)(budget * sizeof(double)));
     hipFuncSetAttribute((const void *)sandwich_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)(budget * sizeof(double)));
-    attr_done = true;
-  }
+  });
   if (a.og == 1) sandwich_kernel<true><<<grid, 256, lds, s>>>(a, (int)gc);
   else sandwich_kernel<false><<<grid, 256, lds, s>>>(a, (int)gc);
   return hipGetLastError();

@@ -20,6 +20,7 @@
 // l + 64, ... (RPL of them).  Column dot products are wave reductions, so a
 // Householder step needs one barrier: the owner of column j publishes its
 // reflector through LDS and every wave updates its own columns.
+#include <mutex>
 #include "common.h"
 
 namespace hatt {
@@ -423,12 +424,11 @@ hipError_t launch_trinv(const double *r, int64_t rbs, double *x, int64_t xbs, in
   if (batch <= 0) return hipSuccess;
   if (n < 1 || n > 128) return hipErrorInvalidValue;
   const size_t lds = (size_t)(n * n + n) * sizeof(double);
-  static bool attr = false;
-  if (!attr) {
+  static std::once_flag attr;
+  std::call_once(attr, [&] {
     hipFuncSetAttribute((const void *)trinv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)((128 * 128 + 128) * sizeof(double)));
-    attr = true;
-  }
+  });
   trinv_kernel<<<batch, 1024, lds, s>>>(r, rbs, x, xbs, n, flag, fstride, first, mask, mbs, dep_abs);
   return hipGetLastError();
 }

@@ -20,6 +20,7 @@
 // rank-deficient input still yields an orthonormal Q.  Finally the signs of
 // diag(R) are made non-negative (columns of Q and rows of R flipped
 // together).
+#include <mutex>
 #include "common.h"
 #include "stage.h"
 
@@ -324,12 +325,11 @@ hipError_t launch_tsqr(const QrPlan &p, CMat a, Mat q, Mat r, double *ws, int64_
   const int64_t n = p.n;
   const int ch = qr_chunk(p.m, n, p.k);
   const size_t lds_max = (size_t)kQrLdsDoubles * sizeof(double);
-  static bool attr_done = false;  // set once: the maximum a launch may ask for
-  if (!attr_done) {
+  static std::once_flag attr_done;  // set once: the maximum a launch may ask for
+  std::call_once(attr_done, [&] {
     hipFuncSetAttribute((const void *)tsqr_factor_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
     hipFuncSetAttribute((const void *)tsqr_formq_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
-    attr_done = true;
-  }
+  });
   // upward pass
   for (int L = 0; L < p.levels; ++L) {
     QrLevelArgs la{};
@@ -619,12 +619,11 @@ hipError_t launch_chol(const double *g, int64_t gbs, int ks, int64_t kstride, do
                        hipStream_t s) {
   if (n > kCholMaxN || n < 1 || ks < 1) return hipErrorInvalidValue;
   const size_t lds = (size_t)n * (2 * n + 1) * sizeof(double);
-  static bool attr_done = false;
-  if (!attr_done) {
+  static std::once_flag attr_done;
+  std::call_once(attr_done, [&] {
     hipFuncSetAttribute((const void *)chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)(kCholMaxN * (2 * kCholMaxN + 1) * sizeof(double)));
-    attr_done = true;
-  }
+  });
   chol_kernel<<<batch, 256, lds, s>>>(g, gbs, ks, kstride, r, rinv, rbs, n, flag, fstride, first, thr_rel);
   return hipGetLastError();
 }
@@ -633,15 +632,14 @@ hipError_t launch_gram_chol(CMat A, int64_t m, int n, double *r, double *rinv, i
                             int64_t fstride, int first, double thr_rel, int batch, hipStream_t s) {
   if (n > kCholMaxN || n < 1 || m < 1) return hipErrorInvalidValue;
   const size_t lds = (size_t)n * (2 * n + 1) * sizeof(double);
-  static bool attr_done = false;
-  if (!attr_done) {
+  static std::once_flag attr_done;
+  std::call_once(attr_done, [&] {
     const int mx = (int)(kCholMaxN * (2 * kCholMaxN + 1) * sizeof(double));
     hipFuncSetAttribute((const void *)gram_chol_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     hipFuncSetAttribute((const void *)gram_chol_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     hipFuncSetAttribute((const void *)gram_chol_kernel<3>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     hipFuncSetAttribute((const void *)gram_chol_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    attr_done = true;
-  }
+  });
   const int nb = (n + 15) / 16;
   if (nb == 1) gram_chol_kernel<1><<<batch, 256, lds, s>>>(A, m, r, rinv, rbs, n, flag, fstride, first, thr_rel);
   else if (nb == 2) gram_chol_kernel<2><<<batch, 256, lds, s>>>(A, m, r, rinv, rbs, n, flag, fstride, first, thr_rel);

@@ -12,6 +12,7 @@
 //     8 quantiles (q = j/7, linear between order statistics) of
 //     ln max(c_a, 1e-300), c_a the squared norm of column a of V(x_k),
 //     the same 8 for y.
+#include <mutex>
 #include "common.h"
 
 namespace hatt {
@@ -115,12 +116,11 @@ __global__ __launch_bounds__(256) void rp_forward_kernel(const float *theta, con
 
 hipError_t launch_rp_forward(const float *theta, const float *stats, const float *feat, int64_t rows, float *pred,
                              hipStream_t s) {
-  static bool attr = false;
+  static std::once_flag attr;
   const size_t lds = (size_t)kRpTheta * sizeof(float);
-  if (!attr) {
+  std::call_once(attr, [&] {
     hipFuncSetAttribute((const void *)rp_forward_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    attr = true;
-  }
+  });
   if (rows < 1) return hipSuccess;
   const int64_t grid = (rows + 255) / 256;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
@@ -319,12 +319,11 @@ __global__ __launch_bounds__(256) void rp_reduce_kernel(const float *part, int n
 hipError_t launch_rp_grad(const float *theta, const float *stats, const float *feat, const float *label,
                           const int32_t *idx, int64_t batch, float *part, float *loss_part, float *grad,
                           float *loss, const RpAdam &ad, hipStream_t s) {
-  static bool attr = false;
+  static std::once_flag attr;
   const size_t lds = rp_grad_lds_bytes();
-  if (!attr) {
+  std::call_once(attr, [&] {
     hipFuncSetAttribute((const void *)rp_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    attr = true;
-  }
+  });
   const int64_t nblk = (batch + kRows - 1) / kRows;
   if (batch < 1 || nblk > 0x7fffffff) return hipErrorInvalidValue;
   rp_grad_kernel<<<(unsigned)nblk, 256, lds, s>>>(theta, stats, feat, label, idx, batch, 1.0f / (float)batch, part,

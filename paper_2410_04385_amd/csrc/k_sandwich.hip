@@ -12,6 +12,7 @@
 // 16 lanes of an output row segment store to consecutive addresses:
 // (b', g) with g fastest when the output is contiguous in g, (g, b') otherwise
 // (the column-major W_L of HPCRL and the core update, both contiguous in b').
+#include <mutex>
 #include "common.h"
 #include "stage.h"
 
@@ -1024,8 +1025,8 @@ const char *sandwich_mfma_name(const SandwichArgs &a, const SwPlan &pl) {
 hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStream_t s) {
   const size_t esz = a.prec == 2 ? sizeof(__bf16) : (a.prec ? sizeof(float) : sizeof(double));
   const size_t lds = (size_t)pl.lds_doubles * esz;
-  static bool attr_done = false;  // set once: the maximum a launch may ask for
-  if (!attr_done) {
+  static std::once_flag attr_done;  // set once: the maximum a launch may ask for
+  std::call_once(attr_done, [&] {
     const int mx = (int)(kSandwichLdsDoubles * sizeof(double));
     (void)hipFuncSetAttribute((const void *)sandwich_mfma_kernel<true, double>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, mx);
@@ -1048,8 +1049,7 @@ hipError_t launch_sandwich_mfma(const SandwichArgs &a, const SwPlan &pl, hipStre
     ks_attrs<7>(mx);
     ks_attrs<8>(mx);
     (void)hipFuncSetAttribute((const void *)sandwich_slice_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    attr_done = true;
-  }
+  });
   if (pl.slice) {
     sandwich_slice_kernel<<<dim3((unsigned)pl.iblocks, (unsigned)pl.gblocks, (unsigned)a.batch), 256, lds, s>>>(a, pl);
     return hipGetLastError();

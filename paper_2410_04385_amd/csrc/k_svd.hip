@@ -19,6 +19,7 @@
 //     registers; partners are read through LDS.
 //   * larger nc: one 256-thread workgroup per matrix, A in LDS, each pair
 //     handled by a group of lanes that reduce with shuffles.
+#include <mutex>
 #include "common.h"
 
 namespace hatt {
@@ -210,11 +211,10 @@ namespace {
 template <int KR>
 hipError_t svd_wave_launch(const SvdArgs &a, hipStream_t s) {
   const size_t lds = (size_t)(2 * KR * 64) * sizeof(double);
-  static bool attr_done = false;
-  if (!attr_done) {
+  static std::once_flag attr_done;
+  std::call_once(attr_done, [&] {
     hipFuncSetAttribute((const void *)svd_wave_kernel<KR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    attr_done = true;
-  }
+  });
   svd_wave_kernel<KR><<<a.batch, 64, lds, s>>>(a);
   return hipGetLastError();
 }
@@ -594,14 +594,13 @@ hipError_t launch_svd_trunc(const SvdArgs &a, hipStream_t s) {
     // per lane.  (16 lanes per column, with blocks of 4 and twice the waves,
     // measured slower at 128 rows: twice the block rounds and barriers for
     // the same shuffle traffic.)
-    static bool attr_bj = false;
-    if (!attr_bj) {
+    static std::once_flag attr_bj;
+    std::call_once(attr_bj, [&] {
       const int mx = (int)(128 * 128 * sizeof(double));
       hipFuncSetAttribute((const void *)svd_bj_kernel<8, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
       hipFuncSetAttribute((const void *)svd_bj_kernel<8, 12>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
       hipFuncSetAttribute((const void *)svd_bj_kernel<8, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-      attr_bj = true;
-    }
+    });
     int nb = (a.nc + 7) / 8;
     nb += nb & 1;
     const size_t lds = (size_t)nb * 8 * a.kr * sizeof(double);
@@ -616,12 +615,11 @@ hipError_t launch_svd_trunc(const SvdArgs &a, hipStream_t s) {
   int tpg = 16;
   while (tpg > 1 && tpg * npairs > kBlockThreads) tpg >>= 1;
   const size_t lds = (size_t)a.nc * a.kr * sizeof(double);
-  static bool attr_done = false;  // set once: the maximum a launch may ask for
-  if (!attr_done) {
+  static std::once_flag attr_done;  // set once: the maximum a launch may ask for
+  std::call_once(attr_done, [&] {
     hipFuncSetAttribute((const void *)svd_block_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)(kQrLdsDoubles * sizeof(double)));
-    attr_done = true;
-  }
+  });
   svd_block_kernel<<<a.batch, kBlockThreads, lds, s>>>(a, tpg);
   return hipGetLastError();
 }
@@ -761,12 +759,11 @@ __global__ __launch_bounds__(kBigRoundThreads) void svd_big_round_kernel(double 
 hipError_t launch_svd_big_round(double *acol, int64_t acs, int kr, int nc, int bw, int nb, int t, int *flags,
                                 int batch, hipStream_t s) {
   const size_t lds = (size_t)2 * bw * kr * sizeof(double);
-  static bool attr_done = false;  // set once: the maximum a launch may ask for
-  if (!attr_done) {
+  static std::once_flag attr_done;  // set once: the maximum a launch may ask for
+  std::call_once(attr_done, [&] {
     hipFuncSetAttribute((const void *)svd_big_round_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)(kQrLdsDoubles * sizeof(double)));
-    attr_done = true;
-  }
+  });
   svd_big_round_kernel<<<dim3((unsigned)(nb / 2), (unsigned)batch), kBigRoundThreads, lds, s>>>(acol, acs, kr, nc, bw, nb, t,
                                                                                  flags);
   return hipGetLastError();
