@@ -158,8 +158,11 @@ HATT_API hatt_status hatt_recompress_noalloc(const hatt_tt *x, const hatt_tt *y,
  * library-owned streams forked from `stream` and joined back to it (so the
  * call composes with stream order and graph capture); concurrent pairs use
  * separate workspace slots.  How many streams run concurrently is bounded by
- * the process's hardware queues (HIP's GPU_MAX_HW_QUEUES).  No host
- * synchronisation.  Errors of any pair are reported before anything is
+ * the process's hardware queues (HIP's GPU_MAX_HW_QUEUES).  Each stream's
+ * pairs are enqueued by a short-lived host thread of its own (on the caller's
+ * device; one thread does it all under graph capture, with the profiler on
+ * or while the autotuner records), so a pair with many launches does not
+ * hold back the other streams.  No host synchronisation.  Errors of any pair are reported before anything is
  * enqueued.  While `stream` is being captured into a HIP graph at most 12
  * pairs are accepted (HATT_EUNSUPPORTED above that: a capture of 512 pairs,
  * some 10^5 kernel nodes, ended the host process).  Concurrent calls from
