@@ -461,13 +461,17 @@ hipError_t launch_complete_cols(double *a, int64_t m, int n, int64_t abs_, const
 // Gaussian elimination of [G | I] (G = L D L^T; R = D^{1/2} L^T,
 // R^{-1} = L^{-T} D^{-1/2}), held in registers: thread (ty, tx) of 16 x 64
 // holds rows ty + 16 k of the columns tx + 64 s.  The multipliers of pivot j
-// are its own row (symmetry), published through a double-buffered LDS row by
-// its owner.  Pivots <= thr_rel * max diag(G) (and NaN) clear the flag.
+// are its own row (symmetry).  Two pivots per barrier: the owners of rows j
+// and j + 1 publish them (updated through pivot j - 1) in a double-buffered
+// LDS pair, and every thread forms row j + 1's update by pivot j itself where
+// it needs it (its columns, its rows' multipliers and the second pivot), with
+// the same operations as the owner.  Pivots <= thr_rel * max diag(G) (and
+// NaN) clear the flag.
 __global__ __launch_bounds__(1024) void chol1k_kernel(const double *g, int64_t gbs, double *ro, double *rio,
                                                       int64_t rbs, int n, int *flag, int64_t fstride, int first,
                                                       double thr_rel) {
   constexpr int KR = 8, NS = 4;  // rows per thread, column slots (2n <= 256)
-  __shared__ double prow[2][256];
+  __shared__ double prow[2][2][256];
   __shared__ double piv[128];
   __shared__ double dmax_s;
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
@@ -486,11 +490,11 @@ __global__ __launch_bounds__(1024) void chol1k_kernel(const double *g, int64_t g
       w[k][s] = v;
     }
   }
-  if (ty == 0) {
+  if (ty < 2 && ty < n) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int c = tx + 64 * s;
-      if (c < n2) prow[0][c] = w[0][s];
+      if (c < n2) prow[0][ty][c] = w[0][s];
     }
   }
   if (tid == 0) {
@@ -503,50 +507,80 @@ __global__ __launch_bounds__(1024) void chol1k_kernel(const double *g, int64_t g
   const bool dmax_ok = (dmax > 0.0) && (dmax < 1e300);
   const double thr = thr_rel * dmax;
   int bad = dmax_ok ? 0 : 1;
-  for (int j = 0; j < n; ++j) {
-    const double *pr = prow[j & 1];
-    double d = pr[j];
+  for (int j = 0; j < n; j += 2) {
+    const double *pj = prow[(j >> 1) & 1][0], *pk = prow[(j >> 1) & 1][1];
+    const bool two = j + 1 < n;  // block-uniform
+    double d = pj[j];
     if (!(d > thr)) {
       bad = 1;
       d = (thr > 0.0 && thr < 1e300) ? thr : 1.0;
     }
-    if (tid == 0) piv[j] = d;
     const double inv = 1.0 / d;
-    double pc[NS];
+    // pc / pc2: the scaled pivot rows on the columns each pivot updates (left
+    // half: columns > j; right half: up to n + j), zero elsewhere, so that
+    // the row updates below need no column tests (on the left half they also
+    // touch the lower triangle, which is never read or written out)
+    double pc[NS], pc2[NS];
     bool act[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int c = tx + 64 * s;
-      // left half: columns > j (upper triangle only, rows i <= c); right half: up to n + j
       act[s] = (c < n) ? (c > j) : (c < n2 && c <= n + j);
-      pc[s] = act[s] ? pr[c] * inv : 0.0;
+      pc[s] = act[s] ? pj[c] * inv : 0.0;
     }
+    // row j + 1 after pivot j: pk - m pj / d on the columns pivot j touches
+    const double m = two ? pj[j + 1] : 0.0;
+    double inv2 = 0.0;
+    if (two) {
+      double d2 = pk[j + 1] - m * (pj[j + 1] * inv);
+      if (!(d2 > thr)) {
+        bad = 1;
+        d2 = (thr > 0.0 && thr < 1e300) ? thr : 1.0;
+      }
+      if (tid == 0) piv[j + 1] = d2;
+      inv2 = 1.0 / d2;
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int c = tx + 64 * s;
+      const bool act2 = two && ((c < n) ? (c > j + 1) : (c < n2 && c <= n + j + 1));
+      const double rk = act[s] ? pk[c] - m * pc[s] : (c < n2 ? pk[c] : 0.0);
+      pc2[s] = act2 ? rk * inv2 : 0.0;
+    }
+    if (tid == 0) piv[j] = d;
     // rows ty + 16 k <= j are final: k below kmin is skipped (wave-uniform)
     const int kmin = (j + 16 - ty) >> 4;  // first k with ty + 16 k > j
 #pragma unroll
     for (int k = 0; k < KR; ++k) {
       const int i = ty + 16 * k;
       if (k >= kmin && i < n) {
-        const double mul = pr[i];
+        const double mul = pj[i];
+        const bool second = two && i > j + 1;
+        const double mul2 = second ? pk[i] - m * (pj[i] * inv) : 0.0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          const int c = tx + 64 * s;
-          if (act[s] && (c >= n || i <= c)) w[k][s] -= mul * pc[s];
+          w[k][s] -= mul * pc[s];
+          if (second) w[k][s] -= mul2 * pc2[s];
         }
       }
     }
-    if (j + 1 < n && ty == ((j + 1) & 15)) {
-      const int kk = (j + 1) >> 4;
-      double *nr = prow[(j + 1) & 1];
+    // the owners of rows j + 2 and j + 3 publish them for the next pair
+    double(*nb)[256] = prow[((j >> 1) + 1) & 1];
 #pragma unroll
-      for (int k = 0; k < KR; ++k)
-        if (k == kk) {
+    for (int h = 0; h < 2; ++h) {
+      const int r = j + 2 + h;
+      if (r < n && ty == (r & 15)) {
+        const int kk = r >> 4;
 #pragma unroll
-          for (int s = 0; s < NS; ++s) {
-            const int c = tx + 64 * s;
-            if (c < n2) nr[c] = w[k][s];
+        for (int k = 0; k < KR; ++k)
+          if (k == kk) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+              const int c = tx + 64 * s;
+              if (c < n2) nb[h][c] = w[k][s];
+            }
           }
-        }
+      }
     }
     __syncthreads();
   }
