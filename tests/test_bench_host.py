@@ -90,3 +90,32 @@ def test_traffic_record_is_tied_to_batch_precision_and_source():
         assert b._traffic(kernel, ent["batch"] + 1, prec) is None
         assert b._traffic(kernel, ent["batch"], other) is None
     assert b._traffic("no_such_kernel", 512, "f64") is None
+
+
+def test_width_predictor_chunks_respect_the_memory_budget():
+    """bench.py's chunking for the batched tolerance mode: consecutive pairs,
+    every pair once, at most `most` per chunk, and each chunk's output slots
+    (from the library's plan, on the host) within the budget unless a single
+    pair exceeds it on its own."""
+    import torch
+    import workloads as wk
+    from paper_2410_04385_amd import api
+    b = _bench()
+
+    def cpu_tt(n, ranks):
+        _, tot = api._offsets(n, ranks)
+        return api.TT(torch.zeros(tot, dtype=torch.float64), n, ranks, 1)
+
+    pairs = []
+    for d, n, rx, ry in wk.batched_pair_shapes(7, 40):
+        nn = [n] * d
+        pairs.append((cpu_tt(nn, wk.feasible_ranks(nn, rx)), cpu_tt(nn, wk.feasible_ranks(nn, ry))))
+    size = [8 * api.batched_adaptive_plan([p], 1e-6)["out_offset"][-1] for p in pairs]
+    budget = 3 * max(size)
+    chunks = b._rp_chunks(api, pairs, 1e-6, budget=budget, most=7)
+    assert [k for ch in chunks for k in ch] == list(range(len(pairs)))
+    assert all(1 <= len(ch) <= 7 for ch in chunks)
+    assert all(sum(size[k] for k in ch) <= budget for ch in chunks)
+    # a chunk closes only when the next pair would break a limit
+    for ch, nxt in zip(chunks, chunks[1:]):
+        assert len(ch) == 7 or sum(size[k] for k in ch) + size[nxt[0]] > budget
