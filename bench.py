@@ -875,8 +875,9 @@ def _bench_rankpred(args, torch, wk, H) -> int:
             # the difference TT has ranks rho_0 + rho_1: measured where that stays moderate
             err = H.rel_err(H.kept_cores(r1[j]), H.kept_cores(r0[j])) if max(k0) + max(k1) <= 1200 else None
             rec.append(dict(shape=fresh[k][0], attempts_plain=a0[j], attempts_pred=a1[j], err_vs_plain=err,
-                            width_plain=max(ell0[j]), width_pred=max(ell1[j]), kept_plain=max(k0),
-                            kept_pred=max(k1), rho_pred=max(widths[k][1])))
+                            width_plain=max(ell0[j]), width_pred=max(ell1[j]), width_sum_plain=sum(ell0[j]),
+                            width_sum_pred=sum(ell1[j]), kept_plain=max(k0), kept_pred=max(k1),
+                            rho_pred=max(widths[k][1])))
         say(f"eval {ch[0]}..{ch[-1]}: plain {dt0:.1f} s (attempts {max(a0)} max), predicted {dt1:.1f} s "
             f"(attempts {max(a1)} max)")
         del r0, r1
