@@ -515,24 +515,28 @@ def _bench_trig(args, torch, wk, H, perfmodel) -> int:
         from threadpoolctl import threadpool_info
 
         from oracle import hatt as ohatt
-        from oracle import philox, rounding, tt
+        from oracle import philox, plan as oplan, rounding, tt
 
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        # the oracle's own chain: u2 from u, then u3 from the oracle's u2, at
+        # the requested widths clamped by the oracle's own ranks
+        w2 = oplan.clamp_ell(list(U.n), tt.ranks(u), tt.ranks(u), [1] + [l2] * (len(U.n) - 1) + [1])
         t0 = time.perf_counter()
-        ref2 = rounding.tt_round_left_orth(ohatt.hatt(u, u, philox.sketch(s2, U.n, ell2)), tol=tol)
+        ref2 = rounding.tt_round_left_orth(ohatt.hatt(u, u, philox.sketch(s2, U.n, w2)), tol=tol)
         ta = time.perf_counter() - t0
+        w3 = oplan.clamp_ell(list(U.n), tt.ranks(ref2), tt.ranks(u), [1] + [l3] * (len(U.n) - 1) + [1])
         t0 = time.perf_counter()
-        ref3 = rounding.tt_round_left_orth(ohatt.hatt(g2, u, philox.sketch(s3, U.n, ell3)), tol=tol)
+        ref3 = rounding.tt_round_left_orth(ohatt.hatt(ref2, u, philox.sketch(s3, U.n, w3)), tol=tol)
         tb = time.perf_counter() - t0
         cpu = {"value": 2.0 / (ta + tb), "unit": "recompressions/s", "cores": threads, "kind": "oracle",
                "sample": "one step: u2 and u3 by the FP64 numpy oracle (HaTT-1 with the same Philox sketches, "
-                         "then TT-Rounding at tol 1e-8), u3 from the GPU's u2 factor",
-               "u2_s": ta, "u3_s": tb}
+                         "then TT-Rounding at tol 1e-8), u3 from the oracle's own u2",
+               "u2_s": ta, "u3_s": tb, "widths": {"u2": w2, "u3": w3}}
         # the same oracle on one host thread (u2 only, a bounded sample)
         from threadpoolctl import threadpool_limits
         with threadpool_limits(limits=1):
             t0 = time.perf_counter()
-            rounding.tt_round_left_orth(ohatt.hatt(u, u, philox.sketch(s2, U.n, ell2)), tol=tol)
+            rounding.tt_round_left_orth(ohatt.hatt(u, u, philox.sketch(s2, U.n, w2)), tol=tol)
             t1 = time.perf_counter() - t0
         cpu["one_core"] = {"value": 1.0 / t1, "unit": "recompressions/s", "cores": 1,
                            "sample": "u2 by the oracle on one BLAS thread"}
@@ -1050,10 +1054,11 @@ def main() -> int:
         from threadpoolctl import threadpool_info
 
         from oracle import hatt as ohatt
-        from oracle import philox, rounding, tt
+        from oracle import philox, plan as oplan, rounding, tt
 
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-        l = p["ell"]
+        # the widths by the oracle's own clamp (the pairs share one shape)
+        l = oplan.clamp_ell(tt.modes(pairs[0][0]), tt.ranks(pairs[0][0]), tt.ranks(pairs[0][1]), ell)
         R = philox.sketch(seed, x.n, l)
         t0 = time.perf_counter()
         done = 0
